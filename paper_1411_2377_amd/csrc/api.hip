@@ -1,0 +1,213 @@
+// C ABI of the multiple-precision SpMV / Krylov library (declarations in include/mpspmv.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/mpspmv.h"
+#include "api_internal.hpp"
+#include "spmv_kernels.hpp"
+
+namespace mpapi {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(MPS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- per-device context -----------------------------------------------------------------
+static std::mutex g_ctx_mu;
+static std::vector<DeviceCtx*> g_ctx;
+
+int get_ctx(DeviceCtx** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
+  if (!g_ctx[dev]) {
+    DeviceCtx* c = new DeviceCtx();
+    c->device = dev;
+    e = hipMalloc((void**)&c->status, sizeof(uint32_t) * 4);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(MPS_ENOMEM, "hipMalloc(status): %s", hipGetErrorString(e));
+    }
+    e = hipMemset(c->status, 0, sizeof(uint32_t) * 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    g_ctx[dev] = c;
+  }
+  *out = g_ctx[dev];
+  return MPS_OK;
+}
+
+// ---- validation ---------------------------------------------------------------------------
+int limbs_of(int prec) {
+  switch (prec) {
+    case 128: return 4;
+    case 256: return 8;
+    case 512: return 16;
+    default: return 0;
+  }
+}
+
+int check_vec(const mp_vec* v, int64_t want_len, const char* name) {
+  if (!v) return fail(MPS_EINVAL, "%s: null descriptor", name);
+  if (v->len != want_len)
+    return fail(MPS_EINVAL, "%s: length %lld, expected %lld", name, (long long)v->len,
+                (long long)want_len);
+  if (v->len < 0 || v->ld < v->len) return fail(MPS_EINVAL, "%s: bad len/ld", name);
+  if (v->len > 0 && (!v->limb || !v->hdr)) return fail(MPS_EINVAL, "%s: null pointer", name);
+  return MPS_OK;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  if (!pa || !pb || na == 0 || nb == 0) return false;
+  return pa < pb + nb && pb < pa + na;
+}
+
+bool vec_overlap(const mp_vec* a, const mp_vec* b, int L) {
+  const size_t la = (size_t)((L - 1) * a->ld + a->len) * 4, lb = (size_t)((L - 1) * b->ld + b->len) * 4;
+  return overlap(a->limb, la, b->limb, lb) || overlap(a->hdr, (size_t)a->len * 4, b->hdr, (size_t)b->len * 4) ||
+         overlap(a->limb, la, b->hdr, (size_t)b->len * 4) || overlap(a->hdr, (size_t)a->len * 4, b->limb, lb);
+}
+
+int check_csr(const mp_csr* A, int check_device_data) {
+  if (!A) return fail(MPS_EINVAL, "A: null descriptor");
+  if (!limbs_of(A->prec)) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512}", A->prec);
+  if (A->row_dim < 0 || A->col_dim < 0 || A->nnz < 0)
+    return fail(MPS_EINVAL, "A: negative dimension");
+  if (A->nnz > INT32_MAX || A->row_dim >= INT32_MAX || A->col_dim >= INT32_MAX)
+    return fail(MPS_EINVAL, "A: sizes must fit 32-bit indices");
+  if (!A->row_ptr) return fail(MPS_EINVAL, "A: null row_ptr");
+  if (A->nnz > 0 && !A->col_idx) return fail(MPS_EINVAL, "A: null col_idx");
+  int r = check_vec(&A->val, A->nnz, "A.val");
+  if (r) return r;
+  if (check_device_data) {
+    std::vector<int32_t> rp(A->row_dim + 1), ci(A->nnz);
+    hipError_t e = hipMemcpy(rp.data(), A->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(row_ptr)");
+    if (A->nnz) {
+      e = hipMemcpy(ci.data(), A->col_idx, ci.size() * 4, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpy(col_idx)");
+    }
+    if (rp[0] != 0 || rp[A->row_dim] != A->nnz)
+      return fail(MPS_EINVAL, "A: row_ptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < A->row_dim; ++i) {
+      if (rp[i + 1] < rp[i]) return fail(MPS_EINVAL, "A: row_ptr decreases at row %lld", (long long)i);
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (ci[k] < 0 || ci[k] >= A->col_dim)
+          return fail(MPS_EINVAL, "A: column index out of range in row %lld", (long long)i);
+        if (k > rp[i] && ci[k] <= ci[k - 1])
+          return fail(MPS_EINVAL, "A: columns not strictly ascending in row %lld", (long long)i);
+      }
+    }
+  }
+  return MPS_OK;
+}
+
+// ---- SpMV launch ----------------------------------------------------------------------------
+template <int L>
+static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock);
+  if (mode == MP_SEQ)
+    hipLaunchKernelGGL(mp::spmv_seq_kernel<L>, dim3(grid), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(mp::spmv_exact_kernel<L>, dim3(grid), dim3(64), 0, s, a);
+}
+
+int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                const mp_vec& val, const mp_vec& x, mp_vec& y, int mode, uint32_t* status,
+                hipStream_t s) {
+  if (n_rows == 0) return MPS_OK;
+  mp::SpmvArgs a;
+  a.n_rows = n_rows;
+  a.row_ptr = row_ptr;
+  a.col_idx = col_idx;
+  a.a_limb = val.limb;
+  a.a_hdr = val.hdr;
+  a.a_ld = val.ld;
+  a.x_limb = x.limb;
+  a.x_hdr = x.hdr;
+  a.x_ld = x.ld;
+  a.y_limb = y.limb;
+  a.y_hdr = y.hdr;
+  a.y_ld = y.ld;
+  a.status = status;
+  switch (L) {
+    case 4: launch_spmv<4>(a, mode, s); break;
+    case 8: launch_spmv<8>(a, mode, s); break;
+    case 16: launch_spmv<16>(a, mode, s); break;
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "spmv launch");
+  return MPS_OK;
+}
+
+}  // namespace mpapi
+
+using namespace mpapi;
+
+extern "C" {
+
+const char* mp_last_error(void) { return g_err; }
+
+int mp_validate_csr(const mp_csr* A, int check_device_data) {
+  clear_error();
+  return check_csr(A, check_device_data);
+}
+
+int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if ((r = check_vec(x, A->col_dim, "x"))) return r;
+  if ((r = check_vec(y, A->row_dim, "y"))) return r;
+  const int L = limbs_of(A->prec);
+  if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L))
+    return fail(MPS_EINVAL, "y overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
+                     (hipStream_t)stream);
+}
+
+int mp_status(void* stream, uint32_t* flags) {
+  clear_error();
+  DeviceCtx* ctx;
+  int r = get_ctx(&ctx);
+  if (r) return r;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t h = 0;
+  e = hipMemcpy(&h, ctx->status, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
+  e = hipMemset(ctx->status, 0, 4);
+  if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
+  if (flags) *flags = h;
+  if (h & MP_ST_RANGE) return fail(MPS_ERANGE, "a result exponent left the range");
+  if (h & MP_ST_WINDOW) return fail(MPS_ENOTSUP, "an exact accumulation was wider than supported");
+  return MPS_OK;
+}
+
+}  // extern "C"

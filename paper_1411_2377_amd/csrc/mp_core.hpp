@@ -1,0 +1,321 @@
+// Device limb arithmetic for p-bit binary floating point with round-to-nearest-even.
+//
+// Number model (Kouya, Sec. 2: the MPFR number with its mantissa kept apart from the exponent,
+// IEEE-754-1985-like semantics, round-to-nearest):
+//     x = (-1)^s * M * 2^(e - p),  2^(p-1) <= M < 2^p,  p = 32 * L
+// M is held as L 32-bit limbs (m[0] least significant).  A zero has e == kZeroE and M == 0 and
+// keeps its sign.  Exponents outside [kEmin, kEmax] (MPFR's default range) raise kStRange in the
+// device status word; the paper never leaves that range.
+//
+// Storage (structure of arrays): limb k of element i at limb[k * ld + i]; hdr[i] = (e << 1) | s.
+// A zero's header is INT32_MIN (+0) or INT32_MIN + 1 (-0); its limbs are ignored.
+//
+// All arithmetic is on 32-bit limbs with 32x32->64 multiplies and add/sub-with-carry chains.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MPD __device__ __forceinline__
+
+namespace mp {
+
+constexpr int32_t kZeroE = -(1 << 30);
+constexpr int32_t kEmin = 1 - (1 << 30);
+constexpr int32_t kEmax = (1 << 30) - 1;
+
+// device status word bits
+constexpr uint32_t kStRange = 1u;    // a result exponent left [kEmin, kEmax]
+constexpr uint32_t kStWindow = 2u;   // an exact accumulation needed a wider window than allowed
+constexpr uint32_t kStDivZero = 4u;  // a scalar division by zero was requested
+
+template <int L>
+struct Num {
+  uint32_t m[L];
+  int32_t e;
+  uint32_t s;
+};
+
+MPD bool hdr_is_zero(int32_t h) { return (h >> 1) == kZeroE; }
+MPD int32_t make_hdr(int32_t e, uint32_t s) { return (int32_t)(((uint32_t)e << 1) | (s & 1u)); }
+
+template <int L>
+MPD void set_zero(Num<L>& x, uint32_t s) {
+#pragma unroll
+  for (int k = 0; k < L; ++k) x.m[k] = 0;
+  x.e = kZeroE;
+  x.s = s;
+}
+
+template <int L>
+MPD bool is_zero(const Num<L>& x) { return x.e == kZeroE; }
+
+// Load element i; the limbs of a zero are not read (zero fast path).
+template <int L>
+MPD void load(Num<L>& x, const uint32_t* __restrict__ limb, const int32_t* __restrict__ hdr,
+              int64_t ld, int64_t i) {
+  int32_t h = hdr[i];
+  x.e = h >> 1;
+  x.s = (uint32_t)h & 1u;
+  if (x.e != kZeroE) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) x.m[k] = limb[(int64_t)k * ld + i];
+  } else {
+#pragma unroll
+    for (int k = 0; k < L; ++k) x.m[k] = 0;
+  }
+}
+
+template <int L>
+MPD void store(const Num<L>& x, uint32_t* __restrict__ limb, int32_t* __restrict__ hdr,
+               int64_t ld, int64_t i) {
+  hdr[i] = make_hdr(x.e, x.s);
+#pragma unroll
+  for (int k = 0; k < L; ++k) limb[(int64_t)k * ld + i] = x.m[k];
+}
+
+// (hi:lo) >> s for 0 <= s < 32
+MPD uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
+
+// ------------------------------------------------------------------------------------------
+// Exact L x L limb product: p = a * b (2L limbs).  Row i is a[i] * b formed with one 32x32->64
+// multiply-add per limb (the running carry is the added word), then added into p with a
+// carry chain.
+// ------------------------------------------------------------------------------------------
+template <int L>
+MPD void mul_full(const uint32_t (&a)[L], const uint32_t (&b)[L], uint32_t (&p)[2 * L]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    uint32_t row[L + 1];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      uint64_t t = (uint64_t)a[i] * b[j] + c;
+      row[j] = (uint32_t)t;
+      c = (uint32_t)(t >> 32);
+    }
+    row[L] = c;
+    if (i == 0) {
+#pragma unroll
+      for (int j = 0; j <= L; ++j) p[j] = row[j];
+    } else {
+      uint32_t cy = 0;
+#pragma unroll
+      for (int j = 0; j < L; ++j) p[i + j] = __builtin_addc(p[i + j], row[j], cy, &cy);
+      p[i + L] = row[L] + cy;
+    }
+  }
+}
+
+// Round the exact product (2L limbs, value P * 2^(e2 - 2p), P != 0 with its top bit at 2p-1 or
+// 2p-2) to p bits, ties to even.
+template <int L>
+MPD void round_product(const uint32_t (&pr)[2 * L], int32_t e2, uint32_t s, Num<L>& out,
+                       uint32_t& st) {
+  const bool top = (pr[2 * L - 1] >> 31) != 0;
+  uint32_t m[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) m[k] = top ? pr[L + k] : fshr(pr[L + k], pr[L + k - 1], 31);
+  uint32_t rnd = top ? (pr[L - 1] >> 31) : ((pr[L - 1] >> 30) & 1u);
+  uint32_t sticky = top ? (pr[L - 1] << 1) : (pr[L - 1] << 2);
+#pragma unroll
+  for (int k = 0; k < L - 1; ++k) sticky |= pr[k];
+  int32_t e = top ? e2 : e2 - 1;
+  uint32_t inc = rnd & (uint32_t)((sticky != 0) | (m[0] & 1u));
+  uint32_t cy = inc;
+#pragma unroll
+  for (int k = 0; k < L; ++k) m[k] = __builtin_addc(m[k], 0u, cy, &cy);
+  if (cy) {
+    m[L - 1] = 0x80000000u;
+    e += 1;
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = m[k];
+  out.e = e;
+  out.s = s;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, s);
+  }
+}
+
+// RN(a * b) with the zero fast path: a zero factor gives a zero with the xor sign.
+template <int L>
+MPD Num<L> mul_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
+  Num<L> r;
+  if (is_zero(a) || is_zero(b)) {
+    set_zero(r, a.s ^ b.s);
+    return r;
+  }
+  uint32_t pr[2 * L];
+  mul_full<L>(a.m, b.m, pr);
+  round_product<L>(pr, a.e + b.e, a.s ^ b.s, r, st);
+  return r;
+}
+
+// x (N limbs) >>= d, 0 <= d < 32N; bits shifted out are ORed into bit 0 (sticky).
+template <int N>
+MPD void shr_sticky(uint32_t (&x)[N], uint32_t d) {
+  const uint32_t q = d >> 5, r = d & 31u;
+  uint32_t sticky = 0;
+#pragma unroll
+  for (int bit = 1; bit < N; bit <<= 1) {
+    if (q & (uint32_t)bit) {
+#pragma unroll
+      for (int i = 0; i < bit; ++i) sticky |= x[i];
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = (i + bit < N) ? x[i + bit] : 0u;
+    }
+  }
+  sticky |= r ? (x[0] << (32u - r)) : 0u;
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i) x[i] = fshr(x[i + 1], x[i], r);
+  x[N - 1] >>= r;
+  x[0] |= (sticky != 0) ? 1u : 0u;
+}
+
+// x (N limbs) <<= d, 0 <= d < 32N
+template <int N>
+MPD void shl(uint32_t (&x)[N], uint32_t d) {
+  const uint32_t q = d >> 5, r = d & 31u;
+#pragma unroll
+  for (int bit = 1; bit < N; bit <<= 1) {
+    if (q & (uint32_t)bit) {
+#pragma unroll
+      for (int i = N - 1; i >= 0; --i) x[i] = (i >= bit) ? x[i - bit] : 0u;
+    }
+  }
+  if (r) {
+#pragma unroll
+    for (int i = N - 1; i >= 1; --i) x[i] = fshr(x[i], x[i - 1], 32u - r);
+    x[0] <<= r;
+  }
+}
+
+template <int N>
+MPD uint32_t clz_n(const uint32_t (&x)[N]) {
+  uint32_t lz = 0;
+  bool found = false;
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    if (!found) {
+      if (x[i]) {
+        lz += __clz(x[i]);
+        found = true;
+      } else {
+        lz += 32;
+      }
+    }
+  }
+  return lz;
+}
+
+// RN(a + b), IEEE/MPFR signed-zero rules for round-to-nearest.
+//
+// The operand with the larger exponent is X.  Both mantissas get one extra low limb (32 guard
+// bits); Y's is shifted right by the exponent difference d with the shifted-out bits ORed into
+// bit 0.  For d >= 2 an effective subtraction loses at most one leading bit, so that sticky
+// bit always stays below the round bit (bit 31 of the guard limb); for d <= 1 no bit is
+// shifted out and the difference is exact before normalisation.  For d >= p + 2, |Y| is below
+// a quarter of X's last unit and the result is X.
+template <int L>
+MPD Num<L> add_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
+  const bool az = is_zero(a), bz = is_zero(b);
+  if (az || bz) {
+    Num<L> r;
+    if (az && bz) {
+      set_zero(r, a.s & b.s);
+      return r;
+    }
+    return az ? b : a;
+  }
+  const bool sw = b.e > a.e;
+  Num<L> X, Y;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    X.m[k] = sw ? b.m[k] : a.m[k];
+    Y.m[k] = sw ? a.m[k] : b.m[k];
+  }
+  X.e = sw ? b.e : a.e;
+  Y.e = sw ? a.e : b.e;
+  X.s = sw ? b.s : a.s;
+  Y.s = sw ? a.s : b.s;
+  const uint32_t d = (uint32_t)(X.e - Y.e);
+  if (d >= (uint32_t)(32 * L + 2)) return X;
+
+  uint32_t xa[L + 1], ya[L + 1];
+  xa[0] = 0;
+  ya[0] = 0;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    xa[k + 1] = X.m[k];
+    ya[k + 1] = Y.m[k];
+  }
+  shr_sticky<L + 1>(ya, d);
+  int32_t e = X.e;
+  uint32_t s = X.s;
+  uint32_t r[L + 1];
+  if (X.s == Y.s) {
+    uint32_t cy = 0;
+#pragma unroll
+    for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(xa[k], ya[k], cy, &cy);
+    if (cy) {
+      const uint32_t lost = r[0] & 1u;
+#pragma unroll
+      for (int k = 0; k < L; ++k) r[k] = fshr(r[k + 1], r[k], 1);
+      r[L] = (r[L] >> 1) | 0x80000000u;
+      r[0] |= lost;
+      e += 1;
+    }
+  } else {
+    uint32_t bw = 0;
+#pragma unroll
+    for (int k = 0; k <= L; ++k) r[k] = __builtin_subc(xa[k], ya[k], bw, &bw);
+    if (bw) {  // only when d == 0 and |Y| > |X|
+      uint32_t c = 1;
+#pragma unroll
+      for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(~r[k], 0u, c, &c);
+      s ^= 1u;
+    }
+    const uint32_t lz = clz_n<L + 1>(r);
+    if (lz >= 32u * (L + 1)) {
+      Num<L> z;
+      set_zero(z, 0);
+      return z;
+    }
+    if (lz) shl<L + 1>(r, lz);
+    e -= (int32_t)lz;
+  }
+  const uint32_t rnd = r[0] >> 31;
+  const uint32_t sticky = r[0] & 0x7fffffffu;
+  Num<L> out;
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = r[k + 1];
+  uint32_t cy = rnd & (uint32_t)((sticky != 0) | (out.m[0] & 1u));
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = __builtin_addc(out.m[k], 0u, cy, &cy);
+  if (cy) {
+    out.m[L - 1] = 0x80000000u;
+    e += 1;
+  }
+  out.e = e;
+  out.s = s;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, s);
+  }
+  return out;
+}
+
+template <int L>
+MPD Num<L> neg(const Num<L>& a) {
+  Num<L> r = a;
+  r.s ^= 1u;
+  return r;
+}
+
+template <int L>
+MPD Num<L> sub_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
+  return add_rn<L>(a, neg<L>(b), st);
+}
+
+}  // namespace mp

@@ -1,0 +1,131 @@
+// Exact fixed-point accumulation of p-bit products ("superaccumulator") and its single final
+// rounding.
+//
+// A window is an array of signed 64-bit digits; digit w carries weight 2^(32 w + base).  Each
+// exact product (2L limbs) is shifted to its bit offset and its 32-bit pieces are added into the
+// digits without carry propagation (carry-save), so the order of additions never matters and
+// partial windows combine by plain integer addition.  With fewer than 2^31 addends per digit no
+// digit overflows.  Finalisation propagates carries once, takes the sign, locates the leading
+// bit and rounds to p bits with round and sticky bits: RN of the exact sum.
+#pragma once
+#include "mp_core.hpp"
+
+namespace mp {
+
+// Number of digits for products whose (e_a + e_b) spans [emin, emax]: the widest product sits
+// at digit offset (span >> 5) and occupies 2L + 1 digits after the bit shift; one more digit of
+// headroom absorbs the carries of up to 2^31 addends and the sign.
+template <int L>
+MPD int window_digits(int32_t emin, int32_t emax) {
+  return (int)(((uint32_t)(emax - emin)) >> 5) + 2 * L + 2;
+}
+
+// Shift the exact product P (2L limbs) left by r bits (0 <= r < 32) into 2L + 1 limbs.
+template <int L>
+MPD void shift_product(const uint32_t (&P)[2 * L], uint32_t r, uint32_t (&sp)[2 * L + 1]) {
+  sp[0] = P[0] << r;
+#pragma unroll
+  for (int j = 1; j < 2 * L; ++j) sp[j] = r ? fshr(P[j], P[j - 1], 32u - r) : P[j];
+  sp[2 * L] = r ? (P[2 * L - 1] >> (32u - r)) : 0u;
+}
+
+// win[w * ws] += (-1)^s * (P << off) split in 32-bit digits (no carry propagation).
+template <int L>
+MPD void window_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, uint32_t off) {
+  uint32_t sp[2 * L + 1];
+  shift_product<L>(P, off & 31u, sp);
+  const int q = (int)(off >> 5);
+#pragma unroll
+  for (int j = 0; j <= 2 * L; ++j) {
+    const int64_t v = s ? -(int64_t)sp[j] : (int64_t)sp[j];
+    win[(q + j) * ws] += v;
+  }
+}
+
+// Same, with atomic adds (a window shared by several lanes).
+template <int L>
+MPD void window_add_atomic(int64_t* win, const uint32_t (&P)[2 * L], uint32_t s, uint32_t off) {
+  uint32_t sp[2 * L + 1];
+  shift_product<L>(P, off & 31u, sp);
+  const int q = (int)(off >> 5);
+#pragma unroll
+  for (int j = 0; j <= 2 * L; ++j) {
+    if (sp[j]) {
+      const uint64_t v = s ? (uint64_t)(-(int64_t)sp[j]) : (uint64_t)sp[j];
+      atomicAdd((unsigned long long*)&win[q + j], (unsigned long long)v);
+    }
+  }
+}
+
+// RN_p of the window value sum_w win[w*ws] * 2^(32 w + base).  The digits are overwritten
+// (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
+template <int L>
+MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
+  int64_t c = 0;
+  for (int w = 0; w < W; ++w) {
+    const int64_t t = win[w * ws] + c;
+    win[w * ws] = (int64_t)(uint32_t)t;
+    c = t >> 32;
+  }
+  const uint32_t sgn = (c < 0) ? 1u : 0u;
+  if (sgn) {
+    uint32_t cy = 1;
+    for (int w = 0; w < W; ++w) {
+      const uint32_t v = __builtin_addc(~(uint32_t)win[w * ws], 0u, cy, &cy);
+      win[w * ws] = (int64_t)v;
+    }
+  }
+  int top = -1;
+  for (int w = W - 1; w >= 0; --w) {
+    if ((uint32_t)win[w * ws] != 0u) {
+      top = w;
+      break;
+    }
+  }
+  Num<L> out;
+  if (top < 0) {
+    set_zero(out, 0);
+    return out;
+  }
+  const int T = 32 * top + 31 - (int)__clz((uint32_t)win[top * ws]);  // leading bit index
+  const int b0 = T - 32 * L + 1;                                       // mantissa LSB index
+  auto limb_at = [&](int idx) -> uint32_t {
+    return (idx >= 0 && idx < W) ? (uint32_t)win[idx * ws] : 0u;
+  };
+  auto bits_at = [&](int b) -> uint32_t {  // the 32 bits starting at bit index b (b may be < 0)
+    if (b <= -32) return 0u;
+    if (b < 0) return limb_at(0) << (uint32_t)(-b);
+    const int i = b >> 5;
+    const uint32_t sh = (uint32_t)(b & 31);
+    return sh ? fshr(limb_at(i + 1), limb_at(i), sh) : limb_at(i);
+  };
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = bits_at(b0 + 32 * k);
+  uint32_t rnd = 0, sticky = 0;
+  const int rb = b0 - 1;
+  if (rb >= 0) {
+    rnd = (limb_at(rb >> 5) >> (rb & 31)) & 1u;
+    const int ri = rb >> 5;
+    const uint32_t below = (rb & 31) ? (limb_at(ri) & ((1u << (rb & 31)) - 1u)) : 0u;
+    sticky = below;
+    for (int w = 0; w < ri && !sticky; ++w) sticky |= limb_at(w);
+  }
+  int64_t e = (int64_t)b0 + base + 32 * L;
+  uint32_t cy = rnd & (uint32_t)((sticky != 0) | (out.m[0] & 1u));
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = __builtin_addc(out.m[k], 0u, cy, &cy);
+  if (cy) {
+    out.m[L - 1] = 0x80000000u;
+    e += 1;
+  }
+  out.s = sgn;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, sgn);
+    return out;
+  }
+  out.e = (int32_t)e;
+  return out;
+}
+
+}  // namespace mp

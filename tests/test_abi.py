@@ -1,0 +1,70 @@
+"""The C-ABI library loads, exports every symbol its header declares, and validates arguments on
+the host (no GPU needed for any of these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpspmv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1411_2377_amd import _lib
+    names = declared_functions()
+    assert "mpspmv_csr" in names and len(names) >= 4
+    for n in names:
+        assert hasattr(_lib.LIB, n), n
+        assert n in _lib.SIGNATURES or n in _lib.SPECIAL, "binding lacks a signature for %s" % n
+
+
+def test_host_validation_errors():
+    from paper_1411_2377_amd import _lib
+    a = _lib.MpCsr()
+    a.row_dim, a.col_dim, a.nnz, a.prec = 4, 4, 0, 100
+    a.row_ptr = 1234
+    a.val.len, a.val.ld = 0, 0
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL
+    assert "precision" in _lib.last_error()
+    a.prec = 256
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_OK
+    a.nnz = 3
+    a.val.len, a.val.ld = 3, 3
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL   # null col_idx
+    a.col_idx = 4321
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL   # null val pointers
+    a.val.limb, a.val.hdr = 1000, 2000
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_OK
+    a.val.ld = 2
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL   # ld < len
+    a.val.ld = 3
+    a.row_dim = -1
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL
+    a.row_dim = 4
+    # SpMV argument checks happen before any device work
+    x = _lib.MpVec(5000, 6000, 3, 3)   # wrong length (col_dim = 4)
+    y = _lib.MpVec(7000, 8000, 4, 4)
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 0, None) == _lib.MPS_EINVAL
+    x.len, x.ld = 4, 4
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 7, None) == _lib.MPS_EINVAL
+    assert "mode" in _lib.last_error()
+    yy = _lib.MpVec(5000, 6000, 4, 4)   # aliases x
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(yy), 0, None) == _lib.MPS_EINVAL
+    assert "overlap" in _lib.last_error()
+
+
+@pytest.mark.parametrize("prec", [64, 96, 1024, 0])
+def test_unsupported_precisions_rejected(prec):
+    from paper_1411_2377_amd import _lib
+    a = _lib.MpCsr()
+    a.row_dim, a.col_dim, a.nnz, a.prec = 1, 1, 0, prec
+    a.row_ptr = 1
+    assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL

@@ -1,0 +1,167 @@
+"""GPU parity of y = A x (SEQ and EXACT) against the oracle, bit for bit.
+
+Sizes: the random-CSR workload in full; edge-case matrices spanning several 64-row blocks and
+128-entry chunks with a ragged tail; the convection-diffusion and power-law workloads at full
+size, checked on sampled rows (always including the first, last and longest rows).
+"""
+import random
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import codec, mpnum
+from oracle.mpnum import MP
+from tests.util import assert_bitwise, oracle_spmv_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    import paper_1411_2377_amd as M
+    return M
+
+
+def run(A_host, x_host, mode):
+    M = lib()
+    A = M.CSRMatrix.from_host(A_host)
+    x = M.MPArray.from_host(x_host)
+    y = M.mpspmv_csr(A, x, mode=mode)
+    assert M.mp_status() == 0
+    return y.to_numpy()
+
+
+def edge_problem(p, seed, n=333, m=301):
+    """Rows of every kind: empty, single, short, multi-chunk (> 128 entries); stored zeros,
+    -0 entries, exponent spreads from 0 to ~2000 bits (the widest rows need the block-shared
+    window), exact cancellations leaving a tiny remainder, all-ones mantissas."""
+    rng = random.Random(seed)
+
+    def rnd(e_lo, e_hi):
+        return MP(rng.randint(0, 1), rng.getrandbits(p) | (1 << (p - 1)), rng.randint(e_lo, e_hi), p)
+    x = []
+    for j in range(m):
+        r = rng.random()
+        if j < 40 and j % 2 == 1:
+            x.append(x[j - 1])                      # equal pairs for exact cancellations
+        elif r < 0.05:
+            x.append(mpnum.zero(p, rng.randint(0, 1)))
+        elif r < 0.1:
+            x.append(MP(rng.randint(0, 1), (1 << p) - 1, rng.randint(-5, 5), p))
+        else:
+            x.append(rnd(-20, 20))
+    rp, ci, vals = [0], [], []
+    for i in range(n):
+        kind = i % 11
+        row = {}
+        if kind == 9:
+            for t in rng.sample(range(20), 4):      # a x_2t - a x_2t+1 = 0 exactly
+                v = rnd(-3, 3)
+                row[2 * t] = v
+                row[2 * t + 1] = v.neg()
+            row[rng.randrange(40, m)] = rnd(-150, -100)
+        else:
+            k = {0: 0, 1: 1, 2: rng.randint(129, 300)}.get(kind, rng.randint(2, 24))
+            spread = {3: 0, 4: 3, 5: 40, 6: 200, 7: 1000, 8: 2000}.get(kind, 10)
+            for c in rng.sample(range(m), min(k, m)):
+                if rng.random() < 0.08:
+                    row[c] = mpnum.zero(p, rng.randint(0, 1))
+                else:
+                    row[c] = rnd(-spread, spread) if spread else rnd(0, 0)
+        for c in sorted(row):
+            ci.append(c)
+            vals.append(row[c])
+        rp.append(len(ci))
+    vl, vh = codec.encode(vals, p)
+    xl, xh = codec.encode(x, p)
+    A = synth.CSRHost(n, m, np.array(rp, np.int32), np.array(ci, np.int32), synth.MPHost(vl, vh, p))
+    return A, synth.MPHost(xl, xh, p)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_random_csr_workload_full(mode):
+    A, x = synth.config1()
+    yl, yh = run(A, x, mode)
+    want = oracle_spmv_rows(A, x, np.arange(A.n_rows), mode)
+    assert_bitwise(yl, yh, want, A.vals.p, what="config1")
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_edge_cases(p, mode):
+    A, x = edge_problem(p, seed=p + mode)
+    yl, yh = run(A, x, mode)
+    want = oracle_spmv_rows(A, x, np.arange(A.n_rows), mode)
+    assert_bitwise(yl, yh, want, p, what="edge p=%d" % p)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_convdiff_full_size_sampled(mode):
+    A, ones = synth.config2()
+    rng = np.random.default_rng(0)
+    x = synth.mp_uniform(rng, A.n_cols, A.vals.p)
+    yl, yh = run(A, x, mode)
+    rows = np.unique(np.concatenate([[0, 1, 255, 256, A.n_rows - 1], rng.integers(0, A.n_rows, 300)]))
+    want = oracle_spmv_rows(A, x, rows, mode)
+    assert_bitwise(yl, yh, want, A.vals.p, rows=rows, what="config2")
+    # A * ones in EXACT mode as the solver right-hand side: spot rows again
+    yl1, yh1 = run(A, ones, 1)
+    want1 = oracle_spmv_rows(A, ones, rows, 1)
+    assert_bitwise(yl1, yh1, want1, A.vals.p, rows=rows, what="config2 A*1")
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_powerlaw_full_size_sampled(p, mode):
+    A, x, g = synth.config3(p=p)
+    yl, yh = run(A, x, mode)
+    lengths = np.diff(A.row_ptr)
+    rng = np.random.default_rng(p)
+    rows = np.unique(np.concatenate([[0, A.n_rows - 1, int(np.argmax(lengths))],
+                                     np.argsort(lengths)[-5:], rng.integers(0, A.n_rows, 60)]))
+    want = oracle_spmv_rows(A, x, rows, mode)
+    assert_bitwise(yl, yh, want, p, rows=rows, what="config3 p=%d" % p)
+
+
+def test_deterministic_and_invariants():
+    M = lib()
+    A_h, x_h = synth.config1(p=256)
+    A = M.CSRMatrix.from_host(A_h)
+    x = M.MPArray.from_host(x_h)
+    for mode in (0, 1):
+        y1 = M.mpspmv_csr(A, x, mode=mode).to_numpy()
+        y2 = M.mpspmv_csr(A, x, mode=mode).to_numpy()
+        assert np.array_equal(y1[0], y2[0]) and np.array_equal(y1[1], y2[1])
+        # x = 0 (with -0 entries) gives +0 everywhere
+        z = M.MPArray.zeros(A.n_cols, 256)
+        z.hdr[1::2] = -(1 << 31) + 1
+        yz = M.mpspmv_csr(A, z, mode=mode).to_numpy()
+        assert np.all(yz[1] == np.int32(-(1 << 31)))
+        # scaling x by 2^k scales y by 2^k exactly
+        xs = x.clone()
+        nz = (xs.hdr >> 1) != -(1 << 30)
+        xs.hdr[nz] += 2 * 7
+        ys = M.mpspmv_csr(A, xs, mode=mode).to_numpy()
+        nzy = (y1[1] >> 1) != -(1 << 30)
+        assert np.array_equal(ys[0], y1[0])
+        assert np.array_equal(ys[1][nzy], y1[1][nzy] + 14)
+
+
+def test_empty_shapes():
+    M = lib()
+    p = 128
+    # nnz = 0 with rows: y = +0
+    A = M.CSRMatrix(5, 3, torch.zeros(6, dtype=torch.int32, device="cuda"),
+                    torch.zeros(0, dtype=torch.int32, device="cuda"), M.MPArray.empty(0, p))
+    x = M.MPArray.zeros(3, p)
+    y = M.mpspmv_csr(A, x, mode=1).to_numpy()
+    assert np.all(y[1] == np.int32(-(1 << 31)))
+    y = M.mpspmv_csr(A, x, mode=0).to_numpy()
+    assert np.all(y[1] == np.int32(-(1 << 31)))
+    # zero rows: nothing to do
+    A0 = M.CSRMatrix(0, 3, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                     torch.zeros(0, dtype=torch.int32, device="cuda"), M.MPArray.empty(0, p))
+    M.mpspmv_csr(A0, x, mode=0)
+    torch.cuda.synchronize()
