@@ -81,6 +81,42 @@ typedef struct {
   mp_vec val;              /* [nnz] */
 } mp_csr;
 
+/* Opaque transposed-product plan: the CSR of A^T (rows = columns of A, entries in ascending
+ * original-row order, built from the per-column non-zero counts of the paper's sparse
+ * structure, Sec. 2) with A's values permuted into it.  Owned by the library. */
+typedef struct mp_plan mp_plan;
+
+/* Solver options.  Tolerances are decimal m * 10^e, turned into p-bit constants by exact
+ * rounding: the stopping test (*) of Sec. 4.1 is ||r_k||_2 <= c_rel ||r_0||_2 + c_abs with
+ * c_rel = RN_p(rtol_m 10^rtol_e10), c_abs = RN_p(atol_m 10^atol_e10) (the paper: 1e-20, 1e-50). */
+typedef struct {
+  int32_t mode;       /* MP_SEQ or MP_EXACT, for every product with A and A^T */
+  int32_t transpose;  /* 0: solve A x = b; 1: solve A^T x = b (needs the plan) */
+  int64_t maxit;      /* iteration limit (>= 0); reaching it returns MP_NC */
+  int64_t rtol_m, rtol_e10;
+  int64_t atol_m, atol_e10;
+  int32_t chunk;      /* iterations per host poll of the device done flag, replayed from one
+                         captured HIP graph; <= 0 launches every kernel eagerly instead.
+                         Results are bit-identical for every value. */
+  int32_t use_x0;     /* 0: x0 = +0 and x is output only; 1: x holds x0 on entry */
+  mp_vec *res_hist;   /* nullable; element i-1 receives RN(r_i . r_i) after iteration i (up to
+                         res_hist->len entries) — the residual history of Fig. 7 squared */
+} mp_solve_opts;
+
+/* solver outcome (mp_solve_info.status) */
+#define MP_CONVERGED 0
+#define MP_NC 1              /* not convergent within maxit (Tables 1-2: "NC") */
+#define MP_BREAKDOWN_RHO 2   /* rho = 0: the listings' "exits" */
+#define MP_BREAKDOWN_SIGMA 3 /* the denominator of alpha is 0 */
+#define MP_BREAKDOWN_ZETA 4  /* GPBiCG: zeta = 0 */
+#define MP_BREAKDOWN_TAU 5   /* GPBiCG: tau = 0 (or mu5 = 0 in the first iteration) */
+
+typedef struct {
+  int32_t status;        /* MP_CONVERGED ... */
+  int64_t iters;         /* completed iterations */
+  double final_rel_res;  /* ||r|| / ||r_0|| in double, for display only */
+} mp_solve_info;
+
 /* Message describing the last error returned on the calling thread ("" if none). */
 const char *mp_last_error(void);
 
@@ -93,6 +129,48 @@ int mp_validate_csr(const mp_csr *A, int check_device_data);
 /* y = A x (Sec. 2-3 of the paper) in the given mode.  x.len == col_dim, y.len == row_dim, all
  * at A->prec.  y must not overlap x or A.  Asynchronous on `stream`. */
 int mpspmv_csr(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, void *stream);
+
+/* Build the transposed-product plan of A (synchronises `stream`; allocates device memory).
+ * The plan records A's shape and precision; its values are a copy: after changing A's values
+ * in place call mp_plan_refresh.  Returns MPS_OK, MPS_EINVAL or MPS_ENOMEM. */
+int mp_plan_create(const mp_csr *A, void *stream, mp_plan **plan);
+int mp_plan_destroy(mp_plan *plan);
+int mp_plan_refresh(mp_plan *plan, const mp_csr *A, void *stream);
+
+/* y = A^T x, computed as the product with the plan's explicit transpose (SEQ sums over the
+ * original rows in ascending order).  x.len == row_dim, y.len == col_dim. */
+int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp_plan *plan,
+                 void *stream);
+
+/* gvals_k = RN(g_i x_j) for each stored entry k = (i, j) in A's CSR order (negated when
+ * negate != 0): the gradient of <g, A x> with respect to the stored values.  Needs the plan
+ * (for the row of each entry).  g.len == row_dim, x.len == col_dim, gvals.len == nnz. */
+int mp_grad_vals(const mp_csr *A, const mp_plan *plan, const mp_vec *g, const mp_vec *x,
+                 mp_vec *gvals, int negate, void *stream);
+
+/* y_i <- RN(y_i + RN(alpha x_i)); alpha is a one-element device vector (the x + alpha p lines
+ * of Fig. 5).  x.len == y.len. */
+int mp_axpy(const mp_vec *alpha, const mp_vec *x, mp_vec *y, int prec, void *stream);
+
+/* out[0] = RN(sum_i x_i y_i), the sum formed exactly (the inner products of Fig. 5).  Uses a
+ * per-device workspace: calls on different streams of one device must not overlap. */
+int mp_dot(const mp_vec *x, const mp_vec *y, mp_vec *out, int prec, void *stream);
+
+/* out[0] = RN_p(m * 10^e10), |e10| <= 2000 (exact rounding of a decimal constant). */
+int mp_const_decimal(int64_t m, int64_t e10, int prec, mp_vec *out, void *stream);
+
+/* BiCG (Fig. 5 left, K = I) for A x = b (or A^T x = b).  The plan is used for the products
+ * with A^T; pass NULL to have one built and freed inside the call.  Synchronous: returns
+ * after the solve with *info filled.  Returns MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_EHIP, or
+ * MPS_ERANGE / MPS_ENOTSUP when a device condition was raised during the solve. */
+int bicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
+         const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
+/* GPBiCG (Fig. 5 right; Zhang's updates z = zeta r + eta z - alpha u and
+ * r = t - eta y - zeta A t).  Same conventions as bicg; the plan is needed only when
+ * opts->transpose != 0 (NULL: built inside the call). */
+int gpbicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
+           const mp_solve_opts *opts, mp_solve_info *info, void *stream);
 
 /* Synchronise `stream`, then read and clear the calling device's status word into *flags
  * (MP_ST_* bits).  Returns MPS_OK, or MPS_ERANGE / MPS_ENOTSUP when such a bit was set. */

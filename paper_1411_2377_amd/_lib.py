@@ -80,6 +80,23 @@ SIGNATURES = {
     "mpspmv_csr": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                    ctypes.c_int, ctypes.c_void_p],
     "mp_status": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
+    "mp_plan_create": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "mp_plan_destroy": [ctypes.c_void_p],
+    "mp_plan_refresh": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_void_p],
+    "mpspmv_csr_t": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+                     ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "mp_grad_vals": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec),
+                     ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int, ctypes.c_void_p],
+    "mp_axpy": [ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
+                ctypes.c_void_p],
+    "mp_dot": [ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
+               ctypes.c_void_p],
+    "mp_const_decimal": [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(MpVec),
+                         ctypes.c_void_p],
+    "bicg": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+             ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "gpbicg": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+               ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
 }
 OPTIONAL = {}
 # symbols bound by hand above (non-int return types)

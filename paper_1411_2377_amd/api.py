@@ -39,3 +39,132 @@ def mp_status(stream=None, raise_on_error=True):
     if raise_on_error:
         check(code)
     return int(flags.value)
+
+
+class Plan:
+    """Transposed-product plan of a CSRMatrix (owns library memory; freed on close/GC)."""
+
+    def __init__(self, A, stream=None):
+        self.A = A
+        self._h = ctypes.c_void_p()
+        d = A.desc()
+        check(_lib.LIB.mp_plan_create(ctypes.byref(d), _stream(stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def refresh(self, stream=None):
+        d = self.A.desc()
+        check(_lib.LIB.mp_plan_refresh(self._h, ctypes.byref(d), _stream(stream)))
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.LIB.mp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mp_plan_create(A, stream=None):
+    return Plan(A, stream)
+
+
+def mpspmv_csr_t(A, plan, x, y=None, mode=MP_SEQ, stream=None):
+    """y = A^T x (with the plan's explicit transpose); allocates y when not given."""
+    if y is None:
+        y = MPArray.empty(A.n_cols, A.p, device=x.device)
+    a, xd, yd = A.desc(), x.desc(), y.desc()
+    check(_lib.LIB.mpspmv_csr_t(ctypes.byref(a), ctypes.byref(xd), ctypes.byref(yd), int(mode),
+                                plan.handle, _stream(stream)))
+    return y
+
+
+def mp_grad_vals(A, plan, g, x, out=None, negate=False, stream=None):
+    """out_k = RN(g_i x_j) for each stored entry k = (i, j) (negated if asked)."""
+    if out is None:
+        out = MPArray.empty(A.nnz, A.p, device=x.device)
+    a, gd, xd, od = A.desc(), g.desc(), x.desc(), out.desc()
+    check(_lib.LIB.mp_grad_vals(ctypes.byref(a), plan.handle, ctypes.byref(gd), ctypes.byref(xd),
+                                ctypes.byref(od), int(bool(negate)), _stream(stream)))
+    return out
+
+
+def mp_axpy(alpha, x, y, stream=None):
+    """y <- y + alpha x (alpha a one-element MPArray), in place."""
+    ad, xd, yd = alpha.desc(), x.desc(), y.desc()
+    check(_lib.LIB.mp_axpy(ctypes.byref(ad), ctypes.byref(xd), ctypes.byref(yd), int(y.p),
+                           _stream(stream)))
+    return y
+
+
+def mp_dot(x, y, out=None, stream=None):
+    """out = RN(sum x_i y_i) as a one-element MPArray."""
+    if out is None:
+        out = MPArray.empty(1, x.p, device=x.device)
+    xd, yd, od = x.desc(), y.desc(), out.desc()
+    check(_lib.LIB.mp_dot(ctypes.byref(xd), ctypes.byref(yd), ctypes.byref(od), int(x.p),
+                          _stream(stream)))
+    return out
+
+
+def mp_const_decimal(m, e10, p, device="cuda", stream=None):
+    """RN_p(m * 10^e10) as a one-element MPArray."""
+    out = MPArray.empty(1, p, device=device)
+    od = out.desc()
+    check(_lib.LIB.mp_const_decimal(int(m), int(e10), int(p), ctypes.byref(od), _stream(stream)))
+    return out
+
+
+class SolveInfo:
+    def __init__(self, status, iters, final_rel_res, hist=None):
+        self.status = status
+        self.iters = iters
+        self.final_rel_res = final_rel_res
+        self.res_hist = hist
+
+    def __repr__(self):
+        return "SolveInfo(status=%d, iters=%d, rel_res=%.3g)" % (self.status, self.iters,
+                                                                  self.final_rel_res)
+
+
+def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50),
+           chunk=16, transpose=False, x0=None, hist=False, stream=None):
+    if x is None:
+        x = MPArray.empty(A.n_rows, A.p, device=b.device)
+    use_x0 = 0
+    if x0 is not None:
+        x.copy_(x0)
+        use_x0 = 1
+    o = _lib.MpSolveOpts()
+    o.mode = int(mode)
+    o.transpose = int(bool(transpose))
+    o.maxit = int(maxit)
+    o.rtol_m, o.rtol_e10 = int(rtol[0]), int(rtol[1])
+    o.atol_m, o.atol_e10 = int(atol[0]), int(atol[1])
+    o.chunk = int(chunk)
+    o.use_x0 = use_x0
+    hist_arr = None
+    if hist:
+        hist_arr = MPArray.zeros(max(1, int(maxit)), A.p, device=b.device)
+        hd = hist_arr.desc()
+        o.res_hist = ctypes.pointer(hd)
+    info = _lib.MpSolveInfo()
+    a, bd, xd = A.desc(), b.desc(), x.desc()
+    check(fn(ctypes.byref(a), plan.handle if plan is not None else None, ctypes.byref(bd),
+             ctypes.byref(xd), ctypes.byref(o), ctypes.byref(info), _stream(stream)))
+    return x, SolveInfo(info.status, info.iters, info.final_rel_res, hist_arr)
+
+
+def bicg(A, b, **kw):
+    """BiCG (K = I) for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
+    return _solve(_lib.LIB.bicg, A, b, **kw)
+
+
+def gpbicg(A, b, **kw):
+    """GPBiCG for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
+    return _solve(_lib.LIB.gpbicg, A, b, **kw)

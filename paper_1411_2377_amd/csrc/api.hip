@@ -49,6 +49,13 @@ int get_ctx(DeviceCtx** out) {
     }
     e = hipMemset(c->status, 0, sizeof(uint32_t) * 4);
     if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
+    e = hipMalloc((void**)&c->dot_part, dot_workspace_bytes());
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dot_ticket, 64);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->scal_limb, 16 * 32 * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->scal_hdr, 32 * 4);
+    if (e != hipSuccess) return fail(MPS_ENOMEM, "context workspace: %s", hipGetErrorString(e));
+    e = hipMemset(c->dot_ticket, 0, 64);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(ticket)");
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     g_ctx[dev] = c;
@@ -135,8 +142,8 @@ static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
 }
 
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
-                const mp_vec& val, const mp_vec& x, mp_vec& y, int mode, uint32_t* status,
-                hipStream_t s) {
+                const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
+                const int32_t* done, hipStream_t s) {
   if (n_rows == 0) return MPS_OK;
   mp::SpmvArgs a;
   a.n_rows = n_rows;
@@ -152,6 +159,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.y_hdr = y.hdr;
   a.y_ld = y.ld;
   a.status = status;
+  a.done = done;
   switch (L) {
     case 4: launch_spmv<4>(a, mode, s); break;
     case 8: launch_spmv<8>(a, mode, s); break;
@@ -189,7 +197,7 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stre
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
-                     (hipStream_t)stream);
+                     nullptr, (hipStream_t)stream);
 }
 
 int mp_status(void* stream, uint32_t* flags) {

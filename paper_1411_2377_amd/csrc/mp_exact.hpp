@@ -12,6 +12,10 @@
 
 namespace mp {
 
+// Per-lane private window size used by the fast paths (spans up to 8 digits of exponent).
+template <int L>
+constexpr int window_fast_digits() { return 2 * L + 10; }
+
 // Number of digits for products whose (e_a + e_b) spans [emin, emax]: the widest product sits
 // at digit offset (span >> 5) and occupies 2L + 1 digits after the bit shift; one more digit of
 // headroom absorbs the carries of up to 2^31 addends and the sign.

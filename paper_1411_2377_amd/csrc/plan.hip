@@ -1,0 +1,279 @@
+// Transposed-product plan (CSR of A^T), A^T x, and the value gradient of a product.
+//
+// The plan is the explicit transpose in CSR form whose rows (the columns of A) list their
+// entries in ascending original-row order, so a SEQ product with A^T accumulates in that order.
+// It is built once: a stable radix sort of the entry indices by column (rocPRIM), the per-column
+// entry counts (the paper's per-column non-zero numbers of its sparse structure, Sec. 2) and
+// their prefix sum, and a gather of the values into structure-of-arrays order.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <rocprim/rocprim.hpp>
+
+#include "../../include/mpspmv.h"
+#include "api_internal.hpp"
+#include "mp_core.hpp"
+#include "plan_internal.hpp"
+
+namespace {
+
+__global__ void row_of_kernel(const int32_t* __restrict__ row_ptr, int64_t n_rows,
+                              int32_t* __restrict__ row_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) row_of[k] = (int32_t)i;
+}
+
+__global__ void iota_kernel(int32_t* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int32_t)i;
+}
+
+__global__ void count_kernel(const int32_t* __restrict__ col_idx, int64_t nnz,
+                             int32_t* __restrict__ counts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) atomicAdd(&counts[col_idx[k]], 1);
+}
+
+__global__ void transposed_index_kernel(const int32_t* __restrict__ perm,
+                                        const int32_t* __restrict__ row_of, int64_t nnz,
+                                        int32_t* __restrict__ t_col) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nnz) t_col[t] = row_of[perm[t]];
+}
+
+template <int L>
+__global__ void gather_values_kernel(const int32_t* __restrict__ perm, int64_t nnz,
+                                     const uint32_t* __restrict__ src_limb,
+                                     const int32_t* __restrict__ src_hdr, int64_t src_ld,
+                                     uint32_t* __restrict__ dst_limb, int32_t* __restrict__ dst_hdr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  const int64_t k = perm[t];
+  dst_hdr[t] = src_hdr[k];
+#pragma unroll
+  for (int q = 0; q < L; ++q) dst_limb[(int64_t)q * nnz + t] = src_limb[(int64_t)q * src_ld + k];
+}
+
+// gvals_k = (-1)^neg * RN(g_i x_j) for entry k = (i, j), in CSR order of A.
+template <int L>
+__global__ void grad_vals_kernel(int64_t nnz, const int32_t* __restrict__ row_of,
+                                 const int32_t* __restrict__ col_idx, const uint32_t* g_limb,
+                                 const int32_t* g_hdr, int64_t g_ld, const uint32_t* x_limb,
+                                 const int32_t* x_hdr, int64_t x_ld, uint32_t* out_limb,
+                                 int32_t* out_hdr, int64_t out_ld, uint32_t neg, uint32_t* status) {
+  uint32_t st = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    mp::Num<L> g, x;
+    mp::load<L>(g, g_limb, g_hdr, g_ld, row_of[k]);
+    mp::load<L>(x, x_limb, x_hdr, x_ld, col_idx[k]);
+    mp::Num<L> r = mp::mul_rn<L>(g, x, st);
+    r.s ^= neg;
+    mp::store<L>(r, out_limb, out_hdr, out_ld, k);
+  }
+  if (st) atomicOr(status, st);
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+namespace mpapi {
+
+int plan_free(mp_plan* P) {
+  if (!P) return MPS_OK;
+  hipFree(P->t_row_ptr);
+  hipFree(P->t_col_idx);
+  hipFree(P->perm);
+  hipFree(P->row_of);
+  hipFree(P->t_limb);
+  hipFree(P->t_hdr);
+  delete P;
+  return MPS_OK;
+}
+
+int plan_gather(mp_plan* P, const mp_csr* A, hipStream_t s) {
+  if (P->nnz == 0) return MPS_OK;
+  const unsigned g = blocks_for(P->nnz, 256);
+  switch (P->L) {
+    case 4: hipLaunchKernelGGL(gather_values_kernel<4>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
+    case 8: hipLaunchKernelGGL(gather_values_kernel<8>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
+    case 16: hipLaunchKernelGGL(gather_values_kernel<16>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "gather launch");
+}
+
+int plan_build(const mp_csr* A, hipStream_t s, mp_plan** out) {
+  mp_plan* P = new mp_plan();
+  P->L = limbs_of(A->prec);
+  P->prec = A->prec;
+  P->n_rows = A->row_dim;
+  P->n_cols = A->col_dim;
+  P->nnz = A->nnz;
+  hipGetDevice(&P->device);
+  const int64_t nnz = A->nnz;
+  hipError_t e;
+#define MPS_ALLOC(ptr, bytes)                                          \
+  e = hipMalloc((void**)&(ptr), (bytes) > 0 ? (bytes) : 4);            \
+  if (e != hipSuccess) {                                               \
+    plan_free(P);                                                      \
+    return fail(MPS_ENOMEM, "plan allocation: %s", hipGetErrorString(e)); \
+  }
+  MPS_ALLOC(P->t_row_ptr, (A->col_dim + 1) * 4);
+  MPS_ALLOC(P->t_col_idx, nnz * 4);
+  MPS_ALLOC(P->perm, nnz * 4);
+  MPS_ALLOC(P->row_of, nnz * 4);
+  MPS_ALLOC(P->t_limb, nnz * 4 * P->L);
+  MPS_ALLOC(P->t_hdr, nnz * 4);
+#undef MPS_ALLOC
+  e = hipMemsetAsync(P->t_row_ptr, 0, (A->col_dim + 1) * 4, s);
+  if (e != hipSuccess) { plan_free(P); return hip_fail(e, "hipMemsetAsync"); }
+  if (nnz > 0) {
+    uint32_t* keys_out = nullptr;
+    int32_t* iota = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    e = hipMalloc((void**)&keys_out, nnz * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&iota, nnz * 4);
+    if (e != hipSuccess) {
+      hipFree(keys_out);
+      plan_free(P);
+      return fail(MPS_ENOMEM, "plan scratch: %s", hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(row_of_kernel, dim3(blocks_for(A->row_dim, 256)), dim3(256), 0, s,
+                       A->row_ptr, A->row_dim, P->row_of);
+    hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, iota, nnz);
+    hipLaunchKernelGGL(count_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, A->col_idx,
+                       nnz, P->t_row_ptr + 1);
+    // stable sort of entry indices by column: ties keep ascending entry (= row) order
+    unsigned end_bit = 1;
+    while (end_bit < 31 && ((int64_t)1 << end_bit) < A->col_dim) ++end_bit;
+    size_t scan_bytes = 0;
+    e = rocprim::radix_sort_pairs(nullptr, temp_bytes, (const uint32_t*)A->col_idx, keys_out,
+                                  (const int32_t*)iota, P->perm, (size_t)nnz, 0, end_bit, s);
+    if (e == hipSuccess)
+      e = rocprim::inclusive_scan(nullptr, scan_bytes, P->t_row_ptr + 1, P->t_row_ptr + 1,
+                                  (size_t)A->col_dim, rocprim::plus<int32_t>(), s);
+    if (scan_bytes > temp_bytes) temp_bytes = scan_bytes;
+    if (e == hipSuccess) e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 4);
+    if (e == hipSuccess)
+      e = rocprim::radix_sort_pairs(temp, temp_bytes, (const uint32_t*)A->col_idx, keys_out,
+                                    (const int32_t*)iota, P->perm, (size_t)nnz, 0, end_bit, s);
+    // per-column counts -> row pointers of A^T (the sort is done with temp: same stream order)
+    if (e == hipSuccess)
+      e = rocprim::inclusive_scan(temp, scan_bytes, P->t_row_ptr + 1, P->t_row_ptr + 1,
+                                  (size_t)A->col_dim, rocprim::plus<int32_t>(), s);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(transposed_index_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, s,
+                         P->perm, P->row_of, nnz, P->t_col_idx);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    else hipStreamSynchronize(s);
+    hipFree(temp);
+    hipFree(keys_out);
+    hipFree(iota);
+    if (e != hipSuccess) {
+      plan_free(P);
+      return hip_fail(e, "plan build");
+    }
+  }
+  int r = plan_gather(P, A, s);
+  if (r) {
+    plan_free(P);
+    return r;
+  }
+  *out = P;
+  return MPS_OK;
+}
+
+int check_plan(const mp_plan* P, const mp_csr* A) {
+  if (!P) return fail(MPS_EINVAL, "plan is required");
+  if (P->n_rows != A->row_dim || P->n_cols != A->col_dim || P->nnz != A->nnz || P->prec != A->prec)
+    return fail(MPS_EINVAL, "plan was built for a different matrix");
+  return MPS_OK;
+}
+
+int grad_vals_launch(const mp_csr* A, const mp_plan* P, const mp_vec* g, const mp_vec* x,
+                     mp_vec* out, int negate, uint32_t* status, hipStream_t s) {
+  if (A->nnz == 0) return MPS_OK;
+  const unsigned grid = (unsigned)std::min<int64_t>(blocks_for(A->nnz, 256), 65536);
+  const uint32_t neg = negate ? 1u : 0u;
+  switch (P->L) {
+    case 4: hipLaunchKernelGGL(grad_vals_kernel<4>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 8: hipLaunchKernelGGL(grad_vals_kernel<8>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 16: hipLaunchKernelGGL(grad_vals_kernel<16>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "grad_vals launch");
+}
+
+}  // namespace mpapi
+
+using namespace mpapi;
+
+extern "C" {
+
+int mp_plan_create(const mp_csr* A, void* stream, mp_plan** plan) {
+  clear_error();
+  if (!plan) return fail(MPS_EINVAL, "plan: null output pointer");
+  *plan = nullptr;
+  int r = check_csr(A, 0);
+  if (r) return r;
+  return plan_build(A, (hipStream_t)stream, plan);
+}
+
+int mp_plan_destroy(mp_plan* plan) {
+  clear_error();
+  if (plan) hipDeviceSynchronize();
+  return plan_free(plan);
+}
+
+int mp_plan_refresh(mp_plan* plan, const mp_csr* A, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  return plan_gather(plan, A, (hipStream_t)stream);
+}
+
+int mpspmv_csr_t(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_plan* plan,
+                 void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if ((r = check_vec(x, A->row_dim, "x"))) return r;
+  if ((r = check_vec(y, A->col_dim, "y"))) return r;
+  const int L = limbs_of(A->prec);
+  if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L)) return fail(MPS_EINVAL, "y overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  mp_vec tv;
+  tv.limb = plan->t_limb;
+  tv.hdr = plan->t_hdr;
+  tv.len = plan->nnz;
+  tv.ld = plan->nnz;
+  return spmv_launch(L, A->col_dim, plan->t_row_ptr, plan->t_col_idx, tv, *x, *y, mode,
+                     ctx->status, nullptr, (hipStream_t)stream);
+}
+
+int mp_grad_vals(const mp_csr* A, const mp_plan* plan, const mp_vec* g, const mp_vec* x,
+                 mp_vec* gvals, int negate, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  if ((r = check_vec(g, A->row_dim, "g"))) return r;
+  if ((r = check_vec(x, A->col_dim, "x"))) return r;
+  if ((r = check_vec(gvals, A->nnz, "gvals"))) return r;
+  const int L = limbs_of(A->prec);
+  if (vec_overlap(g, gvals, L) || vec_overlap(x, gvals, L)) return fail(MPS_EINVAL, "gvals overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  return grad_vals_launch(A, plan, g, x, gvals, negate, ctx->status, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,576 @@
+// BiCG and GPBiCG drivers (Kouya, Fig. 5 with K = I; stopping test (*) of Sec. 4.1).
+//
+// The whole iteration stays on the device: the scalars (rho, alpha, beta, zeta, eta, ...) are
+// formed by the epilogues of the inner-product kernels, the stopping test is the exact integer
+// comparison q < (thr + ulp/2)^2 (no square root per iteration), and a done flag turns every
+// later kernel into a no-op.  One iteration is captured as a HIP graph and replayed `chunk`
+// times between host polls of the 32-byte control block; since replays past the stopping point
+// do nothing, every result is bit-identical for every chunk size (and for eager launches).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "../../include/mpspmv.h"
+#include "api_internal.hpp"
+#include "plan_internal.hpp"
+#include "solver_kernels.hpp"
+#include "vec_internal.hpp"
+
+namespace mpapi {
+
+// ---- exact decimal constants: RN_p(m * 10^e) --------------------------------------------
+namespace {
+
+struct Big {
+  std::vector<uint32_t> d;  // little endian
+  int bits() const {
+    for (int i = (int)d.size() - 1; i >= 0; --i)
+      if (d[i]) return 32 * i + 32 - __builtin_clz(d[i]);
+    return 0;
+  }
+  int bit(int i) const {
+    const int w = i >> 5;
+    return (w < (int)d.size()) ? (int)((d[w] >> (i & 31)) & 1u) : 0;
+  }
+  void mul_small(uint32_t m) {
+    uint64_t c = 0;
+    for (auto& x : d) {
+      const uint64_t t = (uint64_t)x * m + c;
+      x = (uint32_t)t;
+      c = t >> 32;
+    }
+    if (c) d.push_back((uint32_t)c);
+  }
+  void shl1_or(int b) {
+    uint32_t c = (uint32_t)b;
+    for (auto& x : d) {
+      const uint32_t n = x >> 31;
+      x = (x << 1) | c;
+      c = n;
+    }
+    if (c) d.push_back(c);
+  }
+  int cmp(const Big& o) const {
+    const size_t n = std::max(d.size(), o.d.size());
+    for (size_t i = n; i-- > 0;) {
+      const uint32_t a = i < d.size() ? d[i] : 0u, b = i < o.d.size() ? o.d[i] : 0u;
+      if (a != b) return a < b ? -1 : 1;
+    }
+    return 0;
+  }
+  void sub(const Big& o) {  // *this >= o
+    int64_t br = 0;
+    for (size_t i = 0; i < d.size(); ++i) {
+      const int64_t t = (int64_t)d[i] - (i < o.d.size() ? o.d[i] : 0u) - br;
+      d[i] = (uint32_t)t;
+      br = t < 0;
+    }
+  }
+  bool zero() const {
+    for (auto x : d)
+      if (x) return false;
+    return true;
+  }
+};
+
+// RN_p of |m| * 10^e10 into (limbs, hdr); returns false if out of the supported range.
+bool decimal_to_mp(int64_t m, int64_t e10, int L, uint32_t* limbs, int32_t* hdr) {
+  const int p = 32 * L;
+  for (int k = 0; k < L; ++k) limbs[k] = 0;
+  if (m == 0) {
+    *hdr = (int32_t)0x80000000u;
+    return true;
+  }
+  if (e10 > 2000 || e10 < -2000) return false;
+  const int sign = m < 0;
+  const uint64_t am = m < 0 ? (uint64_t)(-(m + 1)) + 1u : (uint64_t)m;
+  Big N;
+  N.d = {(uint32_t)am, (uint32_t)(am >> 32)};
+  Big D;
+  D.d = {1u};
+  if (e10 >= 0)
+    for (int64_t i = 0; i < e10; ++i) N.mul_small(10);
+  else
+    for (int64_t i = 0; i < -e10; ++i) D.mul_small(10);
+  // Q = floor(N * 2^s / D) with at least p + 2 bits; sticky = remainder != 0
+  int s = p + 3 + D.bits() - N.bits();
+  if (s < 0) s = 0;
+  Big Q, R;
+  Q.d = {0u};
+  R.d = {0u};
+  const int xb = N.bits() + s;
+  for (int i = xb - 1; i >= 0; --i) {
+    const int b = (i >= s) ? N.bit(i - s) : 0;
+    R.shl1_or(b);
+    Q.shl1_or(0);
+    if (R.cmp(D) >= 0) {
+      R.sub(D);
+      Q.d[0] |= 1u;
+    }
+  }
+  const bool sticky = !R.zero();
+  const int nq = Q.bits();
+  const int drop = nq - p;  // >= 2
+  // mantissa = Q >> drop; tail = low `drop` bits
+  std::vector<uint32_t> mant(L, 0u);
+  for (int i = 0; i < p; ++i)
+    if (Q.bit(i + drop)) mant[i >> 5] |= 1u << (i & 31);
+  const int half = Q.bit(drop - 1);
+  bool rest = sticky;
+  for (int i = 0; i < drop - 1 && !rest; ++i) rest = Q.bit(i) != 0;
+  int64_t e = (int64_t)nq - s;  // value = Q * 2^-s, Q in [2^(nq-1), 2^nq)
+  const bool up = half && (rest || (mant[0] & 1u));
+  if (up) {
+    uint64_t c = 1;
+    for (int k = 0; k < L; ++k) {
+      const uint64_t t = (uint64_t)mant[k] + c;
+      mant[k] = (uint32_t)t;
+      c = t >> 32;
+    }
+    if (c) {
+      mant[L - 1] = 0x80000000u;
+      e += 1;
+    }
+  }
+  if (e > mp::kEmax || e < mp::kEmin) return false;
+  for (int k = 0; k < L; ++k) limbs[k] = mant[k];
+  *hdr = (int32_t)(((uint32_t)e << 1) | (uint32_t)sign);
+  return true;
+}
+
+double mp_to_double(const uint32_t* limbs, int32_t hdr, int L, int64_t ld) {
+  const int32_t e = hdr >> 1;
+  if (e == mp::kZeroE) return 0.0;
+  const uint64_t top = ((uint64_t)limbs[(L - 1) * ld] << 32) | limbs[(L - 2) * ld];
+  double v = std::ldexp((double)top, (int)std::max<int64_t>(-100000, std::min<int64_t>(100000, (int64_t)e - 64)));
+  return (hdr & 1) ? -v : v;
+}
+
+// Device workspace of one solve.
+struct Work {
+  int L = 0;
+  int64_t n = 0;
+  int nvec = 0;
+  uint32_t* vlimb = nullptr;
+  int32_t* vhdr = nullptr;
+  mp::Scalars S{nullptr, nullptr};
+  mp::Ctl* ctl = nullptr;
+  int32_t* part = nullptr;
+  uint32_t* ticket = nullptr;
+  mp::Ctl* h_ctl = nullptr;  // pinned
+  hipStream_t ws = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  mp::VecRef vec(int i) const {
+    mp::VecRef r;
+    r.limb = vlimb + (size_t)i * L * n;
+    r.hdr = vhdr + (size_t)i * n;
+    r.ld = n;
+    return r;
+  }
+  mp_vec desc(int i) const {
+    mp_vec v;
+    v.limb = vlimb + (size_t)i * L * n;
+    v.hdr = vhdr + (size_t)i * n;
+    v.len = n;
+    v.ld = n;
+    return v;
+  }
+  ~Work() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (ws) hipStreamSynchronize(ws);
+    hipFree(vlimb);
+    hipFree(vhdr);
+    hipFree(S.limb);
+    hipFree(S.hdr);
+    hipFree(ctl);
+    hipFree(part);
+    hipFree(ticket);
+    if (h_ctl) hipHostFree(h_ctl);
+    if (ev) hipEventDestroy(ev);
+    if (ws) hipStreamDestroy(ws);
+  }
+};
+
+int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
+  W.L = L;
+  W.n = n;
+  W.nvec = nvec;
+  hipError_t e = hipMalloc((void**)&W.vlimb, std::max<size_t>(4, (size_t)nvec * L * n * 4));
+  if (e == hipSuccess) e = hipMalloc((void**)&W.vhdr, std::max<size_t>(4, (size_t)nvec * n * 4));
+  if (e == hipSuccess) e = hipMalloc((void**)&W.S.limb, (size_t)L * mp::kNumScalars * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.S.hdr, (size_t)mp::kNumScalars * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.ctl, sizeof(mp::Ctl));
+  if (e == hipSuccess) e = hipMalloc((void**)&W.part, dot_workspace_bytes());
+  if (e == hipSuccess) e = hipMalloc((void**)&W.ticket, 64);
+  if (e != hipSuccess) return fail(MPS_ENOMEM, "solver workspace: %s", hipGetErrorString(e));
+  e = hipHostMalloc((void**)&W.h_ctl, sizeof(mp::Ctl), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&W.ws, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&W.ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(W.ev, user);
+  if (e == hipSuccess) e = hipStreamWaitEvent(W.ws, W.ev, 0);
+  if (e == hipSuccess) e = hipMemsetAsync(W.ticket, 0, 64, W.ws);
+  if (e != hipSuccess) return hip_fail(e, "solver setup");
+  // every scalar slot starts as +0
+  mp::VecArgs a{};
+  a.n = mp::kNumScalars;
+  a.v[0].limb = W.S.limb;
+  a.v[0].hdr = W.S.hdr;
+  a.v[0].ld = mp::kNumScalars;
+  return launch_ew(L, EW_ZERO, a, W.ws);
+}
+
+// y = Aop v with the given arrays (Aop = A or A^T via the plan), no-op once done.
+struct Op {
+  int64_t n_out;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  mp_vec val;
+};
+
+int apply(const Op& op, int L, int mode, const mp::VecRef& x, const mp::VecRef& y,
+          uint32_t* status, const mp::Ctl* ctl, hipStream_t s) {
+  mp_vec xv{x.limb, x.hdr, 0, x.ld}, yv{y.limb, y.hdr, 0, y.ld};
+  return spmv_launch(L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
+                     ctl ? &ctl->done : nullptr, s);
+}
+
+mp::DotArgs dot_args(const Work& W, uint32_t* status, int epi) {
+  mp::DotArgs a{};
+  a.n = W.n;
+  a.S = W.S;
+  a.part = W.part;
+  a.ticket = W.ticket;
+  a.ctl = W.ctl;
+  a.status = status;
+  a.epi = epi;
+  return a;
+}
+
+mp::VecArgs ew_args(const Work& W, uint32_t* status) {
+  mp::VecArgs a{};
+  a.n = W.n;
+  a.S = W.S;
+  a.ctl = W.ctl;
+  a.status = status;
+  return a;
+}
+
+int check_solve_args(const mp_csr* A, const mp_vec* b, const mp_vec* x, const mp_solve_opts* o,
+                     mp_solve_info* info) {
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if (A->row_dim != A->col_dim) return fail(MPS_EINVAL, "A must be square");
+  if (!o || !info) return fail(MPS_EINVAL, "null opts/info");
+  if (o->mode != MP_SEQ && o->mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if (o->maxit < 0 || o->maxit > INT32_MAX) return fail(MPS_EINVAL, "maxit out of range");
+  if ((r = check_vec(b, A->row_dim, "b"))) return r;
+  if ((r = check_vec(x, A->row_dim, "x"))) return r;
+  const int L = limbs_of(A->prec);
+  if (vec_overlap(b, x, L)) return fail(MPS_EINVAL, "x overlaps b");
+  if (o->res_hist && o->res_hist->len > 0 && (!o->res_hist->limb || !o->res_hist->hdr))
+    return fail(MPS_EINVAL, "res_hist: null pointer");
+  return MPS_OK;
+}
+
+// Common setup: control block, tolerance constants, x0, r0 = b - A x0, rt = r0, q0, rho1.
+// Vector slots used: 0 = r, 1 = rt, 2 = scratch.
+int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+                uint32_t* status) {
+  const int L = W.L;
+  hipLaunchKernelGGL(mp::ctl_init_kernel, dim3(1), dim3(1), 0, W.ws, W.ctl, (int32_t)o->maxit,
+                     (int32_t)(o->res_hist ? o->res_hist->len : 0));
+  uint32_t m[16];
+  int32_t h;
+  if (!decimal_to_mp(o->rtol_m, o->rtol_e10, L, m, &h)) return fail(MPS_EINVAL, "rtol out of range");
+  int r = set_scalar(L, mp::slot_ref(W.S, mp::S_CREL), m, h, W.ws);
+  if (r) return r;
+  if (!decimal_to_mp(o->atol_m, o->atol_e10, L, m, &h)) return fail(MPS_EINVAL, "atol out of range");
+  if ((r = set_scalar(L, mp::slot_ref(W.S, mp::S_CABS), m, h, W.ws))) return r;
+  mp::VecArgs a = ew_args(W, status);
+  if (o->use_x0) {
+    // r = b - Aop x0
+    if ((r = apply(Aop, L, o->mode, ref(*x), W.vec(2), status, nullptr, W.ws))) return r;
+    a.v[0] = W.vec(0);
+    a.v[1] = ref(*b);
+    a.v[2] = W.vec(2);
+    if ((r = launch_ew(L, EW_SUB, a, W.ws))) return r;
+  } else {
+    // x0 = +0, r = b - A x0 = b exactly
+    a.v[0] = ref(*x);
+    if ((r = launch_ew(L, EW_ZERO, a, W.ws))) return r;
+    a.v[0] = W.vec(0);
+    a.v[1] = ref(*b);
+    if ((r = launch_ew(L, EW_COPY, a, W.ws))) return r;
+  }
+  a.v[0] = W.vec(1);
+  a.v[1] = W.vec(0);
+  if ((r = launch_ew(L, EW_COPY, a, W.ws))) return r;
+  mp::DotArgs d = dot_args(W, status, mp::EPI_SETUP);
+  d.nd = 2;
+  d.x[0] = W.vec(0);
+  d.y[0] = W.vec(0);
+  d.out[0] = mp::slot_ref(W.S, mp::S_Q0);
+  d.x[1] = W.vec(1);
+  d.y[1] = W.vec(0);
+  d.out[1] = mp::slot_ref(W.S, mp::S_RHO);
+  return launch_dot(L, d, W.ws);
+}
+
+// Run iterations until the control block says done (graph replays, or eager when chunk <= 0).
+template <class F>
+int run_iterations(Work& W, const mp_solve_opts* o, F&& enqueue_iteration) {
+  hipError_t e;
+  int r;
+  const int chunk = o->chunk;
+  // the setup may already have finished the solve
+  e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl), hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
+  if (e != hipSuccess) return hip_fail(e, "poll");
+  if (W.h_ctl->done) return MPS_OK;
+  if (chunk > 0) {
+    e = hipStreamBeginCapture(W.ws, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    r = enqueue_iteration();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(W.ws, &g);
+    if (r) {
+      if (g) hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    W.graph = g;
+    e = hipGraphInstantiate(&W.exec, W.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  }
+  int64_t launched = 0;
+  const int64_t limit = o->maxit + 2;
+  while (true) {
+    const int batch = chunk > 0 ? chunk : 1;
+    for (int c = 0; c < batch; ++c) {
+      if (chunk > 0) {
+        e = hipGraphLaunch(W.exec, W.ws);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      } else if ((r = enqueue_iteration())) {
+        return r;
+      }
+      ++launched;
+    }
+    e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl), hipMemcpyDeviceToHost, W.ws);
+    if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
+    if (e != hipSuccess) return hip_fail(e, "poll");
+    if (W.h_ctl->done) break;
+    if (launched > limit) return fail(MPS_EHIP, "solver did not reach its iteration limit");
+  }
+  return MPS_OK;
+}
+
+int finish_solve(Work& W, mp_solve_info* info, uint32_t* status) {
+  info->status = W.h_ctl->status;
+  info->iters = W.h_ctl->iters;
+  // display-only residual ratio from q and q0
+  std::vector<uint32_t> sl((size_t)W.L * mp::kNumScalars);
+  std::vector<int32_t> sh(mp::kNumScalars);
+  hipError_t e = hipMemcpyAsync(sl.data(), W.S.limb, sl.size() * 4, hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipMemcpyAsync(sh.data(), W.S.hdr, sh.size() * 4, hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
+  if (e != hipSuccess) return hip_fail(e, "result readback");
+  const double q0 = mp_to_double(sl.data() + mp::S_Q0, sh[mp::S_Q0], W.L, mp::kNumScalars);
+  const double q = info->iters > 0 ? mp_to_double(sl.data() + mp::S_Q, sh[mp::S_Q], W.L, mp::kNumScalars) : q0;
+  info->final_rel_res = q0 > 0 ? std::sqrt(q / q0) : 0.0;
+  const uint32_t fl = W.h_ctl->flags;
+  if (fl & mp::kStRange) return fail(MPS_ERANGE, "a result exponent left the range during the solve");
+  if (fl & mp::kStWindow) return fail(MPS_ENOTSUP, "an exact accumulation was wider than supported");
+  (void)status;
+  return MPS_OK;
+}
+
+struct OwnedPlan {
+  mp_plan* p = nullptr;
+  ~OwnedPlan() {
+    if (p) plan_free(p);
+  }
+};
+
+// The two products of a solve: Aop (the system matrix) and its transpose.
+int make_ops(const mp_csr* A, const mp_plan* P, int transpose, Op* op, Op* opT) {
+  Op a{A->row_dim, A->row_ptr, A->col_idx, A->val};
+  Op t{A->col_dim, nullptr, nullptr, A->val};
+  if (P) {
+    t.row_ptr = P->t_row_ptr;
+    t.col_idx = P->t_col_idx;
+    t.val.limb = P->t_limb;
+    t.val.hdr = P->t_hdr;
+    t.val.len = P->nnz;
+    t.val.ld = P->nnz;
+  }
+  *op = transpose ? t : a;
+  *opT = transpose ? a : t;
+  return MPS_OK;
+}
+
+}  // namespace
+
+int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+              const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if (!plan) {
+    if ((r = plan_build(A, user, &own.p))) return r;
+    plan = own.p;
+  } else if ((r = check_plan(plan, A))) {
+    return r;
+  }
+  const int L = limbs_of(A->prec);
+  Work W;
+  // vectors: 0 r, 1 rt, 2 scratch/z, 3 p, 4 pt, 5 zt
+  if ((r = work_alloc(W, L, A->row_dim, 6, user))) return r;
+  Op op, opT;
+  make_ops(A, plan, o->transpose, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), Z = W.vec(2), P = W.vec(3), PT = W.vec(4), ZT = W.vec(5);
+  const mp::VecRef X = ref(*x);
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  auto iteration = [&]() -> int {
+    int rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
+    if ((rr = launch_ew(L, EW_BICG_DIR, a, W.ws))) return rr;
+    if ((rr = apply(op, L, o->mode, P, Z, st, W.ctl, W.ws))) return rr;
+    if ((rr = apply(opT, L, o->mode, PT, ZT, st, W.ctl, W.ws))) return rr;
+    mp::DotArgs d = dot_args(W, st, mp::EPI_BICG_SIGMA);
+    d.nd = 1;
+    d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA);
+    if ((rr = launch_dot(L, d, W.ws))) return rr;
+    a = ew_args(W, st);
+    a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
+    if ((rr = launch_ew(L, EW_BICG_UPDATE, a, W.ws))) return rr;
+    d = dot_args(W, st, mp::EPI_BICG_CONV);
+    d.nd = 2;
+    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q);
+    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT);
+    d.hist = hist;
+    return launch_dot(L, d, W.ws);
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
+int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+                const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if (o->transpose) {
+    if (!plan) {
+      if ((r = plan_build(A, user, &own.p))) return r;
+      plan = own.p;
+    } else if ((r = check_plan(plan, A))) {
+      return r;
+    }
+  }
+  const int L = limbs_of(A->prec);
+  Work W;
+  // vectors: 0 r, 1 rt, 2 scratch, 3 p, 4 q, 5 t, 6 v, 7 s, 8 w, 9 y, 10 u, 11 z
+  if ((r = work_alloc(W, L, A->row_dim, 12, user))) return r;
+  Op op, opT;
+  make_ops(A, plan, o->transpose, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), Q = W.vec(4), T = W.vec(5),
+                   V = W.vec(6), S = W.vec(7), Wv = W.vec(8), Y = W.vec(9), U = W.vec(10),
+                   Z = W.vec(11);
+  const mp::VecRef X = ref(*x);
+  {
+    // u = z = s = w = t = p = q = v = y = +0; beta = +0 (scalars were cleared to +0)
+    mp::VecArgs a = ew_args(W, st);
+    for (int i = 3; i < 12; ++i) {
+      a.v[0] = W.vec(i);
+      if ((r = launch_ew(L, EW_ZERO, a, W.ws))) return r;
+    }
+  }
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  auto iteration = [&]() -> int {
+    int rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
+    if ((rr = launch_ew(L, EW_GP_DIR, a, W.ws))) return rr;
+    if ((rr = apply(op, L, o->mode, P, Q, st, W.ctl, W.ws))) return rr;
+    mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
+    d.nd = 1;
+    d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN);
+    if ((rr = launch_dot(L, d, W.ws))) return rr;
+    a = ew_args(W, st);
+    a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
+    if ((rr = launch_ew(L, EW_GP_TSY, a, W.ws))) return rr;
+    if ((rr = apply(op, L, o->mode, T, V, st, W.ctl, W.ws))) return rr;
+    d = dot_args(W, st, mp::EPI_GP_ZETA);
+    d.nd = 5;
+    d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1);
+    d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2);
+    d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3);
+    d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4);
+    d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5);
+    if ((rr = launch_dot(L, d, W.ws))) return rr;
+    mp::GpUpdArgs g{};
+    g.a = ew_args(W, st);
+    g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
+    g.a.v[6] = P; g.a.v[7] = T;
+    g.y = Y;
+    g.v = V;
+    if ((rr = launch_gp_update(L, g, W.ws))) return rr;
+    d = dot_args(W, st, mp::EPI_GP_CONV);
+    d.nd = 2;
+    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q);
+    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT);
+    d.hist = hist;
+    return launch_dot(L, d, W.ws);
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
+}  // namespace mpapi
+
+using namespace mpapi;
+
+extern "C" {
+
+int bicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+         const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return bicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int gpbicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+           const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return gpbicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int mp_const_decimal(int64_t m, int64_t e10, int prec, mp_vec* out, void* stream) {
+  clear_error();
+  const int L = limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  int r = check_vec(out, 1, "out");
+  if (r) return r;
+  uint32_t m_[16];
+  int32_t h;
+  if (!decimal_to_mp(m, e10, L, m_, &h)) return fail(MPS_EINVAL, "constant out of range");
+  return set_scalar(L, ref(*out), m_, h, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -25,9 +25,6 @@ namespace mp {
 constexpr int kRowsPerBlock = 64;
 constexpr int kChunk = 128;
 
-template <int L>
-constexpr int window_fast_digits() { return 2 * L + 10; }
-
 struct SpmvArgs {
   int64_t n_rows;
   const int32_t* row_ptr;
@@ -42,6 +39,7 @@ struct SpmvArgs {
   int32_t* y_hdr;
   int64_t y_ld;
   uint32_t* status;
+  const int32_t* done;  // nullable: a set flag turns the launch into a no-op (solver graphs)
 };
 
 template <int L>
@@ -51,6 +49,7 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
   __shared__ int32_t s_e[kChunk];
   __shared__ uint32_t s_s[kChunk];
 
+  if (A.done && *(volatile const int32_t*)A.done) return;
   const int lane = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
   const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);
@@ -115,6 +114,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   __shared__ uint32_t s_s[kChunk];
   __shared__ int64_t s_win[WF * 64];
 
+  if (A.done && *(volatile const int32_t*)A.done) return;
   const int lane = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
   const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);

@@ -1,0 +1,167 @@
+// Vector entry points (y <- y + alpha x, exact inner product) and the launch helpers that the
+// Krylov drivers share.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "../../include/mpspmv.h"
+#include "api_internal.hpp"
+#include "solver_kernels.hpp"
+#include "vec_internal.hpp"
+
+namespace mpapi {
+
+size_t dot_workspace_bytes() {
+  return (size_t)mp::kDotMaxBlocks * mp::kDotMaxND * mp::dot_rec_ints<16>() * sizeof(int32_t);
+}
+
+mp::VecRef ref(const mp_vec& v) {
+  mp::VecRef r;
+  r.limb = v.limb;
+  r.hdr = v.hdr;
+  r.ld = v.ld;
+  return r;
+}
+
+unsigned dot_grid(int64_t n) {
+  int64_t g = (n + 64 * 8 - 1) / (64 * 8);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, mp::kDotMaxBlocks));
+}
+
+unsigned ew_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
+  const unsigned g = dot_grid(a.n);
+  switch (L) {
+    case 4: hipLaunchKernelGGL(mp::dot_kernel<4>, dim3(g), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(mp::dot_kernel<8>, dim3(g), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(mp::dot_kernel<16>, dim3(g), dim3(64), 0, s, a); break;
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "dot launch");
+}
+
+#define MPS_EW_CASES(KERNEL, ARG)                                                             \
+  switch (L) {                                                                                \
+    case 4: hipLaunchKernelGGL(mp::KERNEL<4>, dim3(g), dim3(256), 0, s, ARG); break;          \
+    case 8: hipLaunchKernelGGL(mp::KERNEL<8>, dim3(g), dim3(256), 0, s, ARG); break;          \
+    case 16: hipLaunchKernelGGL(mp::KERNEL<16>, dim3(g), dim3(256), 0, s, ARG); break;        \
+    default: return fail(MPS_EINVAL, "bad limb count");                                       \
+  }
+
+int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
+  if (a.n == 0) return MPS_OK;
+  const unsigned g = ew_grid(a.n);
+  switch (kind) {
+    case EW_AXPY: MPS_EW_CASES(axpy_kernel, a); break;
+    case EW_COPY: MPS_EW_CASES(copy_kernel, a); break;
+    case EW_ZERO: MPS_EW_CASES(zero_kernel, a); break;
+    case EW_SUB: MPS_EW_CASES(sub_kernel, a); break;
+    case EW_BICG_DIR: MPS_EW_CASES(bicg_dir_kernel, a); break;
+    case EW_BICG_UPDATE: MPS_EW_CASES(bicg_update_kernel, a); break;
+    case EW_GP_DIR: MPS_EW_CASES(gp_dir_kernel, a); break;
+    case EW_GP_TSY: MPS_EW_CASES(gp_tsy_kernel, a); break;
+    default: return fail(MPS_EINVAL, "bad element-wise kernel");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "element-wise launch");
+}
+
+int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s) {
+  if (a.a.n == 0) return MPS_OK;
+  const unsigned g = ew_grid(a.a.n);
+  MPS_EW_CASES(gp_update_kernel, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "gp_update launch");
+}
+
+int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s) {
+  switch (L) {
+    case 4: {
+      mp::ConstArgs<4> a;
+      a.out = out; a.hdr = hdr;
+      for (int k = 0; k < 4; ++k) a.m[k] = m[k];
+      hipLaunchKernelGGL(mp::set_scalar_kernel<4>, dim3(1), dim3(1), 0, s, a);
+      break;
+    }
+    case 8: {
+      mp::ConstArgs<8> a;
+      a.out = out; a.hdr = hdr;
+      for (int k = 0; k < 8; ++k) a.m[k] = m[k];
+      hipLaunchKernelGGL(mp::set_scalar_kernel<8>, dim3(1), dim3(1), 0, s, a);
+      break;
+    }
+    case 16: {
+      mp::ConstArgs<16> a;
+      a.out = out; a.hdr = hdr;
+      for (int k = 0; k < 16; ++k) a.m[k] = m[k];
+      hipLaunchKernelGGL(mp::set_scalar_kernel<16>, dim3(1), dim3(1), 0, s, a);
+      break;
+    }
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "set_scalar launch");
+}
+
+int check_scalar(const mp_vec* v, const char* name) { return check_vec(v, 1, name); }
+
+}  // namespace mpapi
+
+using namespace mpapi;
+
+extern "C" {
+
+int mp_axpy(const mp_vec* alpha, const mp_vec* x, mp_vec* y, int prec, void* stream) {
+  clear_error();
+  const int L = limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  int r;
+  if ((r = check_scalar(alpha, "alpha"))) return r;
+  if (!x || !y) return fail(MPS_EINVAL, "null vector");
+  if ((r = check_vec(x, y->len, "x"))) return r;
+  if ((r = check_vec(y, y->len, "y"))) return r;
+  if (vec_overlap(x, y, L) || vec_overlap(alpha, y, L)) return fail(MPS_EINVAL, "y overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  mp::VecArgs a{};
+  a.n = y->len;
+  a.v[0] = ref(*y);
+  a.v[1] = ref(*x);
+  a.v[2] = ref(*alpha);
+  a.ctl = nullptr;
+  a.status = ctx->status;
+  return launch_ew(L, EW_AXPY, a, (hipStream_t)stream);
+}
+
+int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream) {
+  clear_error();
+  const int L = limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  int r;
+  if (!x || !y) return fail(MPS_EINVAL, "null vector");
+  if ((r = check_vec(y, x->len, "y"))) return r;
+  if ((r = check_vec(x, x->len, "x"))) return r;
+  if ((r = check_scalar(out, "out"))) return r;
+  if (vec_overlap(x, out, L) || vec_overlap(y, out, L)) return fail(MPS_EINVAL, "out overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  mp::DotArgs a{};
+  a.n = x->len;
+  a.nd = 1;
+  a.x[0] = ref(*x);
+  a.y[0] = ref(*y);
+  a.out[0] = ref(*out);
+  a.part = ctx->dot_part;
+  a.ticket = ctx->dot_ticket;
+  a.ctl = nullptr;
+  a.status = ctx->status;
+  a.epi = mp::EPI_NONE;
+  return launch_dot(L, a, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,20 @@
+// Launch helpers for the vector, inner-product and driver-step kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/mpspmv.h"
+#include "solver_kernels.hpp"
+
+namespace mpapi {
+
+enum EwKind {
+  EW_AXPY, EW_COPY, EW_ZERO, EW_SUB, EW_BICG_DIR, EW_BICG_UPDATE, EW_GP_DIR, EW_GP_TSY
+};
+
+mp::VecRef ref(const mp_vec& v);
+int launch_dot(int L, const mp::DotArgs& a, hipStream_t s);
+int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s);
+int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s);
+int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s);
+
+}  // namespace mpapi

@@ -1,0 +1,162 @@
+"""GPU parity of the transposed product, the value gradient, y + alpha x, the exact inner product
+and the decimal constants, bit for bit against the oracle."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import blas, codec, mpnum, spmv as ospmv
+from tests.util import assert_bitwise, decode_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    import paper_1411_2377_amd as M
+    return M
+
+
+def host(arr):
+    limbs, hdr = arr.to_numpy()
+    return synth.MPHost(limbs, hdr, arr.p)
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_transpose_product_random(p, mode):
+    M = lib()
+    rng = np.random.default_rng(p + mode)
+    n, m = 700, 523
+    lengths = rng.integers(0, 25, size=n)
+    lengths[5] = 300                               # a row longer than one 128-entry chunk
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lengths, out=rp[1:])
+    cols = synth._distinct_sorted_columns(rng, lengths, m)
+    vals = synth.mp_uniform(rng, len(cols), p)
+    A_h = synth.CSRHost(n, m, rp.astype(np.int32), cols.astype(np.int32), vals)
+    x_h = synth.mp_uniform(rng, n, p)
+    A = M.CSRMatrix.from_host(A_h)
+    P = M.mp_plan_create(A)
+    y = M.mpspmv_csr_t(A, P, M.MPArray.from_host(x_h), mode=mode)
+    assert M.mp_status() == 0
+    yl, yh = y.to_numpy()
+    vals_o = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    x_o = codec.decode(x_h.limbs, x_h.hdr, p)
+    want = ospmv.spmv_t(n, m, A_h.row_ptr.tolist(), A_h.col_idx.tolist(), vals_o, x_o, p, mode)
+    assert_bitwise(yl, yh, want, p, what="A^T x")
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_transpose_powerlaw_full_size_sampled(mode):
+    """The power-law workload at p = 128: A^T g on sampled columns (incl. the heaviest)."""
+    M = lib()
+    A_h, x_h, g_h = synth.config3(p=128)
+    A = M.CSRMatrix.from_host(A_h)
+    P = M.mp_plan_create(A)
+    y = M.mpspmv_csr_t(A, P, M.MPArray.from_host(g_h), mode=mode)
+    yl, yh = y.to_numpy()
+    counts = np.bincount(A_h.col_idx, minlength=A_h.n_cols)
+    rng = np.random.default_rng(1)
+    cols = np.unique(np.concatenate([[0, A_h.n_cols - 1], np.argsort(counts)[-3:],
+                                     rng.integers(0, A_h.n_cols, 40)]))
+    # oracle: column j of A = entries with col_idx == j in ascending row order
+    row_of = np.repeat(np.arange(A_h.n_rows), np.diff(A_h.row_ptr))
+    want = []
+    for j in cols:
+        ks = np.nonzero(A_h.col_idx == j)[0]
+        vals = codec.decode(A_h.vals.limbs[:, ks], A_h.vals.hdr[ks], 128)
+        gs = decode_vec(g_h, row_of[ks])
+        pairs = [(v, gs[int(i)]) for v, i in zip(vals, row_of[ks])]
+        if mode == 1:
+            want.append(ospmv.exact_sum_of_products(pairs, 128))
+        else:
+            acc = mpnum.zero(128)
+            for a, b in pairs:
+                acc = mpnum.add(acc, mpnum.mul(a, b))
+            want.append(acc)
+    assert_bitwise(yl, yh, want, 128, rows=cols, what="A^T g power-law")
+
+
+@pytest.mark.parametrize("p", [128, 512])
+def test_grad_vals_and_symmetric_transpose(p):
+    M = lib()
+    A_h, ones = synth.config2(p=p, m=24)
+    rng = np.random.default_rng(3)
+    g_h = synth.mp_uniform(rng, A_h.n_rows, p)
+    x_h = synth.mp_uniform(rng, A_h.n_cols, p)
+    A = M.CSRMatrix.from_host(A_h)
+    P = M.mp_plan_create(A)
+    gv = M.mp_grad_vals(A, P, M.MPArray.from_host(g_h), M.MPArray.from_host(x_h))
+    gvn = M.mp_grad_vals(A, P, M.MPArray.from_host(g_h), M.MPArray.from_host(x_h), negate=True)
+    gl, gh = gv.to_numpy()
+    want = ospmv.grad_vals(A_h.row_ptr.tolist(), A_h.col_idx.tolist(), codec.decode(g_h.limbs, g_h.hdr, p),
+                           codec.decode(x_h.limbs, x_h.hdr, p), p)
+    assert_bitwise(gl, gh, want, p, what="grad vals")
+    nl, nh = gvn.to_numpy()
+    assert_bitwise(nl, nh, [w.neg() for w in want], p, what="negated grad vals")
+    # a symmetric matrix (pattern and values) has A^T x == A x bitwise in both modes
+    n = 50
+    rows, cols_, vals = [], [], []
+    rr = np.random.default_rng(5)
+    dense = {}
+    for i in range(n):
+        for j in range(i, n):
+            if i == j or rr.random() < 0.1:
+                dense[(i, j)] = dense[(j, i)] = len(vals)
+                vals.append(None)
+    keys = sorted(dense)
+    uniq = synth.mp_uniform(rr, len(vals), p)
+    idx = np.array([dense[k] for k in keys])
+    S_h = synth.CSRHost(n, n, np.concatenate([[0], np.cumsum(np.bincount([k[0] for k in keys], minlength=n))]).astype(np.int32),
+                        np.array([k[1] for k in keys], np.int32), uniq.take(idx))
+    S = M.CSRMatrix.from_host(S_h)
+    SP = M.mp_plan_create(S)
+    xs = M.MPArray.from_host(synth.mp_uniform(rr, n, p))
+    for mode in (0, 1):
+        a = M.mpspmv_csr(S, xs, mode=mode).to_numpy()
+        b = M.mpspmv_csr_t(S, SP, xs, mode=mode).to_numpy()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_axpy_dot_const(p):
+    M = lib()
+    rng = np.random.default_rng(p)
+    n = 5000 + 37
+    x_h = synth.mp_uniform(rng, n, p)
+    y_h = synth.mp_loguniform(rng, n, p, -30, 30)
+    y_h.hdr[::17] = np.int32(-(1 << 31)) + (np.arange(len(y_h.hdr[::17])) % 2).astype(np.int32)   # +-0
+    a_h = synth.mp_uniform(rng, 1, p)
+    x, y, a = M.MPArray.from_host(x_h), M.MPArray.from_host(y_h), M.MPArray.from_host(a_h)
+    d = M.mp_dot(x, y).to_numpy()
+    xo, yo = codec.decode(x_h.limbs, x_h.hdr, p), codec.decode(y_h.limbs, y_h.hdr, p)
+    assert_bitwise(d[0], d[1], [blas.dot(xo, yo, p)], p, what="dot")
+    # an exactly cancelling inner product: x . [y, -y] on [x, x]
+    xx = synth.mp_concat([x_h, x_h])
+    yy = synth.mp_concat([y_h, synth.MPHost(y_h.limbs.copy(), y_h.hdr ^ np.int32(1), p)])
+    d0 = M.mp_dot(M.MPArray.from_host(xx), M.MPArray.from_host(yy)).to_numpy()
+    assert d0[1][0] == np.int32(-(1 << 31))
+    M.mp_axpy(a, x, y)
+    yl, yh = y.to_numpy()
+    assert_bitwise(yl, yh, blas.axpy(codec.decode(a_h.limbs, a_h.hdr, p)[0], xo, yo), p, what="axpy")
+    for m_, e_ in ((1, -20), (1, -50), (1, -100), (-3, 7), (123456789, -3), (0, 5)):
+        c = M.mp_const_decimal(m_, e_, p).to_numpy()
+        want = mpnum.round_fraction(Fraction(m_) * Fraction(10) ** e_, p)
+        assert_bitwise(c[0], c[1], [want], p, what="const %d e%d" % (m_, e_))
+
+
+def test_dot_wide_span_and_long():
+    """Products spanning ~2000 bits (the block-shared window) and a long vector (many blocks)."""
+    M = lib()
+    p = 256
+    rng = np.random.default_rng(9)
+    n = 300000
+    x_h = synth.mp_uniform(rng, n, p)
+    y_h = synth.mp_loguniform(rng, n, p, -300, 300)
+    d = M.mp_dot(M.MPArray.from_host(x_h), M.MPArray.from_host(y_h)).to_numpy()
+    xo, yo = codec.decode(x_h.limbs, x_h.hdr, p), codec.decode(y_h.limbs, y_h.hdr, p)
+    assert_bitwise(d[0], d[1], [blas.dot(xo, yo, p)], p, what="wide dot")
+    assert M.mp_status() == 0
