@@ -61,31 +61,13 @@ MPD void window_add_atomic(int64_t* win, const uint32_t (&P)[2 * L], uint32_t s,
   }
 }
 
-// RN_p of the window value sum_w win[w*ws] * 2^(32 w + base).  The digits are overwritten
-// (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
+// RN_p of (-1)^sgn * sum_{w < nl} win[w*ws] 2^(32 w + base) for magnitude limbs (each digit
+// holds a 32-bit limb; limb nl-1 is the top non-zero one, nl == 0 means zero).
 template <int L>
-MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
-  int64_t c = 0;
-  for (int w = 0; w < W; ++w) {
-    const int64_t t = win[w * ws] + c;
-    win[w * ws] = (int64_t)(uint32_t)t;
-    c = t >> 32;
-  }
-  const uint32_t sgn = (c < 0) ? 1u : 0u;
-  if (sgn) {
-    uint32_t cy = 1;
-    for (int w = 0; w < W; ++w) {
-      const uint32_t v = __builtin_addc(~(uint32_t)win[w * ws], 0u, cy, &cy);
-      win[w * ws] = (int64_t)v;
-    }
-  }
-  int top = -1;
-  for (int w = W - 1; w >= 0; --w) {
-    if ((uint32_t)win[w * ws] != 0u) {
-      top = w;
-      break;
-    }
-  }
+MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, uint32_t& st,
+                       int ws = 1) {
+  const int W = nl;
+  const int top = nl - 1;
   Num<L> out;
   if (top < 0) {
     set_zero(out, 0);
@@ -126,6 +108,137 @@ MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& 
   if (e > kEmax || e < kEmin) {
     st |= kStRange;
     set_zero(out, sgn);
+    return out;
+  }
+  out.e = (int32_t)e;
+  return out;
+}
+
+
+// RN_p of the window value sum_w win[w*ws] * 2^(32 w + base).  The digits are overwritten
+// (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
+template <int L>
+MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
+  int64_t c = 0;
+  for (int w = 0; w < W; ++w) {
+    const int64_t t = win[w * ws] + c;
+    win[w * ws] = (int64_t)(uint32_t)t;
+    c = t >> 32;
+  }
+  const uint32_t sgn = (c < 0) ? 1u : 0u;
+  if (sgn) {
+    uint32_t cy = 1;
+    for (int w = 0; w < W; ++w) {
+      const uint32_t v = __builtin_addc(~(uint32_t)win[w * ws], 0u, cy, &cy);
+      win[w * ws] = (int64_t)v;
+    }
+  }
+  int top = -1;
+  for (int w = W - 1; w >= 0; --w) {
+    if ((uint32_t)win[w * ws] != 0u) {
+      top = w;
+      break;
+    }
+  }
+  return limbs_round<L>(win, top + 1, sgn, base, st, ws);
+}
+
+}  // namespace mp
+
+namespace mp {
+
+// Register-resident variants for windows of at most WMAX digits (the common case): the digits
+// are read from LDS once, then carried, signed and rounded in registers with fully unrolled
+// loops, avoiding a chain of dependent LDS round trips.
+template <int WMAX>
+struct RegWindow {
+  uint32_t limb[WMAX];
+  uint32_t neg;
+  int nl;  // limbs up to and including the top non-zero one (0: the value is zero)
+};
+
+// Carry-propagate W <= WMAX carry-save digits into sign + magnitude limbs.
+template <int WMAX>
+MPD void reg_normalize(const int64_t* win, int ws, int W, RegWindow<WMAX>& R) {
+  int64_t d[WMAX];
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w) d[w] = (w < W) ? win[w * ws] : 0;
+  int64_t c = 0;
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w) {
+    const int64_t t = d[w] + c;
+    R.limb[w] = (uint32_t)t;
+    c = t >> 32;
+  }
+  R.neg = (c < 0) ? 1u : 0u;
+  if (R.neg) {
+    uint32_t cy = 1;
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) R.limb[w] = __builtin_addc(~R.limb[w], 0u, cy, &cy);
+  }
+  int nl = 0;
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w)
+    if (R.limb[w] && w < W) nl = w + 1;
+  R.nl = nl;
+}
+
+// RN_p of (-1)^neg * sum_w limb[w] 2^(32 w + base).
+template <int L, int WMAX>
+MPD Num<L> reg_round(const RegWindow<WMAX>& R, int64_t base, uint32_t& st) {
+  Num<L> out;
+  if (R.nl == 0) {
+    set_zero(out, 0);
+    return out;
+  }
+  uint32_t top_limb = 0;
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w)
+    if (w == R.nl - 1) top_limb = R.limb[w];
+  const int T = 32 * (R.nl - 1) + 31 - (int)__clz(top_limb);
+  const int b0 = T - 32 * L + 1;
+  // mantissa limb k = bits [b0 + 32k, b0 + 32k + 32); b0 = 32 q0 + r0 (q0 may be negative)
+  const int q0 = b0 >> 5;  // arithmetic shift: floor division
+  const uint32_t r0 = (uint32_t)(b0 & 31);
+  auto limb_at = [&](int idx) -> uint32_t {
+    uint32_t v = 0;
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w)
+      if (w == idx) v = R.limb[w];
+    return v;
+  };
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const uint32_t lo = limb_at(q0 + k), hi = limb_at(q0 + k + 1);
+    out.m[k] = r0 ? fshr(hi, lo, r0) : lo;
+  }
+  // round bit at b0 - 1, sticky below it
+  uint32_t rnd = 0, sticky = 0;
+  const int rb = b0 - 1;
+  if (rb >= 0) {
+    const int ri = rb >> 5;
+    const uint32_t rs = (uint32_t)(rb & 31);
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) {
+      if (w < ri) sticky |= R.limb[w];
+      if (w == ri) {
+        rnd = (R.limb[w] >> rs) & 1u;
+        sticky |= rs ? (R.limb[w] & ((1u << rs) - 1u)) : 0u;
+      }
+    }
+  }
+  int64_t e = (int64_t)b0 + base + 32 * L;
+  uint32_t cy = rnd & (uint32_t)((sticky != 0) | (out.m[0] & 1u));
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = __builtin_addc(out.m[k], 0u, cy, &cy);
+  if (cy) {
+    out.m[L - 1] = 0x80000000u;
+    e += 1;
+  }
+  out.s = R.neg;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, R.neg);
     return out;
   }
   out.e = (int32_t)e;

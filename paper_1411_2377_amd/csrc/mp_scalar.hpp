@@ -46,11 +46,24 @@ MPD Num<L> div_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
   u[NU] = 0;
   const uint32_t* v = b.m;
   uint32_t q[NU - L + 1];
+  // The trial digit floor(num / v_top) is estimated in double precision (num < 2^64 is off by
+  // at most a few units after rounding to 53 bits) and then made exact with integer steps.
+  const double vtop_inv = 1.0 / (double)v[L - 1];
 #pragma unroll
   for (int j = NU - L; j >= 0; --j) {
     const uint64_t num = ((uint64_t)u[j + L] << 32) | u[j + L - 1];
-    uint64_t qhat = num / v[L - 1];
-    uint64_t rhat = num - qhat * v[L - 1];
+    const double numd = (double)u[j + L] * 4294967296.0 + (double)u[j + L - 1];
+    uint64_t qhat = (uint64_t)(numd * vtop_inv);
+    int64_t rs = (int64_t)(num - qhat * (uint64_t)v[L - 1]);  // |rs| < 2^40: exact in int64
+    while (rs < 0) {
+      qhat -= 1;
+      rs += v[L - 1];
+    }
+    while (rs >= (int64_t)v[L - 1]) {
+      qhat += 1;
+      rs -= v[L - 1];
+    }
+    uint64_t rhat = (uint64_t)rs;
     while (qhat >> 32 ||
            (L >= 2 && qhat * v[L - 2] > ((rhat << 32) | (L >= 2 ? u[j + L - 2] : 0u)))) {
       qhat -= 1;

@@ -194,18 +194,28 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
 }
 
 // ------------------------------------------------------------------------------------------
-// Exact inner products: up to kDotMaxND dots of length n in one launch (64-thread blocks).
+// Exact inner products: up to kDotMaxND dots of length n in one launch (256-thread blocks).
 // Each block forms the exact products of its elements in per-lane carry-save windows anchored
 // at the block's smallest product exponent, sums the lane windows digit by digit, normalises
 // the block sum to sign + magnitude limbs and writes that record out.  The last block to finish
-// (integer ticket) aligns all records into one window, rounds once, stores the result in a
-// scalar slot and runs the driver epilogue.
+// (integer ticket) aligns all records into one window, rounds once, stores the result and runs
+// the driver epilogue.  Lane windows are padded to an odd stride so that both the per-lane
+// adds and the per-digit sums hit distinct LDS banks.
 // ------------------------------------------------------------------------------------------
 constexpr int kDotMaxND = 5;
 constexpr int kDotMaxBlocks = 128;
+constexpr int kDotThreads = 256;
+constexpr int kDotStride = kDotThreads + 1;
 
 template <int L>
-constexpr int dot_rec_ints() { return 3 + 64 * window_fast_digits<L>(); }
+constexpr int dot_window_digits() { return window_fast_digits<L>(); }
+
+// block-shared window capacity (the per-lane windows' LDS reused as one array)
+template <int L>
+constexpr int dot_shared_digits() { return window_fast_digits<L>() * kDotStride; }
+
+template <int L>
+constexpr int dot_rec_ints() { return 3 + dot_shared_digits<L>(); }
 
 struct DotArgs {
   int64_t n;
@@ -234,22 +244,42 @@ MPD int32_t wave_max(int32_t v) {
   return v;
 }
 
+MPD int64_t wave_max64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int64_t t = __shfl_xor(v, o);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
 template <int L>
-__global__ void __launch_bounds__(64) dot_kernel(DotArgs A) {
-  constexpr int WF = window_fast_digits<L>();
-  constexpr int WB = WF * 64;
+__global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
+  constexpr int WF = dot_window_digits<L>();
+  constexpr int WB = dot_shared_digits<L>();
   constexpr int REC = dot_rec_ints<L>();
+  constexpr int kRecPre = 3 + WF;          // record words staged in LDS by the last block
+  constexpr int WMAXF = 2 * L + 16;        // final windows up to this size stay in registers
+  static_assert(64 + (kDotMaxBlocks * kRecPre + 1) / 2 <= WB, "record staging must fit");
   __shared__ int64_t s_win[WB];
+  // the last block stages record heads behind the first 64 window digits
+  int32_t(*s_rec)[kRecPre] = reinterpret_cast<int32_t(*)[kRecPre]>(s_win + 64);
+  __shared__ int64_t s_red[2][kDotThreads / 64];
+  __shared__ int64_t s_part[kDotThreads / 64][64];
   __shared__ uint32_t s_last;
   if (solve_done(A.ctl)) return;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
+  const int wave = t >> 6;
   uint32_t st = 0;
-  const int64_t stride = (int64_t)gridDim.x * 64;
+  const int64_t stride = (int64_t)gridDim.x * kDotThreads;
+  const int64_t first = (int64_t)blockIdx.x * kDotThreads + t;
+  const int d = blockIdx.y;  // the dots of one launch run side by side, one grid row each
 
-  for (int d = 0; d < A.nd; ++d) {
+  do {
     const VecRef X = A.x[d], Y = A.y[d];
+    // exponent range of the block's non-zero products
     int32_t emin = INT32_MAX, emax = INT32_MIN;
-    for (int64_t i = (int64_t)blockIdx.x * 64 + lane; i < A.n; i += stride) {
+    for (int64_t i = first; i < A.n; i += stride) {
       const int32_t hx = X.hdr[i], hy = Y.hdr[i];
       if (!hdr_is_zero(hx) && !hdr_is_zero(hy)) {
         const int32_t e = (hx >> 1) + (hy >> 1);
@@ -259,62 +289,108 @@ __global__ void __launch_bounds__(64) dot_kernel(DotArgs A) {
     }
     emin = wave_min(emin);
     emax = wave_max(emax);
+    if ((t & 63) == 0) {
+      s_red[0][wave] = emin;
+      s_red[1][wave] = emax;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kDotThreads / 64; ++w) {
+      emin = min(emin, (int32_t)s_red[0][w]);
+      emax = max(emax, (int32_t)s_red[1][w]);
+    }
+    __syncthreads();
     int32_t* rec = A.part + ((int64_t)blockIdx.x * kDotMaxND + d) * REC;
     if (emax < emin) {
-      if (lane == 0) rec[0] = 0;
-      continue;
+      if (t == 0) rec[0] = 0;
+      break;
     }
     const int W = window_digits<L>(emin, emax);
     if (W > WB) {
       st |= kStWindow;
-      if (lane == 0) rec[0] = 0;
-      continue;
+      if (t == 0) rec[0] = 0;
+      break;
     }
-    if (W <= WF) {
-      int64_t* mywin = s_win + lane;
-      for (int w = 0; w < WF; ++w) mywin[w * 64] = 0;
-      for (int64_t i = (int64_t)blockIdx.x * 64 + lane; i < A.n; i += stride) {
-        const int32_t hx = X.hdr[i], hy = Y.hdr[i];
-        if (hdr_is_zero(hx) || hdr_is_zero(hy)) continue;
-        uint32_t xm[L], ym[L], pr[2 * L];
-#pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = X.limb[(int64_t)q * X.ld + i];
-#pragma unroll
-        for (int q = 0; q < L; ++q) ym[q] = Y.limb[(int64_t)q * Y.ld + i];
-        mul_full<L>(xm, ym, pr);
-        window_add<L>(mywin, 64, pr, (uint32_t)(hx ^ hy) & 1u, (uint32_t)((hx >> 1) + (hy >> 1) - emin));
-      }
-      __syncthreads();
-      int64_t dsum = 0;
-      if (lane < W) {
-        for (int j = 0; j < 64; ++j) dsum += s_win[lane * 64 + j];
-      }
-      __syncthreads();
-      if (lane < W) s_win[lane] = dsum;
-      __syncthreads();
+    const bool fast = W <= WF;
+    if (fast) {
+      for (int w = 0; w < WF; ++w) s_win[w * kDotStride + t] = 0;
     } else {
-      for (int w = lane; w < W; w += 64) s_win[w] = 0;
+      for (int w = t; w < W; w += kDotThreads) s_win[w] = 0;
       __syncthreads();
-      for (int64_t i = (int64_t)blockIdx.x * 64 + lane; i < A.n; i += stride) {
-        const int32_t hx = X.hdr[i], hy = Y.hdr[i];
-        if (hdr_is_zero(hx) || hdr_is_zero(hy)) continue;
-        uint32_t xm[L], ym[L], pr[2 * L];
+    }
+    // products, two elements at a time: both headers, then both limb sets in flight together
+    for (int64_t i0 = first; i0 < A.n; i0 += 2 * stride) {
+      const int64_t i1 = i0 + stride;
+      const bool has1 = i1 < A.n;
+      const int32_t hx0 = X.hdr[i0], hy0 = Y.hdr[i0];
+      const int32_t hx1 = has1 ? X.hdr[i1] : (int32_t)0x80000000, hy1 = has1 ? Y.hdr[i1] : (int32_t)0x80000000;
+      const bool nz0 = !hdr_is_zero(hx0) && !hdr_is_zero(hy0);
+      const bool nz1 = !hdr_is_zero(hx1) && !hdr_is_zero(hy1);
+      uint32_t x0[L], y0[L], x1[L], y1[L];
 #pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = X.limb[(int64_t)q * X.ld + i];
-#pragma unroll
-        for (int q = 0; q < L; ++q) ym[q] = Y.limb[(int64_t)q * Y.ld + i];
-        mul_full<L>(xm, ym, pr);
-        window_add_atomic<L>(s_win, pr, (uint32_t)(hx ^ hy) & 1u, (uint32_t)((hx >> 1) + (hy >> 1) - emin));
+      for (int q = 0; q < L; ++q) {
+        x0[q] = nz0 ? X.limb[(int64_t)q * X.ld + i0] : 0u;
+        y0[q] = nz0 ? Y.limb[(int64_t)q * Y.ld + i0] : 0u;
+        x1[q] = nz1 ? X.limb[(int64_t)q * X.ld + i1] : 0u;
+        y1[q] = nz1 ? Y.limb[(int64_t)q * Y.ld + i1] : 0u;
       }
+      if (nz0) {
+        uint32_t pr[2 * L];
+        mul_full<L>(x0, y0, pr);
+        const uint32_t off = (uint32_t)((hx0 >> 1) + (hy0 >> 1) - emin);
+        if (fast) window_add<L>(s_win + t, kDotStride, pr, (uint32_t)(hx0 ^ hy0) & 1u, off);
+        else window_add_atomic<L>(s_win, pr, (uint32_t)(hx0 ^ hy0) & 1u, off);
+      }
+      if (nz1) {
+        uint32_t pr[2 * L];
+        mul_full<L>(x1, y1, pr);
+        const uint32_t off = (uint32_t)((hx1 >> 1) + (hy1 >> 1) - emin);
+        if (fast) window_add<L>(s_win + t, kDotStride, pr, (uint32_t)(hx1 ^ hy1) & 1u, off);
+        else window_add_atomic<L>(s_win, pr, (uint32_t)(hx1 ^ hy1) & 1u, off);
+      }
+    }
+    __syncthreads();
+    if (fast) {
+      // digit w is summed over the 256 lane windows by TPD consecutive threads (an odd row
+      // stride keeps their reads on distinct banks), then combined with shuffles
+      constexpr int TPD = (WF <= 32) ? 8 : 4;
+      constexpr int SEG = 64 / TPD;
+      const int w = t / TPD, sub = t % TPD;
+      int64_t a0 = 0, a1 = 0;
+      if (w < W) {
+        const int64_t* row = s_win + w * kDotStride + SEG * sub;
+#pragma unroll
+        for (int m = 0; m < kDotThreads / 64; ++m) {
+#pragma unroll
+          for (int k = 0; k < SEG; k += 2) {
+            a0 += row[64 * m + k];
+            a1 += row[64 * m + k + 1];
+          }
+        }
+      }
+      int64_t dsum = a0 + a1;
+#pragma unroll
+      for (int o = 1; o < TPD; o <<= 1) dsum += __shfl_xor(dsum, o);
+      __syncthreads();
+      if (w < W && sub == 0) s_win[w] = dsum;
       __syncthreads();
     }
     // normalise the block sum to sign + magnitude limbs (one lane)
-    if (lane == 0) {
+    if (t == 0 && fast) {
+      RegWindow<WF> R;
+      reg_normalize<WF>(s_win, 1, W, R);
+      rec[1] = emin;
+      rec[2] = R.nl;
+#pragma unroll
+      for (int w = 0; w < WF; ++w)
+        if (w < R.nl) rec[3 + w] = (int32_t)R.limb[w];
+      rec[0] = R.nl ? (1 | ((int)R.neg << 1)) : 0;
+    } else if (t == 0) {
       int64_t c = 0;
       for (int w = 0; w < W; ++w) {
-        const int64_t t = s_win[w] + c;
-        s_win[w] = (int64_t)(uint32_t)t;
-        c = t >> 32;
+        const int64_t v = s_win[w] + c;
+        s_win[w] = (int64_t)(uint32_t)v;
+        c = v >> 32;
       }
       const int neg = c < 0;
       if (neg) {
@@ -329,10 +405,10 @@ __global__ void __launch_bounds__(64) dot_kernel(DotArgs A) {
       rec[0] = nl ? (1 | (neg << 1)) : 0;
     }
     __syncthreads();
-  }
+  } while (false);
 
   __threadfence();
-  if (lane == 0) s_last = (atomicAdd(A.ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
+  if (t == 0) s_last = (atomicAdd(&A.ticket[d], 1u) == gridDim.x - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) {
     if (st) atomicOr(A.status, st);
@@ -340,66 +416,101 @@ __global__ void __launch_bounds__(64) dot_kernel(DotArgs A) {
   }
   __threadfence();
   const int G = gridDim.x;
-  for (int d = 0; d < A.nd; ++d) {
+  {
+    // stage the head of every block record in LDS with independent coalesced loads (the fence
+    // above makes the other blocks' writes visible); longer records are read on from memory
+#pragma unroll 4
+    for (int idx = t; idx < G * kRecPre; idx += kDotThreads) {
+      const int b = idx / kRecPre, j = idx - b * kRecPre;
+      s_rec[b][j] = A.part[((int64_t)b * kDotMaxND + d) * REC + j];
+    }
+    __syncthreads();
     int32_t gmin = INT32_MAX;
     int64_t gtop = INT64_MIN;
-    for (int b = lane; b < G; b += 64) {
-      const volatile int32_t* rec = A.part + ((int64_t)b * kDotMaxND + d) * REC;
-      if (rec[0] & 1) {
-        gmin = min(gmin, (int32_t)rec[1]);
-        gtop = max(gtop, (int64_t)rec[1] + 32 * (int64_t)rec[2]);
+    for (int b = t; b < G; b += kDotThreads) {
+      if (s_rec[b][0] & 1) {
+        gmin = min(gmin, s_rec[b][1]);
+        gtop = max(gtop, (int64_t)s_rec[b][1] + 32 * (int64_t)s_rec[b][2]);
       }
     }
     gmin = wave_min(gmin);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const int64_t t = __shfl_xor(gtop, o);
-      gtop = t > gtop ? t : gtop;
+    gtop = wave_max64(gtop);
+    if ((t & 63) == 0) {
+      s_red[0][wave] = gmin;
+      s_red[1][wave] = gtop;
     }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kDotThreads / 64; ++w) {
+      gmin = min(gmin, (int32_t)s_red[0][w]);
+      gtop = s_red[1][w] > gtop ? s_red[1][w] : gtop;
+    }
+    __syncthreads();
     Num<L> res;
     set_zero(res, 0);
-    if (gtop != INT64_MIN) {
-      const int64_t span = gtop - (int64_t)gmin;
-      const int Wg = (int)(span >> 5) + 2;
-      if (Wg > WB) {
-        st |= kStWindow;
-      } else {
-        for (int w = lane; w < Wg; w += 64) {
-          int64_t acc = 0;
-          for (int b = 0; b < G; ++b) {
-            const volatile int32_t* rec = A.part + ((int64_t)b * kDotMaxND + d) * REC;
-            const int32_t fl = rec[0];
-            if (!(fl & 1)) continue;
-            const int nl = rec[2];
-            const int start = 32 * w - (rec[1] - gmin);  // bit index into this record
-            uint32_t v;
-            if (start <= -32 || start >= 32 * nl) {
-              v = 0;
-            } else if (start < 0) {
-              v = (uint32_t)rec[3] << (uint32_t)(-start);
-            } else {
-              const int i = start >> 5;
-              const uint32_t sh = (uint32_t)(start & 31);
-              const uint32_t lo = (uint32_t)rec[3 + i];
-              const uint32_t hi = (i + 1 < nl) ? (uint32_t)rec[3 + i + 1] : 0u;
-              v = sh ? fshr(hi, lo, sh) : lo;
-            }
-            acc += (fl & 2) ? -(int64_t)v : (int64_t)v;
+    const int Wg = gtop != INT64_MIN ? (int)((gtop - (int64_t)gmin) >> 5) + 2 : 0;
+    if (Wg > WB) st |= kStWindow;
+    // a final window wider than 64 digits overwrites the staged records: read them from memory
+    const bool staged = Wg <= 64;
+    __syncthreads();
+    if (Wg > 0 && Wg <= WB) {
+      for (int w = t; w < Wg; w += kDotThreads) s_win[w] = 0;
+      __syncthreads();
+      // each lane adds its records, shifted to the common anchor, with integer LDS atomics
+      for (int b = t; b < G; b += kDotThreads) {
+        const int32_t* far = A.part + ((int64_t)b * kDotMaxND + d) * REC;
+        const int32_t fl = staged ? s_rec[b][0] : far[0];
+        if (!(fl & 1)) continue;
+        const uint32_t off = (uint32_t)((staged ? s_rec[b][1] : far[1]) - gmin);
+        const int nl = staged ? s_rec[b][2] : far[2];
+        const int q = (int)(off >> 5);
+        const uint32_t r = off & 31u;
+        auto limb = [&](int j) -> uint32_t {
+          if (j < 0 || j >= nl) return 0u;
+          return (staged && 3 + j < kRecPre) ? (uint32_t)s_rec[b][3 + j] : (uint32_t)far[3 + j];
+        };
+        // start each record at a different digit so that the lanes' atomics spread over banks
+        for (int jj = 0; jj <= nl; ++jj) {
+          int j = jj + b;
+          j %= (nl + 1);
+          const uint32_t cur = limb(j), prev = limb(j - 1);
+          const uint32_t v = r ? fshr(cur, prev, 32u - r) : cur;
+          if (v) {
+            const uint64_t add = (fl & 2) ? (uint64_t)(-(int64_t)v) : (uint64_t)v;
+            atomicAdd((unsigned long long*)&s_win[q + j], (unsigned long long)add);
           }
-          s_win[w] = acc;
         }
-        __syncthreads();
-        if (lane == 0) res = window_finalize<L>(s_win, 1, Wg, (int64_t)gmin - 64 * L, st);
+      }
+      __syncthreads();
+      if (t == 0) {
+        if (Wg <= WMAXF) {
+          // carries in registers, then the rounding reads the limbs back from LDS
+          RegWindow<WMAXF> R;
+          reg_normalize<WMAXF>(s_win, 1, Wg, R);
+#pragma unroll
+          for (int w = 0; w < WMAXF; ++w)
+            if (w < Wg) s_win[w] = (int64_t)R.limb[w];
+          res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)gmin - 64 * L, st);
+        } else {
+          res = window_finalize<L>(s_win, 1, Wg, (int64_t)gmin - 64 * L, st);
+        }
       }
     }
-    if (lane == 0) vstore<L>(A.out[d], 0, res);
-    __syncthreads();
+    if (t == 0) vstore<L>(A.out[d], 0, res);
   }
-  if (lane == 0) {
+  if (t == 0) {
+    A.ticket[d] = 0;
+    if (A.ctl && st) atomicOr(&A.ctl->flags, st);
+    // the last dot to finish runs the driver epilogue
     __threadfence();
-    epilogue<L>(A.epi, A.S, A.ctl, A.hist, st);
-    *A.ticket = 0;
-    if (A.ctl) A.ctl->flags |= st;
+    if (atomicAdd(&A.ticket[kDotMaxND], 1u) == (unsigned)A.nd - 1) {
+      __threadfence();
+      uint32_t st2 = 0;
+      epilogue<L>(A.epi, A.S, A.ctl, A.hist, st2);
+      A.ticket[kDotMaxND] = 0;
+      if (A.ctl && st2) atomicOr(&A.ctl->flags, st2);
+      st |= st2;
+    }
   }
   if (st) atomicOr(A.status, st);
 }
@@ -430,7 +541,7 @@ __host__ __device__ inline VecRef slot_ref(const Scalars& S, int slot) {
 
 // v0 <- v0 + v2[0] * v1   (mp_axpy: y <- y + alpha x)
 template <int L>
-__global__ void axpy_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) axpy_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = vload<L>(A.v[2], 0);
@@ -443,14 +554,14 @@ __global__ void axpy_kernel(VecArgs A) {
 
 // v0 <- v1 (copy)
 template <int L>
-__global__ void copy_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) copy_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, vload<L>(A.v[1], i)); }
 }
 
 // v0 <- +0
 template <int L>
-__global__ void zero_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) zero_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   Num<L> z;
   set_zero(z, 0);
@@ -459,7 +570,7 @@ __global__ void zero_kernel(VecArgs A) {
 
 // v0 <- v1 - v2
 template <int L>
-__global__ void sub_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) sub_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, sub_rn<L>(vload<L>(A.v[1], i), vload<L>(A.v[2], i), st)); }
@@ -468,7 +579,7 @@ __global__ void sub_kernel(VecArgs A) {
 
 // BiCG directions: v = {p, pt, r, rt}. First iteration p = r, pt = rt; then p = r + beta p.
 template <int L>
-__global__ void bicg_dir_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const bool first = A.ctl->iters == 0;
@@ -488,7 +599,7 @@ __global__ void bicg_dir_kernel(VecArgs A) {
 
 // BiCG update: v = {x, r, rt, p, z, zt}: x += alpha p; r -= alpha z; rt -= alpha zt.
 template <int L>
-__global__ void bicg_update_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = sload<L>(A.S, S_ALPHA);
@@ -503,7 +614,7 @@ __global__ void bicg_update_kernel(VecArgs A) {
 // GPBiCG direction: v = {p, w, r, v, q, u}.  First iteration p = r; then
 // w = v + beta q, p = r + beta (p - u).
 template <int L>
-__global__ void gp_dir_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const bool first = A.ctl->iters == 0;
@@ -525,7 +636,7 @@ __global__ void gp_dir_kernel(VecArgs A) {
 // GPBiCG t, s, y: v = {t, s, y, r, q, w}.  s = t - r (not in the first iteration),
 // t = r - alpha q, y = alpha q - r (first) or s - alpha (w - q).
 template <int L>
-__global__ void gp_tsy_kernel(VecArgs A) {
+__global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const bool first = A.ctl->iters == 0;
@@ -558,7 +669,7 @@ struct GpUpdArgs {
 };
 
 template <int L>
-__global__ void gp_update_kernel(GpUpdArgs G) {
+__global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   const VecArgs& A = G.a;
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;

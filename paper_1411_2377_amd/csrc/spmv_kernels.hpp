@@ -23,7 +23,9 @@
 namespace mp {
 
 constexpr int kRowsPerBlock = 64;
-constexpr int kChunk = 128;
+// entries staged per phase-1 chunk (about 8 KB of rounded products in LDS at every precision)
+template <int L>
+constexpr int chunk_entries() { return 2048 / L; }
 
 struct SpmvArgs {
   int64_t n_rows;
@@ -44,6 +46,7 @@ struct SpmvArgs {
 
 template <int L>
 __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
+  constexpr int kChunk = chunk_entries<L>();
   __shared__ int32_t s_rp[kRowsPerBlock + 1];
   __shared__ uint32_t s_m[L][kChunk];
   __shared__ int32_t s_e[kChunk];
@@ -108,6 +111,7 @@ template <int L>
 __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   constexpr int WF = window_fast_digits<L>();
   constexpr int WB = WF * 64;  // digits of the shared window used for wide rows
+  constexpr int kChunk = chunk_entries<L>();
   __shared__ int32_t s_rp[kRowsPerBlock + 1];
   __shared__ uint32_t s_p[2 * L][kChunk];
   __shared__ int32_t s_e[kChunk];

@@ -23,8 +23,14 @@ mp::VecRef ref(const mp_vec& v) {
   return r;
 }
 
-unsigned dot_grid(int64_t n) {
-  int64_t g = (n + 64 * 8 - 1) / (64 * 8);
+// Blocks per inner product: two elements per thread, at most kDotMaxBlocks, and few enough
+// that all the dots of one launch are resident at once: the per-lane windows take
+// 8 * window_fast_digits * 257 bytes of LDS (L = 4: 37 KB, 8: 53 KB, 16: 86 KB of the 160 KB
+// per CU), i.e. 4, 2 or 1 blocks per CU on 256 CUs.
+unsigned dot_grid(int64_t n, int nd, int L) {
+  const int per_cu = (L == 4) ? 4 : (L == 8) ? 2 : 1;
+  int64_t g = (n + 2 * mp::kDotThreads - 1) / (2 * mp::kDotThreads);
+  g = std::min<int64_t>(g, (256 * per_cu) / std::max(1, nd));
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, mp::kDotMaxBlocks));
 }
 
@@ -34,11 +40,11 @@ unsigned ew_grid(int64_t n) {
 }
 
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
-  const unsigned g = dot_grid(a.n);
+  const unsigned g = dot_grid(a.n, a.nd, L);
   switch (L) {
-    case 4: hipLaunchKernelGGL(mp::dot_kernel<4>, dim3(g), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(mp::dot_kernel<8>, dim3(g), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(mp::dot_kernel<16>, dim3(g), dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(mp::dot_kernel<4>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(mp::dot_kernel<8>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(mp::dot_kernel<16>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
