@@ -6,3 +6,4 @@ built.
 """
 from .api import *  # noqa: F401,F403
 from .mparray import CSRMatrix, MPArray  # noqa: F401
+from . import autograd  # noqa: F401,E402

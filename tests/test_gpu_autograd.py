@@ -1,0 +1,153 @@
+"""Autograd wrappers: gradients bit-identical to the oracle's (A^T g, RN(g_i x_j), the adjoint
+solve), central finite differences on the power-law workload, and the one-use limit."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import codec, krylov, mpnum, spmv as ospmv
+from tests.util import assert_bitwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def lib():
+    import paper_1411_2377_amd as M
+    return M
+
+
+def packed(M, h):
+    return M.autograd.pack(M.MPArray.from_host(h)).requires_grad_(True)
+
+
+def to_np(M, t, p):
+    return M.autograd.unpack(t.detach(), p).to_numpy()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+@pytest.mark.parametrize("p", [128, 512])
+def test_spmv_backward_matches_oracle(mode, p):
+    M = lib()
+    A_h, x_h = synth.config1(p=p, n=300, per_row=9)
+    g_h = synth.mp_uniform(np.random.default_rng(7), A_h.n_rows, p)
+    A = M.CSRMatrix.from_host(A_h)
+    S = M.autograd.SparseStructure.of(A)
+    vt, xt = packed(M, A_h.vals), packed(M, x_h)
+    y = M.autograd.spmv(S, vt, xt, mode)
+    y.backward(M.autograd.pack(M.MPArray.from_host(g_h)))
+    gl, gh = to_np(M, xt.grad, p)
+    vl, vh = to_np(M, vt.grad, p)
+    rp, ci = A_h.row_ptr.tolist(), A_h.col_idx.tolist()
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    go = codec.decode(g_h.limbs, g_h.hdr, p)
+    xo = codec.decode(x_h.limbs, x_h.hdr, p)
+    assert_bitwise(gl, gh, ospmv.spmv_t(A_h.n_rows, A_h.n_cols, rp, ci, vals, go, p, mode), p, what="grad x")
+    assert_bitwise(vl, vh, ospmv.grad_vals(rp, ci, go, xo, p), p, what="grad vals")
+    yl, yh = to_np(M, y, p)
+    assert_bitwise(yl, yh, ospmv.spmv(rp, ci, vals, xo, p, mode), p, what="forward")
+
+
+def test_second_use_raises():
+    M = lib()
+    A_h, x_h = synth.config1(p=128, n=64, per_row=3)
+    A = M.CSRMatrix.from_host(A_h)
+    S = M.autograd.SparseStructure.of(A)
+    vt, xt = packed(M, A_h.vals), packed(M, x_h)
+    M.autograd.spmv(S, vt, xt, 0)
+    with pytest.raises(RuntimeError):
+        M.autograd.spmv(S, vt, packed(M, x_h), 0)
+
+
+def loss(M, A, x, g):
+    """<g, A x> (EXACT product, exact inner product) as a Fraction."""
+    y = M.mpspmv_csr(A, x, mode=1)
+    d = M.mp_dot(g, y).to_numpy()
+    return codec.decode(d[0], d[1], x.p)[0].to_fraction()
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_finite_differences_powerlaw(p):
+    """Central differences of L(x, a) = <g, A x> on the power-law workload (n = 500000, mean
+    20 / max 2000 entries per row): the loss is linear, so the difference quotient equals the
+    gradient up to rounding of the products and inner products (relative 2^-(p/2))."""
+    M = lib()
+    A_h, x_h, g_h = synth.config3(p=p)
+    A = M.CSRMatrix.from_host(A_h)
+    S = M.autograd.SparseStructure.of(A)
+    vt, xt = packed(M, A_h.vals), packed(M, x_h)
+    y = M.autograd.spmv(S, vt, xt, 1)
+    y.backward(M.autograd.pack(M.MPArray.from_host(g_h)))
+    gx = to_np(M, xt.grad, p)
+    gv = to_np(M, vt.grad, p)
+    g = M.MPArray.from_host(g_h)
+    rng = np.random.default_rng(p)
+    tol = Fraction(1, 2 ** (p // 2))
+
+    xdev = M.MPArray.from_host(x_h)
+
+    def fd(kind, idx):
+        """(L(v + h) - L(v - h)) / (2h) with the entry changed in place on the device."""
+        base = x_h if kind == "x" else A_h.vals
+        dev = xdev if kind == "x" else A.vals
+        v = codec.decode(base.limbs[:, [idx]], base.hdr[[idx]], p)[0]
+        h = mpnum.MP(0, 1 << (p - 1), v.e - 12, p) if v.m else mpnum.round_fraction(Fraction(1, 2 ** 40), p)
+        out = []
+        for nv in (mpnum.add(v, h), mpnum.sub(v, h)):
+            l, hh = codec.encode([nv], p)
+            dev.limbs[:, idx] = torch.from_numpy(l[:, 0].view(np.int32)).to(dev.limbs.device)
+            dev.hdr[idx] = int(hh[0])
+            out.append((loss(M, A, xdev, g), nv))
+        l, hh = codec.encode([v], p)
+        dev.limbs[:, idx] = torch.from_numpy(l[:, 0].view(np.int32)).to(dev.limbs.device)
+        dev.hdr[idx] = int(hh[0])
+        (lp, vp), (lm, vm) = out
+        return (lp - lm) / (vp.to_fraction() - vm.to_fraction())
+    lengths = np.diff(A_h.row_ptr)
+    for j in list(rng.integers(0, A_h.n_cols, 6)):
+        want = codec.decode(gx[0][:, [j]], gx[1][[j]], p)[0].to_fraction()
+        got = fd("x", int(j))
+        assert abs(got - want) <= tol * max(abs(want), Fraction(1, 2 ** 200)), (j, float(got), float(want))
+    ks = list(rng.integers(0, A_h.nnz, 6)) + [int(A_h.row_ptr[int(np.argmax(lengths))])]
+    for k in ks:
+        want = codec.decode(gv[0][:, [k]], gv[1][[k]], p)[0].to_fraction()
+        got = fd("a", int(k))
+        assert abs(got - want) <= tol * max(abs(want), Fraction(1, 2 ** 200)), (k, float(got), float(want))
+
+
+def test_solve_adjoint_matches_oracle_and_duality():
+    """x = A^{-1} b on the scaled 3-D operator (16^3 instance of the ill-conditioned workload,
+    p = 512); d(sum x)/db = lambda from one transposed solve, bit-identical to the oracle's
+    transposed BiCG, and <lambda, b> = sum x to the solver tolerance."""
+    M = lib()
+    p = 512
+    A_h, xstar_h, ones_h = synth.config5(p=p, m=8)
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.mpspmv_csr(A, M.MPArray.from_host(xstar_h), mode=1)
+    S = M.autograd.SparseStructure.of(A)
+    vt = packed(M, A_h.vals)
+    bt = M.autograd.pack(b).requires_grad_(True)
+    opts = dict(mode=1, maxit=2000, rtol=(1, -100), atol=(0, 0), chunk=32)
+    xt = M.autograd.solve(S, vt, bt, **opts)
+    xt.backward(M.autograd.pack(M.MPArray.from_host(ones_h)))
+    lam = to_np(M, bt.grad, p)
+    xs = to_np(M, xt, p)
+    # oracle: the transposed solve with the same parameters
+    rp, ci = A_h.row_ptr.tolist(), A_h.col_idx.tolist()
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    tp, ti, tv = ospmv.transpose(A_h.n_rows, A_h.n_cols, rp, ci, vals)
+    c_rel = mpnum.round_fraction(Fraction(1, 10 ** 100), p)
+    ones = codec.decode(ones_h.limbs, ones_h.hdr, p)
+    ref = krylov.bicg(lambda v: ospmv.spmv_exact(tp, ti, tv, v, p), lambda v: ospmv.spmv_exact(rp, ci, vals, v, p),
+                      ones, c_rel, mpnum.zero(p), 2000, p)
+    assert ref.status == krylov.CONVERGED
+    assert_bitwise(lam[0], lam[1], ref.x, p, what="adjoint lambda")
+    bo = codec.decode(*b.to_numpy(), p)
+    lb = sum(l.to_fraction() * v.to_fraction() for l, v in zip(ref.x, bo))
+    sx = sum(v.to_fraction() for v in codec.decode(xs[0], xs[1], p))
+    assert abs(lb - sx) <= Fraction(1, 10 ** 80) * abs(sx)
+    gv = to_np(M, vt.grad, p)
+    xo = codec.decode(xs[0], xs[1], p)
+    assert_bitwise(gv[0], gv[1], ospmv.grad_vals(rp, ci, ref.x, xo, p, negate=True), p, what="grad vals (solve)")
