@@ -22,7 +22,7 @@ import torch
 from . import api
 from .mparray import CSRMatrix, MPArray
 
-_USES = weakref.WeakKeyDictionary()
+_USES = {}  # id(tensor) -> (weak reference, uses pending backward)
 
 
 def pack(a):
@@ -46,16 +46,18 @@ def unpack(t, p):
 def _claim(t):
     if t is None or not t.requires_grad:
         return
-    n = _USES.get(t, 0)
-    if n >= 1:
+    ent = _USES.get(id(t))
+    if ent is not None and ent[0]() is t and ent[1] >= 1:
         raise RuntimeError("an MP tensor may feed only one MP operation per backward pass "
                            "(float gradient accumulation would corrupt it)")
-    _USES[t] = n + 1
+    key = id(t)
+    _USES[key] = (weakref.ref(t, lambda _r, k=key: _USES.pop(k, None)), 1)
 
 
 def _release(t):
-    if t is not None and t in _USES:
-        _USES[t] = max(0, _USES[t] - 1)
+    ent = _USES.get(id(t)) if t is not None else None
+    if ent is not None and ent[0]() is t:
+        _USES[id(t)] = (ent[0], 0)
 
 
 class SparseStructure:

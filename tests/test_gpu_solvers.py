@@ -143,3 +143,19 @@ def test_convdiff_full_size_first_iterations(solver, mode):
     A_h, _ = synth.config2()
     b_h, b_o = rhs_ones(A_h)
     run_both(solver, A_h, b_h, mode, maxit=2, rtol=(1, -20), atol=(1, -50), b_oracle=b_o)
+
+
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+def test_scaled_3d_ill_conditioned_iterates(solver):
+    """The row-scaled 3-D operator (d_i = 10^u, u ~ U(-15, 15); condition about 1e30) at
+    p = 512 on an 8^3 grid: 40 iterations bit-identical to the oracle in EXACT mode."""
+    A_h, xs_h, _ = synth.config5(p=512, m=8)
+    M = lib()
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.mpspmv_csr(A, M.MPArray.from_host(xs_h), mode=1)
+    bl, bh = b.to_numpy()
+    S = OracleSystem(A_h)
+    b_o = ospmv.spmv_exact(S.rp, S.ci, S.vals, codec.decode(xs_h.limbs, xs_h.hdr, 512), 512)
+    assert_bitwise(bl, bh, b_o, 512, what="b = A x*")
+    run_both(solver, A_h, synth.MPHost(bl, bh, 512), 1, maxit=40, rtol=(1, -100), atol=(0, 0),
+             b_oracle=b_o)
