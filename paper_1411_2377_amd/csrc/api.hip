@@ -49,13 +49,8 @@ int get_ctx(DeviceCtx** out) {
     }
     e = hipMemset(c->status, 0, sizeof(uint32_t) * 4);
     if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
-    e = hipMalloc((void**)&c->dot_part, dot_workspace_bytes());
-    if (e == hipSuccess) e = hipMalloc((void**)&c->dot_ticket, 64);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->scal_limb, 16 * 32 * 4);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->scal_hdr, 32 * 4);
-    if (e != hipSuccess) return fail(MPS_ENOMEM, "context workspace: %s", hipGetErrorString(e));
-    e = hipMemset(c->dot_ticket, 0, 64);
-    if (e != hipSuccess) return hip_fail(e, "hipMemset(ticket)");
+    int r = dot_work_alloc(1, &c->dot_anchor, &c->dot_win, &c->dot_ticket, nullptr);
+    if (r) return r;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     g_ctx[dev] = c;
@@ -143,7 +138,7 @@ static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
 
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s) {
+                const int32_t* done, hipStream_t s, const SpmvPairs* pairs) {
   if (n_rows == 0) return MPS_OK;
   mp::SpmvArgs a;
   a.n_rows = n_rows;
@@ -160,6 +155,20 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.y_ld = y.ld;
   a.status = status;
   a.done = done;
+  a.npair = 0;
+  a.anchor = nullptr;
+  for (int k = 0; k < 3; ++k) {
+    a.pair_hdr[k] = nullptr;
+    a.pair_slot[k] = 0;
+  }
+  if (pairs && pairs->npair > 0) {
+    a.npair = pairs->npair;
+    a.anchor = pairs->anchor;
+    for (int k = 0; k < pairs->npair; ++k) {
+      a.pair_hdr[k] = pairs->hdr[k];
+      a.pair_slot[k] = pairs->slot[k];
+    }
+  }
   switch (L) {
     case 4: launch_spmv<4>(a, mode, s); break;
     case 8: launch_spmv<8>(a, mode, s); break;

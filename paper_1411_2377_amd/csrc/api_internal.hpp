@@ -10,15 +10,24 @@ namespace mpapi {
 struct DeviceCtx {
   int device = 0;
   uint32_t* status = nullptr;  // device status word (MP_ST_* bits)
-  // workspace of the stand-alone inner product entry point
-  int32_t* dot_part = nullptr;
+  // inner-product state of the stand-alone mp_dot (one slot)
+  int32_t* dot_anchor = nullptr;
+  int64_t* dot_win = nullptr;
   uint32_t* dot_ticket = nullptr;
-  uint32_t* scal_limb = nullptr;  // [16][32] scalar slots
-  int32_t* scal_hdr = nullptr;    // [32]
 };
 
-// bytes of the inner-product partial-record workspace (largest precision)
-size_t dot_workspace_bytes();
+// Inner products of y = A x with other vectors, whose exponent anchors the product kernel fills.
+struct SpmvPairs {
+  int npair = 0;
+  const int32_t* hdr[3] = {nullptr, nullptr, nullptr};  // nullptr: y itself
+  int slot[3] = {0, 0, 0};
+  int32_t* anchor = nullptr;
+};
+
+// int64 digits of one inner-product window slot (largest precision)
+int64_t dot_window_stride();
+// allocate and clear inner-product state with `nslots` slots
+int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s);
 
 int fail(int code, const char* fmt, ...);
 void clear_error();
@@ -30,6 +39,6 @@ bool vec_overlap(const mp_vec* a, const mp_vec* b, int L);
 int check_csr(const mp_csr* A, int check_device_data);
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s);
+                const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr);
 
 }  // namespace mpapi

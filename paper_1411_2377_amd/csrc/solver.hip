@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <initializer_list>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpspmv.h"
@@ -157,7 +159,8 @@ struct Work {
   int32_t* vhdr = nullptr;
   mp::Scalars S{nullptr, nullptr};
   mp::Ctl* ctl = nullptr;
-  int32_t* part = nullptr;
+  int32_t* anchor = nullptr;  // inner-product slots (see DotWork)
+  int64_t* win = nullptr;
   uint32_t* ticket = nullptr;
   mp::Ctl* h_ctl = nullptr;  // pinned
   hipStream_t ws = nullptr;
@@ -189,7 +192,8 @@ struct Work {
     hipFree(S.limb);
     hipFree(S.hdr);
     hipFree(ctl);
-    hipFree(part);
+    hipFree(anchor);
+    hipFree(win);
     hipFree(ticket);
     if (h_ctl) hipHostFree(h_ctl);
     if (ev) hipEventDestroy(ev);
@@ -206,16 +210,15 @@ int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
   if (e == hipSuccess) e = hipMalloc((void**)&W.S.limb, (size_t)L * mp::kNumScalars * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&W.S.hdr, (size_t)mp::kNumScalars * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&W.ctl, sizeof(mp::Ctl));
-  if (e == hipSuccess) e = hipMalloc((void**)&W.part, dot_workspace_bytes());
-  if (e == hipSuccess) e = hipMalloc((void**)&W.ticket, 64);
   if (e != hipSuccess) return fail(MPS_ENOMEM, "solver workspace: %s", hipGetErrorString(e));
   e = hipHostMalloc((void**)&W.h_ctl, sizeof(mp::Ctl), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&W.ws, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&W.ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(W.ev, user);
   if (e == hipSuccess) e = hipStreamWaitEvent(W.ws, W.ev, 0);
-  if (e == hipSuccess) e = hipMemsetAsync(W.ticket, 0, 64, W.ws);
   if (e != hipSuccess) return hip_fail(e, "solver setup");
+  int r = dot_work_alloc(mp::kDotSlots, &W.anchor, &W.win, &W.ticket, W.ws);
+  if (r) return r;
   // every scalar slot starts as +0
   mp::VecArgs a{};
   a.n = mp::kNumScalars;
@@ -234,18 +237,29 @@ struct Op {
 };
 
 int apply(const Op& op, int L, int mode, const mp::VecRef& x, const mp::VecRef& y,
-          uint32_t* status, const mp::Ctl* ctl, hipStream_t s) {
+          uint32_t* status, const mp::Ctl* ctl, hipStream_t s, const SpmvPairs* pairs = nullptr) {
   mp_vec xv{x.limb, x.hdr, 0, x.ld}, yv{y.limb, y.hdr, 0, y.ld};
   return spmv_launch(L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                     ctl ? &ctl->done : nullptr, s);
+                     ctl ? &ctl->done : nullptr, s, pairs);
+}
+
+// Inner products of an SpMV output with up to three vectors (nullptr: the output itself).
+SpmvPairs pairs_of(const Work& W, std::initializer_list<std::pair<const int32_t*, int>> list) {
+  SpmvPairs P;
+  P.anchor = W.anchor;
+  for (auto& it : list) {
+    P.hdr[P.npair] = it.first;
+    P.slot[P.npair] = it.second;
+    ++P.npair;
+  }
+  return P;
 }
 
 mp::DotArgs dot_args(const Work& W, uint32_t* status, int epi) {
   mp::DotArgs a{};
   a.n = W.n;
   a.S = W.S;
-  a.part = W.part;
-  a.ticket = W.ticket;
+  a.w = dot_work(W.anchor, W.win, W.ticket, mp::kDotSlots);
   a.ctl = W.ctl;
   a.status = status;
   a.epi = epi;
@@ -310,15 +324,20 @@ int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_sol
   }
   a.v[0] = W.vec(1);
   a.v[1] = W.vec(0);
-  if ((r = launch_ew(L, EW_COPY, a, W.ws))) return r;
+  a.anchor = W.anchor;
+  a.aslot[0] = 1;
+  a.aslot[1] = 2;
+  if ((r = launch_ew(L, EW_COPY_ANCHOR, a, W.ws))) return r;
   mp::DotArgs d = dot_args(W, status, mp::EPI_SETUP);
   d.nd = 2;
   d.x[0] = W.vec(0);
   d.y[0] = W.vec(0);
   d.out[0] = mp::slot_ref(W.S, mp::S_Q0);
+  d.slot[0] = 1;
   d.x[1] = W.vec(1);
   d.y[1] = W.vec(0);
   d.out[1] = mp::slot_ref(W.S, mp::S_RHO);
+  d.slot[1] = 2;
   return launch_dot(L, d, W.ws);
 }
 
@@ -446,19 +465,21 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
     if ((rr = launch_ew(L, EW_BICG_DIR, a, W.ws))) return rr;
-    if ((rr = apply(op, L, o->mode, P, Z, st, W.ctl, W.ws))) return rr;
+    const SpmvPairs sig = pairs_of(W, {{PT.hdr, 0}});
+    if ((rr = apply(op, L, o->mode, P, Z, st, W.ctl, W.ws, &sig))) return rr;
     if ((rr = apply(opT, L, o->mode, PT, ZT, st, W.ctl, W.ws))) return rr;
     mp::DotArgs d = dot_args(W, st, mp::EPI_BICG_SIGMA);
     d.nd = 1;
-    d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA);
+    d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA); d.slot[0] = 0;
     if ((rr = launch_dot(L, d, W.ws))) return rr;
     a = ew_args(W, st);
     a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
+    a.anchor = W.anchor; a.aslot[0] = 1; a.aslot[1] = 2;
     if ((rr = launch_ew(L, EW_BICG_UPDATE, a, W.ws))) return rr;
     d = dot_args(W, st, mp::EPI_BICG_CONV);
     d.nd = 2;
-    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q);
-    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT);
+    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
+    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
     d.hist = hist;
     return launch_dot(L, d, W.ws);
   };
@@ -508,34 +529,39 @@ int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
     if ((rr = launch_ew(L, EW_GP_DIR, a, W.ws))) return rr;
-    if ((rr = apply(op, L, o->mode, P, Q, st, W.ctl, W.ws))) return rr;
+    const SpmvPairs den = pairs_of(W, {{RT.hdr, 0}});
+    if ((rr = apply(op, L, o->mode, P, Q, st, W.ctl, W.ws, &den))) return rr;
     mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
     d.nd = 1;
-    d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN);
+    d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN); d.slot[0] = 0;
     if ((rr = launch_dot(L, d, W.ws))) return rr;
     a = ew_args(W, st);
     a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
+    a.anchor = W.anchor; a.aslot[0] = 3; a.aslot[1] = 5;   // (y, y), (y, t)
     if ((rr = launch_ew(L, EW_GP_TSY, a, W.ws))) return rr;
-    if ((rr = apply(op, L, o->mode, T, V, st, W.ctl, W.ws))) return rr;
+    const SpmvPairs mus = pairs_of(W, {{T.hdr, 4}, {Y.hdr, 6}, {nullptr, 7}});  // (v,t) (v,y) (v,v)
+    if ((rr = apply(op, L, o->mode, T, V, st, W.ctl, W.ws, &mus))) return rr;
     d = dot_args(W, st, mp::EPI_GP_ZETA);
     d.nd = 5;
-    d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1);
-    d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2);
-    d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3);
-    d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4);
-    d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5);
+    d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1); d.slot[0] = 3;
+    d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2); d.slot[1] = 4;
+    d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3); d.slot[2] = 5;
+    d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4); d.slot[3] = 6;
+    d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5); d.slot[4] = 7;
     if ((rr = launch_dot(L, d, W.ws))) return rr;
     mp::GpUpdArgs g{};
     g.a = ew_args(W, st);
     g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
     g.a.v[6] = P; g.a.v[7] = T;
+    g.a.anchor = W.anchor; g.a.aslot[0] = 1; g.a.aslot[1] = 2;
     g.y = Y;
     g.v = V;
+    g.rt = RT;
     if ((rr = launch_gp_update(L, g, W.ws))) return rr;
     d = dot_args(W, st, mp::EPI_GP_CONV);
     d.nd = 2;
-    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q);
-    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT);
+    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
+    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
     d.hist = hist;
     return launch_dot(L, d, W.ws);
   };

@@ -194,42 +194,41 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
 }
 
 // ------------------------------------------------------------------------------------------
-// Exact inner products: up to kDotMaxND dots of length n in one launch (256-thread blocks).
-// Each block forms the exact products of its elements in per-lane carry-save windows anchored
-// at the block's smallest product exponent, sums the lane windows digit by digit, normalises
-// the block sum to sign + magnitude limbs and writes that record out.  The last block to finish
-// (integer ticket) aligns all records into one window, rounds once, stores the result and runs
-// the driver epilogue.  Lane windows are padded to an odd stride so that both the per-lane
-// adds and the per-digit sums hit distinct LDS banks.
+// Exact inner products.
+//
+// Every inner product owns a slot: an exponent anchor (the smallest and largest e_x + e_y over
+// its non-zero products, kept with integer atomic min/max), a global carry-save window of int64
+// digits, and an integer ticket.  The kernel that *produces* the operands fills the anchor while
+// it writes them (the SpMV for products with its output, the vector updates for theirs), so the
+// inner-product kernel starts with a global anchor: each block accumulates its exact products in
+// per-lane LDS windows, sums them digit by digit and adds the digit sums to the slot's window
+// with integer atomics (associative, hence order-independent and deterministic).  The last block
+// rounds the window once, clears the slot for its next use and, once every inner product of the
+// launch is done, runs the driver epilogue.  Lane windows are padded to an odd stride so that the
+// per-lane adds and the per-digit sums hit distinct LDS banks.
 // ------------------------------------------------------------------------------------------
 constexpr int kDotMaxND = 5;
 constexpr int kDotMaxBlocks = 128;
 constexpr int kDotThreads = 256;
 constexpr int kDotStride = kDotThreads + 1;
-
-template <int L>
-constexpr int dot_window_digits() { return window_fast_digits<L>(); }
+constexpr int kDotSlots = 8;
 
 // block-shared window capacity (the per-lane windows' LDS reused as one array)
 template <int L>
 constexpr int dot_shared_digits() { return window_fast_digits<L>() * kDotStride; }
 
-template <int L>
-constexpr int dot_rec_ints() { return 3 + dot_shared_digits<L>(); }
+// Per-solve (or per-context) inner-product state.
+// Anchors are spread over kAnchorBins bins per slot (a producing wave updates bin
+// wave-index mod kAnchorBins) so that a thousand producing waves do not contend on one address;
+// the inner-product kernel reduces the bins.
+constexpr int kAnchorBins = 64;
 
-struct DotArgs {
-  int64_t n;
-  int nd;
-  VecRef x[kDotMaxND];
-  VecRef y[kDotMaxND];
-  VecRef out[kDotMaxND];  // result d goes to element 0 of out[d]
-  Scalars S;
-  int32_t* part;     // [gridDim][kDotMaxND][dot_rec_ints]
-  uint32_t* ticket;  // zero before the launch, reset by the last block
-  Ctl* ctl;          // nullable
-  uint32_t* status;
-  int epi;
-  VecRef hist;
+struct DotWork {
+  int32_t* anchor;    // [nslots][kAnchorBins][2]: emin, emax; (INT32_MAX, INT32_MIN) when empty
+  int64_t* win;       // [nslots][win_stride] carry-save digits, zero between uses
+  uint32_t* ticket;   // [nslots + 1]; the last one counts finished inner products of a launch
+  int64_t win_stride; // >= dot_shared_digits<L>()
+  int nslots;
 };
 
 MPD int32_t wave_min(int32_t v) {
@@ -244,73 +243,84 @@ MPD int32_t wave_max(int32_t v) {
   return v;
 }
 
-MPD int64_t wave_max64(int64_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const int64_t t = __shfl_xor(v, o);
-    v = t > v ? t : v;
+// Fold the exponent of the product of two headers into a running (emin, emax).
+MPD void pair_exponent(int32_t h1, int32_t h2, int32_t& emin, int32_t& emax) {
+  if (!hdr_is_zero(h1) && !hdr_is_zero(h2)) {
+    const int32_t e = (h1 >> 1) + (h2 >> 1);
+    emin = min(emin, e);
+    emax = max(emax, e);
   }
-  return v;
 }
+
+// Publish a block's (emin, emax) to an anchor slot: wave reduction, then one lane per wave
+// (an integer min/max is order-independent).
+MPD int anchor_bin() {
+  return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kAnchorBins - 1));
+}
+
+MPD void anchor_publish(int32_t* anchor, int slot, int32_t emin, int32_t emax) {
+  emin = wave_min(emin);
+  emax = wave_max(emax);
+  if ((threadIdx.x & 63) == 0 && emax >= emin) {
+    int32_t* a = anchor + 2 * ((int64_t)slot * kAnchorBins + anchor_bin());
+    atomicMin(&a[0], emin);
+    atomicMax(&a[1], emax);
+  }
+}
+
+struct DotArgs {
+  int64_t n;
+  int nd;
+  VecRef x[kDotMaxND];
+  VecRef y[kDotMaxND];
+  VecRef out[kDotMaxND];  // result d goes to element 0 of out[d]
+  int slot[kDotMaxND];
+  DotWork w;
+  Scalars S;
+  Ctl* ctl;  // nullable
+  uint32_t* status;
+  int epi;
+  VecRef hist;
+};
 
 template <int L>
 __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
-  constexpr int WF = dot_window_digits<L>();
+  constexpr int WF = window_fast_digits<L>();
   constexpr int WB = dot_shared_digits<L>();
-  constexpr int REC = dot_rec_ints<L>();
-  constexpr int kRecPre = 3 + WF;          // record words staged in LDS by the last block
-  constexpr int WMAXF = 2 * L + 16;        // final windows up to this size stay in registers
-  static_assert(64 + (kDotMaxBlocks * kRecPre + 1) / 2 <= WB, "record staging must fit");
+  constexpr int WMAXF = 2 * L + 16;  // final windows up to this size are carried in registers
   __shared__ int64_t s_win[WB];
-  // the last block stages record heads behind the first 64 window digits
-  int32_t(*s_rec)[kRecPre] = reinterpret_cast<int32_t(*)[kRecPre]>(s_win + 64);
-  __shared__ int64_t s_red[2][kDotThreads / 64];
-  __shared__ int64_t s_part[kDotThreads / 64][64];
   __shared__ uint32_t s_last;
+  __shared__ int32_t s_anc[2][kDotThreads / 64];
   if (solve_done(A.ctl)) return;
   const int t = threadIdx.x;
-  const int wave = t >> 6;
   uint32_t st = 0;
-  const int64_t stride = (int64_t)gridDim.x * kDotThreads;
-  const int64_t first = (int64_t)blockIdx.x * kDotThreads + t;
-  const int d = blockIdx.y;  // the dots of one launch run side by side, one grid row each
-
-  do {
-    const VecRef X = A.x[d], Y = A.y[d];
-    // exponent range of the block's non-zero products
-    int32_t emin = INT32_MAX, emax = INT32_MIN;
-    for (int64_t i = first; i < A.n; i += stride) {
-      const int32_t hx = X.hdr[i], hy = Y.hdr[i];
-      if (!hdr_is_zero(hx) && !hdr_is_zero(hy)) {
-        const int32_t e = (hx >> 1) + (hy >> 1);
-        emin = min(emin, e);
-        emax = max(emax, e);
-      }
-    }
-    emin = wave_min(emin);
-    emax = wave_max(emax);
-    if ((t & 63) == 0) {
-      s_red[0][wave] = emin;
-      s_red[1][wave] = emax;
-    }
-    __syncthreads();
+  const int d = blockIdx.y;  // the inner products of one launch run side by side, one row each
+  const int slot = A.slot[d];
+  int32_t* abins = A.w.anchor + 2 * (int64_t)slot * kAnchorBins;
+  int32_t emin = INT32_MAX, emax = INT32_MIN;
+  if (t < kAnchorBins) {
+    emin = abins[2 * t];
+    emax = abins[2 * t + 1];
+  }
+  emin = wave_min(emin);
+  emax = wave_max(emax);
+  if ((t & 63) == 0) {
+    s_anc[0][t >> 6] = emin;
+    s_anc[1][t >> 6] = emax;
+  }
+  __syncthreads();
 #pragma unroll
-    for (int w = 0; w < kDotThreads / 64; ++w) {
-      emin = min(emin, (int32_t)s_red[0][w]);
-      emax = max(emax, (int32_t)s_red[1][w]);
-    }
-    __syncthreads();
-    int32_t* rec = A.part + ((int64_t)blockIdx.x * kDotMaxND + d) * REC;
-    if (emax < emin) {
-      if (t == 0) rec[0] = 0;
-      break;
-    }
-    const int W = window_digits<L>(emin, emax);
-    if (W > WB) {
-      st |= kStWindow;
-      if (t == 0) rec[0] = 0;
-      break;
-    }
+  for (int k = 0; k < kDotThreads / 64; ++k) {
+    emin = min(emin, s_anc[0][k]);
+    emax = max(emax, s_anc[1][k]);
+  }
+  int64_t* gw = A.w.win + (int64_t)slot * A.w.win_stride;
+  const bool any = emax >= emin;
+  const int W = any ? window_digits<L>(emin, emax) : 0;
+  if (any && W > WB) st |= kStWindow;
+  if (any && W <= WB) {
+    const VecRef X = A.x[d], Y = A.y[d];
+    const int64_t stride = (int64_t)gridDim.x * kDotThreads;
     const bool fast = W <= WF;
     if (fast) {
       for (int w = 0; w < WF; ++w) s_win[w * kDotStride + t] = 0;
@@ -319,11 +329,12 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
       __syncthreads();
     }
     // products, two elements at a time: both headers, then both limb sets in flight together
-    for (int64_t i0 = first; i0 < A.n; i0 += 2 * stride) {
+    for (int64_t i0 = (int64_t)blockIdx.x * kDotThreads + t; i0 < A.n; i0 += 2 * stride) {
       const int64_t i1 = i0 + stride;
       const bool has1 = i1 < A.n;
       const int32_t hx0 = X.hdr[i0], hy0 = Y.hdr[i0];
-      const int32_t hx1 = has1 ? X.hdr[i1] : (int32_t)0x80000000, hy1 = has1 ? Y.hdr[i1] : (int32_t)0x80000000;
+      const int32_t hx1 = has1 ? X.hdr[i1] : (int32_t)0x80000000;
+      const int32_t hy1 = has1 ? Y.hdr[i1] : (int32_t)0x80000000;
       const bool nz0 = !hdr_is_zero(hx0) && !hdr_is_zero(hy0);
       const bool nz1 = !hdr_is_zero(hx1) && !hdr_is_zero(hy1);
       uint32_t x0[L], y0[L], x1[L], y1[L];
@@ -351,8 +362,8 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     }
     __syncthreads();
     if (fast) {
-      // digit w is summed over the 256 lane windows by TPD consecutive threads (an odd row
-      // stride keeps their reads on distinct banks), then combined with shuffles
+      // digit w is summed over the 256 lane windows by TPD consecutive threads, then combined
+      // with shuffles; the sum goes to the slot's global window
       constexpr int TPD = (WF <= 32) ? 8 : 4;
       constexpr int SEG = 64 / TPD;
       const int w = t / TPD, sub = t % TPD;
@@ -371,148 +382,95 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
       int64_t dsum = a0 + a1;
 #pragma unroll
       for (int o = 1; o < TPD; o <<= 1) dsum += __shfl_xor(dsum, o);
-      __syncthreads();
-      if (w < W && sub == 0) s_win[w] = dsum;
-      __syncthreads();
-    }
-    // normalise the block sum to sign + magnitude limbs (one lane)
-    if (t == 0 && fast) {
-      RegWindow<WF> R;
-      reg_normalize<WF>(s_win, 1, W, R);
-      rec[1] = emin;
-      rec[2] = R.nl;
-#pragma unroll
-      for (int w = 0; w < WF; ++w)
-        if (w < R.nl) rec[3 + w] = (int32_t)R.limb[w];
-      rec[0] = R.nl ? (1 | ((int)R.neg << 1)) : 0;
-    } else if (t == 0) {
-      int64_t c = 0;
-      for (int w = 0; w < W; ++w) {
-        const int64_t v = s_win[w] + c;
-        s_win[w] = (int64_t)(uint32_t)v;
-        c = v >> 32;
+      if (w < W && sub == 0 && dsum != 0)
+        atomicAdd((unsigned long long*)&gw[w], (unsigned long long)dsum);
+    } else {
+      for (int w = t; w < W; w += kDotThreads) {
+        const int64_t v = s_win[w];
+        if (v) atomicAdd((unsigned long long*)&gw[w], (unsigned long long)v);
       }
-      const int neg = c < 0;
-      if (neg) {
-        uint32_t cy = 1;
-        for (int w = 0; w < W; ++w) s_win[w] = (int64_t)__builtin_addc(~(uint32_t)s_win[w], 0u, cy, &cy);
-      }
-      int nl = W;
-      while (nl > 0 && (uint32_t)s_win[nl - 1] == 0u) --nl;
-      rec[1] = emin;
-      rec[2] = nl;
-      for (int w = 0; w < nl; ++w) rec[3 + w] = (int32_t)(uint32_t)s_win[w];
-      rec[0] = nl ? (1 | (neg << 1)) : 0;
     }
-    __syncthreads();
-  } while (false);
+  }
 
   __threadfence();
-  if (t == 0) s_last = (atomicAdd(&A.ticket[d], 1u) == gridDim.x - 1) ? 1u : 0u;
+  __syncthreads();
+  if (t == 0) s_last = (atomicAdd(&A.w.ticket[slot], 1u) == gridDim.x - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) {
     if (st) atomicOr(A.status, st);
     return;
   }
   __threadfence();
-  const int G = gridDim.x;
-  {
-    // stage the head of every block record in LDS with independent coalesced loads (the fence
-    // above makes the other blocks' writes visible); longer records are read on from memory
-#pragma unroll 4
-    for (int idx = t; idx < G * kRecPre; idx += kDotThreads) {
-      const int b = idx / kRecPre, j = idx - b * kRecPre;
-      s_rec[b][j] = A.part[((int64_t)b * kDotMaxND + d) * REC + j];
+  // last block of this inner product: take the window back (clearing it), round once
+  Num<L> res;
+  set_zero(res, 0);
+  if (any && W <= WB) {
+    for (int w = t; w < W; w += kDotThreads) {
+      s_win[w] = __hip_atomic_load(&gw[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      gw[w] = 0;
     }
     __syncthreads();
-    int32_t gmin = INT32_MAX;
-    int64_t gtop = INT64_MIN;
-    for (int b = t; b < G; b += kDotThreads) {
-      if (s_rec[b][0] & 1) {
-        gmin = min(gmin, s_rec[b][1]);
-        gtop = max(gtop, (int64_t)s_rec[b][1] + 32 * (int64_t)s_rec[b][2]);
-      }
-    }
-    gmin = wave_min(gmin);
-    gtop = wave_max64(gtop);
-    if ((t & 63) == 0) {
-      s_red[0][wave] = gmin;
-      s_red[1][wave] = gtop;
-    }
-    __syncthreads();
+    if (t == 0) {
+      if (W <= WMAXF) {
+        RegWindow<WMAXF> R;
+        reg_normalize<WMAXF>(s_win, 1, W, R);
 #pragma unroll
-    for (int w = 0; w < kDotThreads / 64; ++w) {
-      gmin = min(gmin, (int32_t)s_red[0][w]);
-      gtop = s_red[1][w] > gtop ? s_red[1][w] : gtop;
-    }
-    __syncthreads();
-    Num<L> res;
-    set_zero(res, 0);
-    const int Wg = gtop != INT64_MIN ? (int)((gtop - (int64_t)gmin) >> 5) + 2 : 0;
-    if (Wg > WB) st |= kStWindow;
-    // a final window wider than 64 digits overwrites the staged records: read them from memory
-    const bool staged = Wg <= 64;
-    __syncthreads();
-    if (Wg > 0 && Wg <= WB) {
-      for (int w = t; w < Wg; w += kDotThreads) s_win[w] = 0;
-      __syncthreads();
-      // each lane adds its records, shifted to the common anchor, with integer LDS atomics
-      for (int b = t; b < G; b += kDotThreads) {
-        const int32_t* far = A.part + ((int64_t)b * kDotMaxND + d) * REC;
-        const int32_t fl = staged ? s_rec[b][0] : far[0];
-        if (!(fl & 1)) continue;
-        const uint32_t off = (uint32_t)((staged ? s_rec[b][1] : far[1]) - gmin);
-        const int nl = staged ? s_rec[b][2] : far[2];
-        const int q = (int)(off >> 5);
-        const uint32_t r = off & 31u;
-        auto limb = [&](int j) -> uint32_t {
-          if (j < 0 || j >= nl) return 0u;
-          return (staged && 3 + j < kRecPre) ? (uint32_t)s_rec[b][3 + j] : (uint32_t)far[3 + j];
-        };
-        // start each record at a different digit so that the lanes' atomics spread over banks
-        for (int jj = 0; jj <= nl; ++jj) {
-          int j = jj + b;
-          j %= (nl + 1);
-          const uint32_t cur = limb(j), prev = limb(j - 1);
-          const uint32_t v = r ? fshr(cur, prev, 32u - r) : cur;
-          if (v) {
-            const uint64_t add = (fl & 2) ? (uint64_t)(-(int64_t)v) : (uint64_t)v;
-            atomicAdd((unsigned long long*)&s_win[q + j], (unsigned long long)add);
-          }
-        }
-      }
-      __syncthreads();
-      if (t == 0) {
-        if (Wg <= WMAXF) {
-          // carries in registers, then the rounding reads the limbs back from LDS
-          RegWindow<WMAXF> R;
-          reg_normalize<WMAXF>(s_win, 1, Wg, R);
-#pragma unroll
-          for (int w = 0; w < WMAXF; ++w)
-            if (w < Wg) s_win[w] = (int64_t)R.limb[w];
-          res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)gmin - 64 * L, st);
-        } else {
-          res = window_finalize<L>(s_win, 1, Wg, (int64_t)gmin - 64 * L, st);
-        }
+        for (int w = 0; w < WMAXF; ++w)
+          if (w < W) s_win[w] = (int64_t)R.limb[w];
+        res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)emin - 64 * L, st);
+      } else {
+        res = window_finalize<L>(s_win, 1, W, (int64_t)emin - 64 * L, st);
       }
     }
-    if (t == 0) vstore<L>(A.out[d], 0, res);
+  }
+  if (t < kAnchorBins) {
+    abins[2 * t] = INT32_MAX;
+    abins[2 * t + 1] = INT32_MIN;
   }
   if (t == 0) {
-    A.ticket[d] = 0;
+    vstore<L>(A.out[d], 0, res);
+    A.w.ticket[slot] = 0;
     if (A.ctl && st) atomicOr(&A.ctl->flags, st);
-    // the last dot to finish runs the driver epilogue
+    // the last inner product of the launch to finish runs the driver epilogue
     __threadfence();
-    if (atomicAdd(&A.ticket[kDotMaxND], 1u) == (unsigned)A.nd - 1) {
+    if (atomicAdd(&A.w.ticket[A.w.nslots], 1u) == (unsigned)A.nd - 1) {
       __threadfence();
       uint32_t st2 = 0;
       epilogue<L>(A.epi, A.S, A.ctl, A.hist, st2);
-      A.ticket[kDotMaxND] = 0;
+      A.w.ticket[A.w.nslots] = 0;
       if (A.ctl && st2) atomicOr(&A.ctl->flags, st2);
       st |= st2;
     }
   }
   if (st) atomicOr(A.status, st);
+}
+
+// Anchors of stand-alone inner products (no producing kernel): one pass over the headers.
+struct AnchorArgs {
+  int64_t n;
+  int nd;
+  VecRef x[kDotMaxND];
+  VecRef y[kDotMaxND];
+  int slot[kDotMaxND];
+  int32_t* anchor;
+};
+
+static __global__ void __launch_bounds__(256) dot_anchor_kernel(AnchorArgs A) {
+  for (int d = 0; d < A.nd; ++d) {
+    int32_t emin = INT32_MAX, emax = INT32_MIN;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+      pair_exponent(A.x[d].hdr[i], A.y[d].hdr[i], emin, emax);
+    anchor_publish(A.anchor, A.slot[d], emin, emax);
+  }
+}
+
+// Reset anchors to empty.
+static __global__ void dot_work_init_kernel(int32_t* anchor, int nslots) {
+  for (int i = threadIdx.x; i < nslots * kAnchorBins; i += blockDim.x) {
+    anchor[2 * i] = INT32_MAX;
+    anchor[2 * i + 1] = INT32_MIN;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -524,6 +482,8 @@ struct VecArgs {
   Scalars S;
   Ctl* ctl;
   uint32_t* status;
+  int32_t* anchor;  // nullable: inner-product anchors filled for the products this kernel makes
+  int aslot[2];
 };
 
 // The scalar slot as a one-element vector reference.
@@ -557,6 +517,23 @@ template <int L>
 __global__ void __launch_bounds__(256) copy_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, vload<L>(A.v[1], i)); }
+}
+
+// v0 <- v1, and the anchors of (v1, v1) and (v0, v1) = (v1, v1) (the solver setup's rt = r)
+template <int L>
+__global__ void __launch_bounds__(256) copy_anchor_kernel(VecArgs A) {
+  if (solve_done(A.ctl)) return;
+  int32_t a0 = INT32_MAX, b0 = INT32_MIN;
+  MP_ELEMENTWISE_LOOP(A) {
+    const Num<L> r = vload<L>(A.v[1], i);
+    vstore<L>(A.v[0], i, r);
+    const int32_t h = make_hdr(r.e, r.s);
+    pair_exponent(h, h, a0, b0);
+  }
+  if (A.anchor) {
+    anchor_publish(A.anchor, A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, A.aslot[1], a0, b0);
+  }
 }
 
 // v0 <- +0
@@ -603,10 +580,20 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   if (solve_done(A.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = sload<L>(A.S, S_ALPHA);
+  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     vstore<L>(A.v[0], i, add_rn<L>(vload<L>(A.v[0], i), mul_rn<L>(alpha, vload<L>(A.v[3], i), st), st));
-    vstore<L>(A.v[1], i, sub_rn<L>(vload<L>(A.v[1], i), mul_rn<L>(alpha, vload<L>(A.v[4], i), st), st));
-    vstore<L>(A.v[2], i, sub_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[5], i), st), st));
+    const Num<L> r = sub_rn<L>(vload<L>(A.v[1], i), mul_rn<L>(alpha, vload<L>(A.v[4], i), st), st);
+    vstore<L>(A.v[1], i, r);
+    const Num<L> rt = sub_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[5], i), st), st);
+    vstore<L>(A.v[2], i, rt);
+    const int32_t hr = make_hdr(r.e, r.s), hrt = make_hdr(rt.e, rt.s);
+    pair_exponent(hr, hr, a0, b0);
+    pair_exponent(hrt, hr, a1, b1);
+  }
+  if (A.anchor) {
+    anchor_publish(A.anchor, A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -641,6 +628,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   uint32_t st = 0;
   const bool first = A.ctl->iters == 0;
   const Num<L> alpha = sload<L>(A.S, S_ALPHA);
+  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> r = vload<L>(A.v[3], i), q = vload<L>(A.v[4], i);
     const Num<L> aq = mul_rn<L>(alpha, q, st);
@@ -649,13 +637,23 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
       s = sub_rn<L>(vload<L>(A.v[0], i), r, st);
       vstore<L>(A.v[1], i, s);
     }
-    vstore<L>(A.v[0], i, sub_rn<L>(r, aq, st));
+    const Num<L> tn = sub_rn<L>(r, aq, st);
+    vstore<L>(A.v[0], i, tn);
+    Num<L> y;
     if (first) {
-      vstore<L>(A.v[2], i, sub_rn<L>(aq, r, st));
+      y = sub_rn<L>(aq, r, st);
     } else {
       const Num<L> wq = sub_rn<L>(vload<L>(A.v[5], i), q, st);
-      vstore<L>(A.v[2], i, sub_rn<L>(s, mul_rn<L>(alpha, wq, st), st));
+      y = sub_rn<L>(s, mul_rn<L>(alpha, wq, st), st);
     }
+    vstore<L>(A.v[2], i, y);
+    const int32_t hy = make_hdr(y.e, y.s), ht = make_hdr(tn.e, tn.s);
+    pair_exponent(hy, hy, a0, b0);
+    pair_exponent(hy, ht, a1, b1);
+  }
+  if (A.anchor) {
+    anchor_publish(A.anchor, A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -665,7 +663,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
 // r = t - eta y - zeta v.
 struct GpUpdArgs {
   VecArgs a;
-  VecRef y, v;
+  VecRef y, v, rt;
 };
 
 template <int L>
@@ -675,6 +673,7 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   uint32_t st = 0;
   const Num<L> alpha = sload<L>(A.S, S_ALPHA), beta = sload<L>(A.S, S_BETA);
   const Num<L> zeta = sload<L>(A.S, S_ZETA), eta = sload<L>(A.S, S_ETA);
+  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> q = vload<L>(A.v[4], i), s = vload<L>(A.v[5], i);
     const Num<L> u_old = vload<L>(A.v[0], i);
@@ -691,6 +690,13 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     const Num<L> rn = sub_rn<L>(sub_rn<L>(t, mul_rn<L>(eta, vload<L>(G.y, i), st), st),
                                 mul_rn<L>(zeta, vload<L>(G.v, i), st), st);
     vstore<L>(A.v[3], i, rn);
+    const int32_t hr = make_hdr(rn.e, rn.s), hrt = G.rt.hdr[i];
+    pair_exponent(hr, hr, a0, b0);
+    pair_exponent(hrt, hr, a1, b1);
+  }
+  if (A.anchor) {
+    anchor_publish(A.anchor, A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }

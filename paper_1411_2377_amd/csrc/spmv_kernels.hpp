@@ -42,7 +42,60 @@ struct SpmvArgs {
   int64_t y_ld;
   uint32_t* status;
   const int32_t* done;  // nullable: a set flag turns the launch into a no-op (solver graphs)
+  // inner-product anchors for products of y with up to three vectors (pair_hdr[k] == nullptr
+  // means y itself): the exponent range of y_i * w_i over the rows, published to anchor slots
+  int npair;
+  const int32_t* pair_hdr[3];
+  int pair_slot[3];
+  int32_t* anchor;
 };
+
+// Fold row r's output header yh into the anchors of its requested products.
+struct PairAcc {
+  int32_t lo[3], hi[3];
+};
+
+MPD void pair_init(PairAcc& P) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P.lo[k] = INT32_MAX;
+    P.hi[k] = INT32_MIN;
+  }
+}
+
+MPD void pair_fold(const SpmvArgs& A, PairAcc& P, int64_t row, int32_t yh) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < A.npair) {
+      const int32_t hp = A.pair_hdr[k] ? A.pair_hdr[k][row] : yh;
+      if (!hdr_is_zero(yh) && !hdr_is_zero(hp)) {
+        const int32_t e = (yh >> 1) + (hp >> 1);
+        P.lo[k] = min(P.lo[k], e);
+        P.hi[k] = max(P.hi[k], e);
+      }
+    }
+  }
+}
+
+MPD void pair_publish(const SpmvArgs& A, PairAcc& P) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < A.npair) {
+      int32_t lo = P.lo[k], hi = P.hi[k];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+      }
+      if ((threadIdx.x & 63) == 0 && hi >= lo) {
+        // bins of 64 per slot, spread by block (the inner-product kernel reduces them)
+        int32_t* a = A.anchor + 2 * ((int64_t)A.pair_slot[k] * 64 + (blockIdx.x & 63));
+        atomicMin(&a[0], lo);
+        atomicMax(&a[1], hi);
+      }
+    }
+  }
+}
 
 template <int L>
 __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
@@ -104,6 +157,12 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
     __syncthreads();
   }
   if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
+  if (A.npair) {
+    PairAcc P;
+    pair_init(P);
+    if (has_row) pair_fold(A, P, r0 + lane, make_hdr(acc.e, acc.s));
+    pair_publish(A, P);
+  }
   if (st) atomicOr(A.status, st);
 }
 
@@ -185,6 +244,8 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     __syncthreads();
   }
   Num<L> y;
+  PairAcc P;
+  pair_init(P);
   if (has_row && !wide) {
     if (any) {
       y = window_finalize<L>(mywin, 64, W, (int64_t)emin - 64 * L, st);
@@ -192,6 +253,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
       set_zero(y, 0);
     }
     store<L>(y, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
+    if (A.npair) pair_fold(A, P, r0 + lane, make_hdr(y.e, y.s));
   }
 
   // wide rows: the whole block shares one window
@@ -231,8 +293,10 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     if (lane == owner) {
       y = window_finalize<L>(s_win, 1, o_W, (int64_t)o_emin - 64 * L, st);
       store<L>(y, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
+      if (A.npair) pair_fold(A, P, r0 + lane, make_hdr(y.e, y.s));
     }
   }
+  if (A.npair) pair_publish(A, P);
   if (st) atomicOr(A.status, st);
 }
 

@@ -11,8 +11,20 @@
 
 namespace mpapi {
 
-size_t dot_workspace_bytes() {
-  return (size_t)mp::kDotMaxBlocks * mp::kDotMaxND * mp::dot_rec_ints<16>() * sizeof(int32_t);
+int64_t dot_window_stride() { return mp::dot_shared_digits<16>(); }
+
+int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s) {
+  hipError_t e = hipMalloc((void**)anchor, (size_t)2 * nslots * mp::kAnchorBins * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)win, (size_t)nslots * dot_window_stride() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)ticket, (size_t)(nslots + 1) * sizeof(uint32_t));
+  if (e != hipSuccess) return fail(MPS_ENOMEM, "inner-product workspace: %s", hipGetErrorString(e));
+  e = hipMemsetAsync(*win, 0, (size_t)nslots * dot_window_stride() * sizeof(int64_t), s);
+  if (e == hipSuccess) e = hipMemsetAsync(*ticket, 0, (size_t)(nslots + 1) * sizeof(uint32_t), s);
+  if (e != hipSuccess) return hip_fail(e, "inner-product workspace");
+  hipLaunchKernelGGL(mp::dot_work_init_kernel, dim3(1), dim3(256), 0, s, *anchor, nslots);
+  e = hipGetLastError();
+  if (e == hipSuccess && !s) e = hipDeviceSynchronize();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "inner-product workspace init");
 }
 
 mp::VecRef ref(const mp_vec& v) {
@@ -32,6 +44,16 @@ unsigned dot_grid(int64_t n, int nd, int L) {
   int64_t g = (n + 2 * mp::kDotThreads - 1) / (2 * mp::kDotThreads);
   g = std::min<int64_t>(g, (256 * per_cu) / std::max(1, nd));
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, mp::kDotMaxBlocks));
+}
+
+mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots) {
+  mp::DotWork w;
+  w.anchor = anchor;
+  w.win = win;
+  w.ticket = ticket;
+  w.win_stride = dot_window_stride();
+  w.nslots = nslots;
+  return w;
 }
 
 unsigned ew_grid(int64_t n) {
@@ -67,6 +89,7 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
     case EW_COPY: MPS_EW_CASES(copy_kernel, a); break;
     case EW_ZERO: MPS_EW_CASES(zero_kernel, a); break;
     case EW_SUB: MPS_EW_CASES(sub_kernel, a); break;
+    case EW_COPY_ANCHOR: MPS_EW_CASES(copy_anchor_kernel, a); break;
     case EW_BICG_DIR: MPS_EW_CASES(bicg_dir_kernel, a); break;
     case EW_BICG_UPDATE: MPS_EW_CASES(bicg_update_kernel, a); break;
     case EW_GP_DIR: MPS_EW_CASES(gp_dir_kernel, a); break;
@@ -156,18 +179,31 @@ int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream
   if (vec_overlap(x, out, L) || vec_overlap(y, out, L)) return fail(MPS_EINVAL, "out overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
+  hipStream_t s = (hipStream_t)stream;
+  // no kernel produced these operands: one pass over the headers fills the anchor
+  mp::AnchorArgs aa{};
+  aa.n = x->len;
+  aa.nd = 1;
+  aa.x[0] = ref(*x);
+  aa.y[0] = ref(*y);
+  aa.slot[0] = 0;
+  aa.anchor = ctx->dot_anchor;
+  if (x->len > 0) {
+    const unsigned g = ew_grid(x->len);
+    hipLaunchKernelGGL(mp::dot_anchor_kernel, dim3(std::min(g, 1024u)), dim3(256), 0, s, aa);
+  }
   mp::DotArgs a{};
   a.n = x->len;
   a.nd = 1;
   a.x[0] = ref(*x);
   a.y[0] = ref(*y);
   a.out[0] = ref(*out);
-  a.part = ctx->dot_part;
-  a.ticket = ctx->dot_ticket;
+  a.slot[0] = 0;
+  a.w = dot_work(ctx->dot_anchor, ctx->dot_win, ctx->dot_ticket, 1);
   a.ctl = nullptr;
   a.status = ctx->status;
   a.epi = mp::EPI_NONE;
-  return launch_dot(L, a, (hipStream_t)stream);
+  return launch_dot(L, a, s);
 }
 
 }  // extern "C"
