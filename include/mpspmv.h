@@ -172,6 +172,21 @@ int bicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
 int gpbicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
            const mp_solve_opts *opts, mp_solve_info *info, void *stream);
 
+/* Batched GPBiCG: nsys systems A[0..nsys-1] (square, same precision, sizes may differ), each
+ * with nrhs right-hand sides, solved as nsys * nrhs independent GPBiCG solves (the method of
+ * Fig. 5 right, K = I, applied to many systems) that share every kernel launch: one captured
+ * iteration graph advances all of them, and each solve stops on its own test.  Solve
+ * i = s * nrhs + k takes b[i] (length A[s].row_dim) and writes x[i]; info[i] receives its
+ * outcome.  Every x[i] is bit-identical to what gpbicg(&A[s], NULL, &b[i], &x[i], opts, ...)
+ * produces.  opts as for gpbicg, except that opts->transpose must be 0 and opts->res_hist NULL
+ * (MPS_ENOTSUP otherwise).  The library builds a block-diagonal copy of the matrices and
+ * concatenated work vectors (each system padded to a multiple of 512 rows) for the duration of
+ * the call and frees them before returning.  Inner products in a batch support exponent spans of
+ * about 7500 bits at p = 256 (MPS_ENOTSUP beyond).  Synchronous; returns as gpbicg, plus
+ * MPS_ENOTSUP for batches of more than 2^20 solves or 2^31 - 1 rows or stored entries. */
+int gpbicg_batched(int nsys, const mp_csr *A, int nrhs, const mp_vec *b, mp_vec *x,
+                   const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
 /* Synchronise `stream`, then read and clear the calling device's status word into *flags
  * (MP_ST_* bits).  Returns MPS_OK, or MPS_ERANGE / MPS_ENOTSUP when such a bit was set. */
 int mp_status(void *stream, uint32_t *flags);

@@ -97,6 +97,9 @@ SIGNATURES = {
              ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "gpbicg": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "gpbicg_batched": [ctypes.c_int, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.POINTER(MpVec),
+                       ctypes.POINTER(MpVec), ctypes.POINTER(MpSolveOpts),
+                       ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
 }
 OPTIONAL = {}
 # symbols bound by hand above (non-int return types)

@@ -132,6 +132,18 @@ class SolveInfo:
                                                                   self.final_rel_res)
 
 
+def _opts(mode, maxit, rtol, atol, chunk, transpose, use_x0):
+    o = _lib.MpSolveOpts()
+    o.mode = int(mode)
+    o.transpose = int(bool(transpose))
+    o.maxit = int(maxit)
+    o.rtol_m, o.rtol_e10 = int(rtol[0]), int(rtol[1])
+    o.atol_m, o.atol_e10 = int(atol[0]), int(atol[1])
+    o.chunk = int(chunk)
+    o.use_x0 = int(use_x0)
+    return o
+
+
 def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50),
            chunk=16, transpose=False, x0=None, hist=False, stream=None):
     if x is None:
@@ -140,14 +152,7 @@ def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), 
     if x0 is not None:
         x.copy_(x0)
         use_x0 = 1
-    o = _lib.MpSolveOpts()
-    o.mode = int(mode)
-    o.transpose = int(bool(transpose))
-    o.maxit = int(maxit)
-    o.rtol_m, o.rtol_e10 = int(rtol[0]), int(rtol[1])
-    o.atol_m, o.atol_e10 = int(atol[0]), int(atol[1])
-    o.chunk = int(chunk)
-    o.use_x0 = use_x0
+    o = _opts(mode, maxit, rtol, atol, chunk, transpose, use_x0)
     hist_arr = None
     if hist:
         hist_arr = MPArray.zeros(max(1, int(maxit)), A.p, device=b.device)
@@ -168,3 +173,33 @@ def bicg(A, b, **kw):
 def gpbicg(A, b, **kw):
     """GPBiCG for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
     return _solve(_lib.LIB.gpbicg, A, b, **kw)
+
+
+def gpbicg_batched(As, bs, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50), chunk=16,
+                   x0s=None, stream=None):
+    """Batched GPBiCG: As is a list of nsys square CSRMatrix, bs a list of nsys lists of nrhs
+    right-hand sides each.  Every solve is bit-identical to gpbicg(As[s], bs[s][k], ...).
+    Returns (xs, infos) shaped like bs."""
+    nsys = len(As)
+    nrhs = len(bs[0]) if nsys else 0
+    if nsys == 0 or nrhs == 0 or any(len(row) != nrhs for row in bs):
+        raise ValueError("bs must hold nsys lists of the same positive length")
+    xs = [[MPArray.empty(A.n_rows, A.p, device=row[0].device) for _ in row] for A, row in zip(As, bs)]
+    use_x0 = 0
+    if x0s is not None:
+        for xr, x0r in zip(xs, x0s):
+            for x, x0 in zip(xr, x0r):
+                x.copy_(x0)
+        use_x0 = 1
+    o = _opts(mode, maxit, rtol, atol, chunk, False, use_x0)
+    a_arr = (_lib.MpCsr * nsys)(*[A.desc() for A in As])
+    n = nsys * nrhs
+    b_arr = (_lib.MpVec * n)(*[b.desc() for row in bs for b in row])
+    x_arr = (_lib.MpVec * n)(*[x.desc() for row in xs for x in row])
+    infos = (_lib.MpSolveInfo * n)()
+    check(_lib.LIB.gpbicg_batched(nsys, a_arr, nrhs, b_arr, x_arr, ctypes.byref(o), infos,
+                                  _stream(stream)))
+    out = [[SolveInfo(infos[s * nrhs + k].status, infos[s * nrhs + k].iters,
+                      infos[s * nrhs + k].final_rel_res, None) for k in range(nrhs)]
+           for s in range(nsys)]
+    return xs, out

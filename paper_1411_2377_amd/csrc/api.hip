@@ -129,7 +129,8 @@ int check_csr(const mp_csr* A, int check_device_data) {
 // ---- SpMV launch ----------------------------------------------------------------------------
 template <int L>
 static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock);
+  const unsigned grid =
+      (unsigned)((a.n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock) * (unsigned)a.nrhs;
   if (mode == MP_SEQ)
     hipLaunchKernelGGL(mp::spmv_seq_kernel<L>, dim3(grid), dim3(64), 0, s, a);
   else
@@ -138,8 +139,13 @@ static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
 
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s, const SpmvPairs* pairs) {
+                const int32_t* done, hipStream_t s, const SpmvPairs* pairs,
+                const SpmvBatch* batch) {
   if (n_rows == 0) return MPS_OK;
+  const SpmvBatch one;
+  if (!batch) batch = &one;
+  if ((n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock * batch->nrhs > (int64_t)UINT32_MAX)
+    return fail(MPS_ENOTSUP, "too many row blocks for one launch");
   mp::SpmvArgs a;
   a.n_rows = n_rows;
   a.row_ptr = row_ptr;
@@ -155,6 +161,13 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.y_ld = y.ld;
   a.status = status;
   a.done = done;
+  a.nrhs = batch->nrhs;
+  a.x_rstride = batch->rstride;
+  a.y_rstride = batch->rstride;
+  a.pair_of_tile = batch->pair_of_tile;
+  a.done_base = batch->done_base;
+  a.done_stride = batch->done_stride;
+  a.slots_per_pair = batch->slots_per_pair;
   a.npair = 0;
   a.anchor = nullptr;
   for (int k = 0; k < 3; ++k) {

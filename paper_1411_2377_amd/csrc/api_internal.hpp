@@ -24,10 +24,24 @@ struct SpmvPairs {
   int32_t* anchor = nullptr;
 };
 
+// Several right-hand sides of a block-diagonal batch in one product launch: x and y hold nrhs
+// segments of rstride elements each; the solve owning a 512-element tile of y decides whether
+// its blocks run (done flags) and where its inner-product anchors go.
+struct SpmvBatch {
+  int nrhs = 1;
+  int64_t rstride = 0;
+  const int32_t* pair_of_tile = nullptr;
+  const int32_t* done_base = nullptr;
+  int64_t done_stride = 0;
+  int slots_per_pair = 0;
+};
+
 // int64 digits of one inner-product window slot (largest precision)
 int64_t dot_window_stride();
-// allocate and clear inner-product state with `nslots` slots
-int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s);
+// allocate and clear inner-product state: `nslots` slots of `win_stride` digits and
+// nslots + nfinal tickets
+int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s,
+                   int64_t win_stride = 0, int nfinal = 1);
 
 int fail(int code, const char* fmt, ...);
 void clear_error();
@@ -39,6 +53,7 @@ bool vec_overlap(const mp_vec* a, const mp_vec* b, int L);
 int check_csr(const mp_csr* A, int check_device_data);
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr);
+                const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr,
+                const SpmvBatch* batch = nullptr);
 
 }  // namespace mpapi

@@ -11,12 +11,14 @@
 #include <algorithm>
 #include <cmath>
 #include <initializer_list>
+#include <string>
 #include <utility>
 #include <vector>
 
 #include "../../include/mpspmv.h"
 #include "api_internal.hpp"
 #include "plan_internal.hpp"
+#include "batch_kernels.hpp"
 #include "solver_kernels.hpp"
 #include "vec_internal.hpp"
 
@@ -150,14 +152,24 @@ double mp_to_double(const uint32_t* limbs, int32_t hdr, int L, int64_t ld) {
   return (hdr & 1) ? -v : v;
 }
 
-// Device workspace of one solve.
+// Device workspace of one solve, or of a batch of independent solves ("pairs") that share
+// every launch: then the vectors are the pairs' segments side by side (each a whole number of
+// mp::kTile tiles), and scalars, control blocks and inner-product slots are per pair.
 struct Work {
   int L = 0;
   int64_t n = 0;
   int nvec = 0;
+  int npairs = 1;
+  int nrhs = 1;
+  int64_t rstride = 0;       // batch: elements per right-hand side (all systems, padded)
+  int64_t win_stride = 0;    // inner-product window digits per slot (0: the default)
+  int32_t* pair_of_tile = nullptr;
+  int32_t* tiles_of_pair = nullptr;
+  int32_t* ndone = nullptr;
+  int32_t* h_ndone = nullptr;  // pinned
   uint32_t* vlimb = nullptr;
   int32_t* vhdr = nullptr;
-  mp::Scalars S{nullptr, nullptr};
+  mp::Scalars S{nullptr, nullptr, 0};
   mp::Ctl* ctl = nullptr;
   int32_t* anchor = nullptr;  // inner-product slots (see DotWork)
   int64_t* win = nullptr;
@@ -183,10 +195,22 @@ struct Work {
     v.ld = n;
     return v;
   }
+  bool batched() const { return pair_of_tile != nullptr; }
+  mp::BatchMap batch_map() const {
+    mp::BatchMap b;
+    b.pair_of_tile = pair_of_tile;
+    b.tiles_of_pair = tiles_of_pair;
+    b.ndone = ndone;
+    return b;
+  }
   ~Work() {
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     if (ws) hipStreamSynchronize(ws);
+    hipFree(pair_of_tile);
+    hipFree(tiles_of_pair);
+    hipFree(ndone);
+    if (h_ndone) hipHostFree(h_ndone);
     hipFree(vlimb);
     hipFree(vhdr);
     hipFree(S.limb);
@@ -201,30 +225,38 @@ struct Work {
   }
 };
 
+// Allocate the workspace of W.npairs solves (W.npairs, and for a batch the tile maps, set by
+// the caller) with nvec work vectors of n elements.
 int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
   W.L = L;
   W.n = n;
   W.nvec = nvec;
+  const int64_t nsc = (int64_t)W.npairs * mp::kNumScalars;
+  W.S.ld = nsc;
   hipError_t e = hipMalloc((void**)&W.vlimb, std::max<size_t>(4, (size_t)nvec * L * n * 4));
   if (e == hipSuccess) e = hipMalloc((void**)&W.vhdr, std::max<size_t>(4, (size_t)nvec * n * 4));
-  if (e == hipSuccess) e = hipMalloc((void**)&W.S.limb, (size_t)L * mp::kNumScalars * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&W.S.hdr, (size_t)mp::kNumScalars * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&W.ctl, sizeof(mp::Ctl));
+  if (e == hipSuccess) e = hipMalloc((void**)&W.S.limb, (size_t)L * nsc * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.S.hdr, (size_t)nsc * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.ctl, sizeof(mp::Ctl) * W.npairs);
+  if (e == hipSuccess && W.batched()) e = hipMalloc((void**)&W.ndone, sizeof(int32_t));
   if (e != hipSuccess) return fail(MPS_ENOMEM, "solver workspace: %s", hipGetErrorString(e));
-  e = hipHostMalloc((void**)&W.h_ctl, sizeof(mp::Ctl), hipHostMallocDefault);
+  e = hipHostMalloc((void**)&W.h_ctl, sizeof(mp::Ctl) * W.npairs, hipHostMallocDefault);
+  if (e == hipSuccess && W.batched()) e = hipHostMalloc((void**)&W.h_ndone, sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&W.ws, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&W.ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(W.ev, user);
   if (e == hipSuccess) e = hipStreamWaitEvent(W.ws, W.ev, 0);
+  if (e == hipSuccess && W.ndone) e = hipMemsetAsync(W.ndone, 0, sizeof(int32_t), W.ws);
   if (e != hipSuccess) return hip_fail(e, "solver setup");
-  int r = dot_work_alloc(mp::kDotSlots, &W.anchor, &W.win, &W.ticket, W.ws);
+  int r = dot_work_alloc(W.npairs * mp::kDotSlots, &W.anchor, &W.win, &W.ticket, W.ws, W.win_stride,
+                         W.npairs);
   if (r) return r;
   // every scalar slot starts as +0
   mp::VecArgs a{};
-  a.n = mp::kNumScalars;
+  a.n = nsc;
   a.v[0].limb = W.S.limb;
   a.v[0].hdr = W.S.hdr;
-  a.v[0].ld = mp::kNumScalars;
+  a.v[0].ld = nsc;
   return launch_ew(L, EW_ZERO, a, W.ws);
 }
 
@@ -236,11 +268,24 @@ struct Op {
   mp_vec val;
 };
 
-int apply(const Op& op, int L, int mode, const mp::VecRef& x, const mp::VecRef& y,
-          uint32_t* status, const mp::Ctl* ctl, hipStream_t s, const SpmvPairs* pairs = nullptr) {
+// y = Aop x on the workspace stream; `gated`: a no-op once the solve is done (for a batch,
+// the blocks of finished solves return at once).
+int apply(const Work& W, const Op& op, int mode, const mp::VecRef& x, const mp::VecRef& y,
+          uint32_t* status, bool gated, const SpmvPairs* pairs = nullptr) {
   mp_vec xv{x.limb, x.hdr, 0, x.ld}, yv{y.limb, y.hdr, 0, y.ld};
-  return spmv_launch(L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                     ctl ? &ctl->done : nullptr, s, pairs);
+  if (W.batched()) {
+    SpmvBatch b;
+    b.nrhs = W.nrhs;
+    b.rstride = W.rstride;
+    b.pair_of_tile = W.pair_of_tile;
+    b.done_base = &W.ctl->done;
+    b.done_stride = (int64_t)(sizeof(mp::Ctl) / sizeof(int32_t));
+    b.slots_per_pair = mp::kDotSlots;
+    return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
+                       nullptr, W.ws, pairs, &b);
+  }
+  return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
+                     gated ? &W.ctl->done : nullptr, W.ws, pairs);
 }
 
 // Inner products of an SpMV output with up to three vectors (nullptr: the output itself).
@@ -259,10 +304,11 @@ mp::DotArgs dot_args(const Work& W, uint32_t* status, int epi) {
   mp::DotArgs a{};
   a.n = W.n;
   a.S = W.S;
-  a.w = dot_work(W.anchor, W.win, W.ticket, mp::kDotSlots);
+  a.w = dot_work(W.anchor, W.win, W.ticket, W.npairs * mp::kDotSlots, W.win_stride);
   a.ctl = W.ctl;
   a.status = status;
   a.epi = epi;
+  a.batch = W.batch_map();
   return a;
 }
 
@@ -272,6 +318,7 @@ mp::VecArgs ew_args(const Work& W, uint32_t* status) {
   a.S = W.S;
   a.ctl = W.ctl;
   a.status = status;
+  a.batch = W.batch_map();
   return a;
 }
 
@@ -297,19 +344,19 @@ int check_solve_args(const mp_csr* A, const mp_vec* b, const mp_vec* x, const mp
 int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
                 uint32_t* status) {
   const int L = W.L;
-  hipLaunchKernelGGL(mp::ctl_init_kernel, dim3(1), dim3(1), 0, W.ws, W.ctl, (int32_t)o->maxit,
-                     (int32_t)(o->res_hist ? o->res_hist->len : 0));
+  hipLaunchKernelGGL(mp::ctl_init_kernel, dim3((W.npairs + 255) / 256), dim3(256), 0, W.ws, W.ctl,
+                     W.npairs, (int32_t)o->maxit, (int32_t)(o->res_hist ? o->res_hist->len : 0));
   uint32_t m[16];
   int32_t h;
   if (!decimal_to_mp(o->rtol_m, o->rtol_e10, L, m, &h)) return fail(MPS_EINVAL, "rtol out of range");
-  int r = set_scalar(L, mp::slot_ref(W.S, mp::S_CREL), m, h, W.ws);
+  int r = set_scalar(L, mp::slot_ref(W.S, mp::S_CREL), m, h, W.ws, W.npairs, mp::kNumScalars);
   if (r) return r;
   if (!decimal_to_mp(o->atol_m, o->atol_e10, L, m, &h)) return fail(MPS_EINVAL, "atol out of range");
-  if ((r = set_scalar(L, mp::slot_ref(W.S, mp::S_CABS), m, h, W.ws))) return r;
+  if ((r = set_scalar(L, mp::slot_ref(W.S, mp::S_CABS), m, h, W.ws, W.npairs, mp::kNumScalars))) return r;
   mp::VecArgs a = ew_args(W, status);
   if (o->use_x0) {
     // r = b - Aop x0
-    if ((r = apply(Aop, L, o->mode, ref(*x), W.vec(2), status, nullptr, W.ws))) return r;
+    if ((r = apply(W, Aop, o->mode, ref(*x), W.vec(2), status, false))) return r;
     a.v[0] = W.vec(0);
     a.v[1] = ref(*b);
     a.v[2] = W.vec(2);
@@ -341,6 +388,19 @@ int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_sol
   return launch_dot(L, d, W.ws);
 }
 
+// Wait for the enqueued work and report whether every solve of W is done.
+int poll_done(Work& W, bool* done) {
+  hipError_t e;
+  if (W.batched())
+    e = hipMemcpyAsync(W.h_ndone, W.ndone, sizeof(int32_t), hipMemcpyDeviceToHost, W.ws);
+  else
+    e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl), hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
+  if (e != hipSuccess) return hip_fail(e, "poll");
+  *done = W.batched() ? (*W.h_ndone >= W.npairs) : (W.h_ctl->done != 0);
+  return MPS_OK;
+}
+
 // Run iterations until the control block says done (graph replays, or eager when chunk <= 0).
 template <class F>
 int run_iterations(Work& W, const mp_solve_opts* o, F&& enqueue_iteration) {
@@ -348,10 +408,9 @@ int run_iterations(Work& W, const mp_solve_opts* o, F&& enqueue_iteration) {
   int r;
   const int chunk = o->chunk;
   // the setup may already have finished the solve
-  e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl), hipMemcpyDeviceToHost, W.ws);
-  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
-  if (e != hipSuccess) return hip_fail(e, "poll");
-  if (W.h_ctl->done) return MPS_OK;
+  bool done = false;
+  if ((r = poll_done(W, &done))) return r;
+  if (done) return MPS_OK;
   if (chunk > 0) {
     e = hipStreamBeginCapture(W.ws, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -380,10 +439,8 @@ int run_iterations(Work& W, const mp_solve_opts* o, F&& enqueue_iteration) {
       }
       ++launched;
     }
-    e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl), hipMemcpyDeviceToHost, W.ws);
-    if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
-    if (e != hipSuccess) return hip_fail(e, "poll");
-    if (W.h_ctl->done) break;
+    if ((r = poll_done(W, &done))) return r;
+    if (done) break;
     if (launched > limit) return fail(MPS_EHIP, "solver did not reach its iteration limit");
   }
   return MPS_OK;
@@ -399,8 +456,8 @@ int finish_solve(Work& W, mp_solve_info* info, uint32_t* status) {
   if (e == hipSuccess) e = hipMemcpyAsync(sh.data(), W.S.hdr, sh.size() * 4, hipMemcpyDeviceToHost, W.ws);
   if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
   if (e != hipSuccess) return hip_fail(e, "result readback");
-  const double q0 = mp_to_double(sl.data() + mp::S_Q0, sh[mp::S_Q0], W.L, mp::kNumScalars);
-  const double q = info->iters > 0 ? mp_to_double(sl.data() + mp::S_Q, sh[mp::S_Q], W.L, mp::kNumScalars) : q0;
+  const double q0 = mp_to_double(sl.data() + mp::S_Q0, sh[mp::S_Q0], W.L, W.S.ld);
+  const double q = info->iters > 0 ? mp_to_double(sl.data() + mp::S_Q, sh[mp::S_Q], W.L, W.S.ld) : q0;
   info->final_rel_res = q0 > 0 ? std::sqrt(q / q0) : 0.0;
   const uint32_t fl = W.h_ctl->flags;
   if (fl & mp::kStRange) return fail(MPS_ERANGE, "a result exponent left the range during the solve");
@@ -466,8 +523,8 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
     if ((rr = launch_ew(L, EW_BICG_DIR, a, W.ws))) return rr;
     const SpmvPairs sig = pairs_of(W, {{PT.hdr, 0}});
-    if ((rr = apply(op, L, o->mode, P, Z, st, W.ctl, W.ws, &sig))) return rr;
-    if ((rr = apply(opT, L, o->mode, PT, ZT, st, W.ctl, W.ws))) return rr;
+    if ((rr = apply(W, op, o->mode, P, Z, st, true, &sig))) return rr;
+    if ((rr = apply(W, opT, o->mode, PT, ZT, st, true))) return rr;
     mp::DotArgs d = dot_args(W, st, mp::EPI_BICG_SIGMA);
     d.nd = 1;
     d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA); d.slot[0] = 0;
@@ -487,6 +544,69 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
   return finish_solve(W, info, st);
 }
 
+// GPBiCG work vectors: 0 r, 1 rt, 2 scratch, 3 p, 4 q, 5 t, 6 v, 7 s, 8 w, 9 y, 10 u, 11 z
+constexpr int kGpVectors = 12;
+
+// Clear the vectors the first GPBiCG iteration reads before writing (u, z, s, w, t, p, q, v,
+// y = +0; beta = +0 since the scalars were cleared).
+int gp_clear(const Work& W, uint32_t* st) {
+  mp::VecArgs a = ew_args(W, st);
+  for (int i = 3; i < kGpVectors; ++i) {
+    a.v[0] = W.vec(i);
+    int r = launch_ew(W.L, EW_ZERO, a, W.ws);
+    if (r) return r;
+  }
+  return MPS_OK;
+}
+
+// One GPBiCG iteration (Fig. 5 with K = I) on the workspace stream.
+int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, const mp::VecRef& hist,
+                 uint32_t* st) {
+  const int L = W.L;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), Q = W.vec(4), T = W.vec(5),
+                   V = W.vec(6), S = W.vec(7), Wv = W.vec(8), Y = W.vec(9), U = W.vec(10),
+                   Z = W.vec(11);
+  int rr;
+  mp::VecArgs a = ew_args(W, st);
+  a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
+  if ((rr = launch_ew(L, EW_GP_DIR, a, W.ws))) return rr;
+  const SpmvPairs den = pairs_of(W, {{RT.hdr, 0}});
+  if ((rr = apply(W, op, mode, P, Q, st, true, &den))) return rr;
+  mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
+  d.nd = 1;
+  d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN); d.slot[0] = 0;
+  if ((rr = launch_dot(L, d, W.ws))) return rr;
+  a = ew_args(W, st);
+  a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
+  a.anchor = W.anchor; a.aslot[0] = 3; a.aslot[1] = 5;   // (y, y), (y, t)
+  if ((rr = launch_ew(L, EW_GP_TSY, a, W.ws))) return rr;
+  const SpmvPairs mus = pairs_of(W, {{T.hdr, 4}, {Y.hdr, 6}, {nullptr, 7}});  // (v,t) (v,y) (v,v)
+  if ((rr = apply(W, op, mode, T, V, st, true, &mus))) return rr;
+  d = dot_args(W, st, mp::EPI_GP_ZETA);
+  d.nd = 5;
+  d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1); d.slot[0] = 3;
+  d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2); d.slot[1] = 4;
+  d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3); d.slot[2] = 5;
+  d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4); d.slot[3] = 6;
+  d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5); d.slot[4] = 7;
+  if ((rr = launch_dot(L, d, W.ws))) return rr;
+  mp::GpUpdArgs g{};
+  g.a = ew_args(W, st);
+  g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
+  g.a.v[6] = P; g.a.v[7] = T;
+  g.a.anchor = W.anchor; g.a.aslot[0] = 1; g.a.aslot[1] = 2;
+  g.y = Y;
+  g.v = V;
+  g.rt = RT;
+  if ((rr = launch_gp_update(L, g, W.ws))) return rr;
+  d = dot_args(W, st, mp::EPI_GP_CONV);
+  d.nd = 2;
+  d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
+  d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
+  d.hist = hist;
+  return launch_dot(L, d, W.ws);
+}
+
 int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
                 const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
   int r = check_solve_args(A, b, x, o, info);
@@ -504,69 +624,219 @@ int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x
   }
   const int L = limbs_of(A->prec);
   Work W;
-  // vectors: 0 r, 1 rt, 2 scratch, 3 p, 4 q, 5 t, 6 v, 7 s, 8 w, 9 y, 10 u, 11 z
-  if ((r = work_alloc(W, L, A->row_dim, 12, user))) return r;
+  if ((r = work_alloc(W, L, A->row_dim, kGpVectors, user))) return r;
   Op op, opT;
   make_ops(A, plan, o->transpose, &op, &opT);
   uint32_t* st = ctx->status;
   if ((r = solve_setup(W, op, b, x, o, st))) return r;
-  const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), Q = W.vec(4), T = W.vec(5),
-                   V = W.vec(6), S = W.vec(7), Wv = W.vec(8), Y = W.vec(9), U = W.vec(10),
-                   Z = W.vec(11);
+  if ((r = gp_clear(W, st))) return r;
   const mp::VecRef X = ref(*x);
-  {
-    // u = z = s = w = t = p = q = v = y = +0; beta = +0 (scalars were cleared to +0)
-    mp::VecArgs a = ew_args(W, st);
-    for (int i = 3; i < 12; ++i) {
-      a.v[0] = W.vec(i);
-      if ((r = launch_ew(L, EW_ZERO, a, W.ws))) return r;
-    }
-  }
   mp::VecRef hist{nullptr, nullptr, 0};
   if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
-  auto iteration = [&]() -> int {
-    int rr;
-    mp::VecArgs a = ew_args(W, st);
-    a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
-    if ((rr = launch_ew(L, EW_GP_DIR, a, W.ws))) return rr;
-    const SpmvPairs den = pairs_of(W, {{RT.hdr, 0}});
-    if ((rr = apply(op, L, o->mode, P, Q, st, W.ctl, W.ws, &den))) return rr;
-    mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
-    d.nd = 1;
-    d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN); d.slot[0] = 0;
-    if ((rr = launch_dot(L, d, W.ws))) return rr;
-    a = ew_args(W, st);
-    a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
-    a.anchor = W.anchor; a.aslot[0] = 3; a.aslot[1] = 5;   // (y, y), (y, t)
-    if ((rr = launch_ew(L, EW_GP_TSY, a, W.ws))) return rr;
-    const SpmvPairs mus = pairs_of(W, {{T.hdr, 4}, {Y.hdr, 6}, {nullptr, 7}});  // (v,t) (v,y) (v,v)
-    if ((rr = apply(op, L, o->mode, T, V, st, W.ctl, W.ws, &mus))) return rr;
-    d = dot_args(W, st, mp::EPI_GP_ZETA);
-    d.nd = 5;
-    d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1); d.slot[0] = 3;
-    d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2); d.slot[1] = 4;
-    d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3); d.slot[2] = 5;
-    d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4); d.slot[3] = 6;
-    d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5); d.slot[4] = 7;
-    if ((rr = launch_dot(L, d, W.ws))) return rr;
-    mp::GpUpdArgs g{};
-    g.a = ew_args(W, st);
-    g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
-    g.a.v[6] = P; g.a.v[7] = T;
-    g.a.anchor = W.anchor; g.a.aslot[0] = 1; g.a.aslot[1] = 2;
-    g.y = Y;
-    g.v = V;
-    g.rt = RT;
-    if ((rr = launch_gp_update(L, g, W.ws))) return rr;
-    d = dot_args(W, st, mp::EPI_GP_CONV);
-    d.nd = 2;
-    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
-    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
-    d.hist = hist;
-    return launch_dot(L, d, W.ws);
-  };
+  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, hist, st); };
   if ((r = run_iterations(W, o, iteration))) return r;
   return finish_solve(W, info, st);
+}
+
+// ---- batched GPBiCG --------------------------------------------------------------------
+// nsys systems, nrhs right-hand sides each: nsys * nrhs independent solves ("pairs", pair
+// s * nrhs + k) advanced together.  The systems are concatenated into one block-diagonal CSR
+// matrix whose diagonal blocks are padded to whole tiles with empty rows; vectors hold nrhs
+// segments of rstride = sum of padded sizes, and pair (s, k) owns the tiles of system s in
+// segment k.  Padding elements stay +0 (every update maps zeros to zeros and inner products skip
+// zero products), so each pair computes exactly what a solve of its own system computes.
+
+namespace {
+
+int64_t padded_rows(int64_t n) {
+  return std::max<int64_t>(mp::kTile, (n + mp::kTile - 1) / mp::kTile * mp::kTile);
+}
+
+int check_batched_args(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, const mp_vec* x,
+                       const mp_solve_opts* o, const mp_solve_info* info) {
+  if (nsys <= 0 || nrhs <= 0) return fail(MPS_EINVAL, "nsys and nrhs must be positive");
+  if (!A || !b || !x || !o || !info) return fail(MPS_EINVAL, "null argument");
+  if (o->transpose) return fail(MPS_ENOTSUP, "batched solves take A, not its transpose");
+  if (o->res_hist && o->res_hist->len > 0) return fail(MPS_ENOTSUP, "batched solves keep no residual history");
+  if (o->mode != MP_SEQ && o->mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if (o->maxit < 0 || o->maxit > INT32_MAX) return fail(MPS_EINVAL, "maxit out of range");
+  int r;
+  for (int s = 0; s < nsys; ++s) {
+    if ((r = check_csr(&A[s], 0))) {
+      const std::string m = mp_last_error();
+      return fail(r, "system %d: %s", s, m.c_str());
+    }
+    if (A[s].row_dim != A[s].col_dim) return fail(MPS_EINVAL, "system %d is not square", s);
+    if (A[s].prec != A[0].prec) return fail(MPS_EINVAL, "system %d: precisions differ", s);
+    const int L = limbs_of(A[s].prec);
+    for (int k = 0; k < nrhs; ++k) {
+      const int64_t i = (int64_t)s * nrhs + k;
+      if ((r = check_vec(&b[i], A[s].row_dim, "b")) || (r = check_vec(&x[i], A[s].row_dim, "x"))) {
+        const std::string m = mp_last_error();
+        return fail(r, "pair %lld: %s", (long long)i, m.c_str());
+      }
+      if (vec_overlap(&b[i], &x[i], L)) return fail(MPS_EINVAL, "pair %lld: x overlaps b", (long long)i);
+    }
+  }
+  return MPS_OK;
+}
+
+// Concatenated block-diagonal matrix (device arrays owned here).
+struct BlockDiag {
+  int32_t* row_ptr = nullptr;
+  int32_t* col_idx = nullptr;
+  uint32_t* limb = nullptr;
+  int32_t* hdr = nullptr;
+  int64_t rows = 0, nnz = 0;
+  ~BlockDiag() {
+    hipFree(row_ptr);
+    hipFree(col_idx);
+    hipFree(limb);
+    hipFree(hdr);
+  }
+};
+
+int build_block_diag(int nsys, const mp_csr* A, int L, const std::vector<int64_t>& row_off,
+                     BlockDiag& M, hipStream_t s) {
+  std::vector<int64_t> nnz_off(nsys + 1, 0);
+  for (int k = 0; k < nsys; ++k) nnz_off[k + 1] = nnz_off[k] + A[k].nnz;
+  M.rows = row_off[nsys];
+  M.nnz = nnz_off[nsys];
+  if (M.nnz > INT32_MAX || M.rows > INT32_MAX)
+    return fail(MPS_ENOTSUP, "the batch has more than 2^31 - 1 rows or stored entries");
+  hipError_t e = hipMalloc((void**)&M.row_ptr, (size_t)(M.rows + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&M.col_idx, std::max<size_t>(4, (size_t)M.nnz * 4));
+  if (e == hipSuccess) e = hipMalloc((void**)&M.limb, std::max<size_t>(4, (size_t)M.nnz * L * 4));
+  if (e == hipSuccess) e = hipMalloc((void**)&M.hdr, std::max<size_t>(4, (size_t)M.nnz * 4));
+  if (e != hipSuccess) return fail(MPS_ENOMEM, "batched matrix: %s", hipGetErrorString(e));
+  for (int k = 0; k < nsys; ++k) {
+    const int64_t n = A[k].row_dim, np = row_off[k + 1] - row_off[k], nz = A[k].nnz;
+    const bool last = k == nsys - 1;
+    mp::BlockRowArgs ra{A[k].row_ptr, n, np + (last ? 1 : 0), (int32_t)nnz_off[k],
+                        (int32_t)nz, M.row_ptr + row_off[k]};
+    hipLaunchKernelGGL(mp::block_row_ptr_kernel, dim3((unsigned)std::min<int64_t>(4096, (np + 256) / 256)),
+                       dim3(256), 0, s, ra);
+    if (nz > 0) {
+      mp::BlockColArgs ca{A[k].col_idx, nz, (int32_t)row_off[k], M.col_idx + nnz_off[k]};
+      hipLaunchKernelGGL(mp::block_col_kernel, dim3((unsigned)std::min<int64_t>(4096, (nz + 255) / 256)),
+                         dim3(256), 0, s, ca);
+      e = hipMemcpy2DAsync(M.limb + nnz_off[k], (size_t)M.nnz * 4, A[k].val.limb,
+                           (size_t)A[k].val.ld * 4, (size_t)nz * 4, (size_t)L, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(M.hdr + nnz_off[k], A[k].val.hdr, (size_t)nz * 4, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "batched matrix copy");
+    }
+  }
+  e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "batched matrix");
+}
+
+// gather (to_batch) the pairs' vectors into v, or scatter v back to them
+int batch_copy(int L, bool to_batch, const mp::PairSeg* seg, const int32_t* pair_of_tile,
+               const mp::VecRef& v, int64_t n, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>(16384, (n + 255) / 256);
+  const int gather = to_batch ? 1 : 0;
+  switch (L) {
+    case 4: hipLaunchKernelGGL(mp::batch_copy_kernel<4>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
+    case 8: hipLaunchKernelGGL(mp::batch_copy_kernel<8>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
+    case 16: hipLaunchKernelGGL(mp::batch_copy_kernel<16>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "batch copy");
+}
+
+}  // namespace
+
+int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec* x,
+                        const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_batched_args(nsys, A, nrhs, b, x, o, info);
+  if (r) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  const int L = limbs_of(A[0].prec);
+  const int64_t npairs64 = (int64_t)nsys * nrhs;
+  if (npairs64 > (1 << 20)) return fail(MPS_ENOTSUP, "more than 2^20 solves in one batch");
+  // layout: padded row offsets, then the tile -> pair map of the nrhs segments
+  std::vector<int64_t> row_off(nsys + 1, 0);
+  for (int k = 0; k < nsys; ++k) row_off[k + 1] = row_off[k] + padded_rows(A[k].row_dim);
+  const int64_t rstride = row_off[nsys];
+  const int64_t n = rstride * nrhs;
+  const int64_t ntiles = n / mp::kTile;
+  if (ntiles > INT32_MAX / 2) return fail(MPS_ENOTSUP, "batch too large");
+  std::vector<int32_t> pot((size_t)ntiles), top((size_t)npairs64);
+  std::vector<mp::PairSeg> seg_b((size_t)npairs64), seg_x((size_t)npairs64);
+  for (int k = 0; k < nrhs; ++k)
+    for (int sy = 0; sy < nsys; ++sy) {
+      const int32_t pair = sy * nrhs + k;
+      const int64_t off = (int64_t)k * rstride + row_off[sy];
+      const int64_t nt = (row_off[sy + 1] - row_off[sy]) / mp::kTile;
+      for (int64_t t = 0; t < nt; ++t) pot[(size_t)(off / mp::kTile + t)] = pair;
+      top[pair] = (int32_t)nt;
+      seg_b[pair] = mp::PairSeg{b[pair].limb, b[pair].hdr, b[pair].ld, A[sy].row_dim, off};
+      seg_x[pair] = mp::PairSeg{x[pair].limb, x[pair].hdr, x[pair].ld, A[sy].row_dim, off};
+    }
+  Work W;
+  W.npairs = (int)npairs64;
+  W.nrhs = nrhs;
+  W.rstride = rstride;
+  W.win_stride = mp::kBatchWindowDigits;
+  mp::PairSeg* d_seg = nullptr;
+  hipError_t e = hipMalloc((void**)&W.pair_of_tile, pot.size() * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.tiles_of_pair, top.size() * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_seg, 2 * seg_b.size() * sizeof(mp::PairSeg));
+  struct SegFree {
+    mp::PairSeg* p;
+    ~SegFree() { hipFree(p); }
+  } seg_free{d_seg};
+  if (e != hipSuccess) return fail(MPS_ENOMEM, "batch maps: %s", hipGetErrorString(e));
+  // vectors 0..11 as in GPBiCG, 12 = x, 13 = b (concatenated)
+  if ((r = work_alloc(W, L, n, kGpVectors + 2, user))) return r;
+  e = hipMemcpyAsync(W.pair_of_tile, pot.data(), pot.size() * 4, hipMemcpyHostToDevice, W.ws);
+  if (e == hipSuccess) e = hipMemcpyAsync(W.tiles_of_pair, top.data(), top.size() * 4, hipMemcpyHostToDevice, W.ws);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_seg, seg_b.data(), seg_b.size() * sizeof(mp::PairSeg), hipMemcpyHostToDevice, W.ws);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_seg + seg_b.size(), seg_x.data(), seg_x.size() * sizeof(mp::PairSeg),
+                       hipMemcpyHostToDevice, W.ws);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);  // the host tables go out of scope below
+  if (e != hipSuccess) return hip_fail(e, "batch maps upload");
+  BlockDiag M;
+  if ((r = build_block_diag(nsys, A, L, row_off, M, W.ws))) return r;
+  Op op{M.rows, M.row_ptr, M.col_idx, mp_vec{M.limb, M.hdr, M.nnz, M.nnz}};
+  uint32_t* st = ctx->status;
+  const mp::VecRef X = W.vec(kGpVectors), B = W.vec(kGpVectors + 1);
+  if ((r = batch_copy(L, true, d_seg, W.pair_of_tile, B, n, W.ws))) return r;
+  if (o->use_x0 && (r = batch_copy(L, true, d_seg + seg_b.size(), W.pair_of_tile, X, n, W.ws))) return r;
+  mp_vec bd = W.desc(kGpVectors + 1), xd = W.desc(kGpVectors);
+  if ((r = solve_setup(W, op, &bd, &xd, o, st))) return r;
+  if ((r = gp_clear(W, st))) return r;
+  const mp::VecRef nohist{nullptr, nullptr, 0};
+  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, nohist, st); };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  if ((r = batch_copy(L, false, d_seg + seg_b.size(), W.pair_of_tile, X, n, W.ws))) return r;
+  // per-pair outcomes
+  std::vector<uint32_t> sl((size_t)L * W.S.ld);
+  std::vector<int32_t> sh((size_t)W.S.ld);
+  e = hipMemcpyAsync(W.h_ctl, W.ctl, sizeof(mp::Ctl) * W.npairs, hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipMemcpyAsync(sl.data(), W.S.limb, sl.size() * 4, hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipMemcpyAsync(sh.data(), W.S.hdr, sh.size() * 4, hipMemcpyDeviceToHost, W.ws);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.ws);
+  if (e != hipSuccess) return hip_fail(e, "batched result readback");
+  uint32_t fl = 0;
+  for (int i = 0; i < W.npairs; ++i) {
+    const mp::Ctl& c = W.h_ctl[i];
+    info[i].status = c.status;
+    info[i].iters = c.iters;
+    const int64_t base = (int64_t)i * mp::kNumScalars;
+    const double q0 = mp_to_double(sl.data() + base + mp::S_Q0, sh[base + mp::S_Q0], L, W.S.ld);
+    const double q = c.iters > 0 ? mp_to_double(sl.data() + base + mp::S_Q, sh[base + mp::S_Q], L, W.S.ld) : q0;
+    info[i].final_rel_res = q0 > 0 ? std::sqrt(q / q0) : 0.0;
+    fl |= c.flags;
+  }
+  if (fl & mp::kStRange) return fail(MPS_ERANGE, "a result exponent left the range during a solve");
+  if (fl & mp::kStWindow) return fail(MPS_ENOTSUP, "an exact accumulation was wider than supported");
+  return MPS_OK;
 }
 
 }  // namespace mpapi
@@ -585,6 +855,12 @@ int gpbicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
            const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
   return gpbicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec* x,
+                   const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return gpbicg_batched_impl(nsys, A, nrhs, b, x, opts, info, (hipStream_t)stream);
 }
 
 int mp_const_decimal(int64_t m, int64_t e10, int prec, mp_vec* out, void* stream) {

@@ -34,9 +34,29 @@ struct Ctl {
   int32_t pad[2];
 };
 
+// Scalar slots of one solve: slot k of limb plane q at limb[q * ld + k].  A batch of solves
+// keeps kNumScalars slots per solve side by side (ld = kNumScalars * number of solves).
 struct Scalars {
-  uint32_t* limb;  // [L][kNumScalars]
-  int32_t* hdr;    // [kNumScalars]
+  uint32_t* limb;
+  int32_t* hdr;
+  int64_t ld;
+  __host__ __device__ Scalars at(int64_t pair) const {
+    Scalars r;
+    r.limb = limb + pair * kNumScalars;
+    r.hdr = hdr + pair * kNumScalars;
+    r.ld = ld;
+    return r;
+  }
+};
+
+// Several independent solves in one set of launches: every solve ("pair": a system and one
+// right-hand side) owns a segment of the concatenated vectors that starts on a kTile boundary,
+// so a tile (and every wavefront or block inside it) belongs to one solve.
+constexpr int kTile = 512;
+struct BatchMap {
+  const int32_t* pair_of_tile;   // nullptr: a single solve
+  const int32_t* tiles_of_pair;  // tiles in each solve's segment
+  int32_t* ndone;                // incremented once per solve that finishes
 };
 
 struct VecRef {
@@ -48,13 +68,13 @@ struct VecRef {
 template <int L>
 MPD Num<L> sload(const Scalars& S, int slot) {
   Num<L> r;
-  load<L>(r, S.limb, S.hdr, kNumScalars, slot);
+  load<L>(r, S.limb, S.hdr, S.ld, slot);
   return r;
 }
 
 template <int L>
 MPD void sstore(const Scalars& S, int slot, const Num<L>& v) {
-  store<L>(v, S.limb, S.hdr, kNumScalars, slot);
+  store<L>(v, S.limb, S.hdr, S.ld, slot);
 }
 
 template <int L>
@@ -281,6 +301,7 @@ struct DotArgs {
   uint32_t* status;
   int epi;
   VecRef hist;
+  BatchMap batch;  // batch.pair_of_tile == nullptr: one solve
 };
 
 template <int L>
@@ -291,11 +312,17 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   __shared__ int64_t s_win[WB];
   __shared__ uint32_t s_last;
   __shared__ int32_t s_anc[2][kDotThreads / 64];
-  if (solve_done(A.ctl)) return;
+  // batch: block = one tile of one solve; otherwise a grid-stride pass over the whole vector
+  const bool batched = A.batch.pair_of_tile != nullptr;
+  const int pair = batched ? A.batch.pair_of_tile[blockIdx.x] : 0;
+  Ctl* const ctl = A.ctl ? A.ctl + pair : nullptr;
+  if (solve_done(ctl)) return;
+  const Scalars S = A.S.at(pair);
   const int t = threadIdx.x;
   uint32_t st = 0;
   const int d = blockIdx.y;  // the inner products of one launch run side by side, one row each
-  const int slot = A.slot[d];
+  const int slot = pair * kDotSlots + A.slot[d];
+  const unsigned nblocks = batched ? (unsigned)A.batch.tiles_of_pair[pair] : gridDim.x;
   int32_t* abins = A.w.anchor + 2 * (int64_t)slot * kAnchorBins;
   int32_t emin = INT32_MAX, emax = INT32_MIN;
   if (t < kAnchorBins) {
@@ -317,10 +344,12 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   int64_t* gw = A.w.win + (int64_t)slot * A.w.win_stride;
   const bool any = emax >= emin;
   const int W = any ? window_digits<L>(emin, emax) : 0;
-  if (any && W > WB) st |= kStWindow;
-  if (any && W <= WB) {
+  const bool fits = W <= WB && W <= A.w.win_stride;
+  if (any && !fits) st |= kStWindow;
+  if (any && fits) {
     const VecRef X = A.x[d], Y = A.y[d];
-    const int64_t stride = (int64_t)gridDim.x * kDotThreads;
+    const int64_t stride = batched ? (int64_t)(kTile / 2) : (int64_t)gridDim.x * kDotThreads;
+    const int64_t n_end = batched ? (int64_t)(blockIdx.x + 1) * kTile : A.n;
     const bool fast = W <= WF;
     if (fast) {
       for (int w = 0; w < WF; ++w) s_win[w * kDotStride + t] = 0;
@@ -329,9 +358,10 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
       __syncthreads();
     }
     // products, two elements at a time: both headers, then both limb sets in flight together
-    for (int64_t i0 = (int64_t)blockIdx.x * kDotThreads + t; i0 < A.n; i0 += 2 * stride) {
+    const int64_t i_first = batched ? (int64_t)blockIdx.x * kTile + t : (int64_t)blockIdx.x * kDotThreads + t;
+    for (int64_t i0 = i_first; i0 < n_end; i0 += 2 * stride) {
       const int64_t i1 = i0 + stride;
-      const bool has1 = i1 < A.n;
+      const bool has1 = i1 < n_end;
       const int32_t hx0 = X.hdr[i0], hy0 = Y.hdr[i0];
       const int32_t hx1 = has1 ? X.hdr[i1] : (int32_t)0x80000000;
       const int32_t hy1 = has1 ? Y.hdr[i1] : (int32_t)0x80000000;
@@ -394,7 +424,7 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
 
   __threadfence();
   __syncthreads();
-  if (t == 0) s_last = (atomicAdd(&A.w.ticket[slot], 1u) == gridDim.x - 1) ? 1u : 0u;
+  if (t == 0) s_last = (atomicAdd(&A.w.ticket[slot], 1u) == nblocks - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) {
     if (st) atomicOr(A.status, st);
@@ -404,7 +434,7 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   // last block of this inner product: take the window back (clearing it), round once
   Num<L> res;
   set_zero(res, 0);
-  if (any && W <= WB) {
+  if (any && fits) {
     for (int w = t; w < W; w += kDotThreads) {
       s_win[w] = __hip_atomic_load(&gw[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       gw[w] = 0;
@@ -428,17 +458,24 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     abins[2 * t + 1] = INT32_MIN;
   }
   if (t == 0) {
-    vstore<L>(A.out[d], 0, res);
+    VecRef o = A.out[d];  // batch: a scalar slot of solve 0, moved to this solve's slots
+    if (batched) {
+      o.limb += (int64_t)pair * kNumScalars;
+      o.hdr += (int64_t)pair * kNumScalars;
+    }
+    vstore<L>(o, 0, res);
     A.w.ticket[slot] = 0;
-    if (A.ctl && st) atomicOr(&A.ctl->flags, st);
-    // the last inner product of the launch to finish runs the driver epilogue
+    if (ctl && st) atomicOr(&ctl->flags, st);
+    // the last inner product of the launch (of this solve) to finish runs the driver epilogue
     __threadfence();
-    if (atomicAdd(&A.w.ticket[A.w.nslots], 1u) == (unsigned)A.nd - 1) {
+    if (atomicAdd(&A.w.ticket[A.w.nslots + pair], 1u) == (unsigned)A.nd - 1) {
       __threadfence();
       uint32_t st2 = 0;
-      epilogue<L>(A.epi, A.S, A.ctl, A.hist, st2);
-      A.w.ticket[A.w.nslots] = 0;
-      if (A.ctl && st2) atomicOr(&A.ctl->flags, st2);
+      const int was_done = ctl ? ctl->done : 0;
+      epilogue<L>(A.epi, S, ctl, A.hist, st2);
+      A.w.ticket[A.w.nslots + pair] = 0;
+      if (ctl && st2) atomicOr(&ctl->flags, st2);
+      if (A.batch.ndone && ctl && !was_done && ctl->done) atomicAdd(A.batch.ndone, 1);
       st |= st2;
     }
   }
@@ -467,7 +504,8 @@ static __global__ void __launch_bounds__(256) dot_anchor_kernel(AnchorArgs A) {
 
 // Reset anchors to empty.
 static __global__ void dot_work_init_kernel(int32_t* anchor, int nslots) {
-  for (int i = threadIdx.x; i < nslots * kAnchorBins; i += blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nslots * kAnchorBins;
+       i += (int64_t)gridDim.x * blockDim.x) {
     anchor[2 * i] = INT32_MAX;
     anchor[2 * i + 1] = INT32_MIN;
   }
@@ -484,14 +522,32 @@ struct VecArgs {
   uint32_t* status;
   int32_t* anchor;  // nullable: inner-product anchors filled for the products this kernel makes
   int aslot[2];
+  BatchMap batch;   // batch: n is whole tiles and the grid has n / blockDim.x blocks
 };
+
+// The solve a block works for: its control block, scalars and first inner-product slot.
+struct EwCtx {
+  Ctl* ctl;
+  Scalars S;
+  int abase;
+};
+
+MPD EwCtx ew_ctx(const VecArgs& A) {
+  const int pair =
+      A.batch.pair_of_tile ? A.batch.pair_of_tile[((int64_t)blockIdx.x * blockDim.x) / kTile] : 0;
+  EwCtx c;
+  c.ctl = A.ctl ? A.ctl + pair : nullptr;
+  c.S = A.S.at(pair);
+  c.abase = pair * kDotSlots;
+  return c;
+}
 
 // The scalar slot as a one-element vector reference.
 __host__ __device__ inline VecRef slot_ref(const Scalars& S, int slot) {
   VecRef r;
   r.limb = S.limb + slot;
   r.hdr = S.hdr + slot;
-  r.ld = kNumScalars;
+  r.ld = S.ld;
   return r;
 }
 
@@ -502,7 +558,8 @@ __host__ __device__ inline VecRef slot_ref(const Scalars& S, int slot) {
 // v0 <- v0 + v2[0] * v1   (mp_axpy: y <- y + alpha x)
 template <int L>
 __global__ void __launch_bounds__(256) axpy_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = vload<L>(A.v[2], 0);
   MP_ELEMENTWISE_LOOP(A) {
@@ -515,14 +572,16 @@ __global__ void __launch_bounds__(256) axpy_kernel(VecArgs A) {
 // v0 <- v1 (copy)
 template <int L>
 __global__ void __launch_bounds__(256) copy_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, vload<L>(A.v[1], i)); }
 }
 
 // v0 <- v1, and the anchors of (v1, v1) and (v0, v1) = (v1, v1) (the solver setup's rt = r)
 template <int L>
 __global__ void __launch_bounds__(256) copy_anchor_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   int32_t a0 = INT32_MAX, b0 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> r = vload<L>(A.v[1], i);
@@ -531,15 +590,16 @@ __global__ void __launch_bounds__(256) copy_anchor_kernel(VecArgs A) {
     pair_exponent(h, h, a0, b0);
   }
   if (A.anchor) {
-    anchor_publish(A.anchor, A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, A.aslot[1], a0, b0);
+    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, c.abase + A.aslot[1], a0, b0);
   }
 }
 
 // v0 <- +0
 template <int L>
 __global__ void __launch_bounds__(256) zero_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   Num<L> z;
   set_zero(z, 0);
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, z); }
@@ -548,7 +608,8 @@ __global__ void __launch_bounds__(256) zero_kernel(VecArgs A) {
 // v0 <- v1 - v2
 template <int L>
 __global__ void __launch_bounds__(256) sub_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, sub_rn<L>(vload<L>(A.v[1], i), vload<L>(A.v[2], i), st)); }
   if (st) atomicOr(A.status, st);
@@ -557,10 +618,11 @@ __global__ void __launch_bounds__(256) sub_kernel(VecArgs A) {
 // BiCG directions: v = {p, pt, r, rt}. First iteration p = r, pt = rt; then p = r + beta p.
 template <int L>
 __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const bool first = A.ctl->iters == 0;
-  const Num<L> beta = sload<L>(A.S, S_BETA);
+  const bool first = c.ctl->iters == 0;
+  const Num<L> beta = sload<L>(c.S, S_BETA);
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> r = vload<L>(A.v[2], i), rt = vload<L>(A.v[3], i);
     if (first) {
@@ -577,9 +639,10 @@ __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
 // BiCG update: v = {x, r, rt, p, z, zt}: x += alpha p; r -= alpha z; rt -= alpha zt.
 template <int L>
 __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const Num<L> alpha = sload<L>(A.S, S_ALPHA);
+  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
   int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     vstore<L>(A.v[0], i, add_rn<L>(vload<L>(A.v[0], i), mul_rn<L>(alpha, vload<L>(A.v[3], i), st), st));
@@ -592,8 +655,8 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
     pair_exponent(hrt, hr, a1, b1);
   }
   if (A.anchor) {
-    anchor_publish(A.anchor, A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, A.aslot[1], a1, b1);
+    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -602,10 +665,11 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
 // w = v + beta q, p = r + beta (p - u).
 template <int L>
 __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const bool first = A.ctl->iters == 0;
-  const Num<L> beta = sload<L>(A.S, S_BETA);
+  const bool first = c.ctl->iters == 0;
+  const Num<L> beta = sload<L>(c.S, S_BETA);
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> r = vload<L>(A.v[2], i);
     if (first) {
@@ -624,10 +688,11 @@ __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
 // t = r - alpha q, y = alpha q - r (first) or s - alpha (w - q).
 template <int L>
 __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const bool first = A.ctl->iters == 0;
-  const Num<L> alpha = sload<L>(A.S, S_ALPHA);
+  const bool first = c.ctl->iters == 0;
+  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
   int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> r = vload<L>(A.v[3], i), q = vload<L>(A.v[4], i);
@@ -652,8 +717,8 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
     pair_exponent(hy, ht, a1, b1);
   }
   if (A.anchor) {
-    anchor_publish(A.anchor, A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, A.aslot[1], a1, b1);
+    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -669,10 +734,11 @@ struct GpUpdArgs {
 template <int L>
 __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   const VecArgs& A = G.a;
-  if (solve_done(A.ctl)) return;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const Num<L> alpha = sload<L>(A.S, S_ALPHA), beta = sload<L>(A.S, S_BETA);
-  const Num<L> zeta = sload<L>(A.S, S_ZETA), eta = sload<L>(A.S, S_ETA);
+  const Num<L> alpha = sload<L>(c.S, S_ALPHA), beta = sload<L>(c.S, S_BETA);
+  const Num<L> zeta = sload<L>(c.S, S_ZETA), eta = sload<L>(c.S, S_ETA);
   int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
   MP_ELEMENTWISE_LOOP(A) {
     const Num<L> q = vload<L>(A.v[4], i), s = vload<L>(A.v[5], i);
@@ -695,8 +761,8 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     pair_exponent(hrt, hr, a1, b1);
   }
   if (A.anchor) {
-    anchor_publish(A.anchor, A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, A.aslot[1], a1, b1);
+    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
+    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -707,26 +773,30 @@ struct ConstArgs {
   VecRef out;
   uint32_t m[L];
   int32_t hdr;
+  int64_t count;  // places written: element j * step of out for j < count
+  int64_t step;
 };
 
 template <int L>
 __global__ void set_scalar_kernel(ConstArgs<L> A) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    A.out.hdr[0] = A.hdr;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.count;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = j * A.step;
+    A.out.hdr[i] = A.hdr;
 #pragma unroll
-    for (int k = 0; k < L; ++k) A.out.limb[(int64_t)k * A.out.ld] = A.m[k];
+    for (int k = 0; k < L; ++k) A.out.limb[(int64_t)k * A.out.ld + i] = A.m[k];
   }
 }
 
-// Initialise a solve's control block.
-static __global__ void ctl_init_kernel(Ctl* ctl, int32_t maxit, int32_t hist_len) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl->done = 0;
-    ctl->status = kNotConverged;
-    ctl->iters = 0;
-    ctl->maxit = maxit;
-    ctl->flags = 0;
-    ctl->hist_len = hist_len;
+// Initialise the control blocks of n solves.
+static __global__ void ctl_init_kernel(Ctl* ctl, int n, int32_t maxit, int32_t hist_len) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    ctl[i].done = 0;
+    ctl[i].status = kNotConverged;
+    ctl[i].iters = 0;
+    ctl[i].maxit = maxit;
+    ctl[i].flags = 0;
+    ctl[i].hist_len = hist_len;
   }
 }
 

@@ -48,7 +48,34 @@ struct SpmvArgs {
   const int32_t* pair_hdr[3];
   int pair_slot[3];
   int32_t* anchor;
+  // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
+  int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
+  int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
+  const int32_t* pair_of_tile;   // solve of each 512-element tile of y (done flags, anchors)
+  const int32_t* done_base;      // &ctl[0].done; solve k's flag at done_base[k * done_stride]
+  int64_t done_stride;
+  int slots_per_pair;
 };
+
+// Row block, right-hand side and solve of this block; false if that solve is finished.
+struct SpmvBlock {
+  int64_t rb;
+  int rhs;
+  int pair;
+};
+
+MPD bool spmv_block(const SpmvArgs& A, SpmvBlock& B) {
+  B.rhs = (int)(blockIdx.x % (unsigned)A.nrhs);
+  B.rb = (int64_t)(blockIdx.x / (unsigned)A.nrhs);
+  B.pair = 0;
+  if (A.pair_of_tile) {
+    B.pair = A.pair_of_tile[(B.rhs * A.y_rstride + B.rb * 64) / 512];
+    if (*(volatile const int32_t*)&A.done_base[B.pair * A.done_stride]) return false;
+  } else if (A.done && *(volatile const int32_t*)A.done) {
+    return false;
+  }
+  return true;
+}
 
 // Fold row r's output header yh into the anchors of its requested products.
 struct PairAcc {
@@ -64,6 +91,7 @@ MPD void pair_init(PairAcc& P) {
 }
 
 MPD void pair_fold(const SpmvArgs& A, PairAcc& P, int64_t row, int32_t yh) {
+  // row: index into y (right-hand side offset included)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k < A.npair) {
@@ -77,7 +105,7 @@ MPD void pair_fold(const SpmvArgs& A, PairAcc& P, int64_t row, int32_t yh) {
   }
 }
 
-MPD void pair_publish(const SpmvArgs& A, PairAcc& P) {
+MPD void pair_publish(const SpmvArgs& A, PairAcc& P, int pair) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (k < A.npair) {
@@ -89,7 +117,8 @@ MPD void pair_publish(const SpmvArgs& A, PairAcc& P) {
       }
       if ((threadIdx.x & 63) == 0 && hi >= lo) {
         // bins of 64 per slot, spread by block (the inner-product kernel reduces them)
-        int32_t* a = A.anchor + 2 * ((int64_t)A.pair_slot[k] * 64 + (blockIdx.x & 63));
+        const int64_t slot = (int64_t)pair * A.slots_per_pair + A.pair_slot[k];
+        int32_t* a = A.anchor + 2 * (slot * 64 + (blockIdx.x & 63));
         atomicMin(&a[0], lo);
         atomicMax(&a[1], hi);
       }
@@ -105,9 +134,13 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
   __shared__ int32_t s_e[kChunk];
   __shared__ uint32_t s_s[kChunk];
 
-  if (A.done && *(volatile const int32_t*)A.done) return;
+  SpmvBlock B;
+  if (!spmv_block(A, B)) return;
   const int lane = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  const int64_t r0 = B.rb * kRowsPerBlock;
+  const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
+  const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
+  const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
   const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);
   for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
   __syncthreads();
@@ -125,7 +158,7 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
       const int64_t k = c0 + j;
       const int32_t ha = A.a_hdr[k];
       const int32_t col = A.col_idx[k];
-      const int32_t hx = A.x_hdr[col];
+      const int32_t hx = x_hdr[col];
       Num<L> t;
       if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
         set_zero(t, (uint32_t)(ha ^ hx) & 1u);
@@ -134,7 +167,7 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
 #pragma unroll
         for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
 #pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = A.x_limb[(int64_t)q * A.x_ld + col];
+        for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
         mul_full<L>(am, xm, pr);
         round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, t, st);
       }
@@ -156,12 +189,12 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
     }
     __syncthreads();
   }
-  if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
+  if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
   if (A.npair) {
     PairAcc P;
     pair_init(P);
-    if (has_row) pair_fold(A, P, r0 + lane, make_hdr(acc.e, acc.s));
-    pair_publish(A, P);
+    if (has_row) pair_fold(A, P, yo + r0 + lane, make_hdr(acc.e, acc.s));
+    pair_publish(A, P, B.pair);
   }
   if (st) atomicOr(A.status, st);
 }
@@ -177,9 +210,13 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   __shared__ uint32_t s_s[kChunk];
   __shared__ int64_t s_win[WF * 64];
 
-  if (A.done && *(volatile const int32_t*)A.done) return;
+  SpmvBlock B;
+  if (!spmv_block(A, B)) return;
   const int lane = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+  const int64_t r0 = B.rb * kRowsPerBlock;
+  const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
+  const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
+  const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
   const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);
   for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
   __syncthreads();
@@ -193,7 +230,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   int32_t emin = INT32_MAX, emax = INT32_MIN;
   for (int k = rs; k < re; ++k) {
     const int32_t ha = A.a_hdr[k];
-    const int32_t hx = A.x_hdr[A.col_idx[k]];
+    const int32_t hx = x_hdr[A.col_idx[k]];
     if (!hdr_is_zero(ha) && !hdr_is_zero(hx)) {
       const int32_t e = (ha >> 1) + (hx >> 1);
       emin = min(emin, e);
@@ -212,7 +249,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
       const int64_t k = c0 + j;
       const int32_t ha = A.a_hdr[k];
       const int32_t col = A.col_idx[k];
-      const int32_t hx = A.x_hdr[col];
+      const int32_t hx = x_hdr[col];
       if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
         s_e[j] = INT32_MIN;
       } else {
@@ -220,7 +257,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
 #pragma unroll
         for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
 #pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = A.x_limb[(int64_t)q * A.x_ld + col];
+        for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
         mul_full<L>(am, xm, pr);
 #pragma unroll
         for (int q = 0; q < 2 * L; ++q) s_p[q][j] = pr[q];
@@ -252,8 +289,8 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     } else {
       set_zero(y, 0);
     }
-    store<L>(y, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
-    if (A.npair) pair_fold(A, P, r0 + lane, make_hdr(y.e, y.s));
+    store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
+    if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
   }
 
   // wide rows: the whole block shares one window
@@ -269,7 +306,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
       if (lane == owner) {
         st |= kStWindow;
         set_zero(y, 0);
-        store<L>(y, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
+        store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
       }
       continue;
     }
@@ -278,13 +315,13 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     for (int k = o_rs + lane; k < o_re; k += 64) {
       const int32_t ha = A.a_hdr[k];
       const int32_t col = A.col_idx[k];
-      const int32_t hx = A.x_hdr[col];
+      const int32_t hx = x_hdr[col];
       if (hdr_is_zero(ha) || hdr_is_zero(hx)) continue;
       uint32_t am[L], xm[L], pr[2 * L];
 #pragma unroll
       for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
 #pragma unroll
-      for (int q = 0; q < L; ++q) xm[q] = A.x_limb[(int64_t)q * A.x_ld + col];
+      for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
       mul_full<L>(am, xm, pr);
       window_add_atomic<L>(s_win, pr, (uint32_t)(ha ^ hx) & 1u,
                            (uint32_t)((ha >> 1) + (hx >> 1) - o_emin));
@@ -292,11 +329,11 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     __syncthreads();
     if (lane == owner) {
       y = window_finalize<L>(s_win, 1, o_W, (int64_t)o_emin - 64 * L, st);
-      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, r0 + lane);
-      if (A.npair) pair_fold(A, P, r0 + lane, make_hdr(y.e, y.s));
+      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
+      if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
     }
   }
-  if (A.npair) pair_publish(A, P);
+  if (A.npair) pair_publish(A, P, B.pair);
   if (st) atomicOr(A.status, st);
 }
 

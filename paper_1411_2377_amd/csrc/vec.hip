@@ -13,15 +13,19 @@ namespace mpapi {
 
 int64_t dot_window_stride() { return mp::dot_shared_digits<16>(); }
 
-int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s) {
+int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s,
+                   int64_t win_stride, int nfinal) {
+  if (win_stride <= 0) win_stride = dot_window_stride();
+  const size_t nwin = (size_t)nslots * win_stride, ntk = (size_t)nslots + nfinal;
   hipError_t e = hipMalloc((void**)anchor, (size_t)2 * nslots * mp::kAnchorBins * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)win, (size_t)nslots * dot_window_stride() * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMalloc((void**)ticket, (size_t)(nslots + 1) * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)win, nwin * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)ticket, ntk * sizeof(uint32_t));
   if (e != hipSuccess) return fail(MPS_ENOMEM, "inner-product workspace: %s", hipGetErrorString(e));
-  e = hipMemsetAsync(*win, 0, (size_t)nslots * dot_window_stride() * sizeof(int64_t), s);
-  if (e == hipSuccess) e = hipMemsetAsync(*ticket, 0, (size_t)(nslots + 1) * sizeof(uint32_t), s);
+  e = hipMemsetAsync(*win, 0, nwin * sizeof(int64_t), s);
+  if (e == hipSuccess) e = hipMemsetAsync(*ticket, 0, ntk * sizeof(uint32_t), s);
   if (e != hipSuccess) return hip_fail(e, "inner-product workspace");
-  hipLaunchKernelGGL(mp::dot_work_init_kernel, dim3(1), dim3(256), 0, s, *anchor, nslots);
+  const unsigned g = (unsigned)std::min<int64_t>(1024, ((int64_t)nslots * mp::kAnchorBins + 255) / 256);
+  hipLaunchKernelGGL(mp::dot_work_init_kernel, dim3(g), dim3(256), 0, s, *anchor, nslots);
   e = hipGetLastError();
   if (e == hipSuccess && !s) e = hipDeviceSynchronize();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "inner-product workspace init");
@@ -46,12 +50,12 @@ unsigned dot_grid(int64_t n, int nd, int L) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, mp::kDotMaxBlocks));
 }
 
-mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots) {
+mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots, int64_t win_stride) {
   mp::DotWork w;
   w.anchor = anchor;
   w.win = win;
   w.ticket = ticket;
-  w.win_stride = dot_window_stride();
+  w.win_stride = win_stride > 0 ? win_stride : dot_window_stride();
   w.nslots = nslots;
   return w;
 }
@@ -61,8 +65,14 @@ unsigned ew_grid(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
+// A batch (vectors of whole kTile tiles, one solve per tile): one 256-thread block per half
+// tile, one element per thread, so that every block belongs to one solve.
+static unsigned ew_grid_of(const mp::VecArgs& a) {
+  return a.batch.pair_of_tile ? (unsigned)(a.n / 256) : ew_grid(a.n);
+}
+
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
-  const unsigned g = dot_grid(a.n, a.nd, L);
+  const unsigned g = a.batch.pair_of_tile ? (unsigned)(a.n / mp::kTile) : dot_grid(a.n, a.nd, L);
   switch (L) {
     case 4: hipLaunchKernelGGL(mp::dot_kernel<4>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
     case 8: hipLaunchKernelGGL(mp::dot_kernel<8>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
@@ -83,7 +93,7 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
 
 int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
   if (a.n == 0) return MPS_OK;
-  const unsigned g = ew_grid(a.n);
+  const unsigned g = ew_grid_of(a);
   switch (kind) {
     case EW_AXPY: MPS_EW_CASES(axpy_kernel, a); break;
     case EW_COPY: MPS_EW_CASES(copy_kernel, a); break;
@@ -102,33 +112,35 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
 
 int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s) {
   if (a.a.n == 0) return MPS_OK;
-  const unsigned g = ew_grid(a.a.n);
+  const unsigned g = ew_grid_of(a.a);
   MPS_EW_CASES(gp_update_kernel, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "gp_update launch");
 }
 
-int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s) {
+int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s,
+               int64_t count, int64_t step) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (count + 255) / 256));
   switch (L) {
     case 4: {
       mp::ConstArgs<4> a;
-      a.out = out; a.hdr = hdr;
+      a.out = out; a.hdr = hdr; a.count = count; a.step = step;
       for (int k = 0; k < 4; ++k) a.m[k] = m[k];
-      hipLaunchKernelGGL(mp::set_scalar_kernel<4>, dim3(1), dim3(1), 0, s, a);
+      hipLaunchKernelGGL(mp::set_scalar_kernel<4>, dim3(g), dim3(256), 0, s, a);
       break;
     }
     case 8: {
       mp::ConstArgs<8> a;
-      a.out = out; a.hdr = hdr;
+      a.out = out; a.hdr = hdr; a.count = count; a.step = step;
       for (int k = 0; k < 8; ++k) a.m[k] = m[k];
-      hipLaunchKernelGGL(mp::set_scalar_kernel<8>, dim3(1), dim3(1), 0, s, a);
+      hipLaunchKernelGGL(mp::set_scalar_kernel<8>, dim3(g), dim3(256), 0, s, a);
       break;
     }
     case 16: {
       mp::ConstArgs<16> a;
-      a.out = out; a.hdr = hdr;
+      a.out = out; a.hdr = hdr; a.count = count; a.step = step;
       for (int k = 0; k < 16; ++k) a.m[k] = m[k];
-      hipLaunchKernelGGL(mp::set_scalar_kernel<16>, dim3(1), dim3(1), 0, s, a);
+      hipLaunchKernelGGL(mp::set_scalar_kernel<16>, dim3(g), dim3(256), 0, s, a);
       break;
     }
     default: return fail(MPS_EINVAL, "bad limb count");

@@ -13,11 +13,14 @@ enum EwKind {
 };
 
 mp::VecRef ref(const mp_vec& v);
-mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots);
+mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots,
+                     int64_t win_stride = 0);
 unsigned ew_grid(int64_t n);
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s);
 int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s);
 int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s);
-int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s);
+// write the constant to out and to count - 1 further places `step` elements apart
+int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s,
+               int64_t count = 1, int64_t step = 0);
 
 }  // namespace mpapi

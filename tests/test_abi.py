@@ -68,3 +68,33 @@ def test_unsupported_precisions_rejected(prec):
     a.row_dim, a.col_dim, a.nnz, a.prec = 1, 1, 0, prec
     a.row_ptr = 1
     assert _lib.LIB.mp_validate_csr(ctypes.byref(a), 0) == _lib.MPS_EINVAL
+
+
+def test_batched_solver_host_validation():
+    from paper_1411_2377_amd import _lib
+    a = (_lib.MpCsr * 2)()
+    for m in a:
+        m.row_dim, m.col_dim, m.nnz, m.prec = 4, 4, 0, 256
+        m.row_ptr = 1234
+    b = (_lib.MpVec * 2)(_lib.MpVec(1000, 2000, 4, 4), _lib.MpVec(3000, 4000, 4, 4))
+    x = (_lib.MpVec * 2)(_lib.MpVec(5000, 6000, 4, 4), _lib.MpVec(7000, 8000, 4, 4))
+    o = _lib.MpSolveOpts()
+    o.maxit = 10
+    info = (_lib.MpSolveInfo * 2)()
+    f = _lib.LIB.gpbicg_batched
+    assert f(0, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
+    assert f(2, a, 0, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
+    o.transpose = 1
+    assert f(2, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_ENOTSUP
+    o.transpose = 0
+    a[1].prec = 128
+    assert f(2, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
+    assert "precision" in _lib.last_error()
+    a[1].prec = 256
+    a[1].col_dim = 5
+    assert f(2, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
+    assert "square" in _lib.last_error()
+    a[1].col_dim = 4
+    x[1] = _lib.MpVec(3000, 4000, 4, 4)   # aliases b[1]
+    assert f(2, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
+    assert "overlap" in _lib.last_error()
