@@ -73,6 +73,40 @@ MPD void store(const Num<L>& x, uint32_t* __restrict__ limb, int32_t* __restrict
   for (int k = 0; k < L; ++k) limb[(int64_t)k * ld + i] = x.m[k];
 }
 
+// Device-coherent accesses for data that blocks of one launch exchange: relaxed device-scope
+// atomic loads and stores, which bypass the per-XCD L2 copies, so they need neither the L2
+// write-back of a device-scope release fence nor the invalidate of an acquire.
+MPD uint32_t ld_dev(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MPD int32_t ld_dev(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MPD void st_dev(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MPD void st_dev(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Wait until every memory operation this wave has issued is complete.  Device-scope atomics and
+// device-coherent stores are then performed at the device's coherence point, so an atomic the
+// wave issues afterwards (a ticket) is observed after them: the ordering half of a release,
+// without its L2 write-back (which the data exchanged this way does not need).
+MPD void wait_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int L>
+MPD void load_dev(Num<L>& x, const uint32_t* limb, const int32_t* hdr, int64_t ld, int64_t i) {
+  const int32_t h = ld_dev(hdr + i);
+  x.e = h >> 1;
+  x.s = (uint32_t)h & 1u;
+#pragma unroll
+  for (int k = 0; k < L; ++k) x.m[k] = (x.e != kZeroE) ? ld_dev(limb + (int64_t)k * ld + i) : 0u;
+}
+
+template <int L>
+MPD void store_dev(const Num<L>& x, uint32_t* limb, int32_t* hdr, int64_t ld, int64_t i) {
+  st_dev(hdr + i, make_hdr(x.e, x.s));
+#pragma unroll
+  for (int k = 0; k < L; ++k) st_dev(limb + (int64_t)k * ld + i, x.m[k]);
+}
+
 // (hi:lo) >> s for 0 <= s < 32
 MPD uint32_t fshr(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 

@@ -72,6 +72,14 @@ MPD Num<L> sload(const Scalars& S, int slot) {
   return r;
 }
 
+// Scalar read that sees values other blocks of the same launch stored with store_dev.
+template <int L>
+MPD Num<L> sload_dev(const Scalars& S, int slot) {
+  Num<L> r;
+  load_dev<L>(r, S.limb, S.hdr, S.ld, slot);
+  return r;
+}
+
 template <int L>
 MPD void sstore(const Scalars& S, int slot, const Num<L>& v) {
   store<L>(v, S.limb, S.hdr, S.ld, slot);
@@ -97,7 +105,8 @@ MPD void finish(Ctl* ctl, int status) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Driver epilogues, run by one thread after the inner products of a step are known.
+// Driver epilogues, run by one thread after the inner products of a step are known (they read
+// the scalars with device-coherent loads: other blocks of the launch stored some of them).
 // ------------------------------------------------------------------------------------------
 enum Epi {
   EPI_NONE = 0,
@@ -114,41 +123,41 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
   if (!ctl || epi == EPI_NONE) return;
   switch (epi) {
     case EPI_SETUP: {
-      const Num<L> q0 = sload<L>(S, S_Q0);
+      const Num<L> q0 = sload_dev<L>(S, S_Q0);
       const Num<L> nrm0 = sqrt_rn<L>(q0, st);
-      const Num<L> thr = add_rn<L>(mul_rn<L>(sload<L>(S, S_CREL), nrm0, st), sload<L>(S, S_CABS), st);
+      const Num<L> thr = add_rn<L>(mul_rn<L>(sload_dev<L>(S, S_CREL), nrm0, st), sload_dev<L>(S, S_CABS), st);
       sstore<L>(S, S_NRM0, nrm0);
       sstore<L>(S, S_THR, thr);
       if (sqrt_le<L>(q0, thr)) {
         finish(ctl, kConverged);
       } else if (ctl->maxit <= 0) {
         finish(ctl, kNotConverged);
-      } else if (is_zero(sload<L>(S, S_RHO))) {
+      } else if (is_zero(sload_dev<L>(S, S_RHO))) {
         finish(ctl, kBreakRho);
       }
       break;
     }
     case EPI_BICG_SIGMA: {
-      const Num<L> sigma = sload<L>(S, S_SIGMA);
+      const Num<L> sigma = sload_dev<L>(S, S_SIGMA);
       if (is_zero(sigma)) {
         finish(ctl, kBreakSigma);
       } else {
-        sstore<L>(S, S_ALPHA, div_rn<L>(sload<L>(S, S_RHO), sigma, st));
+        sstore<L>(S, S_ALPHA, div_rn<L>(sload_dev<L>(S, S_RHO), sigma, st));
       }
       break;
     }
     case EPI_GP_ALPHA: {
-      const Num<L> den = sload<L>(S, S_DEN);
+      const Num<L> den = sload_dev<L>(S, S_DEN);
       if (is_zero(den)) {
         finish(ctl, kBreakSigma);
       } else {
-        sstore<L>(S, S_ALPHA, div_rn<L>(sload<L>(S, S_RHO), den, st));
+        sstore<L>(S, S_ALPHA, div_rn<L>(sload_dev<L>(S, S_RHO), den, st));
       }
       break;
     }
     case EPI_GP_ZETA: {
-      const Num<L> mu1 = sload<L>(S, S_MU1), mu2 = sload<L>(S, S_MU2), mu3 = sload<L>(S, S_MU3);
-      const Num<L> mu4 = sload<L>(S, S_MU4), mu5 = sload<L>(S, S_MU5);
+      const Num<L> mu1 = sload_dev<L>(S, S_MU1), mu2 = sload_dev<L>(S, S_MU2), mu3 = sload_dev<L>(S, S_MU3);
+      const Num<L> mu4 = sload_dev<L>(S, S_MU4), mu5 = sload_dev<L>(S, S_MU5);
       if (ctl->iters == 0) {  // first iteration: zeta = mu2 / mu5, eta = 0
         if (is_zero(mu5)) {
           finish(ctl, kBreakTau);
@@ -174,15 +183,15 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
     }
     case EPI_BICG_CONV:
     case EPI_GP_CONV: {
-      const Num<L> q = sload<L>(S, S_Q);
+      const Num<L> q = sload_dev<L>(S, S_Q);
       const int i = ctl->iters + 1;
       if (hist.limb && i - 1 < ctl->hist_len) vstore<L>(hist, i - 1, q);
       ctl->iters = i;
-      if (sqrt_le<L>(q, sload<L>(S, S_THR))) {
+      if (sqrt_le<L>(q, sload_dev<L>(S, S_THR))) {
         finish(ctl, kConverged);
         break;
       }
-      if (epi == EPI_GP_CONV && is_zero(sload<L>(S, S_ZETA))) {
+      if (epi == EPI_GP_CONV && is_zero(sload_dev<L>(S, S_ZETA))) {
         finish(ctl, kBreakZeta);
         break;
       }
@@ -190,8 +199,8 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
         finish(ctl, kNotConverged);
         break;
       }
-      const Num<L> rho = sload<L>(S, S_RHO);
-      const Num<L> rho_next = sload<L>(S, S_RHO_NEXT);
+      const Num<L> rho = sload_dev<L>(S, S_RHO);
+      const Num<L> rho_next = sload_dev<L>(S, S_RHO_NEXT);
       sstore<L>(S, S_RHO_OLD, rho);
       sstore<L>(S, S_RHO, rho_next);
       if (is_zero(rho_next)) {
@@ -201,7 +210,7 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
       if (epi == EPI_BICG_CONV) {
         sstore<L>(S, S_BETA, div_rn<L>(rho_next, rho, st));
       } else {
-        const Num<L> alpha = sload<L>(S, S_ALPHA), zeta = sload<L>(S, S_ZETA);
+        const Num<L> alpha = sload_dev<L>(S, S_ALPHA), zeta = sload_dev<L>(S, S_ZETA);
         sstore<L>(S, S_ALPHA_OLD, alpha);
         sstore<L>(S, S_ZETA_OLD, zeta);
         sstore<L>(S, S_BETA, mul_rn<L>(div_rn<L>(rho_next, rho, st), div_rn<L>(alpha, zeta, st), st));
@@ -326,8 +335,8 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   int32_t* abins = A.w.anchor + 2 * (int64_t)slot * kAnchorBins;
   int32_t emin = INT32_MAX, emax = INT32_MIN;
   if (t < kAnchorBins) {
-    emin = abins[2 * t];
-    emax = abins[2 * t + 1];
+    emin = ld_dev(&abins[2 * t]);
+    emax = ld_dev(&abins[2 * t + 1]);
   }
   emin = wave_min(emin);
   emax = wave_max(emax);
@@ -422,7 +431,9 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     }
   }
 
-  __threadfence();
+  // the window atomics of every wave are complete before the ticket is taken; the last block
+  // then reads the window with atomics, so no cache write-back or invalidate is needed
+  wait_memory();
   __syncthreads();
   if (t == 0) s_last = (atomicAdd(&A.w.ticket[slot], 1u) == nblocks - 1) ? 1u : 0u;
   __syncthreads();
@@ -430,15 +441,12 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     if (st) atomicOr(A.status, st);
     return;
   }
-  __threadfence();
   // last block of this inner product: take the window back (clearing it), round once
   Num<L> res;
   set_zero(res, 0);
   if (any && fits) {
-    for (int w = t; w < W; w += kDotThreads) {
-      s_win[w] = __hip_atomic_load(&gw[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      gw[w] = 0;
-    }
+    for (int w = t; w < W; w += kDotThreads)
+      s_win[w] = (int64_t)atomicExch((unsigned long long*)&gw[w], 0ull);
     __syncthreads();
     if (t == 0) {
       if (W <= WMAXF) {
@@ -454,8 +462,8 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     }
   }
   if (t < kAnchorBins) {
-    abins[2 * t] = INT32_MAX;
-    abins[2 * t + 1] = INT32_MIN;
+    st_dev(&abins[2 * t], INT32_MAX);
+    st_dev(&abins[2 * t + 1], INT32_MIN);
   }
   if (t == 0) {
     VecRef o = A.out[d];  // batch: a scalar slot of solve 0, moved to this solve's slots
@@ -463,17 +471,16 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
       o.limb += (int64_t)pair * kNumScalars;
       o.hdr += (int64_t)pair * kNumScalars;
     }
-    vstore<L>(o, 0, res);
-    A.w.ticket[slot] = 0;
+    store_dev<L>(res, o.limb, o.hdr, o.ld, 0);  // the epilogue below may run in another block
+    st_dev(&A.w.ticket[slot], 0u);
     if (ctl && st) atomicOr(&ctl->flags, st);
     // the last inner product of the launch (of this solve) to finish runs the driver epilogue
-    __threadfence();
+    wait_memory();
     if (atomicAdd(&A.w.ticket[A.w.nslots + pair], 1u) == (unsigned)A.nd - 1) {
-      __threadfence();
       uint32_t st2 = 0;
       const int was_done = ctl ? ctl->done : 0;
       epilogue<L>(A.epi, S, ctl, A.hist, st2);
-      A.w.ticket[A.w.nslots + pair] = 0;
+      st_dev(&A.w.ticket[A.w.nslots + pair], 0u);
       if (ctl && st2) atomicOr(&ctl->flags, st2);
       if (A.batch.ndone && ctl && !was_done && ctl->done) atomicAdd(A.batch.ndone, 1);
       st |= st2;
