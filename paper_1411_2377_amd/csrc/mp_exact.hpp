@@ -147,6 +147,80 @@ MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& 
 
 namespace mp {
 
+// RN_p of sum_w d_w 2^(32 w + base) for carry-save digits held one per lane of a wave (lane w
+// holds digit w, |d_w| < 2^62; lanes past the window hold 0 and lane 63 must be headroom, so
+// windows of at most 63 digits).  Every lane of the wave calls it and gets the result.
+// Carries move up one lane per step until every digit is a 32-bit value (few steps unless a
+// carry ripples); the sign is then lane 63's top bit; the magnitude, its leading bit, the
+// mantissa limbs (lane k forms limb k), the round and sticky bits and the rounding carry are
+// found with shuffles and lane masks.
+template <int L>
+MPD Num<L> wave_round(int64_t d, int64_t base, uint32_t& st) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+  uint32_t lo = (uint32_t)d;
+  int32_t c = (lane == 63) ? 0 : (int32_t)(d >> 32);
+  while (__ballot(c != 0)) {
+    const int32_t cin = __shfl_up(c, 1);
+    const int64_t t = (int64_t)lo + (lane ? cin : 0);
+    lo = (uint32_t)t;
+    c = (lane == 63) ? 0 : (int32_t)(t >> 32);
+  }
+  const uint32_t neg = __shfl(lo, 63) >> 31;
+  uint32_t m = lo;
+  if (neg) {  // two's complement: ~lo plus a carry that passes every zero lane under this one
+    const uint64_t nz = __ballot(lo != 0);
+    m = ~lo + (((nz & below) == 0) ? 1u : 0u);
+  }
+  const uint64_t nzm = __ballot(m != 0);
+  Num<L> out;
+  if (nzm == 0) {
+    set_zero(out, 0);
+    return out;
+  }
+  const int top = 63 - (int)__clzll((long long)nzm);
+  const uint32_t mtop = __shfl(m, top);
+  const int b0 = 32 * top + 31 - (int)__clz((int)mtop) - 32 * L + 1;  // mantissa LSB bit index
+  const int q0 = b0 >> 5;                                           // floor
+  const uint32_t r0 = (uint32_t)(b0 & 31);
+  const int i_lo = q0 + lane, i_hi = q0 + lane + 1;
+  const uint32_t v_lo = __shfl(m, i_lo & 63), v_hi = __shfl(m, i_hi & 63);
+  const uint32_t w_lo = (i_lo >= 0 && i_lo < 64) ? v_lo : 0u;
+  const uint32_t w_hi = (i_hi >= 0 && i_hi < 64) ? v_hi : 0u;
+  uint32_t limb = r0 ? fshr(w_hi, w_lo, r0) : w_lo;  // mantissa limb `lane` (lanes < L)
+  uint32_t rnd = 0, sticky = 0;
+  const int rb = b0 - 1;
+  if (rb >= 0) {
+    const int ri = rb >> 5;
+    const uint32_t rs = (uint32_t)(rb & 31);
+    const uint32_t mr = __shfl(m, ri);
+    rnd = (mr >> rs) & 1u;
+    const uint64_t under = ri ? (~0ull >> (64 - ri)) : 0ull;
+    sticky = ((rs ? (mr & ((1u << rs) - 1u)) : 0u) != 0u || (nzm & under) != 0) ? 1u : 0u;
+  }
+  int64_t e = (int64_t)b0 + base + 32 * L;
+  const uint32_t m0 = __shfl(limb, 0);
+  if (rnd & (sticky | (m0 & 1u))) {
+    constexpr uint64_t lmask = (L >= 64) ? ~0ull : ((1ull << L) - 1ull);
+    const uint64_t ones = __ballot(limb == 0xFFFFFFFFu) & lmask;
+    if (lane < L && (ones & below) == (below & lmask)) limb += 1u;
+    if (ones == lmask) {  // all ones: the mantissa becomes 2^(p-1) one exponent up
+      limb = (lane == L - 1) ? 0x80000000u : 0u;
+      e += 1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = __shfl(limb, k);
+  out.s = neg;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, neg);
+    return out;
+  }
+  out.e = (int32_t)e;
+  return out;
+}
+
 // Register-resident variants for windows of at most WMAX digits (the common case): the digits
 // are read from LDS once, then carried, signed and rounded in registers with fully unrolled
 // loops, avoiding a chain of dependent LDS round trips.

@@ -444,7 +444,13 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   // last block of this inner product: take the window back (clearing it), round once
   Num<L> res;
   set_zero(res, 0);
-  if (any && fits) {
+  if (any && fits && W <= 63) {
+    // one digit per lane of the first wave, rounded by the whole wave
+    if (t < 64) {
+      const int64_t dg = (t < W) ? (int64_t)atomicExch((unsigned long long*)&gw[t], 0ull) : 0;
+      res = wave_round<L>(dg, (int64_t)emin - 64 * L, st);
+    }
+  } else if (any && fits) {
     for (int w = t; w < W; w += kDotThreads)
       s_win[w] = (int64_t)atomicExch((unsigned long long*)&gw[w], 0ull);
     __syncthreads();

@@ -160,3 +160,40 @@ def test_dot_wide_span_and_long():
     xo, yo = codec.decode(x_h.limbs, x_h.hdr, p), codec.decode(y_h.limbs, y_h.hdr, p)
     assert_bitwise(d[0], d[1], [blas.dot(xo, yo, p)], p, what="wide dot")
     assert M.mp_status() == 0
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_dot_rounding_edge_cases(p):
+    """Inner products whose exact sums sit on the rounding boundaries: ties to even, the
+    all-ones mantissa that rounds up to the next power of two, exact cancellation, negative
+    sums, borrows through many digits and windows of about 60 digits and of more."""
+    from fractions import Fraction as F
+    M = lib()
+    h = F(1, 2 ** p)            # half an ulp of 1 is 2^-p
+    cases = [
+        ([F(1), h], [F(1), F(1)]),                          # tie, even: 1
+        ([F(1), 3 * h / 2], [F(1), F(1)]),                  # above the tie: up
+        ([1 - h, h / 2], [F(1), F(1)]),                      # all ones + half ulp: 1
+        ([F(1, 3), F(1, 3)], [F(1), F(-1)]),                 # exact cancellation: +0
+        ([F(1), h], [F(-1), F(-1)]),                         # negative tie: -1
+        ([F(2) ** 100, F(-1), F(1, 2 ** 100)], [F(1), F(1), F(1)]),
+        ([F(-(2 ** 60)), F(1, 2 ** 200), F(2 ** 60)], [F(1), F(1), F(1)]),
+        ([F(2) ** 500, F(1, 2 ** 500)], [F(2) ** 200, F(-1, 2 ** 600)]),
+        ([F(2) ** 450, F(-3, 2 ** 450)], [F(1), F(1)]),      # a window of about 60 digits
+        ([F(2) ** 900, F(-3, 2 ** 900)], [F(2) ** 900, F(1, 2 ** 900)]),
+        ([F(2) ** 1000, F(1, 2 ** 1000), F(-1)], [F(2) ** 1000, F(-1, 2 ** 1000), F(1)]),
+    ]
+    rng = np.random.default_rng(p + 1)
+    for _ in range(12):   # random cancelling sums: sum of values and their near-negatives
+        k = int(rng.integers(2, 9))
+        xs = [F(int(rng.integers(-2 ** 40, 2 ** 40)), 2 ** int(rng.integers(0, 300))) for _ in range(k)]
+        ys = [F(1)] * k
+        xs = xs + [-v for v in xs[:-1]] + [F(1, 2 ** int(rng.integers(100, 700)))]
+        ys = ys + ys[:-1] + [F(1)]
+        cases.append((xs, ys))
+    for i, (xs, ys) in enumerate(cases):
+        x_h = synth.mp_from_rationals([(v.numerator, v.denominator) for v in xs], p)
+        y_h = synth.mp_from_rationals([(v.numerator, v.denominator) for v in ys], p)
+        d = M.mp_dot(M.MPArray.from_host(x_h), M.MPArray.from_host(y_h)).to_numpy()
+        xo, yo = codec.decode(x_h.limbs, x_h.hdr, p), codec.decode(y_h.limbs, y_h.hdr, p)
+        assert_bitwise(d[0], d[1], [blas.dot(xo, yo, p)], p, what="dot case %d" % i)
