@@ -39,6 +39,11 @@
  * mp_last_error().  Conditions found on the device (an exponent leaving the range, an exact
  * accumulation wider than supported) set bits in the per-device status word, read with
  * mp_status().  The library never aborts and never prints.
+ *
+ * EXACT WINDOW LIMITS.  An EXACT row sum is supported when its non-zero products' exponents
+ * e_a + e_x span at most 32 * (16 R - 2L - 2) bits, R = 2L + 10 digits (L = p/32): about 8,900,
+ * 12,700 and 20,400 bits at p = 128, 256, 512.  Exact inner products (mp_dot, solvers) support
+ * spans of 32 * (257 R - 2L - 2) bits.  Wider sums set MP_ST_WINDOW and give +0.
  */
 #ifndef MPSPMV_H
 #define MPSPMV_H
@@ -127,8 +132,11 @@ const char *mp_last_error(void);
 int mp_validate_csr(const mp_csr *A, int check_device_data);
 
 /* y = A x (Sec. 2-3 of the paper) in the given mode.  x.len == col_dim, y.len == row_dim, all
- * at A->prec.  y must not overlap x or A.  Asynchronous on `stream`. */
-int mpspmv_csr(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, void *stream);
+ * at A->prec.  y must not overlap x or A.  `plan` (nullable; built from A) supplies the kernel
+ * variant chosen by mp_plan_tune; without one the variant follows A's shape.  The result bits do
+ * not depend on the variant.  Asynchronous on `stream`. */
+int mpspmv_csr(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp_plan *plan,
+               void *stream);
 
 /* Build the transposed-product plan of A (synchronises `stream`; allocates device memory).
  * The plan records A's shape and precision; its values are a copy: after changing A's values
@@ -141,6 +149,21 @@ int mp_plan_refresh(mp_plan *plan, const mp_csr *A, void *stream);
  * original rows in ascending order).  x.len == row_dim, y.len == col_dim. */
 int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp_plan *plan,
                  void *stream);
+
+/* Kernel variants (implementation tuning, not part of the paper's method).  The SpMV kernels
+ * process `rows_per_block` rows (16, 32 or 64) per wavefront-sized block, and may first stage x
+ * as one contiguous record per element (`stage_x`: one cache line per gathered x_j instead of
+ * one per limb, which pays for scattered columns).  op 0 is the product with A, op 1 with A^T.
+ * mp_plan_tune times every variant of the four products (both ops, both modes; `reps`
+ * launches each, 0: 3) on a generated operand, synchronously on `stream`, and stores the
+ * fastest in the plan; the plan then selects it for mpspmv_csr, mpspmv_csr_t and the solvers
+ * given the plan.  Results are bit-identical for every variant.  mp_plan_set_variant forces a
+ * variant (rows 0: by shape); mp_plan_get_variant reports the one in effect.  A plan whose
+ * variants stage x holds one staging buffer: calls using it must not overlap in time (one
+ * stream at a time).  All return MPS_OK or MPS_EINVAL (also MPS_ENOMEM; tune also MPS_EHIP). */
+int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
+int mp_plan_set_variant(mp_plan *plan, int op, int mode, int rows_per_block, int stage_x);
+int mp_plan_get_variant(const mp_plan *plan, int op, int mode, int *rows_per_block, int *stage_x);
 
 /* gvals_k = RN(g_i x_j) for each stored entry k = (i, j) in A's CSR order (negated when
  * negate != 0): the gradient of <g, A x> with respect to the stored values.  Needs the plan

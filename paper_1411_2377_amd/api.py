@@ -23,13 +23,14 @@ def mp_validate_csr(A, check_device_data=False):
     return _lib.LIB.mp_validate_csr(ctypes.byref(d), int(bool(check_device_data)))
 
 
-def mpspmv_csr(A, x, y=None, mode=MP_SEQ, stream=None):
-    """y = A x; allocates y when not given.  Returns y."""
+def mpspmv_csr(A, x, y=None, mode=MP_SEQ, plan=None, stream=None):
+    """y = A x; allocates y when not given.  `plan` (optional) supplies tuned kernel variants.
+    Returns y."""
     if y is None:
         y = MPArray.empty(A.n_rows, A.p, device=x.device)
     a, xd, yd = A.desc(), x.desc(), y.desc()
     check(_lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(xd), ctypes.byref(yd), int(mode),
-                              _stream(stream)))
+                              plan.handle if plan is not None else None, _stream(stream)))
     return y
 
 
@@ -57,6 +58,27 @@ class Plan:
     def refresh(self, stream=None):
         d = self.A.desc()
         check(_lib.LIB.mp_plan_refresh(self._h, ctypes.byref(d), _stream(stream)))
+
+    def tune(self, reps=3, stream=None):
+        """Time the SpMV kernel variants on this matrix and keep the fastest (synchronous)."""
+        d = self.A.desc()
+        check(_lib.LIB.mp_plan_tune(self._h, ctypes.byref(d), int(reps), _stream(stream)))
+        return self.variants()
+
+    def set_variant(self, op, mode, rows=0, stage_x=False):
+        """Force a kernel variant: op 0 = A, 1 = A^T; rows in (0, 16, 32, 64), 0 = by shape;
+        stage_x: gather x from staged records."""
+        check(_lib.LIB.mp_plan_set_variant(self._h, int(op), int(mode), int(rows), int(bool(stage_x))))
+
+    def variants(self):
+        """{(op, mode): (rows per block, stage_x)} in effect."""
+        out = {}
+        for op in (0, 1):
+            for mode in (MP_SEQ, MP_EXACT):
+                v, st = ctypes.c_int(0), ctypes.c_int(0)
+                check(_lib.LIB.mp_plan_get_variant(self._h, op, mode, ctypes.byref(v), ctypes.byref(st)))
+                out[(op, mode)] = (v.value, bool(st.value))
+        return out
 
     def close(self):
         if self._h and self._h.value:

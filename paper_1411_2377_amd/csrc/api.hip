@@ -1,6 +1,8 @@
 // C ABI of the multiple-precision SpMV / Krylov library (declarations in include/mpspmv.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -9,6 +11,7 @@
 
 #include "../../include/mpspmv.h"
 #include "api_internal.hpp"
+#include "plan_internal.hpp"
 #include "spmv_kernels.hpp"
 
 namespace mpapi {
@@ -127,24 +130,44 @@ int check_csr(const mp_csr* A, int check_device_data) {
 }
 
 // ---- SpMV launch ----------------------------------------------------------------------------
-template <int L>
-static void launch_spmv(const mp::SpmvArgs& a, int mode, hipStream_t s) {
-  const unsigned grid =
-      (unsigned)((a.n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock) * (unsigned)a.nrhs;
+// Rows per block (one wavefront per block): fewer rows per block give more, shorter waves, which
+// hides latency on short rows; more rows per block amortise a block's fixed work on long ones.
+// Every variant computes the same bits.
+int default_rows_per_block(int64_t n_rows, int64_t nnz) {
+  const int64_t avg = n_rows > 0 ? nnz / n_rows : 0;
+  return avg <= 8 ? 16 : avg <= 24 ? 32 : 64;
+}
+
+bool valid_rows_per_block(int rpw) { return rpw == 16 || rpw == 32 || rpw == 64; }
+
+template <int L, int RPW>
+static void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.n_rows + RPW - 1) / RPW) * (unsigned)a.nrhs;
   if (mode == MP_SEQ)
-    hipLaunchKernelGGL(mp::spmv_seq_kernel<L>, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((mp::spmv_seq_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL(mp::spmv_exact_kernel<L>, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((mp::spmv_exact_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
+}
+
+template <int L>
+static void launch_spmv(const mp::SpmvArgs& a, int mode, int rpw, hipStream_t s) {
+  switch (rpw) {
+    case 16: launch_spmv_rpw<L, 16>(a, mode, s); break;
+    case 32: launch_spmv_rpw<L, 32>(a, mode, s); break;
+    default: launch_spmv_rpw<L, 64>(a, mode, s); break;
+  }
 }
 
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvPairs* pairs,
-                const SpmvBatch* batch) {
+                const SpmvBatch* batch, int rpw, uint32_t* x_rec, int64_t x_len) {
   if (n_rows == 0) return MPS_OK;
+  if (x_rec && batch && batch->nrhs != 1) return fail(MPS_EINVAL, "staged x takes one right-hand side");
   const SpmvBatch one;
   if (!batch) batch = &one;
-  if ((n_rows + mp::kRowsPerBlock - 1) / mp::kRowsPerBlock * batch->nrhs > (int64_t)UINT32_MAX)
+  if (!valid_rows_per_block(rpw)) rpw = default_rows_per_block(n_rows, val.len);
+  if ((n_rows + rpw - 1) / rpw * batch->nrhs > (int64_t)UINT32_MAX)
     return fail(MPS_ENOTSUP, "too many row blocks for one launch");
   mp::SpmvArgs a;
   a.n_rows = n_rows;
@@ -170,6 +193,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.slots_per_pair = batch->slots_per_pair;
   a.npair = 0;
   a.anchor = nullptr;
+  a.x_rec = x_rec;
   for (int k = 0; k < 3; ++k) {
     a.pair_hdr[k] = nullptr;
     a.pair_slot[k] = 0;
@@ -182,10 +206,19 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
       a.pair_slot[k] = pairs->slot[k];
     }
   }
+  if (x_rec && x_len > 0) {
+    const unsigned g = (unsigned)std::min<int64_t>(16384, (x_len + 255) / 256);
+    switch (L) {
+      case 4: hipLaunchKernelGGL(mp::x_stage_kernel<4>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 8: hipLaunchKernelGGL(mp::x_stage_kernel<8>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 16: hipLaunchKernelGGL(mp::x_stage_kernel<16>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      default: return fail(MPS_EINVAL, "bad limb count");
+    }
+  }
   switch (L) {
-    case 4: launch_spmv<4>(a, mode, s); break;
-    case 8: launch_spmv<8>(a, mode, s); break;
-    case 16: launch_spmv<16>(a, mode, s); break;
+    case 4: launch_spmv<4>(a, mode, rpw, s); break;
+    case 8: launch_spmv<8>(a, mode, rpw, s); break;
+    case 16: launch_spmv<16>(a, mode, rpw, s); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -206,10 +239,12 @@ int mp_validate_csr(const mp_csr* A, int check_device_data) {
   return check_csr(A, check_device_data);
 }
 
-int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stream) {
+int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_plan* plan,
+               void* stream) {
   clear_error();
   int r = check_csr(A, 0);
   if (r) return r;
+  if (plan && (r = check_plan(plan, A))) return r;
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if ((r = check_vec(x, A->col_dim, "x"))) return r;
   if ((r = check_vec(y, A->row_dim, "y"))) return r;
@@ -218,8 +253,10 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stre
     return fail(MPS_EINVAL, "y overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
+  const bool stage = plan && plan->stage[0][mode] && plan->x_rec;
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
-                     nullptr, (hipStream_t)stream);
+                     nullptr, (hipStream_t)stream, nullptr, nullptr,
+                     plan ? plan->rpw[0][mode] : 0, stage ? plan->x_rec : nullptr, A->col_dim);
 }
 
 int mp_status(void* stream, uint32_t* flags) {

@@ -54,6 +54,11 @@ int check_csr(const mp_csr* A, int check_device_data);
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr,
-                const SpmvBatch* batch = nullptr);
+                const SpmvBatch* batch = nullptr, int rows_per_block = 0,
+                uint32_t* x_rec = nullptr, int64_t x_len = 0);
+// x_rec (nullable): a buffer of x_len staged x records; the launch first stages x into it
+// rows per block of the SpMV kernels: 16, 32 or 64 (0 or anything else: chosen from the shape)
+int default_rows_per_block(int64_t n_rows, int64_t nnz);
+bool valid_rows_per_block(int rpw);
 
 }  // namespace mpapi

@@ -33,7 +33,9 @@ MPD void shift_product(const uint32_t (&P)[2 * L], uint32_t r, uint32_t (&sp)[2 
   sp[2 * L] = r ? (P[2 * L - 1] >> (32u - r)) : 0u;
 }
 
-// win[w * ws] += (-1)^s * (P << off) split in 32-bit digits (no carry propagation).
+// win[w * ws] += (-1)^s * (P << off) split in 32-bit digits (no carry propagation).  The adds
+// are issued as LDS atomics without return: a window is private to its lane, but an atomic add
+// needs no read-back, so the 2L + 1 adds of a product do not wait on one another.
 template <int L>
 MPD void window_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, uint32_t off) {
   uint32_t sp[2 * L + 1];
@@ -42,9 +44,14 @@ MPD void window_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s
 #pragma unroll
   for (int j = 0; j <= 2 * L; ++j) {
     const int64_t v = s ? -(int64_t)sp[j] : (int64_t)sp[j];
-    win[(q + j) * ws] += v;
+    atomicAdd((unsigned long long*)&win[(q + j) * ws], (unsigned long long)v);
   }
 }
+
+// RN_p of a lane window of W <= WMAX digits at stride ws: digits read once, carried and signed
+// in registers, the magnitude limbs written back and rounded.
+template <int L, int WMAX>
+MPD Num<L> lane_window_round(int64_t* win, int ws, int W, int64_t base, uint32_t& st);
 
 // Same, with atomic adds (a window shared by several lanes).
 template <int L>
@@ -61,11 +68,24 @@ MPD void window_add_atomic(int64_t* win, const uint32_t (&P)[2 * L], uint32_t s,
   }
 }
 
-// RN_p of (-1)^sgn * sum_{w < nl} win[w*ws] 2^(32 w + base) for magnitude limbs (each digit
+// Digit w of a window lives at win[map(w)]: a stride (StrideMap) or a ring rotated so that
+// window digit 0 is ring slot s0 (RingMap).
+struct StrideMap {
+  int ws;
+  MPD int operator()(int w) const { return w * ws; }
+};
+
+template <int R>
+struct RingMap {
+  int ws, s0;
+  MPD int operator()(int w) const { return (s0 + w >= R ? s0 + w - R : s0 + w) * ws; }
+};
+
+// RN_p of (-1)^sgn * sum_{w < nl} win[map(w)] 2^(32 w + base) for magnitude limbs (each digit
 // holds a 32-bit limb; limb nl-1 is the top non-zero one, nl == 0 means zero).
-template <int L>
-MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, uint32_t& st,
-                       int ws = 1) {
+template <int L, class Map>
+MPD Num<L> limbs_round_map(const int64_t* win, Map map, int nl, uint32_t sgn, int64_t base,
+                           uint32_t& st) {
   const int W = nl;
   const int top = nl - 1;
   Num<L> out;
@@ -73,10 +93,10 @@ MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, u
     set_zero(out, 0);
     return out;
   }
-  const int T = 32 * top + 31 - (int)__clz((uint32_t)win[top * ws]);  // leading bit index
+  const int T = 32 * top + 31 - (int)__clz((uint32_t)win[map(top)]);  // leading bit index
   const int b0 = T - 32 * L + 1;                                       // mantissa LSB index
   auto limb_at = [&](int idx) -> uint32_t {
-    return (idx >= 0 && idx < W) ? (uint32_t)win[idx * ws] : 0u;
+    return (idx >= 0 && idx < W) ? (uint32_t)win[map(idx)] : 0u;
   };
   auto bits_at = [&](int b) -> uint32_t {  // the 32 bits starting at bit index b (b may be < 0)
     if (b <= -32) return 0u;
@@ -114,33 +134,43 @@ MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, u
   return out;
 }
 
-
-// RN_p of the window value sum_w win[w*ws] * 2^(32 w + base).  The digits are overwritten
-// (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
 template <int L>
-MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
+MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, uint32_t& st,
+                       int ws = 1) {
+  return limbs_round_map<L>(win, StrideMap{ws}, nl, sgn, base, st);
+}
+
+// RN_p of the window value sum_w win[map(w)] * 2^(32 w + base) over W digits.  The digits are
+// overwritten (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
+template <int L, class Map>
+MPD Num<L> window_finalize_map(int64_t* win, Map map, int W, int64_t base, uint32_t& st) {
   int64_t c = 0;
   for (int w = 0; w < W; ++w) {
-    const int64_t t = win[w * ws] + c;
-    win[w * ws] = (int64_t)(uint32_t)t;
+    const int64_t t = win[map(w)] + c;
+    win[map(w)] = (int64_t)(uint32_t)t;
     c = t >> 32;
   }
   const uint32_t sgn = (c < 0) ? 1u : 0u;
   if (sgn) {
     uint32_t cy = 1;
     for (int w = 0; w < W; ++w) {
-      const uint32_t v = __builtin_addc(~(uint32_t)win[w * ws], 0u, cy, &cy);
-      win[w * ws] = (int64_t)v;
+      const uint32_t v = __builtin_addc(~(uint32_t)win[map(w)], 0u, cy, &cy);
+      win[map(w)] = (int64_t)v;
     }
   }
   int top = -1;
   for (int w = W - 1; w >= 0; --w) {
-    if ((uint32_t)win[w * ws] != 0u) {
+    if ((uint32_t)win[map(w)] != 0u) {
       top = w;
       break;
     }
   }
-  return limbs_round<L>(win, top + 1, sgn, base, st, ws);
+  return limbs_round_map<L>(win, map, top + 1, sgn, base, st);
+}
+
+template <int L>
+MPD Num<L> window_finalize(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
+  return window_finalize_map<L>(win, StrideMap{ws}, W, base, st);
 }
 
 }  // namespace mp
@@ -317,6 +347,16 @@ MPD Num<L> reg_round(const RegWindow<WMAX>& R, int64_t base, uint32_t& st) {
   }
   out.e = (int32_t)e;
   return out;
+}
+
+template <int L, int WMAX>
+MPD Num<L> lane_window_round(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
+  RegWindow<WMAX> R;
+  reg_normalize<WMAX>(win, ws, W, R);
+#pragma unroll
+  for (int w = 0; w < WMAX; ++w)
+    if (w < W) win[w * ws] = (int64_t)R.limb[w];
+  return limbs_round<L>(win, R.nl, R.neg, base, st, ws);
 }
 
 }  // namespace mp

@@ -7,6 +7,8 @@
 // their prefix sum, and a gather of the values into structure-of-arrays order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstring>
 #include <rocprim/rocprim.hpp>
 
@@ -89,7 +91,20 @@ int plan_free(mp_plan* P) {
   hipFree(P->row_of);
   hipFree(P->t_limb);
   hipFree(P->t_hdr);
+  hipFree(P->x_rec);
   delete P;
+  return MPS_OK;
+}
+
+int plan_x_rec(mp_plan* P) {
+  if (P->x_rec) return MPS_OK;
+  const int S = P->L >= 16 ? 32 : (P->L >= 8 ? 16 : 8);
+  const int64_t n = std::max<int64_t>(1, std::max(P->n_rows, P->n_cols));
+  hipError_t e = hipMalloc((void**)&P->x_rec, (size_t)n * S * 4);
+  if (e != hipSuccess) {
+    P->x_rec = nullptr;
+    return fail(MPS_ENOMEM, "staged x buffer: %s", hipGetErrorString(e));
+  }
   return MPS_OK;
 }
 
@@ -213,6 +228,98 @@ int grad_vals_launch(const mp_csr* A, const mp_plan* P, const mp_vec* g, const m
 
 using namespace mpapi;
 
+namespace {
+
+// Time every rows-per-block variant of the four products (A and A^T, both modes) on a random
+// operand and keep the fastest; every variant computes the same bits, so only speed changes.
+template <int L>
+__global__ void tune_fill_kernel(uint32_t* limb, int32_t* hdr, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t h = 0x9e3779b97f4a7c15ull * (uint64_t)(i + 1);
+    for (int k = 0; k < L; ++k) {
+      h ^= h >> 29;
+      h *= 0xbf58476d1ce4e5b9ull;
+      h ^= h >> 32;
+      limb[(int64_t)k * n + i] = (uint32_t)h | (k == L - 1 ? 0x80000000u : 0u);
+    }
+    const int32_t e = -(int32_t)((h >> 40) & 15);
+    hdr[i] = (int32_t)(((uint32_t)e << 1) | (uint32_t)((h >> 50) & 1));
+  }
+}
+
+int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream_t s) {
+  const int L = P->L;
+  const int64_t nmax = std::max<int64_t>(1, std::max(P->n_rows, P->n_cols));
+  uint32_t *xl = nullptr, *yl = nullptr;
+  int32_t *xh = nullptr, *yh = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Free {
+    uint32_t **a, **b;
+    int32_t **c, **d;
+    hipEvent_t *e, *f;
+    ~Free() {
+      hipFree(*a); hipFree(*b); hipFree(*c); hipFree(*d);
+      if (*e) hipEventDestroy(*e);
+      if (*f) hipEventDestroy(*f);
+    }
+  } fr{&xl, &yl, &xh, &yh, &e0, &e1};
+  hipError_t e = hipMalloc((void**)&xl, (size_t)L * nmax * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&yl, (size_t)L * nmax * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&xh, (size_t)nmax * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&yh, (size_t)nmax * 4);
+  if (e != hipSuccess) return fail(MPS_ENOMEM, "tune workspace: %s", hipGetErrorString(e));
+  int r0 = plan_x_rec(P);
+  if (r0) return r0;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    return hip_fail(e, "tune events");
+  const unsigned g = (unsigned)std::min<int64_t>(4096, (nmax + 255) / 256);
+  switch (L) {
+    case 4: hipLaunchKernelGGL(tune_fill_kernel<4>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+    case 8: hipLaunchKernelGGL(tune_fill_kernel<8>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+    default: hipLaunchKernelGGL(tune_fill_kernel<16>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+  }
+  mp_vec tv{P->t_limb, P->t_hdr, P->nnz, P->nnz};
+  for (int op = 0; op < 2; ++op) {
+    const int64_t rows = op ? P->n_cols : P->n_rows, cols = op ? P->n_rows : P->n_cols;
+    const int32_t* rp = op ? P->t_row_ptr : A->row_ptr;
+    const int32_t* ci = op ? P->t_col_idx : A->col_idx;
+    const mp_vec& val = op ? tv : A->val;
+    mp_vec xv{xl, xh, cols, nmax}, yv{yl, yh, rows, nmax};
+    for (int mode = 0; mode < 2; ++mode) {
+      float best = 0.f;
+      int pick = default_rows_per_block(rows, P->nnz), pick_stage = 0;
+      for (int stage = 0; stage < 2; ++stage) {
+        uint32_t* rec = stage ? P->x_rec : nullptr;
+        for (int rpw : {16, 32, 64}) {
+          int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
+                               nullptr, rpw, rec, cols);
+          if (rr) return rr;
+          if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "tune");
+          for (int k = 0; k < reps; ++k)
+            if ((rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
+                                  nullptr, rpw, rec, cols)))
+              return rr;
+          if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+            return hip_fail(e, "tune");
+          float ms = 0.f;
+          if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return hip_fail(e, "tune");
+          if (best == 0.f || ms < best) {
+            best = ms;
+            pick = rpw;
+            pick_stage = stage;
+          }
+        }
+      }
+      P->rpw[op][mode] = pick;
+      P->stage[op][mode] = pick_stage != 0;
+    }
+  }
+  return MPS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mp_plan_create(const mp_csr* A, void* stream, mp_plan** plan) {
@@ -256,8 +363,48 @@ int mpspmv_csr_t(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp
   tv.hdr = plan->t_hdr;
   tv.len = plan->nnz;
   tv.ld = plan->nnz;
+  const bool stage = plan->stage[1][mode] && plan->x_rec;
   return spmv_launch(L, A->col_dim, plan->t_row_ptr, plan->t_col_idx, tv, *x, *y, mode,
-                     ctx->status, nullptr, (hipStream_t)stream);
+                     ctx->status, nullptr, (hipStream_t)stream, nullptr, nullptr,
+                     plan->rpw[1][mode], stage ? plan->x_rec : nullptr, A->row_dim);
+}
+
+int mp_plan_set_variant(mp_plan* plan, int op, int mode, int rows_per_block, int stage_x) {
+  clear_error();
+  if (!plan) return fail(MPS_EINVAL, "null plan");
+  if (op != 0 && op != 1) return fail(MPS_EINVAL, "op must be 0 (A) or 1 (A^T)");
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if (rows_per_block != 0 && !valid_rows_per_block(rows_per_block))
+    return fail(MPS_EINVAL, "rows per block must be 0, 16, 32 or 64");
+  if (stage_x) {
+    int r = plan_x_rec(plan);
+    if (r) return r;
+  }
+  plan->rpw[op][mode] = rows_per_block;
+  plan->stage[op][mode] = stage_x != 0;
+  return MPS_OK;
+}
+
+int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_block, int* stage_x) {
+  clear_error();
+  if (!plan || !rows_per_block || !stage_x) return fail(MPS_EINVAL, "null argument");
+  if (op != 0 && op != 1) return fail(MPS_EINVAL, "op must be 0 (A) or 1 (A^T)");
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  const int64_t rows = op ? plan->n_cols : plan->n_rows;
+  *rows_per_block = plan->rpw[op][mode] ? plan->rpw[op][mode] : default_rows_per_block(rows, plan->nnz);
+  *stage_x = (plan->stage[op][mode] && plan->x_rec) ? 1 : 0;
+  return MPS_OK;
+}
+
+int mp_plan_tune(mp_plan* plan, const mp_csr* A, int reps, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  if (reps <= 0) reps = 3;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  return tune_impl(plan, A, reps, ctx->status, (hipStream_t)stream);
 }
 
 int mp_grad_vals(const mp_csr* A, const mp_plan* plan, const mp_vec* g, const mp_vec* x,

@@ -13,7 +13,15 @@ struct mp_plan {
   int32_t* row_of = nullptr;     // [nnz] row of each entry of A
   uint32_t* t_limb = nullptr;    // [L][nnz] values of A^T
   int32_t* t_hdr = nullptr;      // [nnz]
+  int rpw[2][2] = {{0, 0}, {0, 0}};  // SpMV rows per block for [A, A^T][mode]; 0: by shape
+  bool stage[2][2] = {{false, false}, {false, false}};  // stage x as records for [op][mode]
+  uint32_t* x_rec = nullptr;     // [max(n_rows, n_cols)] staged x records (allocated on demand)
 };
+
+namespace mpapi {
+// allocate the plan's staged-x buffer if it has none
+int plan_x_rec(mp_plan* P);
+}
 
 namespace mpapi {
 int plan_build(const mp_csr* A, hipStream_t s, mp_plan** out);

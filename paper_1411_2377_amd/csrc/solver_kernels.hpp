@@ -255,7 +255,8 @@ constexpr int kAnchorBins = 64;
 struct DotWork {
   int32_t* anchor;    // [nslots][kAnchorBins][2]: emin, emax; (INT32_MAX, INT32_MIN) when empty
   int64_t* win;       // [nslots][win_stride] carry-save digits, zero between uses
-  uint32_t* ticket;   // [nslots + 1]; the last one counts finished inner products of a launch
+  uint32_t* ticket;   // [nslots + number of solves]: entry nslots + k counts the finished blocks
+                      // of solve k's current launch
   int64_t win_stride; // >= dot_shared_digits<L>()
   int nslots;
 };
@@ -313,6 +314,40 @@ struct DotArgs {
   BatchMap batch;  // batch.pair_of_tile == nullptr: one solve
 };
 
+// Anchor (smallest and largest e_x + e_y) of inner-product slot `slot`, its bins reduced by one
+// wave; every lane gets it.
+static_assert(kAnchorBins == 64, "one anchor bin per lane");
+MPD void wave_anchor(const int32_t* anchor, int64_t slot, int32_t& emin, int32_t& emax) {
+  const int32_t* b = anchor + 2 * (slot * kAnchorBins + (threadIdx.x & 63));
+  emin = wave_min(ld_dev(b));
+  emax = wave_max(ld_dev(b + 1));
+}
+
+// The two elements a thread takes per step: headers and limbs are loaded together (the limbs of
+// a zero are loaded too, so no load waits for a header).
+template <int L>
+struct DotElems {
+  int32_t hx[2], hy[2];
+  uint32_t x[2][L], y[2][L];
+};
+
+template <int L>
+MPD void dot_load(DotElems<L>& E, const VecRef& X, const VecRef& Y, int64_t i0, int64_t i1, bool h0,
+                  bool h1) {
+  const int32_t z = (int32_t)0x80000000;  // +0
+  E.hx[0] = h0 ? X.hdr[i0] : z;
+  E.hy[0] = h0 ? Y.hdr[i0] : z;
+  E.hx[1] = h1 ? X.hdr[i1] : z;
+  E.hy[1] = h1 ? Y.hdr[i1] : z;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    E.x[0][q] = h0 ? X.limb[(int64_t)q * X.ld + i0] : 0u;
+    E.y[0][q] = h0 ? Y.limb[(int64_t)q * Y.ld + i0] : 0u;
+    E.x[1][q] = h1 ? X.limb[(int64_t)q * X.ld + i1] : 0u;
+    E.y[1][q] = h1 ? Y.limb[(int64_t)q * Y.ld + i1] : 0u;
+  }
+}
+
 template <int L>
 __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   constexpr int WF = window_fast_digits<L>();
@@ -320,7 +355,6 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   constexpr int WMAXF = 2 * L + 16;  // final windows up to this size are carried in registers
   __shared__ int64_t s_win[WB];
   __shared__ uint32_t s_last;
-  __shared__ int32_t s_anc[2][kDotThreads / 64];
   // batch: block = one tile of one solve; otherwise a grid-stride pass over the whole vector
   const bool batched = A.batch.pair_of_tile != nullptr;
   const int pair = batched ? A.batch.pair_of_tile[blockIdx.x] : 0;
@@ -330,35 +364,25 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   const int t = threadIdx.x;
   uint32_t st = 0;
   const int d = blockIdx.y;  // the inner products of one launch run side by side, one row each
-  const int slot = pair * kDotSlots + A.slot[d];
+  const int64_t slot0 = (int64_t)pair * kDotSlots;
   const unsigned nblocks = batched ? (unsigned)A.batch.tiles_of_pair[pair] : gridDim.x;
-  int32_t* abins = A.w.anchor + 2 * (int64_t)slot * kAnchorBins;
-  int32_t emin = INT32_MAX, emax = INT32_MIN;
-  if (t < kAnchorBins) {
-    emin = ld_dev(&abins[2 * t]);
-    emax = ld_dev(&abins[2 * t + 1]);
-  }
-  emin = wave_min(emin);
-  emax = wave_max(emax);
-  if ((t & 63) == 0) {
-    s_anc[0][t >> 6] = emin;
-    s_anc[1][t >> 6] = emax;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kDotThreads / 64; ++k) {
-    emin = min(emin, s_anc[0][k]);
-    emax = max(emax, s_anc[1][k]);
-  }
-  int64_t* gw = A.w.win + (int64_t)slot * A.w.win_stride;
+
+  // first elements in flight while the anchor is reduced
+  const VecRef X = A.x[d], Y = A.y[d];
+  const int64_t stride = batched ? (int64_t)(kTile / 2) : (int64_t)gridDim.x * kDotThreads;
+  const int64_t n_end = batched ? (int64_t)(blockIdx.x + 1) * kTile : A.n;
+  int64_t i0 = batched ? (int64_t)blockIdx.x * kTile + t : (int64_t)blockIdx.x * kDotThreads + t;
+  DotElems<L> E;
+  dot_load<L>(E, X, Y, i0, i0 + stride, i0 < n_end, i0 + stride < n_end);
+
+  int32_t emin, emax;
+  wave_anchor(A.w.anchor, slot0 + A.slot[d], emin, emax);
+  int64_t* gw = A.w.win + (slot0 + A.slot[d]) * A.w.win_stride;
   const bool any = emax >= emin;
   const int W = any ? window_digits<L>(emin, emax) : 0;
   const bool fits = W <= WB && W <= A.w.win_stride;
   if (any && !fits) st |= kStWindow;
   if (any && fits) {
-    const VecRef X = A.x[d], Y = A.y[d];
-    const int64_t stride = batched ? (int64_t)(kTile / 2) : (int64_t)gridDim.x * kDotThreads;
-    const int64_t n_end = batched ? (int64_t)(blockIdx.x + 1) * kTile : A.n;
     const bool fast = W <= WF;
     if (fast) {
       for (int w = 0; w < WF; ++w) s_win[w * kDotStride + t] = 0;
@@ -366,38 +390,21 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
       for (int w = t; w < W; w += kDotThreads) s_win[w] = 0;
       __syncthreads();
     }
-    // products, two elements at a time: both headers, then both limb sets in flight together
-    const int64_t i_first = batched ? (int64_t)blockIdx.x * kTile + t : (int64_t)blockIdx.x * kDotThreads + t;
-    for (int64_t i0 = i_first; i0 < n_end; i0 += 2 * stride) {
-      const int64_t i1 = i0 + stride;
-      const bool has1 = i1 < n_end;
-      const int32_t hx0 = X.hdr[i0], hy0 = Y.hdr[i0];
-      const int32_t hx1 = has1 ? X.hdr[i1] : (int32_t)0x80000000;
-      const int32_t hy1 = has1 ? Y.hdr[i1] : (int32_t)0x80000000;
-      const bool nz0 = !hdr_is_zero(hx0) && !hdr_is_zero(hy0);
-      const bool nz1 = !hdr_is_zero(hx1) && !hdr_is_zero(hy1);
-      uint32_t x0[L], y0[L], x1[L], y1[L];
+    while (true) {
 #pragma unroll
-      for (int q = 0; q < L; ++q) {
-        x0[q] = nz0 ? X.limb[(int64_t)q * X.ld + i0] : 0u;
-        y0[q] = nz0 ? Y.limb[(int64_t)q * Y.ld + i0] : 0u;
-        x1[q] = nz1 ? X.limb[(int64_t)q * X.ld + i1] : 0u;
-        y1[q] = nz1 ? Y.limb[(int64_t)q * Y.ld + i1] : 0u;
+      for (int k = 0; k < 2; ++k) {
+        if (!hdr_is_zero(E.hx[k]) && !hdr_is_zero(E.hy[k])) {
+          uint32_t pr[2 * L];
+          mul_full<L>(E.x[k], E.y[k], pr);
+          const uint32_t off = (uint32_t)((E.hx[k] >> 1) + (E.hy[k] >> 1) - emin);
+          const uint32_t sg = (uint32_t)(E.hx[k] ^ E.hy[k]) & 1u;
+          if (fast) window_add<L>(s_win + t, kDotStride, pr, sg, off);
+          else window_add_atomic<L>(s_win, pr, sg, off);
+        }
       }
-      if (nz0) {
-        uint32_t pr[2 * L];
-        mul_full<L>(x0, y0, pr);
-        const uint32_t off = (uint32_t)((hx0 >> 1) + (hy0 >> 1) - emin);
-        if (fast) window_add<L>(s_win + t, kDotStride, pr, (uint32_t)(hx0 ^ hy0) & 1u, off);
-        else window_add_atomic<L>(s_win, pr, (uint32_t)(hx0 ^ hy0) & 1u, off);
-      }
-      if (nz1) {
-        uint32_t pr[2 * L];
-        mul_full<L>(x1, y1, pr);
-        const uint32_t off = (uint32_t)((hx1 >> 1) + (hy1 >> 1) - emin);
-        if (fast) window_add<L>(s_win + t, kDotStride, pr, (uint32_t)(hx1 ^ hy1) & 1u, off);
-        else window_add_atomic<L>(s_win, pr, (uint32_t)(hx1 ^ hy1) & 1u, off);
-      }
+      i0 += 2 * stride;
+      if (i0 >= n_end) break;
+      dot_load<L>(E, X, Y, i0, i0 + stride, true, i0 + stride < n_end);
     }
     __syncthreads();
     if (fast) {
@@ -431,66 +438,94 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
     }
   }
 
-  // the window atomics of every wave are complete before the ticket is taken; the last block
-  // then reads the window with atomics, so no cache write-back or invalidate is needed
+  // One ticket per launch (per solve in a batch) counts the blocks of every inner product; the
+  // window atomics of every wave are complete before it is taken, and the last block reads the
+  // windows with atomics, so no cache write-back or invalidate is needed.
   wait_memory();
   __syncthreads();
-  if (t == 0) s_last = (atomicAdd(&A.w.ticket[slot], 1u) == nblocks - 1) ? 1u : 0u;
+  uint32_t* ticket = A.w.ticket + A.w.nslots + pair;
+  if (t == 0) s_last = (atomicAdd(ticket, 1u) == nblocks * (unsigned)A.nd - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) {
     if (st) atomicOr(A.status, st);
     return;
   }
-  // last block of this inner product: take the window back (clearing it), round once
-  Num<L> res;
-  set_zero(res, 0);
-  if (any && fits && W <= 63) {
-    // one digit per lane of the first wave, rounded by the whole wave
-    if (t < 64) {
-      const int64_t dg = (t < W) ? (int64_t)atomicExch((unsigned long long*)&gw[t], 0ull) : 0;
-      res = wave_round<L>(dg, (int64_t)emin - 64 * L, st);
-    }
-  } else if (any && fits) {
-    for (int w = t; w < W; w += kDotThreads)
-      s_win[w] = (int64_t)atomicExch((unsigned long long*)&gw[w], 0ull);
-    __syncthreads();
-    if (t == 0) {
-      if (W <= WMAXF) {
-        RegWindow<WMAXF> R;
-        reg_normalize<WMAXF>(s_win, 1, W, R);
+
+  // The last block: wave k rounds inner products k and k + 4 when their windows have at most 63
+  // digits (one per lane); wider windows are rounded afterwards by the whole block.
+  const int wv = t >> 6, lane = t & 63;
+  int32_t amin[kDotMaxND], amax[kDotMaxND];
 #pragma unroll
-        for (int w = 0; w < WMAXF; ++w)
-          if (w < W) s_win[w] = (int64_t)R.limb[w];
-        res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)emin - 64 * L, st);
-      } else {
-        res = window_finalize<L>(s_win, 1, W, (int64_t)emin - 64 * L, st);
-      }
+  for (int dd = 0; dd < kDotMaxND; ++dd) {
+    amin[dd] = INT32_MAX;
+    amax[dd] = INT32_MIN;
+    if (dd < A.nd) wave_anchor(A.w.anchor, slot0 + A.slot[dd], amin[dd], amax[dd]);
+  }
+  __syncthreads();  // every wave has its anchors: the bins may be reset
+#pragma unroll
+  for (int dd = 0; dd < kDotMaxND; ++dd) {
+    if (dd < A.nd && wv == 0) {
+      int32_t* b = A.w.anchor + 2 * ((slot0 + A.slot[dd]) * kAnchorBins + lane);
+      st_dev(b, INT32_MAX);
+      st_dev(b + 1, INT32_MIN);
     }
   }
-  if (t < kAnchorBins) {
-    st_dev(&abins[2 * t], INT32_MAX);
-    st_dev(&abins[2 * t + 1], INT32_MIN);
-  }
-  if (t == 0) {
-    VecRef o = A.out[d];  // batch: a scalar slot of solve 0, moved to this solve's slots
+#pragma unroll
+  for (int dd = 0; dd < kDotMaxND; ++dd) {
+    if (dd >= A.nd) break;
+    const bool anyd = amax[dd] >= amin[dd];
+    const int Wd = anyd ? window_digits<L>(amin[dd], amax[dd]) : 0;
+    const bool fitsd = Wd <= WB && Wd <= A.w.win_stride;
+    VecRef o = A.out[dd];  // batch: a scalar slot of solve 0, moved to this solve's slots
     if (batched) {
       o.limb += (int64_t)pair * kNumScalars;
       o.hdr += (int64_t)pair * kNumScalars;
     }
-    store_dev<L>(res, o.limb, o.hdr, o.ld, 0);  // the epilogue below may run in another block
-    st_dev(&A.w.ticket[slot], 0u);
-    if (ctl && st) atomicOr(&ctl->flags, st);
-    // the last inner product of the launch (of this solve) to finish runs the driver epilogue
-    wait_memory();
-    if (atomicAdd(&A.w.ticket[A.w.nslots + pair], 1u) == (unsigned)A.nd - 1) {
-      uint32_t st2 = 0;
-      const int was_done = ctl ? ctl->done : 0;
-      epilogue<L>(A.epi, S, ctl, A.hist, st2);
-      st_dev(&A.w.ticket[A.w.nslots + pair], 0u);
-      if (ctl && st2) atomicOr(&ctl->flags, st2);
-      if (A.batch.ndone && ctl && !was_done && ctl->done) atomicAdd(A.batch.ndone, 1);
-      st |= st2;
+    int64_t* gwd = A.w.win + (slot0 + A.slot[dd]) * A.w.win_stride;
+    if (wv == (dd & 3)) {
+      if (anyd && fitsd && Wd <= 63) {
+        const int64_t dg = (lane < Wd) ? (int64_t)atomicExch((unsigned long long*)&gwd[lane], 0ull) : 0;
+        const Num<L> res = wave_round<L>(dg, (int64_t)amin[dd] - 64 * L, st);
+        if (lane == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+      } else if (!(anyd && fitsd) && lane == 0) {
+        Num<L> res;
+        set_zero(res, 0);
+        store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+      }
     }
+    if (anyd && fitsd && Wd > 63) {  // block-uniform
+      __syncthreads();
+      for (int w = t; w < Wd; w += kDotThreads)
+        s_win[w] = (int64_t)atomicExch((unsigned long long*)&gwd[w], 0ull);
+      __syncthreads();
+      if (t == 0) {
+        Num<L> res;
+        if (Wd <= WMAXF) {
+          RegWindow<WMAXF> R;
+          reg_normalize<WMAXF>(s_win, 1, Wd, R);
+#pragma unroll
+          for (int w = 0; w < WMAXF; ++w)
+            if (w < Wd) s_win[w] = (int64_t)R.limb[w];
+          res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)amin[dd] - 64 * L, st);
+        } else {
+          res = window_finalize<L>(s_win, 1, Wd, (int64_t)amin[dd] - 64 * L, st);
+        }
+        store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+      }
+    }
+  }
+  if (ctl && st) atomicOr(&ctl->flags, st);
+  // every result is stored before the epilogue reads them
+  wait_memory();
+  __syncthreads();
+  if (t == 0) {
+    st_dev(ticket, 0u);
+    uint32_t st2 = 0;
+    const int was_done = ctl ? ctl->done : 0;
+    epilogue<L>(A.epi, S, ctl, A.hist, st2);
+    if (ctl && st2) atomicOr(&ctl->flags, st2);
+    if (A.batch.ndone && ctl && !was_done && ctl->done) atomicAdd(A.batch.ndone, 1);
+    st |= st2;
   }
   if (st) atomicOr(A.status, st);
 }

@@ -27,6 +27,31 @@ constexpr int kRowsPerBlock = 64;
 template <int L>
 constexpr int chunk_entries() { return 2048 / L; }
 
+// Words per staged x record: the L limbs and the header, padded to a power of two so that a
+// record sits in one cache line and loads as whole 16-byte pieces.
+template <int L>
+constexpr int x_rec_words() { return L >= 16 ? 32 : (L >= 8 ? 16 : 8); }
+
+// x_rec[i] = (limbs of x_i, header of x_i)
+template <int L>
+__global__ void __launch_bounds__(256) x_stage_kernel(const uint32_t* __restrict__ limb,
+                                                      const int32_t* __restrict__ hdr, int64_t ld,
+                                                      int64_t n, uint32_t* __restrict__ rec) {
+  constexpr int S = x_rec_words<L>();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t w[L + 4];
+#pragma unroll
+    for (int q = 0; q < L; ++q) w[q] = limb[(int64_t)q * ld + i];
+    w[L] = (uint32_t)hdr[i];
+    w[L + 1] = w[L + 2] = w[L + 3] = 0u;
+    uint4* out = reinterpret_cast<uint4*>(rec + i * S);
+#pragma unroll
+    for (int q = 0; q < (L + 4) / 4; ++q) out[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+  }
+}
+
+
 struct SpmvArgs {
   int64_t n_rows;
   const int32_t* row_ptr;
@@ -48,6 +73,9 @@ struct SpmvArgs {
   const int32_t* pair_hdr[3];
   int pair_slot[3];
   int32_t* anchor;
+  // x staged as one record per element (limbs then header, x_rec_words<L>() words apart), or
+  // nullptr: x is read in its own layout
+  const uint32_t* x_rec;
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
@@ -57,19 +85,21 @@ struct SpmvArgs {
   int slots_per_pair;
 };
 
-// Row block, right-hand side and solve of this block; false if that solve is finished.
+// Row block (RPW rows), right-hand side and solve of this block; false if that solve is
+// finished.  RPW divides 512, so a block's rows lie in one solve's tile.
 struct SpmvBlock {
   int64_t rb;
   int rhs;
   int pair;
 };
 
+template <int RPW>
 MPD bool spmv_block(const SpmvArgs& A, SpmvBlock& B) {
   B.rhs = (int)(blockIdx.x % (unsigned)A.nrhs);
   B.rb = (int64_t)(blockIdx.x / (unsigned)A.nrhs);
   B.pair = 0;
   if (A.pair_of_tile) {
-    B.pair = A.pair_of_tile[(B.rhs * A.y_rstride + B.rb * 64) / 512];
+    B.pair = A.pair_of_tile[(B.rhs * A.y_rstride + B.rb * RPW) / 512];
     if (*(volatile const int32_t*)&A.done_base[B.pair * A.done_stride]) return false;
   } else if (A.done && *(volatile const int32_t*)A.done) {
     return false;
@@ -126,22 +156,82 @@ MPD void pair_publish(const SpmvArgs& A, PairAcc& P, int pair) {
   }
 }
 
+// x_j's header and limbs, from the staged records when there are any
 template <int L>
-__global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
-  constexpr int kChunk = chunk_entries<L>();
+MPD void load_x(const SpmvArgs& A, const uint32_t* x_limb, const int32_t* x_hdr, int32_t col,
+                bool want_limbs, int32_t& hx, uint32_t (&xm)[L]) {
+  if (A.x_rec) {
+    const uint4* r = reinterpret_cast<const uint4*>(A.x_rec + (int64_t)col * x_rec_words<L>());
+#pragma unroll
+    for (int q = 0; q < L / 4; ++q) {
+      const uint4 v = r[q];
+      xm[4 * q] = v.x;
+      xm[4 * q + 1] = v.y;
+      xm[4 * q + 2] = v.z;
+      xm[4 * q + 3] = v.w;
+    }
+    hx = (int32_t)A.x_rec[(int64_t)col * x_rec_words<L>() + L];
+  } else {
+    hx = x_hdr[col];
+#pragma unroll
+    for (int q = 0; q < L; ++q) xm[q] = want_limbs ? x_limb[(int64_t)q * A.x_ld + col] : 0u;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Entry loads: a lane takes K entries of a chunk at once.  The column, header and (for a non-zero
+// entry) the limbs of a_k are requested first, then x's header and limbs at that column, so every
+// lane has 2K independent loads in flight per round trip instead of one chain per entry.  Stored
+// zeros cost only their header and column (their limbs and x's limbs are not read).
+// ------------------------------------------------------------------------------------------
+template <int L>
+constexpr int spmv_kper() { return L >= 16 ? 1 : 2; }
+
+template <int L, int K>
+struct EntryLoad {
+  int32_t col[K], ha[K], hx[K];
+  uint32_t am[K][L], xm[K][L];
+};
+
+template <int L, int K>
+MPD void load_entries(EntryLoad<L, K>& E, const SpmvArgs& A, const uint32_t* x_limb,
+                      const int32_t* x_hdr, const int64_t (&k)[K], const bool (&ok)[K]) {
+  const int32_t z = (int32_t)0x80000000;  // +0
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    E.col[i] = ok[i] ? A.col_idx[k[i]] : 0;
+    E.ha[i] = ok[i] ? A.a_hdr[k[i]] : z;
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const bool nz = !hdr_is_zero(E.ha[i]);
+#pragma unroll
+    for (int q = 0; q < L; ++q) E.am[i][q] = nz ? A.a_limb[(int64_t)q * A.a_ld + k[i]] : 0u;
+    if (ok[i]) {
+      load_x<L>(A, x_limb, x_hdr, E.col[i], nz, E.hx[i], E.xm[i]);
+    } else {
+      E.hx[i] = z;
+    }
+  }
+}
+
+template <int L, int RPW>
+__global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
+  constexpr int K = spmv_kper<L>();
+  constexpr int kChunk = 64 * K;
   __shared__ int32_t s_rp[kRowsPerBlock + 1];
   __shared__ uint32_t s_m[L][kChunk];
   __shared__ int32_t s_e[kChunk];
   __shared__ uint32_t s_s[kChunk];
 
   SpmvBlock B;
-  if (!spmv_block(A, B)) return;
+  if (!spmv_block<RPW>(A, B)) return;
   const int lane = threadIdx.x;
-  const int64_t r0 = B.rb * kRowsPerBlock;
+  const int64_t r0 = B.rb * RPW;
   const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
   const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
   const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
-  const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);
+  const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
   for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
   __syncthreads();
   const int kb = s_rp[0], ke = s_rp[nr];
@@ -154,21 +244,27 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
 
   for (int c0 = kb; c0 < ke; c0 += kChunk) {
     const int cn = min(kChunk, ke - c0);
-    for (int j = lane; j < cn; j += 64) {
-      const int64_t k = c0 + j;
-      const int32_t ha = A.a_hdr[k];
-      const int32_t col = A.col_idx[k];
-      const int32_t hx = x_hdr[col];
+    // phase 1: rounded products of the chunk, staged in LDS
+    int64_t k[K];
+    bool ok[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      ok[i] = lane + 64 * i < cn;
+      k[i] = (int64_t)c0 + lane + 64 * i;
+    }
+    EntryLoad<L, K> E;
+    load_entries<L, K>(E, A, x_limb, x_hdr, k, ok);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (!ok[i]) continue;
+      const int j = lane + 64 * i;
+      const int32_t ha = E.ha[i], hx = E.hx[i];
       Num<L> t;
       if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
         set_zero(t, (uint32_t)(ha ^ hx) & 1u);
       } else {
-        uint32_t am[L], xm[L], pr[2 * L];
-#pragma unroll
-        for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
-#pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
-        mul_full<L>(am, xm, pr);
+        uint32_t pr[2 * L];
+        mul_full<L>(E.am[i], E.xm[i], pr);
         round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, t, st);
       }
 #pragma unroll
@@ -177,9 +273,10 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
       s_s[j] = t.s;
     }
     __syncthreads();
+    // phase 2: each lane adds its row's products in storage order
     const int lo = max(rs, c0), hi = min(re, c0 + cn);
-    for (int k = lo; k < hi; ++k) {
-      const int j = k - c0;
+    for (int kk = lo; kk < hi; ++kk) {
+      const int j = kk - c0;
       Num<L> t;
 #pragma unroll
       for (int q = 0; q < L; ++q) t.m[q] = s_m[q][j];
@@ -199,136 +296,244 @@ __global__ void __launch_bounds__(64) spmv_seq_kernel(SpmvArgs A) {
   if (st) atomicOr(A.status, st);
 }
 
+// ------------------------------------------------------------------------------------------
+// EXACT.  Every row's products are added, exactly, into a ring window of R int64 digits in LDS
+// (carry-save: plain integer adds, so their order never matters).  Digit d of the exact sum has
+// weight 2^(32 d - 2p) and lives in ring slot d mod R; a product with exponent e covers digits
+// e >> 5 ... (e >> 5) + 2L.  The ring needs no base chosen in advance: it stays exact as long as
+// the row's products span at most R digits (counting two of headroom), which each row checks
+// from its exponent range once its products are in.
+//
+// Rows of at most kShortRow entries: all lanes take the block's short-row entries in order (long
+// rows left out; coalesced loads), form the exact products and add them straight into the
+// owner row's ring with LDS atomics, keeping the row's exponent range with LDS atomic min/max.
+// Nothing is staged and no lane walks a row alone, so the work is spread evenly whatever the row
+// lengths.  Each row then rounds its ring once.
+//
+// Longer rows, one at a time, with the whole wave: lane l takes entries l, l + 64, ... into ring
+// column l mod RPW; the columns are summed digit by digit (one digit per lane) and rounded by
+// the wave.  A row whose products span more than a ring is redone in a block-shared window at its
+// exact exponent anchor (or raises kStWindow when even that is too narrow).
+// ------------------------------------------------------------------------------------------
+constexpr int kShortRow = 32;
+
+// Ring slot of digit d.
+template <int R>
+MPD int ring_slot(int32_t d) {
+  const int m = d % R;
+  return m < 0 ? m + R : m;
+}
+
+// Ring digits needed by products with exponents in [lo, hi].
 template <int L>
+MPD int ring_span(int32_t lo, int32_t hi) { return (hi >> 5) - (lo >> 5) + 2 * L + 2; }
+
+// Add (-1)^s * P * 2^(e mod 32) at ring digit e >> 5 (slots ws apart) with LDS atomics.
+template <int L, int R>
+MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, int32_t e) {
+  uint32_t sp[2 * L + 1];
+  shift_product<L>(P, (uint32_t)e & 31u, sp);
+  int slot = ring_slot<R>(e >> 5);
+#pragma unroll
+  for (int j = 0; j <= 2 * L; ++j) {
+    if (sp[j]) {
+      const uint64_t v = s ? (uint64_t)(-(int64_t)sp[j]) : (uint64_t)sp[j];
+      atomicAdd((unsigned long long*)&win[slot * ws], (unsigned long long)v);
+    }
+    slot = (slot == R - 1) ? 0 : slot + 1;
+  }
+}
+
+MPD int32_t wave_min32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+MPD int32_t wave_max32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int L, int RPW>
 __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
-  constexpr int WF = window_fast_digits<L>();
-  constexpr int WB = WF * 64;  // digits of the shared window used for wide rows
-  constexpr int kChunk = chunk_entries<L>();
-  __shared__ int32_t s_rp[kRowsPerBlock + 1];
-  __shared__ uint32_t s_p[2 * L][kChunk];
-  __shared__ int32_t s_e[kChunk];
-  __shared__ uint32_t s_s[kChunk];
-  __shared__ int64_t s_win[WF * 64];
+  constexpr int R = window_fast_digits<L>();  // ring digits per row
+  // digits of the block-shared exact window: the same for every variant, so that every variant
+  // accepts the same rows
+  constexpr int WB = R * 16;
+  static_assert(RPW >= 16, "the shared window lives in the ring area");
+  constexpr int K = spmv_kper<L>();
+  constexpr int kChunk = 64 * K;
+  __shared__ int32_t s_rp[RPW + 1];
+  __shared__ int32_t s_cp[65];          // compact (short-row) entry prefix
+  __shared__ uint8_t s_row[kChunk];     // row of each compact entry of the chunk
+  __shared__ int32_t s_lo[RPW], s_hi[RPW];
+  __shared__ int64_t s_win[R * RPW];    // ring slot d of row r at [d * RPW + r]
 
   SpmvBlock B;
-  if (!spmv_block(A, B)) return;
+  if (!spmv_block<RPW>(A, B)) return;
   const int lane = threadIdx.x;
-  const int64_t r0 = B.rb * kRowsPerBlock;
+  const int64_t r0 = B.rb * RPW;
   const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
   const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
   const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
-  const int nr = (int)min((int64_t)kRowsPerBlock, A.n_rows - r0);
+  const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
   for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
+  for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
+  if (lane < RPW) {
+    s_lo[lane] = INT32_MAX;
+    s_hi[lane] = INT32_MIN;
+  }
   __syncthreads();
-  const int kb = s_rp[0], ke = s_rp[nr];
   const bool has_row = lane < nr;
   const int rs = has_row ? s_rp[lane] : 0;
   const int re = has_row ? s_rp[lane + 1] : 0;
+  const bool is_short = has_row && re - rs <= kShortRow;
+  {  // compact positions of the short rows' entries
+    int v = is_short ? re - rs : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    s_cp[lane + 1] = v;
+    if (lane == 0) s_cp[0] = 0;
+  }
+  __syncthreads();
+  const int cs = s_cp[lane], ce = s_cp[lane + 1], ntot = s_cp[64];
   uint32_t st = 0;
 
-  // exponent range of this row's non-zero products
-  int32_t emin = INT32_MAX, emax = INT32_MIN;
-  for (int k = rs; k < re; ++k) {
-    const int32_t ha = A.a_hdr[k];
-    const int32_t hx = x_hdr[A.col_idx[k]];
-    if (!hdr_is_zero(ha) && !hdr_is_zero(hx)) {
-      const int32_t e = (ha >> 1) + (hx >> 1);
-      emin = min(emin, e);
-      emax = max(emax, e);
+  for (int c0 = 0; c0 < ntot; c0 += kChunk) {
+    const int cn = min(kChunk, ntot - c0);
+    for (int j = max(cs, c0); j < min(ce, c0 + cn); ++j) s_row[j - c0] = (uint8_t)lane;
+    __syncthreads();
+    int64_t k[K];
+    bool ok[K];
+    int row[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int j = lane + 64 * i;
+      ok[i] = j < cn;
+      row[i] = ok[i] ? s_row[j] : 0;
+      k[i] = (int64_t)s_rp[row[i]] + (c0 + j - s_cp[row[i]]);
     }
+    EntryLoad<L, K> E;
+    load_entries<L, K>(E, A, x_limb, x_hdr, k, ok);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (!ok[i] || hdr_is_zero(E.ha[i]) || hdr_is_zero(E.hx[i])) continue;
+      const int32_t e = (E.ha[i] >> 1) + (E.hx[i] >> 1);
+      atomicMin(&s_lo[row[i]], e);
+      atomicMax(&s_hi[row[i]], e);
+      uint32_t pr[2 * L];
+      mul_full<L>(E.am[i], E.xm[i], pr);
+      ring_add<L, R>(s_win + row[i], RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
+    }
+    __syncthreads();
   }
-  const bool any = emax >= emin;
-  const int W = any ? window_digits<L>(emin, emax) : 1;
-  const bool wide = any && (W > WF);
-  int64_t* mywin = s_win + lane;  // digit w at mywin[w * 64]
-  for (int w = 0; w < WF; ++w) mywin[w * 64] = 0;
 
-  for (int c0 = kb; c0 < ke; c0 += kChunk) {
-    const int cn = min(kChunk, ke - c0);
-    for (int j = lane; j < cn; j += 64) {
-      const int64_t k = c0 + j;
-      const int32_t ha = A.a_hdr[k];
-      const int32_t col = A.col_idx[k];
-      const int32_t hx = x_hdr[col];
-      if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
-        s_e[j] = INT32_MIN;
-      } else {
-        uint32_t am[L], xm[L], pr[2 * L];
-#pragma unroll
-        for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
-#pragma unroll
-        for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
-        mul_full<L>(am, xm, pr);
-#pragma unroll
-        for (int q = 0; q < 2 * L; ++q) s_p[q][j] = pr[q];
-        s_e[j] = (ha >> 1) + (hx >> 1);
-        s_s[j] = (uint32_t)(ha ^ hx) & 1u;
-      }
-    }
-    __syncthreads();
-    if (!wide) {
-      const int lo = max(rs, c0), hi = min(re, c0 + cn);
-      for (int k = lo; k < hi; ++k) {
-        const int j = k - c0;
-        const int32_t e = s_e[j];
-        if (e == INT32_MIN) continue;
-        uint32_t pr[2 * L];
-#pragma unroll
-        for (int q = 0; q < 2 * L; ++q) pr[q] = s_p[q][j];
-        window_add<L>(mywin, 64, pr, s_s[j], (uint32_t)(e - emin));
-      }
-    }
-    __syncthreads();
-  }
   Num<L> y;
   PairAcc P;
   pair_init(P);
-  if (has_row && !wide) {
-    if (any) {
-      y = window_finalize<L>(mywin, 64, W, (int64_t)emin - 64 * L, st);
-    } else {
+  bool wide = false;
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  if (is_short) {
+    lo = s_lo[lane];
+    hi = s_hi[lane];
+    if (lo == INT32_MAX) {
       set_zero(y, 0);
+    } else if (ring_span<L>(lo, hi) <= R) {
+      y = window_finalize_map<L>(s_win + lane, RingMap<R>{RPW, ring_slot<R>(lo >> 5)},
+                                 ring_span<L>(lo, hi), 32 * (int64_t)(lo >> 5) - 64 * L, st);
+    } else {
+      wide = true;
     }
-    store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
-    if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
+    if (!wide) {
+      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
+      if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
+    }
   }
 
-  // wide rows: the whole block shares one window
-  uint64_t pending = __ballot(has_row && wide);
+  uint64_t pending = __ballot(has_row && (!is_short || wide));
   while (pending) {
     const int owner = __ffsll((unsigned long long)pending) - 1;
     pending &= pending - 1;
-    __syncthreads();
     const int o_rs = s_rp[owner], o_re = s_rp[owner + 1];
-    const int32_t o_emin = __shfl(emin, owner);
-    const int o_W = __shfl(W, owner);
-    if (o_W > WB) {
-      if (lane == owner) {
-        st |= kStWindow;
-        set_zero(y, 0);
-        store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
+    int32_t emin = __shfl(lo, owner), emax = __shfl(hi, owner);  // known for a wide short row
+    const bool known = __shfl(wide ? 1 : 0, owner) != 0;
+    __syncthreads();
+    Num<L> yr;
+    set_zero(yr, 0);
+    bool ring_ok = false;
+    if (!known) {
+      // lane rings: lane l adds into column l mod RPW
+      for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
+      __syncthreads();
+      int32_t llo = INT32_MAX, lhi = INT32_MIN;
+      for (int k0 = o_rs; k0 < o_re; k0 += kChunk) {
+        int64_t k[K];
+        bool ok[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          k[i] = (int64_t)k0 + lane + 64 * i;
+          ok[i] = k[i] < o_re;
+        }
+        EntryLoad<L, K> E;
+        load_entries<L, K>(E, A, x_limb, x_hdr, k, ok);
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          if (!ok[i] || hdr_is_zero(E.ha[i]) || hdr_is_zero(E.hx[i])) continue;
+          const int32_t e = (E.ha[i] >> 1) + (E.hx[i] >> 1);
+          llo = min(llo, e);
+          lhi = max(lhi, e);
+          uint32_t pr[2 * L];
+          mul_full<L>(E.am[i], E.xm[i], pr);
+          ring_add<L, R>(s_win + (lane % RPW), RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
+        }
       }
-      continue;
-    }
-    for (int w = lane; w < o_W; w += 64) s_win[w] = 0;
-    __syncthreads();
-    for (int k = o_rs + lane; k < o_re; k += 64) {
-      const int32_t ha = A.a_hdr[k];
-      const int32_t col = A.col_idx[k];
-      const int32_t hx = x_hdr[col];
-      if (hdr_is_zero(ha) || hdr_is_zero(hx)) continue;
-      uint32_t am[L], xm[L], pr[2 * L];
+      emin = wave_min32(llo);
+      emax = wave_max32(lhi);
+      __syncthreads();
+      if (emax >= emin && ring_span<L>(emin, emax) <= R) {
+        ring_ok = true;
+        int64_t dg = 0;
+        if (lane < ring_span<L>(emin, emax)) {
+          const int64_t* slot = s_win + ring_slot<R>((emin >> 5) + lane) * RPW;
 #pragma unroll
-      for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + k];
-#pragma unroll
-      for (int q = 0; q < L; ++q) xm[q] = x_limb[(int64_t)q * A.x_ld + col];
-      mul_full<L>(am, xm, pr);
-      window_add_atomic<L>(s_win, pr, (uint32_t)(ha ^ hx) & 1u,
-                           (uint32_t)((ha >> 1) + (hx >> 1) - o_emin));
+          for (int c = 0; c < RPW; ++c) dg += slot[c];
+        }
+        yr = wave_round<L>(dg, 32 * (int64_t)(emin >> 5) - 64 * L, st);
+      }
     }
-    __syncthreads();
+    if (!ring_ok && emax >= emin) {
+      // the row's products span more than a ring: a block-shared window at the exact anchor
+      const int W = window_digits<L>(emin, emax);
+      if (W <= WB) {
+        __syncthreads();
+        for (int w = lane; w < W; w += 64) s_win[w] = 0;
+        __syncthreads();
+        for (int kk = o_rs + lane; kk < o_re; kk += 64) {
+          const int32_t ha = A.a_hdr[kk];
+          const int32_t col = A.col_idx[kk];
+          int32_t hx;
+          uint32_t am[L], xm[L], pr[2 * L];
+          load_x<L>(A, x_limb, x_hdr, col, true, hx, xm);
+          if (hdr_is_zero(ha) || hdr_is_zero(hx)) continue;
+#pragma unroll
+          for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + kk];
+          mul_full<L>(am, xm, pr);
+          window_add_atomic<L>(s_win, pr, (uint32_t)(ha ^ hx) & 1u,
+                               (uint32_t)((ha >> 1) + (hx >> 1) - emin));
+        }
+        __syncthreads();
+        if (lane == owner) yr = window_finalize<L>(s_win, 1, W, (int64_t)emin - 64 * L, st);
+      } else if (lane == owner) {
+        st |= kStWindow;
+      }
+    }
     if (lane == owner) {
-      y = window_finalize<L>(s_win, 1, o_W, (int64_t)o_emin - 64 * L, st);
+      y = yr;
       store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
       if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
     }

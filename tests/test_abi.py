@@ -52,12 +52,12 @@ def test_host_validation_errors():
     # SpMV argument checks happen before any device work
     x = _lib.MpVec(5000, 6000, 3, 3)   # wrong length (col_dim = 4)
     y = _lib.MpVec(7000, 8000, 4, 4)
-    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 0, None) == _lib.MPS_EINVAL
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 0, None, None) == _lib.MPS_EINVAL
     x.len, x.ld = 4, 4
-    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 7, None) == _lib.MPS_EINVAL
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 7, None, None) == _lib.MPS_EINVAL
     assert "mode" in _lib.last_error()
     yy = _lib.MpVec(5000, 6000, 4, 4)   # aliases x
-    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(yy), 0, None) == _lib.MPS_EINVAL
+    assert _lib.LIB.mpspmv_csr(ctypes.byref(a), ctypes.byref(x), ctypes.byref(yy), 0, None, None) == _lib.MPS_EINVAL
     assert "overlap" in _lib.last_error()
 
 
@@ -98,3 +98,9 @@ def test_batched_solver_host_validation():
     x[1] = _lib.MpVec(3000, 4000, 4, 4)   # aliases b[1]
     assert f(2, a, 1, b, x, ctypes.byref(o), info, None) == _lib.MPS_EINVAL
     assert "overlap" in _lib.last_error()
+
+
+def test_variant_setter_validation():
+    from paper_1411_2377_amd import _lib
+    f = _lib.LIB.mp_plan_set_variant
+    assert f(None, 0, 0, 16, 0) == _lib.MPS_EINVAL

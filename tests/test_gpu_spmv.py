@@ -165,3 +165,41 @@ def test_empty_shapes():
                      torch.zeros(0, dtype=torch.int32, device="cuda"), M.MPArray.empty(0, p))
     M.mpspmv_csr(A0, x, mode=0)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_every_kernel_variant_same_bits(p):
+    """Each rows-per-block variant of y = A x and y = A^T x, in both modes, matches the oracle
+    bit for bit (edge-case matrix), and the tuner's pick changes nothing."""
+    from tests.util import decode_vec
+    from oracle import spmv as ospmv
+    M = lib()
+    A_h, x_h = edge_problem(p, seed=7 * p)
+    A = M.CSRMatrix.from_host(A_h)
+    x = M.MPArray.from_host(x_h)
+    rng = np.random.default_rng(p)
+    g_h = synth.mp_uniform(rng, A_h.n_rows, p)
+    g = M.MPArray.from_host(g_h)
+    P = M.mp_plan_create(A)
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    tp, ti, tv = ospmv.transpose(A_h.n_rows, A_h.n_cols, A_h.row_ptr.tolist(), A_h.col_idx.tolist(), vals)
+    go = decode_vec(g_h)
+    for mode in (0, 1):
+        want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
+        want_t = ospmv.spmv(tp, ti, tv, go, p, mode)
+        for rows in (16, 32, 64):
+            for stage in (False, True):
+                P.set_variant(0, mode, rows, stage)
+                P.set_variant(1, mode, rows, stage)
+                tag = "%d rows per block, staged x %s, mode %d" % (rows, stage, mode)
+                yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
+                assert_bitwise(yl, yh, want, p, what="A x, " + tag)
+                tl, th = M.mpspmv_csr_t(A, P, g, mode=mode).to_numpy()
+                assert_bitwise(tl, th, want_t, p, what="A^T g, " + tag)
+    picks = P.tune(reps=1)
+    assert {v[0] for v in picks.values()} <= {16, 32, 64}
+    for mode in (0, 1):
+        yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
+        want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
+        assert_bitwise(yl, yh, want, p, what="tuned A x mode %d" % mode)
+    assert M.mp_status() == 0
