@@ -106,7 +106,19 @@ typedef struct {
   int32_t use_x0;     /* 0: x0 = +0 and x is output only; 1: x holds x0 on entry */
   mp_vec *res_hist;   /* nullable; element i-1 receives RN(r_i . r_i) after iteration i (up to
                          res_hist->len entries) — the residual history of Fig. 7 squared */
+  struct mp_solve_profile *profile;  /* nullable; see below */
 } mp_solve_opts;
+
+/* Kernel timing of a solve (measurement only).  With opts->profile set, the iterations run
+ * eagerly (as for chunk <= 0; the results do not change) and every iteration kernel is
+ * bracketed by HIP events on the solver's stream; the durations, launch counts and algorithmic
+ * bytes (the vectors and matrix entries the kernel must read and write once) are added to the
+ * struct per kernel class: [0] inner products, [1] sparse products, [2] vector updates. */
+typedef struct mp_solve_profile {
+  int64_t launches[3];
+  double us[3];
+  double bytes[3];
+} mp_solve_profile;
 
 /* solver outcome (mp_solve_info.status) */
 #define MP_CONVERGED 0

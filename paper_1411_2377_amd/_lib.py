@@ -43,13 +43,19 @@ class MpCsr(ctypes.Structure):
                 ("val", MpVec)]
 
 
+class MpSolveProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 3), ("us", ctypes.c_double * 3),
+                ("bytes", ctypes.c_double * 3)]
+
+
 class MpSolveOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("transpose", ctypes.c_int32),
                 ("maxit", ctypes.c_int64),
                 ("rtol_m", ctypes.c_int64), ("rtol_e10", ctypes.c_int64),
                 ("atol_m", ctypes.c_int64), ("atol_e10", ctypes.c_int64),
                 ("chunk", ctypes.c_int32), ("use_x0", ctypes.c_int32),
-                ("res_hist", ctypes.POINTER(MpVec))]
+                ("res_hist", ctypes.POINTER(MpVec)),
+                ("profile", ctypes.POINTER(MpSolveProfile))]
 
 
 class MpSolveInfo(ctypes.Structure):

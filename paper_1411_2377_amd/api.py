@@ -167,7 +167,7 @@ def _opts(mode, maxit, rtol, atol, chunk, transpose, use_x0):
 
 
 def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50),
-           chunk=16, transpose=False, x0=None, hist=False, stream=None):
+           chunk=16, transpose=False, x0=None, hist=False, profile=None, stream=None):
     if x is None:
         x = MPArray.empty(A.n_rows, A.p, device=b.device)
     use_x0 = 0
@@ -175,6 +175,8 @@ def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), 
         x.copy_(x0)
         use_x0 = 1
     o = _opts(mode, maxit, rtol, atol, chunk, transpose, use_x0)
+    if profile is not None:   # an MpSolveProfile to add kernel timings to
+        o.profile = ctypes.pointer(profile)
     hist_arr = None
     if hist:
         hist_arr = MPArray.zeros(max(1, int(maxit)), A.p, device=b.device)
@@ -187,8 +189,12 @@ def _solve(fn, A, b, x=None, plan=None, mode=MP_SEQ, maxit=1000, rtol=(1, -20), 
     return x, SolveInfo(info.status, info.iters, info.final_rel_res, hist_arr)
 
 
+SolveProfile = _lib.MpSolveProfile
+
+
 def bicg(A, b, **kw):
-    """BiCG (K = I) for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
+    """BiCG (K = I) for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo).
+    profile=SolveProfile() collects per-class kernel timings (eager launches)."""
     return _solve(_lib.LIB.bicg, A, b, **kw)
 
 

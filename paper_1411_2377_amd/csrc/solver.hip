@@ -179,6 +179,8 @@ struct Work {
   hipEvent_t ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  mp_solve_profile* prof = nullptr;  // kernel timing (eager launches)
+  hipEvent_t pe0 = nullptr, pe1 = nullptr;
 
   mp::VecRef vec(int i) const {
     mp::VecRef r;
@@ -221,6 +223,8 @@ struct Work {
     hipFree(ticket);
     if (h_ctl) hipHostFree(h_ctl);
     if (ev) hipEventDestroy(ev);
+    if (pe0) hipEventDestroy(pe0);
+    if (pe1) hipEventDestroy(pe1);
     if (ws) hipStreamDestroy(ws);
   }
 };
@@ -258,6 +262,43 @@ int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
   a.v[0].hdr = W.S.hdr;
   a.v[0].ld = nsc;
   return launch_ew(L, EW_ZERO, a, W.ws);
+}
+
+// Profiling: class of a launch and its algorithmic bytes.
+enum ProfClass { PROF_DOT = 0, PROF_SPMV = 1, PROF_VEC = 2 };
+
+int prof_init(Work& W, mp_solve_profile* prof) {
+  if (!prof) return MPS_OK;
+  W.prof = prof;
+  hipError_t e = hipEventCreate(&W.pe0);
+  if (e == hipSuccess) e = hipEventCreate(&W.pe1);
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "profile events");
+}
+
+// Run `launch`; when profiling, bracket it with events on the workspace stream and add its
+// duration, a launch and `bytes` to class c.
+template <class F>
+int timed(const Work& W, int c, double bytes, F&& launch) {
+  if (!W.prof) return launch();
+  hipError_t e = hipEventRecord(W.pe0, W.ws);
+  const int r = launch();
+  if (r) return r;
+  if (e == hipSuccess) e = hipEventRecord(W.pe1, W.ws);
+  if (e == hipSuccess) e = hipEventSynchronize(W.pe1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, W.pe0, W.pe1);
+  if (e != hipSuccess) return hip_fail(e, "profile events");
+  W.prof->launches[c] += 1;
+  W.prof->us[c] += 1e3 * (double)ms;
+  W.prof->bytes[c] += bytes;
+  return MPS_OK;
+}
+
+// algorithmic bytes: k vectors of W.n elements; a sparse product (entries, x, y, row pointers)
+double vec_bytes(const Work& W, int k) { return (double)k * W.n * (4.0 * W.L + 4.0); }
+double spmv_bytes(const mp_csr* A, int L) {
+  return (double)A->nnz * (4.0 * L + 8.0) + (double)(A->row_dim + A->col_dim) * (4.0 * L + 4.0) +
+         4.0 * (double)(A->row_dim + 1);
 }
 
 // y = Aop v with the given arrays (Aop = A or A^T via the plan), no-op once done.
@@ -410,7 +451,7 @@ template <class F>
 int run_iterations(Work& W, const mp_solve_opts* o, F&& enqueue_iteration) {
   hipError_t e;
   int r;
-  const int chunk = o->chunk;
+  const int chunk = W.prof ? 0 : o->chunk;
   // the setup may already have finished the solve
   bool done = false;
   if ((r = poll_done(W, &done))) return r;
@@ -523,32 +564,38 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
   make_ops(A, plan, o->transpose, &op, &opT);
   uint32_t* st = ctx->status;
   if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  if ((r = prof_init(W, o->profile))) return r;
   const mp::VecRef R = W.vec(0), RT = W.vec(1), Z = W.vec(2), P = W.vec(3), PT = W.vec(4), ZT = W.vec(5);
   const mp::VecRef X = ref(*x);
   mp::VecRef hist{nullptr, nullptr, 0};
   if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 2);
   auto iteration = [&]() -> int {
     int rr;
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
-    if ((rr = launch_ew(L, EW_BICG_DIR, a, W.ws))) return rr;
+    if ((rr = timed(W, PROF_VEC, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
+      return rr;
     const SpmvPairs sig = pairs_of(W, {{PT.hdr, 0}});
-    if ((rr = apply(W, op, o->mode, P, Z, st, true, &sig))) return rr;
-    if ((rr = apply(W, opT, o->mode, PT, ZT, st, true))) return rr;
+    if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
+      return rr;
+    if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, opT, o->mode, PT, ZT, st, true); })))
+      return rr;
     mp::DotArgs d = dot_args(W, st, mp::EPI_BICG_SIGMA);
     d.nd = 1;
     d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA); d.slot[0] = 0;
-    if ((rr = launch_dot(L, d, W.ws))) return rr;
+    if ((rr = timed(W, PROF_DOT, dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
     a = ew_args(W, st);
     a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
     a.anchor = W.anchor; a.aslot[0] = 1; a.aslot[1] = 2;
-    if ((rr = launch_ew(L, EW_BICG_UPDATE, a, W.ws))) return rr;
+    if ((rr = timed(W, PROF_VEC, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); })))
+      return rr;
     d = dot_args(W, st, mp::EPI_BICG_CONV);
     d.nd = 2;
     d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
     d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
     d.hist = hist;
-    return launch_dot(L, d, W.ws);
+    return timed(W, PROF_DOT, 2 * dot1, [&] { return launch_dot(L, d, W.ws); });
   };
   if ((r = run_iterations(W, o, iteration))) return r;
   return finish_solve(W, info, st);
@@ -571,27 +618,28 @@ int gp_clear(const Work& W, uint32_t* st) {
 
 // One GPBiCG iteration (Fig. 5 with K = I) on the workspace stream.
 int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, const mp::VecRef& hist,
-                 uint32_t* st) {
+                 uint32_t* st, double sp_bytes) {
   const int L = W.L;
+  const double dot1 = vec_bytes(W, 2);
   const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), Q = W.vec(4), T = W.vec(5),
                    V = W.vec(6), S = W.vec(7), Wv = W.vec(8), Y = W.vec(9), U = W.vec(10),
                    Z = W.vec(11);
   int rr;
   mp::VecArgs a = ew_args(W, st);
   a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
-  if ((rr = launch_ew(L, EW_GP_DIR, a, W.ws))) return rr;
+  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
   const SpmvPairs den = pairs_of(W, {{RT.hdr, 0}});
-  if ((rr = apply(W, op, mode, P, Q, st, true, &den))) return rr;
+  if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
   mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
   d.nd = 1;
   d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN); d.slot[0] = 0;
-  if ((rr = launch_dot(L, d, W.ws))) return rr;
+  if ((rr = timed(W, PROF_DOT, dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
   a = ew_args(W, st);
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
   a.anchor = W.anchor; a.aslot[0] = 3; a.aslot[1] = 5;   // (y, y), (y, t)
-  if ((rr = launch_ew(L, EW_GP_TSY, a, W.ws))) return rr;
+  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
   const SpmvPairs mus = pairs_of(W, {{T.hdr, 4}, {Y.hdr, 6}, {nullptr, 7}});  // (v,t) (v,y) (v,v)
-  if ((rr = apply(W, op, mode, T, V, st, true, &mus))) return rr;
+  if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
   d = dot_args(W, st, mp::EPI_GP_ZETA);
   d.nd = 5;
   d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1); d.slot[0] = 3;
@@ -599,7 +647,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3); d.slot[2] = 5;
   d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4); d.slot[3] = 6;
   d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5); d.slot[4] = 7;
-  if ((rr = launch_dot(L, d, W.ws))) return rr;
+  if ((rr = timed(W, PROF_DOT, 5 * dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
   mp::GpUpdArgs g{};
   g.a = ew_args(W, st);
   g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
@@ -608,13 +656,13 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   g.y = Y;
   g.v = V;
   g.rt = RT;
-  if ((rr = launch_gp_update(L, g, W.ws))) return rr;
+  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); }))) return rr;
   d = dot_args(W, st, mp::EPI_GP_CONV);
   d.nd = 2;
   d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
   d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
   d.hist = hist;
-  return launch_dot(L, d, W.ws);
+  return timed(W, PROF_DOT, 2 * dot1, [&] { return launch_dot(L, d, W.ws); });
 }
 
 int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
@@ -645,7 +693,9 @@ int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x
   const mp::VecRef X = ref(*x);
   mp::VecRef hist{nullptr, nullptr, 0};
   if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
-  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, hist, st); };
+  if ((r = prof_init(W, o->profile))) return r;
+  const double sp_bytes = spmv_bytes(A, L);
+  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, hist, st, sp_bytes); };
   if ((r = run_iterations(W, o, iteration))) return r;
   return finish_solve(W, info, st);
 }
@@ -670,6 +720,7 @@ int check_batched_args(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, con
   if (!A || !b || !x || !o || !info) return fail(MPS_EINVAL, "null argument");
   if (o->transpose) return fail(MPS_ENOTSUP, "batched solves take A, not its transpose");
   if (o->res_hist && o->res_hist->len > 0) return fail(MPS_ENOTSUP, "batched solves keep no residual history");
+  if (o->profile) return fail(MPS_ENOTSUP, "batched solves take no profile");
   if (o->mode != MP_SEQ && o->mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if (o->maxit < 0 || o->maxit > INT32_MAX) return fail(MPS_EINVAL, "maxit out of range");
   int r;
@@ -824,7 +875,7 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   if ((r = solve_setup(W, op, &bd, &xd, o, st))) return r;
   if ((r = gp_clear(W, st))) return r;
   const mp::VecRef nohist{nullptr, nullptr, 0};
-  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, nohist, st); };
+  auto iteration = [&]() -> int { return gp_iteration(W, op, o->mode, X, nohist, st, 0.0); };
   if ((r = run_iterations(W, o, iteration))) return r;
   if ((r = batch_copy(L, false, d_seg + seg_b.size(), W.pair_of_tile, X, n, W.ws))) return r;
   // per-pair outcomes
