@@ -16,6 +16,8 @@
 
 namespace mpapi {
 
+thread_local LaunchEvents* g_launch_events = nullptr;
+
 static thread_local char g_err[512] = "";
 
 int fail(int code, const char* fmt, ...) {
@@ -144,9 +146,9 @@ template <int L, int RPW>
 static void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_rows + RPW - 1) / RPW) * (unsigned)a.nrhs;
   if (mode == MP_SEQ)
-    hipLaunchKernelGGL((mp::spmv_seq_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
+    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_seq_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL((mp::spmv_exact_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
+    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_exact_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
 }
 
 template <int L>
@@ -209,9 +211,9 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   if (x_rec && x_len > 0) {
     const unsigned g = (unsigned)std::min<int64_t>(16384, (x_len + 255) / 256);
     switch (L) {
-      case 4: hipLaunchKernelGGL(mp::x_stage_kernel<4>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
-      case 8: hipLaunchKernelGGL(mp::x_stage_kernel<8>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
-      case 16: hipLaunchKernelGGL(mp::x_stage_kernel<16>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 4: MPS_LAUNCH(true, false, mp::x_stage_kernel<4>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 8: MPS_LAUNCH(true, false, mp::x_stage_kernel<8>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 16: MPS_LAUNCH(true, false, mp::x_stage_kernel<16>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
       default: return fail(MPS_EINVAL, "bad limb count");
     }
   }

@@ -5,7 +5,29 @@
 
 #include "../../include/mpspmv.h"
 
+#include <hip/hip_ext.h>
+
 namespace mpapi {
+
+// Kernel timing: while set on the calling thread, the launch helpers attach these events to the
+// kernels they launch (the first kernel of a call records `start` when it begins, the last one
+// records `stop` when it ends), so their difference is the kernels' own execution time.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents* g_launch_events;
+
+// hipLaunchKernelGGL, or with the timing events attached (`first`/`last`: whether this launch
+// starts / ends the timed call)
+#define MPS_LAUNCH(first, last, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                        \
+  do {                                                                                        \
+    if (::mpapi::g_launch_events)                                                             \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM,                               \
+                            (first) ? ::mpapi::g_launch_events->start : nullptr,              \
+                            (last) ? ::mpapi::g_launch_events->stop : nullptr, 0, __VA_ARGS__); \
+    else                                                                                      \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                    \
+  } while (0)
 
 struct DeviceCtx {
   int device = 0;

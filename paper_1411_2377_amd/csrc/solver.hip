@@ -275,16 +275,17 @@ int prof_init(Work& W, mp_solve_profile* prof) {
   return e == hipSuccess ? MPS_OK : hip_fail(e, "profile events");
 }
 
-// Run `launch`; when profiling, bracket it with events on the workspace stream and add its
-// duration, a launch and `bytes` to class c.
+// Run `launch`; when profiling, have its kernels record their start and end on two events and
+// add the kernel time, a launch and `bytes` to class c.
 template <class F>
 int timed(const Work& W, int c, double bytes, F&& launch) {
   if (!W.prof) return launch();
-  hipError_t e = hipEventRecord(W.pe0, W.ws);
+  LaunchEvents ev{W.pe0, W.pe1};
+  g_launch_events = &ev;  // the kernels record their own start and end
   const int r = launch();
+  g_launch_events = nullptr;
   if (r) return r;
-  if (e == hipSuccess) e = hipEventRecord(W.pe1, W.ws);
-  if (e == hipSuccess) e = hipEventSynchronize(W.pe1);
+  hipError_t e = hipEventSynchronize(W.pe1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, W.pe0, W.pe1);
   if (e != hipSuccess) return hip_fail(e, "profile events");

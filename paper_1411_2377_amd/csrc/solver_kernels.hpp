@@ -367,8 +367,18 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   const int64_t slot0 = (int64_t)pair * kDotSlots;
   const unsigned nblocks = batched ? (unsigned)A.batch.tiles_of_pair[pair] : gridDim.x;
 
-  // first elements in flight while the anchor is reduced
-  const VecRef X = A.x[d], Y = A.y[d];
+  // first elements in flight while the anchor is reduced (operands picked by comparison: a
+  // dynamic index into the argument arrays would copy them to scratch memory)
+  VecRef X = A.x[0], Y = A.y[0];
+  int dslot = A.slot[0];
+#pragma unroll
+  for (int k = 1; k < kDotMaxND; ++k) {
+    if (k == d) {
+      X = A.x[k];
+      Y = A.y[k];
+      dslot = A.slot[k];
+    }
+  }
   const int64_t stride = batched ? (int64_t)(kTile / 2) : (int64_t)gridDim.x * kDotThreads;
   const int64_t n_end = batched ? (int64_t)(blockIdx.x + 1) * kTile : A.n;
   int64_t i0 = batched ? (int64_t)blockIdx.x * kTile + t : (int64_t)blockIdx.x * kDotThreads + t;
@@ -376,8 +386,8 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   dot_load<L>(E, X, Y, i0, i0 + stride, i0 < n_end, i0 + stride < n_end);
 
   int32_t emin, emax;
-  wave_anchor(A.w.anchor, slot0 + A.slot[d], emin, emax);
-  int64_t* gw = A.w.win + (slot0 + A.slot[d]) * A.w.win_stride;
+  wave_anchor(A.w.anchor, slot0 + dslot, emin, emax);
+  int64_t* gw = A.w.win + (slot0 + dslot) * A.w.win_stride;
   const bool any = emax >= emin;
   const int W = any ? window_digits<L>(emin, emax) : 0;
   const bool fits = W <= WB && W <= A.w.win_stride;
@@ -472,7 +482,7 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   }
 #pragma unroll
   for (int dd = 0; dd < kDotMaxND; ++dd) {
-    if (dd >= A.nd) break;
+    if (dd >= A.nd) continue;  // (continue, not break: the loop must unroll fully)
     const bool anyd = amax[dd] >= amin[dd];
     const int Wd = anyd ? window_digits<L>(amin[dd], amax[dd]) : 0;
     const bool fitsd = Wd <= WB && Wd <= A.w.win_stride;

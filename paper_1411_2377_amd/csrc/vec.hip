@@ -74,9 +74,9 @@ static unsigned ew_grid_of(const mp::VecArgs& a) {
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
   const unsigned g = a.batch.pair_of_tile ? (unsigned)(a.n / mp::kTile) : dot_grid(a.n, a.nd, L);
   switch (L) {
-    case 4: hipLaunchKernelGGL(mp::dot_kernel<4>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(mp::dot_kernel<8>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(mp::dot_kernel<16>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 4: MPS_LAUNCH(true, true, mp::dot_kernel<4>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 8: MPS_LAUNCH(true, true, mp::dot_kernel<8>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 16: MPS_LAUNCH(true, true, mp::dot_kernel<16>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -85,9 +85,9 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
 
 #define MPS_EW_CASES(KERNEL, ARG)                                                             \
   switch (L) {                                                                                \
-    case 4: hipLaunchKernelGGL(mp::KERNEL<4>, dim3(g), dim3(256), 0, s, ARG); break;          \
-    case 8: hipLaunchKernelGGL(mp::KERNEL<8>, dim3(g), dim3(256), 0, s, ARG); break;          \
-    case 16: hipLaunchKernelGGL(mp::KERNEL<16>, dim3(g), dim3(256), 0, s, ARG); break;        \
+    case 4: MPS_LAUNCH(true, true, mp::KERNEL<4>, dim3(g), dim3(256), 0, s, ARG); break;          \
+    case 8: MPS_LAUNCH(true, true, mp::KERNEL<8>, dim3(g), dim3(256), 0, s, ARG); break;          \
+    case 16: MPS_LAUNCH(true, true, mp::KERNEL<16>, dim3(g), dim3(256), 0, s, ARG); break;        \
     default: return fail(MPS_EINVAL, "bad limb count");                                       \
   }
 

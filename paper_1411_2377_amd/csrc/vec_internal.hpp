@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/mpspmv.h"
+#include "api_internal.hpp"
 #include "solver_kernels.hpp"
 
 namespace mpapi {
