@@ -136,9 +136,9 @@ def time_kernel(torch, fn, reps):
 
 
 def spmv_kernel_name(plan, op, mode, L):
-    rows, staged = plan.variants()[(op, mode)]
-    return "%s<%d, %d>%s" % ("spmv_exact_kernel" if mode else "spmv_seq_kernel", L, rows,
-                             " (x staged)" if staged else "")
+    rows, staged, srt = plan.variants()[(op, mode)]
+    return "%s<%d, %d>%s%s" % ("spmv_exact_kernel" if mode else "spmv_seq_kernel", L, rows,
+                               " (x staged)" if staged else "", " (rows by length)" if srt else "")
 
 
 def load_traffic(kernel):

@@ -163,19 +163,25 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
                  void *stream);
 
 /* Kernel variants (implementation tuning, not part of the paper's method).  The SpMV kernels
- * process `rows_per_block` rows (16, 32 or 64) per wavefront-sized block, and may first stage x
- * as one contiguous record per element (`stage_x`: one cache line per gathered x_j instead of
- * one per limb, which pays for scattered columns).  op 0 is the product with A, op 1 with A^T.
- * mp_plan_tune times every variant of the four products (both ops, both modes; `reps`
- * launches each, 0: 3) on a generated operand, synchronously on `stream`, and stores the
+ * process `rows_per_block` rows (16, 32 or 64) per wavefront-sized block; with
+ * MP_VARIANT_STAGE_X they first stage x as one contiguous record per element (one cache line per
+ * gathered x_j instead of one per limb, which pays for scattered columns); with
+ * MP_VARIANT_SORTED_ROWS the blocks take the rows in order of decreasing length (the plan holds
+ * the order), so that a block's rows have similar lengths.  op 0 is the product with A, op 1
+ * with A^T.  mp_plan_tune times every variant of the four products (both ops, both modes;
+ * `reps` launches each, 0: 3) on a generated operand, synchronously on `stream`, and stores the
  * fastest in the plan; the plan then selects it for mpspmv_csr, mpspmv_csr_t and the solvers
  * given the plan.  Results are bit-identical for every variant.  mp_plan_set_variant forces a
- * variant (rows 0: by shape); mp_plan_get_variant reports the one in effect.  A plan whose
- * variants stage x holds one staging buffer: calls using it must not overlap in time (one
- * stream at a time).  All return MPS_OK or MPS_EINVAL (also MPS_ENOMEM; tune also MPS_EHIP). */
+ * variant (rows 0: by shape; A is the plan's matrix, read to order its rows);
+ * mp_plan_get_variant reports the one in effect.  A plan whose variants stage x holds one
+ * staging buffer: calls using it must not overlap in time (one stream at a time).  All return
+ * MPS_OK or MPS_EINVAL (also MPS_ENOMEM, MPS_EHIP). */
+#define MP_VARIANT_STAGE_X 1
+#define MP_VARIANT_SORTED_ROWS 2
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
-int mp_plan_set_variant(mp_plan *plan, int op, int mode, int rows_per_block, int stage_x);
-int mp_plan_get_variant(const mp_plan *plan, int op, int mode, int *rows_per_block, int *stage_x);
+int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
+                        int flags);
+int mp_plan_get_variant(const mp_plan *plan, int op, int mode, int *rows_per_block, int *flags);
 
 /* gvals_k = RN(g_i x_j) for each stored entry k = (i, j) in A's CSR order (negated when
  * negate != 0): the gradient of <g, A x> with respect to the stored values.  Needs the plan

@@ -86,7 +86,8 @@ SIGNATURES = {
     "mpspmv_csr": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "mp_plan_tune": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_void_p],
-    "mp_plan_set_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "mp_plan_set_variant": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int],
     "mp_plan_get_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "mp_status": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],

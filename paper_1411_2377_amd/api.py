@@ -65,19 +65,22 @@ class Plan:
         check(_lib.LIB.mp_plan_tune(self._h, ctypes.byref(d), int(reps), _stream(stream)))
         return self.variants()
 
-    def set_variant(self, op, mode, rows=0, stage_x=False):
+    def set_variant(self, op, mode, rows=0, stage_x=False, sorted_rows=False):
         """Force a kernel variant: op 0 = A, 1 = A^T; rows in (0, 16, 32, 64), 0 = by shape;
-        stage_x: gather x from staged records."""
-        check(_lib.LIB.mp_plan_set_variant(self._h, int(op), int(mode), int(rows), int(bool(stage_x))))
+        stage_x: gather x from staged records; sorted_rows: blocks take rows by decreasing
+        length."""
+        d = self.A.desc()
+        flags = (1 if stage_x else 0) | (2 if sorted_rows else 0)
+        check(_lib.LIB.mp_plan_set_variant(self._h, ctypes.byref(d), int(op), int(mode), int(rows), flags))
 
     def variants(self):
-        """{(op, mode): (rows per block, stage_x)} in effect."""
+        """{(op, mode): (rows per block, stage_x, sorted_rows)} in effect."""
         out = {}
         for op in (0, 1):
             for mode in (MP_SEQ, MP_EXACT):
-                v, st = ctypes.c_int(0), ctypes.c_int(0)
-                check(_lib.LIB.mp_plan_get_variant(self._h, op, mode, ctypes.byref(v), ctypes.byref(st)))
-                out[(op, mode)] = (v.value, bool(st.value))
+                v, fl = ctypes.c_int(0), ctypes.c_int(0)
+                check(_lib.LIB.mp_plan_get_variant(self._h, op, mode, ctypes.byref(v), ctypes.byref(fl)))
+                out[(op, mode)] = (v.value, bool(fl.value & 1), bool(fl.value & 2))
         return out
 
     def close(self):

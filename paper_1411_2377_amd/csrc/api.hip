@@ -145,7 +145,9 @@ bool valid_rows_per_block(int rpw) { return rpw == 16 || rpw == 32 || rpw == 64;
 template <int L, int RPW>
 static void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n_rows + RPW - 1) / RPW) * (unsigned)a.nrhs;
-  if (mode == MP_SEQ)
+  if (mode == MP_SEQ && a.rows)  // rows by length: the four-wave pipelined kernel
+    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW>), dim3(grid), dim3(256), 0, s, a);
+  else if (mode == MP_SEQ)
     MPS_LAUNCH(!a.x_rec, true, (mp::spmv_seq_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
   else
     MPS_LAUNCH(!a.x_rec, true, (mp::spmv_exact_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
@@ -163,8 +165,13 @@ static void launch_spmv(const mp::SpmvArgs& a, int mode, int rpw, hipStream_t s)
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvPairs* pairs,
-                const SpmvBatch* batch, int rpw, uint32_t* x_rec, int64_t x_len) {
+                const SpmvBatch* batch, const SpmvVariant* var) {
   if (n_rows == 0) return MPS_OK;
+  const SpmvVariant plain;
+  if (!var) var = &plain;
+  int rpw = var->rpw;
+  uint32_t* const x_rec = var->x_rec;
+  const int64_t x_len = var->x_len;
   if (x_rec && batch && batch->nrhs != 1) return fail(MPS_EINVAL, "staged x takes one right-hand side");
   const SpmvBatch one;
   if (!batch) batch = &one;
@@ -196,6 +203,8 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.npair = 0;
   a.anchor = nullptr;
   a.x_rec = x_rec;
+  a.rows = var->rows;
+  if (var->rows && batch->nrhs != 1) return fail(MPS_EINVAL, "a row order takes one right-hand side");
   for (int k = 0; k < 3; ++k) {
     a.pair_hdr[k] = nullptr;
     a.pair_slot[k] = 0;
@@ -255,10 +264,9 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_p
     return fail(MPS_EINVAL, "y overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
-  const bool stage = plan && plan->stage[0][mode] && plan->x_rec;
+  const SpmvVariant var = plan ? plan_variant(plan, 0, mode) : SpmvVariant{};
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
-                     nullptr, (hipStream_t)stream, nullptr, nullptr,
-                     plan ? plan->rpw[0][mode] : 0, stage ? plan->x_rec : nullptr, A->col_dim);
+                     nullptr, (hipStream_t)stream, nullptr, nullptr, &var);
 }
 
 int mp_status(void* stream, uint32_t* flags) {

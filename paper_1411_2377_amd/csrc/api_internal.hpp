@@ -73,12 +73,18 @@ int limbs_of(int prec);
 int check_vec(const mp_vec* v, int64_t want_len, const char* name);
 bool vec_overlap(const mp_vec* a, const mp_vec* b, int L);
 int check_csr(const mp_csr* A, int check_device_data);
+// Kernel variant of one product: rows per block (0: by shape), staged x (x_rec: a buffer of
+// x_len records, the launch first stages x into it), rows in a given order (nullptr: in order).
+struct SpmvVariant {
+  int rpw = 0;
+  uint32_t* x_rec = nullptr;
+  int64_t x_len = 0;
+  const int32_t* rows = nullptr;
+};
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr,
-                const SpmvBatch* batch = nullptr, int rows_per_block = 0,
-                uint32_t* x_rec = nullptr, int64_t x_len = 0);
-// x_rec (nullable): a buffer of x_len staged x records; the launch first stages x into it
+                const SpmvBatch* batch = nullptr, const SpmvVariant* var = nullptr);
 // rows per block of the SpMV kernels: 16, 32 or 64 (0 or anything else: chosen from the shape)
 int default_rows_per_block(int64_t n_rows, int64_t nnz);
 bool valid_rows_per_block(int rpw);

@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include <cstring>
+#include <vector>
 #include <rocprim/rocprim.hpp>
 
 #include "../../include/mpspmv.h"
@@ -92,8 +93,41 @@ int plan_free(mp_plan* P) {
   hipFree(P->t_limb);
   hipFree(P->t_hdr);
   hipFree(P->x_rec);
+  hipFree(P->row_order[0]);
+  hipFree(P->row_order[1]);
   delete P;
   return MPS_OK;
+}
+
+int plan_row_order(mp_plan* P, int op, const int32_t* a_row_ptr) {
+  if (P->row_order[op]) return MPS_OK;
+  const int64_t n = op ? P->n_cols : P->n_rows;
+  const int32_t* rp = op ? P->t_row_ptr : a_row_ptr;
+  std::vector<int32_t> h(n + 1), order(n);
+  hipError_t e = hipMemcpy(h.data(), rp, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "row order");
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return h[a + 1] - h[a] > h[b + 1] - h[b];
+  });
+  e = hipMalloc((void**)&P->row_order[op], std::max<size_t>(4, (size_t)n * 4));
+  if (e != hipSuccess) {
+    P->row_order[op] = nullptr;
+    return fail(MPS_ENOMEM, "row order: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(P->row_order[op], order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "row order");
+}
+
+SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
+  SpmvVariant v;
+  v.rpw = P->rpw[op][mode];
+  if (P->stage[op][mode] && P->x_rec) {
+    v.x_rec = P->x_rec;
+    v.x_len = op ? P->n_rows : P->n_cols;
+  }
+  if (P->sorted[op][mode]) v.rows = P->row_order[op];
+  return v;
 }
 
 int plan_x_rec(mp_plan* P) {
@@ -270,6 +304,8 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
   if (e == hipSuccess) e = hipMalloc((void**)&yh, (size_t)nmax * 4);
   if (e != hipSuccess) return fail(MPS_ENOMEM, "tune workspace: %s", hipGetErrorString(e));
   int r0 = plan_x_rec(P);
+  if (!r0) r0 = plan_row_order(P, 0, A->row_ptr);
+  if (!r0) r0 = plan_row_order(P, 1, nullptr);
   if (r0) return r0;
   if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
     return hip_fail(e, "tune events");
@@ -288,17 +324,23 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     mp_vec xv{xl, xh, cols, nmax}, yv{yl, yh, rows, nmax};
     for (int mode = 0; mode < 2; ++mode) {
       float best = 0.f;
-      int pick = default_rows_per_block(rows, P->nnz), pick_stage = 0;
-      for (int stage = 0; stage < 2; ++stage) {
-        uint32_t* rec = stage ? P->x_rec : nullptr;
+      int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0;
+      for (int flags = 0; flags < 4; ++flags) {
         for (int rpw : {16, 32, 64}) {
+          SpmvVariant var;
+          var.rpw = rpw;
+          if (flags & MP_VARIANT_STAGE_X) {
+            var.x_rec = P->x_rec;
+            var.x_len = cols;
+          }
+          if (flags & MP_VARIANT_SORTED_ROWS) var.rows = P->row_order[op];
           int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
-                               nullptr, rpw, rec, cols);
+                               nullptr, &var);
           if (rr) return rr;
           if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "tune");
           for (int k = 0; k < reps; ++k)
             if ((rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
-                                  nullptr, rpw, rec, cols)))
+                                  nullptr, &var)))
               return rr;
           if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
             return hip_fail(e, "tune");
@@ -307,12 +349,13 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
           if (best == 0.f || ms < best) {
             best = ms;
             pick = rpw;
-            pick_stage = stage;
+            pick_flags = flags;
           }
         }
       }
       P->rpw[op][mode] = pick;
-      P->stage[op][mode] = pick_stage != 0;
+      P->stage[op][mode] = (pick_flags & MP_VARIANT_STAGE_X) != 0;
+      P->sorted[op][mode] = (pick_flags & MP_VARIANT_SORTED_ROWS) != 0;
     }
   }
   return MPS_OK;
@@ -363,36 +406,40 @@ int mpspmv_csr_t(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp
   tv.hdr = plan->t_hdr;
   tv.len = plan->nnz;
   tv.ld = plan->nnz;
-  const bool stage = plan->stage[1][mode] && plan->x_rec;
+  const SpmvVariant var = plan_variant(plan, 1, mode);
   return spmv_launch(L, A->col_dim, plan->t_row_ptr, plan->t_col_idx, tv, *x, *y, mode,
-                     ctx->status, nullptr, (hipStream_t)stream, nullptr, nullptr,
-                     plan->rpw[1][mode], stage ? plan->x_rec : nullptr, A->row_dim);
+                     ctx->status, nullptr, (hipStream_t)stream, nullptr, nullptr, &var);
 }
 
-int mp_plan_set_variant(mp_plan* plan, int op, int mode, int rows_per_block, int stage_x) {
+int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int rows_per_block,
+                        int flags) {
   clear_error();
   if (!plan) return fail(MPS_EINVAL, "null plan");
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
   if (op != 0 && op != 1) return fail(MPS_EINVAL, "op must be 0 (A) or 1 (A^T)");
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if (rows_per_block != 0 && !valid_rows_per_block(rows_per_block))
     return fail(MPS_EINVAL, "rows per block must be 0, 16, 32 or 64");
-  if (stage_x) {
-    int r = plan_x_rec(plan);
-    if (r) return r;
-  }
+  if (flags & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS)) return fail(MPS_EINVAL, "unknown variant flags");
+  if ((flags & MP_VARIANT_STAGE_X) && (r = plan_x_rec(plan))) return r;
+  if ((flags & MP_VARIANT_SORTED_ROWS) && (r = plan_row_order(plan, op, A->row_ptr))) return r;
   plan->rpw[op][mode] = rows_per_block;
-  plan->stage[op][mode] = stage_x != 0;
+  plan->stage[op][mode] = (flags & MP_VARIANT_STAGE_X) != 0;
+  plan->sorted[op][mode] = (flags & MP_VARIANT_SORTED_ROWS) != 0;
   return MPS_OK;
 }
 
-int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_block, int* stage_x) {
+int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_block, int* flags) {
   clear_error();
-  if (!plan || !rows_per_block || !stage_x) return fail(MPS_EINVAL, "null argument");
+  if (!plan || !rows_per_block || !flags) return fail(MPS_EINVAL, "null argument");
   if (op != 0 && op != 1) return fail(MPS_EINVAL, "op must be 0 (A) or 1 (A^T)");
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   const int64_t rows = op ? plan->n_cols : plan->n_rows;
   *rows_per_block = plan->rpw[op][mode] ? plan->rpw[op][mode] : default_rows_per_block(rows, plan->nnz);
-  *stage_x = (plan->stage[op][mode] && plan->x_rec) ? 1 : 0;
+  *flags = ((plan->stage[op][mode] && plan->x_rec) ? MP_VARIANT_STAGE_X : 0) |
+           ((plan->sorted[op][mode] && plan->row_order[op]) ? MP_VARIANT_SORTED_ROWS : 0);
   return MPS_OK;
 }
 

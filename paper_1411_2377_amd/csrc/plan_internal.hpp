@@ -15,12 +15,19 @@ struct mp_plan {
   int32_t* t_hdr = nullptr;      // [nnz]
   int rpw[2][2] = {{0, 0}, {0, 0}};  // SpMV rows per block for [A, A^T][mode]; 0: by shape
   bool stage[2][2] = {{false, false}, {false, false}};  // stage x as records for [op][mode]
+  bool sorted[2][2] = {{false, false}, {false, false}}; // rows by length for [op][mode]
   uint32_t* x_rec = nullptr;     // [max(n_rows, n_cols)] staged x records (allocated on demand)
+  int32_t* row_order[2] = {nullptr, nullptr};  // rows of A / A^T by length, longest first
 };
 
 namespace mpapi {
+struct SpmvVariant;
 // allocate the plan's staged-x buffer if it has none
 int plan_x_rec(mp_plan* P);
+// build the plan's row order for op (0: A, whose row pointers are given; 1: A^T) if it has none
+int plan_row_order(mp_plan* P, int op, const int32_t* a_row_ptr);
+// the variant the plan holds for product op in mode
+SpmvVariant plan_variant(const mp_plan* P, int op, int mode);
 }
 
 namespace mpapi {

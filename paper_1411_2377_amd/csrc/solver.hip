@@ -308,9 +308,7 @@ struct Op {
   const int32_t* row_ptr;
   const int32_t* col_idx;
   mp_vec val;
-  int rpw[2];  // rows per block per mode (0: by shape)
-  uint32_t* x_rec[2];  // staged-x buffer per mode (nullptr: x read in place)
-  int64_t n_in;        // length of the operand x
+  SpmvVariant var[2];  // kernel variant per mode
 };
 
 // y = Aop x on the workspace stream; `gated`: a no-op once the solve is done (for a batch,
@@ -327,11 +325,10 @@ int apply(const Work& W, const Op& op, int mode, const mp::VecRef& x, const mp::
     b.done_stride = (int64_t)(sizeof(mp::Ctl) / sizeof(int32_t));
     b.slots_per_pair = mp::kDotSlots;
     return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                       nullptr, W.ws, pairs, &b, op.rpw[mode]);
+                       nullptr, W.ws, pairs, &b, &op.var[mode]);
   }
   return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                     gated ? &W.ctl->done : nullptr, W.ws, pairs, nullptr, op.rpw[mode],
-                     op.x_rec[mode], op.n_in);
+                     gated ? &W.ctl->done : nullptr, W.ws, pairs, nullptr, &op.var[mode]);
 }
 
 // Inner products of an SpMV output with up to three vectors (nullptr: the output itself).
@@ -521,14 +518,12 @@ struct OwnedPlan {
 
 // The two products of a solve: Aop (the system matrix) and its transpose.
 int make_ops(const mp_csr* A, const mp_plan* P, int transpose, Op* op, Op* opT) {
-  Op a{A->row_dim, A->row_ptr, A->col_idx, A->val, {0, 0}, {nullptr, nullptr}, A->col_dim};
-  Op t{A->col_dim, nullptr, nullptr, A->val, {0, 0}, {nullptr, nullptr}, A->row_dim};
+  Op a{A->row_dim, A->row_ptr, A->col_idx, A->val, {}};
+  Op t{A->col_dim, nullptr, nullptr, A->val, {}};
   if (P) {
     for (int m = 0; m < 2; ++m) {
-      a.rpw[m] = P->rpw[0][m];
-      t.rpw[m] = P->rpw[1][m];
-      a.x_rec[m] = P->stage[0][m] ? P->x_rec : nullptr;
-      t.x_rec[m] = P->stage[1][m] ? P->x_rec : nullptr;
+      a.var[m] = plan_variant(P, 0, m);
+      t.var[m] = plan_variant(P, 1, m);
     }
     t.row_ptr = P->t_row_ptr;
     t.col_idx = P->t_col_idx;
@@ -867,7 +862,7 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   if (e != hipSuccess) return hip_fail(e, "batch maps upload");
   BlockDiag M;
   if ((r = build_block_diag(nsys, A, L, row_off, M, W.ws))) return r;
-  Op op{M.rows, M.row_ptr, M.col_idx, mp_vec{M.limb, M.hdr, M.nnz, M.nnz}, {0, 0}, {nullptr, nullptr}, M.rows};
+  Op op{M.rows, M.row_ptr, M.col_idx, mp_vec{M.limb, M.hdr, M.nnz, M.nnz}, {}};
   uint32_t* st = ctx->status;
   const mp::VecRef X = W.vec(kGpVectors), B = W.vec(kGpVectors + 1);
   if ((r = batch_copy(L, true, d_seg, W.pair_of_tile, B, n, W.ws))) return r;

@@ -76,6 +76,8 @@ struct SpmvArgs {
   // x staged as one record per element (limbs then header, x_rec_words<L>() words apart), or
   // nullptr: x is read in its own layout
   const uint32_t* x_rec;
+  // rows in processing order (block b takes rows[b * RPW ...]), or nullptr: 0, 1, 2, ...
+  const int32_t* rows;
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
@@ -178,6 +180,18 @@ MPD void load_x(const SpmvArgs& A, const uint32_t* x_limb, const int32_t* x_hdr,
   }
 }
 
+// Exclusive prefix of each lane's count over the wave, into pre[lane] (pre[64] = total).
+MPD void wave_prefix(int v, int32_t* pre) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  pre[lane + 1] = v;
+  if (lane == 0) pre[0] = 0;
+}
+
 // ------------------------------------------------------------------------------------------
 // Entry loads: a lane takes K entries of a chunk at once.  The column, header and (for a non-zero
 // entry) the limbs of a_k are requested first, then x's header and limbs at that column, so every
@@ -215,11 +229,18 @@ MPD void load_entries(EntryLoad<L, K>& E, const SpmvArgs& A, const uint32_t* x_l
   }
 }
 
+// SEQ.  A block takes RPW rows (consecutive, or the plan's rows sorted by length so that a
+// block's rows have similar lengths).  Phase 1: all lanes form the rounded products of the rows'
+// entries, taken in order (a compact numbering of the rows' entries, the row of each entry
+// painted into LDS per chunk), with batched coalesced loads, and stage them in LDS.  Phase 2:
+// each lane adds its row's staged products in storage order.
 template <int L, int RPW>
 __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
   constexpr int K = spmv_kper<L>();
   constexpr int kChunk = 64 * K;
-  __shared__ int32_t s_rp[kRowsPerBlock + 1];
+  __shared__ int32_t s_rs[RPW];
+  __shared__ int32_t s_cp[65];          // compact entry prefix over the block's rows
+  __shared__ uint8_t s_row[kChunk];     // row of each compact entry of the chunk
   __shared__ uint32_t s_m[L][kChunk];
   __shared__ int32_t s_e[kChunk];
   __shared__ uint32_t s_s[kChunk];
@@ -232,25 +253,31 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
   const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
   const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
   const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
-  for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
-  __syncthreads();
-  const int kb = s_rp[0], ke = s_rp[nr];
   const bool has_row = lane < nr;
-  const int rs = has_row ? s_rp[lane] : 0;
-  const int re = has_row ? s_rp[lane + 1] : 0;
+  const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
+  const int rs = has_row ? A.row_ptr[row] : 0;
+  const int re = has_row ? A.row_ptr[row + 1] : 0;
+  if (lane < RPW) s_rs[lane] = rs;
+  wave_prefix(re - rs, s_cp);
+  __syncthreads();
+  const int cs = s_cp[lane], ce = s_cp[lane + 1], ntot = s_cp[64];
   uint32_t st = 0;
   Num<L> acc;
   set_zero(acc, 0);
 
-  for (int c0 = kb; c0 < ke; c0 += kChunk) {
-    const int cn = min(kChunk, ke - c0);
+  for (int c0 = 0; c0 < ntot; c0 += kChunk) {
+    const int cn = min(kChunk, ntot - c0);
+    for (int j = max(cs, c0); j < min(ce, c0 + cn); ++j) s_row[j - c0] = (uint8_t)lane;
+    __syncthreads();
     // phase 1: rounded products of the chunk, staged in LDS
     int64_t k[K];
     bool ok[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      ok[i] = lane + 64 * i < cn;
-      k[i] = (int64_t)c0 + lane + 64 * i;
+      const int j = lane + 64 * i;
+      ok[i] = j < cn;
+      const int r = ok[i] ? s_row[j] : 0;
+      k[i] = (int64_t)s_rs[r] + (c0 + j - s_cp[r]);
     }
     EntryLoad<L, K> E;
     load_entries<L, K>(E, A, x_limb, x_hdr, k, ok);
@@ -274,24 +301,138 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
     }
     __syncthreads();
     // phase 2: each lane adds its row's products in storage order
-    const int lo = max(rs, c0), hi = min(re, c0 + cn);
-    for (int kk = lo; kk < hi; ++kk) {
-      const int j = kk - c0;
+    for (int j = max(cs, c0); j < min(ce, c0 + cn); ++j) {
       Num<L> t;
 #pragma unroll
-      for (int q = 0; q < L; ++q) t.m[q] = s_m[q][j];
-      t.e = s_e[j];
-      t.s = s_s[j];
+      for (int q = 0; q < L; ++q) t.m[q] = s_m[q][j - c0];
+      t.e = s_e[j - c0];
+      t.s = s_s[j - c0];
       acc = add_rn<L>(acc, t, st);
     }
     __syncthreads();
   }
-  if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
+  if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
   if (A.npair) {
     PairAcc P;
     pair_init(P);
-    if (has_row) pair_fold(A, P, yo + r0 + lane, make_hdr(acc.e, acc.s));
+    if (has_row) pair_fold(A, P, yo + row, make_hdr(acc.e, acc.s));
     pair_publish(A, P, B.pair);
+  }
+  if (st) atomicOr(A.status, st);
+}
+
+MPD int32_t wave_min32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+MPD int32_t wave_max32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// SEQ over rows taken by decreasing length (the plan's row order), so that a block's RPW rows
+// have similar lengths.  The block is four wavefronts: lane r of the first adds row r's products
+// in storage order (the serial RN chain the mode defines), while the other three form the rounded
+// products of the next chunk — Q further entries of every row — into the other half of a
+// double buffer in LDS.  The chains of the block's rows then advance together, and the products
+// are computed off their critical path.
+template <int RPW>
+constexpr int seq_sorted_q() { return RPW >= 64 ? 4 : 8; }
+
+template <int L, int RPW>
+__global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
+  constexpr int Q = seq_sorted_q<RPW>();
+  constexpr int NS = RPW * Q;  // product slots per chunk: row r's t-th entry of the chunk at r*Q+t
+  __shared__ int32_t s_rs[RPW], s_len[RPW];
+  __shared__ int32_t s_maxlen;
+  __shared__ uint32_t s_m[2][L][NS];
+  __shared__ int32_t s_e[2][NS];
+  __shared__ uint32_t s_s[2][NS];
+
+  SpmvBlock B;
+  if (!spmv_block<RPW>(A, B)) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t r0 = B.rb * RPW;
+  const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
+  const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
+  const int64_t yo = B.rhs * A.y_rstride;
+  const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
+  const bool has_row = wv == 0 && lane < nr;
+  const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
+  if (wv == 0) {
+    const int rs = has_row ? A.row_ptr[row] : 0;
+    const int len = has_row ? A.row_ptr[row + 1] - rs : 0;
+    if (lane < RPW) {
+      s_rs[lane] = rs;
+      s_len[lane] = len;
+    }
+    const int mx = wave_max32(len);
+    if (lane == 0) s_maxlen = mx;
+  }
+  __syncthreads();
+  const int nch = (s_maxlen + Q - 1) / Q;
+  uint32_t st = 0;
+
+  // products of chunk c into buffer b by the threads of waves 1..3
+  auto produce = [&](int c, int b) {
+    for (int j = t - 64; j < NS; j += 192) {
+      const int r = j / Q, o = c * Q + j % Q;
+      int64_t k[1];
+      bool ok[1];
+      ok[0] = r < nr && o < s_len[r];
+      k[0] = ok[0] ? (int64_t)s_rs[r] + o : 0;
+      EntryLoad<L, 1> E;
+      load_entries<L, 1>(E, A, x_limb, x_hdr, k, ok);
+      if (!ok[0]) continue;
+      const int32_t ha = E.ha[0], hx = E.hx[0];
+      Num<L> p;
+      if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
+        set_zero(p, (uint32_t)(ha ^ hx) & 1u);
+      } else {
+        uint32_t pr[2 * L];
+        mul_full<L>(E.am[0], E.xm[0], pr);
+        round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, p, st);
+      }
+#pragma unroll
+      for (int q = 0; q < L; ++q) s_m[b][q][j] = p.m[q];
+      s_e[b][j] = p.e;
+      s_s[b][j] = p.s;
+    }
+  };
+
+  Num<L> acc;
+  set_zero(acc, 0);
+  if (wv > 0 && nch > 0) produce(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int b = c & 1;
+    if (wv > 0) {
+      if (c + 1 < nch) produce(c + 1, b ^ 1);
+    } else if (has_row) {
+      const int len = s_len[lane];
+      for (int q = 0; q < Q && c * Q + q < len; ++q) {
+        const int j = lane * Q + q;
+        Num<L> p;
+#pragma unroll
+        for (int w = 0; w < L; ++w) p.m[w] = s_m[b][w][j];
+        p.e = s_e[b][j];
+        p.s = s_s[b][j];
+        acc = add_rn<L>(acc, p, st);
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0) {
+    if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
+    if (A.npair) {
+      PairAcc P;
+      pair_init(P);
+      if (has_row) pair_fold(A, P, yo + row, make_hdr(acc.e, acc.s));
+      pair_publish(A, P, B.pair);
+    }
   }
   if (st) atomicOr(A.status, st);
 }
@@ -344,18 +485,6 @@ MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, 
   }
 }
 
-MPD int32_t wave_min32(int32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
-
-MPD int32_t wave_max32(int32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
 template <int L, int RPW>
 __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   constexpr int R = window_fast_digits<L>();  // ring digits per row
@@ -365,7 +494,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   static_assert(RPW >= 16, "the shared window lives in the ring area");
   constexpr int K = spmv_kper<L>();
   constexpr int kChunk = 64 * K;
-  __shared__ int32_t s_rp[RPW + 1];
+  __shared__ int32_t s_rs[RPW];
   __shared__ int32_t s_cp[65];          // compact (short-row) entry prefix
   __shared__ uint8_t s_row[kChunk];     // row of each compact entry of the chunk
   __shared__ int32_t s_lo[RPW], s_hi[RPW];
@@ -379,27 +508,18 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
   const int64_t yo = B.rhs * A.y_rstride;  // y (and paired vectors) offset of this right-hand side
   const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
-  for (int i = lane; i <= nr; i += 64) s_rp[i] = A.row_ptr[r0 + i];
+  const bool has_row = lane < nr;
+  const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
+  const int rs = has_row ? A.row_ptr[row] : 0;
+  const int re = has_row ? A.row_ptr[row + 1] : 0;
+  const bool is_short = has_row && re - rs <= kShortRow;
   for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
   if (lane < RPW) {
+    s_rs[lane] = rs;
     s_lo[lane] = INT32_MAX;
     s_hi[lane] = INT32_MIN;
   }
-  __syncthreads();
-  const bool has_row = lane < nr;
-  const int rs = has_row ? s_rp[lane] : 0;
-  const int re = has_row ? s_rp[lane + 1] : 0;
-  const bool is_short = has_row && re - rs <= kShortRow;
-  {  // compact positions of the short rows' entries
-    int v = is_short ? re - rs : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int u = __shfl_up(v, o);
-      if (lane >= o) v += u;
-    }
-    s_cp[lane + 1] = v;
-    if (lane == 0) s_cp[0] = 0;
-  }
+  wave_prefix(is_short ? re - rs : 0, s_cp);  // compact positions of the short rows' entries
   __syncthreads();
   const int cs = s_cp[lane], ce = s_cp[lane + 1], ntot = s_cp[64];
   uint32_t st = 0;
@@ -410,13 +530,13 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     __syncthreads();
     int64_t k[K];
     bool ok[K];
-    int row[K];
+    int rw[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const int j = lane + 64 * i;
       ok[i] = j < cn;
-      row[i] = ok[i] ? s_row[j] : 0;
-      k[i] = (int64_t)s_rp[row[i]] + (c0 + j - s_cp[row[i]]);
+      rw[i] = ok[i] ? s_row[j] : 0;
+      k[i] = (int64_t)s_rs[rw[i]] + (c0 + j - s_cp[rw[i]]);
     }
     EntryLoad<L, K> E;
     load_entries<L, K>(E, A, x_limb, x_hdr, k, ok);
@@ -424,11 +544,11 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     for (int i = 0; i < K; ++i) {
       if (!ok[i] || hdr_is_zero(E.ha[i]) || hdr_is_zero(E.hx[i])) continue;
       const int32_t e = (E.ha[i] >> 1) + (E.hx[i] >> 1);
-      atomicMin(&s_lo[row[i]], e);
-      atomicMax(&s_hi[row[i]], e);
+      atomicMin(&s_lo[rw[i]], e);
+      atomicMax(&s_hi[rw[i]], e);
       uint32_t pr[2 * L];
       mul_full<L>(E.am[i], E.xm[i], pr);
-      ring_add<L, R>(s_win + row[i], RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
+      ring_add<L, R>(s_win + rw[i], RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
     }
     __syncthreads();
   }
@@ -450,8 +570,8 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
       wide = true;
     }
     if (!wide) {
-      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
-      if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
+      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + row);
+      if (A.npair) pair_fold(A, P, yo + row, make_hdr(y.e, y.s));
     }
   }
 
@@ -459,7 +579,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   while (pending) {
     const int owner = __ffsll((unsigned long long)pending) - 1;
     pending &= pending - 1;
-    const int o_rs = s_rp[owner], o_re = s_rp[owner + 1];
+    const int o_rs = __shfl(rs, owner), o_re = __shfl(re, owner);
     int32_t emin = __shfl(lo, owner), emax = __shfl(hi, owner);  // known for a wide short row
     const bool known = __shfl(wide ? 1 : 0, owner) != 0;
     __syncthreads();
@@ -534,8 +654,8 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     }
     if (lane == owner) {
       y = yr;
-      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + r0 + lane);
-      if (A.npair) pair_fold(A, P, yo + r0 + lane, make_hdr(y.e, y.s));
+      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + row);
+      if (A.npair) pair_fold(A, P, yo + row, make_hdr(y.e, y.s));
     }
   }
   if (A.npair) pair_publish(A, P, B.pair);

@@ -103,4 +103,4 @@ def test_batched_solver_host_validation():
 def test_variant_setter_validation():
     from paper_1411_2377_amd import _lib
     f = _lib.LIB.mp_plan_set_variant
-    assert f(None, 0, 0, 16, 0) == _lib.MPS_EINVAL
+    assert f(None, None, 0, 0, 16, 0) == _lib.MPS_EINVAL

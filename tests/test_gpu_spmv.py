@@ -188,10 +188,10 @@ def test_every_kernel_variant_same_bits(p):
         want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
         want_t = ospmv.spmv(tp, ti, tv, go, p, mode)
         for rows in (16, 32, 64):
-            for stage in (False, True):
-                P.set_variant(0, mode, rows, stage)
-                P.set_variant(1, mode, rows, stage)
-                tag = "%d rows per block, staged x %s, mode %d" % (rows, stage, mode)
+            for stage, srt in ((False, False), (True, False), (False, True), (True, True)):
+                P.set_variant(0, mode, rows, stage, srt)
+                P.set_variant(1, mode, rows, stage, srt)
+                tag = "%d rows per block, staged x %s, sorted rows %s, mode %d" % (rows, stage, srt, mode)
                 yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
                 assert_bitwise(yl, yh, want, p, what="A x, " + tag)
                 tl, th = M.mpspmv_csr_t(A, P, g, mode=mode).to_numpy()
