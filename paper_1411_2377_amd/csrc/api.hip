@@ -12,7 +12,7 @@
 #include "../../include/mpspmv.h"
 #include "api_internal.hpp"
 #include "plan_internal.hpp"
-#include "spmv_kernels.hpp"
+#include "spmv_internal.hpp"
 
 namespace mpapi {
 
@@ -54,7 +54,8 @@ int get_ctx(DeviceCtx** out) {
     }
     e = hipMemset(c->status, 0, sizeof(uint32_t) * 4);
     if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
-    int r = dot_work_alloc(1, &c->dot_anchor, &c->dot_win, &c->dot_ticket, nullptr);
+    int r = dot_work_alloc(1, kDotRingLog2, kDotReps, kDotGroups, &c->dot_anchor, &c->dot_win,
+                           &c->dot_ticket, nullptr);
     if (r) return r;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -142,29 +143,9 @@ int default_rows_per_block(int64_t n_rows, int64_t nnz) {
 
 bool valid_rows_per_block(int rpw) { return rpw == 16 || rpw == 32 || rpw == 64; }
 
-template <int L, int RPW>
-static void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.n_rows + RPW - 1) / RPW) * (unsigned)a.nrhs;
-  if (mode == MP_SEQ && a.rows)  // rows by length: the four-wave pipelined kernel
-    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW>), dim3(grid), dim3(256), 0, s, a);
-  else if (mode == MP_SEQ)
-    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_seq_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
-  else
-    MPS_LAUNCH(!a.x_rec, true, (mp::spmv_exact_kernel<L, RPW>), dim3(grid), dim3(64), 0, s, a);
-}
-
-template <int L>
-static void launch_spmv(const mp::SpmvArgs& a, int mode, int rpw, hipStream_t s) {
-  switch (rpw) {
-    case 16: launch_spmv_rpw<L, 16>(a, mode, s); break;
-    case 32: launch_spmv_rpw<L, 32>(a, mode, s); break;
-    default: launch_spmv_rpw<L, 64>(a, mode, s); break;
-  }
-}
-
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s, const SpmvPairs* pairs,
+                const int32_t* done, hipStream_t s, const SpmvFuse* fuse,
                 const SpmvBatch* batch, const SpmvVariant* var) {
   if (n_rows == 0) return MPS_OK;
   const SpmvVariant plain;
@@ -199,23 +180,33 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.pair_of_tile = batch->pair_of_tile;
   a.done_base = batch->done_base;
   a.done_stride = batch->done_stride;
-  a.slots_per_pair = batch->slots_per_pair;
-  a.npair = 0;
-  a.anchor = nullptr;
   a.x_rec = x_rec;
   a.rows = var->rows;
   if (var->rows && batch->nrhs != 1) return fail(MPS_EINVAL, "a row order takes one right-hand side");
-  for (int k = 0; k < 3; ++k) {
-    a.pair_hdr[k] = nullptr;
-    a.pair_slot[k] = 0;
-  }
-  if (pairs && pairs->npair > 0) {
-    a.npair = pairs->npair;
-    a.anchor = pairs->anchor;
-    for (int k = 0; k < pairs->npair; ++k) {
-      a.pair_hdr[k] = pairs->hdr[k];
-      a.pair_slot[k] = pairs->slot[k];
+  a.fd = mp::DotOut{};
+  a.dots = mp::DotWork{};
+  a.S = mp::Scalars{};
+  a.ctl = nullptr;
+  a.tiles_of_pair = nullptr;
+  a.first_tile = nullptr;
+  a.ndone = nullptr;
+  for (int k = 0; k < 3; ++k) a.part[k] = mp::VecRef{};
+  if (fuse && fuse->nd > 0) {
+    if (fuse->nd > 3) return fail(MPS_EINVAL, "at most three inner products per product");
+    a.fd.nd = fuse->nd;
+    a.fd.epi = fuse->epi;
+    a.fd.hist = fuse->hist;
+    for (int k = 0; k < fuse->nd; ++k) {
+      a.part[k] = fuse->part[k];
+      a.fd.slot[k] = fuse->slot[k];
+      a.fd.out[k] = fuse->out[k];
     }
+    a.dots = fuse->dots;
+    a.S = fuse->S;
+    a.ctl = fuse->ctl;
+    a.tiles_of_pair = fuse->tiles_of_pair;
+    a.first_tile = fuse->first_tile;
+    a.ndone = fuse->ndone;
   }
   if (x_rec && x_len > 0) {
     const unsigned g = (unsigned)std::min<int64_t>(16384, (x_len + 255) / 256);
@@ -226,11 +217,15 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
       default: return fail(MPS_EINVAL, "bad limb count");
     }
   }
-  switch (L) {
-    case 4: launch_spmv<4>(a, mode, rpw, s); break;
-    case 8: launch_spmv<8>(a, mode, rpw, s); break;
-    case 16: launch_spmv<16>(a, mode, rpw, s); break;
-    default: return fail(MPS_EINVAL, "bad limb count");
+  if (a.fd.nd > 0) {
+    launch_spmv_fused(L, a, mode, rpw, s);
+  } else {
+    switch (L) {
+      case 4: launch_spmv<4, false>(a, mode, rpw, s); break;
+      case 8: launch_spmv<8, false>(a, mode, rpw, s); break;
+      case 16: launch_spmv<16, false>(a, mode, rpw, s); break;
+      default: return fail(MPS_EINVAL, "bad limb count");
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "spmv launch");

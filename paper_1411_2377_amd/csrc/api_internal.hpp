@@ -38,32 +38,29 @@ struct DeviceCtx {
   uint32_t* dot_ticket = nullptr;
 };
 
-// Inner products of y = A x with other vectors, whose exponent anchors the product kernel fills.
-struct SpmvPairs {
-  int npair = 0;
-  const int32_t* hdr[3] = {nullptr, nullptr, nullptr};  // nullptr: y itself
-  int slot[3] = {0, 0, 0};
-  int32_t* anchor = nullptr;
-};
+struct SpmvFuse;  // spmv_internal.hpp
 
 // Several right-hand sides of a block-diagonal batch in one product launch: x and y hold nrhs
 // segments of rstride elements each; the solve owning a 512-element tile of y decides whether
-// its blocks run (done flags) and where its inner-product anchors go.
+// its blocks run (done flags) and which scalars and inner-product slots they use.
 struct SpmvBatch {
   int nrhs = 1;
   int64_t rstride = 0;
   const int32_t* pair_of_tile = nullptr;
   const int32_t* done_base = nullptr;
   int64_t done_stride = 0;
-  int slots_per_pair = 0;
 };
 
-// int64 digits of one inner-product window slot (largest precision)
-int64_t dot_window_stride();
-// allocate and clear inner-product state: `nslots` slots of `win_stride` digits and
-// nslots + nfinal tickets
-int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s,
-                   int64_t win_stride = 0, int nfinal = 1);
+// Inner-product state (see the exact inner products in solver_kernels.hpp): rings of 2^11 digits
+// (exponent spans up to 32 (2048 - 2L - 2) bits), 32 replicas, tickets in 64 groups; a batch of
+// solves keeps 256-digit rings, 8 replicas and 16 groups per solve.
+constexpr int kDotRingLog2 = 11, kDotReps = 32, kDotGroups = 64;
+constexpr int kBatchRingLog2 = 8, kBatchReps = 8, kBatchGroups = 16;
+
+// Allocate and clear inner-product state: `nslots` slots (each `reps` rings of 2^ring_log2
+// digits and 64 exponent bins) and the tickets of `nsolves` solves.
+int dot_work_alloc(int nslots, int ring_log2, int reps, int ngroups, int32_t** anchor, int64_t** win,
+                   uint32_t** ticket, hipStream_t s, int nsolves = 1);
 
 int fail(int code, const char* fmt, ...);
 void clear_error();
@@ -83,7 +80,7 @@ struct SpmvVariant {
 };
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
-                const int32_t* done, hipStream_t s, const SpmvPairs* pairs = nullptr,
+                const int32_t* done, hipStream_t s, const SpmvFuse* fuse = nullptr,
                 const SpmvBatch* batch = nullptr, const SpmvVariant* var = nullptr);
 // rows per block of the SpMV kernels: 16, 32 or 64 (0 or anything else: chosen from the shape)
 int default_rows_per_block(int64_t n_rows, int64_t nnz);

@@ -8,10 +8,6 @@
 
 namespace mp {
 
-// Inner-product window digits per slot in a batch (spans of products up to about
-// 32 * (kBatchWindowDigits - 2L - 2) bits; wider spans raise kStWindow).
-constexpr int64_t kBatchWindowDigits = 256;
-
 // One solve's vector: the caller's array and the solve's place in the concatenated vector.
 struct PairSeg {
   uint32_t* limb;

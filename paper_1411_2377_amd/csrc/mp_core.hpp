@@ -80,6 +80,8 @@ MPD uint32_t ld_dev(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RE
 MPD int32_t ld_dev(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 MPD void st_dev(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 MPD void st_dev(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MPD int64_t ld_dev(const int64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MPD void st_dev(int64_t* p, int64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Wait until every memory operation this wave has issued is complete.  Device-scope atomics and
 // device-coherent stores are then performed at the device's coherence point, so an atomic the
@@ -88,6 +90,17 @@ MPD void st_dev(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAX
 MPD void wait_memory() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Block barrier that orders LDS accesses only: this wave's LDS (and scalar-load) operations are
+// complete (s_waitcnt lgkmcnt(0); the vector-memory and export counters are left alone), then
+// s_barrier.  Global stores and atomics stay in flight across it (__syncthreads would wait for
+// them: its workgroup fence waits for every outstanding memory operation).
+MPD void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 

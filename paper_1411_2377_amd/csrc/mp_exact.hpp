@@ -81,11 +81,28 @@ struct RingMap {
   MPD int operator()(int w) const { return (s0 + w >= R ? s0 + w - R : s0 + w) * ws; }
 };
 
-// RN_p of (-1)^sgn * sum_{w < nl} win[map(w)] 2^(32 w + base) for magnitude limbs (each digit
+// Window accessors: digit w of a window is read with get(w) and written with set(w, v).
+// MapWin: an LDS or private array through an index map; DevRingWin: a ring of digits in global
+// memory (slot (s0 + w) & mask), read and written with device-coherent accesses.
+template <class Map>
+struct MapWin {
+  int64_t* win;
+  Map map;
+  MPD int64_t get(int w) const { return win[map(w)]; }
+  MPD void set(int w, int64_t v) const { win[map(w)] = v; }
+};
+
+struct DevRingWin {
+  int64_t* win;
+  int mask, s0;
+  MPD int64_t get(int w) const { return ld_dev(win + ((s0 + w) & mask)); }
+  MPD void set(int w, int64_t v) const { st_dev(win + ((s0 + w) & mask), v); }
+};
+
+// RN_p of (-1)^sgn * sum_{w < nl} digit(w) 2^(32 w + base) for magnitude limbs (each digit
 // holds a 32-bit limb; limb nl-1 is the top non-zero one, nl == 0 means zero).
-template <int L, class Map>
-MPD Num<L> limbs_round_map(const int64_t* win, Map map, int nl, uint32_t sgn, int64_t base,
-                           uint32_t& st) {
+template <int L, class Acc>
+MPD Num<L> limbs_round_acc(const Acc& a, int nl, uint32_t sgn, int64_t base, uint32_t& st) {
   const int W = nl;
   const int top = nl - 1;
   Num<L> out;
@@ -93,10 +110,10 @@ MPD Num<L> limbs_round_map(const int64_t* win, Map map, int nl, uint32_t sgn, in
     set_zero(out, 0);
     return out;
   }
-  const int T = 32 * top + 31 - (int)__clz((uint32_t)win[map(top)]);  // leading bit index
-  const int b0 = T - 32 * L + 1;                                       // mantissa LSB index
+  const int T = 32 * top + 31 - (int)__clz((uint32_t)a.get(top));  // leading bit index
+  const int b0 = T - 32 * L + 1;                                     // mantissa LSB index
   auto limb_at = [&](int idx) -> uint32_t {
-    return (idx >= 0 && idx < W) ? (uint32_t)win[map(idx)] : 0u;
+    return (idx >= 0 && idx < W) ? (uint32_t)a.get(idx) : 0u;
   };
   auto bits_at = [&](int b) -> uint32_t {  // the 32 bits starting at bit index b (b may be < 0)
     if (b <= -32) return 0u;
@@ -134,38 +151,46 @@ MPD Num<L> limbs_round_map(const int64_t* win, Map map, int nl, uint32_t sgn, in
   return out;
 }
 
+template <int L, class Map>
+MPD Num<L> limbs_round_map(const int64_t* win, Map map, int nl, uint32_t sgn, int64_t base,
+                           uint32_t& st) {
+  return limbs_round_acc<L>(MapWin<Map>{const_cast<int64_t*>(win), map}, nl, sgn, base, st);
+}
+
 template <int L>
 MPD Num<L> limbs_round(const int64_t* win, int nl, uint32_t sgn, int64_t base, uint32_t& st,
                        int ws = 1) {
   return limbs_round_map<L>(win, StrideMap{ws}, nl, sgn, base, st);
 }
 
-// RN_p of the window value sum_w win[map(w)] * 2^(32 w + base) over W digits.  The digits are
+// RN_p of the window value sum_w digit(w) * 2^(32 w + base) over W digits.  The digits are
 // overwritten (they end up holding the 32-bit limbs of the magnitude).  An exact zero gives +0.
-template <int L, class Map>
-MPD Num<L> window_finalize_map(int64_t* win, Map map, int W, int64_t base, uint32_t& st) {
+template <int L, class Acc>
+MPD Num<L> window_finalize_acc(const Acc& a, int W, int64_t base, uint32_t& st) {
   int64_t c = 0;
   for (int w = 0; w < W; ++w) {
-    const int64_t t = win[map(w)] + c;
-    win[map(w)] = (int64_t)(uint32_t)t;
+    const int64_t t = a.get(w) + c;
+    a.set(w, (int64_t)(uint32_t)t);
     c = t >> 32;
   }
   const uint32_t sgn = (c < 0) ? 1u : 0u;
   if (sgn) {
     uint32_t cy = 1;
-    for (int w = 0; w < W; ++w) {
-      const uint32_t v = __builtin_addc(~(uint32_t)win[map(w)], 0u, cy, &cy);
-      win[map(w)] = (int64_t)v;
-    }
+    for (int w = 0; w < W; ++w) a.set(w, (int64_t)__builtin_addc(~(uint32_t)a.get(w), 0u, cy, &cy));
   }
   int top = -1;
   for (int w = W - 1; w >= 0; --w) {
-    if ((uint32_t)win[map(w)] != 0u) {
+    if ((uint32_t)a.get(w) != 0u) {
       top = w;
       break;
     }
   }
-  return limbs_round_map<L>(win, map, top + 1, sgn, base, st);
+  return limbs_round_acc<L>(a, top + 1, sgn, base, st);
+}
+
+template <int L, class Map>
+MPD Num<L> window_finalize_map(int64_t* win, Map map, int W, int64_t base, uint32_t& st) {
+  return window_finalize_acc<L>(MapWin<Map>{win, map}, W, base, st);
 }
 
 template <int L>

@@ -19,6 +19,7 @@
 #include "api_internal.hpp"
 #include "plan_internal.hpp"
 #include "batch_kernels.hpp"
+#include "spmv_internal.hpp"
 #include "solver_kernels.hpp"
 #include "vec_internal.hpp"
 
@@ -162,9 +163,12 @@ struct Work {
   int npairs = 1;
   int nrhs = 1;
   int64_t rstride = 0;       // batch: elements per right-hand side (all systems, padded)
-  int64_t win_stride = 0;    // inner-product window digits per slot (0: the default)
+  int ring_log2 = kDotRingLog2;  // inner-product rings: 2^ring_log2 digits, reps replicas,
+  int reps = kDotReps;           // tickets in ngroups groups
+  int ngroups = kDotGroups;
   int32_t* pair_of_tile = nullptr;
   int32_t* tiles_of_pair = nullptr;
+  int32_t* first_tile = nullptr;
   int32_t* ndone = nullptr;
   int32_t* h_ndone = nullptr;  // pinned
   uint32_t* vlimb = nullptr;
@@ -198,10 +202,14 @@ struct Work {
     return v;
   }
   bool batched() const { return pair_of_tile != nullptr; }
+  mp::DotWork dots() const {
+    return dot_work(anchor, win, ticket, npairs * mp::kDotSlots, ring_log2, reps, ngroups);
+  }
   mp::BatchMap batch_map() const {
     mp::BatchMap b;
     b.pair_of_tile = pair_of_tile;
     b.tiles_of_pair = tiles_of_pair;
+    b.first_tile = first_tile;
     b.ndone = ndone;
     return b;
   }
@@ -211,6 +219,7 @@ struct Work {
     if (ws) hipStreamSynchronize(ws);
     hipFree(pair_of_tile);
     hipFree(tiles_of_pair);
+    hipFree(first_tile);
     hipFree(ndone);
     if (h_ndone) hipHostFree(h_ndone);
     hipFree(vlimb);
@@ -252,8 +261,8 @@ int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
   if (e == hipSuccess) e = hipStreamWaitEvent(W.ws, W.ev, 0);
   if (e == hipSuccess && W.ndone) e = hipMemsetAsync(W.ndone, 0, sizeof(int32_t), W.ws);
   if (e != hipSuccess) return hip_fail(e, "solver setup");
-  int r = dot_work_alloc(W.npairs * mp::kDotSlots, &W.anchor, &W.win, &W.ticket, W.ws, W.win_stride,
-                         W.npairs);
+  int r = dot_work_alloc(W.npairs * mp::kDotSlots, W.ring_log2, W.reps, W.ngroups, &W.anchor, &W.win,
+                         &W.ticket, W.ws, W.npairs);
   if (r) return r;
   // every scalar slot starts as +0
   mp::VecArgs a{};
@@ -314,7 +323,7 @@ struct Op {
 // y = Aop x on the workspace stream; `gated`: a no-op once the solve is done (for a batch,
 // the blocks of finished solves return at once).
 int apply(const Work& W, const Op& op, int mode, const mp::VecRef& x, const mp::VecRef& y,
-          uint32_t* status, bool gated, const SpmvPairs* pairs = nullptr) {
+          uint32_t* status, bool gated, const SpmvFuse* fuse = nullptr) {
   mp_vec xv{x.limb, x.hdr, 0, x.ld}, yv{y.limb, y.hdr, 0, y.ld};
   if (W.batched()) {
     SpmvBatch b;
@@ -323,38 +332,55 @@ int apply(const Work& W, const Op& op, int mode, const mp::VecRef& x, const mp::
     b.pair_of_tile = W.pair_of_tile;
     b.done_base = &W.ctl->done;
     b.done_stride = (int64_t)(sizeof(mp::Ctl) / sizeof(int32_t));
-    b.slots_per_pair = mp::kDotSlots;
     return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                       nullptr, W.ws, pairs, &b, &op.var[mode]);
+                       nullptr, W.ws, fuse, &b, &op.var[mode]);
   }
   return spmv_launch(W.L, op.n_out, op.row_ptr, op.col_idx, op.val, xv, yv, mode, status,
-                     gated ? &W.ctl->done : nullptr, W.ws, pairs, nullptr, &op.var[mode]);
+                     gated ? &W.ctl->done : nullptr, W.ws, fuse, nullptr, &op.var[mode]);
 }
 
-// Inner products of an SpMV output with up to three vectors (nullptr: the output itself).
-SpmvPairs pairs_of(const Work& W, std::initializer_list<std::pair<const int32_t*, int>> list) {
-  SpmvPairs P;
-  P.anchor = W.anchor;
+// Inner products of an SpMV output y with up to three vectors ({nullptr}: y itself), each
+// {partner, slot, scalar}; the launch's last block rounds them and runs epilogue epi.
+struct FuseItem {
+  mp::VecRef part;
+  int slot;
+  int scalar;
+};
+
+SpmvFuse fuse_of(const Work& W, int epi, std::initializer_list<FuseItem> list,
+                 const mp::VecRef& hist = mp::VecRef{nullptr, nullptr, 0}) {
+  SpmvFuse F;
   for (auto& it : list) {
-    P.hdr[P.npair] = it.first;
-    P.slot[P.npair] = it.second;
-    ++P.npair;
+    F.part[F.nd] = it.part;
+    F.slot[F.nd] = it.slot;
+    F.out[F.nd] = mp::slot_ref(W.S, it.scalar);
+    ++F.nd;
   }
-  return P;
+  F.epi = epi;
+  F.hist = hist;
+  F.dots = W.dots();
+  F.S = W.S;
+  F.ctl = W.ctl;
+  F.tiles_of_pair = W.tiles_of_pair;
+  F.first_tile = W.first_tile;
+  F.ndone = W.ndone;
+  return F;
 }
 
 mp::DotArgs dot_args(const Work& W, uint32_t* status, int epi) {
   mp::DotArgs a{};
   a.n = W.n;
   a.S = W.S;
-  a.w = dot_work(W.anchor, W.win, W.ticket, W.npairs * mp::kDotSlots, W.win_stride);
+  a.w = W.dots();
   a.ctl = W.ctl;
   a.status = status;
-  a.epi = epi;
+  a.o.epi = epi;
   a.batch = W.batch_map();
   return a;
 }
 
+// Element-wise step arguments; `fd`: the inner products the kernel forms ({slot, scalar} each)
+// and the epilogue its launch ends with.
 mp::VecArgs ew_args(const Work& W, uint32_t* status) {
   mp::VecArgs a{};
   a.n = W.n;
@@ -362,7 +388,20 @@ mp::VecArgs ew_args(const Work& W, uint32_t* status) {
   a.ctl = W.ctl;
   a.status = status;
   a.batch = W.batch_map();
+  a.dots = W.dots();
   return a;
+}
+
+void set_fd(const Work& W, mp::VecArgs& a, int epi, std::initializer_list<std::pair<int, int>> list,
+            const mp::VecRef& hist = mp::VecRef{nullptr, nullptr, 0}) {
+  a.fd.nd = 0;
+  for (auto& it : list) {
+    a.fd.slot[a.fd.nd] = it.first;
+    a.fd.out[a.fd.nd] = mp::slot_ref(W.S, it.second);
+    ++a.fd.nd;
+  }
+  a.fd.epi = epi;
+  a.fd.hist = hist;
 }
 
 int check_solve_args(const mp_csr* A, const mp_vec* b, const mp_vec* x, const mp_solve_opts* o,
@@ -414,20 +453,17 @@ int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_sol
   }
   a.v[0] = W.vec(1);
   a.v[1] = W.vec(0);
-  a.anchor = W.anchor;
-  a.aslot[0] = 1;
-  a.aslot[1] = 2;
-  if ((r = launch_ew(L, EW_COPY_ANCHOR, a, W.ws))) return r;
+  if ((r = launch_ew(L, EW_COPY, a, W.ws))) return r;
   mp::DotArgs d = dot_args(W, status, mp::EPI_SETUP);
-  d.nd = 2;
+  d.o.nd = 2;
   d.x[0] = W.vec(0);
   d.y[0] = W.vec(0);
-  d.out[0] = mp::slot_ref(W.S, mp::S_Q0);
-  d.slot[0] = 1;
+  d.o.out[0] = mp::slot_ref(W.S, mp::S_Q0);
+  d.o.slot[0] = 1;
   d.x[1] = W.vec(1);
   d.y[1] = W.vec(0);
-  d.out[1] = mp::slot_ref(W.S, mp::S_RHO);
-  d.slot[1] = 2;
+  d.o.out[1] = mp::slot_ref(W.S, mp::S_RHO);
+  d.o.slot[1] = 2;
   return launch_dot(L, d, W.ws);
 }
 
@@ -565,33 +601,24 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
   const mp::VecRef X = ref(*x);
   mp::VecRef hist{nullptr, nullptr, 0};
   if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
-  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 2);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
+  // per iteration: directions; z = A p with sigma = (pt, z) (its last block forms alpha);
+  // zt = A^T pt; the updates with (r, r) and (rt, r) (its last block: stopping test, beta)
   auto iteration = [&]() -> int {
     int rr;
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
     if ((rr = timed(W, PROF_VEC, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
       return rr;
-    const SpmvPairs sig = pairs_of(W, {{PT.hdr, 0}});
-    if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
+    const SpmvFuse sig = fuse_of(W, mp::EPI_BICG_SIGMA, {{PT, 0, mp::S_SIGMA}});
+    if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
       return rr;
     if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, opT, o->mode, PT, ZT, st, true); })))
       return rr;
-    mp::DotArgs d = dot_args(W, st, mp::EPI_BICG_SIGMA);
-    d.nd = 1;
-    d.x[0] = PT; d.y[0] = Z; d.out[0] = mp::slot_ref(W.S, mp::S_SIGMA); d.slot[0] = 0;
-    if ((rr = timed(W, PROF_DOT, dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
     a = ew_args(W, st);
     a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
-    a.anchor = W.anchor; a.aslot[0] = 1; a.aslot[1] = 2;
-    if ((rr = timed(W, PROF_VEC, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); })))
-      return rr;
-    d = dot_args(W, st, mp::EPI_BICG_CONV);
-    d.nd = 2;
-    d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
-    d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
-    d.hist = hist;
-    return timed(W, PROF_DOT, 2 * dot1, [&] { return launch_dot(L, d, W.ws); });
+    set_fd(W, a, mp::EPI_BICG_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
+    return timed(W, PROF_VEC, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); });
   };
   if ((r = run_iterations(W, o, iteration))) return r;
   return finish_solve(W, info, st);
@@ -616,49 +643,37 @@ int gp_clear(const Work& W, uint32_t* st) {
 int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, const mp::VecRef& hist,
                  uint32_t* st, double sp_bytes) {
   const int L = W.L;
-  const double dot1 = vec_bytes(W, 2);
+  const double dot1 = vec_bytes(W, 1);
   const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), Q = W.vec(4), T = W.vec(5),
                    V = W.vec(6), S = W.vec(7), Wv = W.vec(8), Y = W.vec(9), U = W.vec(10),
                    Z = W.vec(11);
+  const mp::VecRef self{nullptr, nullptr, 0};
   int rr;
   mp::VecArgs a = ew_args(W, st);
   a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
-  const SpmvPairs den = pairs_of(W, {{RT.hdr, 0}});
-  if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
-  mp::DotArgs d = dot_args(W, st, mp::EPI_GP_ALPHA);
-  d.nd = 1;
-  d.x[0] = RT; d.y[0] = Q; d.out[0] = mp::slot_ref(W.S, mp::S_DEN); d.slot[0] = 0;
-  if ((rr = timed(W, PROF_DOT, dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
+  // q = A p with (rt, q) (its last block forms alpha)
+  const SpmvFuse den = fuse_of(W, mp::EPI_GP_ALPHA, {{RT, 0, mp::S_DEN}});
+  if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
+  // t, s, y with (y, y) and (y, t)
   a = ew_args(W, st);
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
-  a.anchor = W.anchor; a.aslot[0] = 3; a.aslot[1] = 5;   // (y, y), (y, t)
+  set_fd(W, a, mp::EPI_NONE, {{3, mp::S_MU1}, {5, mp::S_MU3}});
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
-  const SpmvPairs mus = pairs_of(W, {{T.hdr, 4}, {Y.hdr, 6}, {nullptr, 7}});  // (v,t) (v,y) (v,v)
-  if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
-  d = dot_args(W, st, mp::EPI_GP_ZETA);
-  d.nd = 5;
-  d.x[0] = Y; d.y[0] = Y; d.out[0] = mp::slot_ref(W.S, mp::S_MU1); d.slot[0] = 3;
-  d.x[1] = V; d.y[1] = T; d.out[1] = mp::slot_ref(W.S, mp::S_MU2); d.slot[1] = 4;
-  d.x[2] = Y; d.y[2] = T; d.out[2] = mp::slot_ref(W.S, mp::S_MU3); d.slot[2] = 5;
-  d.x[3] = V; d.y[3] = Y; d.out[3] = mp::slot_ref(W.S, mp::S_MU4); d.slot[3] = 6;
-  d.x[4] = V; d.y[4] = V; d.out[4] = mp::slot_ref(W.S, mp::S_MU5); d.slot[4] = 7;
-  if ((rr = timed(W, PROF_DOT, 5 * dot1, [&] { return launch_dot(L, d, W.ws); }))) return rr;
+  // v = A t with (v, t), (v, y), (v, v) (its last block forms zeta and eta)
+  const SpmvFuse mus =
+      fuse_of(W, mp::EPI_GP_ZETA, {{T, 4, mp::S_MU2}, {Y, 6, mp::S_MU4}, {self, 7, mp::S_MU5}});
+  if ((rr = timed(W, PROF_SPMV, sp_bytes + 2 * dot1, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
+  // u, z, x, r with (r, r) and (rt, r) (its last block: stopping test, beta)
   mp::GpUpdArgs g{};
   g.a = ew_args(W, st);
   g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
   g.a.v[6] = P; g.a.v[7] = T;
-  g.a.anchor = W.anchor; g.a.aslot[0] = 1; g.a.aslot[1] = 2;
+  set_fd(W, g.a, mp::EPI_GP_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
   g.y = Y;
   g.v = V;
   g.rt = RT;
-  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); }))) return rr;
-  d = dot_args(W, st, mp::EPI_GP_CONV);
-  d.nd = 2;
-  d.x[0] = R; d.y[0] = R; d.out[0] = mp::slot_ref(W.S, mp::S_Q); d.slot[0] = 1;
-  d.x[1] = RT; d.y[1] = R; d.out[1] = mp::slot_ref(W.S, mp::S_RHO_NEXT); d.slot[1] = 2;
-  d.hist = hist;
-  return timed(W, PROF_DOT, 2 * dot1, [&] { return launch_dot(L, d, W.ws); });
+  return timed(W, PROF_VEC, vec_bytes(W, 16), [&] { return launch_gp_update(L, g, W.ws); });
 }
 
 int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
@@ -823,7 +838,7 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   const int64_t n = rstride * nrhs;
   const int64_t ntiles = n / mp::kTile;
   if (ntiles > INT32_MAX / 2) return fail(MPS_ENOTSUP, "batch too large");
-  std::vector<int32_t> pot((size_t)ntiles), top((size_t)npairs64);
+  std::vector<int32_t> pot((size_t)ntiles), top((size_t)npairs64), ftp((size_t)npairs64);
   std::vector<mp::PairSeg> seg_b((size_t)npairs64), seg_x((size_t)npairs64);
   for (int k = 0; k < nrhs; ++k)
     for (int sy = 0; sy < nsys; ++sy) {
@@ -832,6 +847,7 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
       const int64_t nt = (row_off[sy + 1] - row_off[sy]) / mp::kTile;
       for (int64_t t = 0; t < nt; ++t) pot[(size_t)(off / mp::kTile + t)] = pair;
       top[pair] = (int32_t)nt;
+      ftp[pair] = (int32_t)(off / mp::kTile);
       seg_b[pair] = mp::PairSeg{b[pair].limb, b[pair].hdr, b[pair].ld, A[sy].row_dim, off};
       seg_x[pair] = mp::PairSeg{x[pair].limb, x[pair].hdr, x[pair].ld, A[sy].row_dim, off};
     }
@@ -839,10 +855,13 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   W.npairs = (int)npairs64;
   W.nrhs = nrhs;
   W.rstride = rstride;
-  W.win_stride = mp::kBatchWindowDigits;
+  W.ring_log2 = kBatchRingLog2;
+  W.reps = kBatchReps;
+  W.ngroups = kBatchGroups;
   mp::PairSeg* d_seg = nullptr;
   hipError_t e = hipMalloc((void**)&W.pair_of_tile, pot.size() * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&W.tiles_of_pair, top.size() * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&W.first_tile, ftp.size() * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&d_seg, 2 * seg_b.size() * sizeof(mp::PairSeg));
   struct SegFree {
     mp::PairSeg* p;
@@ -853,6 +872,7 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   if ((r = work_alloc(W, L, n, kGpVectors + 2, user))) return r;
   e = hipMemcpyAsync(W.pair_of_tile, pot.data(), pot.size() * 4, hipMemcpyHostToDevice, W.ws);
   if (e == hipSuccess) e = hipMemcpyAsync(W.tiles_of_pair, top.data(), top.size() * 4, hipMemcpyHostToDevice, W.ws);
+  if (e == hipSuccess) e = hipMemcpyAsync(W.first_tile, ftp.data(), ftp.size() * 4, hipMemcpyHostToDevice, W.ws);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_seg, seg_b.data(), seg_b.size() * sizeof(mp::PairSeg), hipMemcpyHostToDevice, W.ws);
   if (e == hipSuccess)

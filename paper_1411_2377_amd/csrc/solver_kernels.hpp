@@ -56,6 +56,7 @@ constexpr int kTile = 512;
 struct BatchMap {
   const int32_t* pair_of_tile;   // nullptr: a single solve
   const int32_t* tiles_of_pair;  // tiles in each solve's segment
+  const int32_t* first_tile;     // first tile of each solve's segment
   int32_t* ndone;                // incremented once per solve that finishes
 };
 
@@ -119,7 +120,7 @@ enum Epi {
 };
 
 template <int L>
-MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint32_t& st) {
+MPD void epilogue_body(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint32_t& st) {
   if (!ctl || epi == EPI_NONE) return;
   switch (epi) {
     case EPI_SETUP: {
@@ -222,44 +223,59 @@ MPD void epilogue(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint3
   }
 }
 
+// The epilogue as one out-of-line function per precision (it is large and runs once per launch,
+// in one thread).  Only plain values cross the call, so no caller object needs an address.
+template <int L>
+__device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* s_limb, int32_t* s_hdr,
+                                                      int64_t s_ld, Ctl* ctl, uint32_t* h_limb,
+                                                      int32_t* h_hdr, int64_t h_ld) {
+  const Scalars S{s_limb, s_hdr, s_ld};
+  VecRef hist;
+  hist.limb = h_limb;
+  hist.hdr = h_hdr;
+  hist.ld = h_ld;
+  uint32_t st = 0;
+  epilogue_body<L>(epi, S, ctl, hist, st);
+  return st;
+}
+
 // ------------------------------------------------------------------------------------------
 // Exact inner products.
 //
-// Every inner product owns a slot: an exponent anchor (the smallest and largest e_x + e_y over
-// its non-zero products, kept with integer atomic min/max), a global carry-save window of int64
-// digits, and an integer ticket.  The kernel that *produces* the operands fills the anchor while
-// it writes them (the SpMV for products with its output, the vector updates for theirs), so the
-// inner-product kernel starts with a global anchor: each block accumulates its exact products in
-// per-lane LDS windows, sums them digit by digit and adds the digit sums to the slot's window
-// with integer atomics (associative, hence order-independent and deterministic).  The last block
-// rounds the window once, clears the slot for its next use and, once every inner product of the
-// launch is done, runs the driver epilogue.  Lane windows are padded to an odd stride so that the
-// per-lane adds and the per-digit sums hit distinct LDS banks.
+// Every inner product owns a slot: a ring of int64 carry-save digits in global memory, 64
+// exponent bins and (per solve) a ticket.  Digit d of an exact sum has weight 2^(32 d - 2p) and
+// lives at ring position d mod 2^ring_log2, so a digit's place never depends on the other
+// products and no exponent anchor is needed before accumulating.  Any kernel that holds both
+// operands adds to a slot one "pass" at a time: a block forms one exact product per thread,
+// finds the pass's exponent range, sums the products digit by digit in LDS and adds the sums
+// to the ring with integer atomics (replicated `reps` times, by block, to spread contention),
+// and folds its exponent range into the bins with integer atomic min/max.  Integer addition is
+// associative, so the ring's content does not depend on the order of blocks or passes.  The
+// last block of a launch (ticket) reads the bins, checks that the whole range fits the ring,
+// takes the digits out of the ring (clearing it for the next use) and rounds once.
 // ------------------------------------------------------------------------------------------
 constexpr int kDotMaxND = 5;
-constexpr int kDotMaxBlocks = 128;
 constexpr int kDotThreads = 256;
-constexpr int kDotStride = kDotThreads + 1;
 constexpr int kDotSlots = 8;
-
-// block-shared window capacity (the per-lane windows' LDS reused as one array)
-template <int L>
-constexpr int dot_shared_digits() { return window_fast_digits<L>() * kDotStride; }
-
-// Per-solve (or per-context) inner-product state.
-// Anchors are spread over kAnchorBins bins per slot (a producing wave updates bin
-// wave-index mod kAnchorBins) so that a thousand producing waves do not contend on one address;
-// the inner-product kernel reduces the bins.
 constexpr int kAnchorBins = 64;
 
 struct DotWork {
-  int32_t* anchor;    // [nslots][kAnchorBins][2]: emin, emax; (INT32_MAX, INT32_MIN) when empty
-  int64_t* win;       // [nslots][win_stride] carry-save digits, zero between uses
-  uint32_t* ticket;   // [nslots + number of solves]: entry nslots + k counts the finished blocks
-                      // of solve k's current launch
-  int64_t win_stride; // >= dot_shared_digits<L>()
+  int32_t* anchor;   // [nslots][kAnchorBins][2]: emin, emax; (INT32_MAX, INT32_MIN) when empty
+  int64_t* win;      // [nslots][reps][1 << ring_log2] carry-save digits, zero between uses
+  uint32_t* ticket;  // per solve, ngroups + 1 counters kTicketStride words apart (zero between
+                     // launches): the finished blocks of each group, then the finished groups
+  int ring_log2;
+  int reps;          // a power of two
+  int ngroups;       // a power of two
   int nslots;
 };
+
+// Counters on separate cache lines: atomics on one line are serialised.
+constexpr int kTicketStride = 32;
+
+MPD int64_t* slot_ring(const DotWork& w, int64_t slot) {
+  return w.win + slot * ((int64_t)w.reps << w.ring_log2);
+}
 
 MPD int32_t wave_min(int32_t v) {
 #pragma unroll
@@ -273,254 +289,308 @@ MPD int32_t wave_max(int32_t v) {
   return v;
 }
 
-// Fold the exponent of the product of two headers into a running (emin, emax).
-MPD void pair_exponent(int32_t h1, int32_t h2, int32_t& emin, int32_t& emax) {
-  if (!hdr_is_zero(h1) && !hdr_is_zero(h2)) {
-    const int32_t e = (h1 >> 1) + (h2 >> 1);
-    emin = min(emin, e);
-    emax = max(emax, e);
-  }
-}
+// Windows of at most this many digits are summed without atomics (one digit per thread group).
+constexpr int kPassDigits = 64;
+// Most ring replicas a slot may have.
+constexpr int kMaxReps = 32;
 
-// Publish a block's (emin, emax) to an anchor slot: wave reduction, then one lane per wave
-// (an integer min/max is order-independent).
-MPD int anchor_bin() {
-  return (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kAnchorBins - 1));
-}
-
-MPD void anchor_publish(int32_t* anchor, int slot, int32_t emin, int32_t emax) {
-  emin = wave_min(emin);
-  emax = wave_max(emax);
-  if ((threadIdx.x & 63) == 0 && emax >= emin) {
-    int32_t* a = anchor + 2 * ((int64_t)slot * kAnchorBins + anchor_bin());
-    atomicMin(&a[0], emin);
-    atomicMax(&a[1], emax);
-  }
-}
-
-struct DotArgs {
-  int64_t n;
-  int nd;
-  VecRef x[kDotMaxND];
-  VecRef y[kDotMaxND];
-  VecRef out[kDotMaxND];  // result d goes to element 0 of out[d]
-  int slot[kDotMaxND];
-  DotWork w;
-  Scalars S;
-  Ctl* ctl;  // nullable
-  uint32_t* status;
-  int epi;
-  VecRef hist;
-  BatchMap batch;  // batch.pair_of_tile == nullptr: one solve
+template <int L, int NT>
+struct PassLds {
+  int64_t dwin[kPassDigits];  // the window of a narrow pass
+  // block-shared window of a wide pass, or of a rounding
+  int64_t win[((2 * L + 1) * (NT + 1) + 1) / 2];
+  int32_t red[2 * (NT / 64)];
 };
 
-// Anchor (smallest and largest e_x + e_y) of inner-product slot `slot`, its bins reduced by one
-// wave; every lane gets it.
-static_assert(kAnchorBins == 64, "one anchor bin per lane");
-MPD void wave_anchor(const int32_t* anchor, int64_t slot, int32_t& emin, int32_t& emax) {
-  const int32_t* b = anchor + 2 * (slot * kAnchorBins + (threadIdx.x & 63));
-  emin = wave_min(ld_dev(b));
-  emax = wave_max(ld_dev(b + 1));
-}
+// Digits of the block-shared window a wide pass or a rounding can hold in LDS.
+template <int L, int NT>
+constexpr int lds_window_digits() { return ((2 * L + 1) * (NT + 1) + 1) / 2; }
 
-// The two elements a thread takes per step: headers and limbs are loaded together (the limbs of
-// a zero are loaded too, so no load waits for a header).
-template <int L>
-struct DotElems {
-  int32_t hx[2], hy[2];
-  uint32_t x[2][L], y[2][L];
-};
-
-template <int L>
-MPD void dot_load(DotElems<L>& E, const VecRef& X, const VecRef& Y, int64_t i0, int64_t i1, bool h0,
-                  bool h1) {
-  const int32_t z = (int32_t)0x80000000;  // +0
-  E.hx[0] = h0 ? X.hdr[i0] : z;
-  E.hy[0] = h0 ? Y.hdr[i0] : z;
-  E.hx[1] = h1 ? X.hdr[i1] : z;
-  E.hy[1] = h1 ? Y.hdr[i1] : z;
+// a[k] <- a[(k + r) mod D] for every k (a lane-dependent rotation of a register array, in
+// log2 D conditional steps, so that no register is indexed by a lane-varying value).
+template <int D>
+MPD void rotate_digits(uint32_t (&a)[D], int r) {
 #pragma unroll
-  for (int q = 0; q < L; ++q) {
-    E.x[0][q] = h0 ? X.limb[(int64_t)q * X.ld + i0] : 0u;
-    E.y[0][q] = h0 ? Y.limb[(int64_t)q * Y.ld + i0] : 0u;
-    E.x[1][q] = h1 ? X.limb[(int64_t)q * X.ld + i1] : 0u;
-    E.y[1][q] = h1 ? Y.limb[(int64_t)q * Y.ld + i1] : 0u;
+  for (int b = 1; b < D; b <<= 1) {
+    if (r & b) {
+      uint32_t t[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) t[k] = a[(k + b) % D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) a[k] = t[k];
+    }
   }
 }
 
-template <int L>
-__global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
-  constexpr int WF = window_fast_digits<L>();
-  constexpr int WB = dot_shared_digits<L>();
-  constexpr int WMAXF = 2 * L + 16;  // final windows up to this size are carried in registers
-  __shared__ int64_t s_win[WB];
-  __shared__ uint32_t s_last;
-  // batch: block = one tile of one solve; otherwise a grid-stride pass over the whole vector
-  const bool batched = A.batch.pair_of_tile != nullptr;
-  const int pair = batched ? A.batch.pair_of_tile[blockIdx.x] : 0;
-  Ctl* const ctl = A.ctl ? A.ctl + pair : nullptr;
-  if (solve_done(ctl)) return;
-  const Scalars S = A.S.at(pair);
-  const int t = threadIdx.x;
-  uint32_t st = 0;
-  const int d = blockIdx.y;  // the inner products of one launch run side by side, one row each
-  const int64_t slot0 = (int64_t)pair * kDotSlots;
-  const unsigned nblocks = batched ? (unsigned)A.batch.tiles_of_pair[pair] : gridDim.x;
-
-  // first elements in flight while the anchor is reduced (operands picked by comparison: a
-  // dynamic index into the argument arrays would copy them to scratch memory)
-  VecRef X = A.x[0], Y = A.y[0];
-  int dslot = A.slot[0];
-#pragma unroll
-  for (int k = 1; k < kDotMaxND; ++k) {
-    if (k == d) {
-      X = A.x[k];
-      Y = A.y[k];
-      dslot = A.slot[k];
-    }
+// Add sum_u x_u * y_u over the block's NT threads (ok == false: no product) to the ring of
+// `slot`, exactly.  Called by every thread of the block (it synchronises the block).
+template <int L, int NT>
+MPD void pass_dot(PassLds<L, NT>& S, bool ok, int32_t hx, int32_t hy, const uint32_t (&x)[L],
+                  const uint32_t (&y)[L], const DotWork& dw, int64_t slot) {
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  constexpr int NW = NT / 64;
+  constexpr int G = kPassDigits;
+  static_assert(NT >= G, "a thread per window digit");
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const bool nz = ok && !hdr_is_zero(hx) && !hdr_is_zero(hy);
+  const int32_t e = nz ? (hx >> 1) + (hy >> 1) : 0;
+  int32_t lo = wave_min(nz ? e : INT32_MAX), hi = wave_max(nz ? e : INT32_MIN);
+  if (t < G) S.dwin[t] = 0;
+  if (lane == 0) {
+    S.red[wv] = lo;
+    S.red[NW + wv] = hi;
   }
-  const int64_t stride = batched ? (int64_t)(kTile / 2) : (int64_t)gridDim.x * kDotThreads;
-  const int64_t n_end = batched ? (int64_t)(blockIdx.x + 1) * kTile : A.n;
-  int64_t i0 = batched ? (int64_t)blockIdx.x * kTile + t : (int64_t)blockIdx.x * kDotThreads + t;
-  DotElems<L> E;
-  dot_load<L>(E, X, Y, i0, i0 + stride, i0 < n_end, i0 + stride < n_end);
-
-  int32_t emin, emax;
-  wave_anchor(A.w.anchor, slot0 + dslot, emin, emax);
-  int64_t* gw = A.w.win + (slot0 + dslot) * A.w.win_stride;
-  const bool any = emax >= emin;
-  const int W = any ? window_digits<L>(emin, emax) : 0;
-  const bool fits = W <= WB && W <= A.w.win_stride;
-  if (any && !fits) st |= kStWindow;
-  if (any && fits) {
-    const bool fast = W <= WF;
-    if (fast) {
-      for (int w = 0; w < WF; ++w) s_win[w * kDotStride + t] = 0;
-    } else {
-      for (int w = t; w < W; w += kDotThreads) s_win[w] = 0;
-      __syncthreads();
-    }
-    while (true) {
+  lds_barrier();
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        if (!hdr_is_zero(E.hx[k]) && !hdr_is_zero(E.hy[k])) {
-          uint32_t pr[2 * L];
-          mul_full<L>(E.x[k], E.y[k], pr);
-          const uint32_t off = (uint32_t)((E.hx[k] >> 1) + (E.hy[k] >> 1) - emin);
-          const uint32_t sg = (uint32_t)(E.hx[k] ^ E.hy[k]) & 1u;
-          if (fast) window_add<L>(s_win + t, kDotStride, pr, sg, off);
-          else window_add_atomic<L>(s_win, pr, sg, off);
-        }
+  for (int k = 0; k < NW; ++k) {
+    lo = min(lo, S.red[k]);
+    hi = max(hi, S.red[NW + k]);
+  }
+  if (hi < lo) {  // no non-zero product in this pass (the same for every thread)
+    lds_barrier();
+    return;
+  }
+  const int W = (int)(((int64_t)hi - (lo & ~31)) >> 5) + 2 * L + 2;
+  const int64_t mask = ((int64_t)1 << dw.ring_log2) - 1;
+  int64_t* const ring =
+      slot_ring(dw, slot) + ((int64_t)(blockIdx.x & (unsigned)(dw.reps - 1)) << dw.ring_log2);
+  uint32_t pr[2 * L], sp[2 * L + 1];
+  uint32_t sg = 0;
+  if (nz) {
+    mul_full<L>(x, y, pr);
+    sg = (uint32_t)(hx ^ hy) & 1u;
+    shift_product<L>(pr, (uint32_t)e & 31u, sp);  // window digits are ring digits: bit e & 31
+  }
+  if (W <= G) {
+    // narrow pass: the products' digits are added into a window of G digits in LDS.  Lane t adds
+    // its 2L + 1 digits starting from digit t mod (2L + 1), so lanes whose products share an
+    // exponent add to different digits at each step (at most ceil(64 / (2L + 1)) per address).
+    const int64_t wbase = (int64_t)(lo & ~31);
+    if (nz) {
+      constexpr int D = 2 * L + 1;
+      const int q = (int)(((int64_t)e - wbase) >> 5);
+      const int r = t % D;
+      rotate_digits<D>(sp, r);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int j = (r + k >= D) ? r + k - D : r + k;
+        const int64_t v = sg ? -(int64_t)sp[k] : (int64_t)sp[k];
+        atomicAdd((unsigned long long*)&S.dwin[q + j], (unsigned long long)v);
       }
-      i0 += 2 * stride;
-      if (i0 >= n_end) break;
-      dot_load<L>(E, X, Y, i0, i0 + stride, true, i0 + stride < n_end);
     }
-    __syncthreads();
-    if (fast) {
-      // digit w is summed over the 256 lane windows by TPD consecutive threads, then combined
-      // with shuffles; the sum goes to the slot's global window
-      constexpr int TPD = (WF <= 32) ? 8 : 4;
-      constexpr int SEG = 64 / TPD;
-      const int w = t / TPD, sub = t % TPD;
-      int64_t a0 = 0, a1 = 0;
-      if (w < W) {
-        const int64_t* row = s_win + w * kDotStride + SEG * sub;
+    lds_barrier();
+    if (t < W) {
+      const int64_t v = S.dwin[t];
+      if (v) atomicAdd((unsigned long long*)&ring[((wbase >> 5) + t) & mask], (unsigned long long)v);
+    }
+  } else {
+    // wide pass: a block-shared window in LDS (integer atomics; its top covers the largest
+    // product), whose non-zero digits go to the ring; products below it go to the ring directly
+    constexpr int C = lds_window_digits<L, NT>();
+    const int Wc = min(W, C);
+    const int64_t wbase = (W <= C) ? (int64_t)(lo & ~31) : (int64_t)(hi & ~31) - 32 * (int64_t)(C - 2 * L - 2);
+    for (int w = t; w < Wc; w += NT) S.win[w] = 0;
+    lds_barrier();
+    if (nz) {
+      if ((int64_t)e >= wbase) {
+        const int q = (int)(((int64_t)e - wbase) >> 5);
 #pragma unroll
-        for (int m = 0; m < kDotThreads / 64; ++m) {
+        for (int j = 0; j <= 2 * L; ++j) {
+          if (sp[j]) {
+            const int64_t v = sg ? -(int64_t)sp[j] : (int64_t)sp[j];
+            atomicAdd((unsigned long long*)&S.win[q + j], (unsigned long long)v);
+          }
+        }
+      } else {
+        const int64_t d0 = (int64_t)(e >> 5);
 #pragma unroll
-          for (int k = 0; k < SEG; k += 2) {
-            a0 += row[64 * m + k];
-            a1 += row[64 * m + k + 1];
+        for (int j = 0; j <= 2 * L; ++j) {
+          if (sp[j]) {
+            const int64_t v = sg ? -(int64_t)sp[j] : (int64_t)sp[j];
+            atomicAdd((unsigned long long*)&ring[(d0 + j) & mask], (unsigned long long)v);
           }
         }
       }
-      int64_t dsum = a0 + a1;
-#pragma unroll
-      for (int o = 1; o < TPD; o <<= 1) dsum += __shfl_xor(dsum, o);
-      if (w < W && sub == 0 && dsum != 0)
-        atomicAdd((unsigned long long*)&gw[w], (unsigned long long)dsum);
-    } else {
-      for (int w = t; w < W; w += kDotThreads) {
-        const int64_t v = s_win[w];
-        if (v) atomicAdd((unsigned long long*)&gw[w], (unsigned long long)v);
-      }
+    }
+    lds_barrier();
+    for (int w = t; w < Wc; w += NT) {
+      const int64_t v = S.win[w];
+      if (v) atomicAdd((unsigned long long*)&ring[((wbase >> 5) + w) & mask], (unsigned long long)v);
     }
   }
+  if (t == 0) {
+    int32_t* a = dw.anchor + 2 * (slot * kAnchorBins + (blockIdx.x & (kAnchorBins - 1)));
+    atomicMin(&a[0], lo);
+    atomicMax(&a[1], hi);
+  }
+  lds_barrier();  // the LDS is free for the next pass
+}
 
-  // One ticket per launch (per solve in a batch) counts the blocks of every inner product; the
-  // window atomics of every wave are complete before it is taken, and the last block reads the
-  // windows with atomics, so no cache write-back or invalidate is needed.
+// The exponent range of slot `slot`'s products (its 64 bins reduced by one wavefront; every
+// lane gets it); the bins are reset for the slot's next use.
+MPD void ring_range(const DotWork& dw, int64_t slot, int32_t& lo, int32_t& hi) {
+  int32_t* b = dw.anchor + 2 * (slot * kAnchorBins + (threadIdx.x & 63));
+  lo = wave_min(ld_dev(b));
+  hi = wave_max(ld_dev(b + 1));
+  st_dev(b, (int32_t)INT32_MAX);
+  st_dev(b + 1, (int32_t)INT32_MIN);
+}
+
+// Window of a slot with products in [lo, hi]: digit 0 of weight 2^(base - 2p), W digits.
+template <int L>
+MPD int ring_window(int32_t lo, int32_t hi) { return (int)(((int64_t)hi - (lo & ~31)) >> 5) + 2 * L + 2; }
+
+// Digit w of the window starting at ring position s0, summed over the replicas, which are
+// cleared.
+MPD int64_t ring_take(const DotWork& dw, int64_t* ring, int s0, int w) {
+  const int64_t at = (s0 + w) & ((1 << dw.ring_log2) - 1);
+  // every exchange is issued before any result is used: one memory round trip in all
+  uint64_t got[kMaxReps];
+#pragma unroll
+  for (int c = 0; c < kMaxReps; ++c)
+    got[c] = (c < dw.reps) ? atomicExch((unsigned long long*)&ring[((int64_t)c << dw.ring_log2) + at], 0ull) : 0ull;
+  int64_t v = 0;
+#pragma unroll
+  for (int c = 0; c < kMaxReps; ++c) v += (int64_t)got[c];
+  return v;
+}
+
+// RN_p of a slot whose window has at most 63 digits, by one whole wavefront (one digit per
+// lane; every lane gets the result); the digits are cleared.
+template <int L>
+MPD Num<L> ring_round_narrow(const DotWork& dw, int64_t slot, int32_t lo, int32_t hi, uint32_t& st) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)(lo & ~31);
+  const int W = ring_window<L>(lo, hi);
+  const int s0 = (int)((base >> 5) & ((1 << dw.ring_log2) - 1));
+  const int64_t dg = (lane < W) ? ring_take(dw, slot_ring(dw, slot), s0, lane) : 0;
+  return wave_round<L>(dg, base - 64 * L, st);
+}
+
+// RN_p of a slot with a wider window (W > 63), by the whole block; thread 0 gets the result.
+// The digits are summed into `lds` (capacity `cap` digits) and rounded there by thread 0, or,
+// when they do not fit, rounded by thread 0 in global memory.  A window wider than the ring sets
+// kStWindow and gives +0 (the whole ring is cleared).
+template <int L, int NT>
+MPD Num<L> ring_round_wide(const DotWork& dw, int64_t slot, int32_t lo, int32_t hi, int64_t* lds,
+                           int cap, uint32_t& st) {
+  const int t = threadIdx.x;
+  const int R = 1 << dw.ring_log2, mask = R - 1;
+  int64_t* const ring = slot_ring(dw, slot);
+  const int64_t base = (int64_t)(lo & ~31);
+  const int W = ring_window<L>(lo, hi);
+  const int s0 = (int)((base >> 5) & mask);
+  Num<L> res;
+  set_zero(res, 0);
+  if (W > R) {
+    if (t == 0) st |= kStWindow;
+    for (int64_t k = t; k < ((int64_t)dw.reps << dw.ring_log2); k += NT) st_dev(ring + k, (int64_t)0);
+    return res;
+  }
+  if (W <= cap) {
+    for (int w = t; w < W; w += NT) lds[w] = ring_take(dw, ring, s0, w);
+    __syncthreads();
+    if (t == 0) res = window_finalize<L>(lds, 1, W, base - 64 * L, st);
+    __syncthreads();
+    return res;
+  }
+  for (int w = t; w < W; w += NT) st_dev(ring + ((s0 + w) & mask), ring_take(dw, ring, s0, w));
   wait_memory();
   __syncthreads();
-  uint32_t* ticket = A.w.ticket + A.w.nslots + pair;
-  if (t == 0) s_last = (atomicAdd(ticket, 1u) == nblocks * (unsigned)A.nd - 1) ? 1u : 0u;
+  if (t == 0) {
+    res = window_finalize_acc<L>(DevRingWin{ring, mask, s0}, W, base - 64 * L, st);
+    for (int w = 0; w < W; ++w) st_dev(ring + ((s0 + w) & mask), (int64_t)0);
+  }
+  return res;
+}
+
+// Where the last block of a launch puts the launch's inner products, and what it runs next.
+struct DotOut {
+  int nd;
+  int slot[kDotMaxND];
+  VecRef out[kDotMaxND];  // result d goes to element 0 of out[d] (in a batch: solve 0's scalar
+                          // slot, moved to each solve's own slots)
+  int epi;
+  VecRef hist;
+};
+
+// After a block's passes: take the solve's ticket; the last of its nblocks blocks rounds every
+// inner product of the launch (wavefront k takes products k, k + NT/64, ...), stores them, and
+// runs the driver epilogue.  Blocks exchange data only through device-scope atomics and
+// device-coherent loads and stores, ordered by waiting for this wavefront's memory operations,
+// so no cache write-back or invalidate is needed.
+// Whether the calling block (number idx of the solve's nblocks blocks in this launch) is the last
+// to finish; called by one thread after the block's memory operations are complete.  Blocks
+// count in ngroups groups (idx mod ngroups), the last of each group counts in the group
+// counter, so no counter sees more than about nblocks / ngroups contending atomics.  Each
+// counter is reset by the block that completes it.
+MPD bool last_block(const DotWork& dw, int pair, unsigned idx, unsigned nblocks) {
+  const unsigned G = (unsigned)dw.ngroups;
+  uint32_t* tk = dw.ticket + (int64_t)pair * (G + 1) * kTicketStride;
+  const unsigned g = idx & (G - 1);
+  const unsigned gsize = (nblocks - g + G - 1) / G;
+  if (atomicAdd(&tk[g * kTicketStride], 1u) != gsize - 1) return false;
+  st_dev(&tk[g * kTicketStride], 0u);
+  const unsigned ng = min(G, nblocks);
+  if (atomicAdd(&tk[G * kTicketStride], 1u) != ng - 1) return false;
+  st_dev(&tk[G * kTicketStride], 0u);
+  return true;
+}
+
+template <int L, int NT>
+MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched, unsigned idx,
+                     unsigned nblocks, Ctl* ctl, const Scalars& S, int32_t* ndone, uint32_t* status,
+                     uint32_t st, int64_t* lds, int cap) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t s_last;
+  __shared__ int32_t s_lo[kDotMaxND], s_hi[kDotMaxND];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  wait_memory();
+  __syncthreads();
+  if (t == 0) s_last = last_block(dw, pair, idx, nblocks) ? 1u : 0u;
   __syncthreads();
   if (!s_last) {
-    if (st) atomicOr(A.status, st);
+    if (st) atomicOr(status, st);
     return;
   }
-
-  // The last block: wave k rounds inner products k and k + 4 when their windows have at most 63
-  // digits (one per lane); wider windows are rounded afterwards by the whole block.
-  const int wv = t >> 6, lane = t & 63;
-  int32_t amin[kDotMaxND], amax[kDotMaxND];
-#pragma unroll
-  for (int dd = 0; dd < kDotMaxND; ++dd) {
-    amin[dd] = INT32_MAX;
-    amax[dd] = INT32_MIN;
-    if (dd < A.nd) wave_anchor(A.w.anchor, slot0 + A.slot[dd], amin[dd], amax[dd]);
-  }
-  __syncthreads();  // every wave has its anchors: the bins may be reset
-#pragma unroll
-  for (int dd = 0; dd < kDotMaxND; ++dd) {
-    if (dd < A.nd && wv == 0) {
-      int32_t* b = A.w.anchor + 2 * ((slot0 + A.slot[dd]) * kAnchorBins + lane);
-      st_dev(b, INT32_MAX);
-      st_dev(b + 1, INT32_MIN);
-    }
-  }
-#pragma unroll
-  for (int dd = 0; dd < kDotMaxND; ++dd) {
-    if (dd >= A.nd) continue;  // (continue, not break: the loop must unroll fully)
-    const bool anyd = amax[dd] >= amin[dd];
-    const int Wd = anyd ? window_digits<L>(amin[dd], amax[dd]) : 0;
-    const bool fitsd = Wd <= WB && Wd <= A.w.win_stride;
-    VecRef o = A.out[dd];  // batch: a scalar slot of solve 0, moved to this solve's slots
+  const int64_t slot0 = (int64_t)pair * kDotSlots;
+  auto out_of = [&](const VecRef& o0) {
+    VecRef o = o0;
     if (batched) {
       o.limb += (int64_t)pair * kNumScalars;
       o.hdr += (int64_t)pair * kNumScalars;
     }
-    int64_t* gwd = A.w.win + (slot0 + A.slot[dd]) * A.w.win_stride;
-    if (wv == (dd & 3)) {
-      if (anyd && fitsd && Wd <= 63) {
-        const int64_t dg = (lane < Wd) ? (int64_t)atomicExch((unsigned long long*)&gwd[lane], 0ull) : 0;
-        const Num<L> res = wave_round<L>(dg, (int64_t)amin[dd] - 64 * L, st);
-        if (lane == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
-      } else if (!(anyd && fitsd) && lane == 0) {
+    return o;
+  };
+  // windows of at most 63 digits: one wavefront each
+#pragma unroll
+  for (int dd = 0; dd < kDotMaxND; ++dd) {
+    if (dd < O.nd && wv == dd % NW) {
+      int32_t lo, hi;
+      ring_range(dw, slot0 + O.slot[dd], lo, hi);
+      if (hi < lo || ring_window<L>(lo, hi) <= 63) {
         Num<L> res;
-        set_zero(res, 0);
-        store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+        if (hi < lo) set_zero(res, 0);
+        else res = ring_round_narrow<L>(dw, slot0 + O.slot[dd], lo, hi, st);
+        const VecRef o = out_of(O.out[dd]);
+        if (lane == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+      }
+      if (lane == 0) {
+        s_lo[dd] = lo;
+        s_hi[dd] = hi;
       }
     }
-    if (anyd && fitsd && Wd > 63) {  // block-uniform
-      __syncthreads();
-      for (int w = t; w < Wd; w += kDotThreads)
-        s_win[w] = (int64_t)atomicExch((unsigned long long*)&gwd[w], 0ull);
-      __syncthreads();
-      if (t == 0) {
-        Num<L> res;
-        if (Wd <= WMAXF) {
-          RegWindow<WMAXF> R;
-          reg_normalize<WMAXF>(s_win, 1, Wd, R);
+  }
+  __syncthreads();
+  // wider windows: the whole block, one at a time
 #pragma unroll
-          for (int w = 0; w < WMAXF; ++w)
-            if (w < Wd) s_win[w] = (int64_t)R.limb[w];
-          res = limbs_round<L>(s_win, R.nl, R.neg, (int64_t)amin[dd] - 64 * L, st);
-        } else {
-          res = window_finalize<L>(s_win, 1, Wd, (int64_t)amin[dd] - 64 * L, st);
-        }
-        store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+  for (int dd = 0; dd < kDotMaxND; ++dd) {
+    if (dd < O.nd) {
+      const int32_t lo = s_lo[dd], hi = s_hi[dd];
+      if (hi >= lo && ring_window<L>(lo, hi) > 63) {
+        const Num<L> res = ring_round_wide<L, NT>(dw, slot0 + O.slot[dd], lo, hi, lds, cap, st);
+        const VecRef o = out_of(O.out[dd]);
+        if (t == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
       }
     }
   }
@@ -529,35 +599,71 @@ __global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
   wait_memory();
   __syncthreads();
   if (t == 0) {
-    st_dev(ticket, 0u);
-    uint32_t st2 = 0;
     const int was_done = ctl ? ctl->done : 0;
-    epilogue<L>(A.epi, S, ctl, A.hist, st2);
+    const uint32_t st2 = (ctl && O.epi != EPI_NONE)
+        ? epilogue<L>(O.epi, S.limb, S.hdr, S.ld, ctl, O.hist.limb, O.hist.hdr, O.hist.ld) : 0u;
     if (ctl && st2) atomicOr(&ctl->flags, st2);
-    if (A.batch.ndone && ctl && !was_done && ctl->done) atomicAdd(A.batch.ndone, 1);
+    if (ndone && ctl && !was_done && ctl->done) atomicAdd(ndone, 1);
     st |= st2;
   }
-  if (st) atomicOr(A.status, st);
+  if (st) atomicOr(status, st);
 }
 
-// Anchors of stand-alone inner products (no producing kernel): one pass over the headers.
-struct AnchorArgs {
+// Stand-alone inner products: blockIdx.y picks the product, blocks take 256-element passes.
+struct DotArgs {
   int64_t n;
-  int nd;
   VecRef x[kDotMaxND];
   VecRef y[kDotMaxND];
-  int slot[kDotMaxND];
-  int32_t* anchor;
+  DotOut o;
+  DotWork w;
+  Scalars S;
+  Ctl* ctl;  // nullable
+  uint32_t* status;
+  BatchMap batch;  // batch.pair_of_tile == nullptr: one solve
 };
 
-static __global__ void __launch_bounds__(256) dot_anchor_kernel(AnchorArgs A) {
-  for (int d = 0; d < A.nd; ++d) {
-    int32_t emin = INT32_MAX, emax = INT32_MIN;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
-         i += (int64_t)gridDim.x * blockDim.x)
-      pair_exponent(A.x[d].hdr[i], A.y[d].hdr[i], emin, emax);
-    anchor_publish(A.anchor, A.slot[d], emin, emax);
+template <int L>
+__global__ void __launch_bounds__(kDotThreads) dot_kernel(DotArgs A) {
+  __shared__ PassLds<L, kDotThreads> s;
+  // batch: one block per 256 elements, so a block belongs to one solve
+  const bool batched = A.batch.pair_of_tile != nullptr;
+  const int pair = batched ? A.batch.pair_of_tile[((int64_t)blockIdx.x * kDotThreads) / kTile] : 0;
+  Ctl* const ctl = A.ctl ? A.ctl + pair : nullptr;
+  if (solve_done(ctl)) return;
+  const int d = blockIdx.y;
+  // operands picked by comparison: a dynamic index into the argument arrays would copy them
+  // to scratch memory
+  VecRef X = A.x[0], Y = A.y[0];
+  int dslot = A.o.slot[0];
+#pragma unroll
+  for (int k = 1; k < kDotMaxND; ++k) {
+    if (k == d) {
+      X = A.x[k];
+      Y = A.y[k];
+      dslot = A.o.slot[k];
+    }
   }
+  const int64_t slot = (int64_t)pair * kDotSlots + dslot;
+  const int32_t z = (int32_t)0x80000000;  // +0
+  for (int64_t i0 = (int64_t)blockIdx.x * kDotThreads; i0 < A.n;
+       i0 += (int64_t)gridDim.x * kDotThreads) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    const int32_t hx = ok ? X.hdr[i] : z, hy = ok ? Y.hdr[i] : z;
+    uint32_t xm[L], ym[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      xm[q] = ok ? X.limb[(int64_t)q * X.ld + i] : 0u;
+      ym[q] = ok ? Y.limb[(int64_t)q * Y.ld + i] : 0u;
+    }
+    pass_dot<L, kDotThreads>(s, ok, hx, hy, xm, ym, A.w, slot);
+  }
+  // blocks of this solve: per product, all of them (one solve) or two per tile of its segment
+  const unsigned per = batched ? 2u * (unsigned)A.batch.tiles_of_pair[pair] : gridDim.x;
+  const unsigned bx = batched ? blockIdx.x - 2u * (unsigned)A.batch.first_tile[pair] : blockIdx.x;
+  dots_finish<L, kDotThreads>(A.w, A.o, pair, batched, bx + per * blockIdx.y, per * gridDim.y, ctl,
+                              A.S.at(pair), A.batch.ndone, A.status, 0u, s.win,
+                              lds_window_digits<L, kDotThreads>());
 }
 
 // Reset anchors to empty.
@@ -570,7 +676,8 @@ static __global__ void dot_work_init_kernel(int32_t* anchor, int nslots) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Element-wise kernels (one element per thread, grid-stride).
+// Element-wise kernels (one element per thread, grid-stride; those that end with inner products
+// run block-uniform passes).
 // ------------------------------------------------------------------------------------------
 struct VecArgs {
   int64_t n;
@@ -578,25 +685,33 @@ struct VecArgs {
   Scalars S;
   Ctl* ctl;
   uint32_t* status;
-  int32_t* anchor;  // nullable: inner-product anchors filled for the products this kernel makes
-  int aslot[2];
   BatchMap batch;   // batch: n is whole tiles and the grid has n / blockDim.x blocks
+  // inner products the kernel forms from the vectors it writes (kernels that have them)
+  DotWork dots;
+  DotOut fd;
 };
 
-// The solve a block works for: its control block, scalars and first inner-product slot.
+// The solve a block works for: its control block, scalars, first inner-product slot and the
+// number of blocks of the launch that work for it.
 struct EwCtx {
   Ctl* ctl;
   Scalars S;
-  int abase;
+  int pair;
+  int64_t abase;
+  unsigned idx, nblocks;  // this block's number among the solve's blocks, and their count
 };
 
 MPD EwCtx ew_ctx(const VecArgs& A) {
-  const int pair =
-      A.batch.pair_of_tile ? A.batch.pair_of_tile[((int64_t)blockIdx.x * blockDim.x) / kTile] : 0;
+  const bool batched = A.batch.pair_of_tile != nullptr;
+  const int pair = batched ? A.batch.pair_of_tile[((int64_t)blockIdx.x * blockDim.x) / kTile] : 0;
   EwCtx c;
   c.ctl = A.ctl ? A.ctl + pair : nullptr;
   c.S = A.S.at(pair);
-  c.abase = pair * kDotSlots;
+  c.pair = pair;
+  c.abase = (int64_t)pair * kDotSlots;
+  const unsigned per_tile = (unsigned)(kTile / (int)blockDim.x);
+  c.nblocks = batched ? (unsigned)A.batch.tiles_of_pair[pair] * per_tile : gridDim.x;
+  c.idx = batched ? blockIdx.x - (unsigned)A.batch.first_tile[pair] * per_tile : blockIdx.x;
   return c;
 }
 
@@ -633,24 +748,6 @@ __global__ void __launch_bounds__(256) copy_kernel(VecArgs A) {
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   MP_ELEMENTWISE_LOOP(A) { vstore<L>(A.v[0], i, vload<L>(A.v[1], i)); }
-}
-
-// v0 <- v1, and the anchors of (v1, v1) and (v0, v1) = (v1, v1) (the solver setup's rt = r)
-template <int L>
-__global__ void __launch_bounds__(256) copy_anchor_kernel(VecArgs A) {
-  const EwCtx c = ew_ctx(A);
-  if (solve_done(c.ctl)) return;
-  int32_t a0 = INT32_MAX, b0 = INT32_MIN;
-  MP_ELEMENTWISE_LOOP(A) {
-    const Num<L> r = vload<L>(A.v[1], i);
-    vstore<L>(A.v[0], i, r);
-    const int32_t h = make_hdr(r.e, r.s);
-    pair_exponent(h, h, a0, b0);
-  }
-  if (A.anchor) {
-    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, c.abase + A.aslot[1], a0, b0);
-  }
 }
 
 // v0 <- +0
@@ -694,29 +791,35 @@ __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
   if (st) atomicOr(A.status, st);
 }
 
-// BiCG update: v = {x, r, rt, p, z, zt}: x += alpha p; r -= alpha z; rt -= alpha zt.
+// BiCG update: v = {x, r, rt, p, z, zt}: x += alpha p; r -= alpha z; rt -= alpha zt; then the
+// inner products (r, r) and (rt, r) (fd slots 0 and 1) from the values just formed.  The loop
+// is block-uniform: every pass ends with block-wide inner-product steps.
 template <int L>
 __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = sload<L>(c.S, S_ALPHA);
-  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
-  MP_ELEMENTWISE_LOOP(A) {
-    vstore<L>(A.v[0], i, add_rn<L>(vload<L>(A.v[0], i), mul_rn<L>(alpha, vload<L>(A.v[3], i), st), st));
-    const Num<L> r = sub_rn<L>(vload<L>(A.v[1], i), mul_rn<L>(alpha, vload<L>(A.v[4], i), st), st);
-    vstore<L>(A.v[1], i, r);
-    const Num<L> rt = sub_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[5], i), st), st);
-    vstore<L>(A.v[2], i, rt);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    Num<L> r, rt;
+    set_zero(r, 0);
+    set_zero(rt, 0);
+    if (ok) {
+      vstore<L>(A.v[0], i, add_rn<L>(vload<L>(A.v[0], i), mul_rn<L>(alpha, vload<L>(A.v[3], i), st), st));
+      r = sub_rn<L>(vload<L>(A.v[1], i), mul_rn<L>(alpha, vload<L>(A.v[4], i), st), st);
+      vstore<L>(A.v[1], i, r);
+      rt = sub_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[5], i), st), st);
+      vstore<L>(A.v[2], i, rt);
+    }
     const int32_t hr = make_hdr(r.e, r.s), hrt = make_hdr(rt.e, rt.s);
-    pair_exponent(hr, hr, a0, b0);
-    pair_exponent(hrt, hr, a1, b1);
+    pass_dot<L, 256>(lds, ok, hr, hr, r.m, r.m, A.dots, c.abase + A.fd.slot[0]);
+    pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  if (A.anchor) {
-    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
-  }
-  if (st) atomicOr(A.status, st);
+  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
 }
 
 // GPBiCG direction: v = {p, w, r, v, q, u}.  First iteration p = r; then
@@ -743,47 +846,51 @@ __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
 }
 
 // GPBiCG t, s, y: v = {t, s, y, r, q, w}.  s = t - r (not in the first iteration),
-// t = r - alpha q, y = alpha q - r (first) or s - alpha (w - q).
+// t = r - alpha q, y = alpha q - r (first) or s - alpha (w - q); then the inner products
+// (y, y) and (y, t) (fd slots 0 and 1).
 template <int L>
 __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   const bool first = c.ctl->iters == 0;
   const Num<L> alpha = sload<L>(c.S, S_ALPHA);
-  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
-  MP_ELEMENTWISE_LOOP(A) {
-    const Num<L> r = vload<L>(A.v[3], i), q = vload<L>(A.v[4], i);
-    const Num<L> aq = mul_rn<L>(alpha, q, st);
-    Num<L> s;
-    if (!first) {
-      s = sub_rn<L>(vload<L>(A.v[0], i), r, st);
-      vstore<L>(A.v[1], i, s);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    Num<L> tn, y;
+    set_zero(tn, 0);
+    set_zero(y, 0);
+    if (ok) {
+      const Num<L> r = vload<L>(A.v[3], i), q = vload<L>(A.v[4], i);
+      const Num<L> aq = mul_rn<L>(alpha, q, st);
+      Num<L> s;
+      if (!first) {
+        s = sub_rn<L>(vload<L>(A.v[0], i), r, st);
+        vstore<L>(A.v[1], i, s);
+      }
+      tn = sub_rn<L>(r, aq, st);
+      vstore<L>(A.v[0], i, tn);
+      if (first) {
+        y = sub_rn<L>(aq, r, st);
+      } else {
+        const Num<L> wq = sub_rn<L>(vload<L>(A.v[5], i), q, st);
+        y = sub_rn<L>(s, mul_rn<L>(alpha, wq, st), st);
+      }
+      vstore<L>(A.v[2], i, y);
     }
-    const Num<L> tn = sub_rn<L>(r, aq, st);
-    vstore<L>(A.v[0], i, tn);
-    Num<L> y;
-    if (first) {
-      y = sub_rn<L>(aq, r, st);
-    } else {
-      const Num<L> wq = sub_rn<L>(vload<L>(A.v[5], i), q, st);
-      y = sub_rn<L>(s, mul_rn<L>(alpha, wq, st), st);
-    }
-    vstore<L>(A.v[2], i, y);
     const int32_t hy = make_hdr(y.e, y.s), ht = make_hdr(tn.e, tn.s);
-    pair_exponent(hy, hy, a0, b0);
-    pair_exponent(hy, ht, a1, b1);
+    pass_dot<L, 256>(lds, ok, hy, hy, y.m, y.m, A.dots, c.abase + A.fd.slot[0]);
+    pass_dot<L, 256>(lds, ok, hy, ht, y.m, tn.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  if (A.anchor) {
-    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
-  }
-  if (st) atomicOr(A.status, st);
+  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
 }
 
 // GPBiCG update: v = {u, z, x, r, q, s, p, t} and v2 = {y, v} in w[]:
 // u = zeta q + eta (s + beta u); z = zeta r + eta z - alpha u; x = x + alpha p + z;
-// r = t - eta y - zeta v.
+// r = t - eta y - zeta v; then the inner products (r, r) and (rt, r) (fd slots 0 and 1).
 struct GpUpdArgs {
   VecArgs a;
   VecRef y, v, rt;
@@ -791,38 +898,43 @@ struct GpUpdArgs {
 
 template <int L>
 __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
+  __shared__ PassLds<L, 256> lds;
   const VecArgs& A = G.a;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   const Num<L> alpha = sload<L>(c.S, S_ALPHA), beta = sload<L>(c.S, S_BETA);
   const Num<L> zeta = sload<L>(c.S, S_ZETA), eta = sload<L>(c.S, S_ETA);
-  int32_t a0 = INT32_MAX, b0 = INT32_MIN, a1 = INT32_MAX, b1 = INT32_MIN;
-  MP_ELEMENTWISE_LOOP(A) {
-    const Num<L> q = vload<L>(A.v[4], i), s = vload<L>(A.v[5], i);
-    const Num<L> u_old = vload<L>(A.v[0], i);
-    const Num<L> u = add_rn<L>(mul_rn<L>(zeta, q, st),
-                               mul_rn<L>(eta, add_rn<L>(s, mul_rn<L>(beta, u_old, st), st), st), st);
-    vstore<L>(A.v[0], i, u);
-    const Num<L> r = vload<L>(A.v[3], i);
-    const Num<L> z = sub_rn<L>(add_rn<L>(mul_rn<L>(zeta, r, st), mul_rn<L>(eta, vload<L>(A.v[1], i), st), st),
-                               mul_rn<L>(alpha, u, st), st);
-    vstore<L>(A.v[1], i, z);
-    const Num<L> x = add_rn<L>(add_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[6], i), st), st), z, st);
-    vstore<L>(A.v[2], i, x);
-    const Num<L> t = vload<L>(A.v[7], i);
-    const Num<L> rn = sub_rn<L>(sub_rn<L>(t, mul_rn<L>(eta, vload<L>(G.y, i), st), st),
-                                mul_rn<L>(zeta, vload<L>(G.v, i), st), st);
-    vstore<L>(A.v[3], i, rn);
-    const int32_t hr = make_hdr(rn.e, rn.s), hrt = G.rt.hdr[i];
-    pair_exponent(hr, hr, a0, b0);
-    pair_exponent(hrt, hr, a1, b1);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    Num<L> rn, rt;
+    set_zero(rn, 0);
+    set_zero(rt, 0);
+    if (ok) {
+      rt = vload<L>(G.rt, i);
+      const Num<L> q = vload<L>(A.v[4], i), s = vload<L>(A.v[5], i);
+      const Num<L> u_old = vload<L>(A.v[0], i);
+      const Num<L> u = add_rn<L>(mul_rn<L>(zeta, q, st),
+                                 mul_rn<L>(eta, add_rn<L>(s, mul_rn<L>(beta, u_old, st), st), st), st);
+      vstore<L>(A.v[0], i, u);
+      const Num<L> r = vload<L>(A.v[3], i);
+      const Num<L> z = sub_rn<L>(add_rn<L>(mul_rn<L>(zeta, r, st), mul_rn<L>(eta, vload<L>(A.v[1], i), st), st),
+                                 mul_rn<L>(alpha, u, st), st);
+      vstore<L>(A.v[1], i, z);
+      const Num<L> x = add_rn<L>(add_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[6], i), st), st), z, st);
+      vstore<L>(A.v[2], i, x);
+      const Num<L> t = vload<L>(A.v[7], i);
+      rn = sub_rn<L>(sub_rn<L>(t, mul_rn<L>(eta, vload<L>(G.y, i), st), st),
+                     mul_rn<L>(zeta, vload<L>(G.v, i), st), st);
+      vstore<L>(A.v[3], i, rn);
+    }
+    const int32_t hr = make_hdr(rn.e, rn.s), hrt = make_hdr(rt.e, rt.s);
+    pass_dot<L, 256>(lds, ok, hr, hr, rn.m, rn.m, A.dots, c.abase + A.fd.slot[0]);
+    pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, rn.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  if (A.anchor) {
-    anchor_publish(A.anchor, c.abase + A.aslot[0], a0, b0);
-    anchor_publish(A.anchor, c.abase + A.aslot[1], a1, b1);
-  }
-  if (st) atomicOr(A.status, st);
+  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
 }
 
 // Write a constant into element 0 of a vector or a scalar slot (kernel arguments carry it).

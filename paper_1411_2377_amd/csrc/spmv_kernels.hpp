@@ -19,6 +19,7 @@
 #pragma once
 #include "mp_core.hpp"
 #include "mp_exact.hpp"
+#include "solver_kernels.hpp"
 
 namespace mp {
 
@@ -67,12 +68,6 @@ struct SpmvArgs {
   int64_t y_ld;
   uint32_t* status;
   const int32_t* done;  // nullable: a set flag turns the launch into a no-op (solver graphs)
-  // inner-product anchors for products of y with up to three vectors (pair_hdr[k] == nullptr
-  // means y itself): the exponent range of y_i * w_i over the rows, published to anchor slots
-  int npair;
-  const int32_t* pair_hdr[3];
-  int pair_slot[3];
-  int32_t* anchor;
   // x staged as one record per element (limbs then header, x_rec_words<L>() words apart), or
   // nullptr: x is read in its own layout
   const uint32_t* x_rec;
@@ -81,10 +76,19 @@ struct SpmvArgs {
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
-  const int32_t* pair_of_tile;   // solve of each 512-element tile of y (done flags, anchors)
+  const int32_t* pair_of_tile;   // solve of each 512-element tile of y (done flags, scalars)
   const int32_t* done_base;      // &ctl[0].done; solve k's flag at done_base[k * done_stride]
   int64_t done_stride;
-  int slots_per_pair;
+  // inner products of y with up to three vectors (kernels instantiated with fused products):
+  // (y, part[k]) into slot fd.slot[k]; part[k].hdr == nullptr means y itself
+  VecRef part[3];
+  DotOut fd;
+  DotWork dots;
+  Scalars S;
+  Ctl* ctl;
+  const int32_t* tiles_of_pair;
+  const int32_t* first_tile;
+  int32_t* ndone;
 };
 
 // Row block (RPW rows), right-hand side and solve of this block; false if that solve is
@@ -109,53 +113,40 @@ MPD bool spmv_block(const SpmvArgs& A, SpmvBlock& B) {
   return true;
 }
 
-// Fold row r's output header yh into the anchors of its requested products.
-struct PairAcc {
-  int32_t lo[3], hi[3];
-};
-
-MPD void pair_init(PairAcc& P) {
+// The inner products of the rows' results with the requested vectors, one pass each, then the
+// ticket (and in the last block the rounding and the driver epilogue).  The lane of each row
+// holds its result y; lanes without a row take part with no product.
+template <int L, int NT, int RPW>
+MPD void spmv_fused_dots(const SpmvArgs& A, const SpmvBlock& B, bool has_row, int64_t yi,
+                         const Num<L>& y, uint32_t st) {
+  __shared__ PassLds<L, NT> lds;
+  const int32_t hy = has_row ? make_hdr(y.e, y.s) : (int32_t)0x80000000;
+  const int64_t slot0 = (int64_t)B.pair * kDotSlots;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    P.lo[k] = INT32_MAX;
-    P.hi[k] = INT32_MIN;
-  }
-}
-
-MPD void pair_fold(const SpmvArgs& A, PairAcc& P, int64_t row, int32_t yh) {
-  // row: index into y (right-hand side offset included)
+    if (k < A.fd.nd) {
+      int32_t hw = hy;
+      uint32_t wm[L];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (k < A.npair) {
-      const int32_t hp = A.pair_hdr[k] ? A.pair_hdr[k][row] : yh;
-      if (!hdr_is_zero(yh) && !hdr_is_zero(hp)) {
-        const int32_t e = (yh >> 1) + (hp >> 1);
-        P.lo[k] = min(P.lo[k], e);
-        P.hi[k] = max(P.hi[k], e);
+      for (int q = 0; q < L; ++q) wm[q] = y.m[q];
+      if (A.part[k].hdr && has_row) {
+        hw = A.part[k].hdr[yi];
+#pragma unroll
+        for (int q = 0; q < L; ++q) wm[q] = A.part[k].limb[(int64_t)q * A.part[k].ld + yi];
       }
+      pass_dot<L, NT>(lds, has_row, hy, hw, y.m, wm, A.dots, slot0 + A.fd.slot[k]);
     }
   }
-}
-
-MPD void pair_publish(const SpmvArgs& A, PairAcc& P, int pair) {
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (k < A.npair) {
-      int32_t lo = P.lo[k], hi = P.hi[k];
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o));
-        hi = max(hi, __shfl_xor(hi, o));
-      }
-      if ((threadIdx.x & 63) == 0 && hi >= lo) {
-        // bins of 64 per slot, spread by block (the inner-product kernel reduces them)
-        const int64_t slot = (int64_t)pair * A.slots_per_pair + A.pair_slot[k];
-        int32_t* a = A.anchor + 2 * (slot * 64 + (blockIdx.x & 63));
-        atomicMin(&a[0], lo);
-        atomicMax(&a[1], hi);
-      }
-    }
-  }
+  // blocks of this solve: all of them (one solve), or the row blocks of its tiles for its
+  // right-hand side (this block's number: its row block less the solve's first one)
+  const bool batched = A.pair_of_tile != nullptr;
+  const unsigned nblocks =
+      batched ? (unsigned)A.tiles_of_pair[B.pair] * (unsigned)(kTile / RPW) : gridDim.x;
+  const unsigned idx =
+      batched ? (unsigned)(B.rb - ((int64_t)A.first_tile[B.pair] * kTile - B.rhs * A.y_rstride) / RPW)
+              : blockIdx.x;
+  dots_finish<L, NT>(A.dots, A.fd, B.pair, batched, idx, nblocks, A.ctl ? A.ctl + B.pair : nullptr,
+                     A.S.at(B.pair), A.ndone, A.status, st, lds.win, lds_window_digits<L, NT>());
 }
 
 // x_j's header and limbs, from the staged records when there are any
@@ -234,7 +225,7 @@ MPD void load_entries(EntryLoad<L, K>& E, const SpmvArgs& A, const uint32_t* x_l
 // entries, taken in order (a compact numbering of the rows' entries, the row of each entry
 // painted into LDS per chunk), with batched coalesced loads, and stage them in LDS.  Phase 2:
 // each lane adds its row's staged products in storage order.
-template <int L, int RPW>
+template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
   constexpr int K = spmv_kper<L>();
   constexpr int kChunk = 64 * K;
@@ -312,13 +303,11 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
     __syncthreads();
   }
   if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
-  if (A.npair) {
-    PairAcc P;
-    pair_init(P);
-    if (has_row) pair_fold(A, P, yo + row, make_hdr(acc.e, acc.s));
-    pair_publish(A, P, B.pair);
+  if constexpr (FUSE) {
+    spmv_fused_dots<L, 64, RPW>(A, B, has_row, yo + row, acc, st);
+  } else if (st) {
+    atomicOr(A.status, st);
   }
-  if (st) atomicOr(A.status, st);
 }
 
 MPD int32_t wave_min32(int32_t v) {
@@ -342,7 +331,7 @@ MPD int32_t wave_max32(int32_t v) {
 template <int RPW>
 constexpr int seq_sorted_q() { return RPW >= 64 ? 4 : 8; }
 
-template <int L, int RPW>
+template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   constexpr int Q = seq_sorted_q<RPW>();
   constexpr int NS = RPW * Q;  // product slots per chunk: row r's t-th entry of the chunk at r*Q+t
@@ -425,16 +414,12 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
     }
     __syncthreads();
   }
-  if (wv == 0) {
-    if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
-    if (A.npair) {
-      PairAcc P;
-      pair_init(P);
-      if (has_row) pair_fold(A, P, yo + row, make_hdr(acc.e, acc.s));
-      pair_publish(A, P, B.pair);
-    }
+  if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
+  if constexpr (FUSE) {
+    spmv_fused_dots<L, 256, RPW>(A, B, has_row, yo + row, acc, st);
+  } else if (st) {
+    atomicOr(A.status, st);
   }
-  if (st) atomicOr(A.status, st);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -485,7 +470,7 @@ MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, 
   }
 }
 
-template <int L, int RPW>
+template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   constexpr int R = window_fast_digits<L>();  // ring digits per row
   // digits of the block-shared exact window: the same for every variant, so that every variant
@@ -554,8 +539,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
   }
 
   Num<L> y;
-  PairAcc P;
-  pair_init(P);
+  set_zero(y, 0);
   bool wide = false;
   int32_t lo = INT32_MAX, hi = INT32_MIN;
   if (is_short) {
@@ -569,10 +553,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     } else {
       wide = true;
     }
-    if (!wide) {
-      store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + row);
-      if (A.npair) pair_fold(A, P, yo + row, make_hdr(y.e, y.s));
-    }
+    if (!wide) store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + row);
   }
 
   uint64_t pending = __ballot(has_row && (!is_short || wide));
@@ -655,11 +636,13 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     if (lane == owner) {
       y = yr;
       store<L>(y, A.y_limb, A.y_hdr, A.y_ld, yo + row);
-      if (A.npair) pair_fold(A, P, yo + row, make_hdr(y.e, y.s));
     }
   }
-  if (A.npair) pair_publish(A, P, B.pair);
-  if (st) atomicOr(A.status, st);
+  if constexpr (FUSE) {
+    spmv_fused_dots<L, 64, RPW>(A, B, has_row, yo + row, y, st);
+  } else if (st) {
+    atomicOr(A.status, st);
+  }
 }
 
 }  // namespace mp

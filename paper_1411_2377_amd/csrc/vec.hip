@@ -11,12 +11,10 @@
 
 namespace mpapi {
 
-int64_t dot_window_stride() { return mp::dot_shared_digits<16>(); }
-
-int dot_work_alloc(int nslots, int32_t** anchor, int64_t** win, uint32_t** ticket, hipStream_t s,
-                   int64_t win_stride, int nfinal) {
-  if (win_stride <= 0) win_stride = dot_window_stride();
-  const size_t nwin = (size_t)nslots * win_stride, ntk = (size_t)nslots + nfinal;
+int dot_work_alloc(int nslots, int ring_log2, int reps, int ngroups, int32_t** anchor, int64_t** win,
+                   uint32_t** ticket, hipStream_t s, int nsolves) {
+  const size_t nwin = (size_t)nslots * reps << ring_log2;
+  const size_t ntk = (size_t)nsolves * (ngroups + 1) * mp::kTicketStride;
   hipError_t e = hipMalloc((void**)anchor, (size_t)2 * nslots * mp::kAnchorBins * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc((void**)win, nwin * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc((void**)ticket, ntk * sizeof(uint32_t));
@@ -39,23 +37,22 @@ mp::VecRef ref(const mp_vec& v) {
   return r;
 }
 
-// Blocks per inner product: two elements per thread, at most kDotMaxBlocks, and few enough
-// that all the dots of one launch are resident at once: the per-lane windows take
-// 8 * window_fast_digits * 257 bytes of LDS (L = 4: 37 KB, 8: 53 KB, 16: 86 KB of the 160 KB
-// per CU), i.e. 4, 2 or 1 blocks per CU on 256 CUs.
-unsigned dot_grid(int64_t n, int nd, int L) {
-  const int per_cu = (L == 4) ? 4 : (L == 8) ? 2 : 1;
-  int64_t g = (n + 2 * mp::kDotThreads - 1) / (2 * mp::kDotThreads);
-  g = std::min<int64_t>(g, (256 * per_cu) / std::max(1, nd));
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, mp::kDotMaxBlocks));
+// Blocks per inner product: one 256-element pass each, at most 2048 (more passes per block
+// beyond that).
+unsigned dot_grid(int64_t n) {
+  const int64_t g = (n + mp::kDotThreads - 1) / mp::kDotThreads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
 
-mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots, int64_t win_stride) {
+mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots, int ring_log2,
+                     int reps, int ngroups) {
   mp::DotWork w;
   w.anchor = anchor;
   w.win = win;
   w.ticket = ticket;
-  w.win_stride = win_stride > 0 ? win_stride : dot_window_stride();
+  w.ring_log2 = ring_log2;
+  w.reps = reps;
+  w.ngroups = ngroups;
   w.nslots = nslots;
   return w;
 }
@@ -72,11 +69,14 @@ static unsigned ew_grid_of(const mp::VecArgs& a) {
 }
 
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
-  const unsigned g = a.batch.pair_of_tile ? (unsigned)(a.n / mp::kTile) : dot_grid(a.n, a.nd, L);
+  if (a.o.nd < 1 || a.o.nd > mp::kDotMaxND) return fail(MPS_EINVAL, "bad inner-product count");
+  // a batch: one block per 256 elements (every block belongs to one solve)
+  const unsigned g = a.batch.pair_of_tile ? (unsigned)(a.n / mp::kDotThreads) : dot_grid(a.n);
+  const dim3 grid(g, a.o.nd);
   switch (L) {
-    case 4: MPS_LAUNCH(true, true, mp::dot_kernel<4>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
-    case 8: MPS_LAUNCH(true, true, mp::dot_kernel<8>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
-    case 16: MPS_LAUNCH(true, true, mp::dot_kernel<16>, dim3(g, a.nd), dim3(mp::kDotThreads), 0, s, a); break;
+    case 4: MPS_LAUNCH(true, true, mp::dot_kernel<4>, grid, dim3(mp::kDotThreads), 0, s, a); break;
+    case 8: MPS_LAUNCH(true, true, mp::dot_kernel<8>, grid, dim3(mp::kDotThreads), 0, s, a); break;
+    case 16: MPS_LAUNCH(true, true, mp::dot_kernel<16>, grid, dim3(mp::kDotThreads), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -99,7 +99,6 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
     case EW_COPY: MPS_EW_CASES(copy_kernel, a); break;
     case EW_ZERO: MPS_EW_CASES(zero_kernel, a); break;
     case EW_SUB: MPS_EW_CASES(sub_kernel, a); break;
-    case EW_COPY_ANCHOR: MPS_EW_CASES(copy_anchor_kernel, a); break;
     case EW_BICG_DIR: MPS_EW_CASES(bicg_dir_kernel, a); break;
     case EW_BICG_UPDATE: MPS_EW_CASES(bicg_update_kernel, a); break;
     case EW_GP_DIR: MPS_EW_CASES(gp_dir_kernel, a); break;
@@ -191,31 +190,18 @@ int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream
   if (vec_overlap(x, out, L) || vec_overlap(y, out, L)) return fail(MPS_EINVAL, "out overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
-  hipStream_t s = (hipStream_t)stream;
-  // no kernel produced these operands: one pass over the headers fills the anchor
-  mp::AnchorArgs aa{};
-  aa.n = x->len;
-  aa.nd = 1;
-  aa.x[0] = ref(*x);
-  aa.y[0] = ref(*y);
-  aa.slot[0] = 0;
-  aa.anchor = ctx->dot_anchor;
-  if (x->len > 0) {
-    const unsigned g = ew_grid(x->len);
-    hipLaunchKernelGGL(mp::dot_anchor_kernel, dim3(std::min(g, 1024u)), dim3(256), 0, s, aa);
-  }
   mp::DotArgs a{};
   a.n = x->len;
-  a.nd = 1;
   a.x[0] = ref(*x);
   a.y[0] = ref(*y);
-  a.out[0] = ref(*out);
-  a.slot[0] = 0;
-  a.w = dot_work(ctx->dot_anchor, ctx->dot_win, ctx->dot_ticket, 1);
+  a.o.nd = 1;
+  a.o.out[0] = ref(*out);
+  a.o.slot[0] = 0;
+  a.o.epi = mp::EPI_NONE;
+  a.w = dot_work(ctx->dot_anchor, ctx->dot_win, ctx->dot_ticket, 1, kDotRingLog2, kDotReps, kDotGroups);
   a.ctl = nullptr;
   a.status = ctx->status;
-  a.epi = mp::EPI_NONE;
-  return launch_dot(L, a, s);
+  return launch_dot(L, a, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -9,13 +9,12 @@
 namespace mpapi {
 
 enum EwKind {
-  EW_AXPY, EW_COPY, EW_ZERO, EW_SUB, EW_BICG_DIR, EW_BICG_UPDATE, EW_GP_DIR, EW_GP_TSY,
-  EW_COPY_ANCHOR
+  EW_AXPY, EW_COPY, EW_ZERO, EW_SUB, EW_BICG_DIR, EW_BICG_UPDATE, EW_GP_DIR, EW_GP_TSY
 };
 
 mp::VecRef ref(const mp_vec& v);
-mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots,
-                     int64_t win_stride = 0);
+mp::DotWork dot_work(int32_t* anchor, int64_t* win, uint32_t* ticket, int nslots, int ring_log2,
+                     int reps, int ngroups);
 unsigned ew_grid(int64_t n);
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s);
 int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s);
