@@ -200,6 +200,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
       a.part[k] = fuse->part[k];
       a.fd.slot[k] = fuse->slot[k];
       a.fd.out[k] = fuse->out[k];
+      a.fd.sslot[k] = fuse->sslot[k];
     }
     a.dots = fuse->dots;
     a.S = fuse->S;

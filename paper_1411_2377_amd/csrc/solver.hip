@@ -354,6 +354,7 @@ SpmvFuse fuse_of(const Work& W, int epi, std::initializer_list<FuseItem> list,
     F.part[F.nd] = it.part;
     F.slot[F.nd] = it.slot;
     F.out[F.nd] = mp::slot_ref(W.S, it.scalar);
+    F.sslot[F.nd] = it.scalar;
     ++F.nd;
   }
   F.epi = epi;
@@ -398,6 +399,7 @@ void set_fd(const Work& W, mp::VecArgs& a, int epi, std::initializer_list<std::p
   for (auto& it : list) {
     a.fd.slot[a.fd.nd] = it.first;
     a.fd.out[a.fd.nd] = mp::slot_ref(W.S, it.second);
+    a.fd.sslot[a.fd.nd] = it.second;
     ++a.fd.nd;
   }
   a.fd.epi = epi;
@@ -459,10 +461,12 @@ int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_sol
   d.x[0] = W.vec(0);
   d.y[0] = W.vec(0);
   d.o.out[0] = mp::slot_ref(W.S, mp::S_Q0);
+  d.o.sslot[0] = mp::S_Q0;
   d.o.slot[0] = 1;
   d.x[1] = W.vec(1);
   d.y[1] = W.vec(0);
   d.o.out[1] = mp::slot_ref(W.S, mp::S_RHO);
+  d.o.sslot[1] = mp::S_RHO;
   d.o.slot[1] = 2;
   return launch_dot(L, d, W.ws);
 }
@@ -602,15 +606,16 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
   mp::VecRef hist{nullptr, nullptr, 0};
   if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
   const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
-  // per iteration: directions; z = A p with sigma = (pt, z) (its last block forms alpha);
-  // zt = A^T pt; the updates with (r, r) and (rt, r) (its last block: stopping test, beta)
+  // per iteration: directions; z = A p with sigma = (pt, z); zt = A^T pt; the updates, which
+  // first form alpha = rho / sigma, with (r, r) and (rt, r) (their last block: stopping test,
+  // beta)
   auto iteration = [&]() -> int {
     int rr;
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
     if ((rr = timed(W, PROF_VEC, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
       return rr;
-    const SpmvFuse sig = fuse_of(W, mp::EPI_BICG_SIGMA, {{PT, 0, mp::S_SIGMA}});
+    const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{PT, 0, mp::S_SIGMA}});
     if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
       return rr;
     if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, opT, o->mode, PT, ZT, st, true); })))
@@ -652,19 +657,20 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   mp::VecArgs a = ew_args(W, st);
   a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
-  // q = A p with (rt, q) (its last block forms alpha)
-  const SpmvFuse den = fuse_of(W, mp::EPI_GP_ALPHA, {{RT, 0, mp::S_DEN}});
+  // q = A p with (rt, q)
+  const SpmvFuse den = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_DEN}});
   if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
-  // t, s, y with (y, y) and (y, t)
+  // alpha = rho / (rt, q); t, s, y with (y, y) and (y, t)
   a = ew_args(W, st);
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
   set_fd(W, a, mp::EPI_NONE, {{3, mp::S_MU1}, {5, mp::S_MU3}});
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
-  // v = A t with (v, t), (v, y), (v, v) (its last block forms zeta and eta)
+  // v = A t with (v, t), (v, y), (v, v)
   const SpmvFuse mus =
-      fuse_of(W, mp::EPI_GP_ZETA, {{T, 4, mp::S_MU2}, {Y, 6, mp::S_MU4}, {self, 7, mp::S_MU5}});
+      fuse_of(W, mp::EPI_NONE, {{T, 4, mp::S_MU2}, {Y, 6, mp::S_MU4}, {self, 7, mp::S_MU5}});
   if ((rr = timed(W, PROF_SPMV, sp_bytes + 2 * dot1, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
-  // u, z, x, r with (r, r) and (rt, r) (its last block: stopping test, beta)
+  // zeta, eta from mu1..mu5; u, z, x, r with (r, r) and (rt, r) (their last block: stopping
+  // test, beta)
   mp::GpUpdArgs g{};
   g.a = ew_args(W, st);
   g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;

@@ -112,109 +112,155 @@ MPD void finish(Ctl* ctl, int status) {
 enum Epi {
   EPI_NONE = 0,
   EPI_SETUP,        // q0 = (r,r), rho = (rt,r): nrm0, thr = c_rel*nrm0 + c_abs, test r_0
-  EPI_BICG_SIGMA,   // sigma = (pt, z): alpha = rho / sigma
   EPI_BICG_CONV,    // q = (r,r), rho' = (rt,r): stopping test, then beta = rho'/rho
-  EPI_GP_ALPHA,     // den = (rt, q): alpha = rho / den
-  EPI_GP_ZETA,      // mu1..mu5: zeta, eta
   EPI_GP_CONV,      // q = (r,r), rho' = (rt,r): stopping test, zeta = 0 exit, beta
 };
 
+// Step prologues: scalars a step needs that follow from the inner products of the launch before
+// it, formed at the start of the step by thread 0 of every block (every block forms the same
+// bits, so no block waits for another).
+enum Pro {
+  PRO_BICG_ALPHA = 1,  // sigma = (pt, z): alpha = rho / sigma (sigma = 0: breakdown)
+  PRO_GP_ALPHA,        // den = (rt, q): alpha = rho / den (den = 0: breakdown)
+  PRO_GP_ZETA,         // mu1..mu5: zeta, eta (and tau after the first iteration)
+};
+
+// Out-of-line scalar operations for the epilogues (values and status bits cross the call in
+// registers), so that an epilogue needs only the registers of its largest operation, not of all
+// of them inlined together: the kernels that end with an epilogue keep their occupancy.
 template <int L>
-MPD void epilogue_body(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, uint32_t& st) {
+struct NumSt {
+  Num<L> v;
+  uint32_t st;
+};
+
+template <int L>
+__device__ __attribute__((noinline)) NumSt<L> s_mul(Num<L> a, Num<L> b) {
+  NumSt<L> r;
+  r.st = 0;
+  r.v = mul_rn<L>(a, b, r.st);
+  return r;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) NumSt<L> s_div(Num<L> a, Num<L> b) {
+  NumSt<L> r;
+  r.st = 0;
+  r.v = div_rn<L>(a, b, r.st);
+  return r;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) NumSt<L> s_add(Num<L> a, Num<L> b) {
+  NumSt<L> r;
+  r.st = 0;
+  r.v = add_rn<L>(a, b, r.st);
+  return r;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) NumSt<L> s_sub(Num<L> a, Num<L> b) {
+  NumSt<L> r;
+  r.st = 0;
+  r.v = sub_rn<L>(a, b, r.st);
+  return r;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) NumSt<L> s_sqrt(Num<L> a) {
+  NumSt<L> r;
+  r.st = 0;
+  r.v = sqrt_rn<L>(a, r.st);
+  return r;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) bool s_sqrt_le(Num<L> q, Num<L> thr) {
+  return sqrt_le<L>(q, thr);
+}
+
+// Scalars seen by an epilogue: read from a copy of the solve's slots in LDS (taken while the
+// launch's inner products were rounded), written to the copy and to the slots.
+template <int L>
+struct ScalarView {
+  uint32_t* cl;  // LDS copy: limb k of slot s at cl[s * L + k]
+  int32_t* ch;   // LDS copy: header of slot s at ch[s]
+  Scalars S;     // the slots in global memory
+  MPD Num<L> get(int slot) const {
+    Num<L> r;
+    const int32_t h = ch[slot];
+    r.e = h >> 1;
+    r.s = (uint32_t)h & 1u;
+#pragma unroll
+    for (int k = 0; k < L; ++k) r.m[k] = cl[slot * L + k];
+    return r;
+  }
+  MPD void put(int slot, const Num<L>& v) const {
+    ch[slot] = make_hdr(v.e, v.s);
+#pragma unroll
+    for (int k = 0; k < L; ++k) cl[slot * L + k] = v.m[k];
+    sstore<L>(S, slot, v);
+  }
+};
+
+// iters, maxit, hist_len: the solve's control values as they stood when the launch began
+template <int L>
+MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, int maxit, int hist_len,
+                       const VecRef& hist, uint32_t& st) {
   if (!ctl || epi == EPI_NONE) return;
+  auto mul = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_mul<L>(x, y); st |= r.st; return r.v; };
+  auto div = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_div<L>(x, y); st |= r.st; return r.v; };
+  auto add = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_add<L>(x, y); st |= r.st; return r.v; };
+  auto sub = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_sub<L>(x, y); st |= r.st; return r.v; };
   switch (epi) {
     case EPI_SETUP: {
-      const Num<L> q0 = sload_dev<L>(S, S_Q0);
-      const Num<L> nrm0 = sqrt_rn<L>(q0, st);
-      const Num<L> thr = add_rn<L>(mul_rn<L>(sload_dev<L>(S, S_CREL), nrm0, st), sload_dev<L>(S, S_CABS), st);
-      sstore<L>(S, S_NRM0, nrm0);
-      sstore<L>(S, S_THR, thr);
-      if (sqrt_le<L>(q0, thr)) {
+      const Num<L> q0 = sv.get(S_Q0);
+      const Num<L> nrm0 = [&] { const NumSt<L> r = s_sqrt<L>(q0); st |= r.st; return r.v; }();
+      const Num<L> thr = add(mul(sv.get(S_CREL), nrm0), sv.get(S_CABS));
+      sv.put(S_NRM0, nrm0);
+      sv.put(S_THR, thr);
+      if (s_sqrt_le<L>(q0, thr)) {
         finish(ctl, kConverged);
-      } else if (ctl->maxit <= 0) {
+      } else if (maxit <= 0) {
         finish(ctl, kNotConverged);
-      } else if (is_zero(sload_dev<L>(S, S_RHO))) {
+      } else if (is_zero(sv.get(S_RHO))) {
         finish(ctl, kBreakRho);
-      }
-      break;
-    }
-    case EPI_BICG_SIGMA: {
-      const Num<L> sigma = sload_dev<L>(S, S_SIGMA);
-      if (is_zero(sigma)) {
-        finish(ctl, kBreakSigma);
-      } else {
-        sstore<L>(S, S_ALPHA, div_rn<L>(sload_dev<L>(S, S_RHO), sigma, st));
-      }
-      break;
-    }
-    case EPI_GP_ALPHA: {
-      const Num<L> den = sload_dev<L>(S, S_DEN);
-      if (is_zero(den)) {
-        finish(ctl, kBreakSigma);
-      } else {
-        sstore<L>(S, S_ALPHA, div_rn<L>(sload_dev<L>(S, S_RHO), den, st));
-      }
-      break;
-    }
-    case EPI_GP_ZETA: {
-      const Num<L> mu1 = sload_dev<L>(S, S_MU1), mu2 = sload_dev<L>(S, S_MU2), mu3 = sload_dev<L>(S, S_MU3);
-      const Num<L> mu4 = sload_dev<L>(S, S_MU4), mu5 = sload_dev<L>(S, S_MU5);
-      if (ctl->iters == 0) {  // first iteration: zeta = mu2 / mu5, eta = 0
-        if (is_zero(mu5)) {
-          finish(ctl, kBreakTau);
-        } else {
-          Num<L> eta;
-          set_zero(eta, 0);
-          sstore<L>(S, S_ZETA, div_rn<L>(mu2, mu5, st));
-          sstore<L>(S, S_ETA, eta);
-        }
-      } else {
-        const Num<L> tau = sub_rn<L>(mul_rn<L>(mu5, mu1, st), mul_rn<L>(mu4, mu4, st), st);
-        if (is_zero(tau)) {
-          finish(ctl, kBreakTau);
-        } else {
-          const Num<L> zn = sub_rn<L>(mul_rn<L>(mu1, mu2, st), mul_rn<L>(mu3, mu4, st), st);
-          const Num<L> en = sub_rn<L>(mul_rn<L>(mu5, mu3, st), mul_rn<L>(mu4, mu2, st), st);
-          sstore<L>(S, S_TAU, tau);
-          sstore<L>(S, S_ZETA, div_rn<L>(zn, tau, st));
-          sstore<L>(S, S_ETA, div_rn<L>(en, tau, st));
-        }
       }
       break;
     }
     case EPI_BICG_CONV:
     case EPI_GP_CONV: {
-      const Num<L> q = sload_dev<L>(S, S_Q);
-      const int i = ctl->iters + 1;
-      if (hist.limb && i - 1 < ctl->hist_len) vstore<L>(hist, i - 1, q);
+      const Num<L> q = sv.get(S_Q);
+      const int i = iters + 1;
+      if (hist.limb && i - 1 < hist_len) vstore<L>(hist, i - 1, q);
       ctl->iters = i;
-      if (sqrt_le<L>(q, sload_dev<L>(S, S_THR))) {
+      if (s_sqrt_le<L>(q, sv.get(S_THR))) {
         finish(ctl, kConverged);
         break;
       }
-      if (epi == EPI_GP_CONV && is_zero(sload_dev<L>(S, S_ZETA))) {
+      if (epi == EPI_GP_CONV && is_zero(sv.get(S_ZETA))) {
         finish(ctl, kBreakZeta);
         break;
       }
-      if (i >= ctl->maxit) {
+      if (i >= maxit) {
         finish(ctl, kNotConverged);
         break;
       }
-      const Num<L> rho = sload_dev<L>(S, S_RHO);
-      const Num<L> rho_next = sload_dev<L>(S, S_RHO_NEXT);
-      sstore<L>(S, S_RHO_OLD, rho);
-      sstore<L>(S, S_RHO, rho_next);
+      const Num<L> rho = sv.get(S_RHO);
+      const Num<L> rho_next = sv.get(S_RHO_NEXT);
+      sv.put(S_RHO_OLD, rho);
+      sv.put(S_RHO, rho_next);
       if (is_zero(rho_next)) {
         finish(ctl, kBreakRho);
         break;
       }
       if (epi == EPI_BICG_CONV) {
-        sstore<L>(S, S_BETA, div_rn<L>(rho_next, rho, st));
+        sv.put(S_BETA, div(rho_next, rho));
       } else {
-        const Num<L> alpha = sload_dev<L>(S, S_ALPHA), zeta = sload_dev<L>(S, S_ZETA);
-        sstore<L>(S, S_ALPHA_OLD, alpha);
-        sstore<L>(S, S_ZETA_OLD, zeta);
-        sstore<L>(S, S_BETA, mul_rn<L>(div_rn<L>(rho_next, rho, st), div_rn<L>(alpha, zeta, st), st));
+        const Num<L> alpha = sv.get(S_ALPHA), zeta = sv.get(S_ZETA);
+        sv.put(S_ALPHA_OLD, alpha);
+        sv.put(S_ZETA_OLD, zeta);
+        sv.put(S_BETA, mul(div(rho_next, rho), div(alpha, zeta)));
       }
       break;
     }
@@ -226,18 +272,100 @@ MPD void epilogue_body(int epi, const Scalars& S, Ctl* ctl, const VecRef& hist, 
 // The epilogue as one out-of-line function per precision (it is large and runs once per launch,
 // in one thread).  Only plain values cross the call, so no caller object needs an address.
 template <int L>
-__device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* s_limb, int32_t* s_hdr,
-                                                      int64_t s_ld, Ctl* ctl, uint32_t* h_limb,
-                                                      int32_t* h_hdr, int64_t h_ld) {
-  const Scalars S{s_limb, s_hdr, s_ld};
+__device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb, int32_t* c_hdr,
+                                                      uint32_t* s_limb, int32_t* s_hdr, int64_t s_ld,
+                                                      Ctl* ctl, int iters, int maxit, int hist_len,
+                                                      uint32_t* h_limb, int32_t* h_hdr, int64_t h_ld) {
+  ScalarView<L> sv;
+  sv.cl = c_limb;
+  sv.ch = c_hdr;
+  sv.S = Scalars{s_limb, s_hdr, s_ld};
   VecRef hist;
   hist.limb = h_limb;
   hist.hdr = h_hdr;
   hist.ld = h_ld;
   uint32_t st = 0;
-  epilogue_body<L>(epi, S, ctl, hist, st);
+  epilogue_body<L>(epi, sv, ctl, iters, maxit, hist_len, hist, st);
   return st;
 }
+
+// A step prologue (by one thread): results to out (limbs of result k at o_limb[k * L ...], header
+// at o_hdr[k]): alpha; or zeta, eta, tau.  Returns the status bits in bits 0..7, a breakdown
+// (its solver outcome + 1, or 0) in bits 8..15, and bit 16 when tau was formed.
+template <int L>
+__device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_limb, int32_t* s_hdr,
+                                                      int64_t s_ld, int iters, uint32_t* o_limb,
+                                                      int32_t* o_hdr) {
+  const Scalars S{s_limb, s_hdr, s_ld};
+  uint32_t st = 0, brk = 0, tau_ok = 0;
+  auto mul = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_mul<L>(x, y); st |= r.st; return r.v; };
+  auto div = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_div<L>(x, y); st |= r.st; return r.v; };
+  auto sub = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_sub<L>(x, y); st |= r.st; return r.v; };
+  auto put = [&](int k, const Num<L>& v) {
+    o_hdr[k] = make_hdr(v.e, v.s);
+#pragma unroll
+    for (int i = 0; i < L; ++i) o_limb[k * L + i] = v.m[i];
+  };
+  Num<L> zero;
+  set_zero(zero, 0);
+  put(0, zero);
+  put(1, zero);
+  put(2, zero);
+  switch (kind) {
+    case PRO_BICG_ALPHA:
+    case PRO_GP_ALPHA: {
+      const Num<L> den = sload<L>(S, kind == PRO_BICG_ALPHA ? S_SIGMA : S_DEN);
+      if (is_zero(den)) brk = kBreakSigma + 1;
+      else put(0, div(sload<L>(S, S_RHO), den));
+      break;
+    }
+    case PRO_GP_ZETA: {
+      const Num<L> mu1 = sload<L>(S, S_MU1), mu2 = sload<L>(S, S_MU2), mu3 = sload<L>(S, S_MU3);
+      const Num<L> mu4 = sload<L>(S, S_MU4), mu5 = sload<L>(S, S_MU5);
+      if (iters == 0) {  // first iteration: zeta = mu2 / mu5, eta = 0
+        if (is_zero(mu5)) brk = kBreakTau + 1;
+        else put(0, div(mu2, mu5));
+      } else {
+        const Num<L> tau = sub(mul(mu5, mu1), mul(mu4, mu4));
+        if (is_zero(tau)) {
+          brk = kBreakTau + 1;
+        } else {
+          const Num<L> zn = sub(mul(mu1, mu2), mul(mu3, mu4));
+          const Num<L> en = sub(mul(mu5, mu3), mul(mu4, mu2));
+          put(0, div(zn, tau));
+          put(1, div(en, tau));
+          put(2, tau);
+          tau_ok = 1;
+        }
+      }
+      break;
+    }
+    default:
+      break;
+  }
+  return (st & 0xFFu) | (brk << 8) | (tau_ok << 16);
+}
+
+template <int L>
+MPD Num<L> lds_num(const uint32_t* limb, const int32_t* hdr, int k) {
+  Num<L> r;
+  const int32_t h = hdr[k];
+  r.e = h >> 1;
+  r.s = (uint32_t)h & 1u;
+#pragma unroll
+  for (int i = 0; i < L; ++i) r.m[i] = limb[k * L + i];
+  return r;
+}
+
+// A step's prologue results, for the last block's epilogue (scalar slot of result k, the LDS
+// copies) and the breakdown it found (solver outcome + 1, or 0).
+struct ProOut {
+  int n;
+  int slot[3];
+  const uint32_t* limb;
+  const int32_t* hdr;
+  int brk;
+};
 
 // ------------------------------------------------------------------------------------------
 // Exact inner products.
@@ -510,6 +638,7 @@ struct DotOut {
   int slot[kDotMaxND];
   VecRef out[kDotMaxND];  // result d goes to element 0 of out[d] (in a batch: solve 0's scalar
                           // slot, moved to each solve's own slots)
+  int sslot[kDotMaxND];   // the scalar slot out[d] is (the epilogue reads it), or -1
   int epi;
   VecRef hist;
 };
@@ -537,13 +666,19 @@ MPD bool last_block(const DotWork& dw, int pair, unsigned idx, unsigned nblocks)
   return true;
 }
 
-template <int L, int NT>
+// EPI: whether the kernel can run a driver epilogue (kernels that never do are compiled without
+// it, and keep their registers).
+template <int L, int NT, bool EPI = true>
 MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched, unsigned idx,
                      unsigned nblocks, Ctl* ctl, const Scalars& S, int32_t* ndone, uint32_t* status,
-                     uint32_t st, int64_t* lds, int cap) {
+                     uint32_t st, int64_t* lds, int cap, const ProOut* pro = nullptr) {
   constexpr int NW = NT / 64;
+  static_assert(kNumScalars <= 32, "one lane per scalar slot, control values in lanes 32..34");
   __shared__ uint32_t s_last;
   __shared__ int32_t s_lo[kDotMaxND], s_hi[kDotMaxND];
+  __shared__ uint32_t s_cl[kNumScalars * L];  // the solve's scalar slots, for the epilogue
+  __shared__ int32_t s_ch[kNumScalars];
+  __shared__ int32_t s_ctl[3];                // iters, maxit, hist_len
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   wait_memory();
   __syncthreads();
@@ -554,6 +689,24 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
     return;
   }
   const int64_t slot0 = (int64_t)pair * kDotSlots;
+  const int brk = pro ? pro->brk : 0;  // the step broke down: its products are not kept
+  const bool epi_on = EPI && ctl != nullptr && O.epi != EPI_NONE && !brk;
+  // the epilogue's inputs are requested first, so that they arrive while the rings are read
+  uint32_t pm[L];
+  int32_t ph = 0, pc = 0;
+  if (epi_on && wv == 0) {
+    if (lane < kNumScalars) {
+      ph = ld_dev(S.hdr + lane);
+#pragma unroll
+      for (int k = 0; k < L; ++k) pm[k] = ld_dev(S.limb + (int64_t)k * S.ld + lane);
+    } else if (lane == 32) {
+      pc = ld_dev(&ctl->iters);
+    } else if (lane == 33) {
+      pc = ld_dev(&ctl->maxit);
+    } else if (lane == 34) {
+      pc = ld_dev(&ctl->hist_len);
+    }
+  }
   auto out_of = [&](const VecRef& o0) {
     VecRef o = o0;
     if (batched) {
@@ -561,6 +714,17 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
       o.hdr += (int64_t)pair * kNumScalars;
     }
     return o;
+  };
+  auto keep = [&](int dd, const Num<L>& res) {  // by one thread
+    if (brk) return;
+    const VecRef o = out_of(O.out[dd]);
+    store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+    const int ss = O.sslot[dd];
+    if (ss >= 0) {
+      s_ch[ss] = make_hdr(res.e, res.s);
+#pragma unroll
+      for (int k = 0; k < L; ++k) s_cl[ss * L + k] = res.m[k];
+    }
   };
   // windows of at most 63 digits: one wavefront each
 #pragma unroll
@@ -572,8 +736,7 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
         Num<L> res;
         if (hi < lo) set_zero(res, 0);
         else res = ring_round_narrow<L>(dw, slot0 + O.slot[dd], lo, hi, st);
-        const VecRef o = out_of(O.out[dd]);
-        if (lane == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+        if (lane == 0) keep(dd, res);
       }
       if (lane == 0) {
         s_lo[dd] = lo;
@@ -589,22 +752,52 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
       const int32_t lo = s_lo[dd], hi = s_hi[dd];
       if (hi >= lo && ring_window<L>(lo, hi) > 63) {
         const Num<L> res = ring_round_wide<L, NT>(dw, slot0 + O.slot[dd], lo, hi, lds, cap, st);
-        const VecRef o = out_of(O.out[dd]);
-        if (t == 0) store_dev<L>(res, o.limb, o.hdr, o.ld, 0);
+        if (t == 0) keep(dd, res);
       }
     }
   }
   if (ctl && st) atomicOr(&ctl->flags, st);
-  // every result is stored before the epilogue reads them
-  wait_memory();
-  __syncthreads();
-  if (t == 0) {
-    const int was_done = ctl ? ctl->done : 0;
-    const uint32_t st2 = (ctl && O.epi != EPI_NONE)
-        ? epilogue<L>(O.epi, S.limb, S.hdr, S.ld, ctl, O.hist.limb, O.hist.hdr, O.hist.ld) : 0u;
-    if (ctl && st2) atomicOr(&ctl->flags, st2);
-    if (ndone && ctl && !was_done && ctl->done) atomicAdd(ndone, 1);
-    st |= st2;
+  if (brk && t == 0) {
+    finish(ctl, brk - 1);
+    if (ndone) atomicAdd(ndone, 1);
+  }
+  if (!epi_on) {
+    if (st) atomicOr(status, st);
+    return;
+  }
+  if (wv == 0) {  // the prefetched slots, except those this launch just formed
+    bool fresh = false;
+#pragma unroll
+    for (int dd = 0; dd < kDotMaxND; ++dd) fresh |= dd < O.nd && O.sslot[dd] == lane;
+    if (pro) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k < pro->n && pro->slot[k] == lane) {
+          fresh = true;
+          s_ch[lane] = pro->hdr[k];
+#pragma unroll
+          for (int i = 0; i < L; ++i) s_cl[lane * L + i] = pro->limb[k * L + i];
+        }
+      }
+    }
+    if (lane < kNumScalars && !fresh) {
+      s_ch[lane] = ph;
+#pragma unroll
+      for (int k = 0; k < L; ++k) s_cl[lane * L + k] = pm[k];
+    } else if (lane >= 32 && lane < 35) {
+      s_ctl[lane - 32] = pc;
+    }
+  }
+  lds_barrier();
+  if constexpr (EPI) {
+    if (t == 0) {
+      const uint32_t st2 = epilogue<L>(O.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, s_ctl[0], s_ctl[1],
+                                       s_ctl[2], O.hist.limb, O.hist.hdr, O.hist.ld);
+      if (st2) atomicOr(&ctl->flags, st2);
+      // the solve was running when the launch began (its blocks run only then)
+      if (ndone && ctl->done) atomicAdd(ndone, 1);
+      st |= st2;
+    }
   }
   if (st) atomicOr(status, st);
 }
@@ -715,6 +908,37 @@ MPD EwCtx ew_ctx(const VecArgs& A) {
   return c;
 }
 
+// A step prologue run at the start of an element-wise step: thread 0 forms the values, the
+// block reads them after a barrier.  Block 0 of the solve keeps them in the scalar slots (every
+// block formed the same bits); the step's last block takes them from `pro`.
+template <int L>
+struct ProLds {
+  uint32_t limb[3 * L];
+  int32_t hdr[3];
+  uint32_t word;
+};
+
+template <int L>
+MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, int nres, const int (&slots)[3],
+                        uint32_t& st) {
+  if (threadIdx.x == 0)
+    P.word = prologue<L>(kind, c.S.limb, c.S.hdr, c.S.ld, c.ctl->iters, P.limb, P.hdr);
+  __syncthreads();
+  const uint32_t w = P.word;
+  if (threadIdx.x == 0) st |= w & 0xFFu;
+  ProOut o;
+  o.brk = (int)((w >> 8) & 0xFFu);
+  o.n = (kind == PRO_GP_ZETA) ? (((w >> 16) & 1u) ? 3 : 2) : nres;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o.slot[k] = slots[k];
+  o.limb = P.limb;
+  o.hdr = P.hdr;
+  if (!o.brk && c.idx == 0 && threadIdx.x == 0) {
+    for (int k = 0; k < o.n; ++k) sstore<L>(c.S, slots[k], lds_num<L>(P.limb, P.hdr, k));
+  }
+  return o;
+}
+
 // The scalar slot as a one-element vector reference.
 __host__ __device__ inline VecRef slot_ref(const Scalars& S, int slot) {
   VecRef r;
@@ -797,11 +1021,14 @@ __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
 template <int L>
 __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
-  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
-  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+  // alpha = rho / sigma, sigma = (pt, A p) from the product before
+  const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, 1, {S_ALPHA, 0, 0}, st);
+  const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
     const bool ok = i < A.n;
     Num<L> r, rt;
@@ -819,7 +1046,7 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
   }
   dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
-                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
 // GPBiCG direction: v = {p, w, r, v, q, u}.  First iteration p = r; then
@@ -851,12 +1078,15 @@ __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
 template <int L>
 __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   const bool first = c.ctl->iters == 0;
-  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
-  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+  // alpha = rho / den, den = (rt, A p) from the product before
+  const ProOut pro = run_prologue<L>(pl, PRO_GP_ALPHA, c, 1, {S_ALPHA, 0, 0}, st);
+  const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
     const bool ok = i < A.n;
     Num<L> tn, y;
@@ -885,7 +1115,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
     pass_dot<L, 256>(lds, ok, hy, ht, y.m, tn.m, A.dots, c.abase + A.fd.slot[1]);
   }
   dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
-                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
 // GPBiCG update: v = {u, z, x, r, q, s, p, t} and v2 = {y, v} in w[]:
@@ -899,13 +1129,16 @@ struct GpUpdArgs {
 template <int L>
 __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
   const VecArgs& A = G.a;
   const EwCtx c = ew_ctx(A);
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
+  // zeta, eta (and tau) from mu1..mu5 of the two launches before
+  const ProOut pro = run_prologue<L>(pl, PRO_GP_ZETA, c, 3, {S_ZETA, S_ETA, S_TAU}, st);
   const Num<L> alpha = sload<L>(c.S, S_ALPHA), beta = sload<L>(c.S, S_BETA);
-  const Num<L> zeta = sload<L>(c.S, S_ZETA), eta = sload<L>(c.S, S_ETA);
-  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+  const Num<L> zeta = lds_num<L>(pl.limb, pl.hdr, 0), eta = lds_num<L>(pl.limb, pl.hdr, 1);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
     const bool ok = i < A.n;
     Num<L> rn, rt;
@@ -934,7 +1167,7 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, rn.m, A.dots, c.abase + A.fd.slot[1]);
   }
   dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
-                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>());
+                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
 // Write a constant into element 0 of a vector or a scalar slot (kernel arguments carry it).

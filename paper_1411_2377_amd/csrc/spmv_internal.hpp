@@ -15,6 +15,7 @@ struct SpmvFuse {
   mp::VecRef part[3] = {};
   int slot[3] = {0, 0, 0};
   mp::VecRef out[3] = {};
+  int sslot[3] = {-1, -1, -1};  // the scalar slot of out[k], or -1
   int epi = 0;
   mp::VecRef hist = {};
   mp::DotWork dots = {};

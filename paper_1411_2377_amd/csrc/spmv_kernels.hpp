@@ -145,7 +145,7 @@ MPD void spmv_fused_dots(const SpmvArgs& A, const SpmvBlock& B, bool has_row, in
   const unsigned idx =
       batched ? (unsigned)(B.rb - ((int64_t)A.first_tile[B.pair] * kTile - B.rhs * A.y_rstride) / RPW)
               : blockIdx.x;
-  dots_finish<L, NT>(A.dots, A.fd, B.pair, batched, idx, nblocks, A.ctl ? A.ctl + B.pair : nullptr,
+  dots_finish<L, NT, false>(A.dots, A.fd, B.pair, batched, idx, nblocks, A.ctl ? A.ctl + B.pair : nullptr,
                      A.S.at(B.pair), A.ndone, A.status, st, lds.win, lds_window_digits<L, NT>());
 }
 

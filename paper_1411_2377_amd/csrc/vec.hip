@@ -196,6 +196,7 @@ int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream
   a.y[0] = ref(*y);
   a.o.nd = 1;
   a.o.out[0] = ref(*out);
+  a.o.sslot[0] = -1;
   a.o.slot[0] = 0;
   a.o.epi = mp::EPI_NONE;
   a.w = dot_work(ctx->dot_anchor, ctx->dot_win, ctx->dot_ticket, 1, kDotRingLog2, kDotReps, kDotGroups);
