@@ -117,8 +117,8 @@ enum Epi {
 };
 
 // Step prologues: scalars a step needs that follow from the inner products of the launch before
-// it, formed at the start of the step by thread 0 of every block (every block forms the same
-// bits, so no block waits for another).
+// it, formed at the start of the step by the first wavefront of every block (every block forms
+// the same bits, so no block waits for another).
 enum Pro {
   PRO_BICG_ALPHA = 1,  // sigma = (pt, z): alpha = rho / sigma (sigma = 0: breakdown)
   PRO_GP_ALPHA,        // den = (rt, q): alpha = rho / den (den = 0: breakdown)
@@ -179,6 +179,17 @@ __device__ __attribute__((noinline)) bool s_sqrt_le(Num<L> q, Num<L> thr) {
   return sqrt_le<L>(q, thr);
 }
 
+// A value held by lane `src`, to every lane.
+template <int L>
+MPD Num<L> shfl_num(const Num<L>& v, int src) {
+  Num<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) r.m[k] = __shfl(v.m[k], src);
+  r.e = __shfl(v.e, src);
+  r.s = __shfl(v.s, src);
+  return r;
+}
+
 // Scalars seen by an epilogue: read from a copy of the solve's slots in LDS (taken while the
 // launch's inner products were rounded), written to the copy and to the slots.
 template <int L>
@@ -203,28 +214,36 @@ struct ScalarView {
   }
 };
 
-// iters, maxit, hist_len: the solve's control values as they stood when the launch began
+// iters, maxit, hist_len: the solve's control values as they stood when the launch began.
+// Run by every lane of one wavefront: the formulas' values are formed in every lane (the two
+// divisions of GPBiCG's beta side by side in lanes 0 and 1); lane 0 writes.  Returns the status
+// bits in every lane.
 template <int L>
 MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, int maxit, int hist_len,
                        const VecRef& hist, uint32_t& st) {
   if (!ctl || epi == EPI_NONE) return;
+  const bool w0 = (threadIdx.x & 63) == 0;
   auto mul = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_mul<L>(x, y); st |= r.st; return r.v; };
-  auto div = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_div<L>(x, y); st |= r.st; return r.v; };
   auto add = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_add<L>(x, y); st |= r.st; return r.v; };
-  auto sub = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_sub<L>(x, y); st |= r.st; return r.v; };
+  auto put = [&](int slot, const Num<L>& v) {
+    if (w0) sv.put(slot, v);
+  };
+  auto done = [&](int outcome) {
+    if (w0) finish(ctl, outcome);
+  };
   switch (epi) {
     case EPI_SETUP: {
       const Num<L> q0 = sv.get(S_Q0);
       const Num<L> nrm0 = [&] { const NumSt<L> r = s_sqrt<L>(q0); st |= r.st; return r.v; }();
       const Num<L> thr = add(mul(sv.get(S_CREL), nrm0), sv.get(S_CABS));
-      sv.put(S_NRM0, nrm0);
-      sv.put(S_THR, thr);
+      put(S_NRM0, nrm0);
+      put(S_THR, thr);
       if (s_sqrt_le<L>(q0, thr)) {
-        finish(ctl, kConverged);
+        done(kConverged);
       } else if (maxit <= 0) {
-        finish(ctl, kNotConverged);
+        done(kNotConverged);
       } else if (is_zero(sv.get(S_RHO))) {
-        finish(ctl, kBreakRho);
+        done(kBreakRho);
       }
       break;
     }
@@ -232,35 +251,50 @@ MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, in
     case EPI_GP_CONV: {
       const Num<L> q = sv.get(S_Q);
       const int i = iters + 1;
-      if (hist.limb && i - 1 < hist_len) vstore<L>(hist, i - 1, q);
-      ctl->iters = i;
+      if (w0) {
+        if (hist.limb && i - 1 < hist_len) vstore<L>(hist, i - 1, q);
+        ctl->iters = i;
+      }
       if (s_sqrt_le<L>(q, sv.get(S_THR))) {
-        finish(ctl, kConverged);
+        done(kConverged);
         break;
       }
       if (epi == EPI_GP_CONV && is_zero(sv.get(S_ZETA))) {
-        finish(ctl, kBreakZeta);
+        done(kBreakZeta);
         break;
       }
       if (i >= maxit) {
-        finish(ctl, kNotConverged);
+        done(kNotConverged);
         break;
       }
       const Num<L> rho = sv.get(S_RHO);
       const Num<L> rho_next = sv.get(S_RHO_NEXT);
-      sv.put(S_RHO_OLD, rho);
-      sv.put(S_RHO, rho_next);
       if (is_zero(rho_next)) {
-        finish(ctl, kBreakRho);
+        put(S_RHO_OLD, rho);
+        put(S_RHO, rho_next);
+        done(kBreakRho);
         break;
       }
+      const Num<L> alpha = sv.get(S_ALPHA), zeta = sv.get(S_ZETA);
+      // lane 0: rho' / rho; lane 1 (GPBiCG): alpha / zeta
+      const int lane = threadIdx.x & 63;
+      NumSt<L> dq;
+      dq.st = 0;
+      set_zero(dq.v, 0);
+      if (lane == 0 || (lane == 1 && epi == EPI_GP_CONV))
+        dq = s_div<L>(lane == 0 ? rho_next : alpha, lane == 0 ? rho : zeta);
+      const Num<L> d0 = shfl_num<L>(dq.v, 0);
+      st |= __shfl(dq.st, 0);
+      put(S_RHO_OLD, rho);
+      put(S_RHO, rho_next);
       if (epi == EPI_BICG_CONV) {
-        sv.put(S_BETA, div(rho_next, rho));
+        put(S_BETA, d0);
       } else {
-        const Num<L> alpha = sv.get(S_ALPHA), zeta = sv.get(S_ZETA);
-        sv.put(S_ALPHA_OLD, alpha);
-        sv.put(S_ZETA_OLD, zeta);
-        sv.put(S_BETA, mul(div(rho_next, rho), div(alpha, zeta)));
+        const Num<L> d1 = shfl_num<L>(dq.v, 1);
+        st |= __shfl(dq.st, 1);
+        put(S_ALPHA_OLD, alpha);
+        put(S_ZETA_OLD, zeta);
+        put(S_BETA, mul(d0, d1));
       }
       break;
     }
@@ -270,7 +304,7 @@ MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, in
 }
 
 // The epilogue as one out-of-line function per precision (it is large and runs once per launch,
-// in one thread).  Only plain values cross the call, so no caller object needs an address.
+// in one wavefront).  Only plain values cross the call, so no caller object needs an address.
 template <int L>
 __device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb, int32_t* c_hdr,
                                                       uint32_t* s_limb, int32_t* s_hdr, int64_t s_ld,
@@ -289,18 +323,18 @@ __device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb
   return st;
 }
 
-// A step prologue (by one thread): results to out (limbs of result k at o_limb[k * L ...], header
-// at o_hdr[k]): alpha; or zeta, eta, tau.  Returns the status bits in bits 0..7, a breakdown
-// (its solver outcome + 1, or 0) in bits 8..15, and bit 16 when tau was formed.
+// A step prologue, by every lane of one wavefront (independent operations run on different
+// lanes at once): results to out (limbs of result k at o_limb[k * L ...], header at o_hdr[k]):
+// alpha; or zeta, eta, tau.  Returns, in every lane, the status bits of the operations the
+// formulas use in bits 0..7, a breakdown (its solver outcome + 1, or 0) in bits 8..15, and bit
+// 16 when tau was formed.
 template <int L>
 __device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_limb, int32_t* s_hdr,
                                                       int64_t s_ld, int iters, uint32_t* o_limb,
                                                       int32_t* o_hdr) {
+  const int lane = threadIdx.x & 63;
   const Scalars S{s_limb, s_hdr, s_ld};
   uint32_t st = 0, brk = 0, tau_ok = 0;
-  auto mul = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_mul<L>(x, y); st |= r.st; return r.v; };
-  auto div = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_div<L>(x, y); st |= r.st; return r.v; };
-  auto sub = [&](const Num<L>& x, const Num<L>& y) { const NumSt<L> r = s_sub<L>(x, y); st |= r.st; return r.v; };
   auto put = [&](int k, const Num<L>& v) {
     o_hdr[k] = make_hdr(v.e, v.s);
 #pragma unroll
@@ -308,41 +342,75 @@ __device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_lim
   };
   Num<L> zero;
   set_zero(zero, 0);
-  put(0, zero);
-  put(1, zero);
-  put(2, zero);
+  if (lane < 3) put(lane, zero);
   switch (kind) {
     case PRO_BICG_ALPHA:
     case PRO_GP_ALPHA: {
       const Num<L> den = sload<L>(S, kind == PRO_BICG_ALPHA ? S_SIGMA : S_DEN);
-      if (is_zero(den)) brk = kBreakSigma + 1;
-      else put(0, div(sload<L>(S, S_RHO), den));
+      const Num<L> rho = sload<L>(S, S_RHO);
+      if (is_zero(den)) {
+        brk = kBreakSigma + 1;
+      } else if (lane == 0) {
+        const NumSt<L> q = s_div<L>(rho, den);
+        st = q.st;
+        put(0, q.v);
+      }
       break;
     }
     case PRO_GP_ZETA: {
       const Num<L> mu1 = sload<L>(S, S_MU1), mu2 = sload<L>(S, S_MU2), mu3 = sload<L>(S, S_MU3);
       const Num<L> mu4 = sload<L>(S, S_MU4), mu5 = sload<L>(S, S_MU5);
       if (iters == 0) {  // first iteration: zeta = mu2 / mu5, eta = 0
-        if (is_zero(mu5)) brk = kBreakTau + 1;
-        else put(0, div(mu2, mu5));
-      } else {
-        const Num<L> tau = sub(mul(mu5, mu1), mul(mu4, mu4));
-        if (is_zero(tau)) {
+        if (is_zero(mu5)) {
           brk = kBreakTau + 1;
-        } else {
-          const Num<L> zn = sub(mul(mu1, mu2), mul(mu3, mu4));
-          const Num<L> en = sub(mul(mu5, mu3), mul(mu4, mu2));
-          put(0, div(zn, tau));
-          put(1, div(en, tau));
-          put(2, tau);
-          tau_ok = 1;
+        } else if (lane == 0) {
+          const NumSt<L> z = s_div<L>(mu2, mu5);
+          st = z.st;
+          put(0, z.v);
         }
+        break;
       }
+      // lanes 0..5: mu5 mu1, mu4 mu4 | mu1 mu2, mu3 mu4 | mu5 mu3, mu4 mu2
+      const Num<L> fa = lane == 0 ? mu5 : lane == 1 ? mu4 : lane == 2 ? mu1 : lane == 3 ? mu3 : lane == 4 ? mu5 : mu4;
+      const Num<L> fb = lane == 0 ? mu1 : lane == 1 ? mu4 : lane == 2 ? mu2 : lane == 3 ? mu4 : lane == 4 ? mu3 : mu2;
+      NumSt<L> pr;
+      pr.st = 0;
+      set_zero(pr.v, 0);
+      if (lane < 6) pr = s_mul<L>(fa, fb);
+      // lanes 0..2: tau, zeta's numerator, eta's numerator
+      const Num<L> da = shfl_num<L>(pr.v, 2 * lane < 64 ? 2 * lane : 0);
+      const Num<L> db = shfl_num<L>(pr.v, 2 * lane + 1 < 64 ? 2 * lane + 1 : 0);
+      NumSt<L> df;
+      df.st = 0;
+      set_zero(df.v, 0);
+      if (lane < 3) df = s_sub<L>(da, db);
+      const Num<L> tau = shfl_num<L>(df.v, 0);
+      const uint32_t st_tau = __shfl(pr.st, 0) | __shfl(pr.st, 1) | __shfl(df.st, 0);
+      if (is_zero(tau)) {
+        brk = kBreakTau + 1;
+        st = st_tau;
+        break;
+      }
+      // lanes 0, 1: zeta = zn / tau, eta = en / tau
+      const Num<L> num = shfl_num<L>(df.v, lane < 2 ? lane + 1 : 0);
+      NumSt<L> qt;
+      qt.st = 0;
+      set_zero(qt.v, 0);
+      if (lane < 2) qt = s_div<L>(num, tau);
+      if (lane < 2) put(lane, qt.v);
+      if (lane == 0) put(2, tau);
+      uint32_t all = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) all |= __shfl(pr.st, k);
+      all |= __shfl(df.st, 1) | __shfl(df.st, 2) | __shfl(qt.st, 0) | __shfl(qt.st, 1);
+      st = st_tau | all;
+      tau_ok = 1;
       break;
     }
     default:
       break;
   }
+  st = __shfl(st, 0);
   return (st & 0xFFu) | (brk << 8) | (tau_ok << 16);
 }
 
@@ -790,13 +858,15 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
   }
   lds_barrier();
   if constexpr (EPI) {
-    if (t == 0) {
+    if (wv == 0) {  // one wavefront
       const uint32_t st2 = epilogue<L>(O.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, s_ctl[0], s_ctl[1],
                                        s_ctl[2], O.hist.limb, O.hist.hdr, O.hist.ld);
-      if (st2) atomicOr(&ctl->flags, st2);
-      // the solve was running when the launch began (its blocks run only then)
-      if (ndone && ctl->done) atomicAdd(ndone, 1);
-      st |= st2;
+      if (t == 0) {
+        if (st2) atomicOr(&ctl->flags, st2);
+        // the solve was running when the launch began (its blocks run only then)
+        if (ndone && ctl->done) atomicAdd(ndone, 1);
+        st |= st2;
+      }
     }
   }
   if (st) atomicOr(status, st);
@@ -908,8 +978,8 @@ MPD EwCtx ew_ctx(const VecArgs& A) {
   return c;
 }
 
-// A step prologue run at the start of an element-wise step: thread 0 forms the values, the
-// block reads them after a barrier.  Block 0 of the solve keeps them in the scalar slots (every
+// A step prologue run at the start of an element-wise step: the first wavefront forms the
+// values, the block reads them after a barrier.  Block 0 of the solve keeps them in the scalar slots (every
 // block formed the same bits); the step's last block takes them from `pro`.
 template <int L>
 struct ProLds {
@@ -921,8 +991,10 @@ struct ProLds {
 template <int L>
 MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, int nres, const int (&slots)[3],
                         uint32_t& st) {
-  if (threadIdx.x == 0)
-    P.word = prologue<L>(kind, c.S.limb, c.S.hdr, c.S.ld, c.ctl->iters, P.limb, P.hdr);
+  if (threadIdx.x < 64) {  // one wavefront
+    const uint32_t w = prologue<L>(kind, c.S.limb, c.S.hdr, c.S.ld, c.ctl->iters, P.limb, P.hdr);
+    if (threadIdx.x == 0) P.word = w;
+  }
   __syncthreads();
   const uint32_t w = P.word;
   if (threadIdx.x == 0) st |= w & 0xFFu;
