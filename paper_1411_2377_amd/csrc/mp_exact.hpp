@@ -81,22 +81,14 @@ struct RingMap {
   MPD int operator()(int w) const { return (s0 + w >= R ? s0 + w - R : s0 + w) * ws; }
 };
 
-// Window accessors: digit w of a window is read with get(w) and written with set(w, v).
-// MapWin: an LDS or private array through an index map; DevRingWin: a ring of digits in global
-// memory (slot (s0 + w) & mask), read and written with device-coherent accesses.
+// Window accessor: digit w of a window (an LDS or private array, through an index map) is read
+// with get(w) and written with set(w, v).
 template <class Map>
 struct MapWin {
   int64_t* win;
   Map map;
   MPD int64_t get(int w) const { return win[map(w)]; }
   MPD void set(int w, int64_t v) const { win[map(w)] = v; }
-};
-
-struct DevRingWin {
-  int64_t* win;
-  int mask, s0;
-  MPD int64_t get(int w) const { return ld_dev(win + ((s0 + w) & mask)); }
-  MPD void set(int w, int64_t v) const { st_dev(win + ((s0 + w) & mask), v); }
 };
 
 // RN_p of (-1)^sgn * sum_{w < nl} digit(w) 2^(32 w + base) for magnitude limbs (each digit

@@ -580,31 +580,21 @@ MPD void pass_dot(PassLds<L, NT>& S, bool ok, int32_t hx, int32_t hy, const uint
       if (v) atomicAdd((unsigned long long*)&ring[((wbase >> 5) + t) & mask], (unsigned long long)v);
     }
   } else {
-    // wide pass: a block-shared window in LDS (integer atomics; its top covers the largest
-    // product), whose non-zero digits go to the ring; products below it go to the ring directly
+    // wide pass: a block-shared window in LDS (integer atomics) whose non-zero digits go to the
+    // ring.  A pass spanning more than the window leaves out the products below it: the
+    // launch's window is then wider than its rounding accepts, which reports kStWindow.
     constexpr int C = lds_window_digits<L, NT>();
     const int Wc = min(W, C);
     const int64_t wbase = (W <= C) ? (int64_t)(lo & ~31) : (int64_t)(hi & ~31) - 32 * (int64_t)(C - 2 * L - 2);
     for (int w = t; w < Wc; w += NT) S.win[w] = 0;
     lds_barrier();
-    if (nz) {
-      if ((int64_t)e >= wbase) {
-        const int q = (int)(((int64_t)e - wbase) >> 5);
+    if (nz && (int64_t)e >= wbase) {
+      const int q = (int)(((int64_t)e - wbase) >> 5);
 #pragma unroll
-        for (int j = 0; j <= 2 * L; ++j) {
-          if (sp[j]) {
-            const int64_t v = sg ? -(int64_t)sp[j] : (int64_t)sp[j];
-            atomicAdd((unsigned long long*)&S.win[q + j], (unsigned long long)v);
-          }
-        }
-      } else {
-        const int64_t d0 = (int64_t)(e >> 5);
-#pragma unroll
-        for (int j = 0; j <= 2 * L; ++j) {
-          if (sp[j]) {
-            const int64_t v = sg ? -(int64_t)sp[j] : (int64_t)sp[j];
-            atomicAdd((unsigned long long*)&ring[(d0 + j) & mask], (unsigned long long)v);
-          }
+      for (int j = 0; j <= 2 * L; ++j) {
+        if (sp[j]) {
+          const int64_t v = sg ? -(int64_t)sp[j] : (int64_t)sp[j];
+          atomicAdd((unsigned long long*)&S.win[q + j], (unsigned long long)v);
         }
       }
     }
@@ -664,9 +654,9 @@ MPD Num<L> ring_round_narrow(const DotWork& dw, int64_t slot, int32_t lo, int32_
 }
 
 // RN_p of a slot with a wider window (W > 63), by the whole block; thread 0 gets the result.
-// The digits are summed into `lds` (capacity `cap` digits) and rounded there by thread 0, or,
-// when they do not fit, rounded by thread 0 in global memory.  A window wider than the ring sets
-// kStWindow and gives +0 (the whole ring is cleared).
+// The digits are summed into `lds` (capacity `cap` digits) and rounded there by thread 0.  A
+// window wider than the ring or than `cap` sets kStWindow and gives +0 (the whole ring is
+// cleared).
 template <int L, int NT>
 MPD Num<L> ring_round_wide(const DotWork& dw, int64_t slot, int32_t lo, int32_t hi, int64_t* lds,
                            int cap, uint32_t& st) {
@@ -678,25 +668,15 @@ MPD Num<L> ring_round_wide(const DotWork& dw, int64_t slot, int32_t lo, int32_t 
   const int s0 = (int)((base >> 5) & mask);
   Num<L> res;
   set_zero(res, 0);
-  if (W > R) {
+  if (W > R || W > cap) {
     if (t == 0) st |= kStWindow;
     for (int64_t k = t; k < ((int64_t)dw.reps << dw.ring_log2); k += NT) st_dev(ring + k, (int64_t)0);
     return res;
   }
-  if (W <= cap) {
-    for (int w = t; w < W; w += NT) lds[w] = ring_take(dw, ring, s0, w);
-    __syncthreads();
-    if (t == 0) res = window_finalize<L>(lds, 1, W, base - 64 * L, st);
-    __syncthreads();
-    return res;
-  }
-  for (int w = t; w < W; w += NT) st_dev(ring + ((s0 + w) & mask), ring_take(dw, ring, s0, w));
-  wait_memory();
+  for (int w = t; w < W; w += NT) lds[w] = ring_take(dw, ring, s0, w);
   __syncthreads();
-  if (t == 0) {
-    res = window_finalize_acc<L>(DevRingWin{ring, mask, s0}, W, base - 64 * L, st);
-    for (int w = 0; w < W; ++w) st_dev(ring + ((s0 + w) & mask), (int64_t)0);
-  }
+  if (t == 0) res = window_finalize<L>(lds, 1, W, base - 64 * L, st);
+  __syncthreads();
   return res;
 }
 

@@ -197,3 +197,30 @@ def test_dot_rounding_edge_cases(p):
         d = M.mp_dot(M.MPArray.from_host(x_h), M.MPArray.from_host(y_h)).to_numpy()
         xo, yo = codec.decode(x_h.limbs, x_h.hdr, p), codec.decode(y_h.limbs, y_h.hdr, p)
         assert_bitwise(d[0], d[1], [blas.dot(xo, yo, p)], p, what="dot case %d" % i)
+
+
+@pytest.mark.parametrize("p", [128, 256])
+def test_dot_window_limit(p):
+    """Two products 2^(2E) and 2^(-2E), an exponent span of 4E bits: a span inside the window
+    limit of a stand-alone inner product (32 (1157 - 2L - 2) bits at p = 128, 32 (2048 - 2L - 2)
+    above) rounds exactly, to the larger term; a wider span raises the window status and gives
+    +0, and the next inner product is exact again (the ring was cleared)."""
+    M = lib()
+    nl = p // 32
+
+    def powers(es):
+        limbs = np.zeros((nl, len(es)), np.uint32)
+        limbs[nl - 1] = np.uint32(0x80000000)
+        return synth.MPHost(limbs, synth._hdr(np.array(es) + 1, np.zeros(len(es))), p)
+
+    for E, fits in ((8000, True), (40000, False), (100, True)):
+        xh = powers([E, -E])
+        d = M.mp_dot(M.MPArray.from_host(xh), M.MPArray.from_host(xh)).to_numpy()
+        flags = M.mp_status(raise_on_error=False)
+        if fits:
+            xo = codec.decode(xh.limbs, xh.hdr, p)
+            assert flags == 0
+            assert_bitwise(d[0], d[1], [blas.dot(xo, xo, p)], p, what="dot span %d" % E)
+        else:
+            assert flags & 2, flags          # MP_ST_WINDOW
+            assert d[1][0] == np.int32(-(1 << 31))  # +0
