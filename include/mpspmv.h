@@ -42,8 +42,13 @@
  *
  * EXACT WINDOW LIMITS.  An EXACT row sum is supported when its non-zero products' exponents
  * e_a + e_x span at most 32 * (16 R - 2L - 2) bits, R = 2L + 10 digits (L = p/32): about 8,900,
- * 12,700 and 20,400 bits at p = 128, 256, 512.  Exact inner products (mp_dot, solvers) support
- * spans of 32 * (257 R - 2L - 2) bits.  Wider sums set MP_ST_WINDOW and give +0.
+ * 12,700 and 20,400 bits at p = 128, 256, 512.  An exact inner product (mp_dot, the solvers'
+ * scalars) is supported when its products' exponents x_e + y_e span at most 32 * (W - 2L - 2)
+ * bits, W = min(2048, 257 (2L + 1) / 2) digits for mp_dot and the solvers' vector steps
+ * (about 36,700, 65,000 and 64,400 bits at p = 128, 256, 512), W = 65 (2L + 1) / 2 digits for
+ * the products a solver forms inside its SpMV launches (about 9,000, 17,100 and 33,200 bits),
+ * and W = 256 digits in gpbicg_batched (about 7,900, 7,600 and 7,100 bits).  Wider sums set
+ * MP_ST_WINDOW and give +0.
  */
 #ifndef MPSPMV_H
 #define MPSPMV_H
