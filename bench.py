@@ -135,10 +135,18 @@ def time_kernel(torch, fn, reps):
     return e0.elapsed_time(e1) / (3 * reps) * 1e-3   # seconds per launch
 
 
-def spmv_kernel_name(plan, op, mode, L):
+def spmv_symbol(plan, op, mode, L, fused=False):
+    """The kernel symbol (as rocprofv3 names it, without "void mp::" and the arguments) of the
+    plan's variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation,
+    which ends with the inner products of its output."""
     rows, staged, srt = plan.variants()[(op, mode)]
-    return "%s<%d, %d>%s%s" % ("spmv_exact_kernel" if mode else "spmv_seq_kernel", L, rows,
-                               " (x staged)" if staged else "", " (rows by length)" if srt else "")
+    base = "spmv_exact_kernel" if mode else ("spmv_seq_sorted_kernel" if srt else "spmv_seq_kernel")
+    return "%s<%d, %d, %s>" % (base, L, rows, "true" if fused else "false")
+
+
+def spmv_kernel_name(plan, op, mode, L, fused=False):
+    rows, staged, srt = plan.variants()[(op, mode)]
+    return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "")
 
 
 def load_traffic(kernel):
@@ -149,7 +157,7 @@ def load_traffic(kernel):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    ent = d.get(kernel)
+    ent = d.get(kernel.split(" (")[0])
     if not ent or ent.get("kernel_source") != kernel_source_hash():
         return None
     return ent["fetch_bytes"] + ent["write_bytes"]
@@ -291,6 +299,7 @@ def profile_pass(M, torch, which):
     names = {}
     for mode in (M.MP_SEQ, M.MP_EXACT):
         names[mode] = spmv_kernel_name(plan, 0, mode, PREC // 32)
+        names["fused_%d" % mode] = spmv_kernel_name(plan, 0, mode, PREC // 32, fused=True)
         for _ in range(10):
             M.mpspmv_csr(A, x, y, mode=mode, plan=plan)
     if which != "powerlaw":   # the step's solver kernels in their step proportions (20 iterations)
@@ -375,15 +384,15 @@ def main():
             pr = M.SolveProfile()
             solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0), profile=pr)
             prof[(sname, mode)] = pr
-    # per kernel symbol: the inner-product kernel (one symbol for every launch) and the sparse
-    # product of each mode (one symbol per mode: the tuned variant)
-    cand = {"dot_kernel<%d>" % L: [0.0, 0, 0.0]}
+    # per kernel symbol: the sparse products that form the step's inner products (one symbol per
+    # mode, the tuned variant of A x in its solver instantiation) and BiCG's A^T products
+    cand = {}
     for (sname, mode), pr in prof.items():
-        d = cand["dot_kernel<%d>" % L]
-        d[0] += pr.us[0]; d[1] += pr.launches[0]; d[2] += pr.bytes[0]
-        k = spmv_kernel_name(plan, 0, mode, L)
-        e = cand.setdefault(k, [0.0, 0, 0.0])
-        e[0] += pr.us[1]; e[1] += pr.launches[1]; e[2] += pr.bytes[1]
+        for cls, op, fused in ((0, 0, True), (1, 1, False)):
+            if pr.launches[cls] == 0:
+                continue
+            e = cand.setdefault(spmv_kernel_name(plan, op, mode, L, fused=fused), [0.0, 0, 0.0])
+            e[0] += pr.us[cls]; e[1] += pr.launches[cls]; e[2] += pr.bytes[cls]
     comp["solver_kernels"] = {k: {"total_us": round(v[0], 1), "launches": v[1],
                                   "avg_us": round(v[0] / max(1, v[1]), 2)} for k, v in cand.items()}
     comp["solver_vector_updates"] = {"total_us": round(sum(pr.us[2] for pr in prof.values()), 1),

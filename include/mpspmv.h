@@ -118,7 +118,9 @@ typedef struct {
  * eagerly (as for chunk <= 0; the results do not change) and every iteration kernel is
  * bracketed by HIP events on the solver's stream; the durations, launch counts and algorithmic
  * bytes (the vectors and matrix entries the kernel must read and write once) are added to the
- * struct per kernel class: [0] inner products, [1] sparse products, [2] vector updates. */
+ * struct per kernel class: [0] sparse products that also form the step's inner products of
+ * their output, [1] other sparse products, [2] vector steps (directions and updates, with the
+ * inner products they form). */
 typedef struct mp_solve_profile {
   int64_t launches[3];
   double us[3];

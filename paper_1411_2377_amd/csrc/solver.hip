@@ -274,7 +274,8 @@ int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
 }
 
 // Profiling: class of a launch and its algorithmic bytes.
-enum ProfClass { PROF_DOT = 0, PROF_SPMV = 1, PROF_VEC = 2 };
+// [0] sparse products that also form inner products, [1] other sparse products, [2] vector steps
+enum ProfClass { PROF_SPMV_DOT = 0, PROF_SPMV = 1, PROF_VEC = 2 };
 
 int prof_init(Work& W, mp_solve_profile* prof) {
   if (!prof) return MPS_OK;
@@ -616,7 +617,7 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
     if ((rr = timed(W, PROF_VEC, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
       return rr;
     const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{PT, 0, mp::S_SIGMA}});
-    if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
       return rr;
     if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, opT, o->mode, PT, ZT, st, true); })))
       return rr;
@@ -659,7 +660,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
   // q = A p with (rt, q)
   const SpmvFuse den = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_DEN}});
-  if ((rr = timed(W, PROF_SPMV, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
+  if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
   // alpha = rho / (rt, q); t, s, y with (y, y) and (y, t)
   a = ew_args(W, st);
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
@@ -668,7 +669,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   // v = A t with (v, t), (v, y), (v, v)
   const SpmvFuse mus =
       fuse_of(W, mp::EPI_NONE, {{T, 4, mp::S_MU2}, {Y, 6, mp::S_MU4}, {self, 7, mp::S_MU5}});
-  if ((rr = timed(W, PROF_SPMV, sp_bytes + 2 * dot1, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
+  if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + 2 * dot1, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
   // zeta, eta from mu1..mu5; u, z, x, r with (r, r) and (rt, r) (their last block: stopping
   // test, beta)
   mp::GpUpdArgs g{};
@@ -679,7 +680,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   g.y = Y;
   g.v = V;
   g.rt = RT;
-  return timed(W, PROF_VEC, vec_bytes(W, 16), [&] { return launch_gp_update(L, g, W.ws); });
+  return timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); });
 }
 
 int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,

@@ -328,13 +328,21 @@ __device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb
 // alpha; or zeta, eta, tau.  Returns, in every lane, the status bits of the operations the
 // formulas use in bits 0..7, a breakdown (its solver outcome + 1, or 0) in bits 8..15, and bit
 // 16 when tau was formed.
+// Inputs in i_limb / i_hdr (k-th at i_limb[k * L ...], i_hdr[k]): sigma or den, rho; or mu1..mu5.
 template <int L>
-__device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_limb, int32_t* s_hdr,
-                                                      int64_t s_ld, int iters, uint32_t* o_limb,
-                                                      int32_t* o_hdr) {
+__device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* i_limb, int32_t* i_hdr,
+                                                      int iters, uint32_t* o_limb, int32_t* o_hdr) {
   const int lane = threadIdx.x & 63;
-  const Scalars S{s_limb, s_hdr, s_ld};
   uint32_t st = 0, brk = 0, tau_ok = 0;
+  auto in = [&](int k) {
+    Num<L> r;
+    const int32_t h = i_hdr[k];
+    r.e = h >> 1;
+    r.s = (uint32_t)h & 1u;
+#pragma unroll
+    for (int i = 0; i < L; ++i) r.m[i] = i_limb[k * L + i];
+    return r;
+  };
   auto put = [&](int k, const Num<L>& v) {
     o_hdr[k] = make_hdr(v.e, v.s);
 #pragma unroll
@@ -346,8 +354,7 @@ __device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_lim
   switch (kind) {
     case PRO_BICG_ALPHA:
     case PRO_GP_ALPHA: {
-      const Num<L> den = sload<L>(S, kind == PRO_BICG_ALPHA ? S_SIGMA : S_DEN);
-      const Num<L> rho = sload<L>(S, S_RHO);
+      const Num<L> den = in(0), rho = in(1);
       if (is_zero(den)) {
         brk = kBreakSigma + 1;
       } else if (lane == 0) {
@@ -358,8 +365,7 @@ __device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* s_lim
       break;
     }
     case PRO_GP_ZETA: {
-      const Num<L> mu1 = sload<L>(S, S_MU1), mu2 = sload<L>(S, S_MU2), mu3 = sload<L>(S, S_MU3);
-      const Num<L> mu4 = sload<L>(S, S_MU4), mu5 = sload<L>(S, S_MU5);
+      const Num<L> mu1 = in(0), mu2 = in(1), mu3 = in(2), mu4 = in(3), mu5 = in(4);
       if (iters == 0) {  // first iteration: zeta = mu2 / mu5, eta = 0
         if (is_zero(mu5)) {
           brk = kBreakTau + 1;
@@ -433,6 +439,8 @@ struct ProOut {
   const uint32_t* limb;
   const int32_t* hdr;
   int brk;
+  int nclr;     // inner-product slots the prologue read (its launch's last block clears them)
+  int clr[3];
 };
 
 // ------------------------------------------------------------------------------------------
@@ -653,6 +661,96 @@ MPD Num<L> ring_round_narrow(const DotWork& dw, int64_t slot, int32_t lo, int32_
   return wave_round<L>(dg, base - 64 * L, st);
 }
 
+// Digit w of the window starting at ring position s0, summed over the replicas (read only:
+// every load is issued before any result is used).
+MPD int64_t ring_sum(const DotWork& dw, const int64_t* ring, int s0, int w) {
+  const int64_t at = (s0 + w) & ((1 << dw.ring_log2) - 1);
+  int64_t got[kMaxReps];
+#pragma unroll
+  for (int c = 0; c < kMaxReps; ++c)
+    got[c] = (c < dw.reps) ? ld_dev(ring + ((int64_t)c << dw.ring_log2) + at) : 0;
+  int64_t v = 0;
+#pragma unroll
+  for (int c = 0; c < kMaxReps; ++c) v += got[c];
+  return v;
+}
+
+// RN_p of the inner products of N slots, read from their rings and bins without clearing them
+// (the kernel that formed them has ended), by one whole wavefront: every lane gets out[k].  The
+// bins of all slots are read at once, then the windows' digits; windows of more than 63 digits
+// are summed into `lds` (capacity `cap`) and rounded by lane 0.  A window wider than the ring or
+// `cap` sets kStWindow and gives +0.
+template <int L, int N>
+MPD void ring_peek(const DotWork& dw, int64_t slot0, const int (&rs)[N], Num<L> (&out)[N],
+                   int64_t* lds, int cap, uint32_t& st) {
+  const int lane = threadIdx.x & 63;
+  const int R = 1 << dw.ring_log2, mask = R - 1;
+  int32_t lo[N], hi[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int32_t* b = dw.anchor + 2 * ((slot0 + rs[k]) * kAnchorBins + lane);
+    lo[k] = ld_dev(b);
+    hi[k] = ld_dev(b + 1);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    lo[k] = wave_min(lo[k]);
+    hi[k] = wave_max(hi[k]);
+  }
+  int64_t dg[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int W = hi[k] >= lo[k] ? ring_window<L>(lo[k], hi[k]) : 0;
+    const int s0 = (int)((((int64_t)(lo[k] & ~31)) >> 5) & mask);
+    dg[k] = (W <= 63 && lane < W) ? ring_sum(dw, slot_ring(dw, slot0 + rs[k]), s0, lane) : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    set_zero(out[k], 0);
+    if (hi[k] < lo[k]) continue;
+    const int64_t base = (int64_t)(lo[k] & ~31);
+    const int W = ring_window<L>(lo[k], hi[k]);
+    if (W > R || W > cap) {
+      st |= kStWindow;
+    } else if (W <= 63) {
+      out[k] = wave_round<L>(dg[k], base - 64 * L, st);
+    } else {
+      const int s0 = (int)((base >> 5) & mask);
+      for (int w = lane; w < W; w += 64) lds[w] = ring_sum(dw, slot_ring(dw, slot0 + rs[k]), s0, w);
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // this wavefront's LDS writes are done
+      uint32_t st1 = 0;
+      Num<L> r;
+      set_zero(r, 0);
+      if (lane == 0) r = window_finalize<L>(lds, 1, W, base - 64 * L, st1);
+      out[k] = shfl_num<L>(r, 0);
+      st |= __shfl(st1, 0);
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+    }
+  }
+}
+
+// Clear slot `slot` (its window's digits in every replica, or the whole ring when the window
+// is wider than the ring or `cap`) and reset its bins, by one whole wavefront.
+template <int L>
+MPD void ring_clear(const DotWork& dw, int64_t slot, int cap) {
+  const int lane = threadIdx.x & 63;
+  int32_t lo, hi;
+  ring_range(dw, slot, lo, hi);
+  if (hi < lo) return;
+  const int R = 1 << dw.ring_log2, mask = R - 1;
+  int64_t* const ring = slot_ring(dw, slot);
+  const int W = ring_window<L>(lo, hi);
+  if (W > R || W > cap) {
+    for (int64_t k = lane; k < ((int64_t)dw.reps << dw.ring_log2); k += 64) st_dev(ring + k, (int64_t)0);
+    return;
+  }
+  const int s0 = (int)((((int64_t)(lo & ~31)) >> 5) & mask);
+  for (int k = lane; k < W * dw.reps; k += 64) {
+    const int c = k / W, w = k - c * W;
+    st_dev(ring + ((int64_t)c << dw.ring_log2) + ((s0 + w) & mask), (int64_t)0);
+  }
+}
+
 // RN_p of a slot with a wider window (W > 63), by the whole block; thread 0 gets the result.
 // The digits are summed into `lds` (capacity `cap` digits) and rounded there by thread 0.  A
 // window wider than the ring or than `cap` sets kStWindow and gives +0 (the whole ring is
@@ -803,6 +901,11 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
         if (t == 0) keep(dd, res);
       }
     }
+  }
+  if (pro) {  // the rings the step's prologue read
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (k < pro->nclr && wv == k % NW) ring_clear<L>(dw, slot0 + pro->clr[k], cap);
   }
   if (ctl && st) atomicOr(&ctl->flags, st);
   if (brk && t == 0) {
@@ -963,28 +1066,70 @@ MPD EwCtx ew_ctx(const VecArgs& A) {
 // block formed the same bits); the step's last block takes them from `pro`.
 template <int L>
 struct ProLds {
-  uint32_t limb[3 * L];
+  uint32_t limb[3 * L];  // results
   int32_t hdr[3];
+  uint32_t in_limb[5 * L];  // inputs
+  int32_t in_hdr[5];
   uint32_t word;
 };
 
+// The inputs of a prologue: inner products still in their rings (ring slot, input position)
+// and scalars (slot, input position).
 template <int L>
-MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, int nres, const int (&slots)[3],
-                        uint32_t& st) {
+MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, const DotWork& dw, int64_t* lds,
+                        int cap, int nres, const int (&slots)[3], uint32_t& st) {
+  const int lane = threadIdx.x & 63;
+  uint32_t st0 = 0;
+  ProOut o;
+  o.nclr = 0;
+  // the rings were filled by SpMV blocks (64 threads), whose passes hold at most this window
+  const int pcap = min(cap, lds_window_digits<L, 64>());
   if (threadIdx.x < 64) {  // one wavefront
-    const uint32_t w = prologue<L>(kind, c.S.limb, c.S.hdr, c.S.ld, c.ctl->iters, P.limb, P.hdr);
-    if (threadIdx.x == 0) P.word = w;
+    auto keep_in = [&](int k, const Num<L>& v) {
+      if (lane == 0) {
+        P.in_hdr[k] = make_hdr(v.e, v.s);
+#pragma unroll
+        for (int i = 0; i < L; ++i) P.in_limb[k * L + i] = v.m[i];
+      }
+    };
+    if (kind == PRO_GP_ZETA) {  // mu1, mu3 from the t/s/y step; mu2, mu4, mu5 in rings 4, 6, 7
+      Num<L> mu[3];
+      ring_peek<L, 3>(dw, c.abase, {4, 6, 7}, mu, lds, pcap, st0);
+      keep_in(0, sload<L>(c.S, S_MU1));
+      keep_in(1, mu[0]);
+      keep_in(2, sload<L>(c.S, S_MU3));
+      keep_in(3, mu[1]);
+      keep_in(4, mu[2]);
+    } else {  // sigma or den in ring 0, rho
+      Num<L> d[1];
+      ring_peek<L, 1>(dw, c.abase, {0}, d, lds, pcap, st0);
+      keep_in(0, d[0]);
+      keep_in(1, sload<L>(c.S, S_RHO));
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // the inputs are in LDS for the whole wavefront
+    const uint32_t w = prologue<L>(kind, P.in_limb, P.in_hdr, c.ctl->iters, P.limb, P.hdr);
+    if (threadIdx.x == 0) P.word = w | (st0 & 0xFFu);
   }
   __syncthreads();
   const uint32_t w = P.word;
   if (threadIdx.x == 0) st |= w & 0xFFu;
-  ProOut o;
   o.brk = (int)((w >> 8) & 0xFFu);
   o.n = (kind == PRO_GP_ZETA) ? (((w >> 16) & 1u) ? 3 : 2) : nres;
 #pragma unroll
   for (int k = 0; k < 3; ++k) o.slot[k] = slots[k];
   o.limb = P.limb;
   o.hdr = P.hdr;
+  if (kind == PRO_GP_ZETA) {
+    o.nclr = 3;
+    o.clr[0] = 4;
+    o.clr[1] = 6;
+    o.clr[2] = 7;
+  } else {
+    o.nclr = 1;
+    o.clr[0] = 0;
+    o.clr[1] = 0;
+    o.clr[2] = 0;
+  }
   if (!o.brk && c.idx == 0 && threadIdx.x == 0) {
     for (int k = 0; k < o.n; ++k) sstore<L>(c.S, slots[k], lds_num<L>(P.limb, P.hdr, k));
   }
@@ -1078,7 +1223,8 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   // alpha = rho / sigma, sigma = (pt, A p) from the product before
-  const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, 1, {S_ALPHA, 0, 0}, st);
+  const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
+                                     {S_ALPHA, 0, 0}, st);
   const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
@@ -1136,7 +1282,8 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   uint32_t st = 0;
   const bool first = c.ctl->iters == 0;
   // alpha = rho / den, den = (rt, A p) from the product before
-  const ProOut pro = run_prologue<L>(pl, PRO_GP_ALPHA, c, 1, {S_ALPHA, 0, 0}, st);
+  const ProOut pro = run_prologue<L>(pl, PRO_GP_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
+                                     {S_ALPHA, 0, 0}, st);
   const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
@@ -1187,7 +1334,8 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   if (solve_done(c.ctl)) return;
   uint32_t st = 0;
   // zeta, eta (and tau) from mu1..mu5 of the two launches before
-  const ProOut pro = run_prologue<L>(pl, PRO_GP_ZETA, c, 3, {S_ZETA, S_ETA, S_TAU}, st);
+  const ProOut pro = run_prologue<L>(pl, PRO_GP_ZETA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 3,
+                                     {S_ZETA, S_ETA, S_TAU}, st);
   const Num<L> alpha = sload<L>(c.S, S_ALPHA), beta = sload<L>(c.S, S_BETA);
   const Num<L> zeta = lds_num<L>(pl.limb, pl.hdr, 0), eta = lds_num<L>(pl.limb, pl.hdr, 1);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {

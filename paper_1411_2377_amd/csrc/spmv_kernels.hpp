@@ -113,10 +113,11 @@ MPD bool spmv_block(const SpmvArgs& A, SpmvBlock& B) {
   return true;
 }
 
-// The inner products of the rows' results with the requested vectors, one pass each, then the
-// ticket (and in the last block the rounding and the driver epilogue).  The lane of each row
-// holds its result y; lanes without a row take part with no product.
-template <int L, int NT, int RPW>
+// The inner products of the rows' results with the requested vectors, one pass each, added to
+// their rings; the launch that uses them reads and rounds them (the kernel boundary orders
+// every block's additions before it), so no block here waits for its additions or counts.  The
+// lane of each row holds its result y; lanes without a row take part with no product.
+template <int L, int NT>
 MPD void spmv_fused_dots(const SpmvArgs& A, const SpmvBlock& B, bool has_row, int64_t yi,
                          const Num<L>& y, uint32_t st) {
   __shared__ PassLds<L, NT> lds;
@@ -137,16 +138,7 @@ MPD void spmv_fused_dots(const SpmvArgs& A, const SpmvBlock& B, bool has_row, in
       pass_dot<L, NT>(lds, has_row, hy, hw, y.m, wm, A.dots, slot0 + A.fd.slot[k]);
     }
   }
-  // blocks of this solve: all of them (one solve), or the row blocks of its tiles for its
-  // right-hand side (this block's number: its row block less the solve's first one)
-  const bool batched = A.pair_of_tile != nullptr;
-  const unsigned nblocks =
-      batched ? (unsigned)A.tiles_of_pair[B.pair] * (unsigned)(kTile / RPW) : gridDim.x;
-  const unsigned idx =
-      batched ? (unsigned)(B.rb - ((int64_t)A.first_tile[B.pair] * kTile - B.rhs * A.y_rstride) / RPW)
-              : blockIdx.x;
-  dots_finish<L, NT, false>(A.dots, A.fd, B.pair, batched, idx, nblocks, A.ctl ? A.ctl + B.pair : nullptr,
-                     A.S.at(B.pair), A.ndone, A.status, st, lds.win, lds_window_digits<L, NT>());
+  if (st) atomicOr(A.status, st);
 }
 
 // x_j's header and limbs, from the staged records when there are any
@@ -304,7 +296,7 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
   }
   if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
   if constexpr (FUSE) {
-    spmv_fused_dots<L, 64, RPW>(A, B, has_row, yo + row, acc, st);
+    spmv_fused_dots<L, 64>(A, B, has_row, yo + row, acc, st);
   } else if (st) {
     atomicOr(A.status, st);
   }
@@ -416,7 +408,7 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   }
   if (has_row) store<L>(acc, A.y_limb, A.y_hdr, A.y_ld, yo + row);
   if constexpr (FUSE) {
-    spmv_fused_dots<L, 256, RPW>(A, B, has_row, yo + row, acc, st);
+    spmv_fused_dots<L, 256>(A, B, has_row, yo + row, acc, st);
   } else if (st) {
     atomicOr(A.status, st);
   }
@@ -471,7 +463,7 @@ MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, 
 }
 
 template <int L, int RPW, bool FUSE>
-__global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
+__global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
   constexpr int R = window_fast_digits<L>();  // ring digits per row
   // digits of the block-shared exact window: the same for every variant, so that every variant
   // accepts the same rows
@@ -639,7 +631,7 @@ __global__ void __launch_bounds__(64) spmv_exact_kernel(SpmvArgs A) {
     }
   }
   if constexpr (FUSE) {
-    spmv_fused_dots<L, 64, RPW>(A, B, has_row, yo + row, y, st);
+    spmv_fused_dots<L, 64>(A, B, has_row, yo + row, y, st);
   } else if (st) {
     atomicOr(A.status, st);
   }
