@@ -306,6 +306,18 @@ def profile_pass(M, torch, which):
         for solver in (M.bicg, M.gpbicg):
             for mode in (M.MP_SEQ, M.MP_EXACT):
                 solver(A, b, plan=plan, mode=mode, maxit=20, rtol=(1, -70), atol=(0, 0), chunk=0)
+        # then a few iterations with every variant of the solvers' SpMV instantiations, so that
+        # each of their symbols has counters whichever variant a tuning run picks
+        tuned = plan.variants()
+        for mode in (M.MP_SEQ, M.MP_EXACT):
+            for rows in (16, 32, 64):
+                for srt in ((False, True) if mode == M.MP_SEQ else (False,)):
+                    plan.set_variant(0, mode, rows=rows, stage_x=False, sorted_rows=srt)
+                    for solver in (M.bicg, M.gpbicg):
+                        solver(A, b, plan=plan, mode=mode, maxit=5, rtol=(1, -70), atol=(0, 0),
+                               chunk=0)
+            r, st, so = tuned[(0, mode)]
+            plan.set_variant(0, mode, rows=r, stage_x=st, sorted_rows=so)
     torch.cuda.synchronize()
     print(json.dumps({"profile_pass": which, "variants": names, "kernel_source": kernel_source_hash(),
                       "copy_bytes": src.numel() * 4, "n_rows": A.n_rows, "n_cols": A.n_cols,
