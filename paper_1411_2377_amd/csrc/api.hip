@@ -182,6 +182,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.done_stride = batch->done_stride;
   a.x_rec = x_rec;
   a.rows = var->rows;
+  a.pipe = var->pipe ? 1 : 0;
   if (var->rows && batch->nrhs != 1) return fail(MPS_EINVAL, "a row order takes one right-hand side");
   a.fd = mp::DotOut{};
   a.dots = mp::DotWork{};

@@ -71,12 +71,14 @@ int check_vec(const mp_vec* v, int64_t want_len, const char* name);
 bool vec_overlap(const mp_vec* a, const mp_vec* b, int L);
 int check_csr(const mp_csr* A, int check_device_data);
 // Kernel variant of one product: rows per block (0: by shape), staged x (x_rec: a buffer of
-// x_len records, the launch first stages x into it), rows in a given order (nullptr: in order).
+// x_len records, the launch first stages x into it), rows in a given order (nullptr: in order),
+// and for SEQ the pipelined kernel (always with a row order).
 struct SpmvVariant {
   int rpw = 0;
   uint32_t* x_rec = nullptr;
   int64_t x_len = 0;
   const int32_t* rows = nullptr;
+  bool pipe = false;  // SEQ: the four-wavefront pipelined kernel also without a row order
 };
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,

@@ -661,8 +661,21 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   // q = A p with (rt, q)
   const SpmvFuse den = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_DEN}});
   if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
+  // a batch forms each solve's step prologue once, in a launch of its own
+  auto prologue = [&](int kind) {
+    mp::ProArgs pa{};
+    pa.kind = kind;
+    pa.S = W.S;
+    pa.ctl = W.ctl;
+    pa.dots = W.dots();
+    pa.ndone = W.ndone;
+    pa.status = st;
+    return launch_prologue(L, pa, W.npairs, W.ws);
+  };
+  if (W.batched() && (rr = prologue(mp::PRO_GP_ALPHA))) return rr;
   // alpha = rho / (rt, q); t, s, y with (y, y) and (y, t)
   a = ew_args(W, st);
+  a.pro_sep = W.batched() ? 1 : 0;
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
   set_fd(W, a, mp::EPI_NONE, {{3, mp::S_MU1}, {5, mp::S_MU3}});
   if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
@@ -672,15 +685,25 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + 2 * dot1, [&] { return apply(W, op, mode, T, V, st, true, &mus); }))) return rr;
   // zeta, eta from mu1..mu5; u, z, x, r with (r, r) and (rt, r) (their last block: stopping
   // test, beta)
+  if (W.batched() && (rr = prologue(mp::PRO_GP_ZETA))) return rr;
   mp::GpUpdArgs g{};
   g.a = ew_args(W, st);
+  g.a.pro_sep = W.batched() ? 1 : 0;
   g.a.v[0] = U; g.a.v[1] = Z; g.a.v[2] = X; g.a.v[3] = R; g.a.v[4] = Q; g.a.v[5] = S;
   g.a.v[6] = P; g.a.v[7] = T;
   set_fd(W, g.a, mp::EPI_GP_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
   g.y = Y;
   g.v = V;
   g.rt = RT;
-  return timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); });
+  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); }))) return rr;
+  if (!W.batched()) return MPS_OK;
+  mp::EpiArgs ea{};  // a batch runs the stopping test and beta in a launch of its own
+  ea.epi = mp::EPI_GP_CONV;
+  ea.S = W.S;
+  ea.ctl = W.ctl;
+  ea.ndone = W.ndone;
+  ea.status = st;
+  return launch_epilogue(L, ea, W.npairs, W.ws);
 }
 
 int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
@@ -890,6 +913,10 @@ int gpbicg_batched_impl(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp
   BlockDiag M;
   if ((r = build_block_diag(nsys, A, L, row_off, M, W.ws))) return r;
   Op op{M.rows, M.row_ptr, M.col_idx, mp_vec{M.limb, M.hdr, M.nnz, M.nnz}, {}};
+  // SEQ: 64 rows per block in the pipelined kernel (one wavefront's chains advance while three
+  // form the next products), rows in order; EXACT: rows per block by shape
+  op.var[MP_SEQ].rpw = 64;
+  op.var[MP_SEQ].pipe = true;
   uint32_t* st = ctx->status;
   const mp::VecRef X = W.vec(kGpVectors), B = W.vec(kGpVectors + 1);
   if ((r = batch_copy(L, true, d_seg, W.pair_of_tile, B, n, W.ws))) return r;

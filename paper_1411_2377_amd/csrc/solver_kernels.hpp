@@ -1035,6 +1035,7 @@ struct VecArgs {
   // inner products the kernel forms from the vectors it writes (kernels that have them)
   DotWork dots;
   DotOut fd;
+  int pro_sep;  // the step's prologue and epilogue run in launches of their own (batches)
 };
 
 // The solve a block works for: its control block, scalars, first inner-product slot and the
@@ -1073,42 +1074,83 @@ struct ProLds {
   uint32_t word;
 };
 
-// The inputs of a prologue: inner products still in their rings (ring slot, input position)
-// and scalars (slot, input position).
+// A prologue by one wavefront: the inputs (inner products still in their rings, read with the
+// SpMV's window limit, and scalar slots) into P.in_*, the results into P.limb / P.hdr; returns
+// the prologue's word (status bits, breakdown, tau flag) in every lane.
 template <int L>
-MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, const DotWork& dw, int64_t* lds,
-                        int cap, int nres, const int (&slots)[3], uint32_t& st) {
+MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, int64_t abase,
+                           const DotWork& dw, int64_t* lds, int cap) {
   const int lane = threadIdx.x & 63;
   uint32_t st0 = 0;
-  ProOut o;
-  o.nclr = 0;
   // the rings were filled by SpMV blocks (64 threads), whose passes hold at most this window
   const int pcap = min(cap, lds_window_digits<L, 64>());
-  if (threadIdx.x < 64) {  // one wavefront
-    auto keep_in = [&](int k, const Num<L>& v) {
-      if (lane == 0) {
-        P.in_hdr[k] = make_hdr(v.e, v.s);
+  auto keep_in = [&](int k, const Num<L>& v) {
+    if (lane == 0) {
+      P.in_hdr[k] = make_hdr(v.e, v.s);
 #pragma unroll
-        for (int i = 0; i < L; ++i) P.in_limb[k * L + i] = v.m[i];
-      }
-    };
-    if (kind == PRO_GP_ZETA) {  // mu1, mu3 from the t/s/y step; mu2, mu4, mu5 in rings 4, 6, 7
-      Num<L> mu[3];
-      ring_peek<L, 3>(dw, c.abase, {4, 6, 7}, mu, lds, pcap, st0);
-      keep_in(0, sload<L>(c.S, S_MU1));
-      keep_in(1, mu[0]);
-      keep_in(2, sload<L>(c.S, S_MU3));
-      keep_in(3, mu[1]);
-      keep_in(4, mu[2]);
-    } else {  // sigma or den in ring 0, rho
-      Num<L> d[1];
-      ring_peek<L, 1>(dw, c.abase, {0}, d, lds, pcap, st0);
-      keep_in(0, d[0]);
-      keep_in(1, sload<L>(c.S, S_RHO));
+      for (int i = 0; i < L; ++i) P.in_limb[k * L + i] = v.m[i];
     }
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // the inputs are in LDS for the whole wavefront
-    const uint32_t w = prologue<L>(kind, P.in_limb, P.in_hdr, c.ctl->iters, P.limb, P.hdr);
-    if (threadIdx.x == 0) P.word = w | (st0 & 0xFFu);
+  };
+  if (kind == PRO_GP_ZETA) {  // mu1, mu3 from the t/s/y step; mu2, mu4, mu5 in rings 4, 6, 7
+    Num<L> mu[3];
+    ring_peek<L, 3>(dw, abase, {4, 6, 7}, mu, lds, pcap, st0);
+    keep_in(0, sload<L>(S, S_MU1));
+    keep_in(1, mu[0]);
+    keep_in(2, sload<L>(S, S_MU3));
+    keep_in(3, mu[1]);
+    keep_in(4, mu[2]);
+  } else {  // sigma or den in ring 0, rho
+    Num<L> d[1];
+    ring_peek<L, 1>(dw, abase, {0}, d, lds, pcap, st0);
+    keep_in(0, d[0]);
+    keep_in(1, sload<L>(S, S_RHO));
+  }
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // the inputs are in LDS for the whole wavefront
+  const uint32_t w = prologue<L>(kind, P.in_limb, P.in_hdr, iters, P.limb, P.hdr);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // and the results
+  return w | (st0 & 0xFFu);
+}
+
+// The rings a prologue kind reads.
+MPD int prologue_rings(int kind, int (&clr)[3]) {
+  if (kind == PRO_GP_ZETA) {
+    clr[0] = 4;
+    clr[1] = 6;
+    clr[2] = 7;
+    return 3;
+  }
+  clr[0] = clr[1] = clr[2] = 0;
+  return 1;
+}
+
+// The step prologue of an element-wise step.  sep: it ran in its own launch (prologue_kernel,
+// for batches: one wavefront per solve instead of one per block), which kept the results in the
+// scalar slots, finished a solve that broke down and cleared the rings.
+template <int L>
+MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, const DotWork& dw, int64_t* lds,
+                        int cap, int nres, const int (&slots)[3], uint32_t& st, bool sep = false) {
+  ProOut o;
+  o.nclr = 0;
+  if (sep) {
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < 3; ++k) {
+        const Num<L> v = sload<L>(c.S, slots[k]);
+        P.hdr[k] = make_hdr(v.e, v.s);
+        for (int i = 0; i < L; ++i) P.limb[k * L + i] = v.m[i];
+      }
+    }
+    __syncthreads();
+    o.brk = 0;
+    o.n = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.slot[k] = slots[k];
+    o.limb = P.limb;
+    o.hdr = P.hdr;
+    return o;
+  }
+  if (threadIdx.x < 64) {  // one wavefront
+    const uint32_t w = prologue_wave<L>(P, kind, c.S, c.ctl->iters, c.abase, dw, lds, cap);
+    if (threadIdx.x == 0) P.word = w;
   }
   __syncthreads();
   const uint32_t w = P.word;
@@ -1119,21 +1161,92 @@ MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, const DotWork& d
   for (int k = 0; k < 3; ++k) o.slot[k] = slots[k];
   o.limb = P.limb;
   o.hdr = P.hdr;
-  if (kind == PRO_GP_ZETA) {
-    o.nclr = 3;
-    o.clr[0] = 4;
-    o.clr[1] = 6;
-    o.clr[2] = 7;
-  } else {
-    o.nclr = 1;
-    o.clr[0] = 0;
-    o.clr[1] = 0;
-    o.clr[2] = 0;
-  }
+  o.nclr = prologue_rings(kind, o.clr);
   if (!o.brk && c.idx == 0 && threadIdx.x == 0) {
     for (int k = 0; k < o.n; ++k) sstore<L>(c.S, slots[k], lds_num<L>(P.limb, P.hdr, k));
   }
   return o;
+}
+
+// Step prologues of a batch in a launch of their own: one wavefront per solve forms the values,
+// keeps them in the solve's scalar slots (or finishes a solve that broke down) and clears the
+// rings it read.
+struct ProArgs {
+  int kind;
+  Scalars S;
+  Ctl* ctl;
+  DotWork dots;
+  int32_t* ndone;
+  uint32_t* status;
+};
+
+template <int L>
+__global__ void __launch_bounds__(64) prologue_kernel(ProArgs A) {
+  __shared__ ProLds<L> pl;
+  __shared__ int64_t lds[lds_window_digits<L, 64>()];
+  const int pair = blockIdx.x;
+  Ctl* const ctl = A.ctl + pair;
+  if (solve_done(ctl)) return;
+  const Scalars S = A.S.at(pair);
+  const int64_t abase = (int64_t)pair * kDotSlots;
+  const uint32_t w = prologue_wave<L>(pl, A.kind, S, ctl->iters, abase, A.dots, lds,
+                                      lds_window_digits<L, 64>());
+  const int brk = (int)((w >> 8) & 0xFFu);
+  const uint32_t st = w & 0xFFu;
+  if (threadIdx.x == 0) {
+    if (brk) {
+      finish(ctl, brk - 1);
+      if (A.ndone) atomicAdd(A.ndone, 1);
+    } else {
+      const int n = (A.kind == PRO_GP_ZETA) ? (((w >> 16) & 1u) ? 3 : 2) : 1;
+      const int slot0 = (A.kind == PRO_GP_ZETA) ? S_ZETA : S_ALPHA;
+      const int slots[3] = {slot0, S_ETA, S_TAU};
+      for (int k = 0; k < n; ++k) sstore<L>(S, slots[k], lds_num<L>(pl.limb, pl.hdr, k));
+    }
+    if (st) {
+      atomicOr(&ctl->flags, st);
+      atomicOr(A.status, st);
+    }
+  }
+  int clr[3];
+  const int nclr = prologue_rings(A.kind, clr);
+  for (int k = 0; k < nclr; ++k) ring_clear<L>(A.dots, abase + clr[k], lds_window_digits<L, 64>());
+}
+
+// Driver epilogues of a batch in a launch of their own (the batch's element-wise steps are
+// compiled without them): one wavefront per solve, after the step's inner products are rounded.
+struct EpiArgs {
+  int epi;
+  Scalars S;
+  Ctl* ctl;
+  int32_t* ndone;
+  uint32_t* status;
+};
+
+template <int L>
+__global__ void __launch_bounds__(64) epilogue_kernel(EpiArgs A) {
+  __shared__ uint32_t s_cl[kNumScalars * L];
+  __shared__ int32_t s_ch[kNumScalars];
+  const int pair = blockIdx.x, lane = threadIdx.x;
+  Ctl* const ctl = A.ctl + pair;
+  if (solve_done(ctl)) return;
+  const Scalars S = A.S.at(pair);
+  if (lane < kNumScalars) {
+    s_ch[lane] = S.hdr[lane];
+#pragma unroll
+    for (int k = 0; k < L; ++k) s_cl[lane * L + k] = S.limb[(int64_t)k * S.ld + lane];
+  }
+  const int iters = ctl->iters, maxit = ctl->maxit, hist_len = ctl->hist_len;
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // the copy is in LDS for the whole wavefront
+  const uint32_t st = epilogue<L>(A.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, iters, maxit,
+                                  hist_len, nullptr, nullptr, 0);
+  if (lane == 0) {
+    if (st) {
+      atomicOr(&ctl->flags, st);
+      atomicOr(A.status, st);
+    }
+    if (A.ndone && ctl->done) atomicAdd(A.ndone, 1);
+  }
 }
 
 // The scalar slot as a one-element vector reference.
@@ -1215,7 +1328,7 @@ __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
 // BiCG update: v = {x, r, rt, p, z, zt}: x += alpha p; r -= alpha z; rt -= alpha zt; then the
 // inner products (r, r) and (rt, r) (fd slots 0 and 1) from the values just formed.  The loop
 // is block-uniform: every pass ends with block-wide inner-product steps.
-template <int L>
+template <int L, bool SEP>
 __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   __shared__ PassLds<L, 256> lds;
   __shared__ ProLds<L> pl;
@@ -1224,7 +1337,7 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
   uint32_t st = 0;
   // alpha = rho / sigma, sigma = (pt, A p) from the product before
   const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
-                                     {S_ALPHA, 0, 0}, st);
+                                     {S_ALPHA, 0, 0}, st, SEP);
   const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
@@ -1243,7 +1356,7 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
     pass_dot<L, 256>(lds, ok, hr, hr, r.m, r.m, A.dots, c.abase + A.fd.slot[0]);
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+  dots_finish<L, 256, !SEP>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
                       A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
@@ -1273,7 +1386,7 @@ __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
 // GPBiCG t, s, y: v = {t, s, y, r, q, w}.  s = t - r (not in the first iteration),
 // t = r - alpha q, y = alpha q - r (first) or s - alpha (w - q); then the inner products
 // (y, y) and (y, t) (fd slots 0 and 1).
-template <int L>
+template <int L, bool SEP>
 __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   __shared__ PassLds<L, 256> lds;
   __shared__ ProLds<L> pl;
@@ -1283,7 +1396,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
   const bool first = c.ctl->iters == 0;
   // alpha = rho / den, den = (rt, A p) from the product before
   const ProOut pro = run_prologue<L>(pl, PRO_GP_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
-                                     {S_ALPHA, 0, 0}, st);
+                                     {S_ALPHA, 0, 0}, st, SEP);
   const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
     const int64_t i = i0 + threadIdx.x;
@@ -1313,7 +1426,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
     pass_dot<L, 256>(lds, ok, hy, hy, y.m, y.m, A.dots, c.abase + A.fd.slot[0]);
     pass_dot<L, 256>(lds, ok, hy, ht, y.m, tn.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+  dots_finish<L, 256, !SEP>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
                       A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
@@ -1325,7 +1438,7 @@ struct GpUpdArgs {
   VecRef y, v, rt;
 };
 
-template <int L>
+template <int L, bool SEP>
 __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   __shared__ PassLds<L, 256> lds;
   __shared__ ProLds<L> pl;
@@ -1335,7 +1448,7 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   uint32_t st = 0;
   // zeta, eta (and tau) from mu1..mu5 of the two launches before
   const ProOut pro = run_prologue<L>(pl, PRO_GP_ZETA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 3,
-                                     {S_ZETA, S_ETA, S_TAU}, st);
+                                     {S_ZETA, S_ETA, S_TAU}, st, SEP);
   const Num<L> alpha = sload<L>(c.S, S_ALPHA), beta = sload<L>(c.S, S_BETA);
   const Num<L> zeta = lds_num<L>(pl.limb, pl.hdr, 0), eta = lds_num<L>(pl.limb, pl.hdr, 1);
   for (int64_t i0 = (int64_t)blockIdx.x * 256; !pro.brk && i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
@@ -1366,7 +1479,7 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     pass_dot<L, 256>(lds, ok, hr, hr, rn.m, rn.m, A.dots, c.abase + A.fd.slot[0]);
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, rn.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  dots_finish<L, 256>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+  dots_finish<L, 256, !SEP>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
                       A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 

@@ -73,6 +73,7 @@ struct SpmvArgs {
   const uint32_t* x_rec;
   // rows in processing order (block b takes rows[b * RPW ...]), or nullptr: 0, 1, 2, ...
   const int32_t* rows;
+  int pipe;  // SEQ: the pipelined kernel even when rows == nullptr
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y

@@ -91,6 +91,24 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
     default: return fail(MPS_EINVAL, "bad limb count");                                       \
   }
 
+// the update steps: with their prologue and epilogue, or (batches) without
+#define MPS_EW_CASES_SEP(KERNEL, ARG, SEP)                                                    \
+  if (SEP) {                                                                                  \
+    switch (L) {                                                                              \
+      case 4: MPS_LAUNCH(true, true, (mp::KERNEL<4, true>), dim3(g), dim3(256), 0, s, ARG); break;   \
+      case 8: MPS_LAUNCH(true, true, (mp::KERNEL<8, true>), dim3(g), dim3(256), 0, s, ARG); break;   \
+      case 16: MPS_LAUNCH(true, true, (mp::KERNEL<16, true>), dim3(g), dim3(256), 0, s, ARG); break; \
+      default: return fail(MPS_EINVAL, "bad limb count");                                     \
+    }                                                                                         \
+  } else {                                                                                    \
+    switch (L) {                                                                              \
+      case 4: MPS_LAUNCH(true, true, (mp::KERNEL<4, false>), dim3(g), dim3(256), 0, s, ARG); break;  \
+      case 8: MPS_LAUNCH(true, true, (mp::KERNEL<8, false>), dim3(g), dim3(256), 0, s, ARG); break;  \
+      case 16: MPS_LAUNCH(true, true, (mp::KERNEL<16, false>), dim3(g), dim3(256), 0, s, ARG); break; \
+      default: return fail(MPS_EINVAL, "bad limb count");                                     \
+    }                                                                                         \
+  }
+
 int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
   if (a.n == 0) return MPS_OK;
   const unsigned g = ew_grid_of(a);
@@ -100,9 +118,9 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
     case EW_ZERO: MPS_EW_CASES(zero_kernel, a); break;
     case EW_SUB: MPS_EW_CASES(sub_kernel, a); break;
     case EW_BICG_DIR: MPS_EW_CASES(bicg_dir_kernel, a); break;
-    case EW_BICG_UPDATE: MPS_EW_CASES(bicg_update_kernel, a); break;
+    case EW_BICG_UPDATE: MPS_EW_CASES_SEP(bicg_update_kernel, a, a.pro_sep); break;
     case EW_GP_DIR: MPS_EW_CASES(gp_dir_kernel, a); break;
-    case EW_GP_TSY: MPS_EW_CASES(gp_tsy_kernel, a); break;
+    case EW_GP_TSY: MPS_EW_CASES_SEP(gp_tsy_kernel, a, a.pro_sep); break;
     default: return fail(MPS_EINVAL, "bad element-wise kernel");
   }
   hipError_t e = hipGetLastError();
@@ -112,9 +130,33 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
 int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s) {
   if (a.a.n == 0) return MPS_OK;
   const unsigned g = ew_grid_of(a.a);
-  MPS_EW_CASES(gp_update_kernel, a);
+  MPS_EW_CASES_SEP(gp_update_kernel, a, a.a.pro_sep);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "gp_update launch");
+}
+
+int launch_epilogue(int L, const mp::EpiArgs& a, int npairs, hipStream_t s) {
+  const dim3 g((unsigned)npairs);
+  switch (L) {
+    case 4: MPS_LAUNCH(true, true, mp::epilogue_kernel<4>, g, dim3(64), 0, s, a); break;
+    case 8: MPS_LAUNCH(true, true, mp::epilogue_kernel<8>, g, dim3(64), 0, s, a); break;
+    case 16: MPS_LAUNCH(true, true, mp::epilogue_kernel<16>, g, dim3(64), 0, s, a); break;
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "epilogue launch");
+}
+
+int launch_prologue(int L, const mp::ProArgs& a, int npairs, hipStream_t s) {
+  const dim3 g((unsigned)npairs);
+  switch (L) {
+    case 4: MPS_LAUNCH(true, true, mp::prologue_kernel<4>, g, dim3(64), 0, s, a); break;
+    case 8: MPS_LAUNCH(true, true, mp::prologue_kernel<8>, g, dim3(64), 0, s, a); break;
+    case 16: MPS_LAUNCH(true, true, mp::prologue_kernel<16>, g, dim3(64), 0, s, a); break;
+    default: return fail(MPS_EINVAL, "bad limb count");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "prologue launch");
 }
 
 int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s,

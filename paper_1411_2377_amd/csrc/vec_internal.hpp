@@ -19,6 +19,10 @@ unsigned ew_grid(int64_t n);
 int launch_dot(int L, const mp::DotArgs& a, hipStream_t s);
 int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s);
 int launch_gp_update(int L, const mp::GpUpdArgs& a, hipStream_t s);
+// step prologues of a batch: one wavefront per solve
+int launch_prologue(int L, const mp::ProArgs& a, int npairs, hipStream_t s);
+// driver epilogues of a batch: one wavefront per solve
+int launch_epilogue(int L, const mp::EpiArgs& a, int npairs, hipStream_t s);
 // write the constant to out and to count - 1 further places `step` elements apart
 int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hipStream_t s,
                int64_t count = 1, int64_t step = 0);
