@@ -54,7 +54,7 @@ struct SpmvBatch {
 // Inner-product state (see the exact inner products in solver_kernels.hpp): rings of 2^11 digits
 // (exponent spans up to 32 (2048 - 2L - 2) bits), 8 replicas, tickets in 64 groups; a batch of
 // solves keeps 256-digit rings, 8 replicas and 16 groups per solve.
-constexpr int kDotRingLog2 = 11, kDotReps = 8, kDotGroups = 64;
+constexpr int kDotRingLog2 = 11, kDotReps = 8, kDotGroups = 64;  // replicas: at most 8
 constexpr int kBatchRingLog2 = 8, kBatchReps = 8, kBatchGroups = 16;
 
 // Allocate and clear inner-product state: `nslots` slots (each `reps` rings of 2^ring_log2

@@ -125,9 +125,9 @@ enum Pro {
   PRO_GP_ZETA,         // mu1..mu5: zeta, eta (and tau after the first iteration)
 };
 
-// Out-of-line scalar operations for the epilogues (values and status bits cross the call in
-// registers), so that an epilogue needs only the registers of its largest operation, not of all
-// of them inlined together: the kernels that end with an epilogue keep their occupancy.
+// Scalar operations of the prologues and epilogues, returning their status bits with the value.
+// They are inlined into the (out-of-line) prologue and epilogue: a nested out-of-line call would
+// save and restore the callee-saved registers through scratch memory on every operation.
 template <int L>
 struct NumSt {
   Num<L> v;
@@ -135,7 +135,7 @@ struct NumSt {
 };
 
 template <int L>
-__device__ __attribute__((noinline)) NumSt<L> s_mul(Num<L> a, Num<L> b) {
+MPD NumSt<L> s_mul(Num<L> a, Num<L> b) {
   NumSt<L> r;
   r.st = 0;
   r.v = mul_rn<L>(a, b, r.st);
@@ -143,7 +143,7 @@ __device__ __attribute__((noinline)) NumSt<L> s_mul(Num<L> a, Num<L> b) {
 }
 
 template <int L>
-__device__ __attribute__((noinline)) NumSt<L> s_div(Num<L> a, Num<L> b) {
+MPD NumSt<L> s_div(Num<L> a, Num<L> b) {
   NumSt<L> r;
   r.st = 0;
   r.v = div_rn<L>(a, b, r.st);
@@ -151,7 +151,7 @@ __device__ __attribute__((noinline)) NumSt<L> s_div(Num<L> a, Num<L> b) {
 }
 
 template <int L>
-__device__ __attribute__((noinline)) NumSt<L> s_add(Num<L> a, Num<L> b) {
+MPD NumSt<L> s_add(Num<L> a, Num<L> b) {
   NumSt<L> r;
   r.st = 0;
   r.v = add_rn<L>(a, b, r.st);
@@ -159,7 +159,7 @@ __device__ __attribute__((noinline)) NumSt<L> s_add(Num<L> a, Num<L> b) {
 }
 
 template <int L>
-__device__ __attribute__((noinline)) NumSt<L> s_sub(Num<L> a, Num<L> b) {
+MPD NumSt<L> s_sub(Num<L> a, Num<L> b) {
   NumSt<L> r;
   r.st = 0;
   r.v = sub_rn<L>(a, b, r.st);
@@ -167,7 +167,7 @@ __device__ __attribute__((noinline)) NumSt<L> s_sub(Num<L> a, Num<L> b) {
 }
 
 template <int L>
-__device__ __attribute__((noinline)) NumSt<L> s_sqrt(Num<L> a) {
+MPD NumSt<L> s_sqrt(Num<L> a) {
   NumSt<L> r;
   r.st = 0;
   r.v = sqrt_rn<L>(a, r.st);
@@ -175,7 +175,7 @@ __device__ __attribute__((noinline)) NumSt<L> s_sqrt(Num<L> a) {
 }
 
 template <int L>
-__device__ __attribute__((noinline)) bool s_sqrt_le(Num<L> q, Num<L> thr) {
+MPD bool s_sqrt_le(Num<L> q, Num<L> thr) {
   return sqrt_le<L>(q, thr);
 }
 
@@ -496,7 +496,7 @@ MPD int32_t wave_max(int32_t v) {
 // Windows of at most this many digits are summed without atomics (one digit per thread group).
 constexpr int kPassDigits = 64;
 // Most ring replicas a slot may have.
-constexpr int kMaxReps = 32;
+constexpr int kMaxReps = 8;
 
 template <int L, int NT>
 struct PassLds {
@@ -697,12 +697,24 @@ MPD void ring_peek(const DotWork& dw, int64_t slot0, const int (&rs)[N], Num<L> 
     lo[k] = wave_min(lo[k]);
     hi[k] = wave_max(hi[k]);
   }
-  int64_t dg[N];
+  // every slot's digit loads are issued before any is used: one memory round trip
+  int64_t got[N][kMaxReps];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const int W = hi[k] >= lo[k] ? ring_window<L>(lo[k], hi[k]) : 0;
-    const int s0 = (int)((((int64_t)(lo[k] & ~31)) >> 5) & mask);
-    dg[k] = (W <= 63 && lane < W) ? ring_sum(dw, slot_ring(dw, slot0 + rs[k]), s0, lane) : 0;
+    const int64_t at = ((((int64_t)(lo[k] & ~31)) >> 5) + lane) & mask;
+    const int64_t* ring = slot_ring(dw, slot0 + rs[k]);
+    const bool use = W <= 63 && lane < W;
+#pragma unroll
+    for (int c = 0; c < kMaxReps; ++c)
+      got[k][c] = (use && c < dw.reps) ? ld_dev(ring + ((int64_t)c << dw.ring_log2) + at) : 0;
+  }
+  int64_t dg[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    dg[k] = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxReps; ++c) dg[k] += got[k][c];
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -1092,18 +1104,20 @@ MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, 
     }
   };
   if (kind == PRO_GP_ZETA) {  // mu1, mu3 from the t/s/y step; mu2, mu4, mu5 in rings 4, 6, 7
+    const Num<L> mu1 = sload<L>(S, S_MU1), mu3 = sload<L>(S, S_MU3);  // requested first
     Num<L> mu[3];
     ring_peek<L, 3>(dw, abase, {4, 6, 7}, mu, lds, pcap, st0);
-    keep_in(0, sload<L>(S, S_MU1));
+    keep_in(0, mu1);
     keep_in(1, mu[0]);
-    keep_in(2, sload<L>(S, S_MU3));
+    keep_in(2, mu3);
     keep_in(3, mu[1]);
     keep_in(4, mu[2]);
   } else {  // sigma or den in ring 0, rho
+    const Num<L> rho = sload<L>(S, S_RHO);  // requested first
     Num<L> d[1];
     ring_peek<L, 1>(dw, abase, {0}, d, lds, pcap, st0);
     keep_in(0, d[0]);
-    keep_in(1, sload<L>(S, S_RHO));
+    keep_in(1, rho);
   }
   __builtin_amdgcn_s_waitcnt(0xC07F);  // the inputs are in LDS for the whole wavefront
   const uint32_t w = prologue<L>(kind, P.in_limb, P.in_hdr, iters, P.limb, P.hdr);
