@@ -1327,13 +1327,15 @@ __global__ void __launch_bounds__(256) bicg_dir_kernel(VecArgs A) {
   const bool first = c.ctl->iters == 0;
   const Num<L> beta = sload<L>(c.S, S_BETA);
   MP_ELEMENTWISE_LOOP(A) {
+    // every operand is requested before the branch (p, pt are not used in the first iteration)
     const Num<L> r = vload<L>(A.v[2], i), rt = vload<L>(A.v[3], i);
+    const Num<L> p = vload<L>(A.v[0], i), pt = vload<L>(A.v[1], i);
     if (first) {
       vstore<L>(A.v[0], i, r);
       vstore<L>(A.v[1], i, rt);
     } else {
-      vstore<L>(A.v[0], i, add_rn<L>(r, mul_rn<L>(beta, vload<L>(A.v[0], i), st), st));
-      vstore<L>(A.v[1], i, add_rn<L>(rt, mul_rn<L>(beta, vload<L>(A.v[1], i), st), st));
+      vstore<L>(A.v[0], i, add_rn<L>(r, mul_rn<L>(beta, p, st), st));
+      vstore<L>(A.v[1], i, add_rn<L>(rt, mul_rn<L>(beta, pt, st), st));
     }
   }
   if (st) atomicOr(A.status, st);
@@ -1384,13 +1386,14 @@ __global__ void __launch_bounds__(256) gp_dir_kernel(VecArgs A) {
   const bool first = c.ctl->iters == 0;
   const Num<L> beta = sload<L>(c.S, S_BETA);
   MP_ELEMENTWISE_LOOP(A) {
-    const Num<L> r = vload<L>(A.v[2], i);
+    // every operand is requested before the branch (only r is used in the first iteration)
+    const Num<L> r = vload<L>(A.v[2], i), q = vload<L>(A.v[4], i), v = vload<L>(A.v[3], i);
+    const Num<L> p = vload<L>(A.v[0], i), u = vload<L>(A.v[5], i);
     if (first) {
       vstore<L>(A.v[0], i, r);
     } else {
-      const Num<L> q = vload<L>(A.v[4], i);
-      vstore<L>(A.v[1], i, add_rn<L>(vload<L>(A.v[3], i), mul_rn<L>(beta, q, st), st));
-      const Num<L> pmu = sub_rn<L>(vload<L>(A.v[0], i), vload<L>(A.v[5], i), st);
+      vstore<L>(A.v[1], i, add_rn<L>(v, mul_rn<L>(beta, q, st), st));
+      const Num<L> pmu = sub_rn<L>(p, u, st);
       vstore<L>(A.v[0], i, add_rn<L>(r, mul_rn<L>(beta, pmu, st), st));
     }
   }
