@@ -397,18 +397,22 @@ def main():
             solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0), profile=pr)
             prof[(sname, mode)] = pr
     # per kernel symbol: the sparse products that form the step's inner products (one symbol per
-    # mode, the tuned variant of A x in its solver instantiation) and BiCG's A^T products
+    # mode, the tuned variant of A x in its solver instantiation), BiCG's A^T products, and each
+    # element-wise step (directions, updates, GPBiCG's t/s/y)
     cand = {}
     for (sname, mode), pr in prof.items():
-        for cls, op, fused in ((0, 0, True), (1, 1, False)):
+        names = {0: spmv_kernel_name(plan, 0, mode, L, fused=True),
+                 1: spmv_kernel_name(plan, 1, mode, L),
+                 2: "%s_dir_kernel<%d>" % ("bicg" if sname == "bicg" else "gp", L),
+                 3: "%s_update_kernel<%d, false>" % ("bicg" if sname == "bicg" else "gp", L),
+                 4: "gp_tsy_kernel<%d, false>" % L}
+        for cls, kn in names.items():
             if pr.launches[cls] == 0:
                 continue
-            e = cand.setdefault(spmv_kernel_name(plan, op, mode, L, fused=fused), [0.0, 0, 0.0])
+            e = cand.setdefault(kn, [0.0, 0, 0.0])
             e[0] += pr.us[cls]; e[1] += pr.launches[cls]; e[2] += pr.bytes[cls]
     comp["solver_kernels"] = {k: {"total_us": round(v[0], 1), "launches": v[1],
                                   "avg_us": round(v[0] / max(1, v[1]), 2)} for k, v in cand.items()}
-    comp["solver_vector_updates"] = {"total_us": round(sum(pr.us[2] for pr in prof.values()), 1),
-                                     "launches": sum(pr.launches[2] for pr in prof.values())}
     kname = max(cand, key=lambda k: cand[k][0])
     tot_us, nl, nb = cand[kname]
     achieved = nb / (tot_us * 1e-6) / 1e9

@@ -119,12 +119,12 @@ typedef struct {
  * bracketed by HIP events on the solver's stream; the durations, launch counts and algorithmic
  * bytes (the vectors and matrix entries the kernel must read and write once) are added to the
  * struct per kernel class: [0] sparse products that also form the step's inner products of
- * their output, [1] other sparse products, [2] vector steps (directions and updates, with the
- * inner products they form). */
+ * their output, [1] other sparse products, [2] direction steps, [3] update steps (with the
+ * inner products they form), [4] GPBiCG's t, s, y step. */
 typedef struct mp_solve_profile {
-  int64_t launches[3];
-  double us[3];
-  double bytes[3];
+  int64_t launches[5];
+  double us[5];
+  double bytes[5];
 } mp_solve_profile;
 
 /* solver outcome (mp_solve_info.status) */

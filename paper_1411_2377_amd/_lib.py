@@ -44,8 +44,8 @@ class MpCsr(ctypes.Structure):
 
 
 class MpSolveProfile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 3), ("us", ctypes.c_double * 3),
-                ("bytes", ctypes.c_double * 3)]
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("us", ctypes.c_double * 5),
+                ("bytes", ctypes.c_double * 5)]
 
 
 class MpSolveOpts(ctypes.Structure):

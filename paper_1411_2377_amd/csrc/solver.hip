@@ -274,8 +274,9 @@ int work_alloc(Work& W, int L, int64_t n, int nvec, hipStream_t user) {
 }
 
 // Profiling: class of a launch and its algorithmic bytes.
-// [0] sparse products that also form inner products, [1] other sparse products, [2] vector steps
-enum ProfClass { PROF_SPMV_DOT = 0, PROF_SPMV = 1, PROF_VEC = 2 };
+// [0] sparse products that also form inner products, [1] other sparse products, [2] directions,
+// [3] updates, [4] GPBiCG's t, s, y
+enum ProfClass { PROF_SPMV_DOT = 0, PROF_SPMV = 1, PROF_DIR = 2, PROF_UPD = 3, PROF_TSY = 4 };
 
 int prof_init(Work& W, mp_solve_profile* prof) {
   if (!prof) return MPS_OK;
@@ -614,7 +615,7 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
     int rr;
     mp::VecArgs a = ew_args(W, st);
     a.v[0] = P; a.v[1] = PT; a.v[2] = R; a.v[3] = RT;
-    if ((rr = timed(W, PROF_VEC, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
+    if ((rr = timed(W, PROF_DIR, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
       return rr;
     const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{PT, 0, mp::S_SIGMA}});
     if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
@@ -624,7 +625,7 @@ int bicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
     a = ew_args(W, st);
     a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
     set_fd(W, a, mp::EPI_BICG_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
-    return timed(W, PROF_VEC, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); });
+    return timed(W, PROF_UPD, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); });
   };
   if ((r = run_iterations(W, o, iteration))) return r;
   return finish_solve(W, info, st);
@@ -657,7 +658,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   int rr;
   mp::VecArgs a = ew_args(W, st);
   a.v[0] = P; a.v[1] = Wv; a.v[2] = R; a.v[3] = V; a.v[4] = Q; a.v[5] = U;
-  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
+  if ((rr = timed(W, PROF_DIR, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_DIR, a, W.ws); }))) return rr;
   // q = A p with (rt, q)
   const SpmvFuse den = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_DEN}});
   if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, mode, P, Q, st, true, &den); }))) return rr;
@@ -678,7 +679,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   a.pro_sep = W.batched() ? 1 : 0;
   a.v[0] = T; a.v[1] = S; a.v[2] = Y; a.v[3] = R; a.v[4] = Q; a.v[5] = Wv;
   set_fd(W, a, mp::EPI_NONE, {{3, mp::S_MU1}, {5, mp::S_MU3}});
-  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
+  if ((rr = timed(W, PROF_TSY, vec_bytes(W, 7), [&] { return launch_ew(L, EW_GP_TSY, a, W.ws); }))) return rr;
   // v = A t with (v, t), (v, y), (v, v)
   const SpmvFuse mus =
       fuse_of(W, mp::EPI_NONE, {{T, 4, mp::S_MU2}, {Y, 6, mp::S_MU4}, {self, 7, mp::S_MU5}});
@@ -695,7 +696,7 @@ int gp_iteration(const Work& W, const Op& op, int mode, const mp::VecRef& X, con
   g.y = Y;
   g.v = V;
   g.rt = RT;
-  if ((rr = timed(W, PROF_VEC, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); }))) return rr;
+  if ((rr = timed(W, PROF_UPD, vec_bytes(W, 15), [&] { return launch_gp_update(L, g, W.ws); }))) return rr;
   if (!W.batched()) return MPS_OK;
   mp::EpiArgs ea{};  // a batch runs the stopping test and beta in a launch of its own
   ea.epi = mp::EPI_GP_CONV;

@@ -159,3 +159,27 @@ def test_scaled_3d_ill_conditioned_iterates(solver):
     assert_bitwise(bl, bh, b_o, 512, what="b = A x*")
     run_both(solver, A_h, synth.MPHost(bl, bh, 512), 1, maxit=40, rtol=(1, -100), atol=(0, 0),
              b_oracle=b_o)
+
+
+def test_profiled_solve_same_bits_and_counts():
+    """A profiled solve (eager launches, timing events attached to the kernels) gives the bits
+    of a graph-replayed one and counts every iteration kernel in its class: BiCG one fused SpMV,
+    one A^T product, one direction and one update step per iteration; GPBiCG two fused SpMVs,
+    one direction, one update and one t/s/y step."""
+    M = lib()
+    A_h, _ = synth.config2(p=256, m=12)
+    b_h, _ = rhs_ones(A_h)
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.MPArray.from_host(b_h)
+    plan = M.mp_plan_create(A)
+    for fn, per in ((M.bicg, (1, 1, 1, 1, 0)), (M.gpbicg, (2, 0, 1, 1, 1))):
+        for mode in (0, 1):
+            kw = dict(plan=plan, mode=mode, maxit=10, rtol=(1, -60), atol=(0, 0))
+            x0, i0 = fn(A, b, chunk=4, **kw)
+            pr = M.SolveProfile()
+            x1, i1 = fn(A, b, profile=pr, **kw)
+            assert (i0.status, i0.iters) == (i1.status, i1.iters) == (krylov.NOT_CONVERGED, 10)
+            (l0, h0), (l1, h1) = x0.to_numpy(), x1.to_numpy()
+            assert np.array_equal(l0, l1) and np.array_equal(h0, h1)
+            assert list(pr.launches) == [k * i1.iters for k in per], list(pr.launches)
+            assert all((pr.us[k] > 0) == (per[k] > 0) for k in range(5))
