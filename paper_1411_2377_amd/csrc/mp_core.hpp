@@ -49,20 +49,20 @@ MPD void set_zero(Num<L>& x, uint32_t s) {
 template <int L>
 MPD bool is_zero(const Num<L>& x) { return x.e == kZeroE; }
 
-// Load element i; the limbs of a zero are not read (zero fast path).
+// Load element i.  The header and the limbs are requested together (one memory latency rather
+// than a header read followed by dependent limb reads); a zero's limbs, whatever the buffer
+// holds there, are replaced by 0.
 template <int L>
 MPD void load(Num<L>& x, const uint32_t* __restrict__ limb, const int32_t* __restrict__ hdr,
               int64_t ld, int64_t i) {
-  int32_t h = hdr[i];
+  const int32_t h = hdr[i];
+  uint32_t m[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) m[k] = limb[(int64_t)k * ld + i];
   x.e = h >> 1;
   x.s = (uint32_t)h & 1u;
-  if (x.e != kZeroE) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) x.m[k] = limb[(int64_t)k * ld + i];
-  } else {
-#pragma unroll
-    for (int k = 0; k < L; ++k) x.m[k] = 0;
-  }
+  for (int k = 0; k < L; ++k) x.m[k] = (x.e != kZeroE) ? m[k] : 0u;
 }
 
 template <int L>

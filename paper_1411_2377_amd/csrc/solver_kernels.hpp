@@ -1362,10 +1362,22 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
     set_zero(r, 0);
     set_zero(rt, 0);
     if (ok) {
-      vstore<L>(A.v[0], i, add_rn<L>(vload<L>(A.v[0], i), mul_rn<L>(alpha, vload<L>(A.v[3], i), st), st));
-      r = sub_rn<L>(vload<L>(A.v[1], i), mul_rn<L>(alpha, vload<L>(A.v[4], i), st), st);
+      // A plain solve runs one wavefront per SIMD: every operand is requested before the first
+      // store (the stores could alias the loads for all the compiler knows, so it would not move
+      // a load above one).  Batched launches keep several wavefronts per SIMD resident instead,
+      // with fewer registers: each operand is loaded where it is used.
+      Num<L> r0, z, rt0, zt;
+      const Num<L> x = vload<L>(A.v[0], i), p = vload<L>(A.v[3], i);
+      if constexpr (!SEP) {
+        r0 = vload<L>(A.v[1], i), z = vload<L>(A.v[4], i);
+        rt0 = vload<L>(A.v[2], i), zt = vload<L>(A.v[5], i);
+      }
+      vstore<L>(A.v[0], i, add_rn<L>(x, mul_rn<L>(alpha, p, st), st));
+      if constexpr (SEP) r0 = vload<L>(A.v[1], i), z = vload<L>(A.v[4], i);
+      r = sub_rn<L>(r0, mul_rn<L>(alpha, z, st), st);
       vstore<L>(A.v[1], i, r);
-      rt = sub_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[5], i), st), st);
+      if constexpr (SEP) rt0 = vload<L>(A.v[2], i), zt = vload<L>(A.v[5], i);
+      rt = sub_rn<L>(rt0, mul_rn<L>(alpha, zt, st), st);
       vstore<L>(A.v[2], i, rt);
     }
     const int32_t hr = make_hdr(r.e, r.s), hrt = make_hdr(rt.e, rt.s);
@@ -1422,11 +1434,14 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
     set_zero(tn, 0);
     set_zero(y, 0);
     if (ok) {
+      // every operand is requested before the first store (t and w are not used in the first
+      // iteration)
       const Num<L> r = vload<L>(A.v[3], i), q = vload<L>(A.v[4], i);
+      const Num<L> t = vload<L>(A.v[0], i), w = vload<L>(A.v[5], i);
       const Num<L> aq = mul_rn<L>(alpha, q, st);
       Num<L> s;
       if (!first) {
-        s = sub_rn<L>(vload<L>(A.v[0], i), r, st);
+        s = sub_rn<L>(t, r, st);
         vstore<L>(A.v[1], i, s);
       }
       tn = sub_rn<L>(r, aq, st);
@@ -1434,7 +1449,7 @@ __global__ void __launch_bounds__(256) gp_tsy_kernel(VecArgs A) {
       if (first) {
         y = sub_rn<L>(aq, r, st);
       } else {
-        const Num<L> wq = sub_rn<L>(vload<L>(A.v[5], i), q, st);
+        const Num<L> wq = sub_rn<L>(w, q, st);
         y = sub_rn<L>(s, mul_rn<L>(alpha, wq, st), st);
       }
       vstore<L>(A.v[2], i, y);
@@ -1475,21 +1490,28 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     set_zero(rn, 0);
     set_zero(rt, 0);
     if (ok) {
+      // A plain solve requests every operand before the first store; batched launches load
+      // each where it is used (see bicg_update_kernel).
+      Num<L> r, z_old, x_old, p, t, y, v;
       rt = vload<L>(G.rt, i);
       const Num<L> q = vload<L>(A.v[4], i), s = vload<L>(A.v[5], i);
       const Num<L> u_old = vload<L>(A.v[0], i);
+      if constexpr (!SEP) {
+        r = vload<L>(A.v[3], i), z_old = vload<L>(A.v[1], i), x_old = vload<L>(A.v[2], i);
+        p = vload<L>(A.v[6], i), t = vload<L>(A.v[7], i), y = vload<L>(G.y, i), v = vload<L>(G.v, i);
+      }
       const Num<L> u = add_rn<L>(mul_rn<L>(zeta, q, st),
                                  mul_rn<L>(eta, add_rn<L>(s, mul_rn<L>(beta, u_old, st), st), st), st);
       vstore<L>(A.v[0], i, u);
-      const Num<L> r = vload<L>(A.v[3], i);
-      const Num<L> z = sub_rn<L>(add_rn<L>(mul_rn<L>(zeta, r, st), mul_rn<L>(eta, vload<L>(A.v[1], i), st), st),
+      if constexpr (SEP) r = vload<L>(A.v[3], i), z_old = vload<L>(A.v[1], i);
+      const Num<L> z = sub_rn<L>(add_rn<L>(mul_rn<L>(zeta, r, st), mul_rn<L>(eta, z_old, st), st),
                                  mul_rn<L>(alpha, u, st), st);
       vstore<L>(A.v[1], i, z);
-      const Num<L> x = add_rn<L>(add_rn<L>(vload<L>(A.v[2], i), mul_rn<L>(alpha, vload<L>(A.v[6], i), st), st), z, st);
+      if constexpr (SEP) x_old = vload<L>(A.v[2], i), p = vload<L>(A.v[6], i);
+      const Num<L> x = add_rn<L>(add_rn<L>(x_old, mul_rn<L>(alpha, p, st), st), z, st);
       vstore<L>(A.v[2], i, x);
-      const Num<L> t = vload<L>(A.v[7], i);
-      rn = sub_rn<L>(sub_rn<L>(t, mul_rn<L>(eta, vload<L>(G.y, i), st), st),
-                     mul_rn<L>(zeta, vload<L>(G.v, i), st), st);
+      if constexpr (SEP) t = vload<L>(A.v[7], i), y = vload<L>(G.y, i), v = vload<L>(G.v, i);
+      rn = sub_rn<L>(sub_rn<L>(t, mul_rn<L>(eta, y, st), st), mul_rn<L>(zeta, v, st), st);
       vstore<L>(A.v[3], i, rn);
     }
     const int32_t hr = make_hdr(rn.e, rn.s), hrt = make_hdr(rt.e, rt.s);
