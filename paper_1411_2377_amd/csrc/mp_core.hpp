@@ -154,7 +154,7 @@ MPD void mul_full(const uint32_t (&a)[L], const uint32_t (&b)[L], uint32_t (&p)[
 }
 
 // Round the exact product (2L limbs, value P * 2^(e2 - 2p), P != 0 with its top bit at 2p-1 or
-// 2p-2) to p bits, ties to even.
+// 2p-2) to p bits, ties to even; straight-line code (selects).
 template <int L>
 MPD void round_product(const uint32_t (&pr)[2 * L], int32_t e2, uint32_t s, Num<L>& out,
                        uint32_t& st) {
@@ -162,56 +162,61 @@ MPD void round_product(const uint32_t (&pr)[2 * L], int32_t e2, uint32_t s, Num<
   uint32_t m[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) m[k] = top ? pr[L + k] : fshr(pr[L + k], pr[L + k - 1], 31);
-  uint32_t rnd = top ? (pr[L - 1] >> 31) : ((pr[L - 1] >> 30) & 1u);
+  const uint32_t rnd = top ? (pr[L - 1] >> 31) : ((pr[L - 1] >> 30) & 1u);
   uint32_t sticky = top ? (pr[L - 1] << 1) : (pr[L - 1] << 2);
 #pragma unroll
   for (int k = 0; k < L - 1; ++k) sticky |= pr[k];
   int32_t e = top ? e2 : e2 - 1;
-  uint32_t inc = rnd & (uint32_t)((sticky != 0) | (m[0] & 1u));
-  uint32_t cy = inc;
+  uint32_t cy = rnd & (uint32_t)((sticky != 0) | (m[0] & 1u));
 #pragma unroll
   for (int k = 0; k < L; ++k) m[k] = __builtin_addc(m[k], 0u, cy, &cy);
-  if (cy) {
-    m[L - 1] = 0x80000000u;
-    e += 1;
-  }
+  m[L - 1] = cy ? 0x80000000u : m[L - 1];  // rounding carried out of the top: 2^p
+  e += (int32_t)cy;
+  const bool range = (e > kEmax) | (e < kEmin);
+  st |= range ? kStRange : 0u;
 #pragma unroll
-  for (int k = 0; k < L; ++k) out.m[k] = m[k];
-  out.e = e;
+  for (int k = 0; k < L; ++k) out.m[k] = range ? 0u : m[k];
+  out.e = range ? kZeroE : e;
   out.s = s;
-  if (e > kEmax || e < kEmin) {
-    st |= kStRange;
-    set_zero(out, s);
-  }
 }
 
-// RN(a * b) with the zero fast path: a zero factor gives a zero with the xor sign.
+// RN(a * b).  The exact product is formed and rounded for every operand pair, and a zero
+// factor then selects a zero with the xor sign: straight-line code (selects, no divergent
+// branch), so the products of a wavefront's lanes run together whatever their data.  (The
+// sparse products test their stored zeros first and skip the product.)
 template <int L>
 MPD Num<L> mul_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
-  Num<L> r;
-  if (is_zero(a) || is_zero(b)) {
-    set_zero(r, a.s ^ b.s);
-    return r;
-  }
+  const bool z = is_zero(a) | is_zero(b);
   uint32_t pr[2 * L];
   mul_full<L>(a.m, b.m, pr);
-  round_product<L>(pr, a.e + b.e, a.s ^ b.s, r, st);
+  // A zero factor's product (discarded below) is given a top bit, so that the exponent sum of
+  // two zeros (INT32_MIN) is not decremented.
+  pr[2 * L - 1] |= z ? 0x80000000u : 0u;
+  uint32_t st1 = 0;
+  Num<L> r;
+  round_product<L>(pr, (int32_t)((uint32_t)a.e + (uint32_t)b.e), a.s ^ b.s, r, st1);
+  st |= z ? 0u : st1;
+#pragma unroll
+  for (int k = 0; k < L; ++k) r.m[k] = z ? 0u : r.m[k];
+  r.e = z ? kZeroE : r.e;
   return r;
 }
 
-// x (N limbs) >>= d, 0 <= d < 32N; bits shifted out are ORed into bit 0 (sticky).
+// x (N limbs) >>= d, 0 <= d < 32N; bits shifted out are ORed into bit 0 (sticky).  Whole
+// limbs move in log2(N) select stages.
 template <int N>
 MPD void shr_sticky(uint32_t (&x)[N], uint32_t d) {
   const uint32_t q = d >> 5, r = d & 31u;
   uint32_t sticky = 0;
 #pragma unroll
   for (int bit = 1; bit < N; bit <<= 1) {
-    if (q & (uint32_t)bit) {
+    const bool sh = (q & (uint32_t)bit) != 0;
+    uint32_t lost = 0;
 #pragma unroll
-      for (int i = 0; i < bit; ++i) sticky |= x[i];
+    for (int i = 0; i < bit; ++i) lost |= x[i];
+    sticky |= sh ? lost : 0u;
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = (i + bit < N) ? x[i + bit] : 0u;
-    }
+    for (int i = 0; i < N; ++i) x[i] = sh ? ((i + bit < N) ? x[i + bit] : 0u) : x[i];
   }
   sticky |= r ? (x[0] << (32u - r)) : 0u;
 #pragma unroll
@@ -226,32 +231,24 @@ MPD void shl(uint32_t (&x)[N], uint32_t d) {
   const uint32_t q = d >> 5, r = d & 31u;
 #pragma unroll
   for (int bit = 1; bit < N; bit <<= 1) {
-    if (q & (uint32_t)bit) {
+    const bool sh = (q & (uint32_t)bit) != 0;
 #pragma unroll
-      for (int i = N - 1; i >= 0; --i) x[i] = (i >= bit) ? x[i - bit] : 0u;
-    }
+    for (int i = N - 1; i >= 0; --i) x[i] = sh ? ((i >= bit) ? x[i - bit] : 0u) : x[i];
   }
-  if (r) {
 #pragma unroll
-    for (int i = N - 1; i >= 1; --i) x[i] = fshr(x[i], x[i - 1], 32u - r);
-    x[0] <<= r;
-  }
+  for (int i = N - 1; i >= 1; --i) x[i] = r ? fshr(x[i], x[i - 1], 32u - r) : x[i];
+  x[0] <<= r;
 }
 
+// leading zero bits of an N-limb integer (32N for zero)
 template <int N>
 MPD uint32_t clz_n(const uint32_t (&x)[N]) {
   uint32_t lz = 0;
   bool found = false;
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
-    if (!found) {
-      if (x[i]) {
-        lz += __clz(x[i]);
-        found = true;
-      } else {
-        lz += 32;
-      }
-    }
+    lz += found ? 0u : (uint32_t)__clz(x[i]);
+    found |= x[i] != 0;
   }
   return lz;
 }
@@ -263,93 +260,84 @@ MPD uint32_t clz_n(const uint32_t (&x)[N]) {
 // bit 0.  For d >= 2 an effective subtraction loses at most one leading bit, so that sticky
 // bit always stays below the round bit (bit 31 of the guard limb); for d <= 1 no bit is
 // shifted out and the difference is exact before normalisation.  For d >= p + 2, |Y| is below
-// a quarter of X's last unit and the result is X.
+// a quarter of X's last unit and the result is X: d is clamped there (Y then lands inside the
+// guard limb, below its round bit, and rounding returns X).
+//
+// Mostly straight-line code: the subtraction is the addition of Y's complement, an addition that
+// carried out is shifted right by one, a one-bit cancellation is shifted back, and zero
+// operands, an exact zero and range errors are selected at the end.  Only the cases that need
+// d <= 1 branch: a negative difference (negated) and a cancellation of more than one bit.
 template <int L>
 MPD Num<L> add_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
   const bool az = is_zero(a), bz = is_zero(b);
-  if (az || bz) {
-    Num<L> r;
-    if (az && bz) {
-      set_zero(r, a.s & b.s);
-      return r;
-    }
-    return az ? b : a;
-  }
-  const bool sw = b.e > a.e;
-  Num<L> X, Y;
-#pragma unroll
-  for (int k = 0; k < L; ++k) {
-    X.m[k] = sw ? b.m[k] : a.m[k];
-    Y.m[k] = sw ? a.m[k] : b.m[k];
-  }
-  X.e = sw ? b.e : a.e;
-  Y.e = sw ? a.e : b.e;
-  X.s = sw ? b.s : a.s;
-  Y.s = sw ? a.s : b.s;
-  const uint32_t d = (uint32_t)(X.e - Y.e);
-  if (d >= (uint32_t)(32 * L + 2)) return X;
-
+  const bool sw = b.e > a.e;  // a zero's exponent is below every other one
   uint32_t xa[L + 1], ya[L + 1];
   xa[0] = 0;
   ya[0] = 0;
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    xa[k + 1] = X.m[k];
-    ya[k + 1] = Y.m[k];
+    xa[k + 1] = sw ? b.m[k] : a.m[k];
+    ya[k + 1] = sw ? a.m[k] : b.m[k];
   }
+  const int32_t Xe = sw ? b.e : a.e, Ye = sw ? a.e : b.e;
+  const uint32_t Xs = sw ? b.s : a.s, Ys = sw ? a.s : b.s;
+  const uint32_t d = min((uint32_t)(Xe - Ye), (uint32_t)(32 * L + 2));
   shr_sticky<L + 1>(ya, d);
-  int32_t e = X.e;
-  uint32_t s = X.s;
+  const bool sub = Xs != Ys;
+  const uint32_t mask = sub ? ~0u : 0u;
   uint32_t r[L + 1];
-  if (X.s == Y.s) {
-    uint32_t cy = 0;
+  uint32_t cy = sub ? 1u : 0u;
 #pragma unroll
-    for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(xa[k], ya[k], cy, &cy);
-    if (cy) {
-      const uint32_t lost = r[0] & 1u;
+  for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(xa[k], ya[k] ^ mask, cy, &cy);
+  const bool neg = sub & (cy == 0);   // |Y| > |X| (d == 0 only: rare, so a branch)
+  const bool ovf = !sub & (cy != 0);  // the sum carried out of the top limb
+  if (neg) {
+    uint32_t c2 = 1;
 #pragma unroll
-      for (int k = 0; k < L; ++k) r[k] = fshr(r[k + 1], r[k], 1);
-      r[L] = (r[L] >> 1) | 0x80000000u;
-      r[0] |= lost;
-      e += 1;
-    }
-  } else {
-    uint32_t bw = 0;
-#pragma unroll
-    for (int k = 0; k <= L; ++k) r[k] = __builtin_subc(xa[k], ya[k], bw, &bw);
-    if (bw) {  // only when d == 0 and |Y| > |X|
-      uint32_t c = 1;
-#pragma unroll
-      for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(~r[k], 0u, c, &c);
-      s ^= 1u;
-    }
-    const uint32_t lz = clz_n<L + 1>(r);
-    if (lz >= 32u * (L + 1)) {
-      Num<L> z;
-      set_zero(z, 0);
-      return z;
-    }
-    if (lz) shl<L + 1>(r, lz);
-    e -= (int32_t)lz;
+    for (int k = 0; k <= L; ++k) r[k] = __builtin_addc(~r[k], 0u, c2, &c2);
   }
+  const uint32_t s = Xs ^ (neg ? 1u : 0u);
+  int32_t e = Xe + (ovf ? 1 : 0);
+  {
+    const uint32_t lost = r[0] & 1u;
+    uint32_t t[L + 1];
+#pragma unroll
+    for (int k = 0; k < L; ++k) t[k] = fshr(r[k + 1], r[k], 1);
+    t[L] = (r[L] >> 1) | 0x80000000u;
+    t[0] |= lost;
+#pragma unroll
+    for (int k = 0; k <= L; ++k) r[k] = ovf ? t[k] : r[k];
+  }
+  const uint32_t lz = clz_n<L + 1>(r);
+  const bool zres = lz >= 32u * (L + 1);  // exact cancellation
+  const uint32_t lzs = zres ? 0u : lz;
+  if (lzs > 1) {  // a cancellation of more than one bit (d <= 1 only: a branch)
+    shl<L + 1>(r, lzs);
+  } else {
+#pragma unroll
+    for (int k = L; k >= 1; --k) r[k] = lzs ? fshr(r[k], r[k - 1], 31) : r[k];
+    r[0] = lzs ? r[0] << 1 : r[0];
+  }
+  e -= (int32_t)lzs;
   const uint32_t rnd = r[0] >> 31;
   const uint32_t sticky = r[0] & 0x7fffffffu;
+  uint32_t m[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) m[k] = r[k + 1];
+  uint32_t c3 = rnd & (uint32_t)((sticky != 0) | (m[0] & 1u));
+#pragma unroll
+  for (int k = 0; k < L; ++k) m[k] = __builtin_addc(m[k], 0u, c3, &c3);
+  m[L - 1] = c3 ? 0x80000000u : m[L - 1];
+  e += (int32_t)c3;
+  const bool bothz = az & bz;
+  const bool range = !bothz & !zres & ((e > kEmax) | (e < kEmin));
+  st |= range ? kStRange : 0u;
+  const bool zr = bothz | zres | range;
   Num<L> out;
 #pragma unroll
-  for (int k = 0; k < L; ++k) out.m[k] = r[k + 1];
-  uint32_t cy = rnd & (uint32_t)((sticky != 0) | (out.m[0] & 1u));
-#pragma unroll
-  for (int k = 0; k < L; ++k) out.m[k] = __builtin_addc(out.m[k], 0u, cy, &cy);
-  if (cy) {
-    out.m[L - 1] = 0x80000000u;
-    e += 1;
-  }
-  out.e = e;
-  out.s = s;
-  if (e > kEmax || e < kEmin) {
-    st |= kStRange;
-    set_zero(out, s);
-  }
+  for (int k = 0; k < L; ++k) out.m[k] = zr ? 0u : m[k];
+  out.e = zr ? kZeroE : e;
+  out.s = bothz ? (a.s & b.s) : zres ? 0u : s;  // x - x is +0; (-0) + (-0) is -0
   return out;
 }
 

@@ -2,8 +2,8 @@
 // root, and the exact form of the stopping test ||r|| <= thr without a square root.
 //
 // Division is schoolbook long division on 32-bit digits (Knuth, TAOCP Vol. 2, Sec. 4.3.1,
-// Algorithm D): quotient digits are estimated from the top two numerator digits and the top
-// divisor digit, corrected with the second divisor digit, then fixed up by at most one add-back.
+// Algorithm D), with each quotient digit estimated in double precision from three remainder and
+// two divisor digits, so that it is exact or one too large and at most one add-back fixes it.
 // The square root is the binary digit-by-digit method on the scaled mantissa; a non-zero
 // remainder is the sticky bit.
 #pragma once
@@ -46,51 +46,34 @@ MPD Num<L> div_rn(const Num<L>& a, const Num<L>& b, uint32_t& st) {
   u[NU] = 0;
   const uint32_t* v = b.m;
   uint32_t q[NU - L + 1];
-  // The trial digit floor(num / v_top) is estimated in double precision (num < 2^64 is off by
-  // at most a few units after rounding to 53 bits) and then made exact with integer steps.
-  const double vtop_inv = 1.0 / (double)v[L - 1];
+  // Trial digit: the top three remainder limbs times the reciprocal of the top two divisor
+  // limbs, in double precision, plus 2^-17, truncated (and capped at 2^32 - 1).  The quotient
+  // of the truncated operands exceeds the true one by less than 2^-30 (the divisor is
+  // normalised) and the rounding errors stay below 2^-18, so the trial digit is the true digit
+  // or one more: a single add-back (rare) makes it exact.
+  const double rv = 1.0 / ((double)v[L - 1] * 4294967296.0 + (double)v[L - 2]);
 #pragma unroll
   for (int j = NU - L; j >= 0; --j) {
-    const uint64_t num = ((uint64_t)u[j + L] << 32) | u[j + L - 1];
-    const double numd = (double)u[j + L] * 4294967296.0 + (double)u[j + L - 1];
-    uint64_t qhat = (uint64_t)(numd * vtop_inv);
-    int64_t rs = (int64_t)(num - qhat * (uint64_t)v[L - 1]);  // |rs| < 2^40: exact in int64
-    while (rs < 0) {
-      qhat -= 1;
-      rs += v[L - 1];
-    }
-    while (rs >= (int64_t)v[L - 1]) {
-      qhat += 1;
-      rs -= v[L - 1];
-    }
-    uint64_t rhat = (uint64_t)rs;
-    while (qhat >> 32 ||
-           (L >= 2 && qhat * v[L - 2] > ((rhat << 32) | (L >= 2 ? u[j + L - 2] : 0u)))) {
-      qhat -= 1;
-      rhat += v[L - 1];
-      if (rhat >> 32) break;
-    }
+    const double ud =
+        ((double)u[j + L] * 4294967296.0 + (double)u[j + L - 1]) * 4294967296.0 + (double)u[j + L - 2];
+    uint32_t qhat = (uint32_t)fmin(fma(ud, rv, 0x1p-17), 4294967295.0);
     // u[j .. j+L] -= qhat * v
-    uint64_t carry = 0;
-    int64_t borrow = 0;
+    uint32_t c = 0, bw = 0;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      const uint64_t pq = qhat * v[i] + carry;
-      carry = pq >> 32;
-      const int64_t t = (int64_t)u[i + j] - (int64_t)(uint32_t)pq - borrow;
-      u[i + j] = (uint32_t)t;
-      borrow = t < 0 ? 1 : 0;
+      const uint64_t t = (uint64_t)qhat * v[i] + c;
+      c = (uint32_t)(t >> 32);
+      u[j + i] = __builtin_subc(u[j + i], (uint32_t)t, bw, &bw);
     }
-    const int64_t t = (int64_t)u[j + L] - (int64_t)carry - borrow;
-    u[j + L] = (uint32_t)t;
-    if (t < 0) {  // the estimate was one too large: add v back
+    u[j + L] = __builtin_subc(u[j + L], c, bw, &bw);
+    if (bw) {  // the trial digit was one too large: add v back
       qhat -= 1;
       uint32_t cy = 0;
 #pragma unroll
       for (int i = 0; i < L; ++i) u[i + j] = __builtin_addc(u[i + j], v[i], cy, &cy);
       u[j + L] += cy;
     }
-    q[j] = (uint32_t)qhat;
+    q[j] = qhat;
   }
   // quotient Q = q[0 .. L+1] (p+1 or p+2 bits); remainder in u[0 .. L)
   uint32_t rem = 0;
