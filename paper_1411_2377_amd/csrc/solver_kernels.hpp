@@ -441,6 +441,8 @@ struct ProOut {
   int brk;
   int nclr;     // inner-product slots the prologue read (its launch's last block clears them)
   int clr[3];
+  const int32_t* clo;  // their exponent ranges (LDS)
+  const int32_t* chi;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -676,13 +678,14 @@ MPD int64_t ring_sum(const DotWork& dw, const int64_t* ring, int s0, int w) {
 }
 
 // RN_p of the inner products of N slots, read from their rings and bins without clearing them
-// (the kernel that formed them has ended), by one whole wavefront: every lane gets out[k].  The
-// bins of all slots are read at once, then the windows' digits; windows of more than 63 digits
-// are summed into `lds` (capacity `cap`) and rounded by lane 0.  A window wider than the ring or
-// `cap` sets kStWindow and gives +0.
+// (the kernel that formed them has ended), by one whole wavefront: every lane gets out[k] and
+// the slot's exponent range (rlo[k], rhi[k]), which ring_clear_range takes.  The bins of all
+// slots are read at once, then the windows' digits; windows of more than 63 digits are summed
+// into `lds` (capacity `cap`) and rounded by lane 0.  A window wider than the ring or `cap` sets
+// kStWindow and gives +0.
 template <int L, int N>
 MPD void ring_peek(const DotWork& dw, int64_t slot0, const int (&rs)[N], Num<L> (&out)[N],
-                   int64_t* lds, int cap, uint32_t& st) {
+                   int32_t (&rlo)[N], int32_t (&rhi)[N], int64_t* lds, int cap, uint32_t& st) {
   const int lane = threadIdx.x & 63;
   const int R = 1 << dw.ring_log2, mask = R - 1;
   int32_t lo[N], hi[N];
@@ -696,6 +699,8 @@ MPD void ring_peek(const DotWork& dw, int64_t slot0, const int (&rs)[N], Num<L> 
   for (int k = 0; k < N; ++k) {
     lo[k] = wave_min(lo[k]);
     hi[k] = wave_max(hi[k]);
+    rlo[k] = lo[k];
+    rhi[k] = hi[k];
   }
   // every slot's digit loads are issued before any is used: one memory round trip
   int64_t got[N][kMaxReps];
@@ -741,13 +746,15 @@ MPD void ring_peek(const DotWork& dw, int64_t slot0, const int (&rs)[N], Num<L> 
   }
 }
 
-// Clear slot `slot` (its window's digits in every replica, or the whole ring when the window
-// is wider than the ring or `cap`) and reset its bins, by one whole wavefront.
+// Clear slot `slot`, whose products span [lo, hi] (its window's digits in every replica, or
+// the whole ring when the window is wider than the ring or `cap`), and reset its bins, by one
+// whole wavefront: stores only.
 template <int L>
-MPD void ring_clear(const DotWork& dw, int64_t slot, int cap) {
+MPD void ring_clear_range(const DotWork& dw, int64_t slot, int32_t lo, int32_t hi, int cap) {
   const int lane = threadIdx.x & 63;
-  int32_t lo, hi;
-  ring_range(dw, slot, lo, hi);
+  int32_t* b = dw.anchor + 2 * (slot * kAnchorBins + lane);
+  st_dev(b, (int32_t)INT32_MAX);
+  st_dev(b + 1, (int32_t)INT32_MIN);
   if (hi < lo) return;
   const int R = 1 << dw.ring_log2, mask = R - 1;
   int64_t* const ring = slot_ring(dw, slot);
@@ -917,7 +924,8 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
   if (pro) {  // the rings the step's prologue read
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      if (k < pro->nclr && wv == k % NW) ring_clear<L>(dw, slot0 + pro->clr[k], cap);
+      if (k < pro->nclr && wv == k % NW)
+        ring_clear_range<L>(dw, slot0 + pro->clr[k], pro->clo[k], pro->chi[k], cap);
   }
   if (ctl && st) atomicOr(&ctl->flags, st);
   if (brk && t == 0) {
@@ -1083,6 +1091,7 @@ struct ProLds {
   int32_t hdr[3];
   uint32_t in_limb[5 * L];  // inputs
   int32_t in_hdr[5];
+  int32_t rlo[3], rhi[3];   // exponent ranges of the rings read
   uint32_t word;
 };
 
@@ -1106,7 +1115,15 @@ MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, 
   if (kind == PRO_GP_ZETA) {  // mu1, mu3 from the t/s/y step; mu2, mu4, mu5 in rings 4, 6, 7
     const Num<L> mu1 = sload<L>(S, S_MU1), mu3 = sload<L>(S, S_MU3);  // requested first
     Num<L> mu[3];
-    ring_peek<L, 3>(dw, abase, {4, 6, 7}, mu, lds, pcap, st0);
+    int32_t lo[3], hi[3];
+    ring_peek<L, 3>(dw, abase, {4, 6, 7}, mu, lo, hi, lds, pcap, st0);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        P.rlo[k] = lo[k];
+        P.rhi[k] = hi[k];
+      }
+    }
     keep_in(0, mu1);
     keep_in(1, mu[0]);
     keep_in(2, mu3);
@@ -1115,7 +1132,12 @@ MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, 
   } else {  // sigma or den in ring 0, rho
     const Num<L> rho = sload<L>(S, S_RHO);  // requested first
     Num<L> d[1];
-    ring_peek<L, 1>(dw, abase, {0}, d, lds, pcap, st0);
+    int32_t lo[1], hi[1];
+    ring_peek<L, 1>(dw, abase, {0}, d, lo, hi, lds, pcap, st0);
+    if (lane == 0) {
+      P.rlo[0] = lo[0];
+      P.rhi[0] = hi[0];
+    }
     keep_in(0, d[0]);
     keep_in(1, rho);
   }
@@ -1176,6 +1198,8 @@ MPD ProOut run_prologue(ProLds<L>& P, int kind, const EwCtx& c, const DotWork& d
   o.limb = P.limb;
   o.hdr = P.hdr;
   o.nclr = prologue_rings(kind, o.clr);
+  o.clo = P.rlo;
+  o.chi = P.rhi;
   if (!o.brk && c.idx == 0 && threadIdx.x == 0) {
     for (int k = 0; k < o.n; ++k) sstore<L>(c.S, slots[k], lds_num<L>(P.limb, P.hdr, k));
   }
@@ -1224,7 +1248,8 @@ __global__ void __launch_bounds__(64) prologue_kernel(ProArgs A) {
   }
   int clr[3];
   const int nclr = prologue_rings(A.kind, clr);
-  for (int k = 0; k < nclr; ++k) ring_clear<L>(A.dots, abase + clr[k], lds_window_digits<L, 64>());
+  for (int k = 0; k < nclr; ++k)
+    ring_clear_range<L>(A.dots, abase + clr[k], pl.rlo[k], pl.rhi[k], lds_window_digits<L, 64>());
 }
 
 // Driver epilogues of a batch in a launch of their own (the batch's element-wise steps are
