@@ -402,7 +402,12 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
         for (int w = 0; w < L; ++w) p.m[w] = s_m[b][w][j];
         p.e = s_e[b][j];
         p.s = s_s[b][j];
-        acc = add_rn<L>(acc, p, st);
+        if (c == 0 && q == 0) {  // RN(+0 + p): p itself, +0 for a zero p (a uniform branch)
+          acc = p;
+          acc.s = is_zero(p) ? 0u : p.s;
+        } else {
+          acc = add_rn<L>(acc, p, st);
+        }
       }
     }
     __syncthreads();
