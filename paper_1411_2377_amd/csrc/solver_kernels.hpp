@@ -330,8 +330,8 @@ __device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb
 // 16 when tau was formed.
 // Inputs in i_limb / i_hdr (k-th at i_limb[k * L ...], i_hdr[k]): sigma or den, rho; or mu1..mu5.
 template <int L>
-__device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* i_limb, int32_t* i_hdr,
-                                                      int iters, uint32_t* o_limb, int32_t* o_hdr) {
+MPD uint32_t prologue_body(int kind, uint32_t* i_limb, int32_t* i_hdr, int iters, uint32_t* o_limb,
+                           int32_t* o_hdr) {
   const int lane = threadIdx.x & 63;
   uint32_t st = 0, brk = 0, tau_ok = 0;
   auto in = [&](int k) {
@@ -418,6 +418,15 @@ __device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* i_lim
   }
   st = __shfl(st, 0);
   return (st & 0xFFu) | (brk << 8) | (tau_ok << 16);
+}
+
+// The same out of line: the prologue of zeta and eta is large, and the update step that runs it
+// holds many values in registers (inlined there, it would spill them).  The alpha prologues are
+// inlined, which spares their callers the register saves of a call.
+template <int L>
+__device__ __attribute__((noinline)) uint32_t prologue(int kind, uint32_t* i_limb, int32_t* i_hdr,
+                                                      int iters, uint32_t* o_limb, int32_t* o_hdr) {
+  return prologue_body<L>(kind, i_limb, i_hdr, iters, o_limb, o_hdr);
 }
 
 template <int L>
@@ -1142,7 +1151,8 @@ MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, 
     keep_in(1, rho);
   }
   __builtin_amdgcn_s_waitcnt(0xC07F);  // the inputs are in LDS for the whole wavefront
-  const uint32_t w = prologue<L>(kind, P.in_limb, P.in_hdr, iters, P.limb, P.hdr);
+  const uint32_t w = (kind == PRO_GP_ZETA) ? prologue<L>(kind, P.in_limb, P.in_hdr, iters, P.limb, P.hdr)
+                                            : prologue_body<L>(kind, P.in_limb, P.in_hdr, iters, P.limb, P.hdr);
   __builtin_amdgcn_s_waitcnt(0xC07F);  // and the results
   return w | (st0 & 0xFFu);
 }

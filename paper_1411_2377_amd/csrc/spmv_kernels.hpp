@@ -124,21 +124,23 @@ MPD void spmv_fused_dots(const SpmvArgs& A, const SpmvBlock& B, bool has_row, in
   __shared__ PassLds<L, NT> lds;
   const int32_t hy = has_row ? make_hdr(y.e, y.s) : (int32_t)0x80000000;
   const int64_t slot0 = (int64_t)B.pair * kDotSlots;
+  // every partner element is requested before the first pass (one memory latency in all)
+  int32_t hw[3];
+  uint32_t wm[3][L];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (k < A.fd.nd) {
-      int32_t hw = hy;
-      uint32_t wm[L];
+    hw[k] = hy;
 #pragma unroll
-      for (int q = 0; q < L; ++q) wm[q] = y.m[q];
-      if (A.part[k].hdr && has_row) {
-        hw = A.part[k].hdr[yi];
+    for (int q = 0; q < L; ++q) wm[k][q] = y.m[q];
+    if (k < A.fd.nd && A.part[k].hdr && has_row) {
+      hw[k] = A.part[k].hdr[yi];
 #pragma unroll
-        for (int q = 0; q < L; ++q) wm[q] = A.part[k].limb[(int64_t)q * A.part[k].ld + yi];
-      }
-      pass_dot<L, NT>(lds, has_row, hy, hw, y.m, wm, A.dots, slot0 + A.fd.slot[k]);
+      for (int q = 0; q < L; ++q) wm[k][q] = A.part[k].limb[(int64_t)q * A.part[k].ld + yi];
     }
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < A.fd.nd) pass_dot<L, NT>(lds, has_row, hy, hw[k], y.m, wm[k], A.dots, slot0 + A.fd.slot[k]);
   if (st) atomicOr(A.status, st);
 }
 
