@@ -41,6 +41,8 @@ ITERS = 200
 # instructions; v_mad_u64_u32 (the 32x32->64 limb product) issues at half that rate (measured
 # with independent chains), so the limb-product roofline is 19.66 T mads/s.
 PEAK_MAD_TOPS = 256 * 4 * 16 * 2.4e9 / 2 / 1e12
+# VALU issue slots: one wave64 instruction per SIMD every 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("spmv_kernels.hpp", "solver_kernels.hpp", "mp_core.hpp", "mp_exact.hpp",
                   "mp_scalar.hpp")
@@ -149,8 +151,8 @@ def spmv_kernel_name(plan, op, mode, L, fused=False):
     return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "")
 
 
-def load_traffic(kernel):
-    """HBM traffic per launch from the committed counter summary, when it was taken on the
+def load_counters(kernel):
+    """The committed counter summary's entry for a kernel symbol, when it was taken on the
     current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
@@ -160,7 +162,23 @@ def load_traffic(kernel):
     ent = d.get(kernel.split(" (")[0])
     if not ent or ent.get("kernel_source") != kernel_source_hash():
         return None
-    return ent["fetch_bytes"] + ent["write_bytes"]
+    return ent
+
+
+def load_traffic(kernel):
+    """HBM traffic per launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the plain-copy calibration), or None."""
+    ent = load_counters(kernel)
+    return None if ent is None else ent["fetch_bytes"] + ent["write_bytes"]
+
+
+def valu_issue_frac(kernel, launch_us):
+    """VALU instructions per launch from the committed counter summary over the VALU issue
+    slots of a launch of the live duration, or None."""
+    ent = load_counters(kernel)
+    if ent is None or not ent.get("valu_instr"):
+        return None
+    return round(ent["valu_instr"] / (launch_us * 1e-6 * VALU_ISSUE_PEAK), 4)
 
 
 def powerlaw_component(M, torch, reps):
@@ -420,7 +438,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": load_traffic(kname), "kernel": kname,
                 "launch_us": round(tot_us / max(1, nl), 2), "launches": nl,
-                "algorithmic_bytes_per_launch": round(nb / max(1, nl))}
+                "algorithmic_bytes_per_launch": round(nb / max(1, nl)),
+                "valu_issue_frac": valu_issue_frac(kname, tot_us / max(1, nl))}
     # the sparse product of the step alone (its roofline beside the dominant kernel's)
     smode = M.MP_EXACT if comp["spmv_exact_us"] >= comp["spmv_seq_us"] else M.MP_SEQ
     tk = comp["spmv_exact_us" if smode == M.MP_EXACT else "spmv_seq_us"] * 1e-6
@@ -430,7 +449,8 @@ def main():
                              "achieved_gbs": round(nbytes / tk / 1e9, 1),
                              "frac": round(nbytes / tk / 1e9 / HBM_PEAK_GBS, 4),
                              "algorithmic_bytes": nbytes, "traffic": load_traffic(sname),
-                             "mad_frac": round(A.nnz * L * L / tk / (PEAK_MAD_TOPS * 1e12), 4)}
+                             "mad_frac": round(A.nnz * L * L / tk / (PEAK_MAD_TOPS * 1e12), 4),
+                             "valu_issue_frac": valu_issue_frac(sname, tk * 1e6)}
     out = {
         "metric": "MP nonzeros/s for 256-bit MP-SpMV (+ % roofline); BiCG solve time, batched vs plain",
         "value": value,
