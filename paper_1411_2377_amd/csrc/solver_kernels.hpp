@@ -303,13 +303,13 @@ MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, in
   }
 }
 
-// The epilogue as one out-of-line function per precision (it is large and runs once per launch,
-// in one wavefront).  Only plain values cross the call, so no caller object needs an address.
+// The epilogue, once per launch in one wavefront.  Only plain values cross the call, so no
+// caller object needs an address.  BiCG's update step inlines it (which spares it the register
+// saves of a call); the others call the out-of-line copy below, which keeps their registers.
 template <int L>
-__device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb, int32_t* c_hdr,
-                                                      uint32_t* s_limb, int32_t* s_hdr, int64_t s_ld,
-                                                      Ctl* ctl, int iters, int maxit, int hist_len,
-                                                      uint32_t* h_limb, int32_t* h_hdr, int64_t h_ld) {
+MPD uint32_t epilogue_impl(int epi, uint32_t* c_limb, int32_t* c_hdr, uint32_t* s_limb, int32_t* s_hdr,
+                           int64_t s_ld, Ctl* ctl, int iters, int maxit, int hist_len, uint32_t* h_limb,
+                           int32_t* h_hdr, int64_t h_ld) {
   ScalarView<L> sv;
   sv.cl = c_limb;
   sv.ch = c_hdr;
@@ -321,6 +321,15 @@ __device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb
   uint32_t st = 0;
   epilogue_body<L>(epi, sv, ctl, iters, maxit, hist_len, hist, st);
   return st;
+}
+
+template <int L>
+__device__ __attribute__((noinline)) uint32_t epilogue(int epi, uint32_t* c_limb, int32_t* c_hdr,
+                                                      uint32_t* s_limb, int32_t* s_hdr, int64_t s_ld,
+                                                      Ctl* ctl, int iters, int maxit, int hist_len,
+                                                      uint32_t* h_limb, int32_t* h_hdr, int64_t h_ld) {
+  return epilogue_impl<L>(epi, c_limb, c_hdr, s_limb, s_hdr, s_ld, ctl, iters, maxit, hist_len, h_limb,
+                          h_hdr, h_ld);
 }
 
 // A step prologue, by every lane of one wavefront (independent operations run on different
@@ -842,7 +851,7 @@ MPD bool last_block(const DotWork& dw, int pair, unsigned idx, unsigned nblocks)
 
 // EPI: whether the kernel can run a driver epilogue (kernels that never do are compiled without
 // it, and keep their registers).
-template <int L, int NT, bool EPI = true>
+template <int L, int NT, bool EPI = true, bool EPI_INLINE = false>
 MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched, unsigned idx,
                      unsigned nblocks, Ctl* ctl, const Scalars& S, int32_t* ndone, uint32_t* status,
                      uint32_t st, int64_t* lds, int cap, const ProOut* pro = nullptr) {
@@ -971,8 +980,11 @@ MPD void dots_finish(const DotWork& dw, const DotOut& O, int pair, bool batched,
   lds_barrier();
   if constexpr (EPI) {
     if (wv == 0) {  // one wavefront
-      const uint32_t st2 = epilogue<L>(O.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, s_ctl[0], s_ctl[1],
-                                       s_ctl[2], O.hist.limb, O.hist.hdr, O.hist.ld);
+      const uint32_t st2 =
+          EPI_INLINE ? epilogue_impl<L>(O.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, s_ctl[0], s_ctl[1], s_ctl[2],
+                                        O.hist.limb, O.hist.hdr, O.hist.ld)
+                     : epilogue<L>(O.epi, s_cl, s_ch, S.limb, S.hdr, S.ld, ctl, s_ctl[0], s_ctl[1], s_ctl[2],
+                                   O.hist.limb, O.hist.hdr, O.hist.ld);
       if (t == 0) {
         if (st2) atomicOr(&ctl->flags, st2);
         // the solve was running when the launch began (its blocks run only then)
@@ -1419,8 +1431,8 @@ __global__ void __launch_bounds__(256) bicg_update_kernel(VecArgs A) {
     pass_dot<L, 256>(lds, ok, hr, hr, r.m, r.m, A.dots, c.abase + A.fd.slot[0]);
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  dots_finish<L, 256, !SEP>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
-                      A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
+  dots_finish<L, 256, !SEP, true>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl,
+                                  c.S, A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
 // GPBiCG direction: v = {p, w, r, v, q, u}.  First iteration p = r; then
