@@ -304,8 +304,9 @@ MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, in
 }
 
 // The epilogue, once per launch in one wavefront.  Only plain values cross the call, so no
-// caller object needs an address.  BiCG's update step inlines it (which spares it the register
-// saves of a call); the others call the out-of-line copy below, which keeps their registers.
+// caller object needs an address.  The update steps of BiCG and GPBiCG inline it (which spares
+// them the register saves of a call); the others call the out-of-line copy below, which keeps
+// their registers.
 template <int L>
 MPD uint32_t epilogue_impl(int epi, uint32_t* c_limb, int32_t* c_hdr, uint32_t* s_limb, int32_t* s_hdr,
                            int64_t s_ld, Ctl* ctl, int iters, int maxit, int hist_len, uint32_t* h_limb,
@@ -1565,7 +1566,7 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
     pass_dot<L, 256>(lds, ok, hr, hr, rn.m, rn.m, A.dots, c.abase + A.fd.slot[0]);
     pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, rn.m, A.dots, c.abase + A.fd.slot[1]);
   }
-  dots_finish<L, 256, !SEP>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
+  dots_finish<L, 256, !SEP, true>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
                       A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
