@@ -1,29 +1,36 @@
-"""Benchmark: multiple-precision SpMV + BiCG/GPBiCG on one MI355X.
+"""Benchmark: multiple-precision sparse matrix-vector products on one MI355X (the method of
+Kouya, arXiv 1411.2377: y = A x over CSR with every operation rounded to nearest at p bits).
 
-Workload (the step): the nonsymmetric 2-D convection-diffusion operator, 5-point central
-differences on a 256 x 256 grid (n = 65536, nnz = 326656, global Peclet number 10), p = 256 bits,
-right-hand side b = A * ones formed in EXACT mode, x0 = 0.  Synthetic (seeded) data; nothing is
-read from disk.  A plan is built once (transpose, kernel variants tuned on this matrix).
+Headline workload: the power-law matrix, n = 500000 rows and columns, row lengths from a
+truncated power law (mean 20, longest row 2000), 9,932,151 stored entries, values log-uniform in
+magnitude over 1e-8..1e8 with random signs, x uniform on [-1, 1], p = 256 bits (8 limbs);
+seeded synthetic data, generated on the host and resident in HBM before timing.  A plan is built
+and its kernel variants tuned (or read from a tuning cache, --tune-cache).
 
-One step = one pass of the whole hot path on that matrix:
-  * y = A x and y = A^T x in SEQ and in EXACT mode, and the value gradient RN(g_i x_j);
-  * 200 BiCG iterations in SEQ mode and 200 in EXACT mode (2 products per iteration: A, A^T);
-  * 200 GPBiCG iterations in SEQ mode and 200 in EXACT mode (2 products with A per iteration).
-The stopping tolerance is set below what 200 iterations reach, so every solve runs all 200
-iterations (status NC) and the work per step is fixed.
+One step = y = A x in SEQ mode (per-operation rounding in column order) and y = A x in EXACT
+mode (exact sum, one rounding): the two accumulation modes of the product.
+value = MP non-zeros per second = 2 x stored entries / step time.
 
-value = MP non-zeros per second = (stored entries x number of sparse products in a step) /
-step time.  `roofline` reports the kernel with the largest share of the step, timed live: one solve per
-solver and mode runs with every iteration kernel bracketed by HIP events on the solver's stream
-(eager launches, identical results); achieved = algorithmic bytes of those launches (vectors
-read and written once; for a sparse product the matrix once, x and y once, the row pointers) /
-their summed durations, against HBM bandwidth.  `components.spmv_roofline` gives the same for
-the step's SpMV kernel timed alone.
-`components` adds per-kernel times, the solver times, the power-law SpMV workload (n = 500000,
-~9.9M stored entries, p = 256) with its roofline fractions, and optionally (--batched) the
-batched-vs-plain GPBiCG comparison.  `cpu_baseline` times the oracle on the host's cores.
+`roofline` describes the step's dominant kernel (the mode whose kernel takes longer): its
+average launch duration comes from HIP events attached to the kernel launches themselves during
+the timed steps (mp_timer_*, on the launch stream); achieved = algorithmic bytes per launch (the
+matrix entries once: 4L + 8 bytes each; x and y once: 4L + 4 bytes per element; the row
+pointers) / that duration, against the 8 TB/s HBM peak.  `mad_frac` gives the same launch
+against the limb-product peak (L^2 32x32->64 multiply-adds per entry at 19.66 T/s).
+
+`components`: both modes at p = 128, 256 and 512 with their variants, the transposed product
+and value gradient (the autograd backward), cold-cache launches (after a 1 GiB write), 200
+BiCG / GPBiCG iterations per mode on the 256 x 256 convection-diffusion operator with their
+per-kernel profile, and batched GPBiCG on 64 banded systems x 16 right-hand sides against plain
+solves.  `cpu_baseline` times the oracle on a bounded sample of the headline workload's rows.
+
+Other uses:
+  --profile-pass powerlaw|convdiff   launches for a rocprofv3 counter pass only
+  --summarize-stats FILE             text summary of a rocprofv3 *_kernel_stats.csv
+  --summarize-counters DIR DIR       traffic summary of a FETCH_SIZE and a WRITE_SIZE pass
 """
 import argparse
+import glob
 import hashlib
 import json
 import multiprocessing as mproc
@@ -34,8 +41,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-GRID = 256
 PREC = 256
+GRID = 256
 ITERS = 200
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3 T lane-ops/s for full-rate integer VALU
 # instructions; v_mad_u64_u32 (the 32x32->64 limb product) issues at half that rate (measured
@@ -46,19 +53,25 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("spmv_kernels.hpp", "solver_kernels.hpp", "mp_core.hpp", "mp_exact.hpp",
                   "mp_scalar.hpp")
+WORKLOAD = ("power-law CSR n=500000 (row lengths mean 20, max 2000; 9932151 stored entries), "
+            "values log-uniform 1e-8..1e8 with random sign, x uniform [-1,1], p=256; "
+            "step = y = A x in SEQ mode + y = A x in EXACT mode")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-powerlaw", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also time batched vs plain GPBiCG")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed steps (for a kernel-trace profile of the same command)")
+    ap.add_argument("--tune-cache", default="", help="tuning cache file (mp_plan_tune_cached)")
+    ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--profile-pass", default="",
-                    help="counter pass only: 'convdiff' or 'powerlaw' (copy calibration + SpMV launches)")
+                    help="counter pass only: 'powerlaw' or 'convdiff' (copy calibration + launches)")
+    ap.add_argument("--summarize-stats", default="")
+    ap.add_argument("--summarize-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))
     return ap.parse_args()
 
 
@@ -76,71 +89,9 @@ def spmv_bytes(n_rows, n_cols, nnz, L):
     return nnz * (4 * L + 8) + (n_rows + n_cols) * (4 * L + 4) + 4 * (n_rows + 1)
 
 
-def build_problem(M, torch):
-    import numpy as np
-    import synth
-    A_h, ones_h = synth.config2(p=PREC, m=GRID)
-    A = M.CSRMatrix.from_host(A_h)
-    ones = M.MPArray.from_host(ones_h)
-    b = M.mpspmv_csr(A, ones, mode=M.MP_EXACT)
-    rng = np.random.default_rng(0)
-    x = M.MPArray.from_host(synth.mp_uniform(rng, A_h.n_cols, PREC))
-    g = M.MPArray.from_host(synth.mp_uniform(rng, A_h.n_rows, PREC))
-    plan = M.mp_plan_create(A)
-    plan.tune()
-    torch.cuda.synchronize()
-    return A_h, A, b, x, g, plan
-
-
-def one_step(M, A, b, x, g, plan, bufs):
-    y, yt, gv = bufs
-    nprod = 0
-    for mode in (M.MP_SEQ, M.MP_EXACT):
-        M.mpspmv_csr(A, x, y, mode=mode, plan=plan)
-        M.mpspmv_csr_t(A, plan, g, yt, mode=mode)
-        nprod += 2
-    M.mp_grad_vals(A, plan, g, x, gv)
-    infos = []
-    for solver in (M.bicg, M.gpbicg):
-        for mode in (M.MP_SEQ, M.MP_EXACT):
-            _, info = solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0),
-                             chunk=25)
-            infos.append(info)
-            nprod += 2 * info.iters
-    return nprod, infos
-
-
-def time_kernel(torch, fn, reps):
-    """Average duration of one launch: `reps` launches captured in a graph, replayed between
-    two events on the capturing stream."""
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        for _ in range(3):
-            fn()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=s):
-        for _ in range(reps):
-            fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(s):
-        g.replay()
-        torch.cuda.synchronize()
-        e0.record(s)
-        for _ in range(3):
-            g.replay()
-        e1.record(s)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / (3 * reps) * 1e-3   # seconds per launch
-
-
 def spmv_symbol(plan, op, mode, L, fused=False):
-    """The kernel symbol (as rocprofv3 names it, without "void mp::" and the arguments) of the
-    plan's variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation,
-    which ends with the inner products of its output."""
+    """The kernel symbol (rocprofv3's name without "void mp::" and the arguments) of the plan's
+    variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation."""
     rows, staged, srt = plan.variants()[(op, mode)]
     base = "spmv_exact_kernel" if mode else ("spmv_seq_sorted_kernel" if srt else "spmv_seq_kernel")
     return "%s<%d, %d, %s>" % (base, L, rows, "true" if fused else "false")
@@ -166,53 +117,202 @@ def load_counters(kernel):
 
 
 def load_traffic(kernel):
-    """HBM traffic per launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE, each
-    scaled by the plain-copy calibration), or None."""
     ent = load_counters(kernel)
     return None if ent is None else ent["fetch_bytes"] + ent["write_bytes"]
 
 
 def valu_issue_frac(kernel, launch_us):
-    """VALU instructions per launch from the committed counter summary over the VALU issue
-    slots of a launch of the live duration, or None."""
     ent = load_counters(kernel)
     if ent is None or not ent.get("valu_instr"):
         return None
     return round(ent["valu_instr"] / (launch_us * 1e-6 * VALU_ISSUE_PEAK), 4)
 
 
-def powerlaw_component(M, torch, reps):
-    """The power-law workload (n = 500000, mean 20 and max 2000 entries per row, values
-    log-uniform over 1e-8..1e8, x uniform on [-1, 1]) at p = 256: y = A x and A^T g in both
-    modes with the tuned plan."""
+def roofline_entry(kernel, launch_us, nbytes, nnz, L):
+    return {"bound": "hbm", "achieved": round(nbytes / (launch_us * 1e-6) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(nbytes / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(kernel), "kernel": kernel, "launch_us": round(launch_us, 2),
+            "algorithmic_bytes_per_launch": nbytes,
+            "mad_frac": round(nnz * L * L / (launch_us * 1e-6) / (PEAK_MAD_TOPS * 1e12), 4),
+            "valu_issue_frac": valu_issue_frac(kernel, launch_us)}
+
+
+# ---------------------------------------------------------------------------------------------
+# CPU baseline: the oracle on sampled rows of the headline workload (forked before the GPU is
+# touched)
+# ---------------------------------------------------------------------------------------------
+_CPU_PAYLOAD = {}
+
+
+def _oracle_rows(args):
+    rows, mode = args
+    from oracle import codec, spmv as ospmv
+    A_h, x_h = _CPU_PAYLOAD["A"], _CPU_PAYLOAD["x"]
+    p = A_h.vals.p
+    rp = A_h.row_ptr
+    ks = [k for i in rows for k in range(int(rp[i]), int(rp[i + 1]))]
+    sub_rp = [0]
+    for i in rows:
+        sub_rp.append(sub_rp[-1] + int(rp[i + 1] - rp[i]))
+    cols = A_h.col_idx[ks]
+    vals = codec.decode(A_h.vals.limbs[:, ks], A_h.vals.hdr[ks], p)
+    uc = sorted(set(int(c) for c in cols))
+    xs = dict(zip(uc, codec.decode(x_h.limbs[:, uc], x_h.hdr[uc], p)))
+    t0 = time.time()
+    ospmv.spmv(sub_rp, cols.tolist(), vals, xs, p, mode)
+    return len(ks), time.time() - t0
+
+
+def cpu_baseline(A_h, x_h, budget_s=12.0):
+    """The oracle (pure-Python big integers) on the host's cores: rows drawn uniformly at random
+    (seeded) from the headline matrix, each block of rows computed in SEQ and in EXACT mode, in a
+    process pool, until about budget_s seconds have passed."""
+    import numpy as np
+    cores = min(16, os.cpu_count() or 1)
+    _CPU_PAYLOAD["A"], _CPU_PAYLOAD["x"] = A_h, x_h
+    rng = np.random.default_rng(0)
+    ctx = mproc.get_context("fork")
+    done_entries = 0
+    done_rows = 0
+    t0 = time.time()
+    with ctx.Pool(cores) as pool:
+        while time.time() - t0 < budget_s:
+            blocks = [rng.integers(0, A_h.n_rows, 400) for _ in range(cores)]
+            for n_ent, _ in pool.map(_oracle_rows, [(b, m) for b in blocks for m in (0, 1)]):
+                done_entries += n_ent
+            done_rows += 400 * cores
+    dt = time.time() - t0
+    return {"value": done_entries / dt, "unit": "MP nnz/s", "cores": cores, "kind": "oracle",
+            "sample": "%d rows drawn uniformly (seeded) from the headline matrix, each in SEQ and in "
+                      "EXACT mode (%d products of stored entries, p=256), rows split over %d "
+                      "processes, %.1f s wall" % (done_rows, done_entries, cores, dt)}
+
+
+# ---------------------------------------------------------------------------------------------
+# GPU parts
+# ---------------------------------------------------------------------------------------------
+def upload_config3(M, p, tune_cache=""):
     import synth
-    A_h, x_h, g_h = synth.config3(p=PREC)
+    A_h, x_h, g_h = synth.config3(p=p)
     A = M.CSRMatrix.from_host(A_h)
     x = M.MPArray.from_host(x_h)
     g = M.MPArray.from_host(g_h)
-    y = M.MPArray.empty(A.n_rows, PREC)
-    yt = M.MPArray.empty(A.n_cols, PREC)
+    plan = M.mp_plan_create(A)
+    plan.tune(cache=tune_cache or None)
+    return A_h, A, x, g, plan
+
+
+def timed_launches(M, torch, fn, reps, cold=None):
+    """Average kernel duration (us) of fn's main kernel over reps launches (kernel timer)."""
+    tm = M.KernelTimer(reps + 4)
+    for _ in range(reps):
+        if cold is not None:
+            cold.add_(1)      # 1 GiB written between launches: nothing of the operands in cache
+        tm.select()
+        fn()
+        M.KernelTimer.deselect()
+    us, n = tm.read()
+    tm.close()
+    return us / max(1, n)
+
+
+def precision_component(M, torch, p, reps, data=None, tune_cache=""):
+    """Both modes of y = A x, A^T g and the value gradient on the power-law matrix at p bits."""
+    A_h, A, x, g, plan = data if data is not None else upload_config3(M, p, tune_cache)
+    L = p // 32
+    y = M.MPArray.empty(A.n_rows, p)
+    yt = M.MPArray.empty(A.n_cols, p)
+    nb = spmv_bytes(A.n_rows, A.n_cols, A.nnz, L)
+    out = {"nnz": A.nnz}
+    for mode, mname in ((M.MP_SEQ, "seq"), (M.MP_EXACT, "exact")):
+        t = timed_launches(M, torch, lambda: M.mpspmv_csr(A, x, y, mode=mode, plan=plan), reps)
+        tt = timed_launches(M, torch, lambda: M.mpspmv_csr_t(A, plan, g, yt, mode=mode), reps)
+        out[mname] = {"kernel": spmv_kernel_name(plan, 0, mode, L), "kernel_us": round(t, 1),
+                      "nnz_per_s": A.nnz / (t * 1e-6),
+                      "hbm_frac": round(nb / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                      "mad_frac": round(A.nnz * L * L / (t * 1e-6) / (PEAK_MAD_TOPS * 1e12), 4),
+                      "transposed_kernel": spmv_kernel_name(plan, 1, mode, L),
+                      "transposed_us": round(tt, 1), "transposed_nnz_per_s": A.nnz / (tt * 1e-6)}
+    gv = M.MPArray.empty(A.nnz, p)
+    tg = timed_launches(M, torch, lambda: M.mp_grad_vals(A, plan, g, x, gv), reps)
+    out["grad_vals_us"] = round(tg, 1)
+    M.mp_status()
+    return out
+
+
+def cold_component(M, torch, data, reps):
+    """Kernel durations with a 1 GiB write before every launch (MALL and L2 hold nothing of the
+    operands)."""
+    A_h, A, x, g, plan = data
+    y = M.MPArray.empty(A.n_rows, A.p)
+    L = A.p // 32
+    cold = torch.zeros(256 << 20, dtype=torch.int32, device="cuda")
+    nb = spmv_bytes(A.n_rows, A.n_cols, A.nnz, L)
+    out = {}
+    for mode, mname in ((M.MP_SEQ, "seq"), (M.MP_EXACT, "exact")):
+        t = timed_launches(M, torch, lambda: M.mpspmv_csr(A, x, y, mode=mode, plan=plan), reps, cold)
+        out[mname] = {"kernel_us": round(t, 1), "nnz_per_s": A.nnz / (t * 1e-6),
+                      "hbm_frac": round(nb / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    del cold
+    return out
+
+
+def solver_component(M, torch):
+    """200 BiCG and 200 GPBiCG iterations per mode on the 2-D convection-diffusion operator
+    (256 x 256, Peclet 10, p = 256, b = A * ones in EXACT mode), with the per-kernel profile of
+    one eager solve per solver and mode."""
+    import synth
+    A_h, ones_h = synth.config2(p=PREC, m=GRID)
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.mpspmv_csr(A, M.MPArray.from_host(ones_h), mode=M.MP_EXACT)
     plan = M.mp_plan_create(A)
     plan.tune()
     L = PREC // 32
-    out = {"workload": "power-law rows n=500000 nnz=%d p=256" % A.nnz}
-    for mode, mname in ((M.MP_SEQ, "seq"), (M.MP_EXACT, "exact")):
-        t = time_kernel(torch, lambda: M.mpspmv_csr(A, x, y, mode=mode, plan=plan), reps)
-        tt = time_kernel(torch, lambda: M.mpspmv_csr_t(A, plan, g, yt, mode=mode), reps)
-        by = spmv_bytes(A.n_rows, A.n_cols, A.nnz, L)
-        out[mname] = {"spmv_us": round(t * 1e6, 1), "spmv_nnz_per_s": A.nnz / t,
-                      "spmv_t_us": round(tt * 1e6, 1), "spmv_t_nnz_per_s": A.nnz / tt,
-                      "hbm_frac": round(by / t / (HBM_PEAK_GBS * 1e9), 4),
-                      "mad_frac": round(A.nnz * L * L / t / (PEAK_MAD_TOPS * 1e12), 4),
-                      "variant": spmv_kernel_name(plan, 0, mode, L)}
+    out = {"workload": "2-D convection-diffusion 5-point 256x256 (n=65536, nnz=326656), Peclet 10, "
+                       "p=256, b = A*ones; %d iterations (tolerance below reach)" % ITERS}
+    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg)):
+        for mname, mode in (("seq", M.MP_SEQ), ("exact", M.MP_EXACT)):
+            solver(A, b, plan=plan, mode=mode, maxit=5, rtol=(1, -70), atol=(0, 0), chunk=25)
+            torch.cuda.synchronize()
+            t1 = time.time()
+            _, info = solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0),
+                             chunk=25)
+            torch.cuda.synchronize()
+            dt = time.time() - t1
+            out["%s_%s" % (sname, mname)] = {"ms": round(dt * 1e3, 2),
+                                             "us_per_iter": round(dt * 1e6 / max(1, info.iters), 1),
+                                             "status": info.status, "iters": info.iters}
+    cand = {}
+    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg)):
+        for mode in (M.MP_SEQ, M.MP_EXACT):
+            pr = M.SolveProfile()
+            solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0), profile=pr)
+            names = {0: spmv_kernel_name(plan, 0, mode, L, fused=True),
+                     1: spmv_kernel_name(plan, 1, mode, L),
+                     2: "%s_dir_kernel<%d>" % ("bicg" if sname == "bicg" else "gp", L),
+                     3: "%s_update_kernel<%d, false>" % ("bicg" if sname == "bicg" else "gp", L),
+                     4: "gp_tsy_kernel<%d, false>" % L}
+            for cls, kn in names.items():
+                if pr.launches[cls] == 0:
+                    continue
+                e = cand.setdefault(kn, [0.0, 0, 0.0])
+                e[0] += pr.us[cls]
+                e[1] += pr.launches[cls]
+                e[2] += pr.bytes[cls]
+    out["kernels"] = {k: {"total_us": round(v[0], 1), "launches": v[1],
+                          "avg_us": round(v[0] / max(1, v[1]), 2),
+                          "hbm_frac": round(v[2] / (v[0] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                      for k, v in cand.items()}
     M.mp_status()
     return out
 
 
 def batched_component(M, torch):
     """Batched GPBiCG on the banded workload (64 systems of 1000..100000 unknowns, bandwidths
-    7..41, 16 right-hand sides each, p = 256, relative residual 1e-60) against plain solves of
-    a sample of the same (system, right-hand side) pairs, extrapolated to all of them."""
+    7..41, 16 right-hand sides each, p = 256, SEQ products, relative residual 1e-60) against
+    plain solves: one right-hand side of every system solved alone (bit-identity checked), the
+    plain time of each system taken 16 times."""
     import numpy as np
     import synth
     systems = synth.config4(p=PREC)
@@ -229,228 +329,111 @@ def batched_component(M, torch):
     t_batched = time.time() - t0
     iters = [i.iters for row in infos for i in row]
     statuses = sorted({i.status for row in infos for i in row})
+    nrhs = len(bs[0])
     rng = np.random.default_rng(0)
-    sample = [(int(s), int(rng.integers(0, len(bs[0])))) for s in rng.choice(len(As), 8, replace=False)]
     t_plain, same = 0.0, True
-    for s, k in sample:
+    for s in range(len(As)):
+        k = int(rng.integers(0, nrhs))
         t1 = time.time()
         xp, ip = M.gpbicg(As[s], bs[s][k], **opts)
         torch.cuda.synchronize()
-        t_plain += time.time() - t1
+        t_plain += (time.time() - t1) * nrhs
         same &= (ip.iters == infos[s][k].iters) and bool(
             torch.equal(xp.limbs, xs[s][k].limbs) and torch.equal(xp.hdr, xs[s][k].hdr))
-    n_pairs = len(As) * len(bs[0])
-    return {"workload": "64 banded systems n=1000..100000, 16 rhs each, p=256, GPBiCG to 1e-60",
-            "batched_s": round(t_batched, 3), "plain_s_estimated": round(t_plain / len(sample) * n_pairs, 2),
-            "plain_sample_pairs": len(sample), "speedup": round(t_plain / len(sample) * n_pairs / t_batched, 1),
+    return {"workload": "64 banded systems n=1000..100000 (sum 1405456), 16 rhs each, p=256, "
+                        "GPBiCG (SEQ products) to relative residual 1e-60",
+            "batched_s": round(t_batched, 3), "plain_s": round(t_plain, 2),
+            "plain_method": "one right-hand side of each of the 64 systems solved alone, times 16",
+            "speedup": round(t_plain / t_batched, 1),
             "iters_min_max": [min(iters), max(iters)], "statuses": statuses,
-            "sample_bit_identical": same}
+            "plain_bit_identical": same}
 
 
-_CPU_PAYLOAD = {}
-
-
-def _oracle_rows(args):
-    """Oracle y_i for a block of rows (runs in a pool worker; the matrix is inherited)."""
-    rows, mode = args
-    from oracle import codec, spmv as ospmv
-    A_h, x_h = _CPU_PAYLOAD["A"], _CPU_PAYLOAD["x"]
-    p = A_h.vals.p
-    rp = A_h.row_ptr
-    ks = [k for i in rows for k in range(int(rp[i]), int(rp[i + 1]))]
-    sub_rp = [0]
-    for i in rows:
-        sub_rp.append(sub_rp[-1] + int(rp[i + 1] - rp[i]))
-    cols = A_h.col_idx[ks]
-    vals = codec.decode(A_h.vals.limbs[:, ks], A_h.vals.hdr[ks], p)
-    uc = sorted(set(int(c) for c in cols))
-    xs = dict(zip(uc, codec.decode(x_h.limbs[:, uc], x_h.hdr[uc], p)))
-    return len(ospmv.spmv(sub_rp, cols.tolist(), vals, xs, p, mode))
-
-
-def cpu_baseline():
-    """The oracle (pure-Python big integers) on the host's cores: one full y = A x in SEQ mode
-    and one in EXACT mode, rows split into blocks over a process pool (run before the GPU is
-    touched)."""
-    import numpy as np
-    import synth
-    A_h, _ = synth.config2(p=PREC, m=GRID)
-    cores = min(16, os.cpu_count() or 1)
-    rng = np.random.default_rng(0)
-    _CPU_PAYLOAD["A"] = A_h
-    _CPU_PAYLOAD["x"] = synth.mp_uniform(rng, A_h.n_cols, PREC)
-    blocks = np.array_split(np.arange(A_h.n_rows), cores * 4)
-    ctx = mproc.get_context("fork")
+def headline(M, torch, args, data):
+    """The timed steps: y = A x in SEQ and in EXACT mode per step, kernel durations from events
+    attached to the two product kernels."""
+    A_h, A, x, g, plan = data
+    L = PREC // 32
+    y_seq = M.MPArray.empty(A.n_rows, PREC)
+    y_ex = M.MPArray.empty(A.n_rows, PREC)
+    t_seq = M.KernelTimer(args.steps + 8)
+    t_ex = M.KernelTimer(args.steps + 8)
+    for _ in range(args.warmup):
+        M.mpspmv_csr(A, x, y_seq, mode=M.MP_SEQ, plan=plan)
+        M.mpspmv_csr(A, x, y_ex, mode=M.MP_EXACT, plan=plan)
+    torch.cuda.synchronize()
     t0 = time.time()
-    reps = 0
-    with ctx.Pool(cores) as pool:   # whole products until about 10 s have passed
-        while reps < 2 or time.time() - t0 < 10.0:
-            for mode in (0, 1):
-                pool.map(_oracle_rows, [(blk, mode) for blk in blocks])
-            reps += 1
+    for _ in range(args.steps):
+        t_seq.select()
+        M.mpspmv_csr(A, x, y_seq, mode=M.MP_SEQ, plan=plan)
+        t_ex.select()
+        M.mpspmv_csr(A, x, y_ex, mode=M.MP_EXACT, plan=plan)
+        M.KernelTimer.deselect()
+    torch.cuda.synchronize()
     dt = time.time() - t0
-    return {"value": 2 * reps * A_h.nnz / dt, "unit": "MP nnz/s", "cores": cores, "kind": "oracle",
-            "sample": "%d x (one full y = A x in SEQ and one in EXACT mode) on the 256x256 matrix "
-                      "at p=256 (%d products), rows split over %d processes, %.1f s wall"
-                      % (reps, 2 * reps * A_h.nnz, cores, dt)}
-
-
-def profile_pass(M, torch, which):
-    """Launches for a counter run: a plain copy of 256 MiB (the counters' calibration), then ten
-    launches of each tuned SpMV kernel of the chosen workload and, for the step's workload, 20
-    iterations of each solve of the step."""
-    src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    if which == "powerlaw":
-        import synth
-        A_h, x_h, g_h = synth.config3(p=PREC)
-        A = M.CSRMatrix.from_host(A_h)
-        x = M.MPArray.from_host(x_h)
-        plan = M.mp_plan_create(A)
-        plan.tune()
-    else:
-        A_h, A, b, x, g, plan = build_problem(M, torch)
-    y = M.MPArray.empty(A.n_rows, PREC)
-    names = {}
-    for mode in (M.MP_SEQ, M.MP_EXACT):
-        names[mode] = spmv_kernel_name(plan, 0, mode, PREC // 32)
-        names["fused_%d" % mode] = spmv_kernel_name(plan, 0, mode, PREC // 32, fused=True)
-        for _ in range(10):
-            M.mpspmv_csr(A, x, y, mode=mode, plan=plan)
-    if which != "powerlaw":   # the step's solver kernels in their step proportions (20 iterations)
-        for solver in (M.bicg, M.gpbicg):
-            for mode in (M.MP_SEQ, M.MP_EXACT):
-                solver(A, b, plan=plan, mode=mode, maxit=20, rtol=(1, -70), atol=(0, 0), chunk=0)
-        # then a few iterations with every variant of the solvers' SpMV instantiations, so that
-        # each of their symbols has counters whichever variant a tuning run picks
-        tuned = plan.variants()
-        for mode in (M.MP_SEQ, M.MP_EXACT):
-            for rows in (16, 32, 64):
-                for srt in ((False, True) if mode == M.MP_SEQ else (False,)):
-                    plan.set_variant(0, mode, rows=rows, stage_x=False, sorted_rows=srt)
-                    for solver in (M.bicg, M.gpbicg):
-                        solver(A, b, plan=plan, mode=mode, maxit=5, rtol=(1, -70), atol=(0, 0),
-                               chunk=0)
-            r, st, so = tuned[(0, mode)]
-            plan.set_variant(0, mode, rows=r, stage_x=st, sorted_rows=so)
-    torch.cuda.synchronize()
-    print(json.dumps({"profile_pass": which, "variants": names, "kernel_source": kernel_source_hash(),
-                      "copy_bytes": src.numel() * 4, "n_rows": A.n_rows, "n_cols": A.n_cols,
-                      "nnz": A.nnz}))
+    M.mp_status()
+    us_seq, n_seq = t_seq.read()
+    us_ex, n_ex = t_ex.read()
+    k_seq, k_ex = us_seq / n_seq, us_ex / n_ex
+    nb = spmv_bytes(A.n_rows, A.n_cols, A.nnz, L)
+    dom_mode = M.MP_SEQ if k_seq >= k_ex else M.MP_EXACT
+    roof = roofline_entry(spmv_kernel_name(plan, 0, dom_mode, L), max(k_seq, k_ex), nb, A.nnz, L)
+    roof["launches"] = n_seq if dom_mode == M.MP_SEQ else n_ex
+    modes = {}
+    for mode, mname, k in ((M.MP_SEQ, "seq", k_seq), (M.MP_EXACT, "exact", k_ex)):
+        e = roofline_entry(spmv_kernel_name(plan, 0, mode, L), k, nb, A.nnz, L)
+        e["nnz_per_s"] = A.nnz / (k * 1e-6)
+        modes[mname] = e
+    return dt, roof, modes
 
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is a single-device kernel set and no "
               "multi-GPU run is part of this build (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    import synth
+    A_h, x_h, g_h = synth.config3(p=PREC)
     cpu = None
-    if not args.no_cpu_baseline and not args.profile_pass:
-        cpu = cpu_baseline()
+    if not args.no_cpu_baseline and not args.profile_pass and not args.headline_only:
+        cpu = cpu_baseline(A_h, x_h)
     import torch
     import paper_1411_2377_amd as M
     torch.cuda.set_device(0)
     if args.profile_pass:
-        profile_pass(M, torch, args.profile_pass)
+        profile_pass(M, torch, args.profile_pass, args)
         return
-    A_h, A, b, x, g, plan = build_problem(M, torch)
-    y = M.MPArray.empty(A.n_rows, PREC)
-    yt = M.MPArray.empty(A.n_cols, PREC)
-    gv = M.MPArray.empty(A.nnz, PREC)
-    bufs = (y, yt, gv)
-    dres = M.MPArray.empty(1, PREC)
-    for _ in range(args.warmup):
-        one_step(M, A, b, x, g, plan, bufs)
+    A = M.CSRMatrix.from_host(A_h)
+    x = M.MPArray.from_host(x_h)
+    g = M.MPArray.from_host(g_h)
+    plan = M.mp_plan_create(A)
+    plan.tune(cache=args.tune_cache or None)
     torch.cuda.synchronize()
-    t0 = time.time()
-    total = 0
-    for _ in range(args.steps):
-        nprod, infos = one_step(M, A, b, x, g, plan, bufs)
-        total += nprod
-    torch.cuda.synchronize()
-    dt = time.time() - t0
-    M.mp_status()
-    ms_step = dt / args.steps * 1e3
-    value = total * A.nnz / dt
-
-    # per-component times (one extra pass, events around each part)
-    comp = {}
-    L = PREC // 32
-    for name, fn in (
-        ("spmv_seq_us", lambda: M.mpspmv_csr(A, x, y, mode=M.MP_SEQ, plan=plan)),
-        ("spmv_exact_us", lambda: M.mpspmv_csr(A, x, y, mode=M.MP_EXACT, plan=plan)),
-        ("spmv_t_seq_us", lambda: M.mpspmv_csr_t(A, plan, g, yt, mode=M.MP_SEQ)),
-        ("spmv_t_exact_us", lambda: M.mpspmv_csr_t(A, plan, g, yt, mode=M.MP_EXACT)),
-        ("grad_vals_us", lambda: M.mp_grad_vals(A, plan, g, x, gv)),
-        ("dot_us", lambda: M.mp_dot(x, g, dres)),
-    ):
-        comp[name] = round(time_kernel(torch, fn, args.kernel_reps) * 1e6, 2)
-    comp["variants"] = {"%s_%s" % ("A" if op == 0 else "At", "seq" if m == 0 else "exact"): v
-                        for (op, m), v in plan.variants().items()}
-    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg)):
-        for mname, mode in (("seq", M.MP_SEQ), ("exact", M.MP_EXACT)):
-            torch.cuda.synchronize()
-            t1 = time.time()
-            _, info = solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0),
-                             chunk=25)
-            torch.cuda.synchronize()
-            comp["%s_%s_ms_per_%d_it" % (sname, mname, ITERS)] = round((time.time() - t1) * 1e3, 2)
-            comp["%s_%s_status_iters" % (sname, mname)] = [info.status, info.iters]
-    if not args.no_powerlaw:
-        comp["powerlaw_spmv"] = powerlaw_component(M, torch, max(3, args.kernel_reps // 10))
-    if args.batched:
+    data = (A_h, A, x, g, plan)
+    dt, roof, modes = headline(M, torch, args, data)
+    value = 2 * A.nnz * args.steps / dt
+    comp = {"modes": modes, "variants": {"%s_%s" % ("A" if op == 0 else "At", "seq" if m == 0 else "exact"): v
+                                         for (op, m), v in plan.variants().items()},
+            "tune_cache_hit": getattr(plan, "cache_hit", False)}
+    if not args.headline_only:
+        reps = args.kernel_reps
+        comp["p256"] = precision_component(M, torch, PREC, reps, data)
+        comp["cold_cache_p256"] = cold_component(M, torch, data, max(3, reps // 2))
+        del data, A, x, g, plan
+        torch.cuda.empty_cache()
+        for p in (128, 512):
+            comp["p%d" % p] = precision_component(M, torch, p, reps, tune_cache=args.tune_cache)
+            torch.cuda.empty_cache()
+        comp["solvers_convdiff256"] = solver_component(M, torch)
         comp["batched_gpbicg"] = batched_component(M, torch)
-
-    # Kernel times of the step's solves, live: every iteration kernel of one solve per solver
-    # and mode bracketed by HIP events on the solver's stream (eager launches, same results).
-    prof = {}
-    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg)):
-        for mode in (M.MP_SEQ, M.MP_EXACT):
-            pr = M.SolveProfile()
-            solver(A, b, plan=plan, mode=mode, maxit=ITERS, rtol=(1, -70), atol=(0, 0), profile=pr)
-            prof[(sname, mode)] = pr
-    # per kernel symbol: the sparse products that form the step's inner products (one symbol per
-    # mode, the tuned variant of A x in its solver instantiation), BiCG's A^T products, and each
-    # element-wise step (directions, updates, GPBiCG's t/s/y)
-    cand = {}
-    for (sname, mode), pr in prof.items():
-        names = {0: spmv_kernel_name(plan, 0, mode, L, fused=True),
-                 1: spmv_kernel_name(plan, 1, mode, L),
-                 2: "%s_dir_kernel<%d>" % ("bicg" if sname == "bicg" else "gp", L),
-                 3: "%s_update_kernel<%d, false>" % ("bicg" if sname == "bicg" else "gp", L),
-                 4: "gp_tsy_kernel<%d, false>" % L}
-        for cls, kn in names.items():
-            if pr.launches[cls] == 0:
-                continue
-            e = cand.setdefault(kn, [0.0, 0, 0.0])
-            e[0] += pr.us[cls]; e[1] += pr.launches[cls]; e[2] += pr.bytes[cls]
-    comp["solver_kernels"] = {k: {"total_us": round(v[0], 1), "launches": v[1],
-                                  "avg_us": round(v[0] / max(1, v[1]), 2)} for k, v in cand.items()}
-    kname = max(cand, key=lambda k: cand[k][0])
-    tot_us, nl, nb = cand[kname]
-    achieved = nb / (tot_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(kname), "kernel": kname,
-                "launch_us": round(tot_us / max(1, nl), 2), "launches": nl,
-                "algorithmic_bytes_per_launch": round(nb / max(1, nl)),
-                "valu_issue_frac": valu_issue_frac(kname, tot_us / max(1, nl))}
-    # the sparse product of the step alone (its roofline beside the dominant kernel's)
-    smode = M.MP_EXACT if comp["spmv_exact_us"] >= comp["spmv_seq_us"] else M.MP_SEQ
-    tk = comp["spmv_exact_us" if smode == M.MP_EXACT else "spmv_seq_us"] * 1e-6
-    sname = spmv_kernel_name(plan, 0, smode, L)
-    nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, L)
-    comp["spmv_roofline"] = {"kernel": sname, "launch_us": round(tk * 1e6, 2), "bound": "hbm",
-                             "achieved_gbs": round(nbytes / tk / 1e9, 1),
-                             "frac": round(nbytes / tk / 1e9 / HBM_PEAK_GBS, 4),
-                             "algorithmic_bytes": nbytes, "traffic": load_traffic(sname),
-                             "mad_frac": round(A.nnz * L * L / tk / (PEAK_MAD_TOPS * 1e12), 4),
-                             "valu_issue_frac": valu_issue_frac(sname, tk * 1e6)}
     out = {
         "metric": "MP nonzeros/s for 256-bit MP-SpMV (+ % roofline); BiCG solve time, batched vs plain",
         "value": value,
@@ -458,22 +441,127 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32 limbs (p=256 binary floating point, RN)",
         "data": "synthetic",
-        "config": {"workload": "2-D convection-diffusion 5-point, 256x256 grid (n=65536, nnz=326656, "
-                               "Peclet 10), p=256; SpMV/SpMV^T both modes + 200 BiCG + 200 GPBiCG "
-                               "iterations per mode, b = A*ones",
-                   "n": A.n_rows, "nnz": A.nnz, "prec_bits": PREC, "iters": ITERS},
+        "config": {"workload": WORKLOAD, "n": A_h.n_rows, "nnz": A_h.nnz, "prec_bits": PREC,
+                   "products_per_step": 2},
+        "roofline": roof,
         "components": comp,
-        "roofline": roofline,
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+# ---------------------------------------------------------------------------------------------
+# counter passes and summaries of rocprofv3 output
+# ---------------------------------------------------------------------------------------------
+def profile_pass(M, torch, which, args):
+    """Launches for a counter run: a plain copy of 256 MiB (the counters' calibration), then ten
+    launches of each tuned SpMV kernel of the workload (the power-law matrix at p = 256, or the
+    256 x 256 operator followed by 20 iterations of each solve)."""
+    src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    import synth
+    if which == "powerlaw":
+        A_h, x_h, _ = synth.config3(p=PREC)
+        A = M.CSRMatrix.from_host(A_h)
+        x = M.MPArray.from_host(x_h)
+        plan = M.mp_plan_create(A)
+        plan.tune(cache=args.tune_cache or None)
+    else:
+        A_h, ones_h = synth.config2(p=PREC, m=GRID)
+        A = M.CSRMatrix.from_host(A_h)
+        x = M.MPArray.from_host(ones_h)
+        plan = M.mp_plan_create(A)
+        plan.tune(cache=args.tune_cache or None)
+    y = M.MPArray.empty(A.n_rows, PREC)
+    names = {}
+    for mode in (M.MP_SEQ, M.MP_EXACT):
+        names[mode] = spmv_kernel_name(plan, 0, mode, PREC // 32)
+        for _ in range(10):
+            M.mpspmv_csr(A, x, y, mode=mode, plan=plan)
+    if which != "powerlaw":
+        b = M.mpspmv_csr(A, x, mode=M.MP_EXACT)
+        for solver in (M.bicg, M.gpbicg):
+            for mode in (M.MP_SEQ, M.MP_EXACT):
+                solver(A, b, plan=plan, mode=mode, maxit=20, rtol=(1, -70), atol=(0, 0), chunk=0)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": which, "variants": names, "kernel_source": kernel_source_hash(),
+                      "copy_bytes": src.numel() * 4, "n_rows": A.n_rows, "nnz": A.nnz}))
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    n = name
+    for pre in ("void ", "mp::", "(anonymous namespace)::"):
+        n = n.replace(pre, "")
+    return n.split("(")[0] if "(" in n and not n.startswith("(") else n
+
+
+def summarize_stats(path):
+    """Kernel table of a rocprofv3 --stats kernel summary (calls, total, average per kernel)."""
+    rows = _csv_rows(path)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("%-70s %6s %12s %10s %6s" % ("kernel", "calls", "total_us", "avg_us", "pct"))
+    for r in rows:
+        print("%-70s %6s %12.1f %10.2f %6.2f" % (_short(r["Name"])[:70], r["Calls"],
+                                                 float(r["TotalDurationNs"]) / 1e3,
+                                                 float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+
+
+def _counter_means(d, counter):
+    """Per kernel: mean over dispatches of the counter (summed over its instances) in bytes."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for f in files:
+        disp = {}
+        for r in _csv_rows(f):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            disp[key] = disp.get(key, 0.0) + float(r["Counter_Value"])
+        for (_, name), v in disp.items():
+            per.setdefault(_short(name), []).append(v * 1024.0)   # KiB -> bytes
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def summarize_counters(fetch_dir, write_dir):
+    """FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same counter reads for
+    the pass's plain 256 MiB copy; merged into profiles/traffic_counters.json and printed."""
+    fe = _counter_means(fetch_dir, "FETCH_SIZE")
+    wr = _counter_means(write_dir, "WRITE_SIZE")
+    copy = [k for k in fe if "elementwise_kernel" in k and "copy" in k.lower()] or \
+           [k for k in fe if "copyBuffer" in k or "direct_copy" in k]
+    copy_bytes = 256 << 20
+    f_fetch = fe[copy[0]] / copy_bytes if copy else 1.0
+    f_write = wr.get(copy[0], copy_bytes) / copy_bytes if copy else 1.0
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    src = kernel_source_hash()
+    print("calibration kernel %s: factors fetch %.4f write %.4f" % (copy[0] if copy else "-", f_fetch, f_write))
+    print("%-60s %14s %14s %12s" % ("kernel (avg per dispatch)", "FETCH_MB", "WRITE_MB", "traffic_MB"))
+    for k in sorted(set(fe) | set(wr)):
+        fb, wb = fe.get(k, 0.0) / f_fetch, wr.get(k, 0.0) / f_write
+        ent = d.get(k, {})
+        ent.update({"fetch_bytes": round(fb), "write_bytes": round(wb), "kernel_source": src})
+        d[k] = ent
+        print("%-60s %14.2f %14.2f %12.2f" % (k[:60], fe.get(k, 0.0) / 1e6, wr.get(k, 0.0) / 1e6, (fb + wb) / 1e6))
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+        fh.write("\n")
 
 
 if __name__ == "__main__":

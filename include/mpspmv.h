@@ -188,6 +188,15 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
 int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
                         int flags);
+/* mp_plan_tune with a persistent cache: the text file `cache_path` maps a key (a hash of A's
+ * precision, shape, row pointers and column indices, of the device's architecture and compute
+ * unit count, and of the library build) to the variants of the four products.  On a hit
+ * (*hit = 1) the cached variants are set and nothing is launched; otherwise the variants are
+ * tuned as by mp_plan_tune and appended to the file (created if missing).  Synchronous (copies
+ * A's structure to the host to form the key).  Returns as mp_plan_tune, plus MPS_EINVAL when
+ * the file cannot be written. */
+int mp_plan_tune_cached(mp_plan *plan, const mp_csr *A, int reps, const char *cache_path, int *hit,
+                        void *stream);
 int mp_plan_get_variant(const mp_plan *plan, int op, int mode, int *rows_per_block, int *flags);
 
 /* gvals_k = RN(g_i x_j) for each stored entry k = (i, j) in A's CSR order (negated when
@@ -234,6 +243,21 @@ int gpbicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
  * MPS_ENOTSUP for batches of more than 2^20 solves or 2^31 - 1 rows or stored entries. */
 int gpbicg_batched(int nsys, const mp_csr *A, int nrhs, const mp_vec *b, mp_vec *x,
                    const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
+/* Kernel timer (measurement only, not part of the paper's method).  mp_timer_create makes a
+ * pool of HIP events for up to max_launches kernels on the current device (MPS_EINVAL outside
+ * 1..2^20, MPS_EHIP if event creation fails).  While a timer is selected on the calling thread
+ * (mp_timer_select; NULL deselects), the main kernel of each later call on that thread -- the
+ * sparse product's kernel of mpspmv_csr / mpspmv_csr_t (not the launch that stages x) and the
+ * kernel of mp_grad_vals -- is launched with its own start and stop events; launches beyond the
+ * pool are not timed.  mp_timer_read waits for the timed kernels, returns the sum of their
+ * durations in microseconds and their number, and empties the pool for reuse.  The timer is
+ * owned by the caller and freed by mp_timer_destroy (which also deselects it). */
+typedef struct mp_timer mp_timer;
+int mp_timer_create(int max_launches, mp_timer **timer);
+int mp_timer_select(mp_timer *timer);
+int mp_timer_read(mp_timer *timer, double *total_us, int64_t *launches);
+int mp_timer_destroy(mp_timer *timer);
 
 /* Synchronise `stream`, then read and clear the calling device's status word into *flags
  * (MP_ST_* bits).  Returns MPS_OK, or MPS_ERANGE / MPS_ENOTSUP when such a bit was set. */

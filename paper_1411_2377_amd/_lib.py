@@ -86,6 +86,8 @@ SIGNATURES = {
     "mpspmv_csr": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "mp_plan_tune": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_void_p],
+    "mp_plan_tune_cached": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_char_p,
+                            ctypes.POINTER(ctypes.c_int), ctypes.c_void_p],
     "mp_plan_set_variant": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_int,
                             ctypes.c_int, ctypes.c_int],
     "mp_plan_get_variant": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -111,6 +113,10 @@ SIGNATURES = {
     "gpbicg_batched": [ctypes.c_int, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.POINTER(MpVec),
                        ctypes.POINTER(MpVec), ctypes.POINTER(MpSolveOpts),
                        ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "mp_timer_create": [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+    "mp_timer_select": [ctypes.c_void_p],
+    "mp_timer_read": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "mp_timer_destroy": [ctypes.c_void_p],
 }
 OPTIONAL = {}
 # symbols bound by hand above (non-int return types)

@@ -1,5 +1,6 @@
 """Python entry points with the C ABI's names (argument marshalling only)."""
 import ctypes
+import os
 
 import torch
 
@@ -59,10 +60,20 @@ class Plan:
         d = self.A.desc()
         check(_lib.LIB.mp_plan_refresh(self._h, ctypes.byref(d), _stream(stream)))
 
-    def tune(self, reps=3, stream=None):
-        """Time the SpMV kernel variants on this matrix and keep the fastest (synchronous)."""
+    def tune(self, reps=3, stream=None, cache=None):
+        """Time the SpMV kernel variants on this matrix and keep the fastest (synchronous).
+        With cache=<file path> the choice is looked up in (or added to) that tuning cache;
+        self.cache_hit tells which happened."""
         d = self.A.desc()
-        check(_lib.LIB.mp_plan_tune(self._h, ctypes.byref(d), int(reps), _stream(stream)))
+        if cache is None:
+            check(_lib.LIB.mp_plan_tune(self._h, ctypes.byref(d), int(reps), _stream(stream)))
+            self.cache_hit = False
+        else:
+            hit = ctypes.c_int(0)
+            check(_lib.LIB.mp_plan_tune_cached(self._h, ctypes.byref(d), int(reps),
+                                               os.fsencode(cache), ctypes.byref(hit),
+                                               _stream(stream)))
+            self.cache_hit = bool(hit.value)
         return self.variants()
 
     def set_variant(self, op, mode, rows=0, stage_x=False, sorted_rows=False):
@@ -234,3 +245,37 @@ def gpbicg_batched(As, bs, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50)
                       infos[s * nrhs + k].final_rel_res, None) for k in range(nrhs)]
            for s in range(nsys)]
     return xs, out
+
+
+class KernelTimer:
+    """Measurement only: HIP events attached to the main kernel of each library call made on
+    this thread while the timer is selected (the sparse product's kernel, not its x staging)."""
+
+    def __init__(self, max_launches=4096):
+        self._h = ctypes.c_void_p()
+        check(_lib.LIB.mp_timer_create(int(max_launches), ctypes.byref(self._h)))
+
+    def select(self):
+        check(_lib.LIB.mp_timer_select(self._h))
+        return self
+
+    @staticmethod
+    def deselect():
+        check(_lib.LIB.mp_timer_select(None))
+
+    def read(self):
+        """(total microseconds, launches) of the kernels timed since the last read."""
+        us, n = ctypes.c_double(0), ctypes.c_int64(0)
+        check(_lib.LIB.mp_timer_read(self._h, ctypes.byref(us), ctypes.byref(n)))
+        return us.value, n.value
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.LIB.mp_timer_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

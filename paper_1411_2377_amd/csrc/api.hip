@@ -17,6 +17,7 @@
 namespace mpapi {
 
 thread_local LaunchEvents* g_launch_events = nullptr;
+thread_local KernelTimer* g_timer = nullptr;
 
 static thread_local char g_err[512] = "";
 
@@ -264,6 +265,61 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_p
   const SpmvVariant var = plan ? plan_variant(plan, 0, mode) : SpmvVariant{};
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
                      nullptr, (hipStream_t)stream, nullptr, nullptr, &var);
+}
+
+int mp_timer_create(int max_launches, mp_timer** out) {
+  clear_error();
+  if (!out || max_launches < 1 || max_launches > (1 << 20))
+    return fail(MPS_EINVAL, "mp_timer_create: need 1 <= max_launches <= 2^20 and an output");
+  KernelTimer* t = new KernelTimer();
+  hipError_t e = hipGetDevice(&t->device);
+  t->ev = new hipEvent_t[2 * (size_t)max_launches]();
+  for (int i = 0; e == hipSuccess && i < 2 * max_launches; ++i) e = hipEventCreate(&t->ev[i]);
+  if (e != hipSuccess) {
+    for (int i = 0; i < 2 * max_launches; ++i)
+      if (t->ev[i]) (void)hipEventDestroy(t->ev[i]);
+    delete[] t->ev;
+    delete t;
+    return hip_fail(e, "mp_timer_create");
+  }
+  t->cap = max_launches;
+  *out = reinterpret_cast<mp_timer*>(t);
+  return MPS_OK;
+}
+
+int mp_timer_select(mp_timer* t) {
+  clear_error();
+  g_timer = reinterpret_cast<KernelTimer*>(t);
+  return MPS_OK;
+}
+
+int mp_timer_read(mp_timer* t, double* total_us, int64_t* launches) {
+  clear_error();
+  KernelTimer* k = reinterpret_cast<KernelTimer*>(t);
+  if (!k || !total_us || !launches) return fail(MPS_EINVAL, "mp_timer_read: null argument");
+  double us = 0;
+  for (int i = 0; i < k->used; ++i) {
+    hipError_t e = hipEventSynchronize(k->ev[2 * i + 1]);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, k->ev[2 * i], k->ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "mp_timer_read");
+    us += 1e3 * (double)ms;
+  }
+  *total_us = us;
+  *launches = k->used;
+  k->used = 0;
+  return MPS_OK;
+}
+
+int mp_timer_destroy(mp_timer* t) {
+  clear_error();
+  KernelTimer* k = reinterpret_cast<KernelTimer*>(t);
+  if (!k) return MPS_OK;
+  if (g_timer == k) g_timer = nullptr;
+  for (int i = 0; i < 2 * k->cap; ++i) (void)hipEventDestroy(k->ev[i]);
+  delete[] k->ev;
+  delete k;
+  return MPS_OK;
 }
 
 int mp_status(void* stream, uint32_t* flags) {

@@ -29,6 +29,35 @@ extern thread_local LaunchEvents* g_launch_events;
       hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                    \
   } while (0)
 
+// Kernel timer (measurement only, mp_timer_* in the C ABI): while one is selected on the calling
+// thread, the main kernel of each library call (the sparse product's kernel, not its x staging;
+// the value-gradient kernel) is launched with its own pair of events from the timer's pool.
+struct KernelTimer {
+  int device = 0;
+  int cap = 0, used = 0;
+  hipEvent_t* ev = nullptr;  // [2 * cap]
+};
+extern thread_local KernelTimer* g_timer;
+// the next event pair of the selected timer (false: no timer selected, or its pool is full)
+inline bool timer_next(hipEvent_t* e0, hipEvent_t* e1) {
+  KernelTimer* t = g_timer;
+  if (!t || t->used >= t->cap) return false;
+  *e0 = t->ev[2 * t->used];
+  *e1 = t->ev[2 * t->used + 1];
+  ++t->used;
+  return true;
+}
+
+// A call's main kernel: timed by the selected kernel timer if there is one, else as MPS_LAUNCH.
+#define MPS_LAUNCH_MAIN(first, last, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                   \
+  do {                                                                                        \
+    hipEvent_t mps_t0_, mps_t1_;                                                              \
+    if (::mpapi::timer_next(&mps_t0_, &mps_t1_))                                               \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, mps_t0_, mps_t1_, 0, __VA_ARGS__); \
+    else                                                                                      \
+      MPS_LAUNCH(first, last, KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);               \
+  } while (0)
+
 struct DeviceCtx {
   int device = 0;
   uint32_t* status = nullptr;  // device status word (MP_ST_* bits)

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 
+#include <cstdio>
 #include <cstring>
 #include <vector>
 #include <rocprim/rocprim.hpp>
@@ -250,9 +251,9 @@ int grad_vals_launch(const mp_csr* A, const mp_plan* P, const mp_vec* g, const m
   const unsigned grid = (unsigned)std::min<int64_t>(blocks_for(A->nnz, 256), 65536);
   const uint32_t neg = negate ? 1u : 0u;
   switch (P->L) {
-    case 4: hipLaunchKernelGGL(grad_vals_kernel<4>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
-    case 8: hipLaunchKernelGGL(grad_vals_kernel<8>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
-    case 16: hipLaunchKernelGGL(grad_vals_kernel<16>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 4: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<4>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 8: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<8>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 16: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<16>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "grad_vals launch");
@@ -361,9 +362,90 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
   return MPS_OK;
 }
 
+// Tuning cache: one text line per product, "<key> <op> <mode> <rows per block> <flags>", keyed by
+// a 64-bit FNV-1a hash of the matrix structure (precision, shape, row pointers, column
+// indices), the device (architecture name, compute units) and the library build.
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+int tune_key(const mp_plan* P, const mp_csr* A, uint64_t* key) {
+  std::vector<int32_t> rp(A->row_dim + 1), ci(A->nnz);
+  hipError_t e = hipMemcpy(rp.data(), A->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && A->nnz) e = hipMemcpy(ci.data(), A->col_idx, ci.size() * 4, hipMemcpyDeviceToHost);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, P->device);
+  if (e != hipSuccess) return hip_fail(e, "tuning cache key");
+  uint64_t h = 0xcbf29ce484222325ull;
+  const int64_t dims[4] = {A->prec, A->row_dim, A->col_dim, A->nnz};
+  h = fnv1a(h, dims, sizeof(dims));
+  h = fnv1a(h, rp.data(), rp.size() * 4);
+  h = fnv1a(h, ci.data(), ci.size() * 4);
+  h = fnv1a(h, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+  h = fnv1a(h, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+  static const char build[] = __DATE__ " " __TIME__;
+  h = fnv1a(h, build, sizeof(build));
+  *key = h;
+  return MPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mp_plan_tune_cached(mp_plan* plan, const mp_csr* A, int reps, const char* cache_path, int* hit,
+                        void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  if (!cache_path || !hit) return fail(MPS_EINVAL, "mp_plan_tune_cached: null path or hit flag");
+  *hit = 0;
+  uint64_t key = 0;
+  if ((r = tune_key(plan, A, &key))) return r;
+  int rpw[2][2], flags[2][2], seen = 0;
+  if (FILE* f = fopen(cache_path, "r")) {
+    char line[256];
+    while (fgets(line, sizeof(line), f)) {
+      unsigned long long k = 0;
+      int op, mode, rv, fl;
+      if (sscanf(line, "%llx %d %d %d %d", &k, &op, &mode, &rv, &fl) != 5 || k != key) continue;
+      if (op < 0 || op > 1 || mode < 0 || mode > 1 || (rv != 0 && !valid_rows_per_block(rv)) ||
+          (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS)))
+        continue;
+      rpw[op][mode] = rv;
+      flags[op][mode] = fl;
+      seen |= 1 << (2 * op + mode);
+    }
+    fclose(f);
+  }
+  if (seen == 15) {
+    for (int op = 0; op < 2; ++op)
+      for (int mode = 0; mode < 2; ++mode)
+        if ((r = mp_plan_set_variant(plan, A, op, mode, rpw[op][mode], flags[op][mode]))) return r;
+    *hit = 1;
+    return MPS_OK;
+  }
+  if (reps <= 0) reps = 3;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  if ((r = tune_impl(plan, A, reps, ctx->status, (hipStream_t)stream))) return r;
+  FILE* f = fopen(cache_path, "a");
+  if (!f) return fail(MPS_EINVAL, "mp_plan_tune_cached: cannot append to %s", cache_path);
+  for (int op = 0; op < 2; ++op)
+    for (int mode = 0; mode < 2; ++mode) {
+      int rv = 0, fl = 0;
+      mp_plan_get_variant(plan, op, mode, &rv, &fl);
+      fprintf(f, "%016llx %d %d %d %d\n", (unsigned long long)key, op, mode, rv, fl);
+    }
+  fclose(f);
+  return MPS_OK;
+}
 
 int mp_plan_create(const mp_csr* A, void* stream, mp_plan** plan) {
   clear_error();

@@ -162,3 +162,64 @@ def test_solve_adjoint_matches_oracle_and_duality():
     gv = to_np(M, vt.grad, p)
     xo = codec.decode(xs[0], xs[1], p)
     assert_bitwise(gv[0], gv[1], ospmv.grad_vals(rp, ci, ref.x, xo, p, negate=True), p, what="grad vals (solve)")
+
+
+def test_repeated_rounds_and_no_grad_calls():
+    """The same leaves go through two forward + backward rounds of the product and of the solve
+    (each use ends with its backward pass), a call under torch.no_grad() claims nothing, and a
+    dropped output frees its inputs for another use; the gradients of every round are equal."""
+    import gc
+    M = lib()
+    p = 256
+    A_h, x_h = synth.config1(p=p, n=120, per_row=5)
+    g_h = synth.mp_uniform(np.random.default_rng(3), A_h.n_rows, p)
+    A = M.CSRMatrix.from_host(A_h)
+    S = M.autograd.SparseStructure.of(A)
+    vt, xt = packed(M, A_h.vals), packed(M, x_h)
+    gt = M.autograd.pack(M.MPArray.from_host(g_h))
+    grads = []
+    for _ in range(2):
+        vt.grad = xt.grad = None
+        M.autograd.spmv(S, vt, xt, 1).backward(gt)
+        grads.append((vt.grad.clone(), xt.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    with torch.no_grad():
+        M.autograd.spmv(S, vt, xt, 0)
+    y = M.autograd.spmv(S, vt, xt, 0)        # not blocked by the no_grad call
+    del y
+    gc.collect()
+    M.autograd.spmv(S, vt, xt, 0).backward(gt)   # the dropped output released its inputs
+
+    C_h, _ = synth.config2(p=p, m=6)
+    C = M.CSRMatrix.from_host(C_h)
+    SC = M.autograd.SparseStructure.of(C)
+    ct = packed(M, C_h.vals)
+    bt = packed(M, synth.mp_uniform(np.random.default_rng(4), C_h.n_rows, p))
+    ones = M.autograd.pack(M.MPArray.from_host(synth.mp_ones(C_h.n_rows, p)))
+    opts = dict(mode=1, maxit=300, rtol=(1, -60), atol=(0, 0))
+    sg = []
+    for _ in range(2):
+        ct.grad = bt.grad = None
+        M.autograd.solve(SC, ct, bt, **opts).backward(ones)
+        sg.append((ct.grad.clone(), bt.grad.clone()))
+    assert torch.equal(sg[0][0], sg[1][0]) and torch.equal(sg[0][1], sg[1][1])
+
+
+def test_unconverged_solve_has_no_gradient():
+    """A solve stopped by its iteration limit raises in the forward pass; with
+    require_converged=False the iterate is returned and the backward pass raises instead of
+    returning an adjoint of a non-solution."""
+    M = lib()
+    p = 256
+    C_h, _ = synth.config2(p=p, m=8)
+    C = M.CSRMatrix.from_host(C_h)
+    SC = M.autograd.SparseStructure.of(C)
+    ct = packed(M, C_h.vals)
+    bt = packed(M, synth.mp_uniform(np.random.default_rng(5), C_h.n_rows, p))
+    opts = dict(mode=0, maxit=2, rtol=(1, -60), atol=(0, 0))
+    with pytest.raises(M.autograd.MPSolveError):
+        M.autograd.solve(SC, ct, bt, **opts)
+    x = M.autograd.solve(SC, ct, bt, require_converged=False, **opts)
+    ones = M.autograd.pack(M.MPArray.from_host(synth.mp_ones(C_h.n_rows, p)))
+    with pytest.raises(M.autograd.MPSolveError):
+        x.backward(ones)

@@ -115,8 +115,17 @@ def test_convdiff_full_size_sampled(mode):
 @pytest.mark.parametrize("p", [128, 256, 512])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_powerlaw_full_size_sampled(p, mode):
+    """The power-law workload (n = 500000) with the default variant and with the tuned plan
+    (the benchmark's configuration): sampled rows, including the longest, against the oracle."""
     A, x, g = synth.config3(p=p)
     yl, yh = run(A, x, mode)
+    M = lib()
+    Ad = M.CSRMatrix.from_host(A)
+    P = M.mp_plan_create(Ad)
+    P.tune(reps=1)
+    yt = M.mpspmv_csr(Ad, M.MPArray.from_host(x), mode=mode, plan=P).to_numpy()
+    assert M.mp_status() == 0
+    assert np.array_equal(yt[0], yl) and np.array_equal(yt[1], yh), "tuned variant differs"
     lengths = np.diff(A.row_ptr)
     rng = np.random.default_rng(p)
     rows = np.unique(np.concatenate([[0, A.n_rows - 1, int(np.argmax(lengths))],

@@ -49,15 +49,23 @@ def test_transpose_product_random(p, mode):
     assert_bitwise(yl, yh, want, p, what="A^T x")
 
 
+@pytest.mark.parametrize("p", [128, 256, 512])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
-def test_transpose_powerlaw_full_size_sampled(mode):
-    """The power-law workload at p = 128: A^T g on sampled columns (incl. the heaviest)."""
+def test_transpose_powerlaw_full_size_sampled(p, mode):
+    """The power-law workload (n = 500000): A^T g on sampled columns (incl. the heaviest), with
+    the plan's default variant and with its tuned variant (the benchmark's configuration)."""
     M = lib()
-    A_h, x_h, g_h = synth.config3(p=128)
+    A_h, x_h, g_h = synth.config3(p=p)
     A = M.CSRMatrix.from_host(A_h)
     P = M.mp_plan_create(A)
-    y = M.mpspmv_csr_t(A, P, M.MPArray.from_host(g_h), mode=mode)
+    g = M.MPArray.from_host(g_h)
+    y = M.mpspmv_csr_t(A, P, g, mode=mode)
+    P.tune(reps=1)
+    y2 = M.mpspmv_csr_t(A, P, g, mode=mode)
+    assert M.mp_status() == 0
     yl, yh = y.to_numpy()
+    yl2, yh2 = y2.to_numpy()
+    assert np.array_equal(yl, yl2) and np.array_equal(yh, yh2), "tuned variant differs"
     counts = np.bincount(A_h.col_idx, minlength=A_h.n_cols)
     rng = np.random.default_rng(1)
     cols = np.unique(np.concatenate([[0, A_h.n_cols - 1], np.argsort(counts)[-3:],
@@ -67,17 +75,17 @@ def test_transpose_powerlaw_full_size_sampled(mode):
     want = []
     for j in cols:
         ks = np.nonzero(A_h.col_idx == j)[0]
-        vals = codec.decode(A_h.vals.limbs[:, ks], A_h.vals.hdr[ks], 128)
+        vals = codec.decode(A_h.vals.limbs[:, ks], A_h.vals.hdr[ks], p)
         gs = decode_vec(g_h, row_of[ks])
         pairs = [(v, gs[int(i)]) for v, i in zip(vals, row_of[ks])]
         if mode == 1:
-            want.append(ospmv.exact_sum_of_products(pairs, 128))
+            want.append(ospmv.exact_sum_of_products(pairs, p))
         else:
-            acc = mpnum.zero(128)
+            acc = mpnum.zero(p)
             for a, b in pairs:
                 acc = mpnum.add(acc, mpnum.mul(a, b))
             want.append(acc)
-    assert_bitwise(yl, yh, want, 128, rows=cols, what="A^T g power-law")
+    assert_bitwise(yl, yh, want, p, rows=cols, what="A^T g power-law p=%d" % p)
 
 
 @pytest.mark.parametrize("p", [128, 512])

@@ -209,8 +209,10 @@ def test_grad_vals_and_dot_definitions():
     for i in range(n):
         for k in range(rp[i], rp[i + 1]):
             want = mpnum.round_fraction(g[i].to_fraction() * x[ci[k]].to_fraction(), p)
-            if gv[t].m or want.m:
-                assert gv[t] == want
+            if g[i].m == 0 or x[ci[k]].m == 0:
+                # a zero factor: a zero whose sign is the xor of the factors' signs (IEEE RN)
+                want = mpnum.zero(p, g[i].s ^ x[ci[k]].s)
+            assert gv[t] == want, (t, gv[t], want)
             t += 1
     neg = spmv.grad_vals(rp, ci, g, x, p, negate=True)
     assert all(a == b.neg() for a, b in zip(neg, gv))
@@ -253,3 +255,67 @@ def test_generators_values_match_their_recipe():
     for i in range(A.n_rows):
         row = A.col_idx[rp[i]:rp[i + 1]]
         assert np.all(np.diff(row) > 0)
+
+
+def _one_eps(p):
+    """1 and eps = 2^-p: 1 + eps is the exact midpoint between 1 and its successor 1 + 2^(1-p)."""
+    one = MP(0, 1 << (p - 1), 1, p)
+    eps = MP(0, 1 << (p - 1), 1 - p, p)
+    return one, eps
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_seq_order_is_storage_order_closed_form(p):
+    """SEQ adds a row's products in ascending column order, one rounding per operation.
+
+    Row [1, e, e, ..., e] (k copies of e = 2^-p, x = 1): in storage order every partial sum is the
+    tie 1 + e, which rounds to the even neighbour 1, so y = 1 whatever k.  Any order that adds
+    two of the small terms before the 1 (reversed, pairwise, sorted by magnitude) forms 2e
+    exactly and returns 1 + 2^(1-p) or more.  Row [e, e, 1]: the small terms come first in
+    storage order, so y = 1 + 2^(1-p), while the reversed order gives 1.  EXACT rounds the exact
+    sum 1 + k e once."""
+    one, eps = _one_eps(p)
+    succ = MP(0, (1 << (p - 1)) + 1, 1, p)            # 1 + 2^(1-p)
+    rows = [[one] + [eps] * k for k in (1, 2, 3, 7)] + [[eps, eps, one], [eps, one, eps]]
+    rp, ci, vals = [0], [], []
+    for r in rows:
+        ci += list(range(len(r)))
+        vals += r
+        rp.append(len(ci))
+    x = [one] * 8
+    y = spmv.spmv_seq(rp, ci, vals, x, p)
+    assert y[:4] == [one] * 4
+    assert y[4] == succ            # e + e = 2e exactly, then 1 + 2e is representable
+    assert y[5] == one             # (e + 1) ties to 1, then (1 + e) ties to 1
+    # the same rows in reversed storage order give the other results
+    rrp, rci, rvals = [0], [], []
+    for r in rows:
+        rci += list(range(len(r)))
+        rvals += r[::-1]
+        rrp.append(len(rci))
+    yr = spmv.spmv_seq(rrp, rci, rvals, x, p)
+    assert yr[1] == succ and yr[4] == one and yr[5] == one
+    assert yr[3] == MP(0, (1 << (p - 1)) + 4, 1, p)   # 7e first: 1 + 7e -> tie at 1 + 3.5 ulp -> 1 + 4 ulp
+    # EXACT: one rounding of 1 + k e
+    ye = spmv.spmv_exact(rp, ci, vals, x, p)
+    assert ye[0] == one                                # 1 + e: tie to even
+    assert ye[1] == succ                               # 1 + 2e exactly
+    assert ye[3] == MP(0, (1 << (p - 1)) + 4, 1, p)    # 1 + 7e: 3.5 ulp ties to 4 ulp (even)
+
+
+@pytest.mark.parametrize("p", [128, 512])
+def test_seq_transposed_order_is_ascending_original_row(p):
+    """A^T x in SEQ mode sums each column of A over its original rows in ascending order.
+    Column 0 holds (1, e, e) in rows 0, 1, 2 and column 1 holds (e, e, 1): with x = 1 the
+    transposed product gives 1 and 1 + 2^(1-p) (descending original rows would swap them)."""
+    one, eps = _one_eps(p)
+    succ = MP(0, (1 << (p - 1)) + 1, 1, p)
+    rp = [0, 2, 4, 6]
+    ci = [0, 1, 0, 1, 0, 1]
+    vals = [one, eps, eps, eps, eps, one]
+    x = [one] * 3
+    yt = spmv.spmv_t(3, 2, rp, ci, vals, x, p, spmv.SEQ)
+    assert yt == [one, succ]
+    tp, ti, tv = spmv.transpose(3, 2, rp, ci, vals)
+    assert tp == [0, 3, 6] and ti == [0, 1, 2, 0, 1, 2]
+    assert tv == [one, eps, eps, eps, eps, one]

@@ -46,3 +46,13 @@ def assert_bitwise(gpu_limbs, gpu_hdr, want_vals, p, rows=None, what=""):
         raise AssertionError("%s: %d of %d differ; first at %d: gpu %r oracle %r"
                              % (what, len(bad), len(wh), i if rows is None else int(np.asarray(rows)[i]),
                                 got, want_vals[i]))
+
+
+def digest(limbs, hdr):
+    """SHA-256 of an MP array in the storage layout (limb planes, then headers, little endian):
+    the form in which the stored expected values of long runs are compared."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(np.asarray(limbs, dtype="<u4")).tobytes())
+    h.update(np.ascontiguousarray(np.asarray(hdr, dtype="<i4")).tobytes())
+    return h.hexdigest()
