@@ -14,7 +14,7 @@ Cases (the paper's Fig. 5 solvers with the stopping test of Sec. 4.1, K = I):
                      20 iterations of BiCG and GPBiCG, EXACT (tolerance 1e-100);
   banded_*           the two smallest systems of the 64-system banded batch, all 16 right-hand
                      sides, GPBiCG SEQ to 1e-60 (maxit 5000);
-  scaled3d_16_dec2_adjoint  a 16^3 row-scaled operator with decade spread 2, p = 512: the BiCG
+  scaled3d_16_dec1_adjoint  a 16^3 row-scaled operator with decade spread 1, p = 512: the BiCG
                      solve of A x = A [1..n] to 1e-100, the adjoint lambda = A^-T ones (one
                      transposed BiCG) and the value gradient -RN(lambda_i x_j).
 
@@ -149,7 +149,7 @@ def case_banded(k):
 
 def case_adjoint():
     p, m = 512, 16
-    A_h = synth.convdiff3d_scaled(m, p, seed=5, dec=2.0)
+    A_h = synth.convdiff3d_scaled(m, p, seed=5, dec=1.0)
     xs_h = synth.mp_arange1(A_h.n_rows, p)
     S = System(A_h)
     b = ospmv.spmv_exact(S.rp, S.ci, S.vals, codec.decode(xs_h.limbs, xs_h.hdr, p), p)
@@ -160,7 +160,7 @@ def case_adjoint():
     ones = [mpnum.from_int(1, p)] * A_h.n_rows
     adj = krylov.bicg(S.rmv(1), S.mv(1), ones, c_rel, c_abs, opts["maxit"], p)
     gv = ospmv.grad_vals(S.rp, S.ci, adj.x, fwd.x, p, negate=True)
-    return {"workload": "3-D 7-point convection-diffusion 16^3, rows scaled by 10^u, u ~ U(-2, 2), "
+    return {"workload": "3-D 7-point convection-diffusion 16^3, rows scaled by 10^u, u ~ U(-1, 1), "
                         "p=512, b = RN_exact(A [1..n]); adjoint right-hand side ones",
             "mode": 1, "opts": opts, "b_digest": enc_digest(b, p),
             "oracle_wall_s": round(time.time() - t0, 1),
@@ -177,7 +177,7 @@ CASES = {
     "scaled3d_64_p512_gpbicg_exact_20it": lambda: case_scaled3d("gpbicg"),
     "banded_smallest0_p256_gpbicg_seq": lambda: case_banded(0),
     "banded_smallest1_p256_gpbicg_seq": lambda: case_banded(1),
-    "scaled3d_16_dec2_p512_adjoint": case_adjoint,
+    "scaled3d_16_dec1_p512_adjoint": case_adjoint,
 }
 
 
