@@ -157,6 +157,19 @@ int mp_validate_csr(const mp_csr *A, int check_device_data);
 int mpspmv_csr(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp_plan *plan,
                void *stream);
 
+/* y = A x as mpspmv_csr (same modes, same result bits), for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The call allocates nothing, on the device or through any library: x is staged
+ * (one record per element, as the MP_VARIANT_STAGE_X variant) into a file-scope device array of
+ * 32 MiB + 256 bytes that every GPU the library runs on holds until the process ends, and rows
+ * per block follow A's shape.  x.len (= col_dim) may be at most 1,048,576 at p = 128, 524,288 at
+ * p = 256 and 262,144 at p = 512; larger x returns MPS_ENOTSUP before anything is enqueued.
+ * Device conditions go to a status word inside the same array, which mp_status reads and clears
+ * together with the device's other status word.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (two streams, two threads) race and must be ordered by the
+ * caller.  Other arguments, checks and return codes as mpspmv_csr. */
+int mpspmv_csr_noalloc(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, void *stream);
+
 /* Build the transposed-product plan of A (synchronises `stream`; allocates device memory).
  * The plan records A's shape and precision; its values are a copy: after changing A's values
  * in place call mp_plan_refresh.  Returns MPS_OK, MPS_EINVAL or MPS_ENOMEM. */

@@ -85,6 +85,8 @@ SIGNATURES = {
     "mp_validate_csr": [ctypes.POINTER(MpCsr), ctypes.c_int],
     "mpspmv_csr": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "mpspmv_csr_noalloc": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+                           ctypes.c_int, ctypes.c_void_p],
     "mp_plan_tune": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_void_p],
     "mp_plan_tune_cached": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_char_p,
                             ctypes.POINTER(ctypes.c_int), ctypes.c_void_p],

@@ -35,6 +35,15 @@ def mpspmv_csr(A, x, y=None, mode=MP_SEQ, plan=None, stream=None):
     return y
 
 
+def mpspmv_csr_noalloc(A, x, y, mode=MP_SEQ, stream=None):
+    """y = A x into the caller's y through the allocation-free entry point (x staged in the
+    library's static scratch array; x.n bounded by its size).  Returns y."""
+    a, xd, yd = A.desc(), x.desc(), y.desc()
+    check(_lib.LIB.mpspmv_csr_noalloc(ctypes.byref(a), ctypes.byref(xd), ctypes.byref(yd),
+                                      int(mode), _stream(stream)))
+    return y
+
+
 def mp_status(stream=None, raise_on_error=True):
     flags = ctypes.c_uint32(0)
     code = _lib.LIB.mp_status(_stream(stream), ctypes.byref(flags))

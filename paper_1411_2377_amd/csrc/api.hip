@@ -235,6 +235,56 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   return MPS_OK;
 }
 
+// ---- allocation-free product --------------------------------------------------------------
+// mpspmv_csr_noalloc keeps its x staging buffer and its status word in `scratch`, a file-scope
+// device array: each GPU the library runs on holds one copy until the process ends, so the call
+// allocates nothing.  Word 0 is the status word of these calls (mp_status reads it beside the
+// context's); the staged x records start at byte kScratchRecOffset.  Host code never passes the
+// array's name to the device: the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchRecOffset = 256;
+constexpr size_t kScratchRecBytes = size_t(32) << 20;  // staged x records: 32 MiB
+constexpr int kScratchMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint32_t* g_scratch_ptr[kScratchMaxDevices] = {};
+
+}  // namespace mpapi
+
+static __device__ __align__(256) uint32_t scratch[(mpapi::kScratchRecOffset + mpapi::kScratchRecBytes) / 4];
+
+namespace mpapi {
+
+// The calling device's copy of `scratch`, resolved once per device with that device current.
+static int scratch_ptr(uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchMaxDevices)
+    return fail(MPS_ENOTSUP, "mpspmv_csr_noalloc: device %d beyond the first %d", dev, kScratchMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(MPS_EHIP, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MPS_OK;
+}
+
+// The scratch status word of a device whose scratch address was resolved (else nullptr).
+static uint32_t* scratch_status(int dev) {
+  if (dev < 0 || dev >= kScratchMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
+// Elements of x the scratch array can stage at L limbs (records of 8, 16 or 32 words).
+static int64_t scratch_max_x(int L) {
+  const int64_t rec_bytes = 4 * (L >= 16 ? 32 : (L >= 8 ? 16 : 8));
+  return (int64_t)(kScratchRecBytes / rec_bytes);
+}
+
 }  // namespace mpapi
 
 using namespace mpapi;
@@ -265,6 +315,31 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_p
   const SpmvVariant var = plan ? plan_variant(plan, 0, mode) : SpmvVariant{};
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
                      nullptr, (hipStream_t)stream, nullptr, nullptr, &var);
+}
+
+int mpspmv_csr_noalloc(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if ((r = check_vec(x, A->col_dim, "x"))) return r;
+  if ((r = check_vec(y, A->row_dim, "y"))) return r;
+  const int L = limbs_of(A->prec);
+  if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L))
+    return fail(MPS_EINVAL, "y overlaps an input");
+  const int64_t max_x = scratch_max_x(L);
+  if (A->col_dim > max_x)
+    return fail(MPS_ENOTSUP,
+                "mpspmv_csr_noalloc: x has %lld elements, the scratch array stages at most %lld "
+                "at p = %d",
+                (long long)A->col_dim, (long long)max_x, A->prec);
+  uint32_t* sp;
+  if ((r = scratch_ptr(&sp))) return r;
+  SpmvVariant var;
+  var.x_rec = sp + kScratchRecOffset / 4;
+  var.x_len = A->col_dim;
+  return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, sp, nullptr,
+                     (hipStream_t)stream, nullptr, nullptr, &var);
 }
 
 int mp_timer_create(int max_launches, mp_timer** out) {
@@ -334,6 +409,14 @@ int mp_status(void* stream, uint32_t* flags) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
   e = hipMemset(ctx->status, 0, 4);
   if (e != hipSuccess) return hip_fail(e, "hipMemset(status)");
+  if (uint32_t* sw = scratch_status(ctx->device)) {  // the allocation-free calls' status word
+    uint32_t h2 = 0;
+    e = hipMemcpy(&h2, sw, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(scratch status)");
+    e = hipMemset(sw, 0, 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(scratch status)");
+    h |= h2;
+  }
   if (flags) *flags = h;
   if (h & MP_ST_RANGE) return fail(MPS_ERANGE, "a result exponent left the range");
   if (h & MP_ST_WINDOW) return fail(MPS_ENOTSUP, "an exact accumulation was wider than supported");

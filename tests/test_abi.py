@@ -104,3 +104,18 @@ def test_variant_setter_validation():
     from paper_1411_2377_amd import _lib
     f = _lib.LIB.mp_plan_set_variant
     assert f(None, None, 0, 0, 16, 0) == _lib.MPS_EINVAL
+
+
+def test_noalloc_size_limit_rejected_on_the_host():
+    """x beyond what the static scratch array stages is refused before anything is enqueued."""
+    from paper_1411_2377_amd import _lib
+    for prec, max_x in ((128, 1 << 20), (256, 1 << 19), (512, 1 << 18)):
+        a = _lib.MpCsr()
+        a.row_dim, a.col_dim, a.nnz, a.prec = 4, max_x + 1, 0, prec
+        a.row_ptr = 1234
+        a.val.len, a.val.ld = 0, 0
+        x = _lib.MpVec(1 << 40, 1 << 41, max_x + 1, max_x + 1)
+        y = _lib.MpVec(1 << 42, 1 << 43, 4, 4)
+        assert _lib.LIB.mpspmv_csr_noalloc(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 0, None) == _lib.MPS_ENOTSUP
+        assert "scratch" in _lib.last_error()
+        assert _lib.LIB.mpspmv_csr_noalloc(ctypes.byref(a), ctypes.byref(x), ctypes.byref(y), 5, None) == _lib.MPS_EINVAL
