@@ -71,7 +71,10 @@ def parse():
     ap.add_argument("--profile-pass", default="",
                     help="counter pass only: 'powerlaw' or 'convdiff' (copy calibration + launches)")
     ap.add_argument("--summarize-stats", default="")
-    ap.add_argument("--summarize-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-counters", nargs=3, default=None,
+                    metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-valu", nargs=2, default=None, metavar=("WORKLOAD", "DIR"),
+                    help="instruction counts of an SQ_INSTS_VALU/SALU/LDS + SQ_WAVES pass")
     return ap.parse_args()
 
 
@@ -102,15 +105,15 @@ def spmv_kernel_name(plan, op, mode, L, fused=False):
     return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "")
 
 
-def load_counters(kernel):
-    """The committed counter summary's entry for a kernel symbol, when it was taken on the
-    current kernel sources (else None)."""
+def load_counters(kernel, workload="powerlaw"):
+    """The committed counter summary's entry for a kernel symbol in a workload's counter pass,
+    when it was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    ent = d.get(kernel.split(" (")[0])
+    ent = d.get(workload, {}).get(kernel.split(" (")[0])
     if not ent or ent.get("kernel_source") != kernel_source_hash():
         return None
     return ent
@@ -395,6 +398,9 @@ def main():
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
         return
+    if args.summarize_valu:
+        summarize_valu(*args.summarize_valu)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is a single-device kernel set and no "
               "multi-GPU run is part of this build (requested --gpus %d)" % args.gpus,
@@ -461,13 +467,14 @@ def main():
 # counter passes and summaries of rocprofv3 output
 # ---------------------------------------------------------------------------------------------
 def profile_pass(M, torch, which, args):
-    """Launches for a counter run: a plain copy of 256 MiB (the counters' calibration), then ten
+    """Launches for a counter run: an elementwise kernel reading and writing 256 MiB (the
+    counters' calibration), then ten
     launches of each tuned SpMV kernel of the workload (the power-law matrix at p = 256, or the
     256 x 256 operator followed by 20 iterations of each solve)."""
     src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
+    for _ in range(3):   # the calibration: one elementwise kernel reading and writing 256 MiB
+        torch.bitwise_not(src, out=dst)
     torch.cuda.synchronize()
     import synth
     if which == "powerlaw":
@@ -538,29 +545,76 @@ def _counter_means(d, counter):
     return {k: sum(v) / len(v) for k, v in per.items()}
 
 
-def summarize_counters(fetch_dir, write_dir):
+def summarize_counters(workload, fetch_dir, write_dir):
     """FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same counter reads for
-    the pass's plain 256 MiB copy; merged into profiles/traffic_counters.json and printed."""
+    the pass's plain 256 MiB copy; stored under the workload's name in
+    profiles/traffic_counters.json and printed."""
     fe = _counter_means(fetch_dir, "FETCH_SIZE")
     wr = _counter_means(write_dir, "WRITE_SIZE")
-    copy = [k for k in fe if "elementwise_kernel" in k and "copy" in k.lower()] or \
-           [k for k in fe if "copyBuffer" in k or "direct_copy" in k]
+    copy = [k for k in fe if "bitwise_not" in k]
     copy_bytes = 256 << 20
     f_fetch = fe[copy[0]] / copy_bytes if copy else 1.0
     f_write = wr.get(copy[0], copy_bytes) / copy_bytes if copy else 1.0
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
-    d = json.load(open(path)) if os.path.exists(path) else {}
+    d_all = json.load(open(path)) if os.path.exists(path) else {}
+    d_all = {k: v for k, v in d_all.items() if k in ("powerlaw", "convdiff")}
+    d = d_all.setdefault(workload, {})
     src = kernel_source_hash()
     print("calibration kernel %s: factors fetch %.4f write %.4f" % (copy[0] if copy else "-", f_fetch, f_write))
     print("%-60s %14s %14s %12s" % ("kernel (avg per dispatch)", "FETCH_MB", "WRITE_MB", "traffic_MB"))
     for k in sorted(set(fe) | set(wr)):
         fb, wb = fe.get(k, 0.0) / f_fetch, wr.get(k, 0.0) / f_write
         ent = d.get(k, {})
-        ent.update({"fetch_bytes": round(fb), "write_bytes": round(wb), "kernel_source": src})
+        if ent.get("kernel_source") not in (None, src):
+            ent = {}
+        ent.update({"fetch_bytes": round(fb), "write_bytes": round(wb), "kernel_source": src,
+                    "workload": workload})
         d[k] = ent
         print("%-60s %14.2f %14.2f %12.2f" % (k[:60], fe.get(k, 0.0) / 1e6, wr.get(k, 0.0) / 1e6, (fb + wb) / 1e6))
     with open(path, "w") as fh:
-        json.dump(d, fh, indent=1, sort_keys=True)
+        json.dump(d_all, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+
+
+def summarize_valu(workload, d):
+    """Per kernel: mean wavefront instruction counts per dispatch (SQ_INSTS_VALU, _SALU, _LDS,
+    SQ_WAVES) and the mean dispatch duration the same pass recorded; VALU% is the share of the
+    chip's VALU issue slots (one wave64 instruction per SIMD every 4 cycles) the dispatch used.
+    valu_instr is stored under the workload in profiles/traffic_counters.json."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for f in files:
+        disp = {}
+        for r in _csv_rows(f):
+            key = (r["Dispatch_Id"], _short(r["Kernel_Name"]))
+            e = disp.setdefault(key, {"dur": 0.0})
+            e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            if "End_Timestamp" in r and "Start_Timestamp" in r:
+                e["dur"] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3
+        for (_, name), e in disp.items():
+            per.setdefault(name, []).append(e)
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    d_all = json.load(open(path)) if os.path.exists(path) else {}
+    dw = d_all.setdefault(workload, {})
+    src = kernel_source_hash()
+    cols = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES")
+    print("%-48s %5s %9s %12s %10s %10s %8s %7s" % ("kernel (avg per dispatch)", "n", "dur_us",
+                                                    "VALU_instr", "SALU", "LDS", "waves", "VALU%"))
+    for k in sorted(per):
+        es = per[k]
+        avg = {c: sum(e.get(c, 0.0) for e in es) / len(es) for c in cols + ("dur",)}
+        frac = avg["SQ_INSTS_VALU"] / (avg["dur"] * 1e-6 * VALU_ISSUE_PEAK) if avg["dur"] > 0 else 0.0
+        print("%-48s %5d %9.2f %12.0f %10.0f %10.0f %8.0f %6.1f%%" % (
+            k[:48], len(es), avg["dur"], avg["SQ_INSTS_VALU"], avg["SQ_INSTS_SALU"],
+            avg["SQ_INSTS_LDS"], avg["SQ_WAVES"], 100 * frac))
+        ent = dw.get(k, {})
+        if ent.get("kernel_source") not in (None, src):
+            ent = {}
+        ent.update({"valu_instr": round(avg["SQ_INSTS_VALU"]), "kernel_source": src,
+                    "workload": workload})
+        dw[k] = ent
+    with open(path, "w") as fh:
+        json.dump(d_all, fh, indent=1, sort_keys=True)
         fh.write("\n")
 
 
