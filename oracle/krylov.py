@@ -1,4 +1,4 @@
-"""Reference BiCG and GPBiCG in p-bit RN arithmetic (TEST INFRASTRUCTURE ONLY).
+"""Reference BiCG, GPBiCG, CGS and BiCGSTAB in p-bit RN arithmetic (TEST INFRASTRUCTURE ONLY).
 
 Both follow the paper's Fig. 5 (BiCG left, GPBiCG right) with the preconditioner K = I, the
 stopping test (*) of Sec. 4.1, ||r_k||_2 <= c_rel ||r_0||_2 + c_abs, and these readings of
@@ -14,6 +14,19 @@ the printed listings:
     iteration with their own status instead of dividing by zero.
 Every scalar expression is evaluated left to right with one RN per binary operation; inner
 products are exact sums rounded once.
+
+CGS and BiCGSTAB are the other two product-type methods the paper runs (Sec. 4, Tables 1 and 3)
+without printing them; they follow their standard unpreconditioned forms (Sonneveld's CGS, van
+der Vorst's BiCGSTAB) with K = I, the same shadow residual r~ = r_0, the same (*) test on the
+updated residual, and these readings:
+  * CGS: u = r + beta q, p = u + beta (q + beta p), q = u - alpha A p, u^ = u + q,
+    x = x + alpha u^, r = r - alpha A u^; a zero (r~, A p) stops with the alpha breakdown.
+  * BiCGSTAB: beta = (rho / rho_old) (alpha_old / omega_old), p = r + beta (p - omega_old v),
+    v = A p, s = r - alpha v, t = A s, omega = (t, s) / (t, t), x = x + alpha p + omega s,
+    r = s - omega t.  When (t, t) = 0 (t = A s = 0), omega is taken as 0: then x = x + alpha p
+    and r = s, which meets (*) when s = 0 (A s = 0 with s != 0 needs a singular A); omega = 0
+    stops after the (*) test (the zeta breakdown, as GPBiCG's zeta = 0 exit), since the next
+    beta divides by it.
 """
 from .blas import aymx, axpy, dot, xpby
 from .mpnum import add, div, is_zero, le, mul, sqrt, sub, zero
@@ -162,4 +175,98 @@ def gpbicg(matvec, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
         if is_zero(zeta):
             return SolveResult(x, BREAKDOWN_ZETA, i, hist)
         rho_old, alpha_old, zeta_old = rho, alpha, zeta
+    return SolveResult(x, NOT_CONVERGED, maxit, hist)
+
+
+def cgs(matvec, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
+    """Conjugate gradient squared: the BiCG residual polynomial applied twice."""
+    n = len(b)
+    x = list(x0) if x0 is not None else [zero(p)] * n
+    ax = matvec(x)
+    r = [sub(bi, ai) for bi, ai in zip(b, ax)]
+    rt = list(r)
+    q0 = dot(r, r, p)
+    thr = _threshold(sqrt(q0), c_rel, c_abs)
+    hist = []
+    if _converged(q0, thr):
+        return SolveResult(x, CONVERGED, 0, hist)
+    rho_old = None
+    qv = pv = None
+    for i in range(1, maxit + 1):
+        rho = dot(rt, r, p)
+        if is_zero(rho):
+            return SolveResult(x, BREAKDOWN_RHO, i - 1, hist)
+        if i == 1:
+            u = list(r)
+            pv = list(u)
+        else:
+            beta = div(rho, rho_old)
+            u = xpby(r, beta, qv)
+            pv = [add(ui, mul(beta, add(qi, mul(beta, pi)))) for ui, qi, pi in zip(u, qv, pv)]
+        vh = matvec(pv)
+        sigma = dot(rt, vh, p)
+        if is_zero(sigma):
+            return SolveResult(x, BREAKDOWN_SIGMA, i - 1, hist)
+        alpha = div(rho, sigma)
+        qv = aymx(alpha, vh, u)
+        uh = [add(ui, qi) for ui, qi in zip(u, qv)]
+        x = axpy(alpha, uh, x)
+        qh = matvec(uh)
+        r = aymx(alpha, qh, r)
+        q = dot(r, r, p)
+        hist.append(q)
+        if on_iter is not None:
+            on_iter(i, {"x": x, "r": r, "u": u, "p": pv, "q": qv, "rho": rho, "alpha": alpha,
+                        "sigma": sigma, "q2": q})
+        if _converged(q, thr):
+            return SolveResult(x, CONVERGED, i, hist)
+        rho_old = rho
+    return SolveResult(x, NOT_CONVERGED, maxit, hist)
+
+
+def bicgstab(matvec, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
+    """BiCGSTAB: the BiCG polynomial times a product of local residual-minimising steps."""
+    n = len(b)
+    x = list(x0) if x0 is not None else [zero(p)] * n
+    ax = matvec(x)
+    r = [sub(bi, ai) for bi, ai in zip(b, ax)]
+    rt = list(r)
+    q0 = dot(r, r, p)
+    thr = _threshold(sqrt(q0), c_rel, c_abs)
+    hist = []
+    if _converged(q0, thr):
+        return SolveResult(x, CONVERGED, 0, hist)
+    rho_old = alpha_old = omega_old = None
+    pv = v = None
+    for i in range(1, maxit + 1):
+        rho = dot(rt, r, p)
+        if is_zero(rho):
+            return SolveResult(x, BREAKDOWN_RHO, i - 1, hist)
+        if i == 1:
+            pv = list(r)
+        else:
+            beta = mul(div(rho, rho_old), div(alpha_old, omega_old))
+            pv = [add(ri, mul(beta, sub(pi, mul(omega_old, vi)))) for ri, pi, vi in zip(r, pv, v)]
+        v = matvec(pv)
+        sigma = dot(rt, v, p)
+        if is_zero(sigma):
+            return SolveResult(x, BREAKDOWN_SIGMA, i - 1, hist)
+        alpha = div(rho, sigma)
+        s = aymx(alpha, v, r)
+        t = matvec(s)
+        ts = dot(t, s, p)
+        tt = dot(t, t, p)
+        omega = zero(p) if is_zero(tt) else div(ts, tt)
+        x = [add(add(xi, mul(alpha, pi)), mul(omega, si)) for xi, pi, si in zip(x, pv, s)]
+        r = aymx(omega, t, s)
+        q = dot(r, r, p)
+        hist.append(q)
+        if on_iter is not None:
+            on_iter(i, {"x": x, "r": r, "p": pv, "s": s, "t": t, "rho": rho, "alpha": alpha,
+                        "omega": omega, "sigma": sigma, "q": q})
+        if _converged(q, thr):
+            return SolveResult(x, CONVERGED, i, hist)
+        if is_zero(omega):
+            return SolveResult(x, BREAKDOWN_ZETA, i, hist)
+        rho_old, alpha_old, omega_old = rho, alpha, omega
     return SolveResult(x, NOT_CONVERGED, maxit, hist)
