@@ -95,14 +95,15 @@ def spmv_bytes(n_rows, n_cols, nnz, L):
 def spmv_symbol(plan, op, mode, L, fused=False):
     """The kernel symbol (rocprofv3's name without "void mp::" and the arguments) of the plan's
     variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation."""
-    rows, staged, srt = plan.variants()[(op, mode)]
+    rows, staged, srt, gmin = plan.variants()[(op, mode)]
     base = "spmv_exact_kernel" if mode else ("spmv_seq_sorted_kernel" if srt else "spmv_seq_kernel")
     return "%s<%d, %d, %s>" % (base, L, rows, "true" if fused else "false")
 
 
 def spmv_kernel_name(plan, op, mode, L, fused=False):
-    rows, staged, srt = plan.variants()[(op, mode)]
-    return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "")
+    rows, staged, srt, gmin = plan.variants()[(op, mode)]
+    return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "") + \
+        (" (rows of >= %d entries by lane groups)" % gmin if gmin else "")
 
 
 def load_counters(kernel, workload="powerlaw"):

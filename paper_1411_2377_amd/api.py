@@ -85,22 +85,26 @@ class Plan:
             self.cache_hit = bool(hit.value)
         return self.variants()
 
-    def set_variant(self, op, mode, rows=0, stage_x=False, sorted_rows=False):
+    def set_variant(self, op, mode, rows=0, stage_x=False, sorted_rows=False, group_min=0):
         """Force a kernel variant: op 0 = A, 1 = A^T; rows in (0, 16, 32, 64), 0 = by shape;
         stage_x: gather x from staged records; sorted_rows: blocks take rows by decreasing
-        length."""
+        length; group_min (SEQ with sorted rows): rows with at least that many entries are
+        summed by lane groups (0: none)."""
         d = self.A.desc()
         flags = (1 if stage_x else 0) | (2 if sorted_rows else 0)
+        if group_min:
+            flags |= 4 | (int(group_min) << 8)
         check(_lib.LIB.mp_plan_set_variant(self._h, ctypes.byref(d), int(op), int(mode), int(rows), flags))
 
     def variants(self):
-        """{(op, mode): (rows per block, stage_x, sorted_rows)} in effect."""
+        """{(op, mode): (rows per block, stage_x, sorted_rows, group_min)} in effect."""
         out = {}
         for op in (0, 1):
             for mode in (MP_SEQ, MP_EXACT):
                 v, fl = ctypes.c_int(0), ctypes.c_int(0)
                 check(_lib.LIB.mp_plan_get_variant(self._h, op, mode, ctypes.byref(v), ctypes.byref(fl)))
-                out[(op, mode)] = (v.value, bool(fl.value & 1), bool(fl.value & 2))
+                gmin = (fl.value >> 8) if fl.value & 4 else 0
+                out[(op, mode)] = (v.value, bool(fl.value & 1), bool(fl.value & 2), gmin)
         return out
 
     def close(self):
@@ -224,6 +228,16 @@ def bicg(A, b, **kw):
 def gpbicg(A, b, **kw):
     """GPBiCG for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
     return _solve(_lib.LIB.gpbicg, A, b, **kw)
+
+
+def cgs(A, b, **kw):
+    """CGS for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
+    return _solve(_lib.LIB.cgs, A, b, **kw)
+
+
+def bicgstab(A, b, **kw):
+    """BiCGSTAB for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
+    return _solve(_lib.LIB.bicgstab, A, b, **kw)
 
 
 def gpbicg_batched(As, bs, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50), chunk=16,

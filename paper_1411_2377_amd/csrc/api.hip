@@ -158,7 +158,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   const SpmvBatch one;
   if (!batch) batch = &one;
   if (!valid_rows_per_block(rpw)) rpw = default_rows_per_block(n_rows, val.len);
-  if ((n_rows + rpw - 1) / rpw * batch->nrhs > (int64_t)UINT32_MAX)
+  if ((n_rows + rpw - 1) / rpw * batch->nrhs + (n_rows + 3) / 4 > (int64_t)UINT32_MAX)
     return fail(MPS_ENOTSUP, "too many row blocks for one launch");
   mp::SpmvArgs a;
   a.n_rows = n_rows;
@@ -184,6 +184,14 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.x_rec = x_rec;
   a.rows = var->rows;
   a.pipe = var->pipe ? 1 : 0;
+  a.n_long = 0;
+  a.long_blocks = 0;
+  if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
+      !batch->pair_of_tile && !done) {
+    const int rg = 64 / L;  // rows per lane-group block
+    a.n_long = std::min<int64_t>(var->n_long, n_rows);
+    a.long_blocks = (a.n_long + rg - 1) / rg;
+  }
   if (var->rows && batch->nrhs != 1) return fail(MPS_EINVAL, "a row order takes one right-hand side");
   a.fd = mp::DotOut{};
   a.dots = mp::DotWork{};

@@ -108,6 +108,7 @@ struct SpmvVariant {
   int64_t x_len = 0;
   const int32_t* rows = nullptr;
   bool pipe = false;  // SEQ: the four-wavefront pipelined kernel also without a row order
+  int64_t n_long = 0;  // SEQ with a row order: its first n_long rows are summed by lane groups
 };
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,

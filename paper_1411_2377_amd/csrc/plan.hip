@@ -117,7 +117,17 @@ int plan_row_order(mp_plan* P, int op, const int32_t* a_row_ptr) {
     return fail(MPS_ENOMEM, "row order: %s", hipGetErrorString(e));
   }
   e = hipMemcpy(P->row_order[op], order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
-  return e == hipSuccess ? MPS_OK : hip_fail(e, "row order");
+  if (e != hipSuccess) return hip_fail(e, "row order");
+  P->order_len[op].resize(n);
+  for (int64_t i = 0; i < n; ++i) P->order_len[op][i] = h[order[i] + 1] - h[order[i]];
+  return MPS_OK;
+}
+
+// Rows at the head of op's row order with at least min_len entries.
+static int64_t rows_at_least(const mp_plan* P, int op, int min_len) {
+  const std::vector<int32_t>& v = P->order_len[op];
+  return std::lower_bound(v.begin(), v.end(), min_len, [](int32_t a, int m) { return a >= m; }) -
+         v.begin();
 }
 
 SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
@@ -128,6 +138,7 @@ SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
     v.x_len = op ? P->n_rows : P->n_cols;
   }
   if (P->sorted[op][mode]) v.rows = P->row_order[op];
+  if (v.rows && mode == MP_SEQ && P->group_min[op] > 0) v.n_long = rows_at_least(P, op, P->group_min[op]);
   return v;
 }
 
@@ -325,8 +336,13 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     mp_vec xv{xl, xh, cols, nmax}, yv{yl, yh, rows, nmax};
     for (int mode = 0; mode < 2; ++mode) {
       float best = 0.f;
-      int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0;
+      int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0, pick_gmin = 0;
+      // lane groups for the longest rows: SEQ with sorted rows only, when a row is that long
+      const int maxlen = P->order_len[op].empty() ? 0 : P->order_len[op][0];
+      for (int gi = 0; gi < 3; ++gi)
       for (int flags = 0; flags < 4; ++flags) {
+        const int gmin = gi == 0 ? 0 : (gi == 1 ? 128 : 512);
+        if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin)) continue;
         for (int rpw : {16, 32, 64}) {
           SpmvVariant var;
           var.rpw = rpw;
@@ -335,6 +351,7 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
             var.x_len = cols;
           }
           if (flags & MP_VARIANT_SORTED_ROWS) var.rows = P->row_order[op];
+          if (gmin) var.n_long = rows_at_least(P, op, gmin);
           int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
                                nullptr, &var);
           if (rr) return rr;
@@ -351,12 +368,14 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
             best = ms;
             pick = rpw;
             pick_flags = flags;
+            pick_gmin = gmin;
           }
         }
       }
       P->rpw[op][mode] = pick;
       P->stage[op][mode] = (pick_flags & MP_VARIANT_STAGE_X) != 0;
       P->sorted[op][mode] = (pick_flags & MP_VARIANT_SORTED_ROWS) != 0;
+      if (mode == MP_SEQ) P->group_min[op] = pick_gmin;
     }
   }
   return MPS_OK;
@@ -416,7 +435,7 @@ int mp_plan_tune_cached(mp_plan* plan, const mp_csr* A, int reps, const char* ca
       int op, mode, rv, fl;
       if (sscanf(line, "%llx %d %d %d %d", &k, &op, &mode, &rv, &fl) != 5 || k != key) continue;
       if (op < 0 || op > 1 || mode < 0 || mode > 1 || (rv != 0 && !valid_rows_per_block(rv)) ||
-          (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS)))
+          (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS | MP_VARIANT_LANE_GROUPS | ~0xff)))
         continue;
       rpw[op][mode] = rv;
       flags[op][mode] = fl;
@@ -504,12 +523,19 @@ int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int ro
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if (rows_per_block != 0 && !valid_rows_per_block(rows_per_block))
     return fail(MPS_EINVAL, "rows per block must be 0, 16, 32 or 64");
-  if (flags & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS)) return fail(MPS_EINVAL, "unknown variant flags");
+  if (flags < 0 || (flags & 0xf8)) return fail(MPS_EINVAL, "unknown variant flags");
+  const int gmin = (flags & MP_VARIANT_LANE_GROUPS) ? (flags >> 8) : 0;
+  if ((flags & MP_VARIANT_LANE_GROUPS) &&
+      (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || gmin < 1))
+    return fail(MPS_EINVAL, "lane groups need MP_SEQ, sorted rows and a minimum row length >= 1");
+  if (!(flags & MP_VARIANT_LANE_GROUPS) && (flags >> 8))
+    return fail(MPS_EINVAL, "a minimum row length without MP_VARIANT_LANE_GROUPS");
   if ((flags & MP_VARIANT_STAGE_X) && (r = plan_x_rec(plan))) return r;
   if ((flags & MP_VARIANT_SORTED_ROWS) && (r = plan_row_order(plan, op, A->row_ptr))) return r;
   plan->rpw[op][mode] = rows_per_block;
   plan->stage[op][mode] = (flags & MP_VARIANT_STAGE_X) != 0;
   plan->sorted[op][mode] = (flags & MP_VARIANT_SORTED_ROWS) != 0;
+  if (mode == MP_SEQ) plan->group_min[op] = gmin;
   return MPS_OK;
 }
 
@@ -520,8 +546,10 @@ int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_blo
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   const int64_t rows = op ? plan->n_cols : plan->n_rows;
   *rows_per_block = plan->rpw[op][mode] ? plan->rpw[op][mode] : default_rows_per_block(rows, plan->nnz);
+  const bool srt = plan->sorted[op][mode] && plan->row_order[op];
+  const int gmin = (srt && mode == MP_SEQ) ? plan->group_min[op] : 0;
   *flags = ((plan->stage[op][mode] && plan->x_rec) ? MP_VARIANT_STAGE_X : 0) |
-           ((plan->sorted[op][mode] && plan->row_order[op]) ? MP_VARIANT_SORTED_ROWS : 0);
+           (srt ? MP_VARIANT_SORTED_ROWS : 0) | (gmin ? (MP_VARIANT_LANE_GROUPS | (gmin << 8)) : 0);
   return MPS_OK;
 }
 

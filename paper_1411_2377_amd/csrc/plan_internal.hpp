@@ -2,6 +2,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <vector>
+
 struct mp_plan {
   int device = 0;
   int L = 0;
@@ -18,6 +20,9 @@ struct mp_plan {
   bool sorted[2][2] = {{false, false}, {false, false}}; // rows by length for [op][mode]
   uint32_t* x_rec = nullptr;     // [max(n_rows, n_cols)] staged x records (allocated on demand)
   int32_t* row_order[2] = {nullptr, nullptr};  // rows of A / A^T by length, longest first
+  std::vector<int32_t> order_len[2];            // their lengths, in that order (host)
+  int group_min[2] = {0, 0};  // SEQ with sorted rows: rows of at least this many entries are
+                              // summed by lane groups (0: none), for [A, A^T]
 };
 
 namespace mpapi {

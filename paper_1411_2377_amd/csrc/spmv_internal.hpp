@@ -28,7 +28,7 @@ struct SpmvFuse {
 
 template <int L, int RPW, bool FUSE>
 void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.n_rows + RPW - 1) / RPW) * (unsigned)a.nrhs;
+  const unsigned grid = (unsigned)(a.long_blocks + (a.n_rows - a.n_long + RPW - 1) / RPW) * (unsigned)a.nrhs;
   if (mode == MP_SEQ && (a.rows || a.pipe))  // the four-wave pipelined kernel
     MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW, FUSE>), dim3(grid), dim3(256), 0, s, a);
   else if (mode == MP_SEQ)

@@ -19,6 +19,7 @@
 #pragma once
 #include "mp_core.hpp"
 #include "mp_exact.hpp"
+#include "mp_group.hpp"
 #include "solver_kernels.hpp"
 
 namespace mp {
@@ -74,6 +75,10 @@ struct SpmvArgs {
   // rows in processing order (block b takes rows[b * RPW ...]), or nullptr: 0, 1, 2, ...
   const int32_t* rows;
   int pipe;  // SEQ: the pipelined kernel even when rows == nullptr
+  // SEQ with a row order (plain products only): the first n_long rows of that order are summed
+  // by lane groups in the first long_blocks blocks; the other blocks take the rows after them
+  int64_t n_long;
+  int64_t long_blocks;
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
@@ -326,8 +331,111 @@ MPD int32_t wave_max32(int32_t v) {
 template <int RPW>
 constexpr int seq_sorted_q() { return RPW >= 64 ? 4 : 8; }
 
+// SEQ, the long rows at the head of the row order (decreasing length): 64 / L rows per block,
+// each summed by a group of L lanes of the first wavefront, one limb per lane
+// (group_add_rn: the same RN(y_i + t) as add_rn, with the limb loops spread over the lanes, so
+// one step of the serial chain the mode defines costs a few dozen wavefront instructions
+// instead of a few hundred).  The other three wavefronts form the rounded products of the next
+// chunk, kGroupQ further entries of every row, into the other half of a double buffer in LDS.
+constexpr int kGroupQ = 32;
+
+template <int L>
+__device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st) {
+  constexpr int RG = 64 / L;            // rows per block: one per lane group
+  constexpr int Q = kGroupQ;
+  constexpr int NS = RG * Q;            // product slots per chunk: row r's t-th at r * Q + t
+  constexpr int RS = Q * L + L;         // words per row in the limb buffer (padded: banks)
+  __shared__ int32_t g_rs[RG], g_len[RG];
+  __shared__ int32_t g_maxlen;
+  __shared__ uint32_t g_m[2][RG * RS];  // row r, entry t, limb w at r * RS + t * L + w
+  __shared__ int32_t g_h[2][RG * (Q + 1)];
+
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t r0 = blk * RG;
+  const int nr = (int)min((int64_t)RG, A.n_long - r0);
+  const uint32_t* const x_limb = A.x_limb;
+  const int32_t* const x_hdr = A.x_hdr;
+  if (wv == 0) {
+    const bool hr = lane < nr;
+    const int64_t row = hr ? (int64_t)A.rows[r0 + lane] : 0;
+    const int rs = hr ? A.row_ptr[row] : 0;
+    const int len = hr ? A.row_ptr[row + 1] - rs : 0;
+    if (lane < RG) {
+      g_rs[lane] = rs;
+      g_len[lane] = len;
+    }
+    const int mx = wave_max32(len);
+    if (lane == 0) g_maxlen = mx;
+  }
+  __syncthreads();
+  const int maxlen = g_maxlen;
+  const int nch = (maxlen + Q - 1) / Q;
+
+  auto produce = [&](int c, int b) {
+    for (int j = t - 64; j < NS; j += 192) {
+      const int r = j / Q, o = j % Q, e = c * Q + o;
+      int64_t k[1];
+      bool ok[1];
+      ok[0] = r < nr && e < g_len[r];
+      k[0] = ok[0] ? (int64_t)g_rs[r] + e : 0;
+      EntryLoad<L, 1> E;
+      load_entries<L, 1>(E, A, x_limb, x_hdr, k, ok);
+      if (!ok[0]) continue;
+      const int32_t ha = E.ha[0], hx = E.hx[0];
+      Num<L> p;
+      if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
+        set_zero(p, (uint32_t)(ha ^ hx) & 1u);
+      } else {
+        uint32_t pr[2 * L];
+        mul_full<L>(E.am[0], E.xm[0], pr);
+        round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, p, st);
+      }
+#pragma unroll
+      for (int w = 0; w < L; ++w) g_m[b][r * RS + o * L + w] = p.m[w];
+      g_h[b][r * (Q + 1) + o] = make_hdr(p.e, p.s);
+    }
+  };
+
+  const Group<L> G = group_of_lane<L>();
+  const int g = lane / L;
+  const int glen = (wv == 0 && g < nr) ? g_len[g] : 0;
+  uint32_t am = 0u, as = 0u;
+  int32_t ae = kZeroE;
+  if (wv > 0 && nch > 0) produce(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int b = c & 1;
+    if (wv > 0) {
+      if (c + 1 < nch) produce(c + 1, b ^ 1);
+    } else {
+      const int qn = min(Q, maxlen - c * Q);
+      for (int o = 0; o < qn; ++o) {
+        const bool act = c * Q + o < glen;  // rows that ended add +0 (their sum is kept)
+        const uint32_t pm = g_m[b][g * RS + o * L + G.w];
+        const int32_t ph = g_h[b][g * (Q + 1) + o];
+        group_add_rn<L>(G, am, ae, as, act ? pm : 0u, act ? (ph >> 1) : kZeroE,
+                        act ? ((uint32_t)ph & 1u) : 0u, st);
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0 && g < nr) {
+    const int64_t row = A.rows[r0 + g];
+    A.y_limb[(int64_t)G.w * A.y_ld + row] = am;
+    if (G.w == 0) A.y_hdr[row] = make_hdr(ae, as);
+  }
+}
+
 template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
+  if constexpr (!FUSE) {
+    if ((int64_t)blockIdx.x < A.long_blocks) {
+      uint32_t st = 0;
+      spmv_seq_group_rows<L>(A, blockIdx.x, st);
+      if (st) atomicOr(A.status, st);
+      return;
+    }
+  }
   constexpr int Q = seq_sorted_q<RPW>();
   constexpr int NS = RPW * Q;  // product slots per chunk: row r's t-th entry of the chunk at r*Q+t
   __shared__ int32_t s_rs[RPW], s_len[RPW];
@@ -339,7 +447,7 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   SpmvBlock B;
   if (!spmv_block<RPW>(A, B)) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t r0 = B.rb * RPW;
+  const int64_t r0 = A.n_long + (B.rb - A.long_blocks) * RPW;
   const uint32_t* const x_limb = A.x_limb + B.rhs * A.x_rstride;
   const int32_t* const x_hdr = A.x_hdr + B.rhs * A.x_rstride;
   const int64_t yo = B.rhs * A.y_rstride;

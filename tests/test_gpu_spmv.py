@@ -196,19 +196,110 @@ def test_every_kernel_variant_same_bits(p):
     for mode in (0, 1):
         want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
         want_t = ospmv.spmv(tp, ti, tv, go, p, mode)
+        combos = [(False, False, 0), (True, False, 0), (False, True, 0), (True, True, 0)]
+        if mode == 0:   # lane groups for every non-empty row, for rows of >= 2 and of >= 200
+            combos += [(False, True, 1), (True, True, 2), (True, True, 200)]
         for rows in (16, 32, 64):
-            for stage, srt in ((False, False), (True, False), (False, True), (True, True)):
-                P.set_variant(0, mode, rows, stage, srt)
-                P.set_variant(1, mode, rows, stage, srt)
-                tag = "%d rows per block, staged x %s, sorted rows %s, mode %d" % (rows, stage, srt, mode)
+            for stage, srt, gmin in combos:
+                P.set_variant(0, mode, rows, stage, srt, gmin)
+                P.set_variant(1, mode, rows, stage, srt, gmin)
+                tag = "%d rows per block, staged x %s, sorted rows %s, lane groups from %d, mode %d" % (
+                    rows, stage, srt, gmin, mode)
                 yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
                 assert_bitwise(yl, yh, want, p, what="A x, " + tag)
                 tl, th = M.mpspmv_csr_t(A, P, g, mode=mode).to_numpy()
                 assert_bitwise(tl, th, want_t, p, what="A^T g, " + tag)
     picks = P.tune(reps=1)
     assert {v[0] for v in picks.values()} <= {16, 32, 64}
+    assert all(v[3] == 0 for (op, m), v in picks.items() if m == 1)   # lane groups: SEQ only
     for mode in (0, 1):
         yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
         want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
         assert_bitwise(yl, yh, want, p, what="tuned A x mode %d" % mode)
+    assert M.mp_status() == 0
+
+
+def corner_rows(p, seed):
+    """Rows whose SEQ partial sums hit the corners of RN addition (x = 1, so the products are
+    the stored values): ties to even, the all-ones mantissa rounding up to a power of two,
+    cancellations of one, several and p bits, exact zeros, signed zeros, operands far apart,
+    and runs of values within a few binades of each other with mixed signs (differences of
+    exponents 0, 1 and 2 between partial sum and term)."""
+    rng = random.Random(seed)
+    one = MP(0, 1 << (p - 1), 1, p)
+
+    def pw(k, s=0):          # (-1)^s 2^k
+        return MP(s, 1 << (p - 1), k + 1, p)
+
+    def rnd(lo, hi, s=None):
+        return MP(rng.randint(0, 1) if s is None else s, rng.getrandbits(p) | (1 << (p - 1)),
+                  rng.randint(lo, hi), p)
+    allones = MP(0, (1 << p) - 1, 0, p)                     # 1 - 2^-p
+    rows = [
+        [one, pw(-p), pw(-p)],                                # two ties to even: 1
+        [MP(0, (1 << (p - 1)) | 1, 1, p), pw(-p)],            # 1 + 2^(1-p) + 2^-p: tie up
+        [allones, pw(-p - 1)],                                # carries into a new binade
+        [one, allones.neg()],                                 # cancellation of p bits
+        [one, one.neg()],                                     # exact zero: +0
+        [mpnum.zero(p, 1), mpnum.zero(p, 1)],                 # (-0) + (-0)
+        [pw(100), one, pw(100, 1)],                           # large cancellation leaves 1
+        [one, pw(-3000)],                                     # far apart
+        [pw(-3000), one],
+        [rnd(-2, 2) for _ in range(40)],
+        [rnd(0, 2) for _ in range(300)],
+        [rnd(-1, 1, 0) for _ in range(150)] + [rnd(-1, 1, 1) for _ in range(150)],
+        [allones] * 64 + [allones.neg()] * 63,
+        [rnd(-400, 400) for _ in range(257)],
+    ]
+    for _ in range(40):
+        k = rng.randint(1, 90)
+        rows.append([rnd(-3, 3) if rng.random() < 0.8 else mpnum.zero(p, rng.randint(0, 1))
+                     for _ in range(k)])
+    m = max(len(r) for r in rows)
+    rp, ci, vals = [0], [], []
+    for r in rows:
+        ci.extend(range(len(r)))
+        vals.extend(r)
+        rp.append(len(ci))
+    vl, vh = codec.encode(vals, p)
+    xl, xh = codec.encode([one] * m, p)
+    A = synth.CSRHost(len(rows), m, np.array(rp, np.int32), np.array(ci, np.int32), synth.MPHost(vl, vh, p))
+    return A, synth.MPHost(xl, xh, p)
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_lane_group_rows_corner_sums(p):
+    """Every row summed by lane groups (SEQ, sorted rows, rows of >= 1 entry) and by the
+    one-lane chains: both equal the oracle bit for bit on the corner-case rows."""
+    M = lib()
+    A_h, x_h = corner_rows(p, seed=p)
+    A = M.CSRMatrix.from_host(A_h)
+    x = M.MPArray.from_host(x_h)
+    want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), 0)
+    P = M.mp_plan_create(A)
+    for rows, stage, gmin in ((16, False, 1), (64, True, 1), (32, False, 0)):
+        P.set_variant(0, 0, rows, stage, True, gmin)
+        yl, yh = M.mpspmv_csr(A, x, mode=0, plan=P).to_numpy()
+        assert_bitwise(yl, yh, want, p, what="corner rows, lane groups from %d" % gmin)
+    assert M.mp_status() == 0
+
+
+@pytest.mark.parametrize("p", [128, 256, 512])
+def test_powerlaw_lane_groups_sampled(p):
+    """The power-law workload at full size with the longest rows summed by lane groups (rows
+    of >= 64 entries): sampled rows, always including the longest ones, equal the oracle."""
+    M = lib()
+    A_h, x_h, _ = synth.config3(p=p)
+    A = M.CSRMatrix.from_host(A_h)
+    x = M.MPArray.from_host(x_h)
+    P = M.mp_plan_create(A)
+    P.set_variant(0, 0, 16, True, True, 64)
+    yl, yh = M.mpspmv_csr(A, x, mode=0, plan=P).to_numpy()
+    lengths = np.diff(A_h.row_ptr)
+    order = np.argsort(-lengths, kind="stable")
+    rng = np.random.default_rng(p)
+    rows = np.unique(np.concatenate([order[:6], order[np.sum(lengths >= 64) - 3:np.sum(lengths >= 64) + 3],
+                                     rng.integers(0, A_h.n_rows, 40)]))
+    want = oracle_spmv_rows(A_h, x_h, rows, 0)
+    assert_bitwise(yl[:, rows], yh[rows], want, p, what="power-law rows by lane groups")
     assert M.mp_status() == 0
