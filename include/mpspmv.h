@@ -120,7 +120,8 @@ typedef struct {
  * bytes (the vectors and matrix entries the kernel must read and write once) are added to the
  * struct per kernel class: [0] sparse products that also form the step's inner products of
  * their output, [1] other sparse products, [2] direction steps, [3] update steps (with the
- * inner products they form), [4] GPBiCG's t, s, y step. */
+ * inner products they form), [4] the middle element-wise step (GPBiCG's t, s, y; CGS's q, u^, x;
+ * BiCGSTAB's s). */
 typedef struct mp_solve_profile {
   int64_t launches[5];
   double us[5];
@@ -132,7 +133,7 @@ typedef struct mp_solve_profile {
 #define MP_NC 1              /* not convergent within maxit (Tables 1-2: "NC") */
 #define MP_BREAKDOWN_RHO 2   /* rho = 0: the listings' "exits" */
 #define MP_BREAKDOWN_SIGMA 3 /* the denominator of alpha is 0 */
-#define MP_BREAKDOWN_ZETA 4  /* GPBiCG: zeta = 0 */
+#define MP_BREAKDOWN_ZETA 4  /* GPBiCG: zeta = 0; BiCGSTAB: omega = 0 */
 #define MP_BREAKDOWN_TAU 5   /* GPBiCG: tau = 0 (or mu5 = 0 in the first iteration) */
 
 typedef struct {
@@ -187,7 +188,8 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
  * MP_VARIANT_STAGE_X they first stage x as one contiguous record per element (one cache line per
  * gathered x_j instead of one per limb, which pays for scattered columns); with
  * MP_VARIANT_SORTED_ROWS the blocks take the rows in order of decreasing length (the plan holds
- * the order), so that a block's rows have similar lengths.  op 0 is the product with A, op 1
+ * the order), so that a block's rows have similar lengths; MP_VARIANT_LANE_GROUPS (below) adds
+ * lane groups for the longest rows of a SEQ product.  op 0 is the product with A, op 1
  * with A^T.  mp_plan_tune times every variant of the four products (both ops, both modes;
  * `reps` launches each, 0: 3) on a generated operand, synchronously on `stream`, and stores the
  * fastest in the plan; the plan then selects it for mpspmv_csr, mpspmv_csr_t and the solvers
@@ -198,6 +200,12 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
  * MPS_OK or MPS_EINVAL (also MPS_ENOMEM, MPS_EHIP). */
 #define MP_VARIANT_STAGE_X 1
 #define MP_VARIANT_SORTED_ROWS 2
+/* SEQ products with MP_VARIANT_SORTED_ROWS: the rows with at least n stored entries (flags
+ * MP_VARIANT_LANE_GROUPS | MP_VARIANT_GROUP_MIN(n), 1 <= n < 2^23) are each summed by a group of
+ * L lanes holding one limb each, so that the serial rounding chain of a long row advances many
+ * times faster; the other rows as before.  Same result bits. */
+#define MP_VARIANT_LANE_GROUPS 4
+#define MP_VARIANT_GROUP_MIN(n) ((n) << 8)
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
 int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
                         int flags);
@@ -241,6 +249,26 @@ int bicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
  * opts->transpose != 0 (NULL: built inside the call). */
 int gpbicg(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
            const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
+/* CGS (conjugate gradient squared) for A x = b (or A^T x = b), one of the product-type methods
+ * of Sec. 4 (Tables 1 and 3; the paper names it without printing it), with K = I, the shadow
+ * residual r~ = r_0 and the stopping test (*):  u = r + beta q, p = u + beta (q + beta p)
+ * (u = p = r first), alpha = rho / (r~, A p), q = u - alpha A p, u^ = u + q, x = x + alpha u^,
+ * r = r - alpha A u^, beta = rho' / rho.  Statuses: MP_BREAKDOWN_RHO (rho = 0),
+ * MP_BREAKDOWN_SIGMA ((r~, A p) = 0).  Same conventions as gpbicg (plan needed only when
+ * opts->transpose != 0). */
+int cgs(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
+        const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
+/* BiCGSTAB for A x = b (or A^T x = b), the other product-type method of Sec. 4 (Tables 1 and 3,
+ * unpreconditioned here), K = I, r~ = r_0, stopping test (*):  p = r + beta (p - omega v)
+ * (p = r first), v = A p, alpha = rho / (r~, v), s = r - alpha v, t = A s,
+ * omega = (t, s) / (t, t) (0 when (t, t) = 0), x = x + alpha p + omega s, r = s - omega t,
+ * beta = (rho' / rho) (alpha / omega).  Statuses: MP_BREAKDOWN_RHO, MP_BREAKDOWN_SIGMA
+ * ((r~, v) = 0) and MP_BREAKDOWN_ZETA (omega = 0 without convergence: the next beta is
+ * undefined).  Same conventions as gpbicg. */
+int bicgstab(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
+             const mp_solve_opts *opts, mp_solve_info *info, void *stream);
 
 /* Batched GPBiCG: nsys systems A[0..nsys-1] (square, same precision, sizes may differ), each
  * with nrhs right-hand sides, solved as nsys * nrhs independent GPBiCG solves (the method of

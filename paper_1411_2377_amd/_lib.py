@@ -112,6 +112,10 @@ SIGNATURES = {
              ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "gpbicg": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "cgs": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+            ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "bicgstab": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+                 ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "gpbicg_batched": [ctypes.c_int, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.POINTER(MpVec),
                        ctypes.POINTER(MpVec), ctypes.POINTER(MpSolveOpts),
                        ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],

@@ -742,6 +742,146 @@ int gpbicg_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x
   return finish_solve(W, info, st);
 }
 
+// ---- CGS and BiCGSTAB -------------------------------------------------------------------
+// The paper's other two product-type methods (Sec. 4, Tables 1 and 3), K = I, with the same
+// setup, stopping test, graph replays and breakdown statuses as BiCG and GPBiCG.
+
+namespace {
+
+// Set up a solve whose plan is needed only for a transposed system (NULL: built here).
+int plan_for(const mp_csr* A, const mp_plan*& plan, const mp_solve_opts* o, OwnedPlan& own,
+             hipStream_t user) {
+  int r;
+  if (o->transpose) {
+    if (!plan) {
+      if ((r = plan_build(A, user, &own.p))) return r;
+      plan = own.p;
+    } else if ((r = check_plan(plan, A))) {
+      return r;
+    }
+  } else if (plan && (r = check_plan(plan, A))) {
+    return r;
+  }
+  return MPS_OK;
+}
+
+// Clear work vectors first..last-1 (those a first iteration reads before writing).
+int clear_vectors(const Work& W, int first, int last, uint32_t* st) {
+  mp::VecArgs a = ew_args(W, st);
+  for (int i = first; i < last; ++i) {
+    a.v[0] = W.vec(i);
+    int r = launch_ew(W.L, EW_ZERO, a, W.ws);
+    if (r) return r;
+  }
+  return MPS_OK;
+}
+
+}  // namespace
+
+// CGS work vectors: 0 r, 1 rt, 2 A p and then A u^, 3 u, 4 p, 5 q, 6 u^
+int cgs_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+             const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if ((r = plan_for(A, plan, o, own, user))) return r;
+  const int L = limbs_of(A->prec);
+  Work W;
+  if ((r = work_alloc(W, L, A->row_dim, 7, user))) return r;
+  Op op, opT;
+  make_ops(A, plan, o->transpose, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  if ((r = clear_vectors(W, 2, 7, st))) return r;
+  if ((r = prof_init(W, o->profile))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), AV = W.vec(2), U = W.vec(3), P = W.vec(4),
+                   Q = W.vec(5), UH = W.vec(6);
+  const mp::VecRef X = ref(*x);
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
+  // per iteration: u, p; A p with (r~, A p); alpha, q, u^, x; A u^; r with (r, r) and (r~, r)
+  // (their last block: stopping test, beta)
+  auto iteration = [&]() -> int {
+    int rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = U; a.v[1] = P; a.v[2] = R; a.v[3] = Q;
+    if ((rr = timed(W, PROF_DIR, vec_bytes(W, 5), [&] { return launch_ew(L, EW_CGS_DIR, a, W.ws); })))
+      return rr;
+    const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_SIGMA}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, AV, st, true, &sig); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = Q; a.v[1] = UH; a.v[2] = X; a.v[3] = U; a.v[4] = AV;
+    set_fd(W, a, mp::EPI_NONE, {});
+    if ((rr = timed(W, PROF_TSY, vec_bytes(W, 6), [&] { return launch_ew(L, EW_CGS_QUX, a, W.ws); })))
+      return rr;
+    if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, op, o->mode, UH, AV, st, true); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = R; a.v[1] = AV; a.v[2] = RT;
+    set_fd(W, a, mp::EPI_BICG_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
+    return timed(W, PROF_UPD, vec_bytes(W, 4), [&] { return launch_ew(L, EW_CGS_R, a, W.ws); });
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
+// BiCGSTAB work vectors: 0 r, 1 rt, 2 (unused), 3 p, 4 v = A p, 5 s, 6 t = A s
+int bicgstab_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+                  const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if ((r = plan_for(A, plan, o, own, user))) return r;
+  const int L = limbs_of(A->prec);
+  Work W;
+  if ((r = work_alloc(W, L, A->row_dim, 7, user))) return r;
+  Op op, opT;
+  make_ops(A, plan, o->transpose, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  if ((r = clear_vectors(W, 2, 7, st))) return r;
+  if ((r = prof_init(W, o->profile))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), P = W.vec(3), V = W.vec(4), S = W.vec(5),
+                   T = W.vec(6);
+  const mp::VecRef X = ref(*x);
+  const mp::VecRef self{nullptr, nullptr, 0};
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
+  // per iteration: p; v = A p with (r~, v); alpha, s; t = A s with (t, s), (t, t); omega, x, r
+  // with (r, r) and (r~, r) (their last block: stopping test, omega = 0 exit, beta)
+  auto iteration = [&]() -> int {
+    int rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = P; a.v[1] = R; a.v[2] = V;
+    if ((rr = timed(W, PROF_DIR, vec_bytes(W, 4), [&] { return launch_ew(L, EW_STAB_DIR, a, W.ws); })))
+      return rr;
+    const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_SIGMA}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, V, st, true, &sig); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = S; a.v[1] = R; a.v[2] = V;
+    set_fd(W, a, mp::EPI_NONE, {});
+    if ((rr = timed(W, PROF_TSY, vec_bytes(W, 3), [&] { return launch_ew(L, EW_STAB_S, a, W.ws); })))
+      return rr;
+    const SpmvFuse ts = fuse_of(W, mp::EPI_NONE, {{S, 4, mp::S_MU2}, {self, 7, mp::S_MU5}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, S, T, st, true, &ts); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = X; a.v[1] = R; a.v[2] = P; a.v[3] = S; a.v[4] = T; a.v[5] = RT;
+    set_fd(W, a, mp::EPI_GP_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
+    return timed(W, PROF_UPD, vec_bytes(W, 8), [&] { return launch_ew(L, EW_STAB_XR, a, W.ws); });
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
 // ---- batched GPBiCG --------------------------------------------------------------------
 // nsys systems, nrhs right-hand sides each: nsys * nrhs independent solves ("pairs", pair
 // s * nrhs + k) advanced together.  The systems are concatenated into one block-diagonal CSR
@@ -969,6 +1109,18 @@ int gpbicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
            const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
   return gpbicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int cgs(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+        const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return cgs_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int bicgstab(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+             const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return bicgstab_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 
 int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec* x,

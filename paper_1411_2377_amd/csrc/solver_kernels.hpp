@@ -123,6 +123,7 @@ enum Pro {
   PRO_BICG_ALPHA = 1,  // sigma = (pt, z): alpha = rho / sigma (sigma = 0: breakdown)
   PRO_GP_ALPHA,        // den = (rt, q): alpha = rho / den (den = 0: breakdown)
   PRO_GP_ZETA,         // mu1..mu5: zeta, eta (and tau after the first iteration)
+  PRO_STAB_OMEGA,      // BiCGSTAB: (t, s), (t, t): omega = (t, s) / (t, t), or 0 when (t, t) = 0
 };
 
 // Scalar operations of the prologues and epilogues, returning their status bits with the value.
@@ -369,6 +370,15 @@ MPD uint32_t prologue_body(int kind, uint32_t* i_limb, int32_t* i_hdr, int iters
         brk = kBreakSigma + 1;
       } else if (lane == 0) {
         const NumSt<L> q = s_div<L>(rho, den);
+        st = q.st;
+        put(0, q.v);
+      }
+      break;
+    }
+    case PRO_STAB_OMEGA: {
+      const Num<L> ts = in(0), tt = in(1);
+      if (!is_zero(tt) && lane == 0) {  // (t, t) = 0: t = 0, omega stays +0
+        const NumSt<L> q = s_div<L>(ts, tt);
         st = q.st;
         put(0, q.v);
       }
@@ -1151,6 +1161,19 @@ MPD uint32_t prologue_wave(ProLds<L>& P, int kind, const Scalars& S, int iters, 
     keep_in(2, mu3);
     keep_in(3, mu[1]);
     keep_in(4, mu[2]);
+  } else if (kind == PRO_STAB_OMEGA) {  // (t, s), (t, t) in rings 4 and 7
+    Num<L> mu[2];
+    int32_t lo[2], hi[2];
+    ring_peek<L, 2>(dw, abase, {4, 7}, mu, lo, hi, lds, pcap, st0);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        P.rlo[k] = lo[k];
+        P.rhi[k] = hi[k];
+      }
+    }
+    keep_in(0, mu[0]);
+    keep_in(1, mu[1]);
   } else {  // sigma or den in ring 0, rho
     const Num<L> rho = sload<L>(S, S_RHO);  // requested first
     Num<L> d[1];
@@ -1177,6 +1200,12 @@ MPD int prologue_rings(int kind, int (&clr)[3]) {
     clr[1] = 6;
     clr[2] = 7;
     return 3;
+  }
+  if (kind == PRO_STAB_OMEGA) {
+    clr[0] = 4;
+    clr[1] = 7;
+    clr[2] = 0;
+    return 2;
   }
   clr[0] = clr[1] = clr[2] = 0;
   return 1;
@@ -1568,6 +1597,167 @@ __global__ void __launch_bounds__(256) gp_update_kernel(GpUpdArgs G) {
   }
   dots_finish<L, 256, !SEP, true>(A.dots, A.fd, c.pair, A.batch.pair_of_tile != nullptr, c.idx, c.nblocks, c.ctl, c.S,
                       A.batch.ndone, A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
+}
+
+// ------------------------------------------------------------------------------------------
+// CGS and BiCGSTAB steps (the paper's other product-type methods, K = I; one RN per operation
+// in the order written).
+// ------------------------------------------------------------------------------------------
+
+// CGS direction: v = {u, p, r, q}.  First iteration u = p = r; then u = r + beta q,
+// p = u + beta (q + beta p), beta = rho / rho_old (the stopping test's epilogue formed it).
+template <int L>
+__global__ void __launch_bounds__(256) cgs_dir_kernel(VecArgs A) {
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const bool first = c.ctl->iters == 0;
+  const Num<L> beta = sload<L>(c.S, S_BETA);
+  MP_ELEMENTWISE_LOOP(A) {
+    const Num<L> r = vload<L>(A.v[2], i), q = vload<L>(A.v[3], i), p = vload<L>(A.v[1], i);
+    if (first) {
+      vstore<L>(A.v[0], i, r);
+      vstore<L>(A.v[1], i, r);
+    } else {
+      const Num<L> u = add_rn<L>(r, mul_rn<L>(beta, q, st), st);
+      vstore<L>(A.v[0], i, u);
+      const Num<L> qbp = add_rn<L>(q, mul_rn<L>(beta, p, st), st);
+      vstore<L>(A.v[1], i, add_rn<L>(u, mul_rn<L>(beta, qbp, st), st));
+    }
+  }
+  if (st) atomicOr(A.status, st);
+}
+
+// CGS q, u^, x: v = {q, uh, x, u, vh}.  alpha = rho / (r~, A p) (the product's inner product,
+// still in its ring; zero: breakdown); q = u - alpha vh, u^ = u + q, x = x + alpha u^.
+template <int L>
+__global__ void __launch_bounds__(256) cgs_qux_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
+                                     {S_ALPHA, 0, 0}, st);
+  const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; !pro.brk && i < A.n; i += (int64_t)gridDim.x * 256) {
+    const Num<L> u = vload<L>(A.v[3], i), vh = vload<L>(A.v[4], i), x = vload<L>(A.v[2], i);
+    const Num<L> q = sub_rn<L>(u, mul_rn<L>(alpha, vh, st), st);
+    vstore<L>(A.v[0], i, q);
+    const Num<L> uh = add_rn<L>(u, q, st);
+    vstore<L>(A.v[1], i, uh);
+    vstore<L>(A.v[2], i, add_rn<L>(x, mul_rn<L>(alpha, uh, st), st));
+  }
+  dots_finish<L, 256, false>(A.dots, A.fd, c.pair, false, c.idx, c.nblocks, c.ctl, c.S, A.batch.ndone,
+                             A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
+}
+
+// CGS residual: v = {r, qh, rt}.  r = r - alpha qh, then the inner products (r, r) and (r~, r)
+// (fd slots 0 and 1); the last block's epilogue runs the stopping test and forms beta.
+template <int L>
+__global__ void __launch_bounds__(256) cgs_r_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    Num<L> r, rt;
+    set_zero(r, 0);
+    set_zero(rt, 0);
+    if (ok) {
+      const Num<L> r0 = vload<L>(A.v[0], i), qh = vload<L>(A.v[1], i);
+      rt = vload<L>(A.v[2], i);
+      r = sub_rn<L>(r0, mul_rn<L>(alpha, qh, st), st);
+      vstore<L>(A.v[0], i, r);
+    }
+    const int32_t hr = make_hdr(r.e, r.s), hrt = make_hdr(rt.e, rt.s);
+    pass_dot<L, 256>(lds, ok, hr, hr, r.m, r.m, A.dots, c.abase + A.fd.slot[0]);
+    pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
+  }
+  dots_finish<L, 256, true>(A.dots, A.fd, c.pair, false, c.idx, c.nblocks, c.ctl, c.S, A.batch.ndone,
+                            A.status, st, lds.win, lds_window_digits<L, 256>());
+}
+
+// BiCGSTAB direction: v = {p, r, v}.  First iteration p = r; then
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega) (formed by the epilogue of
+// the stopping test), omega in the zeta slot.
+template <int L>
+__global__ void __launch_bounds__(256) stab_dir_kernel(VecArgs A) {
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const bool first = c.ctl->iters == 0;
+  const Num<L> beta = sload<L>(c.S, S_BETA), omega = sload<L>(c.S, S_ZETA);
+  MP_ELEMENTWISE_LOOP(A) {
+    const Num<L> r = vload<L>(A.v[1], i), p = vload<L>(A.v[0], i), v = vload<L>(A.v[2], i);
+    if (first) {
+      vstore<L>(A.v[0], i, r);
+    } else {
+      const Num<L> d = sub_rn<L>(p, mul_rn<L>(omega, v, st), st);
+      vstore<L>(A.v[0], i, add_rn<L>(r, mul_rn<L>(beta, d, st), st));
+    }
+  }
+  if (st) atomicOr(A.status, st);
+}
+
+// BiCGSTAB s: v = {s, r, v}.  alpha = rho / (r~, A p) (zero: breakdown); s = r - alpha v.
+template <int L>
+__global__ void __launch_bounds__(256) stab_s_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const ProOut pro = run_prologue<L>(pl, PRO_BICG_ALPHA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
+                                     {S_ALPHA, 0, 0}, st);
+  const Num<L> alpha = lds_num<L>(pl.limb, pl.hdr, 0);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; !pro.brk && i < A.n; i += (int64_t)gridDim.x * 256) {
+    const Num<L> r = vload<L>(A.v[1], i), v = vload<L>(A.v[2], i);
+    vstore<L>(A.v[0], i, sub_rn<L>(r, mul_rn<L>(alpha, v, st), st));
+  }
+  dots_finish<L, 256, false>(A.dots, A.fd, c.pair, false, c.idx, c.nblocks, c.ctl, c.S, A.batch.ndone,
+                             A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
+}
+
+// BiCGSTAB update: v = {x, r, p, s, t, rt}.  omega = (t, s) / (t, t) (the product's inner
+// products, still in their rings; 0 when (t, t) = 0); x = x + alpha p + omega s,
+// r = s - omega t; then (r, r) and (r~, r) (fd slots 0 and 1); the last block's epilogue runs
+// the stopping test, the omega = 0 exit and forms beta.
+template <int L>
+__global__ void __launch_bounds__(256) stab_xr_kernel(VecArgs A) {
+  __shared__ PassLds<L, 256> lds;
+  __shared__ ProLds<L> pl;
+  const EwCtx c = ew_ctx(A);
+  if (solve_done(c.ctl)) return;
+  uint32_t st = 0;
+  const ProOut pro = run_prologue<L>(pl, PRO_STAB_OMEGA, c, A.dots, lds.win, lds_window_digits<L, 256>(), 1,
+                                     {S_ZETA, 0, 0}, st);
+  const Num<L> omega = lds_num<L>(pl.limb, pl.hdr, 0);
+  const Num<L> alpha = sload<L>(c.S, S_ALPHA);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256; i0 < A.n; i0 += (int64_t)gridDim.x * 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool ok = i < A.n;
+    Num<L> r, rt;
+    set_zero(r, 0);
+    set_zero(rt, 0);
+    if (ok) {
+      const Num<L> x = vload<L>(A.v[0], i), p = vload<L>(A.v[2], i), s = vload<L>(A.v[3], i);
+      const Num<L> t = vload<L>(A.v[4], i);
+      rt = vload<L>(A.v[5], i);
+      const Num<L> xa = add_rn<L>(x, mul_rn<L>(alpha, p, st), st);
+      vstore<L>(A.v[0], i, add_rn<L>(xa, mul_rn<L>(omega, s, st), st));
+      r = sub_rn<L>(s, mul_rn<L>(omega, t, st), st);
+      vstore<L>(A.v[1], i, r);
+    }
+    const int32_t hr = make_hdr(r.e, r.s), hrt = make_hdr(rt.e, rt.s);
+    pass_dot<L, 256>(lds, ok, hr, hr, r.m, r.m, A.dots, c.abase + A.fd.slot[0]);
+    pass_dot<L, 256>(lds, ok, hrt, hr, rt.m, r.m, A.dots, c.abase + A.fd.slot[1]);
+  }
+  dots_finish<L, 256, true>(A.dots, A.fd, c.pair, false, c.idx, c.nblocks, c.ctl, c.S, A.batch.ndone,
+                            A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
 // Write a constant into element 0 of a vector or a scalar slot (kernel arguments carry it).

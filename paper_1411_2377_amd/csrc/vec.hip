@@ -121,6 +121,12 @@ int launch_ew(int L, EwKind kind, const mp::VecArgs& a, hipStream_t s) {
     case EW_BICG_UPDATE: MPS_EW_CASES_SEP(bicg_update_kernel, a, a.pro_sep); break;
     case EW_GP_DIR: MPS_EW_CASES(gp_dir_kernel, a); break;
     case EW_GP_TSY: MPS_EW_CASES_SEP(gp_tsy_kernel, a, a.pro_sep); break;
+    case EW_CGS_DIR: MPS_EW_CASES(cgs_dir_kernel, a); break;
+    case EW_CGS_QUX: MPS_EW_CASES(cgs_qux_kernel, a); break;
+    case EW_CGS_R: MPS_EW_CASES(cgs_r_kernel, a); break;
+    case EW_STAB_DIR: MPS_EW_CASES(stab_dir_kernel, a); break;
+    case EW_STAB_S: MPS_EW_CASES(stab_s_kernel, a); break;
+    case EW_STAB_XR: MPS_EW_CASES(stab_xr_kernel, a); break;
     default: return fail(MPS_EINVAL, "bad element-wise kernel");
   }
   hipError_t e = hipGetLastError();

@@ -9,7 +9,8 @@
 namespace mpapi {
 
 enum EwKind {
-  EW_AXPY, EW_COPY, EW_ZERO, EW_SUB, EW_BICG_DIR, EW_BICG_UPDATE, EW_GP_DIR, EW_GP_TSY
+  EW_AXPY, EW_COPY, EW_ZERO, EW_SUB, EW_BICG_DIR, EW_BICG_UPDATE, EW_GP_DIR, EW_GP_TSY,
+  EW_CGS_DIR, EW_CGS_QUX, EW_CGS_R, EW_STAB_DIR, EW_STAB_S, EW_STAB_XR
 };
 
 mp::VecRef ref(const mp_vec& v);

@@ -1,6 +1,6 @@
-"""GPU parity of the BiCG and GPBiCG drivers against the oracle: every iterate is deterministic,
-so the final x, the status, the iteration count and the residual history must agree bit for
-bit, in both accumulation modes, for every graph chunk size."""
+"""GPU parity of the BiCG, GPBiCG, CGS and BiCGSTAB drivers against the oracle: every iterate is
+deterministic, so the final x, the status, the iteration count and the residual history must
+agree bit for bit, in both accumulation modes, for every graph chunk size."""
 from fractions import Fraction
 
 import numpy as np
@@ -51,7 +51,7 @@ def run_both(solver, A_h, b_h, mode, maxit, rtol=(1, -20), atol=(1, -50), transp
     A = M.CSRMatrix.from_host(A_h)
     b = M.MPArray.from_host(b_h)
     plan = M.mp_plan_create(A)
-    fn = M.bicg if solver == "bicg" else M.gpbicg
+    fn = getattr(M, solver)
     outs = []
     for ch in chunks:
         x, info = fn(A, b, plan=plan, mode=mode, maxit=maxit, rtol=rtol, atol=atol, chunk=ch,
@@ -68,7 +68,7 @@ def run_both(solver, A_h, b_h, mode, maxit, rtol=(1, -20), atol=(1, -50), transp
     if solver == "bicg":
         ref = krylov.bicg(mv, rmv, bo, c_rel, c_abs, maxit, p)
     else:
-        ref = krylov.gpbicg(mv, bo, c_rel, c_abs, maxit, p)
+        ref = getattr(krylov, solver)(mv, bo, c_rel, c_abs, maxit, p)
     assert (info.status, info.iters) == (ref.status, ref.iters), (info, ref.status, ref.iters)
     assert_bitwise(xl, xh, ref.x, p, what="%s x" % solver)
     if ref.iters:
@@ -91,7 +91,7 @@ def rhs_ones(A_h):
     return synth.MPHost(bl, bh, p), want
 
 
-@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_convdiff_small_fixed_iterations(solver, mode):
     A_h, _ = synth.config2(p=256, m=12)
@@ -100,7 +100,7 @@ def test_convdiff_small_fixed_iterations(solver, mode):
              b_oracle=b_o)
 
 
-@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
 @pytest.mark.parametrize("p", [128, 512])
 def test_convergence_to_tolerance(solver, p):
     A_h, _ = synth.config2(p=p, m=6)
@@ -109,7 +109,7 @@ def test_convergence_to_tolerance(solver, p):
     assert info.status == krylov.CONVERGED
 
 
-@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
 def test_transposed_solve(solver):
     A_h, _ = synth.config2(p=256, m=8)
     rng = np.random.default_rng(2)
@@ -123,17 +123,37 @@ def test_breakdown_and_not_converged():
     one = synth.mp_from_ints([1, 1], p)
     A_h = synth.CSRHost(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), one)
     b_h = synth.mp_from_ints([1, 0], p)
-    for solver, want in (("bicg", krylov.BREAKDOWN_SIGMA), ("gpbicg", krylov.BREAKDOWN_SIGMA)):
+    for solver, want in (("bicg", krylov.BREAKDOWN_SIGMA), ("gpbicg", krylov.BREAKDOWN_SIGMA),
+                         ("cgs", krylov.BREAKDOWN_SIGMA), ("bicgstab", krylov.BREAKDOWN_SIGMA)):
         info, ref = run_both(solver, A_h, b_h, 0, maxit=10)
         assert info.status == want and info.iters == 0
     A2, _ = synth.config2(p=p, m=5)
     b2, b2o = rhs_ones(A2)
     info, ref = run_both("bicg", A2, b2, 0, maxit=1, b_oracle=b2o)
     assert info.status == krylov.NOT_CONVERGED and info.iters == 1
+    for solver in ("cgs", "bicgstab"):
+        info, ref = run_both(solver, A2, b2, 1, maxit=1, b_oracle=b2o)
+        assert info.status == krylov.NOT_CONVERGED and info.iters == 1
     # a zero right-hand side meets the test at once
     z = synth.mp_zeros(A2.n_rows, p)
-    info, ref = run_both("gpbicg", A2, z, 0, maxit=5)
-    assert info.status == krylov.CONVERGED and info.iters == 0
+    for solver in ("gpbicg", "cgs", "bicgstab"):
+        info, ref = run_both(solver, A2, z, 0, maxit=5)
+        assert info.status == krylov.CONVERGED and info.iters == 0
+
+
+def test_bicgstab_omega_zero_cases():
+    """(t, t) = 0 gives omega = 0: on A = I the first half step already solves (one iteration,
+    converged); on the singular A = [[1, 1], [0, 0]] with b = (1, 1), A s = 0 with s != 0 ends
+    in the omega = 0 exit."""
+    p = 256
+    I3 = synth.CSRHost(3, 3, np.array([0, 1, 2, 3], np.int32), np.array([0, 1, 2], np.int32),
+                       synth.mp_from_ints([1, 1, 1], p))
+    info, ref = run_both("bicgstab", I3, synth.mp_from_ints([2, 3, 4], p), 0, maxit=10)
+    assert info.status == krylov.CONVERGED and info.iters == 1
+    sing = synth.CSRHost(2, 2, np.array([0, 2, 2], np.int32), np.array([0, 1], np.int32),
+                         synth.mp_from_ints([1, 1], p))
+    info, ref = run_both("bicgstab", sing, synth.mp_from_ints([1, 1], p), 1, maxit=10)
+    assert info.status == krylov.BREAKDOWN_ZETA and info.iters == 1
 
 
 @pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
@@ -145,7 +165,7 @@ def test_convdiff_full_size_first_iterations(solver, mode):
     run_both(solver, A_h, b_h, mode, maxit=2, rtol=(1, -20), atol=(1, -50), b_oracle=b_o)
 
 
-@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
 def test_scaled_3d_ill_conditioned_iterates(solver):
     """The row-scaled 3-D operator (d_i = 10^u, u ~ U(-15, 15); condition about 1e30) at
     p = 512 on an 8^3 grid: 40 iterations bit-identical to the oracle in EXACT mode."""
@@ -165,14 +185,17 @@ def test_profiled_solve_same_bits_and_counts():
     """A profiled solve (eager launches, timing events attached to the kernels) gives the bits
     of a graph-replayed one and counts every iteration kernel in its class: BiCG one fused SpMV,
     one A^T product, one direction and one update step per iteration; GPBiCG two fused SpMVs,
-    one direction, one update and one t/s/y step."""
+    one direction, one update and one t/s/y step; CGS one fused and one plain SpMV, one
+    direction, one q/u^/x and one residual step; BiCGSTAB two fused SpMVs, one direction, one s
+    and one x/r step."""
     M = lib()
     A_h, _ = synth.config2(p=256, m=12)
     b_h, _ = rhs_ones(A_h)
     A = M.CSRMatrix.from_host(A_h)
     b = M.MPArray.from_host(b_h)
     plan = M.mp_plan_create(A)
-    for fn, per in ((M.bicg, (1, 1, 1, 1, 0)), (M.gpbicg, (2, 0, 1, 1, 1))):
+    for fn, per in ((M.bicg, (1, 1, 1, 1, 0)), (M.gpbicg, (2, 0, 1, 1, 1)), (M.cgs, (1, 1, 1, 1, 1)),
+                    (M.bicgstab, (2, 0, 1, 1, 1))):
         for mode in (0, 1):
             kw = dict(plan=plan, mode=mode, maxit=10, rtol=(1, -60), atol=(0, 0))
             x0, i0 = fn(A, b, chunk=4, **kw)
