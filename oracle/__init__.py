@@ -13,5 +13,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   blas.dot / axpy / xpby : pinned (Fraction definitions)
   krylov.bicg / gpbicg : pinned (recursive vs true residual, BiCG = CG on symmetric matrices,
       small systems against exact Gaussian elimination, forced breakdowns)
+  krylov.cgs / bicgstab : pinned (small systems against exact Gaussian elimination, recursive
+      vs true residual, BiCG's Lanczos coefficients, BiCGSTAB's r orthogonal to t, breakdowns)
+  dense.gemv : pinned (Fraction sums, the sparse product of the same matrix without its zeros,
+      integer rows summed exactly, the sequential-summation bound)
 """
-from . import blas, codec, krylov, mpnum, spmv  # noqa: F401
+from . import blas, codec, dense, krylov, mpnum, spmv  # noqa: F401

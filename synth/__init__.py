@@ -419,3 +419,28 @@ def config5(p=512, m=64, seed=5):
     true solution [1..n] (b = A x* formed by the solver side), adjoint right-hand side ones."""
     A = convdiff3d_scaled(m, p, seed=seed)
     return A, mp_arange1(A.n_rows, p), mp_ones(A.n_rows, p)
+
+
+def lotkin(n, p, zero_pct, seed=6):
+    """The Lotkin matrix of the paper's SpMV benchmark (first row all ones, a_ij = 1/(i+j-1)
+    below it, 1-based), each element chopped to p bits, with round(zero_pct * n^2 / 100) of its
+    n^2 elements (positions drawn with a seeded permutation) set to +0.  Returns the dense
+    row-major array (n^2 elements, zeros stored), the CSR of its non-zero elements, and
+    x = [1, 2, ..., n]."""
+    rng = np.random.default_rng(seed)
+    table = mp_from_rationals([(1, k) for k in range(1, 2 * n)], p)   # 1/k, k = 1 .. 2n-1
+    i = np.arange(n, dtype=np.int64)[:, None]
+    j = np.arange(n, dtype=np.int64)[None, :]
+    k = np.where(i == 0, 1, i + j + 1)                                 # 1-based i + j - 1
+    dense = table.take((k - 1).reshape(-1))
+    nz = int(round(zero_pct * n * n / 100.0))
+    zpos = rng.permutation(n * n)[:nz]
+    dense.hdr[zpos] = ZERO_HDR
+    dense.limbs[:, zpos] = 0
+    keep = np.flatnonzero(dense.hdr != ZERO_HDR)
+    rows = (keep // n).astype(np.int64)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr).astype(np.int32)
+    csr = CSRHost(n, n, row_ptr, (keep % n).astype(np.int32), dense.take(keep))
+    return dense, csr, mp_arange1(n, p)
