@@ -91,6 +91,14 @@ typedef struct {
   mp_vec val;              /* [nnz] */
 } mp_csr;
 
+/* A dense matrix: rows x cols p-bit numbers, row-major (element (i, j) at index i * cols + j of
+ * val), zeros stored as elements (the paper's dense format, Sec. 3). */
+typedef struct {
+  int64_t rows, cols;
+  int32_t prec;  /* 128, 256 or 512 */
+  mp_vec val;    /* rows * cols elements */
+} mp_dense;
+
 /* Opaque transposed-product plan: the CSR of A^T (rows = columns of A, entries in ascending
  * original-row order, built from the per-column non-zero counts of the paper's sparse
  * structure, Sec. 2) with A's values permuted into it.  Owned by the library. */
@@ -157,6 +165,16 @@ int mp_validate_csr(const mp_csr *A, int check_device_data);
  * not depend on the variant.  Asynchronous on `stream`. */
 int mpspmv_csr(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp_plan *plan,
                void *stream);
+
+/* y = A x for a dense matrix (the dense multiple-precision MV the paper measures its sparse
+ * product against, Sec. 3, on the Lotkin matrix with s% zeros), in the given mode: SEQ takes
+ * every stored element of a row in ascending column order (y_i <- RN(y_i + RN(a_ij x_j)) from
+ * y_i = +0), EXACT rounds the exact row sum once.  A stored zero takes the zero fast path: its
+ * limbs and x's are not read, its product is not formed and (SEQ) not added, which gives the
+ * same bits as adding it.  The result equals mpspmv_csr on the CSR of A's non-zero elements bit
+ * for bit.  x.len == cols, y.len == rows; y must not overlap x or A; rows * cols < 2^31.
+ * Asynchronous on `stream`.  Returns MPS_OK or MPS_EINVAL. */
+int mp_gemv(const mp_dense *A, const mp_vec *x, mp_vec *y, int mode, void *stream);
 
 /* y = A x as mpspmv_csr (same modes, same result bits), for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -43,6 +43,11 @@ class MpCsr(ctypes.Structure):
                 ("val", MpVec)]
 
 
+class MpDense(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("prec", ctypes.c_int32),
+                ("val", MpVec)]
+
+
 class MpSolveProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 5), ("us", ctypes.c_double * 5),
                 ("bytes", ctypes.c_double * 5)]
@@ -85,6 +90,8 @@ SIGNATURES = {
     "mp_validate_csr": [ctypes.POINTER(MpCsr), ctypes.c_int],
     "mpspmv_csr": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "mp_gemv": [ctypes.POINTER(MpDense), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
+                ctypes.c_void_p],
     "mpspmv_csr_noalloc": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                            ctypes.c_int, ctypes.c_void_p],
     "mp_plan_tune": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_void_p],

@@ -35,6 +35,20 @@ def mpspmv_csr(A, x, y=None, mode=MP_SEQ, plan=None, stream=None):
     return y
 
 
+def mp_gemv(vals, rows, cols, x, y=None, mode=MP_SEQ, stream=None):
+    """y = A x for the dense row-major matrix A whose rows * cols elements are the MPArray vals
+    (zeros stored).  Allocates y when not given.  Returns y."""
+    if y is None:
+        y = MPArray.empty(int(rows), vals.p, device=x.device)
+    d = _lib.MpDense()
+    d.rows, d.cols, d.prec = int(rows), int(cols), int(vals.p)
+    d.val = vals.desc()
+    xd, yd = x.desc(), y.desc()
+    check(_lib.LIB.mp_gemv(ctypes.byref(d), ctypes.byref(xd), ctypes.byref(yd), int(mode),
+                           _stream(stream)))
+    return y
+
+
 def mpspmv_csr_noalloc(A, x, y, mode=MP_SEQ, stream=None):
     """y = A x into the caller's y through the allocation-free entry point (x staged in the
     library's static scratch array; x.n bounded by its size).  Returns y."""

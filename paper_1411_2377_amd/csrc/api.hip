@@ -13,6 +13,7 @@
 #include "api_internal.hpp"
 #include "plan_internal.hpp"
 #include "spmv_internal.hpp"
+#include "vec_internal.hpp"
 
 namespace mpapi {
 
@@ -147,7 +148,7 @@ bool valid_rows_per_block(int rpw) { return rpw == 16 || rpw == 32 || rpw == 64;
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvFuse* fuse,
-                const SpmvBatch* batch, const SpmvVariant* var) {
+                const SpmvBatch* batch, const SpmvVariant* var, int32_t dense_cols) {
   if (n_rows == 0) return MPS_OK;
   const SpmvVariant plain;
   if (!var) var = &plain;
@@ -186,6 +187,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.pipe = var->pipe ? 1 : 0;
   a.n_long = 0;
   a.long_blocks = 0;
+  a.dense_cols = dense_cols;
   if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
       !batch->pair_of_tile && !done) {
     const int rg = 64 / L;  // rows per lane-group block
@@ -323,6 +325,38 @@ int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_p
   const SpmvVariant var = plan ? plan_variant(plan, 0, mode) : SpmvVariant{};
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
                      nullptr, (hipStream_t)stream, nullptr, nullptr, &var);
+}
+
+int mp_gemv(const mp_dense* A, const mp_vec* x, mp_vec* y, int mode, void* stream) {
+  clear_error();
+  if (!A) return fail(MPS_EINVAL, "A: null descriptor");
+  const int L = limbs_of(A->prec);
+  if (!L) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512}", A->prec);
+  if (A->rows < 0 || A->cols < 0) return fail(MPS_EINVAL, "A: negative dimension");
+  if (A->cols > 0 && A->rows > (int64_t)INT32_MAX / A->cols)
+    return fail(MPS_EINVAL, "A: rows * cols must fit 32-bit entry indices");
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  int r;
+  if ((r = check_vec(&A->val, A->rows * A->cols, "A.val"))) return r;
+  if ((r = check_vec(x, A->cols, "x"))) return r;
+  if ((r = check_vec(y, A->rows, "y"))) return r;
+  if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L)) return fail(MPS_EINVAL, "y overlaps an input");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  if (A->rows == 0) return MPS_OK;
+  if (A->cols == 0) {  // every row is empty: y = +0
+    mp::VecArgs a{};
+    a.n = A->rows;
+    a.v[0] = ref(*y);
+    return launch_ew(L, EW_ZERO, a, (hipStream_t)stream);
+  }
+  // SEQ: the four-wavefront pipelined kernel (products formed beside the rows' rounding chains),
+  // 16 rows per block; EXACT: rows per block by the row length
+  SpmvVariant var;
+  var.rpw = mode == MP_SEQ ? 16 : 0;
+  var.pipe = mode == MP_SEQ;
+  return spmv_launch(L, A->rows, nullptr, nullptr, A->val, *x, *y, mode, ctx->status, nullptr,
+                     (hipStream_t)stream, nullptr, nullptr, &var, (int32_t)A->cols);
 }
 
 int mpspmv_csr_noalloc(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, void* stream) {

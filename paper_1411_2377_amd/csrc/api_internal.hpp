@@ -113,7 +113,8 @@ struct SpmvVariant {
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,
                 const int32_t* done, hipStream_t s, const SpmvFuse* fuse = nullptr,
-                const SpmvBatch* batch = nullptr, const SpmvVariant* var = nullptr);
+                const SpmvBatch* batch = nullptr, const SpmvVariant* var = nullptr,
+                int32_t dense_cols = 0);
 // rows per block of the SpMV kernels: 16, 32 or 64 (0 or anything else: chosen from the shape)
 int default_rows_per_block(int64_t n_rows, int64_t nnz);
 bool valid_rows_per_block(int rpw);

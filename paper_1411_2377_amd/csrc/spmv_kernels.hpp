@@ -79,6 +79,9 @@ struct SpmvArgs {
   // by lane groups in the first long_blocks blocks; the other blocks take the rows after them
   int64_t n_long;
   int64_t long_blocks;
+  // > 0: a dense row-major matrix with that many columns (row i holds entries i * dense_cols ...,
+  // entry k sits in column k mod dense_cols); row_ptr and col_idx are then not read
+  int32_t dense_cols;
   // several right-hand sides / independent solves (nrhs == 1 and pair_of_tile == nullptr: one)
   int nrhs;                      // block b works on row block b / nrhs for right-hand side b % nrhs
   int64_t x_rstride, y_rstride;  // element offset between right-hand sides in x and y
@@ -96,6 +99,17 @@ struct SpmvArgs {
   const int32_t* first_tile;
   int32_t* ndone;
 };
+
+// Entry range of a row and column of an entry, from the CSR arrays or the dense shape.
+MPD int row_begin(const SpmvArgs& A, int64_t row) {
+  return A.dense_cols ? (int)(row * A.dense_cols) : A.row_ptr[row];
+}
+MPD int row_end(const SpmvArgs& A, int64_t row) {
+  return A.dense_cols ? (int)((row + 1) * A.dense_cols) : A.row_ptr[row + 1];
+}
+MPD int32_t col_of(const SpmvArgs& A, int64_t k) {
+  return A.dense_cols ? (int32_t)((uint32_t)k % (uint32_t)A.dense_cols) : A.col_idx[k];
+}
 
 // Row block (RPW rows), right-hand side and solve of this block; false if that solve is
 // finished.  RPW divides 512, so a block's rows lie in one solve's tile.
@@ -204,7 +218,7 @@ MPD void load_entries(EntryLoad<L, K>& E, const SpmvArgs& A, const uint32_t* x_l
   const int32_t z = (int32_t)0x80000000;  // +0
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    E.col[i] = ok[i] ? A.col_idx[k[i]] : 0;
+    E.col[i] = ok[i] ? col_of(A, k[i]) : 0;
     E.ha[i] = ok[i] ? A.a_hdr[k[i]] : z;
   }
 #pragma unroll
@@ -246,8 +260,8 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
   const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
   const bool has_row = lane < nr;
   const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
-  const int rs = has_row ? A.row_ptr[row] : 0;
-  const int re = has_row ? A.row_ptr[row + 1] : 0;
+  const int rs = has_row ? row_begin(A, row) : 0;
+  const int re = has_row ? row_end(A, row) : 0;
   if (lane < RPW) s_rs[lane] = rs;
   wave_prefix(re - rs, s_cp);
   __syncthreads();
@@ -298,7 +312,8 @@ __global__ void __launch_bounds__(64, 4) spmv_seq_kernel(SpmvArgs A) {
       for (int q = 0; q < L; ++q) t.m[q] = s_m[q][j - c0];
       t.e = s_e[j - c0];
       t.s = s_s[j - c0];
-      acc = add_rn<L>(acc, t, st);
+      // a zero product leaves the sum as it is (the sum is never -0), so it is not added
+      if (!is_zero(t)) acc = add_rn<L>(acc, t, st);
     }
     __syncthreads();
   }
@@ -358,8 +373,8 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
   if (wv == 0) {
     const bool hr = lane < nr;
     const int64_t row = hr ? (int64_t)A.rows[r0 + lane] : 0;
-    const int rs = hr ? A.row_ptr[row] : 0;
-    const int len = hr ? A.row_ptr[row + 1] - rs : 0;
+    const int rs = hr ? row_begin(A, row) : 0;
+    const int len = hr ? row_end(A, row) - rs : 0;
     if (lane < RG) {
       g_rs[lane] = rs;
       g_len[lane] = len;
@@ -455,8 +470,8 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   const bool has_row = wv == 0 && lane < nr;
   const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
   if (wv == 0) {
-    const int rs = has_row ? A.row_ptr[row] : 0;
-    const int len = has_row ? A.row_ptr[row + 1] - rs : 0;
+    const int rs = has_row ? row_begin(A, row) : 0;
+    const int len = has_row ? row_end(A, row) - rs : 0;
     if (lane < RPW) {
       s_rs[lane] = rs;
       s_len[lane] = len;
@@ -515,7 +530,7 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
         if (c == 0 && q == 0) {  // RN(+0 + p): p itself, +0 for a zero p (a uniform branch)
           acc = p;
           acc.s = is_zero(p) ? 0u : p.s;
-        } else {
+        } else if (!is_zero(p)) {  // a zero product leaves the sum (never -0) as it is
           acc = add_rn<L>(acc, p, st);
         }
       }
@@ -603,8 +618,8 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
   const int nr = (int)min((int64_t)RPW, A.n_rows - r0);
   const bool has_row = lane < nr;
   const int64_t row = has_row ? (A.rows ? (int64_t)A.rows[r0 + lane] : r0 + lane) : 0;
-  const int rs = has_row ? A.row_ptr[row] : 0;
-  const int re = has_row ? A.row_ptr[row + 1] : 0;
+  const int rs = has_row ? row_begin(A, row) : 0;
+  const int re = has_row ? row_end(A, row) : 0;
   const bool is_short = has_row && re - rs <= kShortRow;
   for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
   if (lane < RPW) {
@@ -724,7 +739,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
         __syncthreads();
         for (int kk = o_rs + lane; kk < o_re; kk += 64) {
           const int32_t ha = A.a_hdr[kk];
-          const int32_t col = A.col_idx[kk];
+          const int32_t col = col_of(A, kk);
           int32_t hx;
           uint32_t am[L], xm[L], pr[2 * L];
           load_x<L>(A, x_limb, x_hdr, col, true, hx, xm);
