@@ -17,5 +17,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
       vs true residual, BiCG's Lanczos coefficients, BiCGSTAB's r orthogonal to t, breakdowns)
   dense.gemv : pinned (Fraction sums, the sparse product of the same matrix without its zeros,
       integer rows summed exactly, the sequential-summation bound)
+  ilu.ilu0 / lower_solve / upper_solve / apply, krylov.bicgstab_precond : pinned (L U = A on A's
+      pattern, complete LU on tridiagonal matrices, rounded exact rows in EXACT mode, solve
+      residual bounds, the identity preconditioner giving plain BiCGSTAB bit for bit, Gauss
+      solutions of small systems)
 """
-from . import blas, codec, dense, krylov, mpnum, spmv  # noqa: F401
+from . import blas, codec, dense, ilu, krylov, mpnum, spmv  # noqa: F401

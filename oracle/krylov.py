@@ -270,3 +270,57 @@ def bicgstab(matvec, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
             return SolveResult(x, BREAKDOWN_ZETA, i, hist)
         rho_old, alpha_old, omega_old = rho, alpha, omega
     return SolveResult(x, NOT_CONVERGED, maxit, hist)
+
+
+def bicgstab_precond(matvec, psolve, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
+    """BiCGSTAB with a preconditioner K (psolve(v) = K^{-1} v), applied to the two search
+    directions, so that the residual the (*) test reads stays b - A x:
+    p^ = K^{-1} p, v = A p^, s = r - alpha v, s^ = K^{-1} s, t = A s^,
+    omega = (t, s) / (t, t) (0 when (t, t) = 0), x = x + alpha p^ + omega s^, r = s - omega t.
+    With psolve the identity this is bicgstab, operation for operation."""
+    n = len(b)
+    x = list(x0) if x0 is not None else [zero(p)] * n
+    ax = matvec(x)
+    r = [sub(bi, ai) for bi, ai in zip(b, ax)]
+    rt = list(r)
+    q0 = dot(r, r, p)
+    thr = _threshold(sqrt(q0), c_rel, c_abs)
+    hist = []
+    if _converged(q0, thr):
+        return SolveResult(x, CONVERGED, 0, hist)
+    rho_old = alpha_old = omega_old = None
+    pv = v = None
+    for i in range(1, maxit + 1):
+        rho = dot(rt, r, p)
+        if is_zero(rho):
+            return SolveResult(x, BREAKDOWN_RHO, i - 1, hist)
+        if i == 1:
+            pv = list(r)
+        else:
+            beta = mul(div(rho, rho_old), div(alpha_old, omega_old))
+            pv = [add(ri, mul(beta, sub(pi, mul(omega_old, vi)))) for ri, pi, vi in zip(r, pv, v)]
+        ph = psolve(pv)
+        v = matvec(ph)
+        sigma = dot(rt, v, p)
+        if is_zero(sigma):
+            return SolveResult(x, BREAKDOWN_SIGMA, i - 1, hist)
+        alpha = div(rho, sigma)
+        s = aymx(alpha, v, r)
+        sh = psolve(s)
+        t = matvec(sh)
+        ts = dot(t, s, p)
+        tt = dot(t, t, p)
+        omega = zero(p) if is_zero(tt) else div(ts, tt)
+        x = [add(add(xi, mul(alpha, pi)), mul(omega, si)) for xi, pi, si in zip(x, ph, sh)]
+        r = aymx(omega, t, s)
+        q = dot(r, r, p)
+        hist.append(q)
+        if on_iter is not None:
+            on_iter(i, {"x": x, "r": r, "p": pv, "s": s, "t": t, "rho": rho, "alpha": alpha,
+                        "omega": omega, "sigma": sigma, "q": q})
+        if _converged(q, thr):
+            return SolveResult(x, CONVERGED, i, hist)
+        if is_zero(omega):
+            return SolveResult(x, BREAKDOWN_ZETA, i, hist)
+        rho_old, alpha_old, omega_old = rho, alpha, omega
+    return SolveResult(x, NOT_CONVERGED, maxit, hist)
