@@ -20,9 +20,10 @@ against the limb-product peak (L^2 32x32->64 multiply-adds per entry at 19.66 T/
 
 `components`: both modes at p = 128, 256 and 512 with their variants, the transposed product
 and value gradient (the autograd backward), cold-cache launches (after a 1 GiB write), 200
-BiCG / GPBiCG iterations per mode on the 256 x 256 convection-diffusion operator with their
-per-kernel profile, and batched GPBiCG on 64 banded systems x 16 right-hand sides against plain
-solves.  `cpu_baseline` times the oracle on a bounded sample of the headline workload's rows.
+BiCG / GPBiCG / CGS / BiCGSTAB iterations per mode on the 256 x 256 convection-diffusion
+operator with their per-kernel profile, the Lotkin-with-zeros dense vs sparse product (the
+paper's SpMV benchmark), and batched GPBiCG on 64 banded systems x 16 right-hand sides against
+plain solves.  `cpu_baseline` times the oracle on a bounded sample of the headline workload's rows.
 
 Other uses:
   --profile-pass powerlaw|convdiff   launches for a rocprofv3 counter pass only
@@ -275,7 +276,7 @@ def solver_component(M, torch):
     L = PREC // 32
     out = {"workload": "2-D convection-diffusion 5-point 256x256 (n=65536, nnz=326656), Peclet 10, "
                        "p=256, b = A*ones; %d iterations (tolerance below reach)" % ITERS}
-    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg)):
+    for sname, solver in (("bicg", M.bicg), ("gpbicg", M.gpbicg), ("cgs", M.cgs), ("bicgstab", M.bicgstab)):
         for mname, mode in (("seq", M.MP_SEQ), ("exact", M.MP_EXACT)):
             solver(A, b, plan=plan, mode=mode, maxit=5, rtol=(1, -70), atol=(0, 0), chunk=25)
             torch.cuda.synchronize()
@@ -308,6 +309,36 @@ def solver_component(M, torch):
                           "avg_us": round(v[0] / max(1, v[1]), 2),
                           "hbm_frac": round(v[2] / (v[0] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
                       for k, v in cand.items()}
+    M.mp_status()
+    return out
+
+
+def lotkin_component(M, torch, reps):
+    """The paper's SpMV benchmark (Sec. 3): the Lotkin matrix (n = 2000) with s% of its elements
+    set to zero, b = A [1..n] by the sparse product, then A b by the dense product (all n^2
+    elements stored, zeros taking the fast path) and by the sparse product of the non-zero
+    elements with a tuned plan; speedup = dense time / sparse time (SEQ mode).  Results are
+    bit-identical."""
+    import synth
+    n = 2000
+    out = {"workload": "Lotkin n=2000 with s%% zeros, y = A (A [1..n]) in SEQ mode; dense: %d stored "
+                       "elements" % (n * n)}
+    for p, zs in ((256, (50.0, 90.0, 99.0)), (128, (90.0,)), (512, (90.0,))):
+        for z in zs:
+            D_h, C_h, x_h = synth.lotkin(n, p, z, seed=6)
+            A = M.CSRMatrix.from_host(C_h)
+            D = M.MPArray.from_host(D_h)
+            plan = M.mp_plan_create(A)
+            plan.tune(reps=1)
+            b = M.mpspmv_csr(A, M.MPArray.from_host(x_h), mode=M.MP_SEQ, plan=plan)
+            ys = M.MPArray.empty(n, p)
+            yd = M.MPArray.empty(n, p)
+            ts = timed_launches(M, torch, lambda: M.mpspmv_csr(A, b, ys, mode=M.MP_SEQ, plan=plan), reps)
+            td = timed_launches(M, torch, lambda: M.mp_gemv(D, n, n, b, yd, mode=M.MP_SEQ), reps)
+            same = bool(torch.equal(ys.limbs, yd.limbs) and torch.equal(ys.hdr, yd.hdr))
+            out["p%d_zeros%g" % (p, z)] = {"nnz": A.nnz, "sparse_us": round(ts, 1), "dense_us": round(td, 1),
+                                           "speedup": round(td / ts, 2), "same_bits": same}
+            del A, D, b, ys, yd, plan
     M.mp_status()
     return out
 
@@ -440,6 +471,7 @@ def main():
             comp["p%d" % p] = precision_component(M, torch, p, reps, tune_cache=args.tune_cache)
             torch.cuda.empty_cache()
         comp["solvers_convdiff256"] = solver_component(M, torch)
+        comp["lotkin_dense_vs_sparse"] = lotkin_component(M, torch, reps)
         comp["batched_gpbicg"] = batched_component(M, torch)
     out = {
         "metric": "MP nonzeros/s for 256-bit MP-SpMV (+ % roofline); BiCG solve time, batched vs plain",

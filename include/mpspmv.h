@@ -288,6 +288,36 @@ int cgs(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
 int bicgstab(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
              const mp_solve_opts *opts, mp_solve_info *info, void *stream);
 
+/* ILU(0) preconditioner (Sec. 4.2, Table 3: the paper's left preconditioner for BiCGSTAB): the
+ * incomplete LU factorisation without fill-in, K = L U (L unit lower, U upper triangular, both
+ * on the sparsity pattern of the square matrix A, whose every row must store its diagonal
+ * element).  The factors are computed row by row, one RN per operation: for each stored column
+ * k < i of row i in ascending order, a_ik <- RN(a_ik / a_kk), then a_ij <- RN(a_ij - RN(a_ik a_kj))
+ * for each stored column j > k of row i, in ascending order, that row k also stores.  The rows
+ * are processed in dependency levels (one launch per level).  mp_ilu0_create factors A
+ * (synchronises `stream`, copies A's structure to the host for the level sets, allocates device
+ * memory owned by the object; MPS_EINVAL for a missing diagonal element or a zero pivot).
+ * mp_ilu0_apply: w = K^{-1} r = U^{-1} L^{-1} r, each row's sum r_i - sum_k l_ik y_k (and
+ * y_i - sum_j u_ij w_j, then one RN division by u_ii) in the given accumulation mode, as the
+ * sparse product sums a row (SEQ: r_i first, then the products in ascending column order; EXACT:
+ * exactly, one rounding); asynchronous, level by level; the object's work vectors are shared by
+ * its calls, which must not overlap in time.  mp_ilu0_factors copies the factors into lu (A's
+ * CSR layout, nnz elements).  Returns MPS_OK, MPS_EINVAL, MPS_ENOMEM or MPS_EHIP. */
+typedef struct mp_ilu mp_ilu;
+int mp_ilu0_create(const mp_csr *A, void *stream, mp_ilu **ilu);
+int mp_ilu0_destroy(mp_ilu *ilu);
+int mp_ilu0_apply(const mp_ilu *ilu, const mp_vec *r, mp_vec *w, int mode, void *stream);
+int mp_ilu0_factors(const mp_ilu *ilu, mp_vec *lu, void *stream);
+
+/* BiCGSTAB preconditioned by ILU(0) (Sec. 4.2, Table 3), K applied to the two search
+ * directions so that the residual of the stopping test (*) stays b - A x:  p^ = K^{-1} p,
+ * v = A p^, alpha = rho / (r~, v), s = r - alpha v, s^ = K^{-1} s, t = A s^,
+ * omega = (t, s) / (t, t) (0 when (t, t) = 0), x = x + alpha p^ + omega s^, r = s - omega t.
+ * The triangular solves take opts->mode like the products.  opts->transpose must be 0
+ * (MPS_ENOTSUP).  Otherwise as bicgstab. */
+int bicgstab_ilu0(const mp_csr *A, const mp_ilu *ilu, const mp_vec *b, mp_vec *x,
+                  const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
 /* Batched GPBiCG: nsys systems A[0..nsys-1] (square, same precision, sizes may differ), each
  * with nrhs right-hand sides, solved as nsys * nrhs independent GPBiCG solves (the method of
  * Fig. 5 right, K = I, applied to many systems) that share every kernel launch: one captured

@@ -123,6 +123,13 @@ SIGNATURES = {
             ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "bicgstab": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                  ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
+    "mp_ilu0_create": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "mp_ilu0_destroy": [ctypes.c_void_p],
+    "mp_ilu0_apply": [ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
+                      ctypes.c_void_p],
+    "mp_ilu0_factors": [ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.c_void_p],
+    "bicgstab_ilu0": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+                      ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "gpbicg_batched": [ctypes.c_int, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.POINTER(MpVec),
                        ctypes.POINTER(MpVec), ctypes.POINTER(MpSolveOpts),
                        ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],

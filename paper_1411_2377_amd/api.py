@@ -5,7 +5,7 @@ import os
 import torch
 
 from . import _lib
-from ._lib import MP_EXACT, MP_SEQ, check  # noqa: F401
+from ._lib import MP_EXACT, MP_SEQ, MPError, check  # noqa: F401
 from .mparray import CSRMatrix, MPArray  # noqa: F401
 
 
@@ -252,6 +252,57 @@ def cgs(A, b, **kw):
 def bicgstab(A, b, **kw):
     """BiCGSTAB for A x = b (or A^T x = b with transpose=True).  Returns (x, SolveInfo)."""
     return _solve(_lib.LIB.bicgstab, A, b, **kw)
+
+
+class ILU0:
+    """The ILU(0) preconditioner of a square CSRMatrix (factored on creation; owns library
+    memory, freed on close/GC)."""
+
+    def __init__(self, A, stream=None):
+        self.A = A
+        self._h = ctypes.c_void_p()
+        d = A.desc()
+        check(_lib.LIB.mp_ilu0_create(ctypes.byref(d), _stream(stream), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, r, w=None, mode=MP_SEQ, stream=None):
+        """w = K^{-1} r.  Returns w."""
+        if w is None:
+            w = MPArray.empty(r.n, r.p, device=r.device)
+        rd, wd = r.desc(), w.desc()
+        check(_lib.LIB.mp_ilu0_apply(self._h, ctypes.byref(rd), ctypes.byref(wd), int(mode), _stream(stream)))
+        return w
+
+    def factors(self, stream=None):
+        """The factors L (strictly below the diagonal) and U in A's CSR layout, as an MPArray."""
+        lu = MPArray.empty(self.A.nnz, self.A.p, device=self.A.row_ptr.device)
+        d = lu.desc()
+        check(_lib.LIB.mp_ilu0_factors(self._h, ctypes.byref(d), _stream(stream)))
+        return lu
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.LIB.mp_ilu0_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bicgstab_ilu0(A, ilu, b, **kw):
+    """BiCGSTAB preconditioned by ILU(0) (an ILU0 of A).  Returns (x, SolveInfo)."""
+    return _solve(_lib.LIB.bicgstab_ilu0, A, b, plan=_Handle(ilu.handle), **kw)
+
+
+class _Handle:
+    def __init__(self, h):
+        self.handle = h
 
 
 def gpbicg_batched(As, bs, mode=MP_SEQ, maxit=1000, rtol=(1, -20), atol=(1, -50), chunk=16,

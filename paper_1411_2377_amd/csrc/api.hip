@@ -158,7 +158,18 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   if (x_rec && batch && batch->nrhs != 1) return fail(MPS_EINVAL, "staged x takes one right-hand side");
   const SpmvBatch one;
   if (!batch) batch = &one;
-  if (!valid_rows_per_block(rpw)) rpw = default_rows_per_block(n_rows, val.len);
+  bool pipe = var->pipe;
+  if (!valid_rows_per_block(rpw)) {
+    rpw = default_rows_per_block(n_rows, val.len);
+    // plain SEQ products with long rows (more than 24 entries on average): the pipelined
+    // kernel with 16 rows per block, whose rows' rounding chains advance together (the one-lane
+    // kernel stages a block's entries row after row, so its chains would run one at a time)
+    if (mode == MP_SEQ && !var->rows && !(fuse && fuse->nd > 0) && batch->nrhs == 1 && !done &&
+        val.len > 24 * n_rows) {
+      pipe = true;
+      rpw = 16;
+    }
+  }
   if ((n_rows + rpw - 1) / rpw * batch->nrhs + (n_rows + 3) / 4 > (int64_t)UINT32_MAX)
     return fail(MPS_ENOTSUP, "too many row blocks for one launch");
   mp::SpmvArgs a;
@@ -184,7 +195,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.done_stride = batch->done_stride;
   a.x_rec = x_rec;
   a.rows = var->rows;
-  a.pipe = var->pipe ? 1 : 0;
+  a.pipe = pipe ? 1 : 0;
   a.n_long = 0;
   a.long_blocks = 0;
   a.dense_cols = dense_cols;

@@ -17,6 +17,7 @@
 
 #include "../../include/mpspmv.h"
 #include "api_internal.hpp"
+#include "ilu_internal.hpp"
 #include "plan_internal.hpp"
 #include "batch_kernels.hpp"
 #include "spmv_internal.hpp"
@@ -882,6 +883,62 @@ int bicgstab_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec*
   return finish_solve(W, info, st);
 }
 
+// BiCGSTAB with the ILU(0) preconditioner K on its two search directions (Sec. 4.2, Table 3):
+// p^ = K^{-1} p, v = A p^, s = r - alpha v, s^ = K^{-1} s, t = A s^, omega = (t, s) / (t, t),
+// x = x + alpha p^ + omega s^, r = s - omega t; the (*) test reads r = b - A x.
+// Work vectors: 0 r, 1 rt, 2 p^, 3 p, 4 v, 5 s, 6 t, 7 s^
+int bicgstab_ilu0_impl(const mp_csr* A, const mp_ilu* K, const mp_vec* b, mp_vec* x,
+                       const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  if (o->transpose) return fail(MPS_ENOTSUP, "the preconditioned solve takes A, not its transpose");
+  if ((r = check_ilu(K, A))) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  const int L = limbs_of(A->prec);
+  Work W;
+  if ((r = work_alloc(W, L, A->row_dim, 8, user))) return r;
+  Op op, opT;
+  make_ops(A, nullptr, 0, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  if ((r = clear_vectors(W, 2, 8, st))) return r;
+  if ((r = prof_init(W, o->profile))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), PH = W.vec(2), P = W.vec(3), V = W.vec(4),
+                   S = W.vec(5), T = W.vec(6), SH = W.vec(7);
+  const mp::VecRef X = ref(*x);
+  const mp::VecRef self{nullptr, nullptr, 0};
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
+  auto iteration = [&]() -> int {
+    int rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = P; a.v[1] = R; a.v[2] = V;
+    if ((rr = timed(W, PROF_DIR, vec_bytes(W, 4), [&] { return launch_ew(L, EW_STAB_DIR, a, W.ws); })))
+      return rr;
+    if ((rr = ilu_apply(K, W.desc(3), W.desc(2), o->mode, st, W.ctl, W.ws))) return rr;
+    const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{RT, 0, mp::S_SIGMA}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, PH, V, st, true, &sig); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = S; a.v[1] = R; a.v[2] = V;
+    set_fd(W, a, mp::EPI_NONE, {});
+    if ((rr = timed(W, PROF_TSY, vec_bytes(W, 3), [&] { return launch_ew(L, EW_STAB_S, a, W.ws); })))
+      return rr;
+    if ((rr = ilu_apply(K, W.desc(5), W.desc(7), o->mode, st, W.ctl, W.ws))) return rr;
+    const SpmvFuse ts = fuse_of(W, mp::EPI_NONE, {{S, 4, mp::S_MU2}, {self, 7, mp::S_MU5}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, SH, T, st, true, &ts); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = X; a.v[1] = R; a.v[2] = PH; a.v[3] = S; a.v[4] = T; a.v[5] = RT; a.v[6] = SH;
+    set_fd(W, a, mp::EPI_GP_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
+    return timed(W, PROF_UPD, vec_bytes(W, 9), [&] { return launch_ew(L, EW_STAB_XR, a, W.ws); });
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
 // ---- batched GPBiCG --------------------------------------------------------------------
 // nsys systems, nrhs right-hand sides each: nsys * nrhs independent solves ("pairs", pair
 // s * nrhs + k) advanced together.  The systems are concatenated into one block-diagonal CSR
@@ -1121,6 +1178,12 @@ int bicgstab(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
              const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
   return bicgstab_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+}
+
+int bicgstab_ilu0(const mp_csr* A, const mp_ilu* ilu, const mp_vec* b, mp_vec* x,
+                  const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return bicgstab_ilu0_impl(A, ilu, b, x, opts, info, (hipStream_t)stream);
 }
 
 int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec* x,

@@ -1722,8 +1722,9 @@ __global__ void __launch_bounds__(256) stab_s_kernel(VecArgs A) {
                              A.status, st, lds.win, lds_window_digits<L, 256>(), &pro);
 }
 
-// BiCGSTAB update: v = {x, r, p, s, t, rt}.  omega = (t, s) / (t, t) (the product's inner
-// products, still in their rings; 0 when (t, t) = 0); x = x + alpha p + omega s,
+// BiCGSTAB update: v = {x, r, p, s, t, rt, s^}.  omega = (t, s) / (t, t) (the product's inner
+// products, still in their rings; 0 when (t, t) = 0); x = x + alpha p + omega s^ (s^ = s
+// unless v[6] is given: the preconditioned direction K^{-1} s, with K^{-1} p in v[2]),
 // r = s - omega t; then (r, r) and (r~, r) (fd slots 0 and 1); the last block's epilogue runs
 // the stopping test, the omega = 0 exit and forms beta.
 template <int L>
@@ -1747,8 +1748,9 @@ __global__ void __launch_bounds__(256) stab_xr_kernel(VecArgs A) {
       const Num<L> x = vload<L>(A.v[0], i), p = vload<L>(A.v[2], i), s = vload<L>(A.v[3], i);
       const Num<L> t = vload<L>(A.v[4], i);
       rt = vload<L>(A.v[5], i);
+      const Num<L> sx = A.v[6].hdr ? vload<L>(A.v[6], i) : s;
       const Num<L> xa = add_rn<L>(x, mul_rn<L>(alpha, p, st), st);
-      vstore<L>(A.v[0], i, add_rn<L>(xa, mul_rn<L>(omega, s, st), st));
+      vstore<L>(A.v[0], i, add_rn<L>(xa, mul_rn<L>(omega, sx, st), st));
       r = sub_rn<L>(s, mul_rn<L>(omega, t, st), st);
       vstore<L>(A.v[1], i, r);
     }

@@ -8,8 +8,8 @@ full (limbs and header, for a readable first difference), and the oracle's wall 
 
 Cases (the paper's Fig. 5 solvers with the stopping test of Sec. 4.1, K = I):
   convdiff2d_256_*   2-D convection-diffusion 256 x 256, p = 256, b = RN_exact(A * ones):
-                     200 iterations of BiCG and GPBiCG in SEQ and EXACT mode (tolerance 1e-70,
-                     out of reach, so all 200 run);
+                     200 iterations of BiCG, GPBiCG, CGS and BiCGSTAB in SEQ and EXACT mode
+                     (tolerance 1e-70, out of reach, so all 200 run);
   scaled3d_64_*      row-scaled 3-D operator 64^3, p = 512, b = RN_exact(A [1..n]): the first
                      20 iterations of BiCG and GPBiCG, EXACT (tolerance 1e-100);
   banded_*           the two smallest systems of the 64-system banded batch, all 16 right-hand
@@ -79,7 +79,7 @@ def solve(S, solver, mode, b, rtol, atol, maxit):
     c_rel, c_abs = const(*rtol, p), const(*atol, p)
     if solver == "bicg":
         return krylov.bicg(S.mv(mode), S.rmv(mode), b, c_rel, c_abs, maxit, p)
-    return krylov.gpbicg(S.mv(mode), b, c_rel, c_abs, maxit, p)
+    return getattr(krylov, solver)(S.mv(mode), b, c_rel, c_abs, maxit, p)
 
 
 def result(ref, p, with_samples=True):
@@ -173,6 +173,10 @@ CASES = {
     "convdiff2d_256_p256_bicg_exact": lambda: case_convdiff2d("bicg", 1),
     "convdiff2d_256_p256_gpbicg_seq": lambda: case_convdiff2d("gpbicg", 0),
     "convdiff2d_256_p256_gpbicg_exact": lambda: case_convdiff2d("gpbicg", 1),
+    "convdiff2d_256_p256_cgs_seq": lambda: case_convdiff2d("cgs", 0),
+    "convdiff2d_256_p256_cgs_exact": lambda: case_convdiff2d("cgs", 1),
+    "convdiff2d_256_p256_bicgstab_seq": lambda: case_convdiff2d("bicgstab", 0),
+    "convdiff2d_256_p256_bicgstab_exact": lambda: case_convdiff2d("bicgstab", 1),
     "scaled3d_64_p512_bicg_exact_20it": lambda: case_scaled3d("bicg"),
     "scaled3d_64_p512_gpbicg_exact_20it": lambda: case_scaled3d("gpbicg"),
     "banded_smallest0_p256_gpbicg_seq": lambda: case_banded(0),

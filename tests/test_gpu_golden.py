@@ -2,8 +2,8 @@
 (tests/golden/make_golden.py, from the seeded inputs of synth/): every iterate is deterministic,
 so status, iteration count, every residual-history entry and every bit of x must agree.
 
-  * 2-D convection-diffusion 256 x 256, p = 256: 200 BiCG and 200 GPBiCG iterations in SEQ and
-    EXACT mode (the benchmark's solver runs, tuned plan, graph chunks of 25);
+  * 2-D convection-diffusion 256 x 256, p = 256: 200 iterations of BiCG, GPBiCG, CGS and
+    BiCGSTAB in SEQ and EXACT mode (the benchmark's solver runs, tuned plan, graph chunks of 25);
   * row-scaled 3-D operator 64^3, p = 512: the first 20 BiCG and GPBiCG iterations (EXACT);
   * the banded batch: its two smallest systems with all 16 right-hand sides (GPBiCG, SEQ, to
     1e-60), solved alone and inside the whole 64-system batch, and every member of the whole
@@ -57,7 +57,7 @@ def check_run(gold, xl, xh, info, hist=None, what=""):
     assert digest(xl, xh) == gold["x_digest"], "%s: x differs from the oracle's" % what
 
 
-@pytest.mark.parametrize("solver", ["bicg", "gpbicg"])
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_convdiff256_200_iterations(solver, mode):
     M = lib()
@@ -69,7 +69,7 @@ def test_convdiff256_200_iterations(solver, mode):
     plan = M.mp_plan_create(A)
     plan.tune(reps=1)
     o = gold["opts"]
-    fn = M.bicg if solver == "bicg" else M.gpbicg
+    fn = getattr(M, solver)
     x, info = fn(A, b, plan=plan, mode=mode, maxit=o["maxit"], rtol=tuple(o["rtol"]),
                  atol=tuple(o["atol"]), chunk=25, hist=True)
     xl, xh = x.to_numpy()
