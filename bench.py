@@ -22,8 +22,8 @@ against the limb-product peak (L^2 32x32->64 multiply-adds per entry at 19.66 T/
 and value gradient (the autograd backward), cold-cache launches (after a 1 GiB write), 200
 BiCG / GPBiCG / CGS / BiCGSTAB iterations per mode on the 256 x 256 convection-diffusion
 operator with their per-kernel profile, the Lotkin-with-zeros dense vs sparse product (the
-paper's SpMV benchmark), and batched GPBiCG on 64 banded systems x 16 right-hand sides against
-plain solves.  `cpu_baseline` times the oracle on a bounded sample of the headline workload's rows.
+paper's SpMV benchmark), BiCGSTAB with and without ILU(0) (the paper's Table 3 comparison), and
+batched GPBiCG on 64 banded systems x 16 right-hand sides against plain solves.  `cpu_baseline` times the oracle on a bounded sample of the headline workload's rows.
 
 Other uses:
   --profile-pass powerlaw|convdiff   launches for a rocprofv3 counter pass only
@@ -313,6 +313,34 @@ def solver_component(M, torch):
     return out
 
 
+def ilu_component(M, torch):
+    """The paper's Table 3 comparison on a stand-in operator: BiCGSTAB and BiCGSTAB with ILU(0)
+    to the (*) test of Sec. 4.1 (1e-20, 1e-50) on the 2-D convection-diffusion operator on a
+    64 x 64 grid, p = 256, x* = [1..n], b = A x* (EXACT), both modes: iterations and times (the
+    factorisation timed apart)."""
+    import synth
+    A_h, _ = synth.config2(p=PREC, m=64)
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.mpspmv_csr(A, M.MPArray.from_host(synth.mp_arange1(A_h.n_rows, PREC)), mode=M.MP_EXACT)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    K = M.ILU0(A)
+    torch.cuda.synchronize()
+    out = {"workload": "2-D convection-diffusion 64x64 (n=4096), p=256, x* = [1..n], tolerance "
+                       "1e-20 relative + 1e-50", "ilu0_factor_ms": round((time.time() - t0) * 1e3, 2)}
+    for mname, mode in (("seq", M.MP_SEQ), ("exact", M.MP_EXACT)):
+        for name, run in (("bicgstab", lambda: M.bicgstab(A, b, mode=mode, maxit=5000, chunk=25)),
+                          ("bicgstab_ilu0", lambda: M.bicgstab_ilu0(A, K, b, mode=mode, maxit=5000, chunk=5))):
+            torch.cuda.synchronize()
+            t1 = time.time()
+            _, info = run()
+            torch.cuda.synchronize()
+            out["%s_%s" % (name, mname)] = {"iters": info.iters, "status": info.status,
+                                             "ms": round((time.time() - t1) * 1e3, 2)}
+    M.mp_status()
+    return out
+
+
 def lotkin_component(M, torch, reps):
     """The paper's SpMV benchmark (Sec. 3): the Lotkin matrix (n = 2000) with s% of its elements
     set to zero, b = A [1..n] by the sparse product, then A b by the dense product (all n^2
@@ -472,6 +500,7 @@ def main():
             torch.cuda.empty_cache()
         comp["solvers_convdiff256"] = solver_component(M, torch)
         comp["lotkin_dense_vs_sparse"] = lotkin_component(M, torch, reps)
+        comp["ilu0_bicgstab"] = ilu_component(M, torch)
         comp["batched_gpbicg"] = batched_component(M, torch)
     out = {
         "metric": "MP nonzeros/s for 256-bit MP-SpMV (+ % roofline); BiCG solve time, batched vs plain",
