@@ -13,15 +13,19 @@ of row i in ascending order,
 The factors overwrite a copy of A's values in its CSR layout (L strictly below the diagonal,
 U on and above it).  A zero pivot a_kk raises ZeroPivot.
 
+K^T w = r (BiCG's shadow solve in Fig. 5) by the transposed solves U^T y = r (forward) and
+L^T w = y (backward), whose rows are the columns of U and L taken in ascending original-row
+order (the order of the transposed product).
+
 K w = r by two triangular solves, each row's sum in the product's accumulation mode:
     forward  L y = r:   y_i = r_i - sum_{k<i} l_ik y_k
     backward U w = y:   w_i = (y_i - sum_{j>i} u_ij w_j) / u_ii   (rows in descending order)
-SEQ: from r_i (y_i), subtract RN(l_ik y_k) (RN(u_ij w_j)) in ascending column order with one RN
-per operation; EXACT: the difference is formed exactly and rounded once.  Then one RN division
-by u_ii.
+SEQ: a sum from +0 of r_i (y_i), then of -RN(l_ik y_k) (-RN(u_ij w_j)) in ascending column
+order, one RN per operation (the sparse product's SEQ sum of the row [r_i, -l_ik y_k ...]);
+EXACT: the difference is formed exactly and rounded once.  Then one RN division by u_ii.
 """
-from .mpnum import MP, div, is_zero, mul, sub
-from .spmv import EXACT, SEQ, exact_sum_of_products
+from .mpnum import MP, add, div, is_zero, mul, sub, zero
+from .spmv import EXACT, SEQ, exact_sum_of_products, transpose
 
 
 class ZeroPivot(ArithmeticError):
@@ -59,7 +63,7 @@ def ilu0(n, row_ptr, col_idx, vals):
 def _row_sum(start, terms, p, mode):
     """start - sum of the products in terms ((a, b) pairs), in the given mode."""
     if mode == SEQ:
-        acc = start
+        acc = add(zero(p), start)
         for x, y in terms:
             acc = sub(acc, mul(x, y))
         return acc
@@ -98,4 +102,26 @@ def upper_solve(n, row_ptr, col_idx, lu, y, p, mode):
 def apply(n, row_ptr, col_idx, lu, r, p, mode):
     """w = K^{-1} r = U^{-1} L^{-1} r."""
     return upper_solve(n, row_ptr, col_idx, lu, lower_solve(n, row_ptr, col_idx, lu, r, p, mode), p, mode)
+
+
+def apply_t(n, row_ptr, col_idx, lu, r, p, mode):
+    """w = K^{-T} r = L^{-T} U^{-T} r, through the explicit transpose of the factors (row i of
+    the transpose lists column i of L and U, ascending original row)."""
+    tp, ti, tv = transpose(n, n, row_ptr, col_idx, lu)
+    y = [None] * n
+    for i in range(n):                       # U^T y = r: entries k < i are u_ki, k == i is u_ii
+        d = None
+        terms = []
+        for t in range(tp[i], tp[i + 1]):
+            k = ti[t]
+            if k == i:
+                d = tv[t]
+            elif k < i:
+                terms.append((tv[t], y[k]))
+        y[i] = div(_row_sum(r[i], terms, p, mode), d)
+    w = [None] * n
+    for i in range(n - 1, -1, -1):           # L^T w = y: entries k > i are l_ki
+        terms = [(tv[t], w[ti[t]]) for t in range(tp[i], tp[i + 1]) if ti[t] > i]
+        w[i] = _row_sum(y[i], terms, p, mode)
+    return w
 

@@ -324,3 +324,56 @@ def bicgstab_precond(matvec, psolve, b, c_rel, c_abs, maxit, p, x0=None, on_iter
             return SolveResult(x, BREAKDOWN_ZETA, i, hist)
         rho_old, alpha_old, omega_old = rho, alpha, omega
     return SolveResult(x, NOT_CONVERGED, maxit, hist)
+
+
+def bicg_precond(matvec, rmatvec, psolve, psolve_t, b, c_rel, c_abs, maxit, p, x0=None, on_iter=None):
+    """BiCG with the left preconditioner K as the paper's Fig. 5 (left) lists it
+    (psolve(v) = K^{-1} v, psolve_t(v) = K^{-T} v): w = K^{-1} r, w~ = K^{-T} r~,
+    rho = (r~, w), p = w + beta p, p~ = w~ + beta p~ (first: p = w, p~ = w~), z = A p,
+    z~ = A^T p~, alpha = rho / (p~, z), x += alpha p, r -= alpha z, r~ -= alpha z~, (*) on r.
+    The listing prints rho = (w~, w) = (r~, K^{-1} K^{-1} r), which breaks BiCG's
+    biorthogonality for K != I (it does not converge on a small convection-diffusion system that
+    plain BiCG solves); rho = (r~, K^{-1} r) = (K^{-T} r~, r) is the preconditioned BiCG's
+    coefficient.  With K = I the two forms agree and this is bicg, operation for operation."""
+    n = len(b)
+    x = list(x0) if x0 is not None else [zero(p)] * n
+    ax = matvec(x)
+    r = [sub(bi, ai) for bi, ai in zip(b, ax)]
+    rt = list(r)
+    q0 = dot(r, r, p)
+    thr = _threshold(sqrt(q0), c_rel, c_abs)
+    hist = []
+    if _converged(q0, thr):
+        return SolveResult(x, CONVERGED, 0, hist)
+    rho_old = None
+    pv = pt = None
+    for i in range(1, maxit + 1):
+        w = psolve(r)
+        wt = psolve_t(rt)
+        rho = dot(rt, w, p)
+        if is_zero(rho):
+            return SolveResult(x, BREAKDOWN_RHO, i - 1, hist)
+        if i == 1:
+            pv, pt = list(w), list(wt)
+        else:
+            beta = div(rho, rho_old)
+            pv = xpby(w, beta, pv)
+            pt = xpby(wt, beta, pt)
+        z = matvec(pv)
+        zt = rmatvec(pt)
+        sigma = dot(pt, z, p)
+        if is_zero(sigma):
+            return SolveResult(x, BREAKDOWN_SIGMA, i - 1, hist)
+        alpha = div(rho, sigma)
+        x = axpy(alpha, pv, x)
+        r = aymx(alpha, z, r)
+        rt = aymx(alpha, zt, rt)
+        q = dot(r, r, p)
+        hist.append(q)
+        if on_iter is not None:
+            on_iter(i, {"x": x, "r": r, "rt": rt, "p": pv, "pt": pt, "rho": rho, "alpha": alpha,
+                        "sigma": sigma, "q": q})
+        if _converged(q, thr):
+            return SolveResult(x, CONVERGED, i, hist)
+        rho_old = rho
+    return SolveResult(x, NOT_CONVERGED, maxit, hist)

@@ -8,7 +8,10 @@ mathematics fixes:
 * triangular solves: L y = r and U w = y to their rounding bounds; in EXACT mode each y_i is the
   rounded exact value; a diagonal U divides;
 * preconditioned BiCGSTAB with the identity preconditioner is plain BiCGSTAB, bit for bit; with
-  ILU(0) it solves small systems to their Gauss solution and needs fewer iterations.
+  ILU(0) it solves small systems to their Gauss solution and needs fewer iterations;
+* the transposed application K^{-T} is the adjoint of K^{-1} (a planted K^{-1} in its place
+  fails); preconditioned BiCG with the identity preconditioner is plain BiCG, bit for bit, and
+  with ILU(0) it reaches the exact solution.
 """
 from fractions import Fraction
 import random
@@ -190,5 +193,68 @@ def test_ilu_bicgstab_solves_and_saves_iterations(mode):
     plain = krylov.bicgstab(mv, b, c_rel, mpnum.zero(p), 200, p)
     assert pre.status == krylov.CONVERGED and plain.status == krylov.CONVERGED
     assert pre.iters < plain.iters
+    err = max(abs(a.to_fraction() - (i + 1)) for i, a in enumerate(pre.x))
+    assert err <= Fraction(n, 10 ** 50)
+
+
+@pytest.mark.parametrize("mode", [spmv.SEQ, spmv.EXACT])
+def test_transposed_application_is_the_adjoint(mode):
+    """<a, K^{-1} c> = <K^{-T} a, c> for the exact operators; the computed sides agree to the
+    solves' rounding (p = 512, so far below any planted mistake's effect), and on a diagonal K
+    both applications divide."""
+    p = 512
+    n = 14
+    rp, ci, vals = rand_sparse(31, n, p, density=0.3)
+    lu = ilu.ilu0(n, rp, ci, vals)
+    rng = random.Random(6)
+    a = [MP(rng.randint(0, 1), rng.getrandbits(p) | (1 << (p - 1)), rng.randint(-3, 3), p) for _ in range(n)]
+    c = [MP(rng.randint(0, 1), rng.getrandbits(p) | (1 << (p - 1)), rng.randint(-3, 3), p) for _ in range(n)]
+    kc = ilu.apply(n, rp, ci, lu, c, p, mode)
+    kta = ilu.apply_t(n, rp, ci, lu, a, p, mode)
+    lhs = sum(x.to_fraction() * y.to_fraction() for x, y in zip(a, kc))
+    rhs = sum(x.to_fraction() * y.to_fraction() for x, y in zip(kta, c))
+    scale = sum(abs(x.to_fraction() * y.to_fraction()) for x, y in zip(a, kc))
+    assert abs(lhs - rhs) <= scale * Fraction(1, 2 ** (p - 40))
+    # a planted mistake (K^{-1} in place of K^{-T}) is far off on a nonsymmetric factor
+    wrong = ilu.apply(n, rp, ci, lu, a, p, mode)
+    rw = sum(x.to_fraction() * y.to_fraction() for x, y in zip(wrong, c))
+    assert abs(lhs - rw) > scale * Fraction(1, 10 ** 6)
+    d = [MP(0, rng.getrandbits(p) | (1 << (p - 1)), rng.randint(-3, 3), p) for _ in range(n)]
+    drp, dci = list(range(n + 1)), list(range(n))
+    assert ilu.apply_t(n, drp, dci, d, a, p, mode) == ilu.apply(n, drp, dci, d, a, p, mode)
+
+
+def test_identity_preconditioner_is_plain_bicg():
+    p = 128
+    n = 16
+    rp, ci, vals = rand_sparse(22, n, p, dominance=1)
+    b = [mpnum.from_int(i + 1, p) for i in range(n)]
+    mv = lambda v: spmv.spmv(rp, ci, vals, v, p, spmv.EXACT)  # noqa: E731
+    rmv = lambda v: spmv.spmv_t(n, n, rp, ci, vals, v, p, spmv.EXACT)  # noqa: E731
+    c_rel = mpnum.round_fraction(Fraction(1, 10 ** 30), p)
+    a = krylov.bicg(mv, rmv, b, c_rel, mpnum.zero(p), 12, p)
+    ident = lambda v: list(v)  # noqa: E731
+    b2 = krylov.bicg_precond(mv, rmv, ident, ident, b, c_rel, mpnum.zero(p), 12, p)
+    assert (a.status, a.iters) == (b2.status, b2.iters)
+    assert a.x == b2.x and a.res_hist == b2.res_hist
+
+
+@pytest.mark.parametrize("mode", [spmv.SEQ, spmv.EXACT])
+def test_ilu_bicg_solves(mode):
+    p = 256
+    A_h, _ = synth.config2(p=p, m=8)
+    n = A_h.n_rows
+    rp, ci = A_h.row_ptr.tolist(), A_h.col_idx.tolist()
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    xs = [mpnum.from_int(i + 1, p) for i in range(n)]
+    b = spmv.spmv_exact(rp, ci, vals, xs, p)
+    lu = ilu.ilu0(n, rp, ci, vals)
+    mv = lambda v: spmv.spmv(rp, ci, vals, v, p, mode)  # noqa: E731
+    rmv = lambda v: spmv.spmv_t(n, n, rp, ci, vals, v, p, mode)  # noqa: E731
+    c_rel = mpnum.round_fraction(Fraction(1, 10 ** 60), p)
+    pre = krylov.bicg_precond(mv, rmv, lambda v: ilu.apply(n, rp, ci, lu, v, p, mode),
+                              lambda v: ilu.apply_t(n, rp, ci, lu, v, p, mode), b, c_rel,
+                              mpnum.zero(p), 300, p)
+    assert pre.status == krylov.CONVERGED
     err = max(abs(a.to_fraction() - (i + 1)) for i, a in enumerate(pre.x))
     assert err <= Fraction(n, 10 ** 50)
