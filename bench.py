@@ -53,7 +53,7 @@ PEAK_MAD_TOPS = 256 * 4 * 16 * 2.4e9 / 2 / 1e12
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("spmv_kernels.hpp", "solver_kernels.hpp", "mp_core.hpp", "mp_exact.hpp",
-                  "mp_scalar.hpp")
+                  "mp_scalar.hpp", "mp_group.hpp")
 WORKLOAD = ("power-law CSR n=500000 (row lengths mean 20, max 2000; 9932151 stored entries), "
             "values log-uniform 1e-8..1e8 with random sign, x uniform [-1,1], p=256; "
             "step = y = A x in SEQ mode + y = A x in EXACT mode")
