@@ -301,12 +301,18 @@ int bicgstab(const mp_csr *A, const mp_plan *plan, const mp_vec *b, mp_vec *x,
  * y_i - sum_j u_ij w_j, then one RN division by u_ii) in the given accumulation mode, as the
  * sparse product sums a row (SEQ: r_i first, then the products in ascending column order; EXACT:
  * exactly, one rounding); asynchronous, level by level; the object's work vectors are shared by
- * its calls, which must not overlap in time.  mp_ilu0_factors copies the factors into lu (A's
- * CSR layout, nnz elements).  Returns MPS_OK, MPS_EINVAL, MPS_ENOMEM or MPS_EHIP. */
+ * its calls, which must not overlap in time.  mp_ilu0_apply_t: w = K^{-T} r = L^{-T} U^{-T} r
+ * (the shadow system's preconditioner in BiCG, Fig. 5 left): y_i = (r_i - sum_k u_ki y_k) / u_ii
+ * over the rows k < i that store column i, then w_i = y_i - sum_k l_ki w_k over the rows k > i
+ * that store column i, each sum over ascending k (the transpose's storage order) in the given
+ * mode; same conventions and shared work vectors as mp_ilu0_apply.  mp_ilu0_factors copies the
+ * factors into lu (A's CSR layout, nnz elements).  Returns MPS_OK, MPS_EINVAL, MPS_ENOMEM or
+ * MPS_EHIP. */
 typedef struct mp_ilu mp_ilu;
 int mp_ilu0_create(const mp_csr *A, void *stream, mp_ilu **ilu);
 int mp_ilu0_destroy(mp_ilu *ilu);
 int mp_ilu0_apply(const mp_ilu *ilu, const mp_vec *r, mp_vec *w, int mode, void *stream);
+int mp_ilu0_apply_t(const mp_ilu *ilu, const mp_vec *r, mp_vec *w, int mode, void *stream);
 int mp_ilu0_factors(const mp_ilu *ilu, mp_vec *lu, void *stream);
 
 /* BiCGSTAB preconditioned by ILU(0) (Sec. 4.2, Table 3), K applied to the two search
@@ -317,6 +323,17 @@ int mp_ilu0_factors(const mp_ilu *ilu, mp_vec *lu, void *stream);
  * (MPS_ENOTSUP).  Otherwise as bicgstab. */
 int bicgstab_ilu0(const mp_csr *A, const mp_ilu *ilu, const mp_vec *b, mp_vec *x,
                   const mp_solve_opts *opts, mp_solve_info *info, void *stream);
+
+/* BiCG preconditioned by ILU(0) (Fig. 5 left with K = L U): w = K^{-1} r, w~ = K^{-T} r~,
+ * rho = (r~, w), beta = rho / rho_old, p = w + beta p, p~ = w~ + beta p~ (first iteration:
+ * p = w, p~ = w~), z = A p, z~ = A^T p~, alpha = rho / (p~, z), x += alpha p, r -= alpha z,
+ * r~ -= alpha z~, and the stopping test (*) on r = b - A x.  The figure prints rho = (w~, w),
+ * which applies K twice and loses BiCG's biorthogonality; this solve uses rho = (r~, K^{-1} r)
+ * = (K^{-T} r~, r), equal to it for K = I.  The triangular solves take opts->mode like the
+ * products; plan as for bicg (NULL: built and freed here); opts->transpose must be 0
+ * (MPS_ENOTSUP).  Statuses and conventions as bicg. */
+int bicg_ilu0(const mp_csr *A, const mp_plan *plan, const mp_ilu *ilu, const mp_vec *b, mp_vec *x,
+              const mp_solve_opts *opts, mp_solve_info *info, void *stream);
 
 /* Batched GPBiCG: nsys systems A[0..nsys-1] (square, same precision, sizes may differ), each
  * with nrhs right-hand sides, solved as nsys * nrhs independent GPBiCG solves (the method of

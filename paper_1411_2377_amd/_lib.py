@@ -127,7 +127,12 @@ SIGNATURES = {
     "mp_ilu0_destroy": [ctypes.c_void_p],
     "mp_ilu0_apply": [ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
                       ctypes.c_void_p],
+    "mp_ilu0_apply_t": [ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec), ctypes.c_int,
+                        ctypes.c_void_p],
     "mp_ilu0_factors": [ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.c_void_p],
+    "bicg_ilu0": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(MpVec),
+                  ctypes.POINTER(MpVec), ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo),
+                  ctypes.c_void_p],
     "bicgstab_ilu0": [ctypes.POINTER(MpCsr), ctypes.c_void_p, ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                       ctypes.POINTER(MpSolveOpts), ctypes.POINTER(MpSolveInfo), ctypes.c_void_p],
     "gpbicg_batched": [ctypes.c_int, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.POINTER(MpVec),

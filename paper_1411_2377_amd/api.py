@@ -276,6 +276,14 @@ class ILU0:
         check(_lib.LIB.mp_ilu0_apply(self._h, ctypes.byref(rd), ctypes.byref(wd), int(mode), _stream(stream)))
         return w
 
+    def apply_t(self, r, w=None, mode=MP_SEQ, stream=None):
+        """w = K^{-T} r.  Returns w."""
+        if w is None:
+            w = MPArray.empty(r.n, r.p, device=r.device)
+        rd, wd = r.desc(), w.desc()
+        check(_lib.LIB.mp_ilu0_apply_t(self._h, ctypes.byref(rd), ctypes.byref(wd), int(mode), _stream(stream)))
+        return w
+
     def factors(self, stream=None):
         """The factors L (strictly below the diagonal) and U in A's CSR layout, as an MPArray."""
         lu = MPArray.empty(self.A.nnz, self.A.p, device=self.A.row_ptr.device)
@@ -298,6 +306,16 @@ class ILU0:
 def bicgstab_ilu0(A, ilu, b, **kw):
     """BiCGSTAB preconditioned by ILU(0) (an ILU0 of A).  Returns (x, SolveInfo)."""
     return _solve(_lib.LIB.bicgstab_ilu0, A, b, plan=_Handle(ilu.handle), **kw)
+
+
+def bicg_ilu0(A, ilu, b, plan=None, **kw):
+    """BiCG preconditioned by ILU(0) (an ILU0 of A), K^{-1} on r and K^{-T} on the shadow
+    residual.  plan: a Plan of A (None: the library builds one).  Returns (x, SolveInfo)."""
+    h = ilu.handle
+
+    def fn(a, pl, bd, xd, o, info, s):
+        return _lib.LIB.bicg_ilu0(a, pl, h, bd, xd, o, info, s)
+    return _solve(fn, A, b, plan=plan, **kw)
 
 
 class _Handle:

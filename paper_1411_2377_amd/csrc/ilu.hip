@@ -11,6 +11,11 @@
 // x = [r; y], which the SEQ and EXACT kernels sum exactly as the rows r_i - sum l_ik y_k are
 // defined (r_i first, then the terms in ascending column order; or exactly, rounded once); then
 // the backward solve the same way on [y; w], each level followed by the division by u_ii.
+//
+// Transposed application K^{-T} r (BiCG's shadow system, Fig. 5 left): U^T y = r forward, then
+// L^T w = y backward, over augmented systems built from the factors' columns (row i of U^T lists
+// the u_ki of the rows k < i that store column i, in ascending k), each forward level followed by
+// the division by u_ii.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,7 +111,31 @@ __global__ void __launch_bounds__(256) ilu_pack_kernel(int64_t n, const int32_t*
   }
 }
 
-// w_i <- RN(w_i / u_ii) for the rows of one backward level (w in place).
+// Values of an augmented system from a map of its entries: +1 where src < 0, else the negated
+// factor entry src.
+template <int L>
+__global__ void __launch_bounds__(256) ilu_pack_map_kernel(int64_t m, const int32_t* __restrict__ src,
+                                                            const uint32_t* __restrict__ lu_limb,
+                                                            const int32_t* __restrict__ lu_hdr, int64_t ld,
+                                                            uint32_t* out_limb, int32_t* out_hdr, int64_t out_ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t t = src[e];
+  Num<L> v;
+  if (t < 0) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) v.m[k] = 0u;
+    v.m[L - 1] = 0x80000000u;
+    v.e = 1;
+    v.s = 0;
+  } else {
+    mp::load<L>(v, lu_limb, lu_hdr, ld, t);
+    v = mp::neg<L>(v);
+  }
+  mp::store<L>(v, out_limb, out_hdr, out_ld, e);
+}
+
+// w_i <- RN(w_i / u_ii) for the rows of one level (w in place).
 template <int L>
 __global__ void __launch_bounds__(256) ilu_div_kernel(const int32_t* __restrict__ rows, int64_t count,
                                                        const int32_t* __restrict__ diag,
@@ -168,6 +197,9 @@ void ilu_free(mp_ilu* K) {
   free_dev(K->rp_lo); free_dev(K->ci_lo); free_dev(K->rp_up); free_dev(K->ci_up);
   free_dev(K->v_lo_limb); free_dev(K->v_lo_hdr); free_dev(K->v_up_limb); free_dev(K->v_up_hdr);
   free_dev(K->fwd_rows); free_dev(K->bwd_rows);
+  free_dev(K->rp_tu); free_dev(K->ci_tu); free_dev(K->rp_tl); free_dev(K->ci_tl);
+  free_dev(K->v_tu_limb); free_dev(K->v_tu_hdr); free_dev(K->v_tl_limb); free_dev(K->v_tl_hdr);
+  free_dev(K->tf_rows); free_dev(K->tb_rows);
   free_dev(K->aug_lo_limb); free_dev(K->aug_lo_hdr); free_dev(K->aug_up_limb); free_dev(K->aug_up_hdr);
   free_dev(K->pivot_flag);
   delete K;
@@ -184,66 +216,95 @@ int check_ilu(const mp_ilu* K, const mp_csr* A) {
   return MPS_OK;
 }
 
-int ilu_apply(const mp_ilu* K, const mp_vec& r, const mp_vec& w, int mode, uint32_t* status,
-              void* ctl_v, hipStream_t s) {
+namespace {
+
+// One triangular solve as level-by-level sparse products over an augmented system: x = [v; y]
+// (v copied in first), each level's rows of y from their row sums, divided by u_ii after the
+// level when `divide`.
+struct TriSys {
+  const int32_t* rp;
+  const int32_t* ci;
+  mp_vec val;
+  const int32_t* rows;
+  const std::vector<int64_t>* ptr;
+  bool divide;
+};
+
+int tri_solve(const mp_ilu* K, const TriSys& T, uint32_t* aug_limb, int32_t* aug_hdr, const mp_vec& in,
+              int mode, uint32_t* status, mp::Ctl* ctl, hipStream_t s) {
   const int L = K->L;
   const int64_t n = K->n;
-  if (n == 0) return MPS_OK;
-  mp::Ctl* ctl = static_cast<mp::Ctl*>(ctl_v);
   const int32_t* done = ctl ? &ctl->done : nullptr;
-  auto half = [&](uint32_t* limb, int32_t* hdr, int64_t off) {
-    mp_vec v;
-    v.limb = limb + off;
-    v.hdr = hdr + off;
-    v.len = n;
-    v.ld = 2 * n;
-    return v;
-  };
-  const mp_vec lo_x{K->aug_lo_limb, K->aug_lo_hdr, 2 * n, 2 * n};
-  const mp_vec up_x{K->aug_up_limb, K->aug_up_hdr, 2 * n, 2 * n};
-  const mp_vec lo_r = half(K->aug_lo_limb, K->aug_lo_hdr, 0), lo_y = half(K->aug_lo_limb, K->aug_lo_hdr, n);
-  const mp_vec up_y = half(K->aug_up_limb, K->aug_up_hdr, 0), up_w = half(K->aug_up_limb, K->aug_up_hdr, n);
-  const mp_vec lo_val{K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->nnz_lo};
-  const mp_vec up_val{K->v_up_limb, K->v_up_hdr, K->nnz_up, K->nnz_up};
+  const mp_vec x{aug_limb, aug_hdr, 2 * n, 2 * n};
+  const mp_vec xv{aug_limb, aug_hdr, n, 2 * n};
+  const mp_vec y{aug_limb + n, aug_hdr + n, n, 2 * n};
   mp::VecArgs a{};
   a.n = n;
   a.ctl = ctl;
   a.status = status;
+  a.v[0] = ref(xv);
+  a.v[1] = ref(in);
   int rr;
-  a.v[0] = ref(lo_r);
-  a.v[1] = ref(r);
   if ((rr = launch_ew(L, EW_COPY, a, s))) return rr;
-  for (size_t l = 0; l + 1 < K->fwd_ptr.size(); ++l) {
+  const std::vector<int64_t>& ptr = *T.ptr;
+  for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     SpmvVariant var;
-    var.rows = K->fwd_rows + K->fwd_ptr[l];
-    const int64_t cnt = K->fwd_ptr[l + 1] - K->fwd_ptr[l];
-    if ((rr = spmv_launch(L, cnt, K->rp_lo, K->ci_lo, lo_val, lo_x, lo_y, mode, status, done, s, nullptr,
-                          nullptr, &var)))
+    var.rows = T.rows + ptr[l];
+    const int64_t cnt = ptr[l + 1] - ptr[l];
+    if ((rr = spmv_launch(L, cnt, T.rp, T.ci, T.val, x, y, mode, status, done, s, nullptr, nullptr, &var)))
       return rr;
-  }
-  a.v[0] = ref(up_y);
-  a.v[1] = ref(lo_y);
-  if ((rr = launch_ew(L, EW_COPY, a, s))) return rr;
-  for (size_t l = 0; l + 1 < K->bwd_ptr.size(); ++l) {
-    SpmvVariant var;
-    var.rows = K->bwd_rows + K->bwd_ptr[l];
-    const int64_t cnt = K->bwd_ptr[l + 1] - K->bwd_ptr[l];
-    if ((rr = spmv_launch(L, cnt, K->rp_up, K->ci_up, up_val, up_x, up_w, mode, status, done, s, nullptr,
-                          nullptr, &var)))
-      return rr;
+    if (!T.divide) continue;
     const unsigned g = blocks_of(cnt);
-    const int32_t* rows = K->bwd_rows + K->bwd_ptr[l];
+    const int32_t* rows = T.rows + ptr[l];
     switch (L) {
-      case 4: hipLaunchKernelGGL(ilu_div_kernel<4>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, up_w.limb, up_w.hdr, up_w.ld, ctl, status); break;
-      case 8: hipLaunchKernelGGL(ilu_div_kernel<8>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, up_w.limb, up_w.hdr, up_w.ld, ctl, status); break;
-      default: hipLaunchKernelGGL(ilu_div_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, up_w.limb, up_w.hdr, up_w.ld, ctl, status); break;
+      case 4: hipLaunchKernelGGL(ilu_div_kernel<4>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
+      case 8: hipLaunchKernelGGL(ilu_div_kernel<8>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
+      default: hipLaunchKernelGGL(ilu_div_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
     }
   }
+  return MPS_OK;
+}
+
+// The two triangular solves of an application: first into the lower work vector's y, then from
+// there into the upper one's, then out to w.
+int two_solves(const mp_ilu* K, const TriSys& first, const TriSys& second, const mp_vec& r,
+               const mp_vec& w, int mode, uint32_t* status, void* ctl_v, hipStream_t s) {
+  const int64_t n = K->n;
+  if (n == 0) return MPS_OK;
+  mp::Ctl* ctl = static_cast<mp::Ctl*>(ctl_v);
+  int rr;
+  if ((rr = tri_solve(K, first, K->aug_lo_limb, K->aug_lo_hdr, r, mode, status, ctl, s))) return rr;
+  const mp_vec y{K->aug_lo_limb + n, K->aug_lo_hdr + n, n, 2 * n};
+  if ((rr = tri_solve(K, second, K->aug_up_limb, K->aug_up_hdr, y, mode, status, ctl, s))) return rr;
+  mp::VecArgs a{};
+  a.n = n;
+  a.ctl = ctl;
+  a.status = status;
   a.v[0] = ref(w);
-  a.v[1] = ref(up_w);
-  if ((rr = launch_ew(L, EW_COPY, a, s))) return rr;
+  a.v[1] = ref(mp_vec{K->aug_up_limb + n, K->aug_up_hdr + n, n, 2 * n});
+  if ((rr = launch_ew(K->L, EW_COPY, a, s))) return rr;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "ILU(0) application");
+}
+
+}  // namespace
+
+int ilu_apply(const mp_ilu* K, const mp_vec& r, const mp_vec& w, int mode, uint32_t* status,
+              void* ctl, hipStream_t s) {
+  const TriSys lo{K->rp_lo, K->ci_lo, mp_vec{K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->nnz_lo},
+                  K->fwd_rows, &K->fwd_ptr, false};
+  const TriSys up{K->rp_up, K->ci_up, mp_vec{K->v_up_limb, K->v_up_hdr, K->nnz_up, K->nnz_up},
+                  K->bwd_rows, &K->bwd_ptr, true};
+  return two_solves(K, lo, up, r, w, mode, status, ctl, s);
+}
+
+int ilu_apply_t(const mp_ilu* K, const mp_vec& r, const mp_vec& w, int mode, uint32_t* status,
+                void* ctl, hipStream_t s) {
+  const TriSys tu{K->rp_tu, K->ci_tu, mp_vec{K->v_tu_limb, K->v_tu_hdr, K->nnz_tu, K->nnz_tu},
+                  K->tf_rows, &K->tf_ptr, true};
+  const TriSys tl{K->rp_tl, K->ci_tl, mp_vec{K->v_tl_limb, K->v_tl_hdr, K->nnz_tl, K->nnz_tl},
+                  K->tb_rows, &K->tb_ptr, false};
+  return two_solves(K, tu, tl, r, w, mode, status, ctl, s);
 }
 
 }  // namespace mpapi
@@ -283,6 +344,37 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
     rlo[i + 1] = (int32_t)clo.size();
     rup[i + 1] = (int32_t)cup.size();
   }
+  // the factors' columns: for column i, the rows k storing it (ascending) and their entries
+  std::vector<int32_t> tp(n + 1, 0), tk(nnz), tt(nnz);
+  for (int64_t t = 0; t < nnz; ++t) tp[ci[t] + 1]++;
+  for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+  {
+    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+    for (int64_t k = 0; k < n; ++k)
+      for (int32_t t = rp[k]; t < rp[k + 1]; ++t) {
+        const int32_t f = fill[ci[t]]++;
+        tk[f] = (int32_t)k;
+        tt[f] = t;
+      }
+  }
+  std::vector<int32_t> rtu(n + 1, 0), rtl(n + 1, 0), ctu, ctl_, stu, stl;
+  for (int64_t i = 0; i < n; ++i) {
+    ctu.push_back((int32_t)i);
+    stu.push_back(-1);
+    ctl_.push_back((int32_t)i);
+    stl.push_back(-1);
+    for (int32_t f = tp[i]; f < tp[i + 1]; ++f) {
+      if (tk[f] < i) {
+        ctu.push_back((int32_t)(n + tk[f]));
+        stu.push_back(tt[f]);
+      } else if (tk[f] > i) {
+        ctl_.push_back((int32_t)(n + tk[f]));
+        stl.push_back(tt[f]);
+      }
+    }
+    rtu[i + 1] = (int32_t)ctu.size();
+    rtl[i + 1] = (int32_t)ctl_.size();
+  }
   mp_ilu* K = new mp_ilu();
   K->device = 0;
   (void)hipGetDevice(&K->device);
@@ -295,6 +387,12 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
   std::vector<int32_t> frows, brows;
   levels(n, rp, ci, true, frows, K->fwd_ptr);
   levels(n, rp, ci, false, brows, K->bwd_ptr);
+  std::vector<int32_t> tfrows, tbrows;
+  levels(n, tp, tk, true, tfrows, K->tf_ptr);
+  levels(n, tp, tk, false, tbrows, K->tb_ptr);
+  K->nnz_tu = (int64_t)ctu.size();
+  K->nnz_tl = (int64_t)ctl_.size();
+  int32_t *src_tu = nullptr, *src_tl = nullptr;
   auto alloc = [&](auto*& p, size_t bytes) {
     return hipMalloc((void**)&p, std::max<size_t>(bytes, 4));
   };
@@ -318,7 +416,24 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
   if (e == hipSuccess) e = alloc(K->aug_up_limb, (size_t)L * 2 * n * 4);
   if (e == hipSuccess) e = alloc(K->aug_up_hdr, 2 * n * 4);
   if (e == hipSuccess) e = alloc(K->pivot_flag, 4);
+  if (e == hipSuccess) e = alloc(K->rp_tu, (n + 1) * 4);
+  if (e == hipSuccess) e = alloc(K->ci_tu, K->nnz_tu * 4);
+  if (e == hipSuccess) e = alloc(K->rp_tl, (n + 1) * 4);
+  if (e == hipSuccess) e = alloc(K->ci_tl, K->nnz_tl * 4);
+  if (e == hipSuccess) e = alloc(K->v_tu_limb, (size_t)L * K->nnz_tu * 4);
+  if (e == hipSuccess) e = alloc(K->v_tu_hdr, K->nnz_tu * 4);
+  if (e == hipSuccess) e = alloc(K->v_tl_limb, (size_t)L * K->nnz_tl * 4);
+  if (e == hipSuccess) e = alloc(K->v_tl_hdr, K->nnz_tl * 4);
+  if (e == hipSuccess) e = alloc(K->tf_rows, n * 4);
+  if (e == hipSuccess) e = alloc(K->tb_rows, n * 4);
+  if (e == hipSuccess) e = alloc(src_tu, K->nnz_tu * 4);
+  if (e == hipSuccess) e = alloc(src_tl, K->nnz_tl * 4);
+  auto free_src = [&] {
+    free_dev(src_tu);
+    free_dev(src_tl);
+  };
   if (e != hipSuccess) {
+    free_src();
     ilu_free(K);
     return fail(MPS_ENOMEM, "ILU(0) allocation: %s", hipGetErrorString(e));
   }
@@ -331,9 +446,18 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
   if (e == hipSuccess && n) e = hipMemcpyAsync(K->ci_up, cup.data(), cup.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && n) e = hipMemcpyAsync(K->fwd_rows, frows.data(), n * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && n) e = hipMemcpyAsync(K->bwd_rows, brows.data(), n * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(K->rp_tu, rtu.data(), (n + 1) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(K->ci_tu, ctu.data(), ctu.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(K->rp_tl, rtl.data(), (n + 1) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(K->ci_tl, ctl_.data(), ctl_.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(src_tu, stu.data(), stu.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(src_tl, stl.data(), stl.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(K->tf_rows, tfrows.data(), n * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n) e = hipMemcpyAsync(K->tb_rows, tbrows.data(), n * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(K->pivot_flag, 0, 4, s);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);
+    free_src();
     ilu_free(K);
     return hip_fail(e, "ILU(0) setup");
   }
@@ -344,6 +468,7 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
   a.v[1] = ref(A->val);
   if ((r = launch_ew(L, EW_COPY, a, s))) {
     (void)hipStreamSynchronize(s);
+    free_src();
     ilu_free(K);
     return r;
   }
@@ -364,10 +489,28 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
       default: hipLaunchKernelGGL(ilu_pack_kernel<16>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
     }
   }
+  if (n) {
+    const int64_t mu = K->nnz_tu, ml = K->nnz_tl;
+    switch (L) {
+      case 4:
+        hipLaunchKernelGGL(ilu_pack_map_kernel<4>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
+        hipLaunchKernelGGL(ilu_pack_map_kernel<4>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
+        break;
+      case 8:
+        hipLaunchKernelGGL(ilu_pack_map_kernel<8>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
+        hipLaunchKernelGGL(ilu_pack_map_kernel<8>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
+        break;
+      default:
+        hipLaunchKernelGGL(ilu_pack_map_kernel<16>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
+        hipLaunchKernelGGL(ilu_pack_map_kernel<16>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
+        break;
+    }
+  }
   int32_t piv = 0;
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&piv, K->pivot_flag, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  free_src();
   if (e != hipSuccess) {
     ilu_free(K);
     return hip_fail(e, "ILU(0) factorisation");
@@ -398,6 +541,19 @@ int mp_ilu0_apply(const mp_ilu* ilu, const mp_vec* r, mp_vec* w, int mode, void*
   DeviceCtx* ctx;
   if ((rr = get_ctx(&ctx))) return rr;
   return ilu_apply(ilu, *r, *w, mode, ctx->status, nullptr, (hipStream_t)stream);
+}
+
+int mp_ilu0_apply_t(const mp_ilu* ilu, const mp_vec* r, mp_vec* w, int mode, void* stream) {
+  clear_error();
+  if (!ilu) return fail(MPS_EINVAL, "null preconditioner");
+  if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  int rr;
+  if ((rr = check_vec(r, ilu->n, "r"))) return rr;
+  if ((rr = check_vec(w, ilu->n, "w"))) return rr;
+  if (vec_overlap(r, w, ilu->L)) return fail(MPS_EINVAL, "w overlaps r");
+  DeviceCtx* ctx;
+  if ((rr = get_ctx(&ctx))) return rr;
+  return ilu_apply_t(ilu, *r, *w, mode, ctx->status, nullptr, (hipStream_t)stream);
 }
 
 int mp_ilu0_factors(const mp_ilu* ilu, mp_vec* lu, void* stream) {

@@ -28,6 +28,16 @@ struct mp_ilu {
   // level sets: rows in order of level, and each level's first position (host)
   int32_t *fwd_rows = nullptr, *bwd_rows = nullptr;
   std::vector<int64_t> fwd_ptr, bwd_ptr;
+  // the transposed factors' augmented systems, for K^{-T} r = L^{-T} (U^{-T} r): row i of the
+  // first holds (column i: +1) and (column n + k: -u_ki) for the k < i whose row stores column
+  // i, of the second (column i: +1) and (column n + k: -l_ki) for those k > i, both in
+  // ascending k (the transpose's row order); U^T's rows are then divided by u_ii
+  int32_t *rp_tu = nullptr, *ci_tu = nullptr, *rp_tl = nullptr, *ci_tl = nullptr;
+  uint32_t *v_tu_limb = nullptr, *v_tl_limb = nullptr;
+  int32_t *v_tu_hdr = nullptr, *v_tl_hdr = nullptr;
+  int64_t nnz_tu = 0, nnz_tl = 0;
+  int32_t *tf_rows = nullptr, *tb_rows = nullptr;  // level sets of U^T (forward), L^T (backward)
+  std::vector<int64_t> tf_ptr, tb_ptr;
   // work vectors [r; y] and [y; w] (2n elements each; calls must not overlap in time)
   uint32_t *aug_lo_limb = nullptr, *aug_up_limb = nullptr;
   int32_t *aug_lo_hdr = nullptr, *aug_up_hdr = nullptr;
@@ -39,5 +49,8 @@ namespace mpapi {
 // solve's mp::Ctl): every launch is a no-op once the solve is done.
 int ilu_apply(const mp_ilu* K, const mp_vec& r, const mp_vec& w, int mode, uint32_t* status,
               void* ctl, hipStream_t s);
+// w = K^{-T} r = L^{-T} (U^{-T} r), the same way over the transposed factors' systems.
+int ilu_apply_t(const mp_ilu* K, const mp_vec& r, const mp_vec& w, int mode, uint32_t* status,
+                void* ctl, hipStream_t s);
 int check_ilu(const mp_ilu* K, const mp_csr* A);
 }  // namespace mpapi

@@ -939,6 +939,72 @@ int bicgstab_ilu0_impl(const mp_csr* A, const mp_ilu* K, const mp_vec* b, mp_vec
   return finish_solve(W, info, st);
 }
 
+// BiCG with the ILU(0) preconditioner K (Fig. 5 left): w = K^{-1} r, w~ = K^{-T} r~,
+// rho = (r~, w) (zero: breakdown), beta = rho / rho_old, p = w + beta p, p~ = w~ + beta p~
+// (first iteration: p = w, p~ = w~), z = A p with sigma = (p~, z), z~ = A^T p~, alpha = rho /
+// sigma, x += alpha p, r -= alpha z, r~ -= alpha z~, (*) on r.
+// Work vectors: 0 r, 1 rt, 2 z, 3 p, 4 pt, 5 zt, 6 w, 7 wt
+int bicg_ilu0_impl(const mp_csr* A, const mp_plan* plan, const mp_ilu* K, const mp_vec* b, mp_vec* x,
+                   const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_solve_args(A, b, x, o, info);
+  if (r) return r;
+  if (o->transpose) return fail(MPS_ENOTSUP, "the preconditioned solve takes A, not its transpose");
+  if ((r = check_ilu(K, A))) return r;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if (!plan) {
+    if ((r = plan_build(A, user, &own.p))) return r;
+    plan = own.p;
+  } else if ((r = check_plan(plan, A))) {
+    return r;
+  }
+  const int L = limbs_of(A->prec);
+  Work W;
+  if ((r = work_alloc(W, L, A->row_dim, 8, user))) return r;
+  Op op, opT;
+  make_ops(A, plan, 0, &op, &opT);
+  uint32_t* st = ctx->status;
+  if ((r = solve_setup(W, op, b, x, o, st))) return r;
+  if ((r = clear_vectors(W, 2, 8, st))) return r;
+  if ((r = prof_init(W, o->profile))) return r;
+  const mp::VecRef R = W.vec(0), RT = W.vec(1), Z = W.vec(2), P = W.vec(3), PT = W.vec(4), ZT = W.vec(5),
+                   Wv = W.vec(6), WT = W.vec(7);
+  const mp::VecRef X = ref(*x);
+  mp::VecRef hist{nullptr, nullptr, 0};
+  if (o->res_hist && o->res_hist->len > 0) hist = ref(*o->res_hist);
+  const double sp_bytes = spmv_bytes(A, L), dot1 = vec_bytes(W, 1);
+  auto iteration = [&]() -> int {
+    int rr;
+    if ((rr = ilu_apply(K, W.desc(0), W.desc(6), o->mode, st, W.ctl, W.ws))) return rr;
+    if ((rr = ilu_apply_t(K, W.desc(1), W.desc(7), o->mode, st, W.ctl, W.ws))) return rr;
+    mp::DotArgs d = dot_args(W, st, mp::EPI_PRHO);
+    d.o.nd = 1;
+    d.x[0] = RT;
+    d.y[0] = Wv;
+    d.o.out[0] = mp::slot_ref(W.S, mp::S_RHO_NEXT);
+    d.o.sslot[0] = mp::S_RHO_NEXT;
+    d.o.slot[0] = 3;
+    if ((rr = launch_dot(L, d, W.ws))) return rr;
+    mp::VecArgs a = ew_args(W, st);
+    a.v[0] = P; a.v[1] = PT; a.v[2] = Wv; a.v[3] = WT;
+    if ((rr = timed(W, PROF_DIR, vec_bytes(W, 6), [&] { return launch_ew(L, EW_BICG_DIR, a, W.ws); })))
+      return rr;
+    const SpmvFuse sig = fuse_of(W, mp::EPI_NONE, {{PT, 0, mp::S_SIGMA}});
+    if ((rr = timed(W, PROF_SPMV_DOT, sp_bytes + dot1, [&] { return apply(W, op, o->mode, P, Z, st, true, &sig); })))
+      return rr;
+    if ((rr = timed(W, PROF_SPMV, sp_bytes, [&] { return apply(W, opT, o->mode, PT, ZT, st, true); })))
+      return rr;
+    a = ew_args(W, st);
+    a.v[0] = X; a.v[1] = R; a.v[2] = RT; a.v[3] = P; a.v[4] = Z; a.v[5] = ZT;
+    // the update also forms (r~, r) in its second slot; this solve's rho comes from K^{-1} r
+    set_fd(W, a, mp::EPI_CONV, {{1, mp::S_Q}, {2, mp::S_RHO_NEXT}}, hist);
+    return timed(W, PROF_UPD, vec_bytes(W, 9), [&] { return launch_ew(L, EW_BICG_UPDATE, a, W.ws); });
+  };
+  if ((r = run_iterations(W, o, iteration))) return r;
+  return finish_solve(W, info, st);
+}
+
 // ---- batched GPBiCG --------------------------------------------------------------------
 // nsys systems, nrhs right-hand sides each: nsys * nrhs independent solves ("pairs", pair
 // s * nrhs + k) advanced together.  The systems are concatenated into one block-diagonal CSR
@@ -1184,6 +1250,12 @@ int bicgstab_ilu0(const mp_csr* A, const mp_ilu* ilu, const mp_vec* b, mp_vec* x
                   const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
   return bicgstab_ilu0_impl(A, ilu, b, x, opts, info, (hipStream_t)stream);
+}
+
+int bicg_ilu0(const mp_csr* A, const mp_plan* plan, const mp_ilu* ilu, const mp_vec* b, mp_vec* x,
+              const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
+  clear_error();
+  return bicg_ilu0_impl(A, plan, ilu, b, x, opts, info, (hipStream_t)stream);
 }
 
 int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec* x,

@@ -114,6 +114,8 @@ enum Epi {
   EPI_SETUP,        // q0 = (r,r), rho = (rt,r): nrm0, thr = c_rel*nrm0 + c_abs, test r_0
   EPI_BICG_CONV,    // q = (r,r), rho' = (rt,r): stopping test, then beta = rho'/rho
   EPI_GP_CONV,      // q = (r,r), rho' = (rt,r): stopping test, zeta = 0 exit, beta
+  EPI_CONV,         // q = (r,r): stopping test only (preconditioned BiCG)
+  EPI_PRHO,         // rho' = (rt, K^{-1} r): zero exit, then beta = rho'/rho after the first
 };
 
 // Step prologues: scalars a step needs that follow from the inner products of the launch before
@@ -297,6 +299,43 @@ MPD void epilogue_body(int epi, const ScalarView<L>& sv, Ctl* ctl, int iters, in
         put(S_ZETA_OLD, zeta);
         put(S_BETA, mul(d0, d1));
       }
+      break;
+    }
+    case EPI_CONV: {
+      const Num<L> q = sv.get(S_Q);
+      const int i = iters + 1;
+      if (w0) {
+        if (hist.limb && i - 1 < hist_len) vstore<L>(hist, i - 1, q);
+        ctl->iters = i;
+      }
+      if (s_sqrt_le<L>(q, sv.get(S_THR))) {
+        done(kConverged);
+      } else if (i >= maxit) {
+        done(kNotConverged);
+      }
+      break;
+    }
+    case EPI_PRHO: {
+      const Num<L> rho_next = sv.get(S_RHO_NEXT);
+      if (is_zero(rho_next)) {
+        done(kBreakRho);
+        break;
+      }
+      if (iters == 0) {
+        put(S_RHO, rho_next);
+        break;
+      }
+      const Num<L> rho = sv.get(S_RHO);
+      const int lane = threadIdx.x & 63;
+      NumSt<L> dq;
+      dq.st = 0;
+      set_zero(dq.v, 0);
+      if (lane == 0) dq = s_div<L>(rho_next, rho);
+      const Num<L> beta = shfl_num<L>(dq.v, 0);
+      st |= __shfl(dq.st, 0);
+      put(S_RHO_OLD, rho);
+      put(S_RHO, rho_next);
+      put(S_BETA, beta);
       break;
     }
     default:

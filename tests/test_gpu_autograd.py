@@ -132,6 +132,67 @@ def test_finite_differences_powerlaw(p):
         assert abs(got - want) <= abs(want) * Fraction(1, 2 ** (p // 3))   # and well inside p/3 bits
 
 
+def approx_abs(h):
+    """|v| of a host MP array in double, from the top limb (relative error below 2^-31)."""
+    e = (h.hdr >> 1).astype(np.int64)
+    top = h.limbs[h.limbs.shape[0] - 1].astype(np.float64)
+    v = np.ldexp(top, (e - 32).clip(-1000, 1000))
+    return np.where(h.hdr == np.int32(-(1 << 31)), 0.0, v)
+
+
+def test_finite_differences_powerlaw_seq():
+    """SEQ mode on the power-law workload at p = 256: the gradient of L(x) = <g, A x> (A^T g in
+    SEQ order) against central differences of the SEQ loss.  Row i's SEQ sum is within
+    gamma_k sum_j |a_ij x_j| of the exact one (k = row length + 1), and column j's transposed SEQ
+    sum within gamma_k sum_i |a_ij g_i|, so
+    |FD - grad| <= (2 sum_i |g_i| gamma_k_i T_i + 2^-p |L+| + 2^-p |L-|) / |v+ - v-| + gamma C_j."""
+    M = lib()
+    p = 256
+    A_h, x_h, g_h = synth.config3(p=p)
+    A = M.CSRMatrix.from_host(A_h)
+    S = M.autograd.SparseStructure.of(A)
+    vt, xt = packed(M, A_h.vals), packed(M, x_h)
+    y = M.autograd.spmv(S, vt, xt, 0)
+    y.backward(M.autograd.pack(M.MPArray.from_host(g_h)))
+    gx = to_np(M, xt.grad, p)
+    g = M.MPArray.from_host(g_h)
+    u = 2.0 ** -p
+    rows = np.repeat(np.arange(A_h.n_rows), np.diff(A_h.row_ptr))
+    av, xv, gv = approx_abs(A_h.vals), approx_abs(x_h), approx_abs(g_h)
+    T = np.bincount(rows, weights=av * xv[A_h.col_idx], minlength=A_h.n_rows)
+    C = np.bincount(A_h.col_idx, weights=av * gv[rows], minlength=A_h.n_cols)
+    k = np.diff(A_h.row_ptr).astype(np.float64) + 1
+    kc = np.bincount(A_h.col_idx, minlength=A_h.n_cols).astype(np.float64) + 1
+    row_err = float(np.sum(gv * (k * u / (1 - k * u)) * T)) * (1 + 2.0 ** -20)
+    xdev = M.MPArray.from_host(x_h)
+
+    def seq_loss(xd):
+        yy = M.mpspmv_csr(A, xd, mode=0)
+        d = M.mp_dot(g, yy).to_numpy()
+        return codec.decode(d[0], d[1], p)[0].to_fraction()
+    rng = np.random.default_rng(9)
+    for j in [int(v) for v in rng.integers(0, A_h.n_cols, 6)] + [int(np.argmax(kc))]:
+        v = codec.decode(x_h.limbs[:, [j]], x_h.hdr[[j]], p)[0]
+        h = mpnum.MP(0, 1 << (p - 1), v.e - 12, p) if v.m else mpnum.round_fraction(Fraction(1, 2 ** 40), p)
+        out = []
+        for nv in (mpnum.add(v, h), mpnum.sub(v, h)):
+            l, hh = codec.encode([nv], p)
+            xdev.limbs[:, j] = torch.from_numpy(l[:, 0].view(np.int32)).to(xdev.limbs.device)
+            xdev.hdr[j] = int(hh[0])
+            out.append((seq_loss(xdev), nv))
+        l, hh = codec.encode([v], p)
+        xdev.limbs[:, j] = torch.from_numpy(l[:, 0].view(np.int32)).to(xdev.limbs.device)
+        xdev.hdr[j] = int(hh[0])
+        (lp, vp), (lm, vm) = out
+        dv = vp.to_fraction() - vm.to_fraction()
+        got = (lp - lm) / dv
+        want = codec.decode(gx[0][:, [j]], gx[1][[j]], p)[0].to_fraction()
+        slack = (Fraction(2 * row_err) + Fraction(u) * (abs(lp) + abs(lm))) / abs(dv) + \
+            Fraction(float(kc[j] * u / (1 - kc[j] * u) * C[j] * (1 + 2.0 ** -20)))
+        assert abs(got - want) <= slack, (j, float(got), float(want), float(slack))
+        assert abs(got - want) <= abs(want) * Fraction(1, 2 ** (p // 3))
+
+
 def test_solve_adjoint_matches_oracle_and_duality():
     """x = A^{-1} b (2-D convection-diffusion, 6 x 6 grid, p = 512, b = A [1..n], relative
     tolerance 1e-100); d(sum x)/db = lambda from one transposed solve, bit-identical to the

@@ -1,6 +1,7 @@
 """ILU(0) on the GPU against the oracle, bit for bit: the factors (row-wise, one RN per
-operation), the preconditioner's application K^{-1} r in both accumulation modes, and
-BiCGSTAB preconditioned by it (every iterate, status, residual history, every chunk size)."""
+operation), the preconditioner's applications K^{-1} r and K^{-T} r in both accumulation modes,
+and BiCGSTAB and BiCG preconditioned by it (every iterate, status, residual history, every chunk
+size)."""
 from fractions import Fraction
 import random
 
@@ -75,6 +76,8 @@ def test_factors_and_application(case, p):
     for mode in (0, 1):
         wl, wh = K.apply(r, mode=mode).to_numpy()
         assert_bitwise(wl, wh, ilu.apply(n, rp, ci, lu, ro, p, mode), p, what="K^-1 r mode %d" % mode)
+        wl, wh = K.apply_t(r, mode=mode).to_numpy()
+        assert_bitwise(wl, wh, ilu.apply_t(n, rp, ci, lu, ro, p, mode), p, what="K^-T r mode %d" % mode)
     assert M.mp_status() == 0
 
 
@@ -122,6 +125,72 @@ def test_preconditioned_bicgstab_matches_oracle(mode):
     plain = krylov.bicgstab(lambda v: ospmv.spmv(rp, ci, vals, v, p, mode), bo, c_rel, mpnum.zero(p), 200, p)
     assert ref.iters < plain.iters
     assert M.mp_status() == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+@pytest.mark.parametrize("case", ["convdiff2d_10", "random_120"])
+def test_preconditioned_bicg_matches_oracle(case, mode):
+    M = lib()
+    p = 256
+    A_h = synth.config2(p=p, m=10)[0] if case == "convdiff2d_10" else rand_pattern(5, 120, p, density=0.05)
+    n = A_h.n_rows
+    rp, ci = A_h.row_ptr.tolist(), A_h.col_idx.tolist()
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    xs = synth.mp_arange1(n, p)
+    A = M.CSRMatrix.from_host(A_h)
+    b = M.mpspmv_csr(A, M.MPArray.from_host(xs), mode=1)
+    bo = ospmv.spmv_exact(rp, ci, vals, codec.decode(xs.limbs, xs.hdr, p), p)
+    K = M.ILU0(A)
+    lu = ilu.ilu0(n, rp, ci, vals)
+    tp, ti, tv = ospmv.transpose(n, n, rp, ci, vals)
+    c_rel = mpnum.round_fraction(Fraction(1, 10 ** 60), p)
+    ref = krylov.bicg_precond(lambda v: ospmv.spmv(rp, ci, vals, v, p, mode),
+                              lambda v: ospmv.spmv(tp, ti, tv, v, p, mode),
+                              lambda v: ilu.apply(n, rp, ci, lu, v, p, mode),
+                              lambda v: ilu.apply_t(n, rp, ci, lu, v, p, mode), bo, c_rel,
+                              mpnum.zero(p), 150, p)
+    assert ref.status == krylov.CONVERGED
+    plan = M.Plan(A)
+    for chunk in (5, 0):
+        x, info = M.bicg_ilu0(A, K, b, plan=plan if chunk else None, mode=mode, maxit=150, rtol=(1, -60),
+                              atol=(0, 0), chunk=chunk, hist=True)
+        assert (info.status, info.iters) == (ref.status, ref.iters)
+        xl, xh = x.to_numpy()
+        assert_bitwise(xl, xh, ref.x, p, what="x")
+        hl, hh = info.res_hist.to_numpy()
+        assert_bitwise(hl[:, :ref.iters], hh[:ref.iters], ref.res_hist, p, what="history")
+    assert M.mp_status() == 0
+
+
+def test_preconditioned_bicg_limits():
+    """maxit reached (NC after exactly maxit iterations, iterate as the oracle's), and the
+    transposed system refused."""
+    M = lib()
+    p = 128
+    A_h = synth.config2(p=p, m=6)[0]
+    n = A_h.n_rows
+    rp, ci = A_h.row_ptr.tolist(), A_h.col_idx.tolist()
+    vals = codec.decode(A_h.vals.limbs, A_h.vals.hdr, p)
+    A = M.CSRMatrix.from_host(A_h)
+    bh = synth.mp_uniform(np.random.default_rng(3), n, p)
+    b = M.MPArray.from_host(bh)
+    K = M.ILU0(A)
+    lu = ilu.ilu0(n, rp, ci, vals)
+    tp, ti, tv = ospmv.transpose(n, n, rp, ci, vals)
+    c_rel = mpnum.round_fraction(Fraction(1, 10 ** 30), p)
+    ref = krylov.bicg_precond(lambda v: ospmv.spmv(rp, ci, vals, v, p, 0),
+                              lambda v: ospmv.spmv(tp, ti, tv, v, p, 0),
+                              lambda v: ilu.apply(n, rp, ci, lu, v, p, 0),
+                              lambda v: ilu.apply_t(n, rp, ci, lu, v, p, 0),
+                              codec.decode(bh.limbs, bh.hdr, p), c_rel, mpnum.zero(p), 3, p)
+    assert ref.status == krylov.NOT_CONVERGED and ref.iters == 3
+    x, info = M.bicg_ilu0(A, K, b, mode=0, maxit=3, rtol=(1, -30), atol=(0, 0), chunk=2)
+    assert (info.status, info.iters) == (ref.status, ref.iters)
+    xl, xh = x.to_numpy()
+    assert_bitwise(xl, xh, ref.x, p, what="x after maxit")
+    with pytest.raises(M.MPError):
+        M.bicg_ilu0(A, K, b, mode=0, maxit=3, transpose=True)
+    M.mp_status(raise_on_error=False)
 
 
 def test_missing_diagonal_and_zero_pivot():
