@@ -424,10 +424,16 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
       if (c + 1 < nch) produce(c + 1, b ^ 1);
     } else {
       const int qn = min(Q, maxlen - c * Q);
+      // the next product is read from LDS while the current one is added
+      uint32_t pm_next = g_m[b][g * RS + G.w];
+      int32_t ph_next = g_h[b][g * (Q + 1)];
       for (int o = 0; o < qn; ++o) {
         const bool act = c * Q + o < glen;  // rows that ended add +0 (their sum is kept)
-        const uint32_t pm = g_m[b][g * RS + o * L + G.w];
-        const int32_t ph = g_h[b][g * (Q + 1) + o];
+        const uint32_t pm = pm_next;
+        const int32_t ph = ph_next;
+        const int on = min(o + 1, Q - 1);
+        pm_next = g_m[b][g * RS + on * L + G.w];
+        ph_next = g_h[b][g * (Q + 1) + on];
         group_add_rn<L>(G, am, ae, as, act ? pm : 0u, act ? (ph >> 1) : kZeroE,
                         act ? ((uint32_t)ph & 1u) : 0u, st);
       }
