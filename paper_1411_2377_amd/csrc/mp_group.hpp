@@ -141,17 +141,18 @@ MPD uint32_t group_or_down(uint32_t v) {
   return v;
 }
 
-// The value of the group's top lane (limb L - 1), in every lane of the group.
+// The value of the group's top lane (limb L - 1), in every lane of the group (every lane is a
+// valid source, so the old value passed is never kept).
 template <int L>
 MPD uint32_t group_top(uint32_t v) {
   if constexpr (L == 4) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xFF, 0xf, 0xf, false);  // quad_perm 3,3,3,3
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xFF, 0xf, 0xf, false);  // quad_perm 3,3,3,3
   } else if constexpr (L == 8) {
-    const uint32_t t7 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x157, 0xf, 0xf, false);  // row_newbcast:7
-    const uint32_t t15 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x15F, 0xf, 0xf, false);
+    const uint32_t t7 = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x157, 0xf, 0xf, false);  // row_newbcast:7
+    const uint32_t t15 = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x15F, 0xf, 0xf, false);
     return (threadIdx.x & 8u) ? t15 : t7;
   } else {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x15F, 0xf, 0xf, false);  // row_newbcast:15
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x15F, 0xf, 0xf, false);  // row_newbcast:15
   }
 }
 
@@ -319,8 +320,9 @@ MPD bool group_add_fast(const Group<L>& G, uint32_t& am, int32_t& ae, uint32_t& 
   const uint32_t cin = (w == 0) ? (cg ? 1u : 0u) : gen_below;
   const bool chain = cin != 0u && s0 == ~0u;
   const uint32_t rm = s0 + cin;
-  const bool co = group_top<L>(gen) != 0u;
-  const uint32_t top = group_top<L>(rm);
+  // the top limb's two leading bits and its carry out, in one broadcast
+  const uint32_t top = group_top<L>((rm & 0xC0000000u) | gen);
+  const bool co = (top & 1u) != 0u;
   const bool neg = sub && !co;
   const bool ovf = !sub && co;
   const bool lz0 = (top >> 31) != 0u, lz1 = (top >> 30) == 1u;

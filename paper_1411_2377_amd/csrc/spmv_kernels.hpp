@@ -395,16 +395,18 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
       k[0] = ok[0] ? (int64_t)g_rs[r] + e : 0;
       EntryLoad<L, 1> E;
       load_entries<L, 1>(E, A, x_limb, x_hdr, k, ok);
-      if (!ok[0]) continue;
       const int32_t ha = E.ha[0], hx = E.hx[0];
       Num<L> p;
-      if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
+      if (!ok[0]) {
+        set_zero(p, 0u);  // past the row's end: +0, which leaves the sum as it is
+      } else if (hdr_is_zero(ha) || hdr_is_zero(hx)) {
         set_zero(p, (uint32_t)(ha ^ hx) & 1u);
       } else {
         uint32_t pr[2 * L];
         mul_full<L>(E.am[0], E.xm[0], pr);
         round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, p, st);
       }
+      if (r >= nr) continue;
 #pragma unroll
       for (int w = 0; w < L; ++w) g_m[b][r * RS + o * L + w] = p.m[w];
       g_h[b][r * (Q + 1) + o] = make_hdr(p.e, p.s);
@@ -412,36 +414,37 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
   };
 
   const Group<L> G = group_of_lane<L>();
-  const int g = lane / L;
-  const int glen = (wv == 0 && g < nr) ? g_len[g] : 0;
+  const int gi = lane / L;
+  const int g = min(gi, max(nr - 1, 0));  // groups without a row repeat the last one's (unstored)
   uint32_t am = 0u, as = 0u;
   int32_t ae = kZeroE;
   if (wv > 0 && nch > 0) produce(0, 0);
+  // the chains are the block's critical path: their wavefront issues first
+  if (wv == 0) __builtin_amdgcn_s_setprio(3);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int b = c & 1;
     if (wv > 0) {
       if (c + 1 < nch) produce(c + 1, b ^ 1);
     } else {
+      // rows that ended add the +0 products past their end (their sums are kept); the next
+      // product is read from LDS while the current one is added
       const int qn = min(Q, maxlen - c * Q);
-      // the next product is read from LDS while the current one is added
       uint32_t pm_next = g_m[b][g * RS + G.w];
       int32_t ph_next = g_h[b][g * (Q + 1)];
       for (int o = 0; o < qn; ++o) {
-        const bool act = c * Q + o < glen;  // rows that ended add +0 (their sum is kept)
         const uint32_t pm = pm_next;
         const int32_t ph = ph_next;
         const int on = min(o + 1, Q - 1);
         pm_next = g_m[b][g * RS + on * L + G.w];
         ph_next = g_h[b][g * (Q + 1) + on];
-        group_add_rn<L>(G, am, ae, as, act ? pm : 0u, act ? (ph >> 1) : kZeroE,
-                        act ? ((uint32_t)ph & 1u) : 0u, st);
+        group_add_rn<L>(G, am, ae, as, pm, ph >> 1, (uint32_t)ph & 1u, st);
       }
     }
     __syncthreads();
   }
-  if (wv == 0 && g < nr) {
-    const int64_t row = A.rows[r0 + g];
+  if (wv == 0 && gi < nr) {
+    const int64_t row = A.rows[r0 + gi];
     A.y_limb[(int64_t)G.w * A.y_ld + row] = am;
     if (G.w == 0) A.y_hdr[row] = make_hdr(ae, as);
   }
