@@ -73,6 +73,7 @@ int limbs_of(int prec) {
     case 128: return 4;
     case 256: return 8;
     case 512: return 16;
+    case 1024: return 32;
     default: return 0;
   }
 }
@@ -102,7 +103,7 @@ bool vec_overlap(const mp_vec* a, const mp_vec* b, int L) {
 
 int check_csr(const mp_csr* A, int check_device_data) {
   if (!A) return fail(MPS_EINVAL, "A: null descriptor");
-  if (!limbs_of(A->prec)) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512}", A->prec);
+  if (!limbs_of(A->prec)) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512, 1024}", A->prec);
   if (A->row_dim < 0 || A->col_dim < 0 || A->nnz < 0)
     return fail(MPS_EINVAL, "A: negative dimension");
   if (A->nnz > INT32_MAX || A->row_dim >= INT32_MAX || A->col_dim >= INT32_MAX)
@@ -200,7 +201,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.long_blocks = 0;
   a.dense_cols = dense_cols;
   if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
-      !batch->pair_of_tile && !done) {
+      !batch->pair_of_tile && !done && L <= 16) {  // lane groups hold at most 16 limbs
     const int rg = 64 / L;  // rows per lane-group block
     a.n_long = std::min<int64_t>(var->n_long, n_rows);
     a.long_blocks = (a.n_long + rg - 1) / rg;
@@ -238,6 +239,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
       case 4: MPS_LAUNCH(true, false, mp::x_stage_kernel<4>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
       case 8: MPS_LAUNCH(true, false, mp::x_stage_kernel<8>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
       case 16: MPS_LAUNCH(true, false, mp::x_stage_kernel<16>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
+      case 32: MPS_LAUNCH(true, false, mp::x_stage_kernel<32>, dim3(g), dim3(256), 0, s, x.limb, x.hdr, x.ld, x_len, x_rec); break;
       default: return fail(MPS_EINVAL, "bad limb count");
     }
   }
@@ -248,6 +250,7 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
       case 4: launch_spmv<4, false>(a, mode, rpw, s); break;
       case 8: launch_spmv<8, false>(a, mode, rpw, s); break;
       case 16: launch_spmv<16, false>(a, mode, rpw, s); break;
+      case 32: launch_spmv<32, false>(a, mode, rpw, s); break;
       default: return fail(MPS_EINVAL, "bad limb count");
     }
   }
@@ -300,9 +303,9 @@ static uint32_t* scratch_status(int dev) {
   return g_scratch_ptr[dev];
 }
 
-// Elements of x the scratch array can stage at L limbs (records of 8, 16 or 32 words).
+// Elements of x the scratch array can stage at L limbs (records of 8, 16, 32 or 64 words).
 static int64_t scratch_max_x(int L) {
-  const int64_t rec_bytes = 4 * (L >= 16 ? 32 : (L >= 8 ? 16 : 8));
+  const int64_t rec_bytes = 4 * mp::x_rec_words_of(L);
   return (int64_t)(kScratchRecBytes / rec_bytes);
 }
 
@@ -342,7 +345,7 @@ int mp_gemv(const mp_dense* A, const mp_vec* x, mp_vec* y, int mode, void* strea
   clear_error();
   if (!A) return fail(MPS_EINVAL, "A: null descriptor");
   const int L = limbs_of(A->prec);
-  if (!L) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512}", A->prec);
+  if (!L) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512, 1024}", A->prec);
   if (A->rows < 0 || A->cols < 0) return fail(MPS_EINVAL, "A: negative dimension");
   if (A->cols > 0 && A->rows > (int64_t)INT32_MAX / A->cols)
     return fail(MPS_EINVAL, "A: rows * cols must fit 32-bit entry indices");

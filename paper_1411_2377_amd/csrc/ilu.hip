@@ -259,7 +259,8 @@ int tri_solve(const mp_ilu* K, const TriSys& T, uint32_t* aug_limb, int32_t* aug
     switch (L) {
       case 4: hipLaunchKernelGGL(ilu_div_kernel<4>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
       case 8: hipLaunchKernelGGL(ilu_div_kernel<8>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
-      default: hipLaunchKernelGGL(ilu_div_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
+      case 16: hipLaunchKernelGGL(ilu_div_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
+      default: hipLaunchKernelGGL(ilu_div_kernel<32>, dim3(g), dim3(256), 0, s, rows, cnt, K->diag, K->lu_limb, K->lu_hdr, K->nnz, y.limb, y.hdr, y.ld, ctl, status); break;
     }
   }
   return MPS_OK;
@@ -479,14 +480,16 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
     switch (L) {
       case 4: hipLaunchKernelGGL(ilu_factor_kernel<4>, dim3(g), dim3(256), 0, s, rows, cnt, K->row_ptr, K->col_idx, K->diag, K->lu_limb, K->lu_hdr, nnz, K->pivot_flag, ctx->status); break;
       case 8: hipLaunchKernelGGL(ilu_factor_kernel<8>, dim3(g), dim3(256), 0, s, rows, cnt, K->row_ptr, K->col_idx, K->diag, K->lu_limb, K->lu_hdr, nnz, K->pivot_flag, ctx->status); break;
-      default: hipLaunchKernelGGL(ilu_factor_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->row_ptr, K->col_idx, K->diag, K->lu_limb, K->lu_hdr, nnz, K->pivot_flag, ctx->status); break;
+      case 16: hipLaunchKernelGGL(ilu_factor_kernel<16>, dim3(g), dim3(256), 0, s, rows, cnt, K->row_ptr, K->col_idx, K->diag, K->lu_limb, K->lu_hdr, nnz, K->pivot_flag, ctx->status); break;
+      default: hipLaunchKernelGGL(ilu_factor_kernel<32>, dim3(g), dim3(256), 0, s, rows, cnt, K->row_ptr, K->col_idx, K->diag, K->lu_limb, K->lu_hdr, nnz, K->pivot_flag, ctx->status); break;
     }
   }
   if (n) {
     switch (L) {
       case 4: hipLaunchKernelGGL(ilu_pack_kernel<4>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
       case 8: hipLaunchKernelGGL(ilu_pack_kernel<8>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
-      default: hipLaunchKernelGGL(ilu_pack_kernel<16>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
+      case 16: hipLaunchKernelGGL(ilu_pack_kernel<16>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
+      default: hipLaunchKernelGGL(ilu_pack_kernel<32>, dim3(blocks_of(n)), dim3(256), 0, s, n, K->row_ptr, K->diag, K->lu_limb, K->lu_hdr, nnz, K->rp_lo, K->rp_up, K->v_lo_limb, K->v_lo_hdr, K->nnz_lo, K->v_up_limb, K->v_up_hdr, K->nnz_up); break;
     }
   }
   if (n) {
@@ -500,9 +503,13 @@ int mp_ilu0_create(const mp_csr* A, void* stream, mp_ilu** out) {
         hipLaunchKernelGGL(ilu_pack_map_kernel<8>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
         hipLaunchKernelGGL(ilu_pack_map_kernel<8>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
         break;
-      default:
+      case 16:
         hipLaunchKernelGGL(ilu_pack_map_kernel<16>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
         hipLaunchKernelGGL(ilu_pack_map_kernel<16>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
+        break;
+      default:
+        hipLaunchKernelGGL(ilu_pack_map_kernel<32>, dim3(blocks_of(mu)), dim3(256), 0, s, mu, src_tu, K->lu_limb, K->lu_hdr, nnz, K->v_tu_limb, K->v_tu_hdr, mu);
+        hipLaunchKernelGGL(ilu_pack_map_kernel<32>, dim3(blocks_of(ml)), dim3(256), 0, s, ml, src_tl, K->lu_limb, K->lu_hdr, nnz, K->v_tl_limb, K->v_tl_hdr, ml);
         break;
     }
   }

@@ -28,6 +28,11 @@ constexpr uint32_t kStRange = 1u;    // a result exponent left [kEmin, kEmax]
 constexpr uint32_t kStWindow = 2u;   // an exact accumulation needed a wider window than allowed
 constexpr uint32_t kStDivZero = 4u;  // a scalar division by zero was requested
 
+// Words per staged x record (the sparse product's copy of x, one record per element): the L
+// limbs and the header, padded to a power of two so that a record sits in one cache line and
+// loads as whole 16-byte pieces.  Host code sizes the staging buffers with it.
+constexpr int x_rec_words_of(int L) { return L >= 32 ? 64 : (L >= 16 ? 32 : (L >= 8 ? 16 : 8)); }
+
 template <int L>
 struct Num {
   uint32_t m[L];

@@ -144,7 +144,7 @@ SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
 
 int plan_x_rec(mp_plan* P) {
   if (P->x_rec) return MPS_OK;
-  const int S = P->L >= 16 ? 32 : (P->L >= 8 ? 16 : 8);
+  const int S = mp::x_rec_words_of(P->L);
   const int64_t n = std::max<int64_t>(1, std::max(P->n_rows, P->n_cols));
   hipError_t e = hipMalloc((void**)&P->x_rec, (size_t)n * S * 4);
   if (e != hipSuccess) {
@@ -161,6 +161,7 @@ int plan_gather(mp_plan* P, const mp_csr* A, hipStream_t s) {
     case 4: hipLaunchKernelGGL(gather_values_kernel<4>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
     case 8: hipLaunchKernelGGL(gather_values_kernel<8>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
     case 16: hipLaunchKernelGGL(gather_values_kernel<16>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
+    case 32: hipLaunchKernelGGL(gather_values_kernel<32>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "gather launch");
@@ -265,6 +266,7 @@ int grad_vals_launch(const mp_csr* A, const mp_plan* P, const mp_vec* g, const m
     case 4: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<4>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
     case 8: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<8>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
     case 16: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<16>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
+    case 32: MPS_LAUNCH_MAIN(true, true, grad_vals_kernel<32>, dim3(grid), dim3(256), 0, s, A->nnz, P->row_of, A->col_idx, g->limb, g->hdr, g->ld, x->limb, x->hdr, x->ld, out->limb, out->hdr, out->ld, neg, status); break;
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MPS_OK : hip_fail(e, "grad_vals launch");
@@ -325,7 +327,8 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
   switch (L) {
     case 4: hipLaunchKernelGGL(tune_fill_kernel<4>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
     case 8: hipLaunchKernelGGL(tune_fill_kernel<8>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
-    default: hipLaunchKernelGGL(tune_fill_kernel<16>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+    case 16: hipLaunchKernelGGL(tune_fill_kernel<16>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+    default: hipLaunchKernelGGL(tune_fill_kernel<32>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
   }
   mp_vec tv{P->t_limb, P->t_hdr, P->nnz, P->nnz};
   for (int op = 0; op < 2; ++op) {
@@ -342,7 +345,7 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
       for (int gi = 0; gi < 3; ++gi)
       for (int flags = 0; flags < 4; ++flags) {
         const int gmin = gi == 0 ? 0 : (gi == 1 ? 128 : 512);
-        if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin)) continue;
+        if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin || P->L > 16)) continue;
         for (int rpw : {16, 32, 64}) {
           SpmvVariant var;
           var.rpw = rpw;

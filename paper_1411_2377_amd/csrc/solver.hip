@@ -433,7 +433,7 @@ int solve_setup(Work& W, const Op& Aop, const mp_vec* b, mp_vec* x, const mp_sol
   const int L = W.L;
   hipLaunchKernelGGL(mp::ctl_init_kernel, dim3((W.npairs + 255) / 256), dim3(256), 0, W.ws, W.ctl,
                      W.npairs, (int32_t)o->maxit, (int32_t)(o->res_hist ? o->res_hist->len : 0));
-  uint32_t m[16];
+  uint32_t m[32];
   int32_t h;
   if (!decimal_to_mp(o->rtol_m, o->rtol_e10, L, m, &h)) return fail(MPS_EINVAL, "rtol out of range");
   int r = set_scalar(L, mp::slot_ref(W.S, mp::S_CREL), m, h, W.ws, W.npairs, mp::kNumScalars);
@@ -1108,6 +1108,7 @@ int batch_copy(int L, bool to_batch, const mp::PairSeg* seg, const int32_t* pair
     case 4: hipLaunchKernelGGL(mp::batch_copy_kernel<4>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
     case 8: hipLaunchKernelGGL(mp::batch_copy_kernel<8>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
     case 16: hipLaunchKernelGGL(mp::batch_copy_kernel<16>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
+    case 32: hipLaunchKernelGGL(mp::batch_copy_kernel<32>, dim3(g), dim3(256), 0, s, seg, pair_of_tile, v, n, gather); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -1267,10 +1268,10 @@ int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec*
 int mp_const_decimal(int64_t m, int64_t e10, int prec, mp_vec* out, void* stream) {
   clear_error();
   const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
   int r = check_vec(out, 1, "out");
   if (r) return r;
-  uint32_t m_[16];
+  uint32_t m_[32];
   int32_t h;
   if (!decimal_to_mp(m, e10, L, m_, &h)) return fail(MPS_EINVAL, "constant out of range");
   return set_scalar(L, ref(*out), m_, h, (hipStream_t)stream);

@@ -9,6 +9,7 @@ void launch_spmv_fused(int L, const mp::SpmvArgs& a, int mode, int rpw, hipStrea
     case 4: launch_spmv<4, true>(a, mode, rpw, s); break;
     case 8: launch_spmv<8, true>(a, mode, rpw, s); break;
     case 16: launch_spmv<16, true>(a, mode, rpw, s); break;
+    case 32: launch_spmv<32, true>(a, mode, rpw, s); break;
     default: break;
   }
 }

@@ -29,10 +29,9 @@ constexpr int kRowsPerBlock = 64;
 template <int L>
 constexpr int chunk_entries() { return 2048 / L; }
 
-// Words per staged x record: the L limbs and the header, padded to a power of two so that a
-// record sits in one cache line and loads as whole 16-byte pieces.
+// Words per staged x record (x_rec_words_of in mp_core.hpp).
 template <int L>
-constexpr int x_rec_words() { return L >= 16 ? 32 : (L >= 8 ? 16 : 8); }
+constexpr int x_rec_words() { return x_rec_words_of(L); }
 
 // x_rec[i] = (limbs of x_i, header of x_i)
 template <int L>
@@ -452,7 +451,7 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
 
 template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
-  if constexpr (!FUSE) {
+  if constexpr (!FUSE && L <= 16) {
     if ((int64_t)blockIdx.x < A.long_blocks) {
       uint32_t st = 0;
       spmv_seq_group_rows<L>(A, blockIdx.x, st);
@@ -728,7 +727,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
       emin = wave_min32(llo);
       emax = wave_max32(lhi);
       __syncthreads();
-      if (emax >= emin && ring_span<L>(emin, emax) <= R) {
+      if (emax >= emin && ring_span<L>(emin, emax) <= min(R, 63)) {  // a digit per lane
         ring_ok = true;
         int64_t dg = 0;
         if (lane < ring_span<L>(emin, emax)) {

@@ -77,6 +77,7 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
     case 4: MPS_LAUNCH(true, true, mp::dot_kernel<4>, grid, dim3(mp::kDotThreads), 0, s, a); break;
     case 8: MPS_LAUNCH(true, true, mp::dot_kernel<8>, grid, dim3(mp::kDotThreads), 0, s, a); break;
     case 16: MPS_LAUNCH(true, true, mp::dot_kernel<16>, grid, dim3(mp::kDotThreads), 0, s, a); break;
+    case 32: MPS_LAUNCH(true, true, mp::dot_kernel<32>, grid, dim3(mp::kDotThreads), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -88,6 +89,7 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
     case 4: MPS_LAUNCH(true, true, mp::KERNEL<4>, dim3(g), dim3(256), 0, s, ARG); break;          \
     case 8: MPS_LAUNCH(true, true, mp::KERNEL<8>, dim3(g), dim3(256), 0, s, ARG); break;          \
     case 16: MPS_LAUNCH(true, true, mp::KERNEL<16>, dim3(g), dim3(256), 0, s, ARG); break;        \
+    case 32: MPS_LAUNCH(true, true, mp::KERNEL<32>, dim3(g), dim3(256), 0, s, ARG); break;        \
     default: return fail(MPS_EINVAL, "bad limb count");                                       \
   }
 
@@ -98,6 +100,7 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
       case 4: MPS_LAUNCH(true, true, (mp::KERNEL<4, true>), dim3(g), dim3(256), 0, s, ARG); break;   \
       case 8: MPS_LAUNCH(true, true, (mp::KERNEL<8, true>), dim3(g), dim3(256), 0, s, ARG); break;   \
       case 16: MPS_LAUNCH(true, true, (mp::KERNEL<16, true>), dim3(g), dim3(256), 0, s, ARG); break; \
+      case 32: MPS_LAUNCH(true, true, (mp::KERNEL<32, true>), dim3(g), dim3(256), 0, s, ARG); break; \
       default: return fail(MPS_EINVAL, "bad limb count");                                     \
     }                                                                                         \
   } else {                                                                                    \
@@ -105,6 +108,7 @@ int launch_dot(int L, const mp::DotArgs& a, hipStream_t s) {
       case 4: MPS_LAUNCH(true, true, (mp::KERNEL<4, false>), dim3(g), dim3(256), 0, s, ARG); break;  \
       case 8: MPS_LAUNCH(true, true, (mp::KERNEL<8, false>), dim3(g), dim3(256), 0, s, ARG); break;  \
       case 16: MPS_LAUNCH(true, true, (mp::KERNEL<16, false>), dim3(g), dim3(256), 0, s, ARG); break; \
+      case 32: MPS_LAUNCH(true, true, (mp::KERNEL<32, false>), dim3(g), dim3(256), 0, s, ARG); break; \
       default: return fail(MPS_EINVAL, "bad limb count");                                     \
     }                                                                                         \
   }
@@ -147,6 +151,7 @@ int launch_epilogue(int L, const mp::EpiArgs& a, int npairs, hipStream_t s) {
     case 4: MPS_LAUNCH(true, true, mp::epilogue_kernel<4>, g, dim3(64), 0, s, a); break;
     case 8: MPS_LAUNCH(true, true, mp::epilogue_kernel<8>, g, dim3(64), 0, s, a); break;
     case 16: MPS_LAUNCH(true, true, mp::epilogue_kernel<16>, g, dim3(64), 0, s, a); break;
+    case 32: MPS_LAUNCH(true, true, mp::epilogue_kernel<32>, g, dim3(64), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -159,6 +164,7 @@ int launch_prologue(int L, const mp::ProArgs& a, int npairs, hipStream_t s) {
     case 4: MPS_LAUNCH(true, true, mp::prologue_kernel<4>, g, dim3(64), 0, s, a); break;
     case 8: MPS_LAUNCH(true, true, mp::prologue_kernel<8>, g, dim3(64), 0, s, a); break;
     case 16: MPS_LAUNCH(true, true, mp::prologue_kernel<16>, g, dim3(64), 0, s, a); break;
+    case 32: MPS_LAUNCH(true, true, mp::prologue_kernel<32>, g, dim3(64), 0, s, a); break;
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -190,6 +196,13 @@ int set_scalar(int L, const mp::VecRef& out, const uint32_t* m, int32_t hdr, hip
       hipLaunchKernelGGL(mp::set_scalar_kernel<16>, dim3(g), dim3(256), 0, s, a);
       break;
     }
+    case 32: {
+      mp::ConstArgs<32> a;
+      a.out = out; a.hdr = hdr; a.count = count; a.step = step;
+      for (int k = 0; k < 32; ++k) a.m[k] = m[k];
+      hipLaunchKernelGGL(mp::set_scalar_kernel<32>, dim3(g), dim3(256), 0, s, a);
+      break;
+    }
     default: return fail(MPS_EINVAL, "bad limb count");
   }
   hipError_t e = hipGetLastError();
@@ -207,7 +220,7 @@ extern "C" {
 int mp_axpy(const mp_vec* alpha, const mp_vec* x, mp_vec* y, int prec, void* stream) {
   clear_error();
   const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
   int r;
   if ((r = check_scalar(alpha, "alpha"))) return r;
   if (!x || !y) return fail(MPS_EINVAL, "null vector");
@@ -229,7 +242,7 @@ int mp_axpy(const mp_vec* alpha, const mp_vec* x, mp_vec* y, int prec, void* str
 int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream) {
   clear_error();
   const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512}", prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
   int r;
   if (!x || !y) return fail(MPS_EINVAL, "null vector");
   if ((r = check_vec(y, x->len, "y"))) return r;

@@ -58,7 +58,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("case", ["convdiff2d_24", "random_300"])
 def test_factors_and_application(case, p):
     M = lib()

@@ -101,7 +101,7 @@ def test_convdiff_small_fixed_iterations(solver, mode):
 
 
 @pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
-@pytest.mark.parametrize("p", [128, 512])
+@pytest.mark.parametrize("p", [128, 512, 1024])
 def test_convergence_to_tolerance(solver, p):
     A_h, _ = synth.config2(p=p, m=6)
     b_h, b_o = rhs_ones(A_h)

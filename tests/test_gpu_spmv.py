@@ -88,7 +88,7 @@ def test_random_csr_workload_full(mode):
     assert_bitwise(yl, yh, want, A.vals.p, what="config1")
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_edge_cases(p, mode):
     A, x = edge_problem(p, seed=p + mode)
@@ -176,7 +176,7 @@ def test_empty_shapes():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_every_kernel_variant_same_bits(p):
     """Each rows-per-block variant of y = A x and y = A^T x, in both modes, matches the oracle
     bit for bit (edge-case matrix), and the tuner's pick changes nothing."""
@@ -267,7 +267,7 @@ def corner_rows(p, seed):
     return A, synth.MPHost(xl, xh, p)
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_lane_group_rows_corner_sums(p):
     """Every row summed by lane groups (SEQ, sorted rows, rows of >= 1 entry) and by the
     one-lane chains: both equal the oracle bit for bit on the corner-case rows."""

@@ -24,7 +24,7 @@ def host(arr):
     return synth.MPHost(limbs, hdr, arr.p)
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_transpose_product_random(p, mode):
     M = lib()
@@ -129,7 +129,7 @@ def test_grad_vals_and_symmetric_transpose(p):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_axpy_dot_const(p):
     M = lib()
     rng = np.random.default_rng(p)
@@ -170,7 +170,7 @@ def test_dot_wide_span_and_long():
     assert M.mp_status() == 0
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 def test_dot_rounding_edge_cases(p):
     """Inner products whose exact sums sit on the rounding boundaries: ties to even, the
     all-ones mantissa that rounds up to the next power of two, exact cancellation, negative
