@@ -10,7 +10,8 @@
  *   - the vector operations and inner products of BiCG and GPBiCG (Fig. 5) and the drivers with
  *     the stopping test (*) of Sec. 4.1.
  *
- * NUMBER FORMAT.  p = 32 L bits, L in {4, 8, 16} (p = 128, 256, 512).
+ * NUMBER FORMAT.  p = 32 L bits, L in {4, 8, 16, 32} (p = 128, 256, 512, 1024; the paper runs
+ * its solvers at 512 to 8192 bits, Sec. 4.1, Tables 1 and 2).
  *   value = (-1)^s * M * 2^(e - p),  2^(p-1) <= M < 2^p  (mantissa in [1/2, 1), as MPFR)
  *   exponent range [1 - 2^30, 2^30 - 1] (MPFR's default); no NaN/Inf; signed zeros.
  * An array of N numbers (struct mp_vec) is stored as structure of arrays in device memory:
@@ -42,12 +43,13 @@
  *
  * EXACT WINDOW LIMITS.  An EXACT row sum is supported when its non-zero products' exponents
  * e_a + e_x span at most 32 * (16 R - 2L - 2) bits, R = 2L + 10 digits (L = p/32): about 8,900,
- * 12,700 and 20,400 bits at p = 128, 256, 512.  An exact inner product (mp_dot, the solvers'
+ * 12,700, 20,400 and 35,700 bits at p = 128, 256, 512, 1024.  An exact inner product (mp_dot, the solvers'
  * scalars) is supported when its products' exponents x_e + y_e span at most 32 * (W - 2L - 2)
  * bits, W = min(2048, 257 (2L + 1) / 2) digits for mp_dot and the solvers' vector steps
- * (about 36,700, 65,000 and 64,400 bits at p = 128, 256, 512), W = 65 (2L + 1) / 2 digits for
- * the products a solver forms inside its SpMV launches (about 9,000, 17,100 and 33,200 bits),
- * and W = 256 digits in gpbicg_batched (about 7,900, 7,600 and 7,100 bits).  Wider sums set
+ * (about 36,700, 65,000, 64,400 and 63,400 bits at p = 128, 256, 512, 1024), W = min(2048,
+ * 65 (2L + 1) / 2) digits for the products a solver forms inside its SpMV launches (about 9,000,
+ * 17,100, 33,200 and 63,400 bits), and W = 256 digits in gpbicg_batched (about 7,900, 7,600,
+ * 7,100 and 6,100 bits).  Wider sums set
  * MP_ST_WINDOW and give +0.
  */
 #ifndef MPSPMV_H
@@ -85,7 +87,7 @@ typedef struct {
 
 typedef struct {
   int64_t row_dim, col_dim, nnz;
-  int32_t prec;            /* 128, 256 or 512 */
+  int32_t prec;            /* 128, 256, 512 or 1024 */
   const int32_t *row_ptr;  /* device [row_dim + 1] */
   const int32_t *col_idx;  /* device [nnz] */
   mp_vec val;              /* [nnz] */
@@ -95,7 +97,7 @@ typedef struct {
  * val), zeros stored as elements (the paper's dense format, Sec. 3). */
 typedef struct {
   int64_t rows, cols;
-  int32_t prec;  /* 128, 256 or 512 */
+  int32_t prec;  /* 128, 256, 512 or 1024 */
   mp_vec val;    /* rows * cols elements */
 } mp_dense;
 
@@ -182,7 +184,8 @@ int mp_gemv(const mp_dense *A, const mp_vec *x, mp_vec *y, int mode, void *strea
  * (one record per element, as the MP_VARIANT_STAGE_X variant) into a file-scope device array of
  * 32 MiB + 256 bytes that every GPU the library runs on holds until the process ends, and rows
  * per block follow A's shape.  x.len (= col_dim) may be at most 1,048,576 at p = 128, 524,288 at
- * p = 256 and 262,144 at p = 512; larger x returns MPS_ENOTSUP before anything is enqueued.
+ * p = 256, 262,144 at p = 512 and 131,072 at p = 1024; larger x returns MPS_ENOTSUP before
+ * anything is enqueued.
  * Device conditions go to a status word inside the same array, which mp_status reads and clears
  * together with the device's other status word.  All calls on one GPU share the array: calls
  * that overlap in time on one GPU (two streams, two threads) race and must be ordered by the

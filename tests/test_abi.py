@@ -109,7 +109,7 @@ def test_variant_setter_validation():
 def test_noalloc_size_limit_rejected_on_the_host():
     """x beyond what the static scratch array stages is refused before anything is enqueued."""
     from paper_1411_2377_amd import _lib
-    for prec, max_x in ((128, 1 << 20), (256, 1 << 19), (512, 1 << 18)):
+    for prec, max_x in ((128, 1 << 20), (256, 1 << 19), (512, 1 << 18), (1024, 1 << 17)):
         a = _lib.MpCsr()
         a.row_dim, a.col_dim, a.nnz, a.prec = 4, max_x + 1, 0, prec
         a.row_ptr = 1234

@@ -36,7 +36,7 @@ def same_as_plain(M, A_h, x_h, mode):
         "allocation-free product differs from mpspmv_csr (n=%d, p=%d, mode %d)" % (A.n_rows, A.p, mode)
 
 
-@pytest.mark.parametrize("p", [128, 256, 512])
+@pytest.mark.parametrize("p", [128, 256, 512, 1024])
 @pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
 def test_two_calls_second_smaller(p, mode):
     M = lib()
