@@ -42,8 +42,12 @@
  * mp_status().  The library never aborts and never prints.
  *
  * EXACT WINDOW LIMITS.  An EXACT row sum is supported when its non-zero products' exponents
- * e_a + e_x span at most 32 * (16 R - 2L - 2) bits, R = 2L + 10 digits (L = p/32): about 8,900,
- * 12,700, 20,400 and 35,700 bits at p = 128, 256, 512, 1024.  An exact inner product (mp_dot, the solvers'
+ * e_a + e_x span at most 32 * (65536 - 2L - 2) bits (about 2.1 million; L = p/32): rows within
+ * 32 * (16 R - 2L - 2) bits, R = 2L + 10 (about 8,900, 12,700, 20,400 and 35,700 bits at p =
+ * 128, 256, 512, 1024), are summed in LDS, wider ones in one of 16 global-memory windows of
+ * 65536 digits per device (8 MiB, allocated with the device's other state on the first call),
+ * which a block takes under a lock and releases when the row is rounded.
+ * mpspmv_csr_noalloc keeps the LDS limit.  An exact inner product (mp_dot, the solvers'
  * scalars) is supported when its products' exponents x_e + y_e span at most 32 * (W - 2L - 2)
  * bits, W = min(2048, 257 (2L + 1) / 2) digits for mp_dot and the solvers' vector steps
  * (about 36,700, 65,000, 64,400 and 63,400 bits at p = 128, 256, 512, 1024), W = min(2048,

@@ -59,6 +59,11 @@ int get_ctx(DeviceCtx** out) {
     int r = dot_work_alloc(1, kDotRingLog2, kDotReps, kDotGroups, &c->dot_anchor, &c->dot_win,
                            &c->dot_ticket, nullptr);
     if (r) return r;
+    e = hipMalloc((void**)&c->wide_win, sizeof(int64_t) * (size_t)mp::kWideSlots * mp::kWideDigits);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->wide_lock, sizeof(int32_t) * mp::kWideSlots);
+    if (e != hipSuccess) return fail(MPS_ENOMEM, "hipMalloc(wide windows): %s", hipGetErrorString(e));
+    e = hipMemset(c->wide_lock, 0, sizeof(int32_t) * mp::kWideSlots);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(wide locks)");
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     g_ctx[dev] = c;
@@ -200,6 +205,15 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.n_long = 0;
   a.long_blocks = 0;
   a.dense_cols = dense_cols;
+  a.wide_win = nullptr;
+  a.wide_lock = nullptr;
+  if (mode == MP_EXACT && !var->no_wide) {
+    DeviceCtx* ctx;
+    const int r = get_ctx(&ctx);
+    if (r) return r;
+    a.wide_win = ctx->wide_win;
+    a.wide_lock = ctx->wide_lock;
+  }
   if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
       !batch->pair_of_tile && !done && L <= 16) {  // lane groups hold at most 16 limbs
     const int rg = 64 / L;  // rows per lane-group block
@@ -394,6 +408,7 @@ int mpspmv_csr_noalloc(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, vo
   SpmvVariant var;
   var.x_rec = sp + kScratchRecOffset / 4;
   var.x_len = A->col_dim;
+  var.no_wide = true;  // the global windows are allocated memory
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, sp, nullptr,
                      (hipStream_t)stream, nullptr, nullptr, &var);
 }

@@ -65,6 +65,9 @@ struct DeviceCtx {
   int32_t* dot_anchor = nullptr;
   int64_t* dot_win = nullptr;
   uint32_t* dot_ticket = nullptr;
+  // global windows (and their locks) of EXACT rows wider than a block's LDS window
+  int64_t* wide_win = nullptr;
+  int32_t* wide_lock = nullptr;
 };
 
 struct SpmvFuse;  // spmv_internal.hpp
@@ -109,6 +112,7 @@ struct SpmvVariant {
   const int32_t* rows = nullptr;
   bool pipe = false;  // SEQ: the four-wavefront pipelined kernel also without a row order
   int64_t n_long = 0;  // SEQ with a row order: its first n_long rows are summed by lane groups
+  bool no_wide = false;  // EXACT: no global windows (rows wider than the LDS window raise kStWindow)
 };
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
                 const mp_vec& val, const mp_vec& x, const mp_vec& y, int mode, uint32_t* status,

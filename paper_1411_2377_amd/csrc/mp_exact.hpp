@@ -366,6 +366,109 @@ MPD Num<L> reg_round(const RegWindow<WMAX>& R, int64_t base, uint32_t& st) {
   return out;
 }
 
+// RN_p of sum_w win[w] 2^(32 w + base) for W carry-save digits in global memory (any W, one
+// whole wavefront; every lane gets the result; the digits are overwritten; every access is
+// device-coherent, like the adds that filled the window).  Three passes over
+// the window, 64 digits at a time:
+//  1. carries: each chunk's digits pass their high words one lane up until every digit is a
+//     32-bit limb; lane 63's high word goes on to the next chunk, and the last chunk's is the
+//     sign (the window's headroom digit keeps the sum inside W limbs of two's complement);
+//  2. a negative sum is complemented into its magnitude (~limbs plus one, the one passing the
+//     chunks' runs of all-ones limbs by lane masks);
+//  3. the leading limb is found from the top, then the mantissa limbs, the round bit and the
+//     sticky bits below it (every lower chunk, by ballots) are read, and rounding carries.
+template <int L>
+MPD Num<L> wave_window_round_global(int64_t* win, int W, int64_t base, uint32_t& st) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;  // lanes under this one
+  int64_t carry = 0;  // into the chunk's lane 0 (wave-uniform)
+  for (int c0 = 0; c0 < W; c0 += 64) {
+    const int w = c0 + lane;
+    int64_t d = (w < W) ? ld_dev(win + w) : 0;
+    if (lane == 0) d += carry;
+    uint32_t lo = (uint32_t)d;
+    int64_t hi = d >> 32;
+    int64_t out = 0;  // lane 63: what leaves the chunk
+    while (__ballot(hi != 0)) {
+      const int64_t from = __shfl_up(hi, 1);
+      if (lane == 63) out += hi;
+      const int64_t t = (int64_t)lo + (lane ? from : 0);
+      lo = (uint32_t)t;
+      hi = t >> 32;
+    }
+    if (w < W) st_dev(win + w, (int64_t)lo);
+    carry = __shfl(out, 63);
+  }
+  wait_memory();
+  const uint32_t neg = carry < 0 ? 1u : 0u;
+  if (neg) {
+    uint32_t cin = 1;  // the +1 of the two's complement, wave-uniform
+    for (int c0 = 0; c0 < W; c0 += 64) {
+      const int w = c0 + lane;
+      const uint32_t m = (w < W) ? ~(uint32_t)ld_dev(win + w) : 0u;
+      const uint64_t ones = __ballot(w < W && m == ~0u);
+      // lane k gets the carry when every lane under it passes it on
+      const bool gets = cin && ((ones & below) == below);
+      if (w < W) st_dev(win + w, (int64_t)(m + (gets ? 1u : 0u)));
+      cin = (cin && __ballot(w < W) == ones) ? 1u : 0u;
+    }
+  }
+  wait_memory();
+  // the leading non-zero limb
+  int top = -1;
+  for (int c0 = ((W - 1) / 64) * 64; c0 >= 0 && top < 0; c0 -= 64) {
+    const int w = c0 + lane;
+    const uint64_t nz = __ballot(w < W && (uint32_t)ld_dev(win + w) != 0u);
+    if (nz) top = c0 + 63 - (int)__clzll((long long)nz);
+  }
+  Num<L> out;
+  if (top < 0) {
+    set_zero(out, 0);
+    return out;
+  }
+  const uint32_t mtop = (uint32_t)ld_dev(win + top);
+  const int b0 = 32 * top + 31 - (int)__clz((int)mtop) - 32 * L + 1;  // mantissa LSB bit index
+  const int q0 = b0 >> 5;
+  const uint32_t r0 = (uint32_t)(b0 & 31);
+  auto limb_at = [&](int i) -> uint32_t { return (i >= 0 && i < W) ? (uint32_t)ld_dev(win + i) : 0u; };
+  uint32_t limb = 0;
+  if (lane < L) limb = r0 ? fshr(limb_at(q0 + lane + 1), limb_at(q0 + lane), r0) : limb_at(q0 + lane);
+  uint32_t rnd = 0, sticky = 0;
+  const int rb = b0 - 1;
+  if (rb >= 0) {
+    const int ri = rb >> 5;
+    const uint32_t rs = (uint32_t)(rb & 31);
+    const uint32_t mr = limb_at(ri);
+    rnd = (mr >> rs) & 1u;
+    sticky = (rs ? (mr & ((1u << rs) - 1u)) : 0u) != 0u ? 1u : 0u;
+    for (int c0 = 0; c0 < ri && !sticky; c0 += 64) {
+      const int w = c0 + lane;
+      if (__ballot(w < ri && (uint32_t)ld_dev(win + w) != 0u)) sticky = 1u;
+    }
+  }
+  int64_t e = (int64_t)b0 + base + 32 * L;
+  const uint32_t m0 = __shfl(limb, 0);
+  if (rnd & (sticky | (m0 & 1u))) {
+    constexpr uint64_t lmask = (L >= 64) ? ~0ull : ((1ull << L) - 1ull);
+    const uint64_t ones = __ballot(limb == 0xFFFFFFFFu) & lmask;
+    if (lane < L && (ones & below) == (below & lmask)) limb += 1u;
+    if (ones == lmask) {  // all ones: the mantissa becomes 2^(p-1) one exponent up
+      limb = (lane == L - 1) ? 0x80000000u : 0u;
+      e += 1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) out.m[k] = __shfl(limb, k);
+  out.s = neg;
+  if (e > kEmax || e < kEmin) {
+    st |= kStRange;
+    set_zero(out, neg);
+    return out;
+  }
+  out.e = (int32_t)e;
+  return out;
+}
+
 template <int L, int WMAX>
 MPD Num<L> lane_window_round(int64_t* win, int ws, int W, int64_t base, uint32_t& st) {
   RegWindow<WMAX> R;

@@ -97,7 +97,35 @@ struct SpmvArgs {
   const int32_t* tiles_of_pair;
   const int32_t* first_tile;
   int32_t* ndone;
+  // EXACT rows wider than the block's LDS window: kWideSlots windows of kWideDigits digits in
+  // global memory, each taken under a lock (nullptr: such rows raise kStWindow)
+  int64_t* wide_win;
+  int32_t* wide_lock;
 };
+
+constexpr int kWideSlots = 16;
+constexpr int kWideDigits = 1 << 16;
+constexpr int kWideTries = 1 << 22;
+
+// A free global window slot, taken with a compare-and-swap from `start` on (a holder releases
+// its slot as soon as its row is rounded, without waiting on anything); -1 after kWideTries
+// attempts.
+MPD int wide_acquire(int32_t* lock, int start) {
+  for (int t = 0; t < kWideTries; ++t) {
+    const int s = (start + t) % kWideSlots;
+    if (atomicCAS(lock + s, 0, 1) == 0) {
+      wait_memory();
+      return s;
+    }
+    if (s == kWideSlots - 1) __builtin_amdgcn_s_sleep(8);
+  }
+  return -1;
+}
+
+MPD void wide_release(int32_t* lock, int s) {
+  wait_memory();
+  atomicExch(lock + s, 0);
+}
 
 // Entry range of a row and column of an entry, from the CSR arrays or the dense shape.
 MPD int row_begin(const SpmvArgs& A, int64_t row) {
@@ -760,8 +788,35 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
         }
         __syncthreads();
         if (lane == owner) yr = window_finalize<L>(s_win, 1, W, (int64_t)emin - 64 * L, st);
-      } else if (lane == owner) {
-        st |= kStWindow;
+      } else {
+        // wider still: a window in global memory, every access device-coherent
+        int slot = -1;
+        if (A.wide_win && W <= kWideDigits) {
+          if (lane == 0) slot = wide_acquire(A.wide_lock, (int)(blockIdx.x % kWideSlots));
+          slot = __shfl(slot, 0);
+        }
+        if (slot < 0) {
+          if (lane == owner) st |= kStWindow;
+        } else {
+          int64_t* const gw = A.wide_win + (int64_t)slot * kWideDigits;
+          for (int w = lane; w < W; w += 64) st_dev(gw + w, (int64_t)0);
+          wait_memory();
+          for (int kk = o_rs + lane; kk < o_re; kk += 64) {
+            const int32_t ha = A.a_hdr[kk];
+            const int32_t col = col_of(A, kk);
+            int32_t hx;
+            uint32_t am[L], xm[L], pr[2 * L];
+            load_x<L>(A, x_limb, x_hdr, col, true, hx, xm);
+            if (hdr_is_zero(ha) || hdr_is_zero(hx)) continue;
+#pragma unroll
+            for (int q = 0; q < L; ++q) am[q] = A.a_limb[(int64_t)q * A.a_ld + kk];
+            mul_full<L>(am, xm, pr);
+            window_add_atomic<L>(gw, pr, (uint32_t)(ha ^ hx) & 1u, (uint32_t)((ha >> 1) + (hx >> 1) - emin));
+          }
+          wait_memory();
+          yr = wave_window_round_global<L>(gw, W, (int64_t)emin - 64 * L, st);
+          if (lane == 0) wide_release(A.wide_lock, slot);
+        }
       }
     }
     if (lane == owner) {

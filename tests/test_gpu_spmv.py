@@ -303,3 +303,64 @@ def test_powerlaw_lane_groups_sampled(p):
     want = oracle_spmv_rows(A_h, x_h, rows, 0)
     assert_bitwise(yl[:, rows], yh[rows], want, p, what="power-law rows by lane groups")
     assert M.mp_status() == 0
+
+
+def wide_span_problem(p, seed):
+    """EXACT rows whose products span far more bits than a block's LDS window: 48 rows of 8-60
+    entries with exponents spread over +-60,000 bits (enough rows to contend for the global
+    windows), rows whose largest products cancel exactly leaving terms 100,000 bits below them
+    (positive and negative remainders), a row that cancels to exactly zero, and ordinary rows."""
+    rng = np.random.default_rng(seed)
+    m = 300
+    x = synth.mp_uniform(rng, m, p)
+    x.limbs[:, 1] = x.limbs[:, 0]          # x_0 == x_1: a_0 x_0 + (-a_0) x_1 cancels exactly
+    x.hdr[1] = x.hdr[0]
+    rows = []                              # (columns, exponents, signs); mantissas random
+    for _ in range(48):
+        k = int(rng.integers(8, 61))
+        cols = np.sort(rng.choice(np.arange(2, m), size=k, replace=False))
+        rows.append((cols, rng.integers(-60000, 60001, size=k), rng.integers(0, 2, size=k)))
+    for sign_small in (0, 1):              # big cancelling pair, remainder 100,000 bits down
+        cols = np.array([0, 1] + sorted(rng.choice(np.arange(2, m), size=5, replace=False).tolist()))
+        exps = np.array([50000, 50000] + rng.integers(-50020, -49980, size=5).tolist())
+        signs = np.array([0, 1] + [sign_small] * 5)
+        rows.append((cols, exps, signs))
+    rows.append((np.array([0, 1]), np.array([70000, 70000]), np.array([1, 0])))   # exactly zero
+    for _ in range(8):                     # ordinary rows around them
+        k = int(rng.integers(1, 20))
+        cols = np.sort(rng.choice(np.arange(2, m), size=k, replace=False))
+        rows.append((cols, rng.integers(-20, 21, size=k), rng.integers(0, 2, size=k)))
+    rp = np.zeros(len(rows) + 1, np.int64)
+    rp[1:] = np.cumsum([len(r[0]) for r in rows])
+    nnz = int(rp[-1])
+    vals = synth.mp_uniform(rng, nnz, p)
+    exps = np.concatenate([r[1] for r in rows]).astype(np.int64)
+    signs = np.concatenate([r[2] for r in rows]).astype(np.int64)
+    vals.hdr[:] = ((exps << 1) | signs).astype(np.int32)
+    # the cancelling pairs share one mantissa (and x_0 == x_1), so their products are negatives
+    for i, r in enumerate(rows):
+        if len(r[0]) >= 2 and r[0][0] == 0 and r[0][1] == 1:
+            k0 = int(rp[i])
+            vals.limbs[:, k0 + 1] = vals.limbs[:, k0]
+    cols = np.concatenate([r[0] for r in rows]).astype(np.int32)
+    A = synth.CSRHost(len(rows), m, rp.astype(np.int32), cols, vals)
+    return A, x
+
+
+@pytest.mark.parametrize("p", [128, 256, 1024])
+def test_exact_rows_wider_than_lds_window(p):
+    """Rows spanning up to ~120,000 bits (global-memory windows taken under locks) equal the
+    oracle's exactly rounded sums, with no status raised; default and tuned variants."""
+    M = lib()
+    A_h, x_h = wide_span_problem(p, seed=p)
+    want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), 1)
+    yl, yh = run(A_h, x_h, 1)
+    assert_bitwise(yl, yh, want, p, what="wide EXACT rows p=%d" % p)
+    assert yh[48 + 2] == np.int32(-(1 << 31))          # the cancelling row is +0
+    A = M.CSRMatrix.from_host(A_h)
+    P = M.mp_plan_create(A)
+    for rows in (16, 64):
+        P.set_variant(0, 1, rows, True, False)
+        yl2, yh2 = M.mpspmv_csr(A, M.MPArray.from_host(x_h), mode=1, plan=P).to_numpy()
+        assert np.array_equal(yl2, yl) and np.array_equal(yh2, yh)
+    assert M.mp_status() == 0
