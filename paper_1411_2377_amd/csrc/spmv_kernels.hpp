@@ -613,20 +613,25 @@ MPD int ring_slot(int32_t d) {
 template <int L>
 MPD int ring_span(int32_t lo, int32_t hi) { return (hi >> 5) - (lo >> 5) + 2 * L + 2; }
 
-// Add (-1)^s * P * 2^(e mod 32) at ring digit e >> 5 (slots ws apart) with LDS atomics.
+// Add (-1)^s * P * 2^(e mod 32) at ring digit e >> 5 (slots ws apart) with LDS atomics.  A
+// negative product X = sum_j x_j 2^(32 j) (D = 2L + 1 digits) is added as its digits'
+// complements plus one, less one a digit above it: -X = sum_j (2^32 - 1 - x_j) 2^(32 j) + 1
+// - 2^(32 D).  Every digit's add is then a 32-bit value with no negation, and every lane issues
+// the same adds (no per-digit branch); only negative products add the extra digit.  The row's
+// window counts that digit (its headroom digit above the widest product).
 template <int L, int R>
 MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, int32_t e) {
   uint32_t sp[2 * L + 1];
   shift_product<L>(P, (uint32_t)e & 31u, sp);
+  const uint32_t mask = s ? ~0u : 0u;
   int slot = ring_slot<R>(e >> 5);
 #pragma unroll
   for (int j = 0; j <= 2 * L; ++j) {
-    if (sp[j]) {
-      const uint64_t v = s ? (uint64_t)(-(int64_t)sp[j]) : (uint64_t)sp[j];
-      atomicAdd((unsigned long long*)&win[slot * ws], (unsigned long long)v);
-    }
+    const uint64_t v = (uint64_t)(sp[j] ^ mask) + ((j == 0) ? (uint64_t)(s & 1u) : 0ull);
+    atomicAdd((unsigned long long*)&win[slot * ws], (unsigned long long)v);
     slot = (slot == R - 1) ? 0 : slot + 1;
   }
+  if (s) atomicAdd((unsigned long long*)&win[slot * ws], ~0ull);
 }
 
 template <int L, int RPW, bool FUSE>
