@@ -10,7 +10,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpspmv.so")
-SOURCES = ["api.hip", "spmv_fused.hip", "plan.hip", "vec.hip", "solver.hip", "ilu.hip"]
+SOURCES = ["api.hip", "spmv_fused.hip", "plan.hip", "vec.hip", "solver.hip", "ilu.hip", "wide.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

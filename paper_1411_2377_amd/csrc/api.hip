@@ -11,6 +11,7 @@
 
 #include "../../include/mpspmv.h"
 #include "api_internal.hpp"
+#include "wide_internal.hpp"
 #include "plan_internal.hpp"
 #include "spmv_internal.hpp"
 #include "vec_internal.hpp"
@@ -106,9 +107,11 @@ bool vec_overlap(const mp_vec* a, const mp_vec* b, int L) {
          overlap(a->limb, la, b->hdr, (size_t)b->len * 4) || overlap(a->hdr, (size_t)a->len * 4, b->limb, lb);
 }
 
-int check_csr(const mp_csr* A, int check_device_data) {
+int check_csr(const mp_csr* A, int check_device_data, bool wide_ok) {
   if (!A) return fail(MPS_EINVAL, "A: null descriptor");
-  if (!limbs_of(A->prec)) return fail(MPS_EINVAL, "A: precision %d not in {128, 256, 512, 1024}", A->prec);
+  if (!limbs_of(A->prec) && !(wide_ok && wide_limbs_of(A->prec)))
+    return fail(MPS_EINVAL, "A: precision %d not supported here (128, 256, 512, 1024%s)", A->prec,
+                wide_ok ? ", 2048, 4096, 8192" : "");
   if (A->row_dim < 0 || A->col_dim < 0 || A->nnz < 0)
     return fail(MPS_EINVAL, "A: negative dimension");
   if (A->nnz > INT32_MAX || A->row_dim >= INT32_MAX || A->col_dim >= INT32_MAX)
@@ -333,23 +336,26 @@ const char* mp_last_error(void) { return g_err; }
 
 int mp_validate_csr(const mp_csr* A, int check_device_data) {
   clear_error();
-  return check_csr(A, check_device_data);
+  return check_csr(A, check_device_data, true);
 }
 
 int mpspmv_csr(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_plan* plan,
                void* stream) {
   clear_error();
-  int r = check_csr(A, 0);
+  int r = check_csr(A, 0, true);
   if (r) return r;
   if (plan && (r = check_plan(plan, A))) return r;
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if ((r = check_vec(x, A->col_dim, "x"))) return r;
   if ((r = check_vec(y, A->row_dim, "y"))) return r;
-  const int L = limbs_of(A->prec);
+  const int WL = wide_limbs_of(A->prec);
+  const int L = WL ? WL : limbs_of(A->prec);
   if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L))
     return fail(MPS_EINVAL, "y overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
+  if (WL)
+    return wide_spmv(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status, (hipStream_t)stream);
   const SpmvVariant var = plan ? plan_variant(plan, 0, mode) : SpmvVariant{};
   return spmv_launch(L, A->row_dim, A->row_ptr, A->col_idx, A->val, *x, *y, mode, ctx->status,
                      nullptr, (hipStream_t)stream, nullptr, nullptr, &var);

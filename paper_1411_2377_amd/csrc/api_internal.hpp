@@ -97,11 +97,14 @@ int dot_work_alloc(int nslots, int ring_log2, int reps, int ngroups, int32_t** a
 int fail(int code, const char* fmt, ...);
 void clear_error();
 int hip_fail(hipError_t e, const char* what);
+// RN_p(m 10^e10) into L limbs and a header (false: out of range)
+bool decimal_to_mp(int64_t m, int64_t e10, int L, uint32_t* limbs, int32_t* hdr);
 int get_ctx(DeviceCtx** out);
 int limbs_of(int prec);
 int check_vec(const mp_vec* v, int64_t want_len, const char* name);
 bool vec_overlap(const mp_vec* a, const mp_vec* b, int L);
-int check_csr(const mp_csr* A, int check_device_data);
+// wide_ok: the precisions of the wide path (2048, 4096, 8192) are accepted too
+int check_csr(const mp_csr* A, int check_device_data, bool wide_ok = false);
 // Kernel variant of one product: rows per block (0: by shape), staged x (x_rec: a buffer of
 // x_len records, the launch first stages x into it), rows in a given order (nullptr: in order),
 // and for SEQ the pipelined kernel (always with a row order).

@@ -18,6 +18,7 @@
 #include "api_internal.hpp"
 #include "mp_core.hpp"
 #include "plan_internal.hpp"
+#include "wide_internal.hpp"
 
 namespace {
 
@@ -156,6 +157,7 @@ int plan_x_rec(mp_plan* P) {
 
 int plan_gather(mp_plan* P, const mp_csr* A, hipStream_t s) {
   if (P->nnz == 0) return MPS_OK;
+  if (P->L > 32) return wide_gather(P->L, P->perm, P->nnz, A->val, P->t_limb, P->t_hdr, s);
   const unsigned g = blocks_for(P->nnz, 256);
   switch (P->L) {
     case 4: hipLaunchKernelGGL(gather_values_kernel<4>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
@@ -169,7 +171,7 @@ int plan_gather(mp_plan* P, const mp_csr* A, hipStream_t s) {
 
 int plan_build(const mp_csr* A, hipStream_t s, mp_plan** out) {
   mp_plan* P = new mp_plan();
-  P->L = limbs_of(A->prec);
+  P->L = limbs_of(A->prec) ? limbs_of(A->prec) : wide_limbs_of(A->prec);
   P->prec = A->prec;
   P->n_rows = A->row_dim;
   P->n_cols = A->col_dim;
@@ -473,7 +475,7 @@ int mp_plan_create(const mp_csr* A, void* stream, mp_plan** plan) {
   clear_error();
   if (!plan) return fail(MPS_EINVAL, "plan: null output pointer");
   *plan = nullptr;
-  int r = check_csr(A, 0);
+  int r = check_csr(A, 0, true);
   if (r) return r;
   return plan_build(A, (hipStream_t)stream, plan);
 }
@@ -486,7 +488,7 @@ int mp_plan_destroy(mp_plan* plan) {
 
 int mp_plan_refresh(mp_plan* plan, const mp_csr* A, void* stream) {
   clear_error();
-  int r = check_csr(A, 0);
+  int r = check_csr(A, 0, true);
   if (r) return r;
   if ((r = check_plan(plan, A))) return r;
   return plan_gather(plan, A, (hipStream_t)stream);
@@ -495,13 +497,13 @@ int mp_plan_refresh(mp_plan* plan, const mp_csr* A, void* stream) {
 int mpspmv_csr_t(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp_plan* plan,
                  void* stream) {
   clear_error();
-  int r = check_csr(A, 0);
+  int r = check_csr(A, 0, true);
   if (r) return r;
   if ((r = check_plan(plan, A))) return r;
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if ((r = check_vec(x, A->row_dim, "x"))) return r;
   if ((r = check_vec(y, A->col_dim, "y"))) return r;
-  const int L = limbs_of(A->prec);
+  const int L = plan->L;
   if (vec_overlap(x, y, L) || vec_overlap(&A->val, y, L)) return fail(MPS_EINVAL, "y overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
@@ -510,6 +512,9 @@ int mpspmv_csr_t(const mp_csr* A, const mp_vec* x, mp_vec* y, int mode, const mp
   tv.hdr = plan->t_hdr;
   tv.len = plan->nnz;
   tv.ld = plan->nnz;
+  if (L > 32)
+    return wide_spmv(L, A->col_dim, plan->t_row_ptr, plan->t_col_idx, tv, *x, *y, mode, ctx->status,
+                     (hipStream_t)stream);
   const SpmvVariant var = plan_variant(plan, 1, mode);
   return spmv_launch(L, A->col_dim, plan->t_row_ptr, plan->t_col_idx, tv, *x, *y, mode,
                      ctx->status, nullptr, (hipStream_t)stream, nullptr, nullptr, &var);

@@ -23,6 +23,7 @@
 #include "spmv_internal.hpp"
 #include "solver_kernels.hpp"
 #include "vec_internal.hpp"
+#include "wide_internal.hpp"
 
 namespace mpapi {
 
@@ -80,6 +81,8 @@ struct Big {
     return true;
   }
 };
+
+}  // namespace
 
 // RN_p of |m| * 10^e10 into (limbs, hdr); returns false if out of the supported range.
 bool decimal_to_mp(int64_t m, int64_t e10, int L, uint32_t* limbs, int32_t* hdr) {
@@ -145,6 +148,8 @@ bool decimal_to_mp(int64_t m, int64_t e10, int L, uint32_t* limbs, int32_t* hdr)
   *hdr = (int32_t)(((uint32_t)e << 1) | (uint32_t)sign);
   return true;
 }
+
+namespace {
 
 double mp_to_double(const uint32_t* limbs, int32_t hdr, int L, int64_t ld) {
   const int32_t e = hdr >> 1;
@@ -1005,6 +1010,36 @@ int bicg_ilu0_impl(const mp_csr* A, const mp_plan* plan, const mp_ilu* K, const 
   return finish_solve(W, info, st);
 }
 
+// BiCG at the wide precisions (2048, 4096, 8192 bits: the top of the paper's sweep, Sec. 4.1,
+// Tables 1 and 2), driven from the host over the wide path's kernels (wide.hip).
+int bicg_wide_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+                   const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+  int r = check_csr(A, 0, true);
+  if (r) return r;
+  if (A->row_dim != A->col_dim) return fail(MPS_EINVAL, "A must be square");
+  if (!o || !info) return fail(MPS_EINVAL, "null opts/info");
+  if (o->mode != MP_SEQ && o->mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
+  if (o->maxit < 0 || o->maxit > INT32_MAX) return fail(MPS_EINVAL, "maxit out of range");
+  if ((r = check_vec(b, A->row_dim, "b"))) return r;
+  if ((r = check_vec(x, A->row_dim, "x"))) return r;
+  const int L = wide_limbs_of(A->prec);
+  if (vec_overlap(b, x, L)) return fail(MPS_EINVAL, "x overlaps b");
+  if (o->res_hist && o->res_hist->len > 0 && (!o->res_hist->limb || !o->res_hist->hdr))
+    return fail(MPS_EINVAL, "res_hist: null pointer");
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  OwnedPlan own;
+  if (!plan) {
+    if ((r = plan_build(A, user, &own.p))) return r;
+    plan = own.p;
+  } else if ((r = check_plan(plan, A))) {
+    return r;
+  }
+  const WideOp a{A->row_dim, A->row_ptr, A->col_idx, A->val};
+  const WideOp t{A->col_dim, plan->t_row_ptr, plan->t_col_idx, mp_vec{plan->t_limb, plan->t_hdr, plan->nnz, plan->nnz}};
+  return wide_bicg(L, o->transpose ? t : a, o->transpose ? a : t, b, x, o, info, ctx->status, user);
+}
+
 // ---- batched GPBiCG --------------------------------------------------------------------
 // nsys systems, nrhs right-hand sides each: nsys * nrhs independent solves ("pairs", pair
 // s * nrhs + k) advanced together.  The systems are concatenated into one block-diagonal CSR
@@ -1226,6 +1261,7 @@ extern "C" {
 int bicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
          const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
+  if (A && wide_limbs_of(A->prec)) return bicg_wide_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
   return bicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 
@@ -1267,14 +1303,23 @@ int gpbicg_batched(int nsys, const mp_csr* A, int nrhs, const mp_vec* b, mp_vec*
 
 int mp_const_decimal(int64_t m, int64_t e10, int prec, mp_vec* out, void* stream) {
   clear_error();
-  const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
+  const int WL = wide_limbs_of(prec);
+  const int L = WL ? WL : limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024, 2048, 4096, 8192}", prec);
   int r = check_vec(out, 1, "out");
   if (r) return r;
-  uint32_t m_[32];
+  std::vector<uint32_t> m_(L);
   int32_t h;
-  if (!decimal_to_mp(m, e10, L, m_, &h)) return fail(MPS_EINVAL, "constant out of range");
-  return set_scalar(L, ref(*out), m_, h, (hipStream_t)stream);
+  if (!decimal_to_mp(m, e10, L, m_.data(), &h)) return fail(MPS_EINVAL, "constant out of range");
+  if (!WL) return set_scalar(L, ref(*out), m_.data(), h, (hipStream_t)stream);
+  // wide: the limbs one plane at a time (a synchronous upload of L + 1 words)
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < L && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(out->limb + (int64_t)k * out->ld, &m_[k], 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out->hdr, &h, 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? MPS_OK : hip_fail(e, "constant upload");
 }
 
 }  // extern "C"

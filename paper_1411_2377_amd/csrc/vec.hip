@@ -8,6 +8,7 @@
 #include "api_internal.hpp"
 #include "solver_kernels.hpp"
 #include "vec_internal.hpp"
+#include "wide_internal.hpp"
 
 namespace mpapi {
 
@@ -219,8 +220,9 @@ extern "C" {
 
 int mp_axpy(const mp_vec* alpha, const mp_vec* x, mp_vec* y, int prec, void* stream) {
   clear_error();
-  const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
+  const int WL = wide_limbs_of(prec);
+  const int L = WL ? WL : limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024, 2048, 4096, 8192}", prec);
   int r;
   if ((r = check_scalar(alpha, "alpha"))) return r;
   if (!x || !y) return fail(MPS_EINVAL, "null vector");
@@ -236,13 +238,15 @@ int mp_axpy(const mp_vec* alpha, const mp_vec* x, mp_vec* y, int prec, void* str
   a.v[2] = ref(*alpha);
   a.ctl = nullptr;
   a.status = ctx->status;
+  if (WL) return wide_axpy(L, 0, *alpha, *x, *y, y->len, ctx->status, (hipStream_t)stream);
   return launch_ew(L, EW_AXPY, a, (hipStream_t)stream);
 }
 
 int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream) {
   clear_error();
-  const int L = limbs_of(prec);
-  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024}", prec);
+  const int WL = wide_limbs_of(prec);
+  const int L = WL ? WL : limbs_of(prec);
+  if (!L) return fail(MPS_EINVAL, "precision %d not in {128, 256, 512, 1024, 2048, 4096, 8192}", prec);
   int r;
   if (!x || !y) return fail(MPS_EINVAL, "null vector");
   if ((r = check_vec(y, x->len, "y"))) return r;
@@ -251,6 +255,7 @@ int mp_dot(const mp_vec* x, const mp_vec* y, mp_vec* out, int prec, void* stream
   if (vec_overlap(x, out, L) || vec_overlap(y, out, L)) return fail(MPS_EINVAL, "out overlaps an input");
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
+  if (WL) return wide_dot(L, *x, *y, *out, ctx->status, (hipStream_t)stream);
   mp::DotArgs a{};
   a.n = x->len;
   a.x[0] = ref(*x);

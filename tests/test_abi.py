@@ -61,7 +61,7 @@ def test_host_validation_errors():
     assert "overlap" in _lib.last_error()
 
 
-@pytest.mark.parametrize("prec", [64, 96, 2048, 0])
+@pytest.mark.parametrize("prec", [64, 96, 3072, 16384, 0])
 def test_unsupported_precisions_rejected(prec):
     from paper_1411_2377_amd import _lib
     a = _lib.MpCsr()
