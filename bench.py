@@ -341,6 +341,36 @@ def ilu_component(M, torch):
     return out
 
 
+def precision_sweep_component(M, torch):
+    """The paper's precision sweep (Sec. 4.1, Tables 1-2: the same solve at 512 to 8192 bits):
+    BiCG on the 2-D convection-diffusion operator on a 16 x 16 grid, b = A * ones (EXACT), SEQ
+    products, 20 iterations (tolerance below reach), at p = 512 and 1024 (one number per lane)
+    and 2048, 4096, 8192 (numbers across a wavefront); ms per iteration and the growth factor per
+    doubling of p (the paper: about 2.8-2.9 per doubling for BiCG on cavity04 in MPFR)."""
+    import synth
+    out = {"workload": "2-D convection-diffusion 16x16 (n=256), BiCG, SEQ, 20 iterations"}
+    prev = None
+    for p in (512, 1024, 2048, 4096, 8192):
+        A_h, ones = synth.config2(p=p, m=16)
+        A = M.CSRMatrix.from_host(A_h)
+        b = M.mpspmv_csr(A, M.MPArray.from_host(ones), mode=M.MP_EXACT)
+        plan = M.mp_plan_create(A)
+        M.bicg(A, b, plan=plan, mode=M.MP_SEQ, maxit=2, rtol=(1, -2000), atol=(0, 0), chunk=0)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, info = M.bicg(A, b, plan=plan, mode=M.MP_SEQ, maxit=20, rtol=(1, -2000), atol=(0, 0), chunk=0)
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) * 1e3 / max(1, info.iters)
+        e = {"ms_per_iter": round(ms, 3), "iters": info.iters, "status": info.status,
+             "path": "one number per lane" if p <= 1024 else "numbers across a wavefront"}
+        if prev:
+            e["x_per_doubling"] = round(ms / prev, 2)
+        out["p%d" % p] = e
+        prev = ms
+    M.mp_status()
+    return out
+
+
 def lotkin_component(M, torch, reps):
     """The paper's SpMV benchmark (Sec. 3): the Lotkin matrix (n = 2000) with s% of its elements
     set to zero, b = A [1..n] by the sparse product, then A b by the dense product (all n^2
@@ -501,6 +531,7 @@ def main():
         comp["solvers_convdiff256"] = solver_component(M, torch)
         comp["lotkin_dense_vs_sparse"] = lotkin_component(M, torch, reps)
         comp["ilu0_bicgstab"] = ilu_component(M, torch)
+        comp["precision_sweep_bicg"] = precision_sweep_component(M, torch)
         comp["batched_gpbicg"] = batched_component(M, torch)
     out = {
         "metric": "MP nonzeros/s for 256-bit MP-SpMV (+ % roofline); BiCG solve time, batched vs plain",
