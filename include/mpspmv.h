@@ -14,9 +14,9 @@
  * precisions L in {64, 128, 256} (p = 2048, 4096, 8192) — the paper runs its solvers at 512 to
  * 8192 bits, Sec. 4.1, Tables 1 and 2.  The wide precisions are served by mpspmv_csr,
  * mpspmv_csr_t (with mp_plan_create / mp_plan_refresh / mp_plan_destroy), mp_dot, mp_axpy,
- * mp_const_decimal, mp_validate_csr and bicg (host-driven: one synchronisation per inner product
- * whose value decides a branch; opts->chunk and opts->profile are ignored); the other entry
- * points return MPS_EINVAL for them.  Each operation is done by one wavefront on numbers held in
+ * mp_const_decimal, mp_validate_csr, bicg, gpbicg, cgs and bicgstab (host-driven: one
+ * synchronisation per inner product whose value decides a branch; opts->chunk and opts->profile
+ * are ignored); the other entry points return MPS_EINVAL for them.  Each operation is done by one wavefront on numbers held in
  * LDS; an EXACT row or a block's share of an inner product must span at most
  * 32 (4096 - 2L - 2) bits (about 114,000 to 131,000; wider sets MP_ST_WINDOW and gives +0), and
  * inner products at these precisions on two streams of one device must not overlap.

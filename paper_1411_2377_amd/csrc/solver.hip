@@ -1010,10 +1010,12 @@ int bicg_ilu0_impl(const mp_csr* A, const mp_plan* plan, const mp_ilu* K, const 
   return finish_solve(W, info, st);
 }
 
-// BiCG at the wide precisions (2048, 4096, 8192 bits: the top of the paper's sweep, Sec. 4.1,
-// Tables 1 and 2), driven from the host over the wide path's kernels (wide.hip).
-int bicg_wide_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
-                   const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
+// BiCG, GPBiCG, CGS and BiCGSTAB at the wide precisions (2048, 4096, 8192 bits: the top of the
+// paper's sweep, Sec. 4.1, Tables 1 and 2), driven from the host over the wide path's kernels
+// (wide.hip).
+enum WideMethod { WM_BICG, WM_GPBICG, WM_CGS, WM_BICGSTAB };
+int wide_solve_impl(WideMethod m, const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
+                    const mp_solve_opts* o, mp_solve_info* info, hipStream_t user) {
   int r = check_csr(A, 0, true);
   if (r) return r;
   if (A->row_dim != A->col_dim) return fail(MPS_EINVAL, "A must be square");
@@ -1029,15 +1031,23 @@ int bicg_wide_impl(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
   OwnedPlan own;
-  if (!plan) {
+  if (plan) {
+    if ((r = check_plan(plan, A))) return r;
+  } else if (m == WM_BICG || o->transpose) {  // A^T is needed: build the transpose
     if ((r = plan_build(A, user, &own.p))) return r;
     plan = own.p;
-  } else if ((r = check_plan(plan, A))) {
-    return r;
   }
   const WideOp a{A->row_dim, A->row_ptr, A->col_idx, A->val};
-  const WideOp t{A->col_dim, plan->t_row_ptr, plan->t_col_idx, mp_vec{plan->t_limb, plan->t_hdr, plan->nnz, plan->nnz}};
-  return wide_bicg(L, o->transpose ? t : a, o->transpose ? a : t, b, x, o, info, ctx->status, user);
+  WideOp t = a;
+  if (plan)
+    t = WideOp{A->col_dim, plan->t_row_ptr, plan->t_col_idx, mp_vec{plan->t_limb, plan->t_hdr, plan->nnz, plan->nnz}};
+  const WideOp& op = o->transpose ? t : a;
+  switch (m) {
+    case WM_BICG: return wide_bicg(L, op, o->transpose ? a : t, b, x, o, info, ctx->status, user);
+    case WM_GPBICG: return wide_gpbicg(L, op, b, x, o, info, ctx->status, user);
+    case WM_CGS: return wide_cgs(L, op, b, x, o, info, ctx->status, user);
+    default: return wide_bicgstab(L, op, b, x, o, info, ctx->status, user);
+  }
 }
 
 // ---- batched GPBiCG --------------------------------------------------------------------
@@ -1261,25 +1271,28 @@ extern "C" {
 int bicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
          const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
-  if (A && wide_limbs_of(A->prec)) return bicg_wide_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
+  if (A && wide_limbs_of(A->prec)) return wide_solve_impl(WM_BICG, A, plan, b, x, opts, info, (hipStream_t)stream);
   return bicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 
 int gpbicg(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
            const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
+  if (A && wide_limbs_of(A->prec)) return wide_solve_impl(WM_GPBICG, A, plan, b, x, opts, info, (hipStream_t)stream);
   return gpbicg_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 
 int cgs(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
         const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
+  if (A && wide_limbs_of(A->prec)) return wide_solve_impl(WM_CGS, A, plan, b, x, opts, info, (hipStream_t)stream);
   return cgs_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 
 int bicgstab(const mp_csr* A, const mp_plan* plan, const mp_vec* b, mp_vec* x,
              const mp_solve_opts* opts, mp_solve_info* info, void* stream) {
   clear_error();
+  if (A && wide_limbs_of(A->prec)) return wide_solve_impl(WM_BICGSTAB, A, plan, b, x, opts, info, (hipStream_t)stream);
   return bicgstab_impl(A, plan, b, x, opts, info, (hipStream_t)stream);
 }
 

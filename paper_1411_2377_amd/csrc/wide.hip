@@ -791,6 +791,7 @@ enum ScalarOp { SC_DIV = 0, SC_MUL, SC_ADD, SC_SQRT, SC_ZERO, SC_CONV };
 
 struct ScalarA {
   int op, L;
+  int negb;  // SC_ADD: a - b
   const uint32_t* a_limb;
   const int32_t* a_hdr;
   int64_t a_ld;
@@ -816,7 +817,12 @@ __global__ void __launch_bounds__(64) scalar(ScalarA A) {
   switch (A.op) {
     case SC_DIV: o = wide_div(S, r, L, S.x, a, S.y, b, st); break;
     case SC_MUL: o = wide_mul(S, r, L, S.x, a, S.y, b, st); break;
-    case SC_ADD: o = wide_add(S, r, L, S.x, a, S.y, b, st); break;
+    case SC_ADD: {
+      WNum bb = b;
+      if (A.negb) bb.s ^= 1u;
+      o = wide_add(S, r, L, S.x, a, S.y, bb, st);
+      break;
+    }
     case SC_SQRT: o = wide_sqrt(S, r, L, S.x, a, st); break;
     case SC_ZERO:
       if (lane_id() == 0) *A.flag = a.e == kZeroE ? 1 : 0;
@@ -829,6 +835,68 @@ __global__ void __launch_bounds__(64) scalar(ScalarA A) {
   }
   if (A.op <= SC_SQRT) store_num(r, o, L, A.o_limb, A.o_hdr, A.o_ld, 0);
   if (st && lane_id() == 0) atomicOr(A.status, st);
+}
+
+// Element programs: per element, a few RN multiplications, additions and subtractions on
+// registers loaded from vectors and scalars, in the order the program lists them (one RN per
+// operation), the chosen registers stored back.  Operands 0..7 are element registers, 8..11
+// scalars.
+constexpr int kProgRegs = 8, kProgScalars = 4, kProgIns = 16, kProgIn = 7, kProgOut = 3;
+enum ProgOp { PO_MUL = 0, PO_ADD, PO_SUB };
+
+struct VRef {
+  const uint32_t* limb;
+  const int32_t* hdr;
+  int64_t ld;
+};
+
+struct ProgA {
+  int64_t n;
+  int L;
+  int n_in, n_sc, n_ins, n_out;
+  VRef in[kProgIn];
+  int in_reg[kProgIn];
+  VRef sc[kProgScalars];
+  int8_t op[kProgIns], dst[kProgIns], a[kProgIns], b[kProgIns];
+  VRef out[kProgOut];
+  int out_reg[kProgOut];
+  uint32_t* status;
+};
+
+__global__ void __launch_bounds__(64) prog(ProgA P) {
+  __shared__ Lds S;
+  __shared__ uint32_t reg[kProgRegs + kProgScalars][kMaxL + 4];
+  const int L = P.L;
+  uint32_t st = 0;
+  WNum w[kProgRegs + kProgScalars];
+  for (int k = 0; k < P.n_sc; ++k)
+    w[kProgRegs + k] = load_num(reg[kProgRegs + k], L, P.sc[k].limb, P.sc[k].hdr, P.sc[k].ld, 0);
+  for (int64_t i = blockIdx.x; i < P.n; i += gridDim.x) {
+    for (int k = 0; k < P.n_in; ++k)
+      w[P.in_reg[k]] = load_num(reg[P.in_reg[k]], L, P.in[k].limb, P.in[k].hdr, P.in[k].ld, i);
+    for (int t = 0; t < P.n_ins; ++t) {
+      const int a = P.a[t], b = P.b[t], d = P.dst[t];
+      WNum r;
+      if (P.op[t] == PO_MUL) {
+        r = wide_mul(S, S.acc, L, reg[a], w[a], reg[b], w[b], st);
+      } else {
+        WNum wb = w[b];
+        if (P.op[t] == PO_SUB) wb.s ^= 1u;
+        r = wide_add(S, S.acc, L, reg[a], w[a], reg[b], wb, st);
+      }
+      big_copy(reg[d], S.acc, L);
+      wsync();
+      w[d] = r;
+    }
+    for (int k = 0; k < P.n_out; ++k) {
+      const int rr = P.out_reg[k];
+      uint32_t* ol = const_cast<uint32_t*>(P.out[k].limb);
+      int32_t* oh = const_cast<int32_t*>(P.out[k].hdr);
+      store_num(reg[rr], w[rr], L, ol, oh, P.out[k].ld, i);
+    }
+    wsync();
+  }
+  if (st && lane_id() == 0) atomicOr(P.status, st);
 }
 
 // dst[k] = src[perm[k]] for every limb plane and the header
@@ -985,9 +1053,9 @@ int wzero(int L, const mp_vec& dst, int64_t n, hipStream_t s) {
 }
 
 int wscalar(int L, int op, const mp_vec& a, const mp_vec* b, const mp_vec* o, int32_t* flag, uint32_t* status,
-            hipStream_t s) {
-  wide_k::ScalarA k{op, L, a.limb, a.hdr, a.ld, b ? b->limb : nullptr, b ? b->hdr : nullptr, b ? b->ld : 0,
-                    o ? o->limb : nullptr, o ? o->hdr : nullptr, o ? o->ld : 0, flag, status};
+            hipStream_t s, bool negb = false) {
+  wide_k::ScalarA k{op, L, negb ? 1 : 0, a.limb, a.hdr, a.ld, b ? b->limb : nullptr, b ? b->hdr : nullptr,
+                    b ? b->ld : 0, o ? o->limb : nullptr, o ? o->hdr : nullptr, o ? o->ld : 0, flag, status};
   hipLaunchKernelGGL(wide_k::scalar, dim3(1), dim3(64), 0, s, k);
   return launched("wide scalar operation");
 }
@@ -1012,6 +1080,468 @@ struct WideBufs {
 };
 
 }  // namespace
+
+namespace {
+
+// A host-driven wide solve: its vectors, scalar slots and the flag the host reads.
+struct WSolve {
+  int L;
+  int64_t n;
+  int mode;
+  uint32_t* status;
+  hipStream_t s;
+  WideBufs B;
+  mp_vec sc{};
+  int32_t* dflag = nullptr;
+  static constexpr int kSlots = 32;
+
+  int init(int L_, int64_t n_, int mode_, uint32_t* st_, hipStream_t s_) {
+    L = L_;
+    n = n_;
+    mode = mode_;
+    status = st_;
+    s = s_;
+    int r = B.vec(L, kSlots, &sc);
+    if (r) return r;
+    hipError_t e = hipMalloc((void**)&dflag, sizeof(int32_t));
+    if (e != hipSuccess) return fail(MPS_ENOMEM, "wide solve flag: %s", hipGetErrorString(e));
+    B.ptrs.push_back(dflag);
+    return MPS_OK;
+  }
+  mp_vec S(int k) const { return elem(sc, k); }
+  int vec(mp_vec* v) { return B.vec(L, n, v); }
+  int read_flag(bool* f) {
+    int32_t h = 0;
+    hipError_t e = hipMemcpyAsync(&h, dflag, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "wide solve flag");
+    *f = h != 0;
+    return MPS_OK;
+  }
+  int is_zero(int k, bool* z) {
+    int r = wscalar(L, wide_k::SC_ZERO, S(k), nullptr, nullptr, dflag, status, s);
+    return r ? r : read_flag(z);
+  }
+  int conv(int q, int thr, bool* c) {
+    const mp_vec t = S(thr);
+    int r = wscalar(L, wide_k::SC_CONV, S(q), &t, nullptr, dflag, status, s);
+    return r ? r : read_flag(c);
+  }
+  // slot o = a (op) b
+  int scal(int op, int a, int b, int o, bool negb = false) {
+    const mp_vec bv = S(b), ov = S(o);
+    return wscalar(L, op, S(a), &bv, &ov, nullptr, status, s, negb);
+  }
+  int copy_slot(int from, int to) { return wcopy(L, S(from), S(to), 1, s); }
+  int dot(const mp_vec& x, const mp_vec& y, int o) { return wide_dot(L, x, y, S(o), status, s); }
+  int spmv(const WideOp& A, const mp_vec& in, const mp_vec& out) {
+    return wide_spmv(L, A.n_out, A.row_ptr, A.col_idx, A.val, in, out, mode, status, s);
+  }
+  int set_const(int k, int64_t m, int64_t e10) {
+    std::vector<uint32_t> l(L);
+    int32_t h;
+    if (!decimal_to_mp(m, e10, L, l.data(), &h)) return fail(MPS_EINVAL, "tolerance out of range");
+    const mp_vec c = S(k);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < L && e == hipSuccess; ++q)
+      e = hipMemcpyAsync(c.limb + (int64_t)q * c.ld, &l[q], 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.hdr, &h, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? MPS_OK : hip_fail(e, "constant upload");
+  }
+};
+
+// An element program under construction: inputs (vector -> register), scalars (slot ->
+// operand 8 + k), instructions, outputs (register -> vector).
+struct Prog {
+  wide_k::ProgA a{};
+  const WSolve* w;
+  explicit Prog(const WSolve& ws) : w(&ws) {
+    a.n = ws.n;
+    a.L = ws.L;
+    a.status = ws.status;
+  }
+  static wide_k::VRef ref(const mp_vec& v) { return wide_k::VRef{v.limb, v.hdr, v.ld}; }
+  bool bad = false;  // a program beyond the kernel's table sizes (a bug here, reported by run)
+  static bool reg_ok(int r) { return r >= 0 && r < wide_k::kProgRegs; }
+  Prog& in(const mp_vec& v, int reg) {
+    if (a.n_in >= wide_k::kProgIn || !reg_ok(reg)) return bad = true, *this;
+    a.in[a.n_in] = ref(v);
+    a.in_reg[a.n_in++] = reg;
+    return *this;
+  }
+  int scalar(int slot) {  // operand index of a scalar slot
+    if (a.n_sc >= wide_k::kProgScalars) return bad = true, 0;
+    a.sc[a.n_sc] = ref(w->S(slot));
+    return wide_k::kProgRegs + a.n_sc++;
+  }
+  Prog& op(int o, int d, int x, int y) {
+    const int lim = wide_k::kProgRegs + wide_k::kProgScalars;
+    if (a.n_ins >= wide_k::kProgIns || !reg_ok(d) || x < 0 || x >= lim || y < 0 || y >= lim)
+      return bad = true, *this;
+    a.op[a.n_ins] = (int8_t)o;
+    a.dst[a.n_ins] = (int8_t)d;
+    a.a[a.n_ins] = (int8_t)x;
+    a.b[a.n_ins++] = (int8_t)y;
+    return *this;
+  }
+  Prog& out(int reg, const mp_vec& v) {
+    if (a.n_out >= wide_k::kProgOut || !reg_ok(reg)) return bad = true, *this;
+    a.out[a.n_out] = ref(v);
+    a.out_reg[a.n_out++] = reg;
+    return *this;
+  }
+  int run() {
+    if (bad) return fail(MPS_EINVAL, "wide element program exceeds its tables");
+    if (a.n == 0) return MPS_OK;
+    hipLaunchKernelGGL(wide_k::prog, dim3(grid_of(a.n, 8192)), dim3(64), 0, w->s, a);
+    return launched("wide element program");
+  }
+};
+
+enum { W_RHO, W_RHO_OLD, W_ALPHA, W_ALPHA_OLD, W_BETA, W_SIGMA, W_Q, W_Q0, W_NRM0, W_THR, W_CREL, W_CABS,
+       W_T1, W_T2, W_T3, W_T4, W_ZETA, W_ZETA_OLD, W_ETA, W_MU1, W_MU2, W_MU3, W_MU4, W_MU5, W_TAU,
+       W_OMEGA, W_OMEGA_OLD, W_TS, W_TT };
+
+// The shared start of the methods: r = b - A x0 (or r = b, x = +0), r~ = r, q0 = (r, r),
+// thr = RN(RN(c_rel RN(sqrt q0)) + c_abs); *done when r_0 already passes the test.
+int wide_setup(WSolve& W, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+               const mp_vec& r, const mp_vec& rt, mp_solve_info* info, bool* done) {
+  int rr;
+  if ((rr = W.set_const(W_CREL, o->rtol_m, o->rtol_e10)) || (rr = W.set_const(W_CABS, o->atol_m, o->atol_e10)))
+    return rr;
+  if (o->use_x0) {
+    if ((rr = W.spmv(op, *x, r))) return rr;
+    if ((rr = wide_axpy(W.L, 3, W.S(W_T1), *b, r, W.n, W.status, W.s))) return rr;  // r = b - A x0
+  } else {
+    if ((rr = wzero(W.L, *x, W.n, W.s)) || (rr = wcopy(W.L, *b, r, W.n, W.s))) return rr;
+  }
+  if ((rr = wcopy(W.L, r, rt, W.n, W.s))) return rr;
+  if ((rr = W.dot(r, r, W_Q0))) return rr;
+  const mp_vec q0 = W.S(W_Q0), nrm0 = W.S(W_NRM0);
+  if ((rr = wscalar(W.L, wide_k::SC_SQRT, q0, nullptr, &nrm0, nullptr, W.status, W.s))) return rr;
+  if ((rr = W.scal(wide_k::SC_MUL, W_CREL, W_NRM0, W_T1)) || (rr = W.scal(wide_k::SC_ADD, W_T1, W_CABS, W_THR)))
+    return rr;
+  info->iters = 0;
+  info->status = MP_NC;
+  bool c = false;
+  if ((rr = W.conv(W_Q0, W_THR, &c))) return rr;
+  if (c) info->status = MP_CONVERGED;
+  *done = c || o->maxit <= 0;
+  return MPS_OK;
+}
+
+// the residual history entry of iteration i, the stopping test; *stop when converged
+int wide_after(WSolve& W, const mp_solve_opts* o, int64_t i, mp_solve_info* info, bool* stop) {
+  int rr;
+  if (o->res_hist && o->res_hist->len > 0 && i - 1 < o->res_hist->len &&
+      (rr = wcopy(W.L, W.S(W_Q), elem(*o->res_hist, i - 1), 1, W.s)))
+    return rr;
+  bool c = false;
+  if ((rr = W.conv(W_Q, W_THR, &c))) return rr;
+  info->iters = i;
+  if (c) info->status = MP_CONVERGED;
+  *stop = c;
+  return MPS_OK;
+}
+
+int final_res(WSolve& W, mp_solve_info* info) {
+  const int L = W.L;
+  uint32_t qt = 0, q0t = 0;
+  int32_t qh = 0, q0h = 0;
+  const mp_vec qv = W.S(info->iters > 0 ? W_Q : W_Q0), q0v = W.S(W_Q0);
+  hipError_t e = hipMemcpyAsync(&qh, qv.hdr, 4, hipMemcpyDeviceToHost, W.s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&q0h, q0v.hdr, 4, hipMemcpyDeviceToHost, W.s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&qt, qv.limb + (int64_t)(L - 1) * qv.ld, 4, hipMemcpyDeviceToHost, W.s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&q0t, q0v.limb + (int64_t)(L - 1) * q0v.ld, 4, hipMemcpyDeviceToHost, W.s);
+  if (e == hipSuccess) e = hipStreamSynchronize(W.s);
+  if (e != hipSuccess) return hip_fail(e, "wide solve readback");
+  auto approx = [](uint32_t top, int32_t hd) {
+    const int32_t ex = hd >> 1;
+    if (ex == kZeroE) return 0.0;
+    return std::ldexp((double)top, std::max(-1070, std::min(1020, ex - 32)));
+  };
+  const double a0 = approx(q0t, q0h), a1 = approx(qt, qh);
+  info->final_rel_res = a0 > 0 ? std::sqrt(a1 / a0) : 0.0;
+  return MPS_OK;
+}
+
+}  // namespace
+
+// CGS (the same operations as the fixed-width cgs and the oracle's)
+int wide_cgs(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o, mp_solve_info* info,
+             uint32_t* status, hipStream_t s) {
+  WSolve W;
+  int rr;
+  mp_vec r, rt, u, p, q, vh, uh, qh;
+  if ((rr = W.init(L, op.n_out, o->mode, status, s)) || (rr = W.vec(&r)) || (rr = W.vec(&rt)) ||
+      (rr = W.vec(&u)) || (rr = W.vec(&p)) || (rr = W.vec(&q)) || (rr = W.vec(&vh)) || (rr = W.vec(&uh)) ||
+      (rr = W.vec(&qh)))
+    return rr;
+  bool done = false;
+  if ((rr = wide_setup(W, op, b, x, o, r, rt, info, &done))) return rr;
+  for (int64_t i = 1; !done && i <= o->maxit; ++i) {
+    bool z = false;
+    if ((rr = W.dot(rt, r, W_RHO)) || (rr = W.is_zero(W_RHO, &z))) return rr;
+    if (z) {
+      info->status = MP_BREAKDOWN_RHO;
+      info->iters = i - 1;
+      break;
+    }
+    if (i == 1) {
+      if ((rr = wcopy(L, r, u, W.n, s)) || (rr = wcopy(L, r, p, W.n, s))) return rr;
+    } else {
+      if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_RHO_OLD, W_BETA))) return rr;
+      // u = r + beta q;  p = u + beta (q + beta p)
+      Prog P(W);
+      const int be = P.scalar(W_BETA);
+      P.in(r, 0).in(q, 1).in(p, 2);
+      P.op(wide_k::PO_MUL, 3, be, 1).op(wide_k::PO_ADD, 4, 0, 3);   // u
+      P.op(wide_k::PO_MUL, 5, be, 2).op(wide_k::PO_ADD, 5, 1, 5).op(wide_k::PO_MUL, 5, be, 5)
+          .op(wide_k::PO_ADD, 6, 4, 5);                              // p
+      P.out(4, u).out(6, p);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, p, vh)) || (rr = W.dot(rt, vh, W_SIGMA)) || (rr = W.is_zero(W_SIGMA, &z))) return rr;
+    if (z) {
+      info->status = MP_BREAKDOWN_SIGMA;
+      info->iters = i - 1;
+      break;
+    }
+    if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_SIGMA, W_ALPHA))) return rr;
+    {
+      // q = u - alpha vh;  uh = u + q;  x = x + alpha uh
+      Prog P(W);
+      const int al = P.scalar(W_ALPHA);
+      P.in(u, 0).in(vh, 1).in(*x, 2);
+      P.op(wide_k::PO_MUL, 3, al, 1).op(wide_k::PO_SUB, 3, 0, 3)   // q
+          .op(wide_k::PO_ADD, 4, 0, 3)                              // uh
+          .op(wide_k::PO_MUL, 5, al, 4).op(wide_k::PO_ADD, 5, 2, 5);  // x
+      P.out(3, q).out(4, uh).out(5, *x);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, uh, qh))) return rr;
+    if ((rr = wide_axpy(L, 2, W.S(W_ALPHA), qh, r, W.n, status, s))) return rr;  // r = r - alpha qh
+    if ((rr = W.dot(r, r, W_Q))) return rr;
+    bool stop = false;
+    if ((rr = wide_after(W, o, i, info, &stop))) return rr;
+    if (stop) break;
+    if ((rr = W.copy_slot(W_RHO, W_RHO_OLD))) return rr;
+  }
+  return final_res(W, info);
+}
+
+// BiCGSTAB
+int wide_bicgstab(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+                  mp_solve_info* info, uint32_t* status, hipStream_t s) {
+  WSolve W;
+  int rr;
+  mp_vec r, rt, p, v, sv, t;
+  if ((rr = W.init(L, op.n_out, o->mode, status, s)) || (rr = W.vec(&r)) || (rr = W.vec(&rt)) ||
+      (rr = W.vec(&p)) || (rr = W.vec(&v)) || (rr = W.vec(&sv)) || (rr = W.vec(&t)))
+    return rr;
+  bool done = false;
+  if ((rr = wide_setup(W, op, b, x, o, r, rt, info, &done))) return rr;
+  for (int64_t i = 1; !done && i <= o->maxit; ++i) {
+    bool z = false;
+    if ((rr = W.dot(rt, r, W_RHO)) || (rr = W.is_zero(W_RHO, &z))) return rr;
+    if (z) {
+      info->status = MP_BREAKDOWN_RHO;
+      info->iters = i - 1;
+      break;
+    }
+    if (i == 1) {
+      if ((rr = wcopy(L, r, p, W.n, s))) return rr;
+    } else {
+      // beta = (rho / rho_old)(alpha_old / omega_old); p = r + beta (p - omega_old v)
+      if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_RHO_OLD, W_T1)) ||
+          (rr = W.scal(wide_k::SC_DIV, W_ALPHA_OLD, W_OMEGA_OLD, W_T2)) ||
+          (rr = W.scal(wide_k::SC_MUL, W_T1, W_T2, W_BETA)))
+        return rr;
+      Prog P(W);
+      const int be = P.scalar(W_BETA), om = P.scalar(W_OMEGA_OLD);
+      P.in(r, 0).in(p, 1).in(v, 2);
+      P.op(wide_k::PO_MUL, 3, om, 2).op(wide_k::PO_SUB, 3, 1, 3).op(wide_k::PO_MUL, 3, be, 3)
+          .op(wide_k::PO_ADD, 4, 0, 3);
+      P.out(4, p);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, p, v)) || (rr = W.dot(rt, v, W_SIGMA)) || (rr = W.is_zero(W_SIGMA, &z))) return rr;
+    if (z) {
+      info->status = MP_BREAKDOWN_SIGMA;
+      info->iters = i - 1;
+      break;
+    }
+    if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_SIGMA, W_ALPHA))) return rr;
+    {
+      Prog P(W);  // s = r - alpha v
+      const int al = P.scalar(W_ALPHA);
+      P.in(r, 0).in(v, 1).op(wide_k::PO_MUL, 2, al, 1).op(wide_k::PO_SUB, 2, 0, 2).out(2, sv);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, sv, t)) || (rr = W.dot(t, sv, W_TS)) || (rr = W.dot(t, t, W_TT))) return rr;
+    bool ttz = false;
+    if ((rr = W.is_zero(W_TT, &ttz))) return rr;
+    if (ttz) {
+      if ((rr = wzero(L, W.S(W_OMEGA), 1, s))) return rr;
+    } else if ((rr = W.scal(wide_k::SC_DIV, W_TS, W_TT, W_OMEGA))) {
+      return rr;
+    }
+    {
+      // x = (x + alpha p) + omega s;  r = s - omega t
+      Prog P(W);
+      const int al = P.scalar(W_ALPHA), om = P.scalar(W_OMEGA);
+      P.in(*x, 0).in(p, 1).in(sv, 2).in(t, 3);
+      P.op(wide_k::PO_MUL, 4, al, 1).op(wide_k::PO_ADD, 4, 0, 4).op(wide_k::PO_MUL, 5, om, 2)
+          .op(wide_k::PO_ADD, 4, 4, 5)                              // x
+          .op(wide_k::PO_MUL, 6, om, 3).op(wide_k::PO_SUB, 6, 2, 6);  // r
+      P.out(4, *x).out(6, r);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.dot(r, r, W_Q))) return rr;
+    bool stop = false;
+    if ((rr = wide_after(W, o, i, info, &stop))) return rr;
+    if (stop) break;
+    bool oz = false;
+    if ((rr = W.is_zero(W_OMEGA, &oz))) return rr;
+    if (oz) {
+      info->status = MP_BREAKDOWN_ZETA;
+      break;
+    }
+    if ((rr = W.copy_slot(W_RHO, W_RHO_OLD)) || (rr = W.copy_slot(W_ALPHA, W_ALPHA_OLD)) ||
+        (rr = W.copy_slot(W_OMEGA, W_OMEGA_OLD)))
+      return rr;
+  }
+  return final_res(W, info);
+}
+
+// GPBiCG (Fig. 5 right, the readings of the fixed-width gpbicg)
+int wide_gpbicg(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+                mp_solve_info* info, uint32_t* status, hipStream_t s) {
+  WSolve W;
+  int rr;
+  mp_vec r, rt, u, z, sv, w, t, p, q, v, y;
+  if ((rr = W.init(L, op.n_out, o->mode, status, s)) || (rr = W.vec(&r)) || (rr = W.vec(&rt)) ||
+      (rr = W.vec(&u)) || (rr = W.vec(&z)) || (rr = W.vec(&sv)) || (rr = W.vec(&w)) || (rr = W.vec(&t)) ||
+      (rr = W.vec(&p)) || (rr = W.vec(&q)) || (rr = W.vec(&v)) || (rr = W.vec(&y)))
+    return rr;
+  bool done = false;
+  if ((rr = wide_setup(W, op, b, x, o, r, rt, info, &done))) return rr;
+  for (const mp_vec* vv : {&u, &z, &sv, &w, &t, &p, &q, &v})
+    if ((rr = wzero(L, *vv, W.n, s))) return rr;
+  if ((rr = wzero(L, W.S(W_BETA), 1, s))) return rr;
+  for (int64_t i = 1; !done && i <= o->maxit; ++i) {
+    bool zf = false;
+    if ((rr = W.dot(rt, r, W_RHO)) || (rr = W.is_zero(W_RHO, &zf))) return rr;
+    if (zf) {
+      info->status = MP_BREAKDOWN_RHO;
+      info->iters = i - 1;
+      break;
+    }
+    if (i == 1) {
+      if ((rr = wcopy(L, r, p, W.n, s))) return rr;
+    } else {
+      // beta = (rho / rho_old)(alpha_old / zeta_old); w = v + beta q; p = r + beta (p - u)
+      if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_RHO_OLD, W_T1)) ||
+          (rr = W.scal(wide_k::SC_DIV, W_ALPHA_OLD, W_ZETA_OLD, W_T2)) ||
+          (rr = W.scal(wide_k::SC_MUL, W_T1, W_T2, W_BETA)))
+        return rr;
+      Prog P(W);
+      const int be = P.scalar(W_BETA);
+      P.in(v, 0).in(q, 1).in(r, 2).in(p, 3).in(u, 4);
+      P.op(wide_k::PO_MUL, 5, be, 1).op(wide_k::PO_ADD, 5, 0, 5)                              // w
+          .op(wide_k::PO_SUB, 6, 3, 4).op(wide_k::PO_MUL, 6, be, 6).op(wide_k::PO_ADD, 6, 2, 6);  // p
+      P.out(5, w).out(6, p);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, p, q)) || (rr = W.dot(rt, q, W_SIGMA)) || (rr = W.is_zero(W_SIGMA, &zf))) return rr;
+    if (zf) {
+      info->status = MP_BREAKDOWN_SIGMA;
+      info->iters = i - 1;
+      break;
+    }
+    if ((rr = W.scal(wide_k::SC_DIV, W_RHO, W_SIGMA, W_ALPHA))) return rr;
+    {
+      // s = t - r (after the first iteration); t = r - alpha q
+      Prog P(W);
+      const int al = P.scalar(W_ALPHA);
+      P.in(t, 0).in(r, 1).in(q, 2);
+      if (i > 1) P.op(wide_k::PO_SUB, 3, 0, 1).out(3, sv);
+      P.op(wide_k::PO_MUL, 4, al, 2).op(wide_k::PO_SUB, 4, 1, 4).out(4, t);
+      if ((rr = P.run())) return rr;
+    }
+    if ((rr = W.spmv(op, t, v))) return rr;
+    if (i == 1) {
+      Prog P(W);  // y = alpha q - r
+      const int al = P.scalar(W_ALPHA);
+      P.in(q, 0).in(r, 1).op(wide_k::PO_MUL, 2, al, 0).op(wide_k::PO_SUB, 2, 2, 1).out(2, y);
+      if ((rr = P.run())) return rr;
+      if ((rr = W.dot(v, t, W_MU2)) || (rr = W.dot(v, v, W_MU5)) || (rr = W.is_zero(W_MU5, &zf))) return rr;
+      if (zf) {
+        info->status = MP_BREAKDOWN_TAU;
+        info->iters = i - 1;
+        break;
+      }
+      if ((rr = W.scal(wide_k::SC_DIV, W_MU2, W_MU5, W_ZETA)) || (rr = wzero(L, W.S(W_ETA), 1, s))) return rr;
+    } else {
+      Prog P(W);  // y = s - alpha (w - q)
+      const int al = P.scalar(W_ALPHA);
+      P.in(sv, 0).in(w, 1).in(q, 2);
+      P.op(wide_k::PO_SUB, 3, 1, 2).op(wide_k::PO_MUL, 3, al, 3).op(wide_k::PO_SUB, 3, 0, 3).out(3, y);
+      if ((rr = P.run())) return rr;
+      if ((rr = W.dot(y, y, W_MU1)) || (rr = W.dot(v, t, W_MU2)) || (rr = W.dot(y, t, W_MU3)) ||
+          (rr = W.dot(v, y, W_MU4)) || (rr = W.dot(v, v, W_MU5)))
+        return rr;
+      // tau = mu5 mu1 - mu4 mu4; zeta = (mu1 mu2 - mu3 mu4) / tau; eta = (mu5 mu3 - mu4 mu2) / tau
+      if ((rr = W.scal(wide_k::SC_MUL, W_MU5, W_MU1, W_T1)) || (rr = W.scal(wide_k::SC_MUL, W_MU4, W_MU4, W_T2)) ||
+          (rr = W.scal(wide_k::SC_ADD, W_T1, W_T2, W_TAU, true)) || (rr = W.is_zero(W_TAU, &zf)))
+        return rr;
+      if (zf) {
+        info->status = MP_BREAKDOWN_TAU;
+        info->iters = i - 1;
+        break;
+      }
+      if ((rr = W.scal(wide_k::SC_MUL, W_MU1, W_MU2, W_T1)) || (rr = W.scal(wide_k::SC_MUL, W_MU3, W_MU4, W_T2)) ||
+          (rr = W.scal(wide_k::SC_ADD, W_T1, W_T2, W_T3, true)) || (rr = W.scal(wide_k::SC_DIV, W_T3, W_TAU, W_ZETA)) ||
+          (rr = W.scal(wide_k::SC_MUL, W_MU5, W_MU3, W_T1)) || (rr = W.scal(wide_k::SC_MUL, W_MU4, W_MU2, W_T2)) ||
+          (rr = W.scal(wide_k::SC_ADD, W_T1, W_T2, W_T3, true)) || (rr = W.scal(wide_k::SC_DIV, W_T3, W_TAU, W_ETA)))
+        return rr;
+    }
+    {
+      // u = zeta q + eta (s + beta u);  z = (zeta r + eta z) - alpha u;  x = (x + alpha p) + z
+      Prog P(W);
+      const int ze = P.scalar(W_ZETA), et = P.scalar(W_ETA), be = P.scalar(W_BETA), al = P.scalar(W_ALPHA);
+      P.in(q, 0).in(sv, 1).in(u, 2).in(r, 3).in(z, 4).in(*x, 5).in(p, 6);
+      P.op(wide_k::PO_MUL, 7, be, 2).op(wide_k::PO_ADD, 7, 1, 7).op(wide_k::PO_MUL, 7, et, 7)
+          .op(wide_k::PO_MUL, 1, ze, 0).op(wide_k::PO_ADD, 2, 1, 7)      // u (reg 2)
+          .op(wide_k::PO_MUL, 7, ze, 3).op(wide_k::PO_MUL, 1, et, 4).op(wide_k::PO_ADD, 7, 7, 1)
+          .op(wide_k::PO_MUL, 1, al, 2).op(wide_k::PO_SUB, 4, 7, 1)      // z (reg 4)
+          .op(wide_k::PO_MUL, 7, al, 6).op(wide_k::PO_ADD, 7, 5, 7).op(wide_k::PO_ADD, 5, 7, 4);  // x (reg 5)
+      P.out(2, u).out(4, z).out(5, *x);
+      if ((rr = P.run())) return rr;
+      // r = (t - eta y) - zeta v
+      Prog R(W);
+      const int ze2 = R.scalar(W_ZETA), et2 = R.scalar(W_ETA);
+      R.in(t, 0).in(y, 1).in(v, 2);
+      R.op(wide_k::PO_MUL, 3, et2, 1).op(wide_k::PO_SUB, 3, 0, 3).op(wide_k::PO_MUL, 4, ze2, 2)
+          .op(wide_k::PO_SUB, 3, 3, 4).out(3, r);
+      if ((rr = R.run())) return rr;
+    }
+    if ((rr = W.dot(r, r, W_Q))) return rr;
+    bool stop = false;
+    if ((rr = wide_after(W, o, i, info, &stop))) return rr;
+    if (stop) break;
+    if ((rr = W.is_zero(W_ZETA, &zf))) return rr;
+    if (zf) {
+      info->status = MP_BREAKDOWN_ZETA;
+      break;
+    }
+    if ((rr = W.copy_slot(W_RHO, W_RHO_OLD)) || (rr = W.copy_slot(W_ALPHA, W_ALPHA_OLD)) ||
+        (rr = W.copy_slot(W_ZETA, W_ZETA_OLD)))
+      return rr;
+  }
+  return final_res(W, info);
+}
 
 int wide_bicg(int L, const WideOp& op, const WideOp& opT, const mp_vec* b, mp_vec* x,
               const mp_solve_opts* o, mp_solve_info* info, uint32_t* status, hipStream_t s) {

@@ -28,8 +28,9 @@ int wide_axpy(int L, int kind, const mp_vec& alpha, const mp_vec& x, const mp_ve
 // transposed values: dst[k] = src[perm[k]] (L limbs per element)
 int wide_gather(int L, const int32_t* perm, int64_t nnz, const mp_vec& src, uint32_t* dst_limb,
                 int32_t* dst_hdr, hipStream_t s);
-// BiCG (Fig. 5 left, K = I) for wide precisions, driven from the host (one synchronisation per
-// inner product that decides a branch)
+// BiCG (Fig. 5 left, K = I), GPBiCG (Fig. 5 right), CGS and BiCGSTAB for wide precisions, driven
+// from the host (one synchronisation per inner product that decides a branch); each performs the
+// operations of its fixed-width counterpart in the same order
 struct WideOp {
   int64_t n_out;
   const int32_t* row_ptr;
@@ -38,5 +39,11 @@ struct WideOp {
 };
 int wide_bicg(int L, const WideOp& op, const WideOp& opT, const mp_vec* b, mp_vec* x,
               const mp_solve_opts* o, mp_solve_info* info, uint32_t* status, hipStream_t s);
+int wide_gpbicg(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+                mp_solve_info* info, uint32_t* status, hipStream_t s);
+int wide_cgs(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o, mp_solve_info* info,
+             uint32_t* status, hipStream_t s);
+int wide_bicgstab(int L, const WideOp& op, const mp_vec* b, mp_vec* x, const mp_solve_opts* o,
+                  mp_solve_info* info, uint32_t* status, hipStream_t s);
 
 }  // namespace mpapi

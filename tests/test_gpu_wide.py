@@ -1,14 +1,15 @@
 """The wide precisions (p = 2048, 4096, 8192: numbers spread over a wavefront's lanes) against the
 oracle, bit for bit: the sparse product in both modes and its transpose on edge-case rows, the
-exact inner product (including an exact cancellation), y + alpha x, decimal constants, and BiCG
-(every iterate, status and residual history; also the transposed system)."""
+exact inner product (including an exact cancellation), y + alpha x, decimal constants, and BiCG,
+GPBiCG, CGS and BiCGSTAB (every iterate, status and residual history; also the transposed system
+and the breakdown exits)."""
 from fractions import Fraction
 
 import numpy as np
 import pytest
 
 import synth
-from oracle import blas, codec, mpnum, spmv as ospmv
+from oracle import blas, codec, krylov, mpnum, spmv as ospmv
 from tests.test_gpu_solvers import rhs_ones, run_both
 from tests.test_gpu_spmv import edge_problem
 from tests.util import assert_bitwise, oracle_spmv_rows
@@ -85,17 +86,49 @@ def test_wide_bicg_matches_oracle(p, mode):
     assert info.status == 0
 
 
-def test_wide_bicg_transposed_limit_and_unsupported():
-    """A^T x = b at p = 2048 (iterates and history), the iteration limit (NC), and a method the
-    wide path does not provide, refused."""
-    M = lib()
+@pytest.mark.parametrize("solver", ["gpbicg", "cgs", "bicgstab"])
+@pytest.mark.parametrize("p", WIDE)
+@pytest.mark.parametrize("mode", [0, 1], ids=["seq", "exact"])
+def test_wide_product_type_methods_match_oracle(solver, p, mode):
+    """GPBiCG, CGS and BiCGSTAB on the 5 x 5 convection-diffusion operator, b = A * ones, to a
+    relative 1e-200: every iterate, the status and the residual history bit for bit."""
+    A_h, _ = synth.config2(p=p, m=5)
+    b_h, b_o = rhs_ones(A_h)
+    info, ref = run_both(solver, A_h, b_h, mode, maxit=80, rtol=(1, -200), atol=(0, 0), b_oracle=b_o)
+    assert info.status == 0
+
+
+@pytest.mark.parametrize("solver", ["bicg", "gpbicg", "cgs", "bicgstab"])
+def test_wide_transposed_and_limit(solver):
+    """A^T x = b at p = 2048 (iterates and history), and the iteration limit (NC)."""
     p = 2048
     A_h, _ = synth.config2(p=p, m=4)
     b_h = synth.mp_uniform(np.random.default_rng(5), A_h.n_rows, p)
-    run_both("bicg", A_h, b_h, 1, maxit=40, rtol=(1, -150), atol=(0, 0), transpose=True)
-    info, ref = run_both("bicg", A_h, b_h, 0, maxit=3, rtol=(1, -150), atol=(0, 0))
+    run_both(solver, A_h, b_h, 1, maxit=40, rtol=(1, -150), atol=(0, 0), transpose=True)
+    info, ref = run_both(solver, A_h, b_h, 0, maxit=3, rtol=(1, -150), atol=(0, 0))
     assert info.status == 1 and info.iters == 3
+
+
+def test_wide_breakdowns_zero_rhs_and_unsupported():
+    """The sigma breakdown on the 2 x 2 swap matrix, BiCGSTAB's omega = 0 exit on a singular
+    matrix, a zero right-hand side (converged after 0 iterations), and an entry point the wide
+    path does not provide (the ILU(0)-preconditioned BiCGSTAB), refused."""
+    M = lib()
+    p = 4096
+    one = synth.mp_from_ints([1, 1], p)
+    swap = synth.CSRHost(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), one)
+    for solver in ("bicg", "gpbicg", "cgs", "bicgstab"):
+        info, ref = run_both(solver, swap, synth.mp_from_ints([1, 0], p), 0, maxit=10)
+        assert info.status == krylov.BREAKDOWN_SIGMA and info.iters == 0
+    sing = synth.CSRHost(2, 2, np.array([0, 2, 2], np.int32), np.array([0, 1], np.int32), one)
+    info, ref = run_both("bicgstab", sing, synth.mp_from_ints([1, 1], p), 1, maxit=10)
+    assert info.status == krylov.BREAKDOWN_ZETA and info.iters == 1
+    A_h, _ = synth.config2(p=p, m=3)
+    z = synth.mp_zeros(A_h.n_rows, p)
+    for solver in ("gpbicg", "cgs", "bicgstab"):
+        info, ref = run_both(solver, A_h, z, 0, maxit=5)
+        assert info.status == krylov.CONVERGED and info.iters == 0
     A = M.CSRMatrix.from_host(A_h)
     with pytest.raises(M.MPError):
-        M.gpbicg(A, M.MPArray.from_host(b_h), maxit=3)
+        M.ILU0(A)
     M.mp_status(raise_on_error=False)
