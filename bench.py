@@ -53,7 +53,7 @@ PEAK_MAD_TOPS = 256 * 4 * 16 * 2.4e9 / 2 / 1e12
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("spmv_kernels.hpp", "solver_kernels.hpp", "mp_core.hpp", "mp_exact.hpp",
-                  "mp_scalar.hpp", "mp_group.hpp")
+                  "mp_scalar.hpp", "mp_group.hpp", "mp_window.hpp")
 WORKLOAD = ("power-law CSR n=500000 (row lengths mean 20, max 2000; 9932151 stored entries), "
             "values log-uniform 1e-8..1e8 with random sign, x uniform [-1,1], p=256; "
             "step = y = A x in SEQ mode + y = A x in EXACT mode")
@@ -96,15 +96,15 @@ def spmv_bytes(n_rows, n_cols, nnz, L):
 def spmv_symbol(plan, op, mode, L, fused=False):
     """The kernel symbol (rocprofv3's name without "void mp::" and the arguments) of the plan's
     variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation."""
-    rows, staged, srt, gmin = plan.variants()[(op, mode)]
+    rows, staged, srt, gmin, win = plan.variants()[(op, mode)]
     base = "spmv_exact_kernel" if mode else ("spmv_seq_sorted_kernel" if srt else "spmv_seq_kernel")
     return "%s<%d, %d, %s>" % (base, L, rows, "true" if fused else "false")
 
 
 def spmv_kernel_name(plan, op, mode, L, fused=False):
-    rows, staged, srt, gmin = plan.variants()[(op, mode)]
+    rows, staged, srt, gmin, win = plan.variants()[(op, mode)]
     return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "") + \
-        (" (rows of >= %d entries by lane groups)" % gmin if gmin else "")
+        (" (rows of >= %d entries by %s)" % (gmin, "windowed chains" if win else "lane groups") if gmin else "")
 
 
 def load_counters(kernel, workload="powerlaw"):

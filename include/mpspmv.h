@@ -239,6 +239,12 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
  * times faster; the other rows as before.  Same result bits. */
 #define MP_VARIANT_LANE_GROUPS 4
 #define MP_VARIANT_GROUP_MIN(n) ((n) << 8)
+/* With MP_VARIANT_LANE_GROUPS: those rows are summed instead by windowed chains, one wavefront
+ * per row: up to 64 consecutive steps of the chain are taken at once as an integer prefix sum
+ * of the products rounded onto the running sum's unit in the last place, exact while the sum
+ * stays in its binade; a step that leaves it (or rounds half-way) is taken alone.  Same result
+ * bits. */
+#define MP_VARIANT_WINDOWS 8
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
 int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
                         int flags);

@@ -1,0 +1,162 @@
+// Windowed SEQ chains: a long row's serial RN additions advanced up to 64 at a time by one
+// wavefront, with exactly the results of the one-at-a-time chain.
+//
+// Let the running sum be Y = (-1)^s M u with M in [2^(p-1), 2^p) and u = 2^(E - p) its unit in
+// the last place, and let the next product be t.  As long as the exact Y + t stays in Y's binade
+// and on Y's side of zero, RN(Y + t) is the multiple of u nearest to Y + t, which is
+// Y + RN_u(t): t rounded on its own to a multiple of u.  Over a run of steps that all stay in
+// the binade, the chain is therefore a plain integer sum, M_k = M + sum_{i <= k} r_i with
+// r_i = RN_u(t_i) / u, and integer sums can be formed in any order.  One round of the wavefront:
+//  * lane i rounds its product t_i onto the grid of u (one shift of its mantissa by E - e_i,
+//    round and sticky bits), giving r_i as an (L + 1)-word two's complement integer relative to
+//    Y's sign;
+//  * an inclusive prefix sum of the r_i over the lanes (DPP row shifts and row broadcasts, one
+//    multi-word addition per stage) gives every M_i = M + sum_{j <= i} r_j;
+//  * lane i's step is exact if 2^(p-1) < M_i < 2^p (the exact sum then lies strictly inside the
+//    binade, because it differs from M_i by less than half a unit) and no earlier step failed;
+//    steps whose product is zero add 0 and always pass;
+//  * the steps up to the first failing lane are committed at once (M taken from the lane before
+//    it), the failing step itself is done with the general RN addition, and the next round
+//    starts after it.
+// A step fails when its product lies above Y's binade, when it rounds half-way (ties to even
+// would depend on the parity of the running sum), or when the sum would leave the binade or
+// cross zero.  A zero running sum takes the next non-zero product as it is (RN(+0 + t) = t).
+// On the power-law workload about one step in 40 fails, so a round commits some 30 steps.
+#pragma once
+#include "mp_core.hpp"
+
+namespace mp {
+
+// A DPP move that reads 0 where the source lane is outside the row or the row is masked off.
+template <int CTRL, int ROWM>
+MPD uint32_t win_dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWM, 0xf, true);
+}
+
+// v += (v of another lane, by the DPP pattern CTRL) over N words with carries.
+template <int N, int CTRL, int ROWM>
+MPD void win_scan_stage(uint32_t (&v)[N]) {
+  uint32_t t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = win_dpp<CTRL, ROWM>(v[i]);
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = __builtin_addc(v[i], t[i], c, &c);
+}
+
+// Inclusive prefix sum of N-word integers (mod 2^(32 N)) over the 64 lanes, in lane order:
+// row shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of row 0 (2) into
+// row 1 (3), then lane 31 into rows 2 and 3.
+template <int N>
+MPD void win_scan(uint32_t (&v)[N]) {
+  win_scan_stage<N, 0x111, 0xf>(v);  // row_shr:1
+  win_scan_stage<N, 0x112, 0xf>(v);  // row_shr:2
+  win_scan_stage<N, 0x114, 0xf>(v);  // row_shr:4
+  win_scan_stage<N, 0x118, 0xf>(v);  // row_shr:8
+  win_scan_stage<N, 0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  win_scan_stage<N, 0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+}
+
+// r = (-1)^neg * RN(M / 2^d) as an (L + 1)-word two's complement integer, M an L-limb mantissa
+// (not zero), d >= 0; *tie when M / 2^d lies exactly half-way between two integers.  The shift
+// is of M * 2^32 (a guard word below), so the guard word's top bit is the round bit and its
+// other bits, with every bit shifted out below it, the sticky bits.
+template <int L>
+MPD void win_align_round(const uint32_t (&m)[L], uint32_t d, bool neg, uint32_t (&r)[L + 1], bool& tie) {
+  uint32_t w[L + 1];
+  w[0] = 0u;
+#pragma unroll
+  for (int i = 0; i < L; ++i) w[i + 1] = m[i];
+  const uint32_t q = min(d >> 5, (uint32_t)(L + 1));  // whole words
+  uint32_t lost = 0u;
+#pragma unroll
+  for (int k = 1; k <= L + 1; k <<= 1) {
+    const bool on = (q & (uint32_t)k) != 0u;
+    uint32_t out = 0u;
+#pragma unroll
+    for (int j = 0; j < k && j <= L; ++j) out |= w[j];
+    lost |= on ? out : 0u;
+#pragma unroll
+    for (int i = 0; i <= L; ++i) w[i] = on ? (i + k <= L ? w[i + k] : 0u) : w[i];
+  }
+  const uint32_t b = d & 31u;
+  lost |= w[0] & ((1u << b) - 1u);
+#pragma unroll
+  for (int i = 0; i < L; ++i) w[i] = __builtin_amdgcn_alignbit(w[i + 1], w[i], b);
+  w[L] >>= b;
+  const bool rnd = (w[0] >> 31) != 0u;
+  const bool sticky = ((w[0] << 1) | lost) != 0u;
+  tie = rnd && !sticky;
+  const uint32_t inc = (rnd && sticky) ? 1u : 0u;
+  // (-1)^neg (S + inc) = (S ^ mask) + (neg ? 1 - inc : inc), S = w[1 .. L]
+  const uint32_t mask = neg ? ~0u : 0u;
+  uint32_t c = neg ? 1u - inc : inc;
+#pragma unroll
+  for (int i = 0; i < L; ++i) r[i] = __builtin_addc(w[i + 1] ^ mask, 0u, c, &c);
+  r[L] = mask + c;
+}
+
+// One windowed chain over the products t_i held by the lanes (lane i: product i of the window),
+// steps i = start .. n - 1 in order, starting from the wave-uniform running sum y.  Every lane
+// must call it together; y comes back wave-uniform.
+template <int L>
+MPD void win_chain(Num<L>& y, const Num<L>& t, int start, int n, uint32_t& st) {
+  const int lane = (int)(threadIdx.x & 63u);
+  while (start < n) {
+    const bool act = lane >= start && lane < n;
+    if (is_zero(y)) {
+      // RN(+0 + t) = t, and a zero t leaves +0: the first non-zero product is taken as it is
+      const uint64_t nz = __ballot(act && !is_zero(t));
+      if (nz == 0ull) return;
+      const int f = __ffsll((unsigned long long)nz) - 1;
+#pragma unroll
+      for (int k = 0; k < L; ++k) y.m[k] = (uint32_t)__shfl((int)t.m[k], f, 64);
+      y.e = __shfl(t.e, f, 64);
+      y.s = (uint32_t)__shfl((int)t.s, f, 64);
+      start = f + 1;
+      continue;
+    }
+    // r_i relative to y's sign, the prefix sums, and the first step the window cannot take
+    uint32_t r[L + 1];
+    bool bad = false;
+    const bool live = act && !is_zero(t);
+    if (live && t.e > y.e) {
+      bad = true;
+#pragma unroll
+      for (int k = 0; k <= L; ++k) r[k] = 0u;
+    } else if (live) {
+      bool tie;
+      win_align_round<L>(t.m, (uint32_t)(y.e - t.e), t.s != y.s, r, tie);
+      bad = tie;
+    } else {
+#pragma unroll
+      for (int k = 0; k <= L; ++k) r[k] = 0u;
+    }
+    win_scan<L + 1>(r);
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) r[k] = __builtin_addc(r[k], y.m[k], c, &c);
+    r[L] += c;
+    uint32_t below = 0u;
+#pragma unroll
+    for (int k = 0; k < L - 1; ++k) below |= r[k];
+    const bool inside = r[L] == 0u && (r[L - 1] >> 31) != 0u && (r[L - 1] != 0x80000000u || below != 0u);
+    const uint64_t fail = __ballot(act && (bad || !inside));
+    const int f = fail ? __ffsll((unsigned long long)fail) - 1 : n;
+    if (f > start) {  // steps start .. f - 1 hold: M from lane f - 1
+#pragma unroll
+      for (int k = 0; k < L; ++k) y.m[k] = (uint32_t)__shfl((int)r[k], f - 1, 64);
+    }
+    if (f >= n) return;
+    // step f by the general RN addition (t_f is not zero)
+    Num<L> tf;
+#pragma unroll
+    for (int k = 0; k < L; ++k) tf.m[k] = (uint32_t)__shfl((int)t.m[k], f, 64);
+    tf.e = __shfl(t.e, f, 64);
+    tf.s = (uint32_t)__shfl((int)t.s, f, 64);
+    y = add_rn<L>(y, tf, st);
+    start = f + 1;
+  }
+}
+
+}  // namespace mp

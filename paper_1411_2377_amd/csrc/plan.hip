@@ -139,7 +139,10 @@ SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
     v.x_len = op ? P->n_rows : P->n_cols;
   }
   if (P->sorted[op][mode]) v.rows = P->row_order[op];
-  if (v.rows && mode == MP_SEQ && P->group_min[op] > 0) v.n_long = rows_at_least(P, op, P->group_min[op]);
+  if (v.rows && mode == MP_SEQ && P->group_min[op] > 0) {
+    v.n_long = rows_at_least(P, op, P->group_min[op]);
+    v.windows = P->windows[op];
+  }
   return v;
 }
 
@@ -342,11 +345,14 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     for (int mode = 0; mode < 2; ++mode) {
       float best = 0.f;
       int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0, pick_gmin = 0;
-      // lane groups for the longest rows: SEQ with sorted rows only, when a row is that long
+      bool pick_win = false;
+      // lane groups or windowed chains for the longest rows: SEQ with sorted rows only, when a
+      // row is that long
       const int maxlen = P->order_len[op].empty() ? 0 : P->order_len[op][0];
-      for (int gi = 0; gi < 3; ++gi)
+      for (int gi = 0; gi < 5; ++gi)
       for (int flags = 0; flags < 4; ++flags) {
-        const int gmin = gi == 0 ? 0 : (gi == 1 ? 128 : 512);
+        const int gmin = gi == 0 ? 0 : ((gi & 1) ? 128 : 512);
+        const bool win = gi >= 3;
         if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin || P->L > 16)) continue;
         for (int rpw : {16, 32, 64}) {
           SpmvVariant var;
@@ -357,6 +363,7 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
           }
           if (flags & MP_VARIANT_SORTED_ROWS) var.rows = P->row_order[op];
           if (gmin) var.n_long = rows_at_least(P, op, gmin);
+          var.windows = win;
           int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
                                nullptr, &var);
           if (rr) return rr;
@@ -374,13 +381,17 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
             pick = rpw;
             pick_flags = flags;
             pick_gmin = gmin;
+            pick_win = win;
           }
         }
       }
       P->rpw[op][mode] = pick;
       P->stage[op][mode] = (pick_flags & MP_VARIANT_STAGE_X) != 0;
       P->sorted[op][mode] = (pick_flags & MP_VARIANT_SORTED_ROWS) != 0;
-      if (mode == MP_SEQ) P->group_min[op] = pick_gmin;
+      if (mode == MP_SEQ) {
+        P->group_min[op] = pick_gmin;
+        P->windows[op] = pick_win;
+      }
     }
   }
   return MPS_OK;
@@ -440,7 +451,8 @@ int mp_plan_tune_cached(mp_plan* plan, const mp_csr* A, int reps, const char* ca
       int op, mode, rv, fl;
       if (sscanf(line, "%llx %d %d %d %d", &k, &op, &mode, &rv, &fl) != 5 || k != key) continue;
       if (op < 0 || op > 1 || mode < 0 || mode > 1 || (rv != 0 && !valid_rows_per_block(rv)) ||
-          (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS | MP_VARIANT_LANE_GROUPS | ~0xff)))
+          (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS | MP_VARIANT_LANE_GROUPS | MP_VARIANT_WINDOWS |
+                  ~0xff)))
         continue;
       rpw[op][mode] = rv;
       flags[op][mode] = fl;
@@ -531,7 +543,9 @@ int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int ro
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if (rows_per_block != 0 && !valid_rows_per_block(rows_per_block))
     return fail(MPS_EINVAL, "rows per block must be 0, 16, 32 or 64");
-  if (flags < 0 || (flags & 0xf8)) return fail(MPS_EINVAL, "unknown variant flags");
+  if (flags < 0 || (flags & 0xf0)) return fail(MPS_EINVAL, "unknown variant flags");
+  if ((flags & MP_VARIANT_WINDOWS) && !(flags & MP_VARIANT_LANE_GROUPS))
+    return fail(MPS_EINVAL, "MP_VARIANT_WINDOWS needs MP_VARIANT_LANE_GROUPS and a minimum row length");
   const int gmin = (flags & MP_VARIANT_LANE_GROUPS) ? (flags >> 8) : 0;
   if ((flags & MP_VARIANT_LANE_GROUPS) &&
       (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || gmin < 1))
@@ -543,7 +557,10 @@ int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int ro
   plan->rpw[op][mode] = rows_per_block;
   plan->stage[op][mode] = (flags & MP_VARIANT_STAGE_X) != 0;
   plan->sorted[op][mode] = (flags & MP_VARIANT_SORTED_ROWS) != 0;
-  if (mode == MP_SEQ) plan->group_min[op] = gmin;
+  if (mode == MP_SEQ) {
+    plan->group_min[op] = gmin;
+    plan->windows[op] = gmin > 0 && (flags & MP_VARIANT_WINDOWS) != 0;
+  }
   return MPS_OK;
 }
 
@@ -557,7 +574,8 @@ int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_blo
   const bool srt = plan->sorted[op][mode] && plan->row_order[op];
   const int gmin = (srt && mode == MP_SEQ) ? plan->group_min[op] : 0;
   *flags = ((plan->stage[op][mode] && plan->x_rec) ? MP_VARIANT_STAGE_X : 0) |
-           (srt ? MP_VARIANT_SORTED_ROWS : 0) | (gmin ? (MP_VARIANT_LANE_GROUPS | (gmin << 8)) : 0);
+           (srt ? MP_VARIANT_SORTED_ROWS : 0) | (gmin ? (MP_VARIANT_LANE_GROUPS | (gmin << 8)) : 0) |
+           ((gmin && plan->windows[op]) ? MP_VARIANT_WINDOWS : 0);
   return MPS_OK;
 }
 

@@ -20,6 +20,7 @@
 #include "mp_core.hpp"
 #include "mp_exact.hpp"
 #include "mp_group.hpp"
+#include "mp_window.hpp"
 #include "solver_kernels.hpp"
 
 namespace mp {
@@ -78,6 +79,7 @@ struct SpmvArgs {
   // by lane groups in the first long_blocks blocks; the other blocks take the rows after them
   int64_t n_long;
   int64_t long_blocks;
+  int window;  // those rows by windowed chains (four rows per block, one per wavefront)
   // > 0: a dense row-major matrix with that many columns (row i holds entries i * dense_cols ...,
   // entry k sits in column k mod dense_cols); row_ptr and col_idx are then not read
   int32_t dense_cols;
@@ -477,12 +479,55 @@ __device__ void spmv_seq_group_rows(const SpmvArgs& A, int64_t blk, uint32_t& st
   }
 }
 
+// SEQ, the long rows at the head of the row order, by windowed chains (mp_window.hpp): four rows
+// per block, one per wavefront.  A wavefront forms its row's rounded products 64 at a time (lane
+// i: entry i of the chunk; the next chunk's loads are issued before the chain runs) and advances
+// the row's chain over them in windows.
+template <int L>
+__device__ void spmv_seq_window_rows(const SpmvArgs& A, int64_t blk, uint32_t& st) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t ri = blk * 4 + wv;
+  if (ri >= A.n_long) return;  // the whole wavefront
+  const int64_t row = A.rows[ri];
+  const int rs = row_begin(A, row), len = row_end(A, row) - rs;
+  Num<L> y;
+  set_zero(y, 0u);
+  int64_t k[1];
+  bool ok[1];
+  ok[0] = lane < len;
+  k[0] = ok[0] ? (int64_t)rs + lane : 0;
+  EntryLoad<L, 1> E;
+  load_entries<L, 1>(E, A, A.x_limb, A.x_hdr, k, ok);
+  for (int c0 = 0; c0 < len; c0 += 64) {
+    Num<L> t;
+    const int32_t ha = E.ha[0], hx = E.hx[0];
+    if (!ok[0] || hdr_is_zero(ha) || hdr_is_zero(hx)) {
+      set_zero(t, (uint32_t)(ha ^ hx) & 1u);
+    } else {
+      uint32_t pr[2 * L];
+      mul_full<L>(E.am[0], E.xm[0], pr);
+      round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, t, st);
+    }
+    const int c1 = c0 + 64;
+    if (c1 < len) {
+      ok[0] = c1 + lane < len;
+      k[0] = ok[0] ? (int64_t)rs + c1 + lane : 0;
+      load_entries<L, 1>(E, A, A.x_limb, A.x_hdr, k, ok);
+    }
+    win_chain<L>(y, t, 0, min(64, len - c0), st);
+  }
+  if (lane == 0) store<L>(y, A.y_limb, A.y_hdr, A.y_ld, row);
+}
+
 template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   if constexpr (!FUSE && L <= 16) {
     if ((int64_t)blockIdx.x < A.long_blocks) {
       uint32_t st = 0;
-      spmv_seq_group_rows<L>(A, blockIdx.x, st);
+      if (A.window)
+        spmv_seq_window_rows<L>(A, blockIdx.x, st);
+      else
+        spmv_seq_group_rows<L>(A, blockIdx.x, st);
       if (st) atomicOr(A.status, st);
       return;
     }
@@ -609,34 +654,55 @@ MPD int ring_slot(int32_t d) {
   return m < 0 ? m + R : m;
 }
 
+// A product P * 2^(e - 64L) goes into the ring at digit (e - 1) >> 5 as P * 2^((e - 1) mod 32 + 1)
+// in 2L + 1 digits: one funnel shift per digit by 31 - ((e - 1) mod 32), with no separate case
+// for a shift of zero (an exponent that is a multiple of 32 anchors the product a digit lower).
+MPD int32_t ring_digit(int32_t e) { return (e - 1) >> 5; }
+
 // Ring digits needed by products with exponents in [lo, hi].
 template <int L>
-MPD int ring_span(int32_t lo, int32_t hi) { return (hi >> 5) - (lo >> 5) + 2 * L + 2; }
+MPD int ring_span(int32_t lo, int32_t hi) { return ring_digit(hi) - ring_digit(lo) + 2 * L + 2; }
 
-// Add (-1)^s * P * 2^(e mod 32) at ring digit e >> 5 (slots ws apart) with LDS atomics.  A
-// negative product X = sum_j x_j 2^(32 j) (D = 2L + 1 digits) is added as its digits'
-// complements plus one, less one a digit above it: -X = sum_j (2^32 - 1 - x_j) 2^(32 j) + 1
-// - 2^(32 D).  Every digit's add is then a 32-bit value with no negation, and every lane issues
+// Slots of a row's ring: R ring digits, then 2L + 2 overflow slots, so that a product's digits
+// land in consecutive slots without wrapping (one base address, immediate offsets).  Overflow
+// slot R + u stands for ring digit u; ring_fold adds it back before the row is read.
+template <int L, int R>
+constexpr int ring_slots() { return R + 2 * L + 2; }
+
+// Add (-1)^s * P * 2^((e - 1) mod 32 + 1) at ring digit ring_digit(e) (slots WS apart) with LDS
+// atomics.  A negative product X = sum_j x_j 2^(32 j) (D = 2L + 1 digits) is added as its
+// digits' complements plus one, less one a digit above it: -X = sum_j (2^32 - 1 - x_j) 2^(32 j)
+// + 1 - 2^(32 D).  Every digit's add is then a 32-bit value with no negation, and every lane issues
 // the same adds (no per-digit branch); only negative products add the extra digit.  The row's
 // window counts that digit (its headroom digit above the widest product).
-template <int L, int R>
-MPD void ring_add(int64_t* win, int ws, const uint32_t (&P)[2 * L], uint32_t s, int32_t e) {
+template <int L, int R, int WS>
+MPD void ring_add(int64_t* win, const uint32_t (&P)[2 * L], uint32_t s, int32_t e) {
+  static_assert(2 * L + 2 <= R, "overflow slots fold onto distinct ring digits");
+  const uint32_t sh = 31u - ((uint32_t)(e - 1) & 31u);
   uint32_t sp[2 * L + 1];
-  shift_product<L>(P, (uint32_t)e & 31u, sp);
-  const uint32_t mask = s ? ~0u : 0u;
-  int slot = ring_slot<R>(e >> 5);
+  sp[0] = fshr(P[0], 0u, sh);
 #pragma unroll
-  for (int j = 0; j <= 2 * L; ++j) {
-    const uint64_t v = (uint64_t)(sp[j] ^ mask) + ((j == 0) ? (uint64_t)(s & 1u) : 0ull);
-    atomicAdd((unsigned long long*)&win[slot * ws], (unsigned long long)v);
-    slot = (slot == R - 1) ? 0 : slot + 1;
-  }
-  if (s) atomicAdd((unsigned long long*)&win[slot * ws], ~0ull);
+  for (int j = 1; j < 2 * L; ++j) sp[j] = fshr(P[j], P[j - 1], sh);
+  sp[2 * L] = fshr(0u, P[2 * L - 1], sh);
+  const uint32_t mask = s ? ~0u : 0u;
+  unsigned long long* const w = reinterpret_cast<unsigned long long*>(win + ring_slot<R>(ring_digit(e)) * WS);
+  atomicAdd(&w[0], (unsigned long long)(sp[0] ^ mask) + (unsigned long long)(s & 1u));
+#pragma unroll
+  for (int j = 1; j <= 2 * L; ++j) atomicAdd(&w[j * WS], (unsigned long long)(sp[j] ^ mask));
+  if (s) atomicAdd(&w[(2 * L + 1) * WS], ~0ull);
+}
+
+// Fold a row's overflow slots onto its ring digits (after every add has landed).
+template <int L, int R, int WS>
+MPD void ring_fold(int64_t* win) {
+#pragma unroll
+  for (int u = 0; u < 2 * L + 2; ++u) win[u * WS] += win[(R + u) * WS];
 }
 
 template <int L, int RPW, bool FUSE>
 __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
   constexpr int R = window_fast_digits<L>();  // ring digits per row
+  constexpr int RS = ring_slots<L, R>();        // with the overflow slots
   // digits of the block-shared exact window: the same for every variant, so that every variant
   // accepts the same rows
   constexpr int WB = R * 16;
@@ -647,7 +713,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
   __shared__ int32_t s_cp[65];          // compact (short-row) entry prefix
   __shared__ uint8_t s_row[kChunk];     // row of each compact entry of the chunk
   __shared__ int32_t s_lo[RPW], s_hi[RPW];
-  __shared__ int64_t s_win[R * RPW];    // ring slot d of row r at [d * RPW + r]
+  __shared__ int64_t s_win[RS * RPW];   // ring slot d of row r at [d * RPW + r]
 
   SpmvBlock B;
   if (!spmv_block<RPW>(A, B)) return;
@@ -662,7 +728,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
   const int rs = has_row ? row_begin(A, row) : 0;
   const int re = has_row ? row_end(A, row) : 0;
   const bool is_short = has_row && re - rs <= kShortRow;
-  for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
+  for (int i = lane; i < RS * RPW; i += 64) s_win[i] = 0;
   if (lane < RPW) {
     s_rs[lane] = rs;
     s_lo[lane] = INT32_MAX;
@@ -697,7 +763,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
       atomicMax(&s_hi[rw[i]], e);
       uint32_t pr[2 * L];
       mul_full<L>(E.am[i], E.xm[i], pr);
-      ring_add<L, R>(s_win + rw[i], RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
+      ring_add<L, R, RPW>(s_win + rw[i], pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
     }
     __syncthreads();
   }
@@ -712,8 +778,9 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
     if (lo == INT32_MAX) {
       set_zero(y, 0);
     } else if (ring_span<L>(lo, hi) <= R) {
-      y = window_finalize_map<L>(s_win + lane, RingMap<R>{RPW, ring_slot<R>(lo >> 5)},
-                                 ring_span<L>(lo, hi), 32 * (int64_t)(lo >> 5) - 64 * L, st);
+      ring_fold<L, R, RPW>(s_win + lane);
+      y = window_finalize_map<L>(s_win + lane, RingMap<R>{RPW, ring_slot<R>(ring_digit(lo))},
+                                 ring_span<L>(lo, hi), 32 * (int64_t)ring_digit(lo) - 64 * L, st);
     } else {
       wide = true;
     }
@@ -733,7 +800,7 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
     bool ring_ok = false;
     if (!known) {
       // lane rings: lane l adds into column l mod RPW
-      for (int i = lane; i < R * RPW; i += 64) s_win[i] = 0;
+      for (int i = lane; i < RS * RPW; i += 64) s_win[i] = 0;
       __syncthreads();
       int32_t llo = INT32_MAX, lhi = INT32_MIN;
       for (int k0 = o_rs; k0 < o_re; k0 += kChunk) {
@@ -754,21 +821,23 @@ __global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
           lhi = max(lhi, e);
           uint32_t pr[2 * L];
           mul_full<L>(E.am[i], E.xm[i], pr);
-          ring_add<L, R>(s_win + (lane % RPW), RPW, pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
+          ring_add<L, R, RPW>(s_win + (lane % RPW), pr, (uint32_t)(E.ha[i] ^ E.hx[i]) & 1u, e);
         }
       }
       emin = wave_min32(llo);
       emax = wave_max32(lhi);
       __syncthreads();
+      if (lane < RPW) ring_fold<L, R, RPW>(s_win + lane);
+      __syncthreads();
       if (emax >= emin && ring_span<L>(emin, emax) <= min(R, 63)) {  // a digit per lane
         ring_ok = true;
         int64_t dg = 0;
         if (lane < ring_span<L>(emin, emax)) {
-          const int64_t* slot = s_win + ring_slot<R>((emin >> 5) + lane) * RPW;
+          const int64_t* slot = s_win + ring_slot<R>(ring_digit(emin) + lane) * RPW;
 #pragma unroll
           for (int c = 0; c < RPW; ++c) dg += slot[c];
         }
-        yr = wave_round<L>(dg, 32 * (int64_t)(emin >> 5) - 64 * L, st);
+        yr = wave_round<L>(dg, 32 * (int64_t)ring_digit(emin) - 64 * L, st);
       }
     }
     if (!ring_ok && emax >= emin) {
