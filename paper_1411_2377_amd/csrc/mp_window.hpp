@@ -18,10 +18,12 @@
 //  * the steps up to the first failing lane are committed at once (M taken from the lane before
 //    it), the failing step itself is done with the general RN addition, and the next round
 //    starts after it.
-// A step fails when its product lies above Y's binade, when it rounds half-way (ties to even
-// would depend on the parity of the running sum), or when the sum would leave the binade or
-// cross zero.  A zero running sum takes the next non-zero product as it is (RN(+0 + t) = t).
-// On the power-law workload about one step in 40 fails, so a round commits some 30 steps.
+// A step fails when its product lies above Y's binade or when the sum would leave the binade or
+// cross zero.  A product that rounds half-way onto the grid is taken rounded towards zero in
+// the prefix sum, then, in lane order, the sums from that step on move one unit when ties to
+// even ask for it (the parity of that step's sum is known once the steps before it are).  A zero
+// running sum takes the next non-zero product as it is (RN(+0 + t) = t).  On the power-law
+// workload about one step in 80 fails, so a round commits some 40 steps.
 #pragma once
 #include "mp_core.hpp"
 
@@ -96,6 +98,15 @@ MPD void win_align_round(const uint32_t (&m)[L], uint32_t d, bool neg, uint32_t 
   r[L] = mask + c;
 }
 
+// 2^(p-1) < M < 2^p for an (L + 1)-word M: the step's exact sum lies inside the binade.
+template <int L>
+MPD bool win_inside(const uint32_t (&m)[L + 1]) {
+  uint32_t below = 0u;
+#pragma unroll
+  for (int k = 0; k < L - 1; ++k) below |= m[k];
+  return m[L] == 0u && (m[L - 1] >> 31) != 0u && (m[L - 1] != 0x80000000u || below != 0u);
+}
+
 // One windowed chain over the products t_i held by the lanes (lane i: product i of the window),
 // steps i = start .. n - 1 in order, starting from the wave-uniform running sum y.  Every lane
 // must call it together; y comes back wave-uniform.
@@ -116,18 +127,18 @@ MPD void win_chain(Num<L>& y, const Num<L>& t, int start, int n, uint32_t& st) {
       start = f + 1;
       continue;
     }
-    // r_i relative to y's sign, the prefix sums, and the first step the window cannot take
+    // r_i relative to y's sign (a half-way step rounded towards zero for now), the prefix sums,
+    // and the first step the window cannot take
     uint32_t r[L + 1];
-    bool bad = false;
+    bool big = false, tie = false;
     const bool live = act && !is_zero(t);
+    const bool neg = t.s != y.s;
     if (live && t.e > y.e) {
-      bad = true;
+      big = true;
 #pragma unroll
       for (int k = 0; k <= L; ++k) r[k] = 0u;
     } else if (live) {
-      bool tie;
-      win_align_round<L>(t.m, (uint32_t)(y.e - t.e), t.s != y.s, r, tie);
-      bad = tie;
+      win_align_round<L>(t.m, (uint32_t)(y.e - t.e), neg, r, tie);
     } else {
 #pragma unroll
       for (int k = 0; k <= L; ++k) r[k] = 0u;
@@ -137,11 +148,25 @@ MPD void win_chain(Num<L>& y, const Num<L>& t, int start, int n, uint32_t& st) {
 #pragma unroll
     for (int k = 0; k < L; ++k) r[k] = __builtin_addc(r[k], y.m[k], c, &c);
     r[L] += c;
-    uint32_t below = 0u;
+    uint64_t fail = __ballot(act && (big || !win_inside<L>(r)));
+    // Half-way steps before the first failure, in order: the exact sum lies half a unit beyond
+    // M_i on the step's side, and ties to even keep M_i when it is even, else move it one unit
+    // further; the sums after it move with it.
+    uint64_t ties = __ballot(act && tie);
+    while (ties) {
+      const int g = __ffsll((unsigned long long)ties) - 1;
+      if (fail && g >= __ffsll((unsigned long long)fail) - 1) break;
+      ties &= ties - 1;
+      if ((__shfl((int)r[0], g, 64) & 1) == 0) continue;
+      const bool gneg = __shfl(neg ? 1 : 0, g, 64) != 0;
+      const bool on = lane >= g;
+      const uint32_t ext = (on && gneg) ? ~0u : 0u;  // -1 or +1 over L + 1 words
+      uint32_t cc = 0;
+      r[0] = __builtin_addc(r[0], on ? (gneg ? ~0u : 1u) : 0u, cc, &cc);
 #pragma unroll
-    for (int k = 0; k < L - 1; ++k) below |= r[k];
-    const bool inside = r[L] == 0u && (r[L - 1] >> 31) != 0u && (r[L - 1] != 0x80000000u || below != 0u);
-    const uint64_t fail = __ballot(act && (bad || !inside));
+      for (int k = 1; k <= L; ++k) r[k] = __builtin_addc(r[k], ext, cc, &cc);
+      fail = __ballot(act && (big || !win_inside<L>(r)));
+    }
     const int f = fail ? __ffsll((unsigned long long)fail) - 1 : n;
     if (f > start) {  // steps start .. f - 1 hold: M from lane f - 1
 #pragma unroll

@@ -349,9 +349,12 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
       // lane groups or windowed chains for the longest rows: SEQ with sorted rows only, when a
       // row is that long
       const int maxlen = P->order_len[op].empty() ? 0 : P->order_len[op][0];
-      for (int gi = 0; gi < 5; ++gi)
+      // (minimum row length, windowed chains): none; lane groups from 128 or 512 entries;
+      // windowed chains from 128, 256 or 512
+      static const int kLongMin[6] = {0, 128, 512, 128, 256, 512};
+      for (int gi = 0; gi < 6; ++gi)
       for (int flags = 0; flags < 4; ++flags) {
-        const int gmin = gi == 0 ? 0 : ((gi & 1) ? 128 : 512);
+        const int gmin = kLongMin[gi];
         const bool win = gi >= 3;
         if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin || P->L > 16)) continue;
         for (int rpw : {16, 32, 64}) {
