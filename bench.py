@@ -97,8 +97,11 @@ def spmv_symbol(plan, op, mode, L, fused=False):
     """The kernel symbol (rocprofv3's name without "void mp::" and the arguments) of the plan's
     variant of product op (0: A, 1: A^T) in a mode; fused: the solvers' instantiation."""
     rows, staged, srt, gmin, win = plan.variants()[(op, mode)]
-    base = "spmv_exact_kernel" if mode else ("spmv_seq_sorted_kernel" if srt else "spmv_seq_kernel")
-    return "%s<%d, %d, %s>" % (base, L, rows, "true" if fused else "false")
+    tf = lambda b: "true" if b else "false"
+    if mode == 0 and srt:  # the sorted kernel is instantiated apart for lane groups
+        return "spmv_seq_sorted_kernel<%d, %d, %s, %s>" % (L, rows, tf(fused), tf(gmin and not win and not fused))
+    base = "spmv_exact_kernel" if mode else "spmv_seq_kernel"
+    return "%s<%d, %d, %s>" % (base, L, rows, tf(fused))
 
 
 def spmv_kernel_name(plan, op, mode, L, fused=False):

@@ -29,9 +29,17 @@ struct SpmvFuse {
 template <int L, int RPW, bool FUSE>
 void launch_spmv_rpw(const mp::SpmvArgs& a, int mode, hipStream_t s) {
   const unsigned grid = (unsigned)(a.long_blocks + (a.n_rows - a.n_long + RPW - 1) / RPW) * (unsigned)a.nrhs;
-  if (mode == MP_SEQ && (a.rows || a.pipe))  // the four-wave pipelined kernel
-    MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW, FUSE>), dim3(grid), dim3(256), 0, s, a);
-  else if (mode == MP_SEQ)
+  if (mode == MP_SEQ && (a.rows || a.pipe)) {  // the four-wave pipelined kernel
+    bool groups = false;  // the lane-group instantiation (its LDS buffers) only where it is used
+    if constexpr (!FUSE && L <= 16) groups = a.long_blocks > 0 && !a.window;
+    if constexpr (!FUSE && L <= 16) {
+      if (groups) {
+        MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW, FUSE, true>), dim3(grid), dim3(256), 0, s, a);
+        return;
+      }
+    }
+    MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_seq_sorted_kernel<L, RPW, FUSE, false>), dim3(grid), dim3(256), 0, s, a);
+  } else if (mode == MP_SEQ)
     MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_seq_kernel<L, RPW, FUSE>), dim3(grid), dim3(64), 0, s, a);
   else
     MPS_LAUNCH_MAIN(!a.x_rec, true, (mp::spmv_exact_kernel<L, RPW, FUSE>), dim3(grid), dim3(64), 0, s, a);

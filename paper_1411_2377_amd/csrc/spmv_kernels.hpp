@@ -519,15 +519,17 @@ __device__ void spmv_seq_window_rows(const SpmvArgs& A, int64_t blk, uint32_t& s
   if (lane == 0) store<L>(y, A.y_limb, A.y_hdr, A.y_ld, row);
 }
 
-template <int L, int RPW, bool FUSE>
+// GROUPS: the long rows are summed by lane groups (whose LDS buffers only this instantiation
+// holds), else by windowed chains.
+template <int L, int RPW, bool FUSE, bool GROUPS>
 __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
   if constexpr (!FUSE && L <= 16) {
     if ((int64_t)blockIdx.x < A.long_blocks) {
       uint32_t st = 0;
-      if (A.window)
-        spmv_seq_window_rows<L>(A, blockIdx.x, st);
-      else
+      if constexpr (GROUPS)
         spmv_seq_group_rows<L>(A, blockIdx.x, st);
+      else
+        spmv_seq_window_rows<L>(A, blockIdx.x, st);
       if (st) atomicOr(A.status, st);
       return;
     }
