@@ -107,7 +107,8 @@ def spmv_symbol(plan, op, mode, L, fused=False):
 def spmv_kernel_name(plan, op, mode, L, fused=False):
     rows, staged, srt, gmin, win = plan.variants()[(op, mode)]
     return spmv_symbol(plan, op, mode, L, fused) + (" (x staged)" if staged else "") + \
-        (" (rows of >= %d entries by %s)" % (gmin, "windowed chains" if win else "lane groups") if gmin else "")
+        (" (rows of >= %d entries by %s)" % (gmin, ("lane groups", "windowed chains", "windowed chains, four rows per wavefront")[win])
+         if gmin else "")
 
 
 def load_counters(kernel, workload="powerlaw"):

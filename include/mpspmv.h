@@ -245,6 +245,10 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
  * stays in its binade; a step that leaves it (or rounds half-way) is taken alone.  Same result
  * bits. */
 #define MP_VARIANT_WINDOWS 8
+/* With MP_VARIANT_WINDOWS: the rows of at least n but fewer than 8n entries four per wavefront,
+ * one per row of 16 lanes (windows of up to 16 steps); the rows of 8n or more entries one per
+ * wavefront as before.  Same result bits. */
+#define MP_VARIANT_SEGMENTS 16
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
 int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
                         int flags);

@@ -100,27 +100,29 @@ class Plan:
         return self.variants()
 
     def set_variant(self, op, mode, rows=0, stage_x=False, sorted_rows=False, group_min=0,
-                    windows=False):
+                    windows=False, segments=False):
         """Force a kernel variant: op 0 = A, 1 = A^T; rows in (0, 16, 32, 64), 0 = by shape;
         stage_x: gather x from staged records; sorted_rows: blocks take rows by decreasing
         length; group_min (SEQ with sorted rows): rows with at least that many entries are
-        summed by lane groups (0: none), or with windows by windowed chains."""
+        summed by lane groups (0: none), or with windows by windowed chains (a row per
+        wavefront, or with segments four rows per wavefront)."""
         d = self.A.desc()
         flags = (1 if stage_x else 0) | (2 if sorted_rows else 0)
         if group_min:
-            flags |= 4 | (int(group_min) << 8) | (8 if windows else 0)
+            flags |= 4 | (int(group_min) << 8) | (8 if windows or segments else 0) | (16 if segments else 0)
         check(_lib.LIB.mp_plan_set_variant(self._h, ctypes.byref(d), int(op), int(mode), int(rows), flags))
 
     def variants(self):
-        """{(op, mode): (rows per block, stage_x, sorted_rows, group_min, windows)} in effect."""
+        """{(op, mode): (rows per block, stage_x, sorted_rows, group_min, windows)} in effect;
+        windows is 0, 1 (a row per wavefront) or 2 (four rows per wavefront)."""
         out = {}
         for op in (0, 1):
             for mode in (MP_SEQ, MP_EXACT):
                 v, fl = ctypes.c_int(0), ctypes.c_int(0)
                 check(_lib.LIB.mp_plan_get_variant(self._h, op, mode, ctypes.byref(v), ctypes.byref(fl)))
                 gmin = (fl.value >> 8) if fl.value & 4 else 0
-                out[(op, mode)] = (v.value, bool(fl.value & 1), bool(fl.value & 2), gmin,
-                                   bool(gmin and fl.value & 8))
+                win = (2 if fl.value & 16 else 1) if (gmin and fl.value & 8) else 0
+                out[(op, mode)] = (v.value, bool(fl.value & 1), bool(fl.value & 2), gmin, win)
         return out
 
     def close(self):

@@ -208,6 +208,8 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   a.n_long = 0;
   a.long_blocks = 0;
   a.window = 0;
+  a.n_win = 0;
+  a.win_blocks = 0;
   a.dense_cols = dense_cols;
   a.wide_win = nullptr;
   a.wide_lock = nullptr;
@@ -220,10 +222,15 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
   }
   if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
       !batch->pair_of_tile && !done && L <= 16) {  // lane groups hold at most 16 limbs
-    const int rg = var->windows ? 4 : 64 / L;  // rows per block: one per wavefront, or per lane group
     a.n_long = std::min<int64_t>(var->n_long, n_rows);
-    a.long_blocks = (a.n_long + rg - 1) / rg;
-    a.window = var->windows ? 1 : 0;
+    a.window = var->windows;
+    if (var->windows) {  // four rows per block (one per wavefront), then sixteen (four per wavefront)
+      a.n_win = var->windows == 1 ? a.n_long : std::min<int64_t>(var->n_win, a.n_long);
+      a.win_blocks = (a.n_win + 3) / 4;
+      a.long_blocks = a.win_blocks + (a.n_long - a.n_win + 15) / 16;
+    } else {  // one row per lane group
+      a.long_blocks = (a.n_long + 64 / L - 1) / (64 / L);
+    }
   }
   if (var->rows && batch->nrhs != 1) return fail(MPS_EINVAL, "a row order takes one right-hand side");
   a.fd = mp::DotOut{};

@@ -115,7 +115,9 @@ struct SpmvVariant {
   const int32_t* rows = nullptr;
   bool pipe = false;  // SEQ: the four-wavefront pipelined kernel also without a row order
   int64_t n_long = 0;  // SEQ with a row order: its first n_long rows are summed by lane groups
-  bool windows = false;  // ... or, with windows, by windowed chains (one wavefront per row)
+  int windows = 0;  // ... or by windowed chains: 1 one row per wavefront; 2 the same for the
+                    // first n_win rows, four per wavefront for the others
+  int64_t n_win = 0;
   bool no_wide = false;  // EXACT: no global windows (rows wider than the LDS window raise kStWindow)
 };
 int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,

@@ -185,3 +185,134 @@ MPD void win_chain(Num<L>& y, const Num<L>& t, int start, int n, uint32_t& st) {
 }
 
 }  // namespace mp
+
+namespace mp {
+
+// ---- segmented windows: four chains per wavefront ----------------------------------------
+// The same rounds with each row of 16 lanes (a DPP row) carrying its own chain: lane j of row
+// g holds the g-th chain's product j, every lane holds its row's running sum, and the prefix
+// sums stop at the row's edge.  Rows whose steps are done, or that have none, stay idle.
+
+// Inclusive prefix sum of N-word integers within each row of 16 lanes.
+template <int N>
+MPD void win_scan16(uint32_t (&v)[N]) {
+  win_scan_stage<N, 0x111, 0xf>(v);  // row_shr:1
+  win_scan_stage<N, 0x112, 0xf>(v);  // row_shr:2
+  win_scan_stage<N, 0x114, 0xf>(v);  // row_shr:4
+  win_scan_stage<N, 0x118, 0xf>(v);  // row_shr:8
+}
+
+// The 16 bits of a wavefront mask that belong to this lane's row, as the low bits.
+MPD uint32_t seg_bits(uint64_t m) { return (uint32_t)(m >> (threadIdx.x & 48u)) & 0xffffu; }
+
+// Lowest set bit of each row's 16 bits of m.
+MPD uint64_t seg_lowest(uint64_t m) {
+  const uint32_t j = threadIdx.x & 15u;
+  const uint32_t b = seg_bits(m);
+  return __ballot(((b >> j) & 1u) != 0u && (b & ((1u << j) - 1u)) == 0u);
+}
+
+template <int L>
+MPD Num<L> seg_take(const Num<L>& t, int src) {
+  Num<L> o;
+#pragma unroll
+  for (int k = 0; k < L; ++k) o.m[k] = (uint32_t)__shfl((int)t.m[k], src, 64);
+  o.e = __shfl(t.e, src, 64);
+  o.s = (uint32_t)__shfl((int)t.s, src, 64);
+  return o;
+}
+
+// Every row's chain over its products t (lane j: product j), steps start .. n - 1 of the row
+// (n <= 16; start and n the same in all lanes of a row), from each row's running sum y.
+template <int L>
+MPD void win_chain_seg(Num<L>& y, const Num<L>& t, int n, uint32_t& st) {
+  const int lane = (int)(threadIdx.x & 63u), j = lane & 15, base = lane & 48;
+  int start = 0;
+  while (__ballot(start < n) != 0ull) {
+    // rows with a zero sum take their next non-zero product as it is
+    if (__ballot(start < n && is_zero(y)) != 0ull) {
+      const bool act = j >= start && j < n;
+      const uint32_t nz = seg_bits(__ballot(act && !is_zero(t)));
+      const bool zrow = start < n && is_zero(y);
+      const int f = nz ? __ffs(nz) - 1 : 16;
+      const Num<L> tf = seg_take<L>(t, base + min(f, 15));
+      if (zrow) {
+        if (f < n) {
+          y = tf;
+          start = f + 1;
+        } else {
+          start = n;
+        }
+      }
+    }
+    const bool work = start < n && !is_zero(y);
+    const bool act = work && j >= start && j < n;
+    uint32_t r[L + 1];
+    bool big = false, tie = false;
+    const bool live = act && !is_zero(t);
+    const bool neg = t.s != y.s;
+    if (live && t.e > y.e) {
+      big = true;
+#pragma unroll
+      for (int k = 0; k <= L; ++k) r[k] = 0u;
+    } else if (live) {
+      win_align_round<L>(t.m, (uint32_t)(y.e - t.e), neg, r, tie);
+    } else {
+#pragma unroll
+      for (int k = 0; k <= L; ++k) r[k] = 0u;
+    }
+    win_scan16<L + 1>(r);
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) r[k] = __builtin_addc(r[k], y.m[k], c, &c);
+    r[L] += c;
+    uint64_t fail = __ballot(act && (big || !win_inside<L>(r)));
+    // half-way steps before each row's first failure, in lane order (as in win_chain)
+    uint64_t ties = __ballot(act && tie);
+    while (ties) {
+      const uint64_t low = seg_lowest(ties);
+      const uint32_t fb = seg_bits(fail), gb = seg_bits(low);
+      const int f = fb ? __ffs(fb) - 1 : 16;
+      const int g = gb ? __ffs(gb) - 1 : 16;
+      const bool pend = g < f;  // this row has a half-way step to settle
+      const uint64_t pending = __ballot(pend);
+      if (pending == 0ull) break;
+      ties &= ~(low & pending);
+      const int src = base + min(g, 15);
+      const bool odd = (__shfl((int)r[0], src, 64) & 1) != 0;
+      const bool gneg = __shfl(neg ? 1 : 0, src, 64) != 0;
+      const bool on = pend && odd && j >= g;
+      const uint32_t ext = (on && gneg) ? ~0u : 0u;
+      uint32_t cc = 0;
+      r[0] = __builtin_addc(r[0], on ? (gneg ? ~0u : 1u) : 0u, cc, &cc);
+#pragma unroll
+      for (int k = 1; k <= L; ++k) r[k] = __builtin_addc(r[k], ext, cc, &cc);
+      fail = __ballot(act && (big || !win_inside<L>(r)));
+    }
+    const uint32_t fb = seg_bits(fail);
+    const int f = fb ? __ffs(fb) - 1 : n;  // first failing step of the row, or n
+    // the row's sum after its steps start .. f - 1: M from lane f - 1
+    uint32_t mc[L];
+    const int src = base + max(min(f, n) - 1, 0);
+#pragma unroll
+    for (int k = 0; k < L; ++k) mc[k] = (uint32_t)__shfl((int)r[k], src, 64);
+    if (work && f > start) {
+#pragma unroll
+      for (int k = 0; k < L; ++k) y.m[k] = mc[k];
+    }
+    // step f by the general RN addition
+    const bool exc = work && f < n;
+    if (__ballot(exc) != 0ull) {
+      const Num<L> tf = seg_take<L>(t, base + min(f, 15));
+      uint32_t sta = 0;  // every row computes it; only a row that takes it reports its status
+      const Num<L> ya = add_rn<L>(y, tf, sta);
+      if (exc) {
+        y = ya;
+        st |= sta;
+      }
+    }
+    if (work) start = exc ? f + 1 : n;
+  }
+}
+
+}  // namespace mp

@@ -142,6 +142,7 @@ SpmvVariant plan_variant(const mp_plan* P, int op, int mode) {
   if (v.rows && mode == MP_SEQ && P->group_min[op] > 0) {
     v.n_long = rows_at_least(P, op, P->group_min[op]);
     v.windows = P->windows[op];
+    if (v.windows == 2) v.n_win = rows_at_least(P, op, 8 * P->group_min[op]);
   }
   return v;
 }
@@ -345,17 +346,19 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     for (int mode = 0; mode < 2; ++mode) {
       float best = 0.f;
       int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0, pick_gmin = 0;
-      bool pick_win = false;
+      int pick_win = 0;
       // lane groups or windowed chains for the longest rows: SEQ with sorted rows only, when a
       // row is that long
       const int maxlen = P->order_len[op].empty() ? 0 : P->order_len[op][0];
-      // (minimum row length, windowed chains): none; lane groups from 128 or 512 entries;
-      // windowed chains from 128, 256 or 512
-      static const int kLongMin[6] = {0, 128, 512, 128, 256, 512};
-      for (int gi = 0; gi < 6; ++gi)
+      // (minimum row length, long-row method): none; lane groups from 128 or 512 entries;
+      // windowed chains, a row per wavefront, from 128, 256 or 512; windowed chains from 16,
+      // 32 or 64, four rows per wavefront below eight times that
+      static const int kLongMin[9] = {0, 128, 512, 128, 256, 512, 16, 32, 64};
+      static const int kLongWin[9] = {0, 0, 0, 1, 1, 1, 2, 2, 2};
+      for (int gi = 0; gi < 9; ++gi)
       for (int flags = 0; flags < 4; ++flags) {
         const int gmin = kLongMin[gi];
-        const bool win = gi >= 3;
+        const int win = kLongWin[gi];
         if (gmin && (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || maxlen < gmin || P->L > 16)) continue;
         for (int rpw : {16, 32, 64}) {
           SpmvVariant var;
@@ -367,6 +370,7 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
           if (flags & MP_VARIANT_SORTED_ROWS) var.rows = P->row_order[op];
           if (gmin) var.n_long = rows_at_least(P, op, gmin);
           var.windows = win;
+          if (win == 2) var.n_win = rows_at_least(P, op, 8 * gmin);
           int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
                                nullptr, &var);
           if (rr) return rr;
@@ -455,7 +459,7 @@ int mp_plan_tune_cached(mp_plan* plan, const mp_csr* A, int reps, const char* ca
       if (sscanf(line, "%llx %d %d %d %d", &k, &op, &mode, &rv, &fl) != 5 || k != key) continue;
       if (op < 0 || op > 1 || mode < 0 || mode > 1 || (rv != 0 && !valid_rows_per_block(rv)) ||
           (fl & ~(MP_VARIANT_STAGE_X | MP_VARIANT_SORTED_ROWS | MP_VARIANT_LANE_GROUPS | MP_VARIANT_WINDOWS |
-                  ~0xff)))
+                  MP_VARIANT_SEGMENTS | ~0xff)))
         continue;
       rpw[op][mode] = rv;
       flags[op][mode] = fl;
@@ -546,9 +550,11 @@ int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int ro
   if (mode != MP_SEQ && mode != MP_EXACT) return fail(MPS_EINVAL, "mode must be MP_SEQ or MP_EXACT");
   if (rows_per_block != 0 && !valid_rows_per_block(rows_per_block))
     return fail(MPS_EINVAL, "rows per block must be 0, 16, 32 or 64");
-  if (flags < 0 || (flags & 0xf0)) return fail(MPS_EINVAL, "unknown variant flags");
+  if (flags < 0 || (flags & 0xe0)) return fail(MPS_EINVAL, "unknown variant flags");
   if ((flags & MP_VARIANT_WINDOWS) && !(flags & MP_VARIANT_LANE_GROUPS))
     return fail(MPS_EINVAL, "MP_VARIANT_WINDOWS needs MP_VARIANT_LANE_GROUPS and a minimum row length");
+  if ((flags & MP_VARIANT_SEGMENTS) && !(flags & MP_VARIANT_WINDOWS))
+    return fail(MPS_EINVAL, "MP_VARIANT_SEGMENTS needs MP_VARIANT_WINDOWS");
   const int gmin = (flags & MP_VARIANT_LANE_GROUPS) ? (flags >> 8) : 0;
   if ((flags & MP_VARIANT_LANE_GROUPS) &&
       (mode != MP_SEQ || !(flags & MP_VARIANT_SORTED_ROWS) || gmin < 1))
@@ -562,7 +568,7 @@ int mp_plan_set_variant(mp_plan* plan, const mp_csr* A, int op, int mode, int ro
   plan->sorted[op][mode] = (flags & MP_VARIANT_SORTED_ROWS) != 0;
   if (mode == MP_SEQ) {
     plan->group_min[op] = gmin;
-    plan->windows[op] = gmin > 0 && (flags & MP_VARIANT_WINDOWS) != 0;
+    plan->windows[op] = (gmin > 0 && (flags & MP_VARIANT_WINDOWS)) ? ((flags & MP_VARIANT_SEGMENTS) ? 2 : 1) : 0;
   }
   return MPS_OK;
 }
@@ -578,7 +584,8 @@ int mp_plan_get_variant(const mp_plan* plan, int op, int mode, int* rows_per_blo
   const int gmin = (srt && mode == MP_SEQ) ? plan->group_min[op] : 0;
   *flags = ((plan->stage[op][mode] && plan->x_rec) ? MP_VARIANT_STAGE_X : 0) |
            (srt ? MP_VARIANT_SORTED_ROWS : 0) | (gmin ? (MP_VARIANT_LANE_GROUPS | (gmin << 8)) : 0) |
-           ((gmin && plan->windows[op]) ? MP_VARIANT_WINDOWS : 0);
+           ((gmin && plan->windows[op]) ? MP_VARIANT_WINDOWS : 0) |
+           ((gmin && plan->windows[op] == 2) ? MP_VARIANT_SEGMENTS : 0);
   return MPS_OK;
 }
 

@@ -23,7 +23,7 @@ struct mp_plan {
   std::vector<int32_t> order_len[2];            // their lengths, in that order (host)
   int group_min[2] = {0, 0};  // SEQ with sorted rows: rows of at least this many entries are
                               // summed by lane groups (0: none), for [A, A^T]
-  bool windows[2] = {false, false};  // ... by windowed chains instead of lane groups
+  int windows[2] = {0, 0};  // ... by windowed chains instead (1: a row per wavefront, 2: four)
 };
 
 namespace mpapi {

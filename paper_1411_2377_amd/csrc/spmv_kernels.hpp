@@ -79,7 +79,11 @@ struct SpmvArgs {
   // by lane groups in the first long_blocks blocks; the other blocks take the rows after them
   int64_t n_long;
   int64_t long_blocks;
-  int window;  // those rows by windowed chains (four rows per block, one per wavefront)
+  // or by windowed chains (window != 0): the first n_win of them one per wavefront in the first
+  // win_blocks blocks, the others four per wavefront (16 lanes each)
+  int window;
+  int64_t n_win;
+  int64_t win_blocks;
   // > 0: a dense row-major matrix with that many columns (row i holds entries i * dense_cols ...,
   // entry k sits in column k mod dense_cols); row_ptr and col_idx are then not read
   int32_t dense_cols;
@@ -487,7 +491,7 @@ template <int L>
 __device__ void spmv_seq_window_rows(const SpmvArgs& A, int64_t blk, uint32_t& st) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t ri = blk * 4 + wv;
-  if (ri >= A.n_long) return;  // the whole wavefront
+  if (ri >= A.n_win) return;  // the whole wavefront
   const int64_t row = A.rows[ri];
   const int rs = row_begin(A, row), len = row_end(A, row) - rs;
   Num<L> y;
@@ -519,6 +523,48 @@ __device__ void spmv_seq_window_rows(const SpmvArgs& A, int64_t blk, uint32_t& s
   if (lane == 0) store<L>(y, A.y_limb, A.y_hdr, A.y_ld, row);
 }
 
+// SEQ, the long rows by segmented windowed chains: sixteen rows per block, four per wavefront
+// (one per row of 16 lanes).  Each wavefront forms its rows' rounded products 16 per row at a
+// time (lane j of row g: entry j of the chunk of the g-th row; the next chunk's loads are issued
+// before the chains run) and advances the four chains together.
+template <int L>
+__device__ void spmv_seq_seg_rows(const SpmvArgs& A, int64_t blk, uint32_t& st) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 15;
+  const int64_t ri = A.n_win + blk * 16 + wv * 4 + (lane >> 4);
+  const bool has = ri < A.n_long;
+  const int64_t row = has ? (int64_t)A.rows[ri] : 0;
+  const int rs = has ? row_begin(A, row) : 0;
+  const int len = has ? row_end(A, row) - rs : 0;
+  const int maxlen = wave_max32(len);
+  Num<L> y;
+  set_zero(y, 0u);
+  int64_t k[1];
+  bool ok[1];
+  ok[0] = j < len;
+  k[0] = ok[0] ? (int64_t)rs + j : 0;
+  EntryLoad<L, 1> E;
+  load_entries<L, 1>(E, A, A.x_limb, A.x_hdr, k, ok);
+  for (int c0 = 0; c0 < maxlen; c0 += 16) {
+    Num<L> t;
+    const int32_t ha = E.ha[0], hx = E.hx[0];
+    if (!ok[0] || hdr_is_zero(ha) || hdr_is_zero(hx)) {
+      set_zero(t, (uint32_t)(ha ^ hx) & 1u);
+    } else {
+      uint32_t pr[2 * L];
+      mul_full<L>(E.am[0], E.xm[0], pr);
+      round_product<L>(pr, (ha >> 1) + (hx >> 1), (uint32_t)(ha ^ hx) & 1u, t, st);
+    }
+    const int c1 = c0 + 16;
+    if (c1 < maxlen) {
+      ok[0] = c1 + j < len;
+      k[0] = ok[0] ? (int64_t)rs + c1 + j : 0;
+      load_entries<L, 1>(E, A, A.x_limb, A.x_hdr, k, ok);
+    }
+    win_chain_seg<L>(y, t, max(0, min(16, len - c0)), st);
+  }
+  if (has && j == 0) store<L>(y, A.y_limb, A.y_hdr, A.y_ld, row);
+}
+
 // GROUPS: the long rows are summed by lane groups (whose LDS buffers only this instantiation
 // holds), else by windowed chains.
 template <int L, int RPW, bool FUSE, bool GROUPS>
@@ -528,8 +574,10 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
       uint32_t st = 0;
       if constexpr (GROUPS)
         spmv_seq_group_rows<L>(A, blockIdx.x, st);
-      else
+      else if ((int64_t)blockIdx.x < A.win_blocks)
         spmv_seq_window_rows<L>(A, blockIdx.x, st);
+      else
+        spmv_seq_seg_rows<L>(A, blockIdx.x - A.win_blocks, st);
       if (st) atomicOr(A.status, st);
       return;
     }

@@ -196,17 +196,17 @@ def test_every_kernel_variant_same_bits(p):
     for mode in (0, 1):
         want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
         want_t = ospmv.spmv(tp, ti, tv, go, p, mode)
-        combos = [(False, False, 0, False), (True, False, 0, False), (False, True, 0, False),
-                  (True, True, 0, False)]
-        if mode == 0:   # lane groups / windowed chains for every non-empty row, rows of >= 2, >= 200
-            combos += [(False, True, 1, False), (True, True, 2, False), (True, True, 200, False),
-                       (False, True, 1, True), (True, True, 2, True), (True, True, 200, True)]
+        combos = [(False, False, 0, 0), (True, False, 0, 0), (False, True, 0, 0), (True, True, 0, 0)]
+        if mode == 0:   # lane groups / windowed chains (a row or four rows per wavefront) for
+            # every non-empty row, rows of >= 2 and of >= 200
+            combos += [(s, True, g, w) for w in (0, 1, 2) for s, g in ((False, 1), (True, 2), (True, 200))]
+        kinds = ("lane groups", "windows", "segmented windows")
         for rows in (16, 32, 64):
             for stage, srt, gmin, win in combos:
-                P.set_variant(0, mode, rows, stage, srt, gmin, win)
-                P.set_variant(1, mode, rows, stage, srt, gmin, win)
+                P.set_variant(0, mode, rows, stage, srt, gmin, win == 1, win == 2)
+                P.set_variant(1, mode, rows, stage, srt, gmin, win == 1, win == 2)
                 tag = "%d rows per block, staged x %s, sorted rows %s, %s from %d, mode %d" % (
-                    rows, stage, srt, "windows" if win else "lane groups", gmin, mode)
+                    rows, stage, srt, kinds[win], gmin, mode)
                 yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
                 assert_bitwise(yl, yh, want, p, what="A x, " + tag)
                 tl, th = M.mpspmv_csr_t(A, P, g, mode=mode).to_numpy()
@@ -280,17 +280,17 @@ def test_lane_group_rows_corner_sums(p):
     x = M.MPArray.from_host(x_h)
     want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), 0)
     P = M.mp_plan_create(A)
-    for rows, stage, gmin, win in ((16, False, 1, False), (64, True, 1, False), (32, False, 0, False),
-                                   (16, True, 1, True), (64, False, 2, True)):
-        P.set_variant(0, 0, rows, stage, True, gmin, win)
+    for rows, stage, gmin, win in ((16, False, 1, 0), (64, True, 1, 0), (32, False, 0, 0),
+                                   (16, True, 1, 1), (64, False, 2, 1), (32, True, 1, 2), (16, False, 3, 2)):
+        P.set_variant(0, 0, rows, stage, True, gmin, win == 1, win == 2)
         yl, yh = M.mpspmv_csr(A, x, mode=0, plan=P).to_numpy()
         assert_bitwise(yl, yh, want, p, what="corner rows, %s from %d" % (
-            "windows" if win else "lane groups", gmin))
+            ("lane groups", "windows", "segmented windows")[win], gmin))
     assert M.mp_status() == 0
 
 
 @pytest.mark.parametrize("p", [128, 256, 512])
-@pytest.mark.parametrize("win", [False, True], ids=["groups", "windows"])
+@pytest.mark.parametrize("win", [0, 1, 2], ids=["groups", "windows", "segments"])
 def test_powerlaw_lane_groups_sampled(p, win):
     """The power-law workload at full size with the longest rows summed by lane groups or by
     windowed chains (rows of >= 64 entries): sampled rows, always including the longest ones,
@@ -300,7 +300,7 @@ def test_powerlaw_lane_groups_sampled(p, win):
     A = M.CSRMatrix.from_host(A_h)
     x = M.MPArray.from_host(x_h)
     P = M.mp_plan_create(A)
-    P.set_variant(0, 0, 16, True, True, 64, win)
+    P.set_variant(0, 0, 16, True, True, 64, win == 1, win == 2)
     yl, yh = M.mpspmv_csr(A, x, mode=0, plan=P).to_numpy()
     lengths = np.diff(A_h.row_ptr)
     order = np.argsort(-lengths, kind="stable")
