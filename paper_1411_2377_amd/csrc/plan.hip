@@ -60,6 +60,48 @@ __global__ void gather_values_kernel(const int32_t* __restrict__ perm, int64_t n
   for (int q = 0; q < L; ++q) dst_limb[(int64_t)q * nnz + t] = src_limb[(int64_t)q * src_ld + k];
 }
 
+// rec[k] = (limbs of value k, its header), x_rec_words_of(L) words per record
+template <int L>
+__global__ void __launch_bounds__(256) value_records_kernel(int64_t nnz, const uint32_t* __restrict__ limb,
+                                                            const int32_t* __restrict__ hdr, int64_t ld,
+                                                            uint32_t* __restrict__ rec) {
+  constexpr int S = mp::x_rec_words_of(L);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t w[L + 4];
+#pragma unroll
+    for (int q = 0; q < L; ++q) w[q] = limb[(int64_t)q * ld + k];
+    w[L] = (uint32_t)hdr[k];
+    w[L + 1] = w[L + 2] = w[L + 3] = 0u;
+    uint4* out = reinterpret_cast<uint4*>(rec + k * S);
+#pragma unroll
+    for (int q = 0; q < (L + 4) / 4; ++q) out[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+  }
+}
+
+// dst[t] = record perm[t]
+template <int L>
+__global__ void __launch_bounds__(256) gather_records_kernel(const int32_t* __restrict__ perm, int64_t nnz,
+                                                             const uint32_t* __restrict__ rec,
+                                                             uint32_t* __restrict__ dst_limb,
+                                                             int32_t* __restrict__ dst_hdr) {
+  constexpr int S = mp::x_rec_words_of(L);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * blockDim.x) {
+    const uint4* r = reinterpret_cast<const uint4*>(rec + (int64_t)perm[t] * S);
+    uint32_t w[L + 4];
+#pragma unroll
+    for (int q = 0; q < (L + 4) / 4; ++q) {
+      const uint4 v = r[q];
+      w[4 * q] = v.x;
+      w[4 * q + 1] = v.y;
+      w[4 * q + 2] = v.z;
+      w[4 * q + 3] = v.w;
+    }
+    dst_hdr[t] = (int32_t)w[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) dst_limb[(int64_t)q * nnz + t] = w[q];
+  }
+}
+
 // gvals_k = (-1)^neg * RN(g_i x_j) for entry k = (i, j), in CSR order of A.
 template <int L>
 __global__ void grad_vals_kernel(int64_t nnz, const int32_t* __restrict__ row_of,
@@ -159,10 +201,34 @@ int plan_x_rec(mp_plan* P) {
   return MPS_OK;
 }
 
+template <int L>
+void gather_via_records(mp_plan* P, const mp_csr* A, uint32_t* rec, unsigned g, hipStream_t s) {
+  hipLaunchKernelGGL(value_records_kernel<L>, dim3(g), dim3(256), 0, s, P->nnz, A->val.limb, A->val.hdr,
+                     A->val.ld, rec);
+  hipLaunchKernelGGL(gather_records_kernel<L>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, rec, P->t_limb, P->t_hdr);
+}
+
 int plan_gather(mp_plan* P, const mp_csr* A, hipStream_t s) {
   if (P->nnz == 0) return MPS_OK;
   if (P->L > 32) return wide_gather(P->L, P->perm, P->nnz, A->val, P->t_limb, P->t_hdr, s);
   const unsigned g = blocks_for(P->nnz, 256);
+  // the values as one record per entry first (read and written in order), then the records
+  // gathered in the transposed order: one cache line per entry instead of one per limb
+  uint32_t* rec = nullptr;
+  const size_t rec_bytes = (size_t)P->nnz * mp::x_rec_words_of(P->L) * 4;
+  if (hipMallocAsync((void**)&rec, rec_bytes, s) == hipSuccess) {
+    switch (P->L) {
+      case 4: gather_via_records<4>(P, A, rec, g, s); break;
+      case 8: gather_via_records<8>(P, A, rec, g, s); break;
+      case 16: gather_via_records<16>(P, A, rec, g, s); break;
+      case 32: gather_via_records<32>(P, A, rec, g, s); break;
+    }
+    hipError_t e = hipGetLastError();
+    const hipError_t ef = hipFreeAsync(rec, s);
+    if (e == hipSuccess) e = ef;
+    return e == hipSuccess ? MPS_OK : hip_fail(e, "gather launch");
+  }
+  (void)hipGetLastError();  // no room for the records: gather limb by limb
   switch (P->L) {
     case 4: hipLaunchKernelGGL(gather_values_kernel<4>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
     case 8: hipLaunchKernelGGL(gather_values_kernel<8>, dim3(g), dim3(256), 0, s, P->perm, P->nnz, A->val.limb, A->val.hdr, A->val.ld, P->t_limb, P->t_hdr); break;
