@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(256) spmv_seq_sorted_kernel(SpmvArgs A) {
 // the wave.  A row whose products span more than a ring is redone in a block-shared window at its
 // exact exponent anchor (or raises kStWindow when even that is too narrow).
 // ------------------------------------------------------------------------------------------
-constexpr int kShortRow = 32;
+constexpr int kShortRow = 64;
 
 // Ring slot of digit d.
 template <int R>
