@@ -220,7 +220,9 @@ int spmv_launch(int L, int64_t n_rows, const int32_t* row_ptr, const int32_t* co
     a.wide_win = ctx->wide_win;
     a.wide_lock = ctx->wide_lock;
   }
-  if (mode == MP_SEQ && var->rows && var->n_long > 0 && !(fuse && fuse->nd > 0) && batch->nrhs == 1 &&
+  // (lane groups need a row order; windowed chains also take the rows in their own order)
+  if (mode == MP_SEQ && (var->rows || (var->pipe && var->windows)) && var->n_long > 0 && !(fuse && fuse->nd > 0) &&
+      batch->nrhs == 1 &&
       !batch->pair_of_tile && !done && L <= 16) {  // lane groups hold at most 16 limbs
     a.n_long = std::min<int64_t>(var->n_long, n_rows);
     a.window = var->windows;
@@ -394,10 +396,16 @@ int mp_gemv(const mp_dense* A, const mp_vec* x, mp_vec* y, int mode, void* strea
     return launch_ew(L, EW_ZERO, a, (hipStream_t)stream);
   }
   // SEQ: the four-wavefront pipelined kernel (products formed beside the rows' rounding chains),
-  // 16 rows per block; EXACT: rows per block by the row length
+  // 16 rows per block, and rows of 16 or more entries by windowed chains (four per wavefront,
+  // one per wavefront from 128 entries); EXACT: rows per block by the row length
   SpmvVariant var;
   var.rpw = mode == MP_SEQ ? 16 : 0;
   var.pipe = mode == MP_SEQ;
+  if (mode == MP_SEQ && L <= 16 && A->cols >= 16) {
+    var.n_long = A->rows;
+    var.windows = 2;
+    var.n_win = A->cols >= 128 ? A->rows : 0;
+  }
   return spmv_launch(L, A->rows, nullptr, nullptr, A->val, *x, *y, mode, ctx->status, nullptr,
                      (hipStream_t)stream, nullptr, nullptr, &var, (int32_t)A->cols);
 }

@@ -492,7 +492,7 @@ __device__ void spmv_seq_window_rows(const SpmvArgs& A, int64_t blk, uint32_t& s
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t ri = blk * 4 + wv;
   if (ri >= A.n_win) return;  // the whole wavefront
-  const int64_t row = A.rows[ri];
+  const int64_t row = A.rows ? (int64_t)A.rows[ri] : ri;
   const int rs = row_begin(A, row), len = row_end(A, row) - rs;
   Num<L> y;
   set_zero(y, 0u);
@@ -532,7 +532,7 @@ __device__ void spmv_seq_seg_rows(const SpmvArgs& A, int64_t blk, uint32_t& st) 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 15;
   const int64_t ri = A.n_win + blk * 16 + wv * 4 + (lane >> 4);
   const bool has = ri < A.n_long;
-  const int64_t row = has ? (int64_t)A.rows[ri] : 0;
+  const int64_t row = has ? (A.rows ? (int64_t)A.rows[ri] : ri) : 0;
   const int rs = has ? row_begin(A, row) : 0;
   const int len = has ? row_end(A, row) - rs : 0;
   const int maxlen = wave_max32(len);
