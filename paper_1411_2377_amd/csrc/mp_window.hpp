@@ -62,7 +62,8 @@ MPD void win_scan(uint32_t (&v)[N]) {
 // r = (-1)^neg * RN(M / 2^d) as an (L + 1)-word two's complement integer, M an L-limb mantissa
 // (not zero), d >= 0; *tie when M / 2^d lies exactly half-way between two integers.  The shift
 // is of M * 2^32 (a guard word below), so the guard word's top bit is the round bit and its
-// other bits, with every bit shifted out below it, the sticky bits.
+// other bits, with every bit shifted out below it, the sticky bits.  Called by the lanes that
+// have a product to place (the stages of whole-word shifts nobody needs are skipped).
 template <int L>
 MPD void win_align_round(const uint32_t (&m)[L], uint32_t d, bool neg, uint32_t (&r)[L + 1], bool& tie) {
   uint32_t w[L + 1];
@@ -74,6 +75,7 @@ MPD void win_align_round(const uint32_t (&m)[L], uint32_t d, bool neg, uint32_t 
 #pragma unroll
   for (int k = 1; k <= L + 1; k <<= 1) {
     const bool on = (q & (uint32_t)k) != 0u;
+    if (k > 1 && __ballot(on) == 0ull) continue;  // no lane shifts by k words (the common case)
     uint32_t out = 0u;
 #pragma unroll
     for (int j = 0; j < k && j <= L; ++j) out |= w[j];
