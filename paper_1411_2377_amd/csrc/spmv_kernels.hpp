@@ -750,7 +750,7 @@ MPD void ring_fold(int64_t* win) {
 }
 
 template <int L, int RPW, bool FUSE>
-__global__ void __launch_bounds__(64, 3) spmv_exact_kernel(SpmvArgs A) {
+__global__ void __launch_bounds__(64, 4) spmv_exact_kernel(SpmvArgs A) {
   constexpr int R = window_fast_digits<L>();  // ring digits per row
   constexpr int RS = ring_slots<L, R>();        // with the overflow slots
   // digits of the block-shared exact window: the same for every variant, so that every variant
