@@ -393,6 +393,7 @@ def lotkin_component(M, torch, reps):
             plan = M.mp_plan_create(A)
             plan.tune(reps=1)
             b = M.mpspmv_csr(A, M.MPArray.from_host(x_h), mode=M.MP_SEQ, plan=plan)
+            plan.tune(reps=1, x=b)   # the variants timed on the operand they will see
             ys = M.MPArray.empty(n, p)
             yd = M.MPArray.empty(n, p)
             ts = timed_launches(M, torch, lambda: M.mpspmv_csr(A, b, ys, mode=M.MP_SEQ, plan=plan), reps)

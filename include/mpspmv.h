@@ -250,6 +250,14 @@ int mpspmv_csr_t(const mp_csr *A, const mp_vec *x, mp_vec *y, int mode, const mp
  * wavefront as before.  Same result bits. */
 #define MP_VARIANT_SEGMENTS 16
 int mp_plan_tune(mp_plan *plan, const mp_csr *A, int reps, void *stream);
+/* mp_plan_tune timing the products on the caller's operands: x (n_cols elements, device) for
+ * y = A x and x_t (n_rows) for A^T x_t; a null pointer takes the generated operands for that
+ * product.  The long-row methods of SEQ are data-dependent (the windowed chains take a step
+ * alone where the running sum leaves its binade, which sums that cancel do often and sums of
+ * one sign rarely), so the operand the products will see picks best.  x and x_t are only read.
+ * Returns as mp_plan_tune, plus MPS_EINVAL for a bad operand. */
+int mp_plan_tune_x(mp_plan *plan, const mp_csr *A, const mp_vec *x, const mp_vec *x_t, int reps,
+                   void *stream);
 int mp_plan_set_variant(mp_plan *plan, const mp_csr *A, int op, int mode, int rows_per_block,
                         int flags);
 /* mp_plan_tune with a persistent cache: the text file `cache_path` maps a key (a hash of A's

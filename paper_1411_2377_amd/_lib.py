@@ -95,6 +95,8 @@ SIGNATURES = {
     "mpspmv_csr_noalloc": [ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
                            ctypes.c_int, ctypes.c_void_p],
     "mp_plan_tune": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_void_p],
+    "mp_plan_tune_x": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.POINTER(MpVec), ctypes.POINTER(MpVec),
+                       ctypes.c_int, ctypes.c_void_p],
     "mp_plan_tune_cached": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_char_p,
                             ctypes.POINTER(ctypes.c_int), ctypes.c_void_p],
     "mp_plan_set_variant": [ctypes.c_void_p, ctypes.POINTER(MpCsr), ctypes.c_int, ctypes.c_int,

@@ -83,12 +83,19 @@ class Plan:
         d = self.A.desc()
         check(_lib.LIB.mp_plan_refresh(self._h, ctypes.byref(d), _stream(stream)))
 
-    def tune(self, reps=3, stream=None, cache=None):
+    def tune(self, reps=3, stream=None, cache=None, x=None, x_t=None):
         """Time the SpMV kernel variants on this matrix and keep the fastest (synchronous).
         With cache=<file path> the choice is looked up in (or added to) that tuning cache;
-        self.cache_hit tells which happened."""
+        self.cache_hit tells which happened.  With x (and/or x_t, MPArrays) the products are
+        timed on those operands instead of generated ones (no cache)."""
         d = self.A.desc()
-        if cache is None:
+        if x is not None or x_t is not None:
+            xd = x.desc() if x is not None else None
+            td = x_t.desc() if x_t is not None else None
+            check(_lib.LIB.mp_plan_tune_x(self._h, ctypes.byref(d), ctypes.byref(xd) if xd else None,
+                                          ctypes.byref(td) if td else None, int(reps), _stream(stream)))
+            self.cache_hit = False
+        elif cache is None:
             check(_lib.LIB.mp_plan_tune(self._h, ctypes.byref(d), int(reps), _stream(stream)))
             self.cache_hit = False
         else:

@@ -350,10 +350,12 @@ using namespace mpapi;
 
 namespace {
 
-// Time every rows-per-block variant of the four products (A and A^T, both modes) on a random
-// operand and keep the fastest; every variant computes the same bits, so only speed changes.
+// Time every rows-per-block variant of the four products (A and A^T, both modes) on two random
+// operands, one with random signs and one with the same magnitudes all positive (SEQ's long-row
+// methods fare differently on sums that cancel and sums that only grow), and keep the variant
+// with the least total time; every variant computes the same bits, so only speed changes.
 template <int L>
-__global__ void tune_fill_kernel(uint32_t* limb, int32_t* hdr, int64_t n) {
+__global__ void tune_fill_kernel(uint32_t* limb, int32_t* hdr, int32_t* hdr_pos, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t h = 0x9e3779b97f4a7c15ull * (uint64_t)(i + 1);
@@ -366,29 +368,33 @@ __global__ void tune_fill_kernel(uint32_t* limb, int32_t* hdr, int64_t n) {
     // exponents as for values uniform on [-1, 1): 0 with probability 1/2, -1 with 1/4, ...
     const int32_t e = -(int32_t)__clz((int)(uint32_t)(h >> 20));
     hdr[i] = (int32_t)(((uint32_t)e << 1) | (uint32_t)((h >> 52) & 1));
+    hdr_pos[i] = (int32_t)((uint32_t)e << 1);
   }
 }
 
-int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream_t s) {
+// xs[op]: the caller's operand for product op (nullptr: the two generated ones)
+int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream_t s,
+              const mp_vec* const (&xs)[2] = {nullptr, nullptr}) {
   const int L = P->L;
   const int64_t nmax = std::max<int64_t>(1, std::max(P->n_rows, P->n_cols));
   uint32_t *xl = nullptr, *yl = nullptr;
-  int32_t *xh = nullptr, *yh = nullptr;
+  int32_t *xh = nullptr, *yh = nullptr, *xh_pos = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   struct Free {
     uint32_t **a, **b;
-    int32_t **c, **d;
+    int32_t **c, **d, **g;
     hipEvent_t *e, *f;
     ~Free() {
-      hipFree(*a); hipFree(*b); hipFree(*c); hipFree(*d);
+      hipFree(*a); hipFree(*b); hipFree(*c); hipFree(*d); hipFree(*g);
       if (*e) hipEventDestroy(*e);
       if (*f) hipEventDestroy(*f);
     }
-  } fr{&xl, &yl, &xh, &yh, &e0, &e1};
+  } fr{&xl, &yl, &xh, &yh, &xh_pos, &e0, &e1};
   hipError_t e = hipMalloc((void**)&xl, (size_t)L * nmax * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&yl, (size_t)L * nmax * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&xh, (size_t)nmax * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&yh, (size_t)nmax * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&xh_pos, (size_t)nmax * 4);
   if (e != hipSuccess) return fail(MPS_ENOMEM, "tune workspace: %s", hipGetErrorString(e));
   int r0 = plan_x_rec(P);
   if (!r0) r0 = plan_row_order(P, 0, A->row_ptr);
@@ -398,10 +404,10 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     return hip_fail(e, "tune events");
   const unsigned g = (unsigned)std::min<int64_t>(4096, (nmax + 255) / 256);
   switch (L) {
-    case 4: hipLaunchKernelGGL(tune_fill_kernel<4>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
-    case 8: hipLaunchKernelGGL(tune_fill_kernel<8>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
-    case 16: hipLaunchKernelGGL(tune_fill_kernel<16>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
-    default: hipLaunchKernelGGL(tune_fill_kernel<32>, dim3(g), dim3(256), 0, s, xl, xh, nmax); break;
+    case 4: hipLaunchKernelGGL(tune_fill_kernel<4>, dim3(g), dim3(256), 0, s, xl, xh, xh_pos, nmax); break;
+    case 8: hipLaunchKernelGGL(tune_fill_kernel<8>, dim3(g), dim3(256), 0, s, xl, xh, xh_pos, nmax); break;
+    case 16: hipLaunchKernelGGL(tune_fill_kernel<16>, dim3(g), dim3(256), 0, s, xl, xh, xh_pos, nmax); break;
+    default: hipLaunchKernelGGL(tune_fill_kernel<32>, dim3(g), dim3(256), 0, s, xl, xh, xh_pos, nmax); break;
   }
   mp_vec tv{P->t_limb, P->t_hdr, P->nnz, P->nnz};
   for (int op = 0; op < 2; ++op) {
@@ -409,7 +415,7 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
     const int32_t* rp = op ? P->t_row_ptr : A->row_ptr;
     const int32_t* ci = op ? P->t_col_idx : A->col_idx;
     const mp_vec& val = op ? tv : A->val;
-    mp_vec xv{xl, xh, cols, nmax}, yv{yl, yh, rows, nmax};
+    mp_vec xv{xl, xh, cols, nmax}, yv{yl, yh, rows, nmax}, xv_pos{xl, xh_pos, cols, nmax};
     for (int mode = 0; mode < 2; ++mode) {
       float best = 0.f;
       int pick = default_rows_per_block(rows, P->nnz), pick_flags = 0, pick_gmin = 0;
@@ -441,18 +447,23 @@ int tune_impl(mp_plan* P, const mp_csr* A, int reps, uint32_t* status, hipStream
           int rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
                                nullptr, &var);
           if (rr) return rr;
-          float ms = 0.f;  // the faster of two timed batches of reps launches
-          for (int batch = 0; batch < 2; ++batch) {
-            if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "tune");
-            for (int k = 0; k < reps; ++k)
-              if ((rr = spmv_launch(L, rows, rp, ci, val, xv, yv, mode, status, nullptr, s, nullptr,
-                                    nullptr, &var)))
-                return rr;
-            if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
-              return hip_fail(e, "tune");
-            float mb = 0.f;
-            if ((e = hipEventElapsedTime(&mb, e0, e1)) != hipSuccess) return hip_fail(e, "tune");
-            ms = batch == 0 ? mb : std::min(ms, mb);
+          float ms = 0.f;  // over the operands, the faster of two timed batches of reps launches
+          for (int opnd = 0; opnd < (xs[op] ? 1 : 2); ++opnd) {
+            const mp_vec& xo = xs[op] ? *xs[op] : (opnd ? xv_pos : xv);
+            float mo = 0.f;
+            for (int batch = 0; batch < 2; ++batch) {
+              if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "tune");
+              for (int k = 0; k < reps; ++k)
+                if ((rr = spmv_launch(L, rows, rp, ci, val, xo, yv, mode, status, nullptr, s, nullptr,
+                                      nullptr, &var)))
+                  return rr;
+              if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+                return hip_fail(e, "tune");
+              float mb = 0.f;
+              if ((e = hipEventElapsedTime(&mb, e0, e1)) != hipSuccess) return hip_fail(e, "tune");
+              mo = batch == 0 ? mb : std::min(mo, mb);
+            }
+            ms += mo;
           }
           if (best == 0.f || ms < best) {
             best = ms;
@@ -669,6 +680,20 @@ int mp_plan_tune(mp_plan* plan, const mp_csr* A, int reps, void* stream) {
   DeviceCtx* ctx;
   if ((r = get_ctx(&ctx))) return r;
   return tune_impl(plan, A, reps, ctx->status, (hipStream_t)stream);
+}
+
+int mp_plan_tune_x(mp_plan* plan, const mp_csr* A, const mp_vec* x, const mp_vec* x_t, int reps, void* stream) {
+  clear_error();
+  int r = check_csr(A, 0);
+  if (r) return r;
+  if ((r = check_plan(plan, A))) return r;
+  if (x && (r = check_vec(x, A->col_dim, "x"))) return r;
+  if (x_t && (r = check_vec(x_t, A->row_dim, "x_t"))) return r;
+  if (reps <= 0) reps = 3;
+  DeviceCtx* ctx;
+  if ((r = get_ctx(&ctx))) return r;
+  const mp_vec* const xs[2] = {x, x_t};
+  return tune_impl(plan, A, reps, ctx->status, (hipStream_t)stream, xs);
 }
 
 int mp_grad_vals(const mp_csr* A, const mp_plan* plan, const mp_vec* g, const mp_vec* x,

@@ -211,13 +211,14 @@ def test_every_kernel_variant_same_bits(p):
                 assert_bitwise(yl, yh, want, p, what="A x, " + tag)
                 tl, th = M.mpspmv_csr_t(A, P, g, mode=mode).to_numpy()
                 assert_bitwise(tl, th, want_t, p, what="A^T g, " + tag)
-    picks = P.tune(reps=1)
-    assert {v[0] for v in picks.values()} <= {16, 32, 64}
-    assert all(v[3] == 0 for (op, m), v in picks.items() if m == 1)   # lane groups: SEQ only
-    for mode in (0, 1):
-        yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
-        want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
-        assert_bitwise(yl, yh, want, p, what="tuned A x mode %d" % mode)
+    for kw in ({}, {"x": x, "x_t": g}):   # generated operands, then the products' own
+        picks = P.tune(reps=1, **kw)
+        assert {v[0] for v in picks.values()} <= {16, 32, 64}
+        assert all(v[3] == 0 for (op, m), v in picks.items() if m == 1)   # lane groups: SEQ only
+        for mode in (0, 1):
+            yl, yh = M.mpspmv_csr(A, x, mode=mode, plan=P).to_numpy()
+            want = oracle_spmv_rows(A_h, x_h, np.arange(A_h.n_rows), mode)
+            assert_bitwise(yl, yh, want, p, what="tuned A x mode %d %s" % (mode, list(kw)))
     assert M.mp_status() == 0
 
 
