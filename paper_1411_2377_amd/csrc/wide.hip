@@ -333,8 +333,12 @@ MPD WNum wide_add(Lds& S, uint32_t* z, int L, const uint32_t* x, WNum xe, const 
   return round_mag(z, L, S.s1, n, (int64_t)Xn.e - p - 32, sgn, false, st);
 }
 
-// z = RN(a / b): Q = floor(Ma 2^(p+1) / Mb) by restoring long division (p + 2 quotient bits),
-// the remainder's non-zero-ness as sticky
+// z = RN(a / b): Q = floor(Ma 2^(p+1) / Mb) by long division in radix 2^32, the remainder's
+// non-zero-ness as sticky.  R = 2 Ma first gives the top quotient digit (1, 2 or 3, by repeated
+// subtraction); then each of the L steps shifts R up one limb, estimates the next digit from
+// R's top two limbs over Mb's top limb (Mb is normalised, so the estimate is at most 2 too
+// large: Knuth, TAOCP 4.3.1, algorithm D), subtracts digit x Mb and adds Mb back while the
+// remainder is negative.
 MPD WNum wide_div(Lds& S, uint32_t* z, int L, const uint32_t* a, WNum ae, const uint32_t* b, WNum be,
                   uint32_t& st) {
   if (be.e == kZeroE) {
@@ -350,35 +354,57 @@ MPD WNum wide_div(Lds& S, uint32_t* z, int L, const uint32_t* a, WNum ae, const 
   }
   const int p = 32 * L, n = L + 1, ln = lane_id();
   uint32_t* R = S.s1;
-  uint32_t* T = S.s2;
-  uint32_t* U = S.s3;
+  uint32_t* U = S.s2;
+  uint32_t* T = S.s3;
+  uint32_t* H = S.c1;
   uint32_t* Q = S.p;
   uint32_t* B = S.c0;
   big_set(Q, L + 2, 0u);
   for (int j = ln; j < n; j += 64) {
-    R[j] = j < L ? a[j] : 0u;
+    U[j] = j < L ? a[j] : 0u;
     B[j] = j < L ? b[j] : 0u;
   }
   wsync();
-  for (int i = 0; i <= p + 1; ++i) {
-    if (i > 0) {
-      big_window(U, n, R, n, -1);  // U = 2 R
-      wsync();
-      uint32_t* t = R;
-      R = U;
-      U = t;
-    }
-    const uint32_t nb = big_add(T, R, B, n, true, 1u);  // T = R - B
+  big_window(R, n, U, n, -1);  // R = 2 Ma < 4 Mb
+  wsync();
+  uint32_t q0 = 0;
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t nb = big_add(T, R, B, n, true, 1u);  // T = R - Mb
     wsync();
-    if (nb) {
-      uint32_t* t = R;
-      R = T;
-      T = t;
-      const int bit = p + 1 - i;
-      if (ln == 0) Q[bit >> 5] |= 1u << (bit & 31);
-      wsync();
-    }
+    if (!nb) break;
+    uint32_t* t = R;
+    R = T;
+    T = t;
+    ++q0;
   }
+  const uint32_t dtop = B[L - 1];
+  for (int j = 1; j <= L; ++j) {
+    // U = R 2^32 (R < Mb, so U fits L + 1 limbs)
+    for (int k = ln; k < n; k += 64) U[k] = k ? R[k - 1] : 0u;
+    wsync();
+    const uint64_t num = ((uint64_t)U[L] << 32) | U[L - 1];
+    uint32_t qh = (uint32_t)min(num / dtop, (uint64_t)0xffffffffu);
+    // T = qh * Mb: low words in place, high words one limb up, then added
+    for (int k = ln; k < n; k += 64) {
+      const uint64_t pr = (uint64_t)qh * (k < L ? B[k] : 0u);
+      T[k] = (uint32_t)pr;
+      H[k + 1] = (uint32_t)(pr >> 32);
+    }
+    if (ln == 0) H[0] = 0u;
+    wsync();
+    big_add(T, T, H, n, false, 0u);
+    wsync();
+    uint32_t nb = big_add(R, U, T, n, true, 1u);  // R = U - T (nb: no borrow)
+    wsync();
+    for (int k = 0; k < 3 && !nb; ++k) {  // the estimate was too large: add Mb back
+      nb = big_add(R, R, B, n, false, 0u);
+      wsync();
+      --qh;
+    }
+    if (ln == 0) Q[L - j] = qh;
+  }
+  if (ln == 0) Q[L] = q0;
+  wsync();
   const bool sticky = big_any(R, n);
   wsync();
   return round_mag(z, L, Q, L + 2, (int64_t)ae.e - be.e - p - 1, ae.s ^ be.s, sticky, st);
