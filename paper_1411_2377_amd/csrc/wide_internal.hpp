@@ -2,9 +2,10 @@
 // paper's precision sweep (Sec. 4.1, Tables 1 and 2).  A number of this width does not fit one
 // lane's registers, so every operation here is done by one whole wavefront on numbers held in
 // LDS, 64 limbs at a time (limb tiles across the lanes): exact products by column sums, carries
-// between lanes by ballots, rounding, long division in radix 2^32, square root bit by bit.  The operations
-// and their results are those of the fixed-width path (RN per operation, exact inner products and
-// EXACT row sums rounded once, SEQ rows folded in column order); only the data movement differs.
+// between lanes by ballots, rounding, long division in radix 2^32, square root bit by bit.  The
+// operations and their results are those of the fixed-width path (RN per operation, exact inner
+// products and EXACT row sums rounded once, SEQ rows folded in column order); only the data
+// movement differs.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
