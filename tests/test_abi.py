@@ -104,6 +104,9 @@ def test_variant_setter_validation():
     from paper_1411_2377_amd import _lib
     f = _lib.LIB.mp_plan_set_variant
     assert f(None, None, 0, 0, 16, 0) == _lib.MPS_EINVAL
+    # the tuners refuse a missing plan or matrix before touching a device
+    assert _lib.LIB.mp_plan_tune(None, None, 1, None) == _lib.MPS_EINVAL
+    assert _lib.LIB.mp_plan_tune_x(None, None, None, None, 1, None) == _lib.MPS_EINVAL
 
 
 def test_noalloc_size_limit_rejected_on_the_host():
