@@ -977,7 +977,7 @@ struct DotWs {
   int64_t* part = nullptr;
   int32_t* meta = nullptr;
 };
-constexpr int kDotBlocks = 64;
+constexpr int kDotBlocks = 256;  // partial windows of an inner product (its parallelism)
 std::vector<DotWs> g_dot_ws;
 std::mutex g_dot_mu;
 
@@ -1034,7 +1034,8 @@ int wide_dot(int L, const mp_vec& x, const mp_vec& y, const mp_vec& out, uint32_
   int r = dot_ws(&w);
   if (r) return r;
   const int64_t n = x.len;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 63) / 64));
+  // a block forms its elements' products one after another: as many blocks as the parts allow
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, n));
   const int64_t per = std::max<int64_t>(1, (n + nb - 1) / nb);
   wide_k::DotA a{n, per, x.limb, x.hdr, x.ld, y.limb, y.hdr, y.ld, L, w->part, w->meta,
                  out.limb, out.hdr, out.ld, nb, status};
